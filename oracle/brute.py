@@ -1,0 +1,101 @@
+"""Brute force CFL-reachability for tiny graphs -- TEST INFRASTRUCTURE.
+
+Straight from the problem statement (Section 1): (i, j) belongs to R_x when
+some path from i to j spells a word of L(x).  Every path of length at most L
+(the empty path included) is enumerated, and its label word is tested for
+membership with the CYK table construction (textbook dynamic programming over
+spans; empty spans hold the nullable symbols).
+
+On an acyclic graph with L >= n - 1 every path is seen, so the result is
+exact.  On a graph with cycles it is a subset of the exact answer that grows
+with L.
+"""
+
+from __future__ import annotations
+
+from .textgrammar import TextGrammar
+
+
+class _Cyk:
+    """Incremental CYK: the word grows by one terminal at a time; column e of
+    the table holds, for each start s <= e, the symbols deriving word[s:e]."""
+
+    def __init__(self, g: TextGrammar):
+        self.g = g
+        self.null = frozenset(g.nullable())
+        self.unit = g.unit
+        self.binary = g.binary
+
+    def _close(self, cell, left_cells, right_cells):
+        # cell: symbols deriving w[s:e]; left_cells[m] = T[s][m],
+        # right_cells[m] = T[m][e] for s <= m <= e (m = e / m = s included:
+        # those are empty spans or the cell itself).
+        changed = True
+        while changed:
+            changed = False
+            for x, y in self.unit:
+                if y in cell and x not in cell:
+                    cell.add(x)
+                    changed = True
+            for x, y, z in self.binary:
+                if x in cell:
+                    continue
+                for lc, rc in zip(left_cells, right_cells):
+                    if y in lc and z in rc:
+                        cell.add(x)
+                        changed = True
+                        break
+        return cell
+
+    def extend(self, cols, terminal):
+        """cols[e][s] = T[s][e] for e < len(cols); returns the new column."""
+        e = len(cols)            # new end index (word length after extension)
+        col = [None] * (e + 1)
+        col[e] = set(self.null)  # empty span T[e][e]
+        for s in range(e - 1, -1, -1):
+            cell = {terminal} if s == e - 1 else set()
+            # split points m in [s, e]: T[s][m] (earlier columns or the cell)
+            # and T[m][e] (this column, computed for m > s already).
+            left = []
+            right = []
+            for m in range(s, e + 1):
+                left.append(cols[m][s] if m < e else cell)
+                right.append(col[m] if m > s else cell)
+            col[s] = self._close(cell, left, right)
+        return col
+
+
+def brute_force(grammar_text: str, graph, max_len: int):
+    """{nt: set of (i, j)} from all paths of length <= max_len."""
+    g = TextGrammar(grammar_text)
+    cyk = _Cyk(g)
+    adj = [[] for _ in range(graph.n)]
+    for u, t, v in graph.edges():
+        adj[u].append((t, v))
+    out = {x: set() for x in g.nts}
+    col0 = [set(cyk.null)]
+
+    def dfs(root, v, cols, depth):
+        for x in cols[-1][0]:
+            if x in out:
+                out[x].add((root, v))
+        if depth == max_len:
+            return
+        for t, w in adj[v]:
+            cols.append(cyk.extend(cols, t))
+            dfs(root, w, cols, depth + 1)
+            cols.pop()
+
+    for i in range(graph.n):
+        dfs(i, i, [col0], 0)
+    return out
+
+
+def word_in(grammar_text: str, nt: str, word) -> bool:
+    """Membership of one word in L(nt) (CYK)."""
+    g = TextGrammar(grammar_text)
+    cyk = _Cyk(g)
+    cols = [[set(cyk.null)]]
+    for t in word:
+        cols.append(cyk.extend(cols, t))
+    return nt in cols[-1][0]

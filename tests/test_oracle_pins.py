@@ -1,0 +1,303 @@
+"""Pins of the CPU oracle against what the definitions fix (no GPU).
+
+Each pin is independent of the oracle's code: brute force over paths with
+CYK membership (exact on acyclic graphs), Algorithm 1 run as printed on dense
+matrices, closed forms (Dyck-1 on a path, transitive closure by BFS, a
+right-linear language by BFS on a product automaton), the paper's pairs of
+equivalent grammars (Figs. 4a/4b, 5a/5b, 6a/6b, 7a/7b), and a derivation
+certificate plus closure check that pins the exact least fixpoint at any
+size.
+"""
+
+import hashlib
+import os
+import shutil
+import subprocess
+import tempfile
+from collections import deque
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.brute import brute_force, word_in
+from oracle.certificate import check_certificate, check_closed
+from oracle.naive import naive_closure
+from workloads import grammars as G
+from workloads import graphs
+
+
+def grammar_cases(fields=2):
+    return {
+        "dyck1": (G.DYCK1, ["a", "b"]),
+        "alias5a": (G.ALIAS_FIG5A_WCNF, ["a", "d", "a_bar", "d_bar"]),
+        "alias5b": (G.ALIAS_FIG5B, ["a", "d", "a_bar", "d_bar"]),
+        "pointsto4b": (G.pointsto_fig4b(fields),
+                       G.symbols_of(G.pointsto_fig4b(fields))[1]),
+        "pointsto4a": (G.pointsto_fig4a(fields),
+                       G.symbols_of(G.pointsto_fig4a(fields))[1]),
+        "valueflow7a": (G.cscvf_fig7a(fields), G.symbols_of(G.cscvf_fig7a(fields))[1]),
+        "valueflow7b": (G.cscvf_fig7b(fields), G.symbols_of(G.cscvf_fig7b(fields))[1]),
+        "fsca6a": (G.fsca_fig6a(fields), G.symbols_of(G.fsca_fig6a(fields))[1]),
+        "fsca6b": (G.fsca_fig6b(fields), G.symbols_of(G.fsca_fig6b(fields))[1]),
+        "transitive": (G.TRANSITIVE, ["a"]),
+        "refl_trans": (G.REFLEXIVE_TRANSITIVE, ["a"]),
+    }
+
+
+def assert_same(oracle_res, expected, nts=None):
+    for x in nts or oracle_res.order:
+        got = oracle_res.pair_set(x)
+        assert got == expected[x], (x, sorted(got ^ expected[x])[:10])
+
+
+@pytest.mark.parametrize("name", list(grammar_cases()))
+def test_oracle_equals_brute_force_on_dags(name, oracle_bin):
+    text, labels = grammar_cases()[name]
+    for seed in range(6):
+        g = graphs.random_graph(6, 10, labels, seed=100 + seed, dag=True)
+        exact = brute_force(text, g, max_len=g.n)   # every path of a DAG
+        assert_same(oracle.solve(text, g), exact)
+
+
+@pytest.mark.parametrize("name", ["dyck1", "alias5a", "valueflow7b", "transitive"])
+def test_brute_force_is_a_lower_bound_on_cycles(name, oracle_bin):
+    text, labels = grammar_cases()[name]
+    for seed in range(4):
+        g = graphs.random_graph(5, 9, labels, seed=200 + seed, self_loops=True)
+        o = oracle.solve(text, g)
+        short = brute_force(text, g, max_len=4)
+        longer = brute_force(text, g, max_len=7)
+        for x in o.order:
+            assert short[x] <= longer[x] <= o.pair_set(x), x
+
+
+@pytest.mark.parametrize("name", list(grammar_cases()))
+def test_oracle_equals_algorithm1_dense(name, oracle_bin):
+    text, labels = grammar_cases()[name]
+    for seed in range(4):
+        g = graphs.random_graph(24, 60, labels, seed=300 + seed, self_loops=True)
+        exact, _ = naive_closure(text, g)
+        assert_same(oracle.solve(text, g), exact)
+
+
+@pytest.mark.parametrize("case", ["dyck_er", "alias", "pointsto", "valueflow"])
+def test_certificate_pins_the_least_fixpoint(case, oracle_bin):
+    if case == "dyck_er":
+        text, g = G.DYCK1, graphs.erdos_renyi(256, 1024, seed=0)
+    elif case == "alias":
+        text, g = G.ALIAS_FIG5A_WCNF, graphs.alias_graph(400, seed=11)
+    elif case == "pointsto":
+        text, g = G.pointsto_fig4b(8), graphs.pointsto_graph(600, fields=8, seed=12)
+    else:
+        text, g = G.cscvf_fig7b(4), graphs.valueflow_graph(500, calls=4, seed=13)
+    r = oracle.solve(text, g, cert=True)
+    try:
+        certified = check_certificate(text, g, r.cert_path)   # sound
+        for x in r.order:
+            assert certified[x] == r.pair_set(x)
+        check_closed(text, g, certified)                      # closed + seeded
+    finally:
+        shutil.rmtree(os.path.dirname(r.cert_path))
+
+
+def dyck_chain_expected(word):
+    """Closed form of Dyck-1 (a = open, b = close) on a labelled path: with
+    h the running height (#a - #b), S(i, j) iff h(j) = h(i) and h stays >=
+    h(i) on [i, j]; A, B are the a- and b-edges; X = S B."""
+    h = np.concatenate([[0], np.cumsum([1 if t == "a" else -1 for t in word])])
+    n = len(word) + 1
+    S, X = set(), set()
+    for i in range(n):
+        lo = h[i]
+        for j in range(i, n):
+            if h[j] < h[i]:
+                break
+            if h[j] == h[i]:
+                S.add((i, j))
+    for (i, k) in S:
+        if k < len(word) and word[k] == "b":
+            X.add((i, k + 1))
+    A = {(i, i + 1) for i, t in enumerate(word) if t == "a"}
+    B = {(i, i + 1) for i, t in enumerate(word) if t == "b"}
+    return {"S": S, "X": X, "A": A, "B": B}
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_dyck1_on_a_path_closed_form(seed, oracle_bin):
+    rng = np.random.default_rng(seed)
+    word = ["a" if x else "b" for x in rng.random(600 + 300 * seed) < 0.5]
+    g = graphs.chain(word, labels=["a", "b"])
+    assert_same(oracle.solve(G.DYCK1, g), dyck_chain_expected(word))
+
+
+def test_dyck1_without_closing_edges_is_identity(oracle_bin):
+    g = graphs.random_graph(50, 200, ["a"], seed=5)
+    r = oracle.solve(G.DYCK1, g)
+    assert r.pair_set("S") == {(i, i) for i in range(50)}
+    assert r.pair_set("X") == set() and r.pair_set("B") == set()
+
+
+def bfs_closure(n, edges, reflexive):
+    adj = [[] for _ in range(n)]
+    for u, v in edges:
+        adj[u].append(v)
+    out = set()
+    for s in range(n):
+        seen = set()
+        dq = deque(adj[s])
+        while dq:
+            v = dq.popleft()
+            if v in seen:
+                continue
+            seen.add(v)
+            dq.extend(adj[v])
+        if reflexive:
+            seen.add(s)
+        out |= {(s, v) for v in seen}
+    return out
+
+
+@pytest.mark.parametrize("reflexive", [False, True])
+def test_transitive_closure_by_bfs(reflexive, oracle_bin):
+    text = G.REFLEXIVE_TRANSITIVE if reflexive else G.TRANSITIVE
+    for seed in range(3):
+        g = graphs.random_graph(300, 450, ["a", "z"], seed=400 + seed,
+                                self_loops=True)
+        a_edges = [(u, v) for u, t, v in g.edges() if t == "a"]
+        r = oracle.solve(text, g)
+        assert r.pair_set("S") == bfs_closure(g.n, a_edges, reflexive)
+
+
+def test_right_linear_language_by_product_bfs(oracle_bin):
+    # S -> a S | b : words a* b; reachability on graph x {before b, after b}
+    text = "S -> a S | b\n"
+    for seed in range(3):
+        g = graphs.random_graph(200, 500, ["a", "b"], seed=500 + seed,
+                                self_loops=True)
+        a_adj = [[] for _ in range(g.n)]
+        b_adj = [[] for _ in range(g.n)]
+        for u, t, v in g.edges():
+            (a_adj if t == "a" else b_adj)[u].append(v)
+        exp = set()
+        for s in range(g.n):
+            seen = {s}
+            dq = deque([s])
+            while dq:
+                u = dq.popleft()
+                for v in a_adj[u]:
+                    if v not in seen:
+                        seen.add(v)
+                        dq.append(v)
+            exp |= {(s, w) for u in seen for w in b_adj[u]}
+        assert oracle.solve(text, g).pair_set("S") == exp
+
+
+EQUIVALENT = [
+    ("alias 5a/5b", G.ALIAS_FIG5A_WCNF, G.ALIAS_FIG5B, ["M"],
+     lambda s: graphs.alias_graph(300, seed=s)),
+    ("points-to 4a/4b", G.pointsto_fig4a(6), G.pointsto_fig4b(6), ["PT", "FT"],
+     lambda s: graphs.pointsto_graph(400, fields=6, seed=s)),
+    ("value-flow 7a/7b", G.cscvf_fig7a(5), G.cscvf_fig7b(5), ["A"],
+     lambda s: graphs.valueflow_graph(300, calls=5, p_call=0.3, seed=s)),
+]
+
+
+@pytest.mark.parametrize("case", EQUIVALENT, ids=[c[0] for c in EQUIVALENT])
+def test_paper_equivalent_grammars_agree(case, oracle_bin):
+    _, text1, text2, shared, make = case
+    for seed in range(3):
+        g = make(600 + seed)
+        r1, r2 = oracle.solve(text1, g), oracle.solve(text2, g)
+        for x in shared:
+            assert r1.pair_set(x) == r2.pair_set(x), x
+        assert any(r1.count[x] for x in shared)
+
+
+def test_fsca_6a_6b_agree(oracle_bin):
+    labels = G.symbols_of(G.fsca_fig6b(3))[1]
+    for seed in range(3):
+        g = graphs.random_graph(40, 90, labels, seed=700 + seed, self_loops=True)
+        r1, r2 = oracle.solve(G.fsca_fig6a(3), g), oracle.solve(G.fsca_fig6b(3), g)
+        for x in ["M", "V", "A", "Abar"]:
+            assert r1.pair_set(x) == r2.pair_set(x), x
+
+
+def test_cyk_membership_textbook_words():
+    assert word_in(G.DYCK1, "S", [])
+    assert word_in(G.DYCK1, "S", list("aabbab"))
+    assert not word_in(G.DYCK1, "S", list("aab"))
+    assert not word_in(G.DYCK1, "S", list("ba"))
+    assert word_in(G.ALIAS_FIG5B, "M", ["d_bar", "d"])
+    assert word_in(G.ALIAS_FIG5B, "M", ["d_bar", "a_bar", "a", "d"])
+    assert not word_in(G.ALIAS_FIG5B, "M", ["d_bar", "a"])
+
+
+def test_digest_is_sha256_of_sorted_pairs(oracle_bin):
+    g = graphs.erdos_renyi(128, 400, seed=9)
+    r = oracle.solve(G.DYCK1, g)
+    for x in r.order:
+        p = r.pairs[x]
+        buf = np.ascontiguousarray(p, dtype="<u4").tobytes()
+        assert hashlib.sha256(buf).hexdigest() == r.digest[x]
+        assert r.count[x] == p.shape[0]
+        assert np.all(np.diff(p[:, 0].astype(np.int64) * 10**6 + p[:, 1]) > 0)
+
+
+def test_golden_files_reproduce(oracle_bin):
+    import json
+    from tests.golden.make_goldens import GOLDENS
+    for name in ["dyck_er_256", "pointsto_4k"]:
+        with open(os.path.join(os.path.dirname(__file__), "golden", f"{name}.json")) as f:
+            gold = json.load(f)
+        text, g = GOLDENS[name]()
+        r = oracle.solve(text, g, pairs=False)
+        assert r.count == gold["count"] and r.digest == gold["sha256"]
+
+
+# A mistake planted in the oracle (compiled on the CPU from the same source
+# with one change) must be caught by the pins above.
+MUTANTS = {
+    "drop_right_products": ("for (uint32_t t = 0; t < n_right[y]; t++) {",
+                            "for (uint32_t t = 0; t < 0 * n_right[y]; t++) {"),
+    "transposed_operand": ("uint64_t *zr = row_set[z][j];",
+                           "uint64_t *zr = col_set[z][j];"),
+    "eps_only_first_vertex": ("for (uint32_t i = 0; i < n_vert; i++) add_fact(rules[r].lhs, i, i, r, UINT32_MAX);",
+                              "for (uint32_t i = 0; i < 1 && i < n_vert; i++) add_fact(rules[r].lhs, i, i, r, UINT32_MAX);"),
+    "unit_rules_ignored": ("add_fact(rules[r].lhs, i, j, r, UINT32_MAX);\n        }",
+                           "(void)r;\n        }"),
+}
+
+
+@pytest.mark.parametrize("mutant", list(MUTANTS))
+def test_planted_oracle_mistakes_are_caught(mutant, oracle_bin, monkeypatch):
+    src = open(oracle.SOURCE).read()
+    old, new = MUTANTS[mutant]
+    assert old in src
+    tmp = tempfile.mkdtemp(prefix="cflr_mutant_")
+    path = os.path.join(tmp, "mutant.c")
+    exe = os.path.join(tmp, "mutant")
+    with open(path, "w") as f:
+        f.write(src.replace(old, new, 1))
+    subprocess.run(["gcc", "-O1", "-std=c11", "-o", exe, path], check=True,
+                   capture_output=True)
+    monkeypatch.setattr(oracle, "BINARY", exe)
+    monkeypatch.setattr(oracle, "_ensure_built", lambda: None)
+    caught = False
+    try:
+        for name in ["dyck1", "alias5a", "alias5b", "fsca6b", "refl_trans"]:
+            text, labels = grammar_cases()[name]
+            for seed in range(3):
+                g = graphs.random_graph(6, 10, labels, seed=100 + seed, dag=True)
+                exact = brute_force(text, g, max_len=g.n)
+                r = oracle.solve(text, g)
+                if any(r.pair_set(x) != exact[x] for x in r.order):
+                    caught = True
+                    break
+            if caught:
+                break
+    finally:
+        for fn in os.listdir(tmp):
+            os.unlink(os.path.join(tmp, fn))
+        os.rmdir(tmp)
+    assert caught, f"pins did not catch mutant {mutant}"
