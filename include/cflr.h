@@ -1,0 +1,227 @@
+/*
+ * cflr.h -- C interface of libcflr, a CFL-reachability solver for AMD
+ * MI355X (gfx950).
+ *
+ * Problem (Section 1 of Muravev, "Optimization of the Context-Free Language
+ * Reachability Matrix-Based Algorithm", arXiv 2401.11029): given a grammar
+ * and an edge-labelled graph, find for every non-terminal x the pairs of
+ * vertices (i, j) joined by a path whose label word x derives.  The answer is
+ * Algorithm 1's Result, M_ij = { x : some path i -> j is derivable from x },
+ * stored as one boolean |V| x |V| matrix per non-terminal.
+ *
+ * Method: the fixpoint of Algorithm 1 over the reachability semiring
+ * (Definition 2), in its semi-naive form (Section 3, optimisation 1): every
+ * round multiplies only the pairs that are new since the previous round,
+ * row by row against row-major copies and column by column against
+ * column-major copies (optimisation 2), masks the candidates against the
+ * existing matrix and ORs the genuinely new ones in place (the requirement of
+ * optimisation 3: a sparse union never rebuilds M).  Rounds repeat until no
+ * matrix changes.
+ *
+ * Conventions (every entry point):
+ *  - Every call returns a cflr_status; on failure cflr_last_error() holds a
+ *    message.  No C++ exception crosses this interface.
+ *  - Inputs are copied during the call; the caller keeps ownership of every
+ *    array it passes.  Handles are owned by the library until their *_free.
+ *  - Vertex ids are 0-based (the paper numbers them 1..n).
+ *  - Edge labels are matched to grammar terminals by name; labels that no
+ *    production uses are ignored.  Reversed ("bar") edges are never implied:
+ *    a label such as a_bar is just another name.
+ *  - Output covers every non-terminal of the grammar text (every left-hand
+ *    side), in the order of first appearance; helpers the library adds are
+ *    hidden.  Pairs are returned sorted by (i, j).
+ *  - A context is used by one host thread at a time (the server below has a
+ *    thread of its own and locks internally).
+ */
+#ifndef CFLR_H
+#define CFLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum cflr_status {
+    CFLR_OK = 0,
+    CFLR_EINVAL = 1,        /* bad argument (null pointer, vertex >= n, ...) */
+    CFLR_EPARSE = 2,        /* grammar text does not parse */
+    CFLR_ENOMEM = 3,        /* device or host memory exhausted */
+    CFLR_EDEVICE = 4,       /* a HIP call failed */
+    CFLR_PENDING = 5,       /* server: the request has not finished */
+    CFLR_ETIMEOUT = 6,      /* server: wait timed out / round limit hit */
+    CFLR_EUNSUPPORTED = 7   /* valid input the library cannot handle */
+} cflr_status;
+
+typedef struct cflr_ctx cflr_ctx;
+typedef struct cflr_grammar cflr_grammar;
+typedef struct cflr_graph cflr_graph;
+typedef struct cflr_result cflr_result;
+typedef struct cflr_server cflr_server;
+
+/* Solver options.  Fill with cflr_opts_default() and change fields. */
+typedef struct cflr_opts {
+    uint32_t max_rounds;       /* stop with CFLR_ETIMEOUT after this many
+                                  rounds; 0 = no limit */
+    uint32_t semi_naive;       /* 1 (default): multiply only the new pairs of
+                                  each round (optimisation 1); 0: multiply
+                                  every pair every round (Algorithm 1 as
+                                  printed; an ablation) */
+    uint32_t kernel_timing;    /* 1: time every product launch with HIP
+                                  events (cflr_stats.product_ms) */
+    uint32_t count_traffic;    /* 1: count the algorithmic bytes of the
+                                  product kernel (cflr_stats.algo_bytes);
+                                  slower, for roofline accounting */
+    uint64_t delta_capacity;   /* initial capacity of the new-pair buffer, in
+                                  pairs; 0 = automatic.  The buffer grows on
+                                  overflow (the round is then re-run). */
+    uint32_t grid_waves;       /* waves of the persistent product kernel;
+                                  0 = automatic (autotuned) */
+    uint32_t rounds_per_sync;  /* rounds replayed per host check of the
+                                  changed flag (batched and served forms);
+                                  0 = automatic */
+} cflr_opts;
+
+/* Per-solve statistics. */
+typedef struct cflr_stats {
+    uint32_t rounds;           /* product rounds until nothing changed */
+    uint32_t reruns;           /* rounds re-run after a buffer overflow */
+    uint64_t seed_pairs;       /* pairs set by edges and eps rules */
+    uint64_t new_pairs;        /* pairs derived by the rounds */
+    uint64_t total_pairs;      /* pairs over every user non-terminal */
+    double fixpoint_ms;        /* seeding start to convergence (HIP events) */
+    double product_ms;         /* sum of product-kernel times (kernel_timing) */
+    uint64_t product_launches; /* product-kernel launches */
+    uint64_t algo_bytes;       /* algorithmic bytes of the product kernels
+                                  (count_traffic) */
+    uint64_t device_bytes;     /* device memory held for this solve */
+    uint64_t max_delta;        /* largest number of new pairs in one round */
+} cflr_stats;
+
+void cflr_opts_default(cflr_opts *opts);
+
+/* Thread-local message of the last failed call on this thread ("" if none).
+   Owned by the library; valid until the next call on the same thread. */
+const char *cflr_last_error(void);
+
+/* Library version string, e.g. "cflr 0.1 gfx950". */
+const char *cflr_version(void);
+
+/* ---- context ----------------------------------------------------------
+ * hip_device: HIP device ordinal.  hip_stream: a hipStream_t to issue all
+ * work on (e.g. torch.cuda.current_stream().cuda_stream), or NULL for a
+ * stream the context creates.  The stream must have default priority.
+ * Errors: EINVAL (bad device), EDEVICE. */
+cflr_status cflr_ctx_create(int hip_device, void *hip_stream, cflr_ctx **out);
+void cflr_ctx_destroy(cflr_ctx *ctx);
+/* Free and total device memory seen by the context, in bytes. */
+cflr_status cflr_ctx_mem_info(cflr_ctx *ctx, uint64_t *free_bytes, uint64_t *total_bytes);
+
+/* ---- grammar (host only; needs no device) -----------------------------
+ * Text format: one production per line, "LHS -> ALT | ALT ...", where ALT is
+ * "eps", one symbol, or two symbols; "#" starts a comment.  Left-hand sides
+ * are the non-terminals; every other symbol is a terminal (edge label).  This
+ * is weak Chomsky normal form (Definition 1) relaxed as the paper's appendix
+ * figures use it: terminals may appear in binary right-hand sides and unit
+ * rules x -> y are allowed; the library lowers both (a terminal t in a binary
+ * position becomes a wrapper non-terminal with T_t -> t; unit rules are
+ * removed by copying the productions of every non-terminal they reach).
+ * len: bytes of text (need not be NUL-terminated).
+ * Errors: EINVAL (null), EPARSE (message names the line). */
+cflr_status cflr_grammar_parse(const char *text, size_t len, cflr_grammar **out);
+void cflr_grammar_free(cflr_grammar *g);
+uint32_t cflr_grammar_num_nonterminals(const cflr_grammar *g);
+/* Name of user non-terminal nt (0-based, first-appearance order); NULL if
+   out of range.  Owned by the grammar. */
+const char *cflr_grammar_nonterminal_name(const cflr_grammar *g, uint32_t nt);
+
+/* Shape of the lowered (strict WCNF) grammar the device works on. */
+typedef struct cflr_grammar_info {
+    uint32_t user_nonterminals;  /* non-terminals of the text */
+    uint32_t wrappers;           /* T_t helpers for terminals in binary slots */
+    uint32_t matrices;           /* user_nonterminals + wrappers */
+    uint32_t binary;             /* binary productions after lowering */
+    uint32_t terminal_rules;     /* x -> t after lowering */
+    uint32_t eps_rules;          /* x -> eps after lowering */
+    uint32_t terminals;          /* distinct terminal names */
+} cflr_grammar_info;
+cflr_status cflr_grammar_info_get(const cflr_grammar *g, cflr_grammar_info *out);
+
+/* ---- graph --------------------------------------------------------------
+ * Edge e is (src[e], label[e], dst[e]); label[e] < n_labels indexes
+ * label_names (NUL-terminated strings).  src/dst/label are host pointers
+ * when on_device == 0 and device pointers of ctx's device when on_device ==
+ * 1; either way they are copied into device memory owned by the graph.
+ * Duplicate edges and self-loops are allowed (set semantics).
+ * Errors: EINVAL (null arrays with n_edges > 0, src/dst >= n_vertices,
+ * label >= n_labels), ENOMEM, EDEVICE. */
+cflr_status cflr_graph_create(cflr_ctx *ctx, uint32_t n_vertices, uint64_t n_edges,
+                              const uint32_t *src, const uint32_t *dst,
+                              const uint32_t *label, uint32_t n_labels,
+                              const char *const *label_names, int on_device,
+                              cflr_graph **out);
+void cflr_graph_free(cflr_graph *g);
+
+/* ---- solve ----------------------------------------------------------------
+ * Runs the fixpoint for one graph.  opts may be NULL (defaults).  The
+ * result holds the device matrices until cflr_result_free.
+ * Errors: EINVAL, ENOMEM (matrices do not fit), EDEVICE, ETIMEOUT
+ * (max_rounds reached; *out is still set and holds the partial state). */
+cflr_status cflr_solve(cflr_ctx *ctx, const cflr_grammar *g, const cflr_graph *graph,
+                       const cflr_opts *opts, cflr_result **out);
+
+/* Batched form: graphs[k] is solved with grammars[k] (the same grammar may be
+ * passed for every k).  All instances advance together, one fused product
+ * launch per round over every (graph, production, block of new pairs), so
+ * many uneven graphs share the device.  outs: caller array of count
+ * pointers, each set to a result (or NULL on failure).  Results are
+ * identical to cflr_solve of each graph alone. */
+cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
+                             const cflr_graph *const *graphs, uint32_t count,
+                             const cflr_opts *opts, cflr_result **outs);
+
+/* ---- results --------------------------------------------------------------
+ * nt indexes the user non-terminals of the result's grammar. */
+cflr_status cflr_result_count(const cflr_result *r, uint32_t nt, uint64_t *n_pairs);
+/* Copy the pairs of nt, sorted by (src, dst), into src/dst (capacity
+ * entries each; host pointers when on_device == 0, device pointers when 1).
+ * *written = pairs copied.  EINVAL if capacity is smaller than the count. */
+cflr_status cflr_result_copy(const cflr_result *r, uint32_t nt, uint32_t *src, uint32_t *dst,
+                             uint64_t capacity, int on_device, uint64_t *written);
+cflr_status cflr_result_stats(const cflr_result *r, cflr_stats *out);
+void cflr_result_free(cflr_result *r);
+
+/* ---- server (continuous batching) --------------------------------------
+ * A worker thread keeps the device busy with every admitted request: between
+ * rounds it admits queued requests while the estimated device footprint of
+ * the running ones plus the new one stays within hbm_budget_bytes and fewer
+ * than max_slots run, and retires requests that converged.  Each round is
+ * one fused launch over all running requests.  Requests may use different
+ * grammars.  Results are identical to cflr_solve of the same input.
+ * A request whose footprint alone exceeds the budget fails with ENOMEM.
+ * The server uses ctx's device and stream; do not use ctx from another
+ * thread while the server lives. */
+cflr_status cflr_server_create(cflr_ctx *ctx, uint64_t hbm_budget_bytes, uint32_t max_slots,
+                               const cflr_opts *opts, cflr_server **out);
+/* Queue a request; the grammar and graph must stay alive until its result is
+ * returned.  *ticket identifies it. */
+cflr_status cflr_server_submit(cflr_server *s, const cflr_grammar *g, const cflr_graph *graph,
+                               uint64_t *ticket);
+/* OK and *out set when finished (the caller then owns *out), PENDING if not
+   yet, or the request's own error status. */
+cflr_status cflr_server_poll(cflr_server *s, uint64_t ticket, cflr_result **out);
+/* Block until finished or timeout_ns elapses (ETIMEOUT). */
+cflr_status cflr_server_wait(cflr_server *s, uint64_t ticket, uint64_t timeout_ns,
+                             cflr_result **out);
+/* Times of a finished request, in seconds on the server's clock. */
+cflr_status cflr_server_times(cflr_server *s, uint64_t ticket, double *submitted,
+                              double *admitted, double *finished);
+/* Stops the worker after the running requests finish; frees the server. */
+void cflr_server_free(cflr_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CFLR_H */

@@ -1,0 +1,443 @@
+// api.cpp -- the extern "C" boundary of libcflr (include/cflr.h).
+//
+// Every entry point catches C++ exceptions and turns them into a status plus
+// a thread-local message; nothing throws across the boundary.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <string>
+
+#include "engine.h"
+
+using namespace cflr;
+
+namespace cflr {
+
+// Free the column-major copies and the helper matrices of a finished
+// instance, keeping only the row-major matrices of the user non-terminals
+// that readout needs.
+void compact_instance(Instance &in) {
+    const uint32_t U = (uint32_t)in.low.user_names.size();
+    const uint64_t words = (uint64_t)in.n * (in.Wp + in.S);
+    const uint64_t bytes = words * 8 * U;
+    if (!bytes || bytes >= in.arena.bytes) return;
+    DevBuf nb(in.ctx->pool.get(), bytes);
+    uint64_t *p = nb.as<uint64_t>();
+    std::vector<MatDev> mats(U);
+    for (uint32_t x = 0; x < U; x++) {
+        hip_check(hipMemcpyAsync(p, in.mats[x].R, (uint64_t)in.n * in.Wp * 8, hipMemcpyDeviceToDevice,
+                                 in.ctx->stream),
+                  "D2D");
+        mats[x].R = p;
+        mats[x].RS = nullptr;
+        mats[x].C = mats[x].CS = nullptr;
+        p += words;
+    }
+    hip_check(hipStreamSynchronize(in.ctx->stream), "sync");
+    in.arena = std::move(nb);
+    in.mats = std::move(mats);
+    in.stats.device_bytes = bytes;
+}
+
+void set_last_error(const std::string &msg);
+
+void ctx_retain(cflr_ctx *ctx) { ctx->refs.fetch_add(1); }
+
+void ctx_release(cflr_ctx *ctx) {
+    if (ctx->refs.fetch_sub(1) != 1) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->pool.reset();
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+}  // namespace cflr
+
+namespace {
+
+thread_local std::string g_last_error;
+std::atomic<uint64_t> g_grammar_serial{1};
+
+cflr_status fail(cflr_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+}  // namespace
+
+void cflr::set_last_error(const std::string &msg) { g_last_error = msg; }
+
+namespace {
+
+template <class F>
+cflr_status guard(F &&f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const Error &e) {
+        return fail(e.status, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(CFLR_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(CFLR_EDEVICE, e.what());
+    }
+}
+
+void set_device(cflr_ctx *ctx) { hip_check(hipSetDevice(ctx->device), "hipSetDevice"); }
+
+cflr_opts effective(const cflr_opts *o) {
+    cflr_opts r;
+    cflr_opts_default(&r);
+    if (o) r = *o;
+    return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+void cflr_opts_default(cflr_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->semi_naive = 1;
+}
+
+const char *cflr_last_error(void) { return g_last_error.c_str(); }
+
+const char *cflr_version(void) { return "cflr 0.1 gfx950"; }
+
+// ------------------------------------------------------------------ context
+
+cflr_status cflr_ctx_create(int hip_device, void *hip_stream, cflr_ctx **out) {
+    return guard([&]() -> cflr_status {
+        if (!out) return fail(CFLR_EINVAL, "out is null");
+        *out = nullptr;
+        int count = 0;
+        hip_check(hipGetDeviceCount(&count), "hipGetDeviceCount");
+        if (hip_device < 0 || hip_device >= count)
+            return fail(CFLR_EINVAL, "no HIP device " + std::to_string(hip_device));
+        auto ctx = std::make_unique<cflr_ctx>();
+        ctx->device = hip_device;
+        hip_check(hipSetDevice(hip_device), "hipSetDevice");
+        hipDeviceProp_t prop;
+        hip_check(hipGetDeviceProperties(&prop, hip_device), "hipGetDeviceProperties");
+        ctx->num_cu = (uint32_t)prop.multiProcessorCount;
+        if (hip_stream) {
+            ctx->stream = (hipStream_t)hip_stream;
+        } else {
+            hip_check(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking), "hipStreamCreate");
+            ctx->own_stream = true;
+        }
+        ctx->pool = std::make_unique<DevPool>(hip_device);
+        *out = ctx.release();
+        return CFLR_OK;
+    });
+}
+
+void cflr_ctx_destroy(cflr_ctx *ctx) {
+    if (ctx) ctx_release(ctx);
+}
+
+cflr_status cflr_ctx_mem_info(cflr_ctx *ctx, uint64_t *free_bytes, uint64_t *total_bytes) {
+    return guard([&]() -> cflr_status {
+        if (!ctx || !free_bytes || !total_bytes) return fail(CFLR_EINVAL, "null argument");
+        set_device(ctx);
+        size_t f = 0, t = 0;
+        hip_check(hipMemGetInfo(&f, &t), "hipMemGetInfo");
+        *free_bytes = f;
+        *total_bytes = t;
+        return CFLR_OK;
+    });
+}
+
+// ------------------------------------------------------------------ grammar
+
+cflr_status cflr_grammar_parse(const char *text, size_t len, cflr_grammar **out) {
+    return guard([&]() -> cflr_status {
+        if (!out || (!text && len)) return fail(CFLR_EINVAL, "null argument");
+        *out = nullptr;
+        auto g = std::make_unique<cflr_grammar>();
+        g->low = parse_and_lower(text ? text : "", len);
+        g->serial = g_grammar_serial++;
+        *out = g.release();
+        return CFLR_OK;
+    });
+}
+
+void cflr_grammar_free(cflr_grammar *g) { delete g; }
+
+uint32_t cflr_grammar_num_nonterminals(const cflr_grammar *g) {
+    return g ? (uint32_t)g->low.user_names.size() : 0;
+}
+
+const char *cflr_grammar_nonterminal_name(const cflr_grammar *g, uint32_t nt) {
+    if (!g || nt >= g->low.user_names.size()) return nullptr;
+    return g->low.user_names[nt].c_str();
+}
+
+cflr_status cflr_grammar_info_get(const cflr_grammar *g, cflr_grammar_info *out) {
+    return guard([&]() -> cflr_status {
+        if (!g || !out) return fail(CFLR_EINVAL, "null argument");
+        out->user_nonterminals = (uint32_t)g->low.user_names.size();
+        out->wrappers = g->low.wrappers;
+        out->matrices = g->low.nmat();
+        out->binary = (uint32_t)g->low.binary.size();
+        out->terminal_rules = (uint32_t)g->low.term.size();
+        out->eps_rules = (uint32_t)g->low.eps.size();
+        out->terminals = (uint32_t)g->low.terminals.size();
+        return CFLR_OK;
+    });
+}
+
+// -------------------------------------------------------------------- graph
+
+cflr_status cflr_graph_create(cflr_ctx *ctx, uint32_t n_vertices, uint64_t n_edges, const uint32_t *src,
+                              const uint32_t *dst, const uint32_t *label, uint32_t n_labels,
+                              const char *const *label_names, int on_device, cflr_graph **out) {
+    return guard([&]() -> cflr_status {
+        if (!ctx || !out) return fail(CFLR_EINVAL, "null argument");
+        *out = nullptr;
+        if (n_edges && (!src || !dst || !label)) return fail(CFLR_EINVAL, "null edge array");
+        if (n_labels && !label_names) return fail(CFLR_EINVAL, "null label names");
+        set_device(ctx);
+        auto g = std::make_unique<cflr_graph>();
+        g->hold = CtxRef(ctx);
+        g->ctx = ctx;
+        g->n = n_vertices;
+        g->m = n_edges;
+        for (uint32_t l = 0; l < n_labels; l++) {
+            if (!label_names[l]) return fail(CFLR_EINVAL, "null label name");
+            g->label_names.emplace_back(label_names[l]);
+        }
+        if (n_edges) {
+            // validate on the host (device input is copied down first)
+            std::vector<uint32_t> hs, hd, hl;
+            const uint32_t *ps = src, *pd = dst, *pl = label;
+            hipStream_t s = ctx->stream;
+            if (on_device) {
+                hs.resize(n_edges);
+                hd.resize(n_edges);
+                hl.resize(n_edges);
+                copy_sync(hs.data(), src, n_edges * 4, hipMemcpyDeviceToHost, s);
+                copy_sync(hd.data(), dst, n_edges * 4, hipMemcpyDeviceToHost, s);
+                copy_sync(hl.data(), label, n_edges * 4, hipMemcpyDeviceToHost, s);
+                ps = hs.data();
+                pd = hd.data();
+                pl = hl.data();
+            }
+            for (uint64_t e = 0; e < n_edges; e++) {
+                if (ps[e] >= n_vertices || pd[e] >= n_vertices)
+                    return fail(CFLR_EINVAL, "edge " + std::to_string(e) + " has a vertex >= n");
+                if (pl[e] >= n_labels)
+                    return fail(CFLR_EINVAL, "edge " + std::to_string(e) + " has a label >= n_labels");
+            }
+            DevPool *pool = ctx->pool.get();
+            g->src = DevBuf(pool, n_edges * 4);
+            g->dst = DevBuf(pool, n_edges * 4);
+            g->lab = DevBuf(pool, n_edges * 4);
+            copy_sync(g->src.ptr, ps, n_edges * 4, hipMemcpyHostToDevice, s);
+            copy_sync(g->dst.ptr, pd, n_edges * 4, hipMemcpyHostToDevice, s);
+            copy_sync(g->lab.ptr, pl, n_edges * 4, hipMemcpyHostToDevice, s);
+        }
+        *out = g.release();
+        return CFLR_OK;
+    });
+}
+
+void cflr_graph_free(cflr_graph *g) {
+    if (!g) return;
+    try {
+        (void)hipSetDevice(g->ctx->device);
+        (void)hipStreamSynchronize(g->ctx->stream);
+    } catch (...) {
+    }
+    delete g;
+}
+
+// -------------------------------------------------------------------- solve
+
+cflr_status cflr_solve(cflr_ctx *ctx, const cflr_grammar *g, const cflr_graph *graph, const cflr_opts *opts,
+                       cflr_result **out) {
+    return guard([&]() -> cflr_status {
+        if (!ctx || !g || !graph || !out) return fail(CFLR_EINVAL, "null argument");
+        if (graph->ctx != ctx) return fail(CFLR_EINVAL, "graph belongs to another context");
+        *out = nullptr;
+        set_device(ctx);
+        cflr_opts o = effective(opts);
+        hipEvent_t e0, e1;
+        hip_check(hipEventCreate(&e0), "event");
+        hip_check(hipEventCreate(&e1), "event");
+        std::shared_ptr<Instance> inst;
+        cflr_status status = CFLR_OK;
+        {
+            hip_check(hipEventRecord(e0, ctx->stream), "event");
+            inst = make_instance(ctx, g->low, graph);
+            Run run(ctx, o, (uint64_t)g->low.nmat() * graph->n, 1);
+            run.add(inst);
+            while (run.round()) {
+                if (o.max_rounds && inst->rounds >= o.max_rounds) {
+                    status = CFLR_ETIMEOUT;
+                    break;
+                }
+            }
+            hip_check(hipEventRecord(e1, ctx->stream), "event");
+            hip_check(hipEventSynchronize(e1), "event");
+            float ms = 0;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+            inst->stats.fixpoint_ms = ms;
+            inst->stats.rounds = inst->rounds;
+            inst->stats.product_ms = run.product_ms();
+            inst->stats.product_launches = run.product_launches();
+            inst->stats.algo_bytes = run.algo_bytes();
+            inst->stats.reruns = run.reruns();
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        instance_counts(*inst);
+        *out = new cflr_result{inst};
+        if (status != CFLR_OK) return fail(status, "round limit reached before the fixpoint");
+        return CFLR_OK;
+    });
+}
+
+cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars, const cflr_graph *const *graphs,
+                             uint32_t count, const cflr_opts *opts, cflr_result **outs) {
+    return guard([&]() -> cflr_status {
+        if (!ctx || (count && (!grammars || !graphs || !outs))) return fail(CFLR_EINVAL, "null argument");
+        for (uint32_t k = 0; k < count; k++) {
+            outs[k] = nullptr;
+            if (!grammars[k] || !graphs[k]) return fail(CFLR_EINVAL, "null grammar or graph");
+            if (graphs[k]->ctx != ctx) return fail(CFLR_EINVAL, "graph belongs to another context");
+        }
+        if (!count) return CFLR_OK;
+        set_device(ctx);
+        cflr_opts o = effective(opts);
+        // admission by device memory: instances join as earlier ones finish
+        size_t free_b = 0, total_b = 0;
+        hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+        uint64_t rows = 0, max_rows = 0;
+        for (uint32_t k = 0; k < count; k++) {
+            uint64_t r = (uint64_t)grammars[k]->low.nmat() * graphs[k]->n;
+            rows += r;
+            max_rows = std::max(max_rows, r);
+        }
+        rows = std::min<uint64_t>(rows, std::max<uint64_t>(max_rows, 0x0FFFFFFFull));
+        hipEvent_t e0, e1;
+        hip_check(hipEventCreate(&e0), "event");
+        hip_check(hipEventCreate(&e1), "event");
+        hip_check(hipEventRecord(e0, ctx->stream), "event");
+        Run run(ctx, o, rows, count);
+        const uint64_t budget = (uint64_t)((double)(free_b + ctx->pool->held()) * 0.6);
+        std::vector<std::shared_ptr<Instance>> all(count);
+        uint64_t in_use = 0;
+        uint32_t next = 0;
+        cflr_status status = CFLR_OK;
+        std::vector<uint64_t> fp(count);
+        for (uint32_t k = 0; k < count; k++) fp[k] = instance_footprint(grammars[k]->low, graphs[k]->n);
+        while (true) {
+            // admit
+            while (next < count) {
+                uint64_t need = fp[next];
+                uint64_t r = (uint64_t)grammars[next]->low.nmat() * graphs[next]->n;
+                if (run.size() && (in_use + need > budget || r > rows)) break;
+                auto inst = make_instance(ctx, grammars[next]->low, graphs[next]);
+                try {
+                    run.add(inst);
+                } catch (const Error &e) {
+                    if (!run.size()) throw;
+                    break;  // row space full: wait for a retirement
+                }
+                all[next] = inst;
+                in_use += need;
+                next++;
+            }
+            if (!run.size()) break;
+            run.round();
+            // retire finished instances
+            std::vector<std::shared_ptr<Instance>> done;
+            for (auto &ip : run.instances())
+                if (ip->done || (o.max_rounds && ip->rounds >= o.max_rounds)) done.push_back(ip);
+            for (auto &ip : done) {
+                if (!ip->done) {
+                    ip->status = CFLR_ETIMEOUT;
+                    status = CFLR_ETIMEOUT;
+                }
+                run.remove(ip.get());
+                in_use -= ip->footprint;
+                ip->stats.rounds = ip->rounds;
+                compact_instance(*ip);
+            }
+        }
+        hip_check(hipEventRecord(e1, ctx->stream), "event");
+        hip_check(hipEventSynchronize(e1), "event");
+        float ms = 0;
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        for (uint32_t k = 0; k < count; k++) {
+            Instance &in = *all[k];
+            in.stats.fixpoint_ms = ms;  // the whole batch shares one clock
+            in.stats.product_ms = run.product_ms();
+            in.stats.product_launches = run.product_launches();
+            in.stats.algo_bytes = run.algo_bytes();
+            in.stats.reruns = run.reruns();
+            instance_counts(in);
+            outs[k] = new cflr_result{all[k]};
+        }
+        if (status != CFLR_OK) return fail(status, "round limit reached before the fixpoint");
+        return CFLR_OK;
+    });
+}
+
+// ------------------------------------------------------------------ results
+
+cflr_status cflr_result_count(const cflr_result *r, uint32_t nt, uint64_t *n_pairs) {
+    return guard([&]() -> cflr_status {
+        if (!r || !n_pairs) return fail(CFLR_EINVAL, "null argument");
+        Instance &in = *r->inst;
+        if (nt >= in.low.user_names.size()) return fail(CFLR_EINVAL, "non-terminal index out of range");
+        set_device(in.ctx);
+        instance_counts(in);
+        *n_pairs = (uint64_t)in.counts[nt];
+        return CFLR_OK;
+    });
+}
+
+cflr_status cflr_result_copy(const cflr_result *r, uint32_t nt, uint32_t *src, uint32_t *dst, uint64_t capacity,
+                             int on_device, uint64_t *written) {
+    return guard([&]() -> cflr_status {
+        if (!r || !written) return fail(CFLR_EINVAL, "null argument");
+        Instance &in = *r->inst;
+        if (nt >= in.low.user_names.size()) return fail(CFLR_EINVAL, "non-terminal index out of range");
+        set_device(in.ctx);
+        instance_counts(in);
+        if (in.counts[nt] > 0 && (!src || !dst)) return fail(CFLR_EINVAL, "null output array");
+        instance_copy(in, nt, src, dst, capacity, on_device != 0, written);
+        return CFLR_OK;
+    });
+}
+
+cflr_status cflr_result_stats(const cflr_result *r, cflr_stats *out) {
+    return guard([&]() -> cflr_status {
+        if (!r || !out) return fail(CFLR_EINVAL, "null argument");
+        *out = r->inst->stats;
+        return CFLR_OK;
+    });
+}
+
+void cflr_result_free(cflr_result *r) {
+    if (!r) return;
+    try {
+        (void)hipSetDevice(r->inst->ctx->device);
+        (void)hipStreamSynchronize(r->inst->ctx->stream);
+    } catch (...) {
+    }
+    delete r;
+}
+
+}  // extern "C"

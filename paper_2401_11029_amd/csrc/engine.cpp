@@ -1,0 +1,632 @@
+// engine.cpp -- host side of the round engine.
+//
+// The fixpoint of Algorithm 1 in its semi-naive form (Section 3, opt. 1):
+//   seed      edges and eps rules set the first pairs; they are the first
+//             round's new pairs (M_old = empty);
+//   round     prep (work table) -> product (all productions, both parts,
+//             every admitted instance in one launch) -> sort of the appended
+//             new pairs into row and column order (next round's dA, dB);
+//   converge  an instance whose round derived no pair is done (its new-pair
+//             set is empty, so no later round can derive anything for it).
+// If the new-pair buffer overflows, the product leaves the overflowing
+// candidates out of M; the host grows the buffer and re-runs the product of
+// the same round (OR is idempotent, so pairs already added are not found
+// again and the missing ones are).
+#include "engine.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+namespace cflr {
+
+void hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return;
+    cflr_status st = (e == hipErrorOutOfMemory) ? CFLR_ENOMEM : CFLR_EDEVICE;
+    throw Error(st, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Stream-ordered copy that returns once the data has landed.
+void copy_sync(void *dst, const void *src, size_t bytes, hipMemcpyKind kind, hipStream_t s) {
+    if (!bytes) return;
+    hip_check(hipMemcpyAsync(dst, src, bytes, kind, s), "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+// ------------------------------------------------------------------ DevPool
+
+static size_t round_bytes(size_t b) {
+    // small blocks: next power of two (>= 256 B); large: 2 MiB granules
+    if (b < ((size_t)1 << 20)) {
+        size_t r = 256;
+        while (r < b) r <<= 1;
+        return r;
+    }
+    const size_t g = (size_t)2 << 20;
+    return (b + g - 1) / g * g;
+}
+
+DevPool::~DevPool() {
+    (void)hipSetDevice(device_);
+    for (auto &kv : cache_) (void)hipFree(kv.second);
+    for (auto &kv : live_) (void)hipFree(kv.first);
+}
+
+void *DevPool::alloc(size_t bytes) {
+    size_t b = round_bytes(bytes);
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = cache_.find(b);
+    if (it != cache_.end()) {
+        void *p = it->second;
+        cache_.erase(it);
+        live_[p] = b;
+        return p;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, b);
+    if (e == hipErrorOutOfMemory && !cache_.empty()) {
+        (void)hipGetLastError();
+        for (auto &kv : cache_) {
+            (void)hipFree(kv.second);
+            held_ -= kv.first;
+        }
+        cache_.clear();
+        e = hipMalloc(&p, b);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(e == hipErrorOutOfMemory ? CFLR_ENOMEM : CFLR_EDEVICE,
+                    "hipMalloc(" + std::to_string(b) + "): " + hipGetErrorString(e));
+    }
+    live_[p] = b;
+    held_ += b;
+    return p;
+}
+
+void DevPool::release(void *p) {
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = live_.find(p);
+    if (it == live_.end()) return;
+    cache_.insert({it->second, p});
+    live_.erase(it);
+}
+
+void DevPool::trim() {
+    std::lock_guard<std::mutex> g(mu_);
+    for (auto &kv : cache_) {
+        (void)hipFree(kv.second);
+        held_ -= kv.first;
+    }
+    cache_.clear();
+}
+
+// ---------------------------------------------------------------- instances
+
+static void plan_layout(const Lowered &low, uint32_t n, uint32_t *S, uint64_t *Wp,
+                        std::vector<uint8_t> *has_col, uint64_t *bytes) {
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    *S = (uint32_t)std::max<uint64_t>(1, (words + kSegWords - 1) / kSegWords);
+    *Wp = (uint64_t)*S * kSegWords;
+    const uint64_t layout = (uint64_t)n * (*Wp + *S) * 8;
+    uint64_t total = 0;
+    has_col->assign(low.nmat(), 0);
+    for (uint32_t x = 0; x < low.nmat(); x++) {
+        total += layout;  // R + RS
+        if (low.dynamic[x] || low.slot_a[x]) {
+            (*has_col)[x] = 1;
+            total += layout;
+        }
+    }
+    *bytes = total;
+}
+
+uint64_t instance_footprint(const Lowered &low, uint32_t n) {
+    uint32_t S;
+    uint64_t Wp, bytes;
+    std::vector<uint8_t> hc;
+    plan_layout(low, n, &S, &Wp, &hc, &bytes);
+    return bytes;
+}
+
+std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const cflr_graph *g) {
+    if (low.nmat() > kMaxMats) throw Error(CFLR_EUNSUPPORTED, "grammar needs more than 65536 matrices");
+    auto inst = std::make_shared<Instance>();
+    inst->hold = CtxRef(ctx);
+    inst->ctx = ctx;
+    inst->low = low;
+    inst->graph = g;
+    inst->n = g->n;
+    std::vector<uint8_t> has_col;
+    uint64_t bytes;
+    plan_layout(low, g->n, &inst->S, &inst->Wp, &has_col, &bytes);
+    inst->footprint = bytes;
+    inst->counts.assign(low.user_names.size(), -1);
+    const uint64_t layout_words = (uint64_t)g->n * inst->Wp;
+    const uint64_t sum_words = (uint64_t)g->n * inst->S;
+    if (bytes) inst->arena = DevBuf(ctx->pool.get(), bytes);
+    uint64_t *p = inst->arena.as<uint64_t>();
+    inst->mats.resize(low.nmat());
+    for (uint32_t x = 0; x < low.nmat(); x++) {
+        MatDev &M = inst->mats[x];
+        M.R = p;
+        p += layout_words;
+        M.RS = p;
+        p += sum_words;
+        M.C = M.CS = nullptr;
+        if (has_col[x]) {
+            M.C = p;
+            p += layout_words;
+            M.CS = p;
+            p += sum_words;
+        }
+    }
+    if (bytes) hip_check(hipMemsetAsync(inst->arena.ptr, 0, bytes, ctx->stream), "zero matrices");
+
+    // graph label -> matrices x with x -> label (after lowering)
+    std::map<std::string, uint32_t> term_id;
+    for (uint32_t t = 0; t < low.terminals.size(); t++) term_id[low.terminals[t]] = t;
+    std::vector<std::vector<uint32_t>> by_term(low.terminals.size());
+    for (auto &tm : low.term) by_term[tm.first].push_back(tm.second);
+    const uint32_t L = (uint32_t)g->label_names.size();
+    std::vector<uint32_t> ptr(L + 1, 0), mats;
+    uint32_t max_per_label = 0;
+    for (uint32_t l = 0; l < L; l++) {
+        auto it = term_id.find(g->label_names[l]);
+        if (it != term_id.end())
+            for (uint32_t x : by_term[it->second]) mats.push_back(x);
+        ptr[l + 1] = (uint32_t)mats.size();
+        max_per_label = std::max(max_per_label, ptr[l + 1] - ptr[l]);
+    }
+    inst->lm_ptr = DevBuf(ctx->pool.get(), ptr.size() * 4);
+    copy_sync(inst->lm_ptr.ptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, ctx->stream);
+    inst->lm_mat = DevBuf(ctx->pool.get(), std::max<size_t>(1, mats.size()) * 4);
+    if (!mats.empty())
+        copy_sync(inst->lm_mat.ptr, mats.data(), mats.size() * 4, hipMemcpyHostToDevice, ctx->stream);
+    inst->n_eps = (uint32_t)low.eps.size();
+    inst->eps_mat = DevBuf(ctx->pool.get(), std::max<size_t>(1, low.eps.size()) * 4);
+    if (!low.eps.empty())
+        copy_sync(inst->eps_mat.ptr, low.eps.data(), low.eps.size() * 4, hipMemcpyHostToDevice, ctx->stream);
+    inst->max_seeds = g->m * max_per_label + (uint64_t)g->n * inst->n_eps;
+    inst->stats.device_bytes = bytes;
+    return inst;
+}
+
+// ---------------------------------------------------------------------- Run
+
+Run::Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t row_capacity, uint32_t max_instances)
+    : hold_(ctx), ctx_(ctx), opts_(opts), s_(ctx->stream), row_cap_(row_capacity), max_inst_(max_instances) {
+    if (row_cap_ >= 0xFFFFFFF0ull) throw Error(CFLR_EUNSUPPORTED, "too many matrix rows for one run");
+    if (max_inst_ == 0 || max_inst_ > kMaxSlots)
+        throw Error(CFLR_EINVAL, "instances per run must be in [1, " + std::to_string(kMaxSlots) + "]");
+    DevPool *pool = ctx->pool.get();
+    free_rows_[0] = row_cap_;
+    d_rcnt_ = DevBuf(pool, (row_cap_ + 1) * 4);
+    d_ccnt_ = DevBuf(pool, (row_cap_ + 1) * 4);
+    d_bsum_ = DevBuf(pool, 2ull * scan_block_count(row_cap_) * 4);
+    d_counters_ = DevBuf(pool, 64);
+    d_inst_new_ = DevBuf(pool, (uint64_t)max_inst_ * 8);
+    d_inst_over_ = DevBuf(pool, (uint64_t)max_inst_ * 4);
+    hip_check(hipMemsetAsync(d_counters_.ptr, 0, 64, s_), "memset");
+    hip_check(hipMemsetAsync(d_inst_over_.ptr, 0, (uint64_t)max_inst_ * 4, s_), "memset");
+    // the row/column starts must read as "no new pairs" before the first sort
+    hip_check(launch_fill_u32(d_rcnt_.as<uint32_t>(), row_cap_ + 1, 0, s_), "fill");
+    hip_check(launch_fill_u32(d_ccnt_.as<uint32_t>(), row_cap_ + 1, 0, s_), "fill");
+    hip_check(hipHostMalloc((void **)&h_new_, (uint64_t)max_inst_ * 8, 0), "hipHostMalloc");
+    hip_check(hipHostMalloc((void **)&h_over_, (uint64_t)max_inst_ * 4, 0), "hipHostMalloc");
+    hip_check(hipHostMalloc((void **)&h_counters_, 64, 0), "hipHostMalloc");
+    hip_check(hipEventCreate(&ev0_), "event");
+    hip_check(hipEventCreate(&ev1_), "event");
+    uint64_t cap = opts_.delta_capacity ? opts_.delta_capacity : ctx->delta_capacity_hint;
+    if (!cap) cap = std::max<uint64_t>(1ull << 22, std::min<uint64_t>(16 * row_cap_, 1ull << 28));
+    ensure_capacity(cap, false);
+    log_ = std::getenv("CFLR_LOG") != nullptr;
+    uint32_t waves = opts_.grid_waves ? opts_.grid_waves : ctx->grid_waves_tuned;
+    grid_ = waves ? waves : ctx->num_cu * 32;
+}
+
+Run::~Run() {
+    if (h_new_) (void)hipHostFree(h_new_);
+    if (h_over_) (void)hipHostFree(h_over_);
+    if (h_counters_) (void)hipHostFree(h_counters_);
+    if (ev0_) (void)hipEventDestroy(ev0_);
+    if (ev1_) (void)hipEventDestroy(ev1_);
+}
+
+void Run::ensure_capacity(uint64_t pairs, bool keep) {
+    if (pairs <= ap_cap_) return;
+    const uint64_t limit = 0xFFFFFFF0ull;
+    if (ap_cap_ >= limit) throw Error(CFLR_ENOMEM, "new-pair buffer at its 2^32 limit");
+    pairs = std::min(pairs, limit);
+    DevPool *pool = ctx_->pool.get();
+    DevBuf *bufs[7] = {&d_ap_key_, &d_ap_i_, &d_ap_j_, &d_rs_i_, &d_rs_k_, &d_cs_j_, &d_cs_k_};
+    for (DevBuf *b : bufs) {
+        DevBuf nb(pool, pairs * 4);
+        if (keep && b->ptr) hip_check(hipMemcpyAsync(nb.ptr, b->ptr, ap_cap_ * 4, hipMemcpyDeviceToDevice, s_),
+                                      "D2D");
+        hip_check(hipStreamSynchronize(s_), "sync");
+        *b = std::move(nb);
+    }
+    ap_cap_ = pairs;
+    ctx_->delta_capacity_hint = std::max(ctx_->delta_capacity_hint, pairs);
+}
+
+uint64_t Run::alloc_rows(uint64_t rows) {
+    for (auto it = free_rows_.begin(); it != free_rows_.end(); ++it) {
+        if (it->second >= rows) {
+            uint64_t base = it->first, len = it->second;
+            free_rows_.erase(it);
+            if (len > rows) free_rows_[base + rows] = len - rows;
+            return base;
+        }
+    }
+    throw Error(CFLR_ENOMEM, "run row space exhausted");
+}
+
+void Run::free_rows(uint64_t base, uint64_t rows) {
+    if (!rows) return;
+    auto it = free_rows_.insert({base, rows}).first;
+    auto nx = std::next(it);
+    if (nx != free_rows_.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        free_rows_.erase(nx);
+    }
+    if (it != free_rows_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            free_rows_.erase(it);
+        }
+    }
+}
+
+void Run::add(const std::shared_ptr<Instance> &inst) {
+    if (insts_.size() >= max_inst_) throw Error(CFLR_EINVAL, "run is full");
+    const uint64_t rows = (uint64_t)inst->low.nmat() * inst->n;
+    inst->rowbase = (uint32_t)alloc_rows(rows);
+    // slot: lowest index not used by a running instance
+    std::vector<uint8_t> used(max_inst_, 0);
+    for (auto &o : insts_) used[o->slot] = 1;
+    uint32_t slot = 0;
+    while (used[slot]) slot++;
+    inst->slot = slot;
+    insts_.push_back(inst);
+    dirty_ = true;
+    // seeds: appended after whatever is already waiting in the buffer
+    hip_check(hipStreamSynchronize(s_), "sync");
+    unsigned long long cur = 0;
+    copy_sync(&cur, d_counters_.ptr, 8, hipMemcpyDeviceToHost, s_);
+    ensure_capacity(cur + inst->max_seeds, true);
+    hip_check(launch_fill_u64(d_inst_new_.as<unsigned long long>() + slot, 1, 0, s_), "fill");
+    DevBuf dmats(ctx_->pool.get(), inst->mats.size() * sizeof(MatDev));
+    hip_check(hipMemcpyAsync(dmats.ptr, inst->mats.data(), inst->mats.size() * sizeof(MatDev),
+                             hipMemcpyHostToDevice, s_),
+              "H2D");
+    SeedArgs A{};
+    A.mats = dmats.as<MatDev>();
+    A.I = InstDev{inst->n, inst->S, inst->rowbase, 0};
+    A.inst = slot;
+    A.src = inst->graph->src.as<uint32_t>();
+    A.dst = inst->graph->dst.as<uint32_t>();
+    A.lab = inst->graph->lab.as<uint32_t>();
+    A.m = inst->graph->m;
+    A.lm_ptr = inst->lm_ptr.as<uint32_t>();
+    A.lm_mat = inst->lm_mat.as<uint32_t>();
+    A.eps_mat = inst->eps_mat.as<uint32_t>();
+    A.n_eps = inst->n_eps;
+    A.ap_key = d_ap_key_.as<uint32_t>();
+    A.ap_i = d_ap_i_.as<uint32_t>();
+    A.ap_j = d_ap_j_.as<uint32_t>();
+    A.ap_count = d_counters_.as<unsigned long long>();
+    A.ap_cap = ap_cap_;
+    A.inst_new = d_inst_new_.as<unsigned long long>();
+    A.inst_overflow = d_inst_over_.as<uint32_t>();
+    hip_check(launch_seed(A, s_), "seed");
+    hip_check(hipMemcpyAsync(h_new_ + slot, d_inst_new_.as<unsigned long long>() + slot, 8,
+                             hipMemcpyDeviceToHost, s_),
+              "D2H");
+    hip_check(hipStreamSynchronize(s_), "sync");
+    inst->stats.seed_pairs = h_new_[slot];
+    inst->rounds = 0;
+    inst->done = false;
+}
+
+uint64_t Run::row_hi() const {
+    // rows at or above the last free range's base are unused
+    if (!free_rows_.empty()) {
+        auto last = std::prev(free_rows_.end());
+        if (last->first + last->second == row_cap_) return last->first;
+    }
+    return row_cap_;
+}
+
+void Run::remove(Instance *inst) {
+    for (size_t k = 0; k < insts_.size(); k++) {
+        if (insts_[k].get() == inst) {
+            if (!inst->done)
+                hip_check(launch_purge_slot(d_ap_key_.as<uint32_t>(), d_counters_.as<unsigned long long>(),
+                                            ap_cap_, inst->slot, ctx_->num_cu * 4, s_),
+                          "purge");
+            free_rows(inst->rowbase, (uint64_t)inst->low.nmat() * inst->n);
+            insts_.erase(insts_.begin() + (long)k);
+            dirty_ = true;
+            return;
+        }
+    }
+}
+
+void Run::rebuild_tables() {
+    if (!dirty_) return;
+    DevPool *pool = ctx_->pool.get();
+    std::vector<InstDev> hi;
+    std::vector<MatDev> hm;
+    std::vector<EntryDev> he;
+    std::vector<uint64_t> toff;
+    uint64_t tbits = 0;
+    // instance table indexed by slot
+    hi.assign(max_inst_, InstDev{0, 1, 0, 0});
+    toff.assign(max_inst_, 0);
+    for (auto &ip : insts_) {
+        Instance &in = *ip;
+        hi[in.slot] = InstDev{in.n, in.S, in.rowbase, (uint32_t)hm.size()};
+        for (auto &m : in.mats) hm.push_back(m);
+        for (auto &b : in.low.binary) {
+            he.push_back(EntryDev{in.slot, b.c, b.a, b.b, 0});
+            he.push_back(EntryDev{in.slot, b.c, b.a, b.b, 1});
+        }
+        toff[in.slot] = tbits;
+        tbits += (uint64_t)in.low.nmat() * 2 * in.n * in.S;
+    }
+    nent_ = (uint32_t)he.size();
+    d_inst_ = DevBuf(pool, hi.size() * sizeof(InstDev));
+    d_mats_ = DevBuf(pool, std::max<size_t>(1, hm.size()) * sizeof(MatDev));
+    d_ent_ = DevBuf(pool, std::max<size_t>(1, he.size()) * sizeof(EntryDev));
+    d_ent_start_ = DevBuf(pool, std::max<size_t>(1, he.size()) * 4);
+    d_ent_cnt_ = DevBuf(pool, std::max<size_t>(1, he.size()) * 4);
+    d_prefix_ = DevBuf(pool, (he.size() + 1) * 8);
+    copy_sync(d_inst_.ptr, hi.data(), hi.size() * sizeof(InstDev), hipMemcpyHostToDevice, s_);
+    if (!hm.empty())
+        copy_sync(d_mats_.ptr, hm.data(), hm.size() * sizeof(MatDev), hipMemcpyHostToDevice, s_);
+    if (!he.empty())
+        copy_sync(d_ent_.ptr, he.data(), he.size() * sizeof(EntryDev), hipMemcpyHostToDevice, s_);
+    if (opts_.count_traffic) {
+        touched_bits_ = tbits;
+        d_touched_ = DevBuf(pool, std::max<uint64_t>(8, (tbits + 31) / 32 * 4));
+        d_touched_off_ = DevBuf(pool, toff.size() * 8);
+        copy_sync(d_touched_off_.ptr, toff.data(), toff.size() * 8, hipMemcpyHostToDevice, s_);
+    }
+    dirty_ = false;
+}
+
+void Run::sort_appended() {
+    SortArgs S{};
+    S.inst = d_inst_.as<InstDev>();
+    S.ap_key = d_ap_key_.as<uint32_t>();
+    S.ap_i = d_ap_i_.as<uint32_t>();
+    S.ap_j = d_ap_j_.as<uint32_t>();
+    S.ap_count = d_counters_.as<unsigned long long>();
+    S.ap_cap = ap_cap_;
+    S.rcnt = d_rcnt_.as<uint32_t>();
+    S.ccnt = d_ccnt_.as<uint32_t>();
+    S.rs_i = d_rs_i_.as<uint32_t>();
+    S.rs_k = d_rs_k_.as<uint32_t>();
+    S.cs_j = d_cs_j_.as<uint32_t>();
+    S.cs_k = d_cs_k_.as<uint32_t>();
+    S.halt = reinterpret_cast<uint32_t *>(d_counters_.as<unsigned long long>() + 3);
+    hip_check(launch_sort(S, row_hi(), d_bsum_.as<uint32_t>(), ctx_->num_cu * 8, s_), "sort");
+    // the appended pairs are consumed
+    hip_check(launch_fill_u64(d_counters_.as<unsigned long long>(), 1, 0, s_), "fill");
+}
+
+void Run::read_flags() {
+    hip_check(hipMemcpyAsync(h_new_, d_inst_new_.ptr, (uint64_t)max_inst_ * 8, hipMemcpyDeviceToHost, s_), "D2H");
+    hip_check(hipMemcpyAsync(h_over_, d_inst_over_.ptr, (uint64_t)max_inst_ * 4, hipMemcpyDeviceToHost, s_),
+              "D2H");
+    hip_check(hipMemcpyAsync(h_counters_, d_counters_.ptr, 32, hipMemcpyDeviceToHost, s_), "D2H");
+    hip_check(hipStreamSynchronize(s_), "sync");
+}
+
+uint32_t Run::round() {
+    if (insts_.empty()) return 0;
+    // pairs appended since the last round (seeds of admitted instances, or
+    // the previous round's new pairs) become this round's dA / dB
+    if (!opts_.semi_naive) {
+        // Algorithm 1 as printed: every pair of M takes part in every round,
+        // so the new-pair buffer is refilled with all of M
+        hip_check(launch_fill_u64(d_counters_.as<unsigned long long>(), 1, 0, s_), "fill");
+        uint64_t total_pairs = 0;
+        std::vector<DevBuf> dmats;
+        for (auto &ip : insts_) {
+            DevBuf cnt(ctx_->pool.get(), std::max<uint32_t>(1, ip->n) * 4ull);
+            DevBuf tot(ctx_->pool.get(), 8);
+            hip_check(launch_fill_u64(tot.as<unsigned long long>(), 1, 0, s_), "fill");
+            for (uint32_t x = 0; x < ip->low.nmat(); x++)
+                hip_check(launch_row_count(ip->mats[x].R, ip->n, ip->S, cnt.as<uint32_t>(),
+                                           tot.as<unsigned long long>(), s_),
+                          "count");
+            unsigned long long t = 0;
+            copy_sync(&t, tot.ptr, 8, hipMemcpyDeviceToHost, s_);
+            total_pairs += t;
+        }
+        ensure_capacity(total_pairs, false);
+        for (auto &ip : insts_) {
+            DevBuf dm(ctx_->pool.get(), ip->mats.size() * sizeof(MatDev));
+            copy_sync(dm.ptr, ip->mats.data(), ip->mats.size() * sizeof(MatDev), hipMemcpyHostToDevice, s_);
+            InstDev I{ip->n, ip->S, ip->rowbase, 0};
+            hip_check(launch_extract_all(dm.as<MatDev>(), I, ip->slot, ip->low.nmat(), d_ap_key_.as<uint32_t>(),
+                                         d_ap_i_.as<uint32_t>(), d_ap_j_.as<uint32_t>(),
+                                         d_counters_.as<unsigned long long>(), ap_cap_,
+                                         d_inst_over_.as<uint32_t>() + ip->slot, s_),
+                      "extract");
+            hip_check(hipStreamSynchronize(s_), "sync");
+        }
+    }
+    rebuild_tables();
+    sort_appended();
+    for (auto &ip : insts_)
+        hip_check(launch_fill_u64(d_inst_new_.as<unsigned long long>() + ip->slot, 1, 0, s_), "fill");
+
+    unsigned long long *counters = d_counters_.as<unsigned long long>();
+    uint32_t *halt = reinterpret_cast<uint32_t *>(counters + 3);
+    PrepArgs P{};
+    P.inst = d_inst_.as<InstDev>();
+    P.ent = d_ent_.as<EntryDev>();
+    P.nent = nent_;
+    P.rptr = d_rcnt_.as<uint32_t>();
+    P.cptr = d_ccnt_.as<uint32_t>();
+    P.ent_start = d_ent_start_.as<uint32_t>();
+    P.ent_cnt = d_ent_cnt_.as<uint32_t>();
+    P.item_prefix = d_prefix_.as<uint64_t>();
+    P.work_counter = counters + 1;
+    P.halt = halt;
+
+    for (int attempt = 0;; attempt++) {
+        if (nent_) hip_check(launch_prep(P, s_), "prep");
+        if (opts_.count_traffic && touched_bits_)
+            hip_check(launch_fill_u32(d_touched_.as<uint32_t>(), (touched_bits_ + 31) / 32, 0, s_), "fill");
+        ProductArgs A{};
+        A.inst = d_inst_.as<InstDev>();
+        A.mats = d_mats_.as<MatDev>();
+        A.ent = d_ent_.as<EntryDev>();
+        A.ent_start = d_ent_start_.as<uint32_t>();
+        A.ent_cnt = d_ent_cnt_.as<uint32_t>();
+        A.item_prefix = d_prefix_.as<uint64_t>();
+        A.nent = nent_;
+        A.rs_i = d_rs_i_.as<uint32_t>();
+        A.rs_k = d_rs_k_.as<uint32_t>();
+        A.cs_j = d_cs_j_.as<uint32_t>();
+        A.cs_k = d_cs_k_.as<uint32_t>();
+        A.ap_key = d_ap_key_.as<uint32_t>();
+        A.ap_i = d_ap_i_.as<uint32_t>();
+        A.ap_j = d_ap_j_.as<uint32_t>();
+        A.ap_count = counters;
+        A.ap_cap = ap_cap_;
+        A.inst_overflow = d_inst_over_.as<uint32_t>();
+        A.halt = halt;
+        A.work_counter = counters + 1;
+        A.touched = d_touched_.as<uint32_t>();
+        A.touched_off = d_touched_off_.as<uint64_t>();
+        A.algo_bytes = counters + 2;
+        if (nent_) {
+            if (opts_.kernel_timing) hip_check(hipEventRecord(ev0_, s_), "event");
+            hip_check(launch_product(A, grid_, opts_.count_traffic != 0, s_), "product");
+            if (opts_.kernel_timing) hip_check(hipEventRecord(ev1_, s_), "event");
+            product_launches_++;
+        }
+        read_flags();
+        if (opts_.kernel_timing && nent_) {
+            float ms = 0;
+            hip_check(hipEventElapsedTime(&ms, ev0_, ev1_), "event");
+            product_ms_ += ms;
+        }
+        uint32_t halted = (uint32_t)(h_counters_[3] & 0xFFFFFFFFu);
+        if (!halted) break;
+        // overflow: keep [0, cap) (pairs and holes), grow, re-run the round
+        reruns_++;
+        uint64_t asked = h_counters_[0];
+        uint64_t old_cap = ap_cap_;
+        ensure_capacity(std::max<uint64_t>(2 * old_cap, asked + asked / 2), true);
+        unsigned long long v = old_cap;
+        copy_sync(counters, &v, 8, hipMemcpyHostToDevice, s_);
+        hip_check(launch_fill_u32(halt, 1, 0, s_), "fill");
+        hip_check(launch_fill_u32(d_inst_over_.as<uint32_t>(), max_inst_, 0, s_), "fill");
+        if (attempt > 64) throw Error(CFLR_ENOMEM, "new-pair buffer keeps overflowing");
+    }
+    if (opts_.count_traffic) algo_bytes_ = h_counters_[2];
+    {
+        SettleArgs T{};
+        T.inst = d_inst_.as<InstDev>();
+        T.mats = d_mats_.as<MatDev>();
+        T.ap_key = d_ap_key_.as<uint32_t>();
+        T.ap_i = d_ap_i_.as<uint32_t>();
+        T.ap_j = d_ap_j_.as<uint32_t>();
+        T.ap_count = counters;
+        T.ap_cap = ap_cap_;
+        T.inst_new = d_inst_new_.as<unsigned long long>();
+        T.halt = halt;
+        hip_check(launch_settle(T, ctx_->num_cu * 8, s_), "settle");
+        read_flags();
+    }
+    if (log_) {
+        uint64_t items = 0;
+        if (nent_) copy_sync(&items, d_prefix_.as<uint64_t>() + nent_, 8, hipMemcpyDeviceToHost, s_);
+        uint64_t fresh = 0;
+        for (auto &ip : insts_) fresh += h_new_[ip->slot];
+        std::fprintf(stderr, "[cflr] round %u: instances %zu items %llu appended %llu new %llu cap %llu reruns %u\n",
+                     (unsigned)round_no_, insts_.size(), (unsigned long long)items,
+                     (unsigned long long)h_counters_[0], (unsigned long long)fresh,
+                     (unsigned long long)ap_cap_, reruns_);
+    }
+    round_no_++;
+
+    uint32_t running = 0;
+    for (auto &ip : insts_) {
+        Instance &in = *ip;
+        if (in.done) continue;
+        in.rounds++;
+        uint64_t fresh = h_new_[in.slot];
+        in.stats.new_pairs += fresh;
+        in.stats.max_delta = std::max<uint64_t>(in.stats.max_delta, fresh);
+        if (fresh == 0) in.done = true;
+        else running++;
+    }
+    return running;
+}
+
+// ------------------------------------------------------------------ readout
+
+void instance_counts(Instance &inst) {
+    bool need = false;
+    for (auto c : inst.counts) need |= c < 0;
+    if (!need) return;
+    cflr_ctx *ctx = inst.ctx;
+    hipStream_t s = ctx->stream;
+    const uint32_t U = (uint32_t)inst.low.user_names.size();
+    DevBuf cnt(ctx->pool.get(), std::max<uint32_t>(1, inst.n) * 4ull);
+    DevBuf tot(ctx->pool.get(), 8ull * U);
+    hip_check(hipMemsetAsync(tot.ptr, 0, 8ull * U, s), "memset");
+    for (uint32_t x = 0; x < U; x++)
+        hip_check(launch_row_count(inst.mats[x].R, inst.n, inst.S, cnt.as<uint32_t>(),
+                                   tot.as<unsigned long long>() + x, s),
+                  "count");
+    std::vector<unsigned long long> h(U);
+    hip_check(hipMemcpyAsync(h.data(), tot.ptr, 8ull * U, hipMemcpyDeviceToHost, s), "D2H");
+    hip_check(hipStreamSynchronize(s), "sync");
+    uint64_t total = 0;
+    for (uint32_t x = 0; x < U; x++) {
+        inst.counts[x] = (int64_t)h[x];
+        total += h[x];
+    }
+    inst.stats.total_pairs = total;
+}
+
+void instance_copy(Instance &inst, uint32_t nt, uint32_t *src, uint32_t *dst, uint64_t capacity,
+                   bool on_device, uint64_t *written) {
+    instance_counts(inst);
+    const uint64_t count = (uint64_t)inst.counts[nt];
+    if (capacity < count) throw Error(CFLR_EINVAL, "capacity smaller than the pair count");
+    *written = count;
+    if (!count) return;
+    cflr_ctx *ctx = inst.ctx;
+    hipStream_t s = ctx->stream;
+    DevBuf cnt(ctx->pool.get(), (uint64_t)inst.n * 4);
+    DevBuf off(ctx->pool.get(), (uint64_t)inst.n * 8);
+    hip_check(launch_row_count(inst.mats[nt].R, inst.n, inst.S, cnt.as<uint32_t>(), nullptr, s), "count");
+    if (on_device) {
+        hip_check(launch_row_write(inst.mats[nt].R, inst.n, inst.S, cnt.as<uint32_t>(), off.as<uint64_t>(), src,
+                                   dst, s),
+                  "readout");
+        hip_check(hipStreamSynchronize(s), "sync");
+        return;
+    }
+    DevBuf dsrc(ctx->pool.get(), count * 4), ddst(ctx->pool.get(), count * 4);
+    hip_check(launch_row_write(inst.mats[nt].R, inst.n, inst.S, cnt.as<uint32_t>(), off.as<uint64_t>(),
+                               dsrc.as<uint32_t>(), ddst.as<uint32_t>(), s),
+              "readout");
+    hip_check(hipMemcpyAsync(src, dsrc.ptr, count * 4, hipMemcpyDeviceToHost, s), "D2H");
+    hip_check(hipMemcpyAsync(dst, ddst.ptr, count * 4, hipMemcpyDeviceToHost, s), "D2H");
+    hip_check(hipStreamSynchronize(s), "sync");
+}
+
+}  // namespace cflr

@@ -1,0 +1,232 @@
+// engine.h -- host engine: context, device pool, instances and rounds.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace cflr {
+
+void hip_check(hipError_t e, const char *what);
+
+// Caching device allocator: blocks are kept per size after release and
+// handed out again, so repeated solves of one shape allocate once.
+class DevPool {
+   public:
+    explicit DevPool(int device) : device_(device) {}
+    ~DevPool();
+    void *alloc(size_t bytes);
+    void release(void *p);
+    void trim();  // return cached blocks to the driver
+    uint64_t held() const { return held_; }
+
+   private:
+    int device_;
+    std::mutex mu_;
+    std::multimap<size_t, void *> cache_;
+    std::map<void *, size_t> live_;
+    uint64_t held_ = 0;
+};
+
+// RAII device buffer from a pool
+struct DevBuf {
+    DevPool *pool = nullptr;
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(DevPool *p, size_t b) : pool(p), ptr(b ? p->alloc(b) : nullptr), bytes(b) {}
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept { *this = std::move(o); }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        reset();
+        pool = o.pool;
+        ptr = o.ptr;
+        bytes = o.bytes;
+        o.ptr = nullptr;
+        o.bytes = 0;
+        return *this;
+    }
+    ~DevBuf() { reset(); }
+    void reset() {
+        if (ptr && pool) pool->release(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T *as() const { return static_cast<T *>(ptr); }
+};
+
+}  // namespace cflr
+
+struct cflr_ctx {
+    // one reference for the caller's handle plus one per graph, instance,
+    // run and server using it; the context is torn down at zero, so objects
+    // freed after cflr_ctx_destroy still find their pool and stream
+    std::atomic<int> refs{1};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint32_t num_cu = 0;
+    std::unique_ptr<cflr::DevPool> pool;
+    uint64_t delta_capacity_hint = 0;  // grown new-pair capacity, reused by later solves
+    uint32_t grid_waves_tuned = 0;     // autotuned product grid (0 = not yet)
+};
+
+namespace cflr {
+
+void ctx_retain(cflr_ctx *ctx);
+void ctx_release(cflr_ctx *ctx);
+
+// Holds a reference to a context for the lifetime of its owner.  Declare it
+// as the owner's first member so that it is released after every buffer.
+struct CtxRef {
+    cflr_ctx *p = nullptr;
+    CtxRef() = default;
+    explicit CtxRef(cflr_ctx *c) : p(c) {
+        if (p) ctx_retain(p);
+    }
+    CtxRef(const CtxRef &o) : CtxRef(o.p) {}
+    CtxRef &operator=(const CtxRef &o) {
+        if (this != &o) {
+            if (o.p) ctx_retain(o.p);
+            if (p) ctx_release(p);
+            p = o.p;
+        }
+        return *this;
+    }
+    ~CtxRef() {
+        if (p) ctx_release(p);
+    }
+};
+
+}  // namespace cflr
+
+struct cflr_graph {
+    cflr::CtxRef hold;
+    cflr_ctx *ctx = nullptr;
+    uint32_t n = 0;
+    uint64_t m = 0;
+    cflr::DevBuf src, dst, lab;
+    std::vector<std::string> label_names;
+};
+
+namespace cflr {
+
+// One graph being solved (or solved): its matrices live in `arena`.
+struct Instance {
+    CtxRef hold;
+    cflr_ctx *ctx = nullptr;
+    Lowered low;  // copy: results outlive the grammar handle
+    uint32_t n = 0, S = 0;
+    uint64_t Wp = 0;
+    DevBuf arena;
+    std::vector<MatDev> mats;
+    uint64_t footprint = 0;
+    // seeding tables
+    DevBuf lm_ptr, lm_mat, eps_mat;
+    uint32_t n_eps = 0;
+    uint64_t max_seeds = 0;
+    const cflr_graph *graph = nullptr;
+    // state
+    uint32_t rowbase = 0;
+    uint32_t slot = 0;
+    uint32_t rounds = 0;
+    bool done = false;
+    cflr_status status = CFLR_OK;
+    std::string error;
+    cflr_stats stats{};
+    // readout cache
+    std::vector<int64_t> counts;  // per user NT, -1 = unknown
+};
+
+// Device bytes an instance of this grammar on n vertices will hold.
+uint64_t instance_footprint(const Lowered &low, uint32_t n);
+
+std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const cflr_graph *g);
+
+// A set of instances advancing round by round together (one fused product
+// launch per round over all of them).
+class Run {
+   public:
+    Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t row_capacity, uint32_t max_instances);
+    ~Run();
+    // Admit an instance: assigns its rows, seeds its pairs (they become the
+    // next round's new pairs).  Between rounds only.
+    void add(const std::shared_ptr<Instance> &inst);
+    // Drop an instance (finished); between rounds only.
+    void remove(Instance *inst);
+    // One round over every admitted instance.  Instances whose round derived
+    // nothing are marked done.  Returns the number still running.
+    uint32_t round();
+    size_t size() const { return insts_.size(); }
+    const std::vector<std::shared_ptr<Instance>> &instances() const { return insts_; }
+    double product_ms() const { return product_ms_; }
+    uint64_t product_launches() const { return product_launches_; }
+    uint64_t algo_bytes() const { return algo_bytes_; }
+    uint32_t reruns() const { return reruns_; }
+    uint64_t delta_capacity() const { return ap_cap_; }
+
+   private:
+    CtxRef hold_;  // first member: released after every buffer below
+    void rebuild_tables();
+    void ensure_capacity(uint64_t pairs, bool keep);
+    void sort_appended();
+    uint64_t alloc_rows(uint64_t rows);
+    void free_rows(uint64_t base, uint64_t rows);
+    void read_flags();
+    uint64_t row_hi() const;
+
+    cflr_ctx *ctx_;
+    cflr_opts opts_;
+    hipStream_t s_;
+    std::vector<std::shared_ptr<Instance>> insts_;
+    bool dirty_ = true;
+    uint64_t row_cap_;
+    uint32_t max_inst_;
+    std::map<uint64_t, uint64_t> free_rows_;  // base -> length
+    // device tables
+    DevBuf d_inst_, d_mats_, d_ent_, d_ent_start_, d_ent_cnt_, d_prefix_;
+    uint32_t nent_ = 0;
+    DevBuf d_rcnt_, d_ccnt_, d_bsum_;
+    DevBuf d_ap_key_, d_ap_i_, d_ap_j_, d_rs_i_, d_rs_k_, d_cs_j_, d_cs_k_;
+    uint64_t ap_cap_ = 0;
+    DevBuf d_counters_;  // [0] ap_count, [1] work_counter, [2] algo_bytes, [3] halt (u32)
+    DevBuf d_inst_new_, d_inst_over_;
+    DevBuf d_touched_, d_touched_off_;
+    uint64_t touched_bits_ = 0;
+    // host mirrors (pinned)
+    unsigned long long *h_new_ = nullptr;
+    uint32_t *h_over_ = nullptr;
+    unsigned long long *h_counters_ = nullptr;
+    hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+    double product_ms_ = 0;
+    uint64_t product_launches_ = 0;
+    uint64_t algo_bytes_ = 0;
+    uint32_t reruns_ = 0;
+    uint32_t grid_ = 0;
+    uint32_t round_no_ = 0;
+    bool log_ = false;
+};
+
+void instance_counts(Instance &inst);
+// keep only the row-major matrices of the user non-terminals (finished instances)
+void compact_instance(Instance &in);
+void set_last_error(const std::string &msg);
+void copy_sync(void *dst, const void *src, size_t bytes, hipMemcpyKind kind, hipStream_t s);
+void instance_copy(Instance &inst, uint32_t nt, uint32_t *src, uint32_t *dst, uint64_t capacity,
+                   bool on_device, uint64_t *written);
+
+}  // namespace cflr
+
+struct cflr_result {
+    std::shared_ptr<cflr::Instance> inst;
+};

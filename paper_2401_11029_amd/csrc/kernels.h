@@ -1,0 +1,157 @@
+// kernels.h -- device data layout shared by the kernels and the host engine.
+//
+// Every matrix of an instance (one per lowered non-terminal) is a dense bit
+// matrix over n x n, stored twice when the productions need both (Section 3,
+// optimisation 2): R (row-major: row i holds bit j for pair (i, j)) and C
+// (column-major: row j holds bit i).  A row is Wp = 64 * S words of 64 bits,
+// cut into S segments of 64 words (4096 columns); one wave of 64 lanes owns
+// one segment, one word per lane.  RS / CS hold one summary word per row
+// segment whose bit l says "word l of this segment is non-zero", so sparse
+// rows are skipped without reading them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cflr {
+
+constexpr uint32_t kWave = 64;        // lanes per wavefront (CDNA)
+constexpr uint32_t kSegWords = 64;    // words per row segment
+constexpr uint32_t kPairsPerItem = 64;  // new pairs per product work item
+
+// Key of an appended pair: bits 0..15 matrix, bits 16..29 instance slot,
+// bit 30 "settled" (both layouts already hold the pair: seeds, restarts),
+// bit 31 "found by the column part" (only the column-major copy holds it
+// until the settle pass).  kHole marks an unused slot.
+constexpr uint32_t kHole = 0xFFFFFFFFu;
+constexpr uint32_t kSettled = 0x40000000u;
+constexpr uint32_t kColFound = 0x80000000u;
+constexpr uint32_t kMaxSlots = 0x3FFFu;
+constexpr uint32_t kMaxMats = 0x10000u;
+__host__ __device__ inline uint32_t pair_key(uint32_t slot, uint32_t mat, uint32_t flags) {
+    return flags | (slot << 16) | mat;
+}
+__host__ __device__ inline uint32_t key_slot(uint32_t key) { return (key >> 16) & kMaxSlots; }
+__host__ __device__ inline uint32_t key_mat(uint32_t key) { return key & 0xFFFFu; }
+
+struct MatDev {
+    uint64_t *R, *RS;  // row-major bits and summaries (always present)
+    uint64_t *C, *CS;  // column-major copy (null when no production needs it)
+};
+
+struct InstDev {
+    uint32_t n;        // vertices
+    uint32_t S;        // segments per row; Wp = 64 * S
+    uint32_t rowbase;  // first row of this instance in the new-pair row space
+    uint32_t mat_off;  // first MatDev of this instance
+};
+
+// One (instance, production, part) of a round; part 0 = rows of the new
+// pairs of a times B (row by row), part 1 = A times the new pairs of b
+// (column by column).
+struct EntryDev {
+    uint32_t inst, c, a, b, part;
+};
+
+
+// ------------------------------------------------------------ kernel arguments
+
+struct ProductArgs {
+    const InstDev *inst;
+    const MatDev *mats;
+    const EntryDev *ent;
+    const uint32_t *ent_start;    // first new pair of the entry's operand
+    const uint32_t *ent_cnt;      // number of new pairs of the operand
+    const uint64_t *item_prefix;  // exclusive prefix of items per entry; [nent] = total
+    uint32_t nent;
+    const uint32_t *rs_i, *rs_k;  // new pairs (i, k) in row order
+    const uint32_t *cs_j, *cs_k;  // new pairs (k, j) stored as (j, k) in column order
+    uint32_t *ap_key, *ap_i, *ap_j;   // appended new pairs: (key, i, j)
+    unsigned long long *ap_count;
+    uint64_t ap_cap;
+    uint32_t *inst_overflow;       // per instance: an append did not fit
+    uint32_t *halt;                // any overflow: later kernels of the round skip
+    unsigned long long *work_counter;
+    // traffic accounting (STATS): first-touch bits per (matrix, layout, row, segment)
+    uint32_t *touched;             // bit array
+    const uint64_t *touched_off;   // per instance: bit offset of its matrices
+    unsigned long long *algo_bytes;
+};
+
+struct PrepArgs {
+    const InstDev *inst;
+    const EntryDev *ent;
+    uint32_t nent;
+    const uint32_t *rptr, *cptr;  // row / column starts of the new pairs
+    uint32_t *ent_start, *ent_cnt;
+    uint64_t *item_prefix;
+    unsigned long long *work_counter;
+    const uint32_t *halt;
+};
+
+struct SortArgs {
+    const InstDev *inst;
+    const uint32_t *ap_key, *ap_i, *ap_j;
+    const unsigned long long *ap_count;
+    uint64_t ap_cap;
+    uint32_t *rcnt, *ccnt;       // counts -> inclusive scan -> starts (after scatter)
+    uint32_t *rs_i, *rs_k, *cs_j, *cs_k;
+    const uint32_t *halt;
+};
+
+// Second half of a round: the part that did not own a new pair's
+// authoritative layout copies it into the other layout; a pair the column
+// part found that the row part also found this round is dropped.  Counts
+// the surviving new pairs per instance.
+struct SettleArgs {
+    const InstDev *inst;
+    const MatDev *mats;
+    uint32_t *ap_key;
+    const uint32_t *ap_i, *ap_j;
+    const unsigned long long *ap_count;
+    uint64_t ap_cap;
+    unsigned long long *inst_new;
+    const uint32_t *halt;
+};
+
+struct SeedArgs {
+    MatDev *mats;  // this instance's matrices (device array)
+    InstDev I;
+    uint32_t inst;
+    const uint32_t *src, *dst, *lab;
+    uint64_t m;
+    const uint32_t *lm_ptr, *lm_mat;  // graph label -> matrices with x -> label
+    const uint32_t *eps_mat;
+    uint32_t n_eps;
+    uint32_t *ap_key, *ap_i, *ap_j;
+    unsigned long long *ap_count;
+    uint64_t ap_cap;
+    unsigned long long *inst_new;
+    uint32_t *inst_overflow;
+};
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_product(const ProductArgs &A, uint32_t grid, bool stats, hipStream_t s);
+hipError_t launch_prep(const PrepArgs &A, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *a, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long v, hipStream_t s);
+// counting sort of the appended pairs over rows [0, nrows] (nrows + 1 counters)
+hipError_t launch_sort(const SortArgs &A, uint64_t nrows, uint32_t *bsum, uint32_t sort_grid,
+                       hipStream_t s);
+uint32_t scan_block_count(uint64_t nrows);
+hipError_t launch_settle(const SettleArgs &A, uint32_t grid, hipStream_t s);
+hipError_t launch_purge_slot(uint32_t *ap_key, const unsigned long long *ap_count, uint64_t ap_cap,
+                             uint32_t slot, uint32_t grid, hipStream_t s);
+hipError_t launch_seed(const SeedArgs &A, hipStream_t s);
+hipError_t launch_extract_all(const MatDev *mats, const InstDev &I, uint32_t slot, uint32_t nmat,
+                              uint32_t *ap_key,
+                              uint32_t *ap_i, uint32_t *ap_j, unsigned long long *ap_count,
+                              uint64_t ap_cap, uint32_t *overflow, hipStream_t s);
+hipError_t launch_row_count(const uint64_t *R, uint32_t n, uint32_t S, uint32_t *cnt,
+                            unsigned long long *total, hipStream_t s);
+hipError_t launch_row_write(const uint64_t *R, uint32_t n, uint32_t S, const uint32_t *cnt,
+                            uint64_t *off, uint32_t *src, uint32_t *dst, hipStream_t s);
+
+}  // namespace cflr

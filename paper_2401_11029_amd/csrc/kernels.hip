@@ -1,0 +1,797 @@
+// kernels.hip -- HIP kernels for gfx950 (CDNA4, wave64).
+//
+// One round of the semi-naive fixpoint (Section 3, optimisations 1 and 2):
+// for every binary production c -> a b,
+//
+//     New_c = ((dA . B) U (A . dB)) \ M_c,      M_c <- M_c U New_c,
+//
+// where dA, dB are the pairs added to a and b in the previous round.  The
+// paper's identity M.M = (M_old.dM) U (dM.M) U (M_old.M_old) is used with A in
+// place of A_old in the second product; that only repeats dA.dB, which the
+// first product already covers, and saves materialising M_old.
+//
+// Kernels:
+//   product_kernel  persistent; one wave per work item = (instance,
+//                   production, part, block of 64 new pairs, row segment).
+//                   Part 0 ORs the B row segments named by a block of dA pairs
+//                   (i, k) into a per-lane register accumulator for row i;
+//                   part 1 ORs the A column segments named by dB pairs (k, j)
+//                   into the accumulator for column j.  The flush masks the
+//                   accumulator with M_c, ORs it in with 64-bit atomics whose
+//                   return value identifies the genuinely new bits, keeps the
+//                   other layout in step, and appends the new pairs.
+//   seed kernels    edges and eps rules -> initial pairs (Algorithm 1's
+//                   seeding, and (i, i) for every x -> eps).
+//   delta kernels   counting sort of the appended pairs into row order and
+//                   column order (the next round's dA and dB).
+//   readout         bit rows -> (i, j) pairs in (i, j) order.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace cflr {
+
+// ------------------------------------------------------------- wave helpers
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ uint32_t rdlane(uint32_t v, uint32_t l) {
+    return __builtin_amdgcn_readlane(v, l);
+}
+__device__ __forceinline__ uint64_t rdlane64(uint64_t v, uint32_t l) {
+    return ((uint64_t)rdlane((uint32_t)(v >> 32), l) << 32) | rdlane((uint32_t)v, l);
+}
+__device__ __forceinline__ uint32_t first_lane(uint32_t v) {
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ uint64_t first_lane64(uint64_t v) {
+    return ((uint64_t)first_lane((uint32_t)(v >> 32)) << 32) | first_lane((uint32_t)v);
+}
+
+// exclusive prefix sum over the 64 lanes of a wave
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t *total) {
+    const uint32_t lane = lane_id();
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= (uint32_t)d) x += y;
+    }
+    *total = rdlane(x, 63);
+    return x - v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+    uint32_t t;
+    wave_excl_scan(v, &t);
+    return t;
+}
+
+// ----------------------------------------------------------- product kernel
+
+
+// Slots of the append buffer are taken from the global counter in chunks
+// per wave, so one device-scope atomic serves many flushes.  Unused slots of
+// a chunk are marked as holes when the wave moves to a new chunk or exits.
+constexpr uint32_t kSlotChunk = 1024;
+
+struct SlotChunk {
+    uint64_t pos = 0, end = 0;  // wave-uniform
+};
+
+__device__ __forceinline__ void retire_chunk(const ProductArgs &A, SlotChunk &ch) {
+    for (uint64_t x = ch.pos + lane_id(); x < ch.end; x += kWave) A.ap_key[x] = kHole;
+    ch.pos = ch.end;
+}
+
+// Reserve `need` slots for this lane (wave-aggregated).  Returns false if
+// the buffer is full: the instance is flagged, the caller leaves M
+// untouched, and the host grows the buffer and re-runs the round.
+__device__ __forceinline__ bool reserve_slots(const ProductArgs &A, SlotChunk &ch, uint32_t inst,
+                                              uint32_t need, uint64_t *pos) {
+    uint32_t total;
+    uint32_t pre = wave_excl_scan(need, &total);
+    *pos = 0;
+    if (total == 0) return true;
+    if (ch.pos + total > ch.end) {
+        retire_chunk(A, ch);
+        const uint64_t want = total > kSlotChunk ? total : kSlotChunk;
+        unsigned long long base = 0;
+        if (lane_id() == 0) base = atomicAdd(A.ap_count, (unsigned long long)want);
+        base = first_lane64(base);
+        if (base + want > A.ap_cap) {
+            for (uint64_t x = base + lane_id(); x < A.ap_cap && x < base + want; x += kWave)
+                A.ap_key[x] = kHole;
+            if (lane_id() == 0) {
+                atomicOr(&A.inst_overflow[inst], 1u);
+                atomicOr(A.halt, 1u);
+            }
+            return false;
+        }
+        ch.pos = base;
+        ch.end = base + want;
+    }
+    *pos = ch.pos + pre;
+    ch.pos += total;
+    return true;
+}
+
+template <bool STATS>
+__device__ __forceinline__ bool first_touch(const ProductArgs &A, uint32_t inst, uint32_t mat,
+                                            uint32_t layout, uint32_t row, uint32_t seg,
+                                            const InstDev &I) {
+    uint64_t bit = A.touched_off[inst] +
+                   (((uint64_t)mat * 2 + layout) * I.n + row) * I.S + seg;
+    uint32_t m = 1u << (bit & 31);
+    uint32_t old = atomicOr(&A.touched[bit >> 5], m);
+    return !(old & m);
+}
+
+// Flush of one accumulator row segment.  COL = false: acc holds candidate
+// bits j of row `key` (= i) of c, word w = 64*seg + lane, and the row-major
+// copy is the authority; COL = true: acc holds candidate rows i of column
+// `key` (= j), and the column-major copy is the authority.  One returning
+// 64-bit atomic OR per word tells which candidates are genuinely new; they
+// are appended (the settle pass updates the other copy after the product).
+template <bool COL, bool STATS>
+__device__ __forceinline__ void flush(const ProductArgs &A, SlotChunk &ch, uint32_t inst, const InstDev &I,
+                                      const MatDev &Mc, uint32_t c, uint32_t key, uint32_t seg,
+                                      uint64_t acc, uint64_t Wp) {
+    const uint32_t lane = lane_id();
+    const uint32_t w = seg * kSegWords + lane;
+    uint64_t *own = (COL ? Mc.C : Mc.R) + (uint64_t)key * Wp + w;
+    uint64_t *own_sum = (COL ? Mc.CS : Mc.RS) + (uint64_t)key * I.S + seg;
+    uint64_t cand = 0;
+    if (acc) cand = acc & ~*own;
+    if (STATS) {
+        uint64_t lanes = __ballot(acc != 0);
+        if (lanes && lane == 0 && first_touch<STATS>(A, inst, c, COL ? 1 : 0, key, seg, I))
+            atomicAdd(A.algo_bytes, 8ull * __popcll(lanes));
+    }
+    uint64_t pos;
+    if (!reserve_slots(A, ch, inst, (uint32_t)__popcll(cand), &pos)) return;
+    uint64_t nw = 0, old = 0;
+    if (cand) {
+        old = atomicOr((unsigned long long *)own, (unsigned long long)cand);
+        nw = cand & ~old;
+    }
+    uint64_t made = __ballot(nw != 0 && old == 0);
+    if (made && lane == 0) atomicOr((unsigned long long *)own_sum, (unsigned long long)made);
+    const uint32_t k = pair_key(inst, c, COL ? kColFound : 0u);
+    uint64_t bits = cand;
+    while (bits) {
+        uint32_t b = __ffsll((unsigned long long)bits) - 1;
+        bits &= bits - 1;
+        if ((nw >> b) & 1) {
+            A.ap_key[pos] = k;
+            A.ap_i[pos] = COL ? w * 64 + b : key;
+            A.ap_j[pos] = COL ? key : w * 64 + b;
+            if (!COL) {
+                // the column part of this round then sees the pair sooner
+                // (fewer pairs found twice); no return value is needed
+                const uint32_t j = w * 64 + b;
+                atomicOr((unsigned long long *)&Mc.C[(uint64_t)j * Wp + (key >> 6)], 1ull << (key & 63));
+                atomicOr((unsigned long long *)&Mc.CS[(uint64_t)j * I.S + (key >> 12)],
+                         1ull << ((key >> 6) & 63));
+            }
+        } else {
+            A.ap_key[pos] = kHole;
+        }
+        pos++;
+    }
+    if (STATS) {
+        uint32_t fresh = wave_sum((uint32_t)__popcll(nw));
+        if (fresh && lane == 0) atomicAdd(A.algo_bytes, 20ull * fresh);
+    }
+}
+
+// Process one block of up to 64 new pairs against one row segment.
+// COL = false: pairs (i, k) of dA, partner rows k of B (row-major).
+// COL = true:  pairs (j, k) of dB, partner rows k of A's column-major copy.
+template <bool COL, bool STATS>
+__device__ __forceinline__ void process_block(const ProductArgs &A, SlotChunk &ch, uint32_t inst,
+                                              const InstDev &I,
+                                              const EntryDev &E, uint32_t start, uint32_t cnt,
+                                              uint32_t seg, bool count_pairs) {
+    const uint32_t lane = lane_id();
+    const uint64_t Wp = (uint64_t)I.S * kSegWords;
+    const MatDev Mc = A.mats[I.mat_off + E.c];
+    const MatDev Mp = A.mats[I.mat_off + (COL ? E.a : E.b)];
+    const uint64_t *P = COL ? Mp.C : Mp.R;
+    const uint64_t *PS = COL ? Mp.CS : Mp.RS;
+    const uint32_t *key = COL ? A.cs_j : A.rs_i;
+    const uint32_t *oth = COL ? A.cs_k : A.rs_k;
+    uint32_t my_key = kHole, my_k = 0;
+    uint64_t my_sm = 0;
+    if (lane < cnt) {
+        my_key = key[start + lane];
+        my_k = oth[start + lane];
+        my_sm = PS[(uint64_t)my_k * I.S + seg];
+    }
+    if (STATS) {
+        // compulsory partner bytes: non-zero words of each partner segment,
+        // counted at its first touch in the round
+        uint32_t bytes = 0;
+        if (lane < cnt && my_sm &&
+            first_touch<STATS>(A, inst, COL ? E.a : E.b, COL ? 1 : 0, my_k, seg, I))
+            bytes = 8u * (uint32_t)__popcll(my_sm);
+        if (count_pairs && lane < cnt) bytes += 8;  // the pair itself, once per production
+        uint32_t tot = wave_sum(bytes);
+        if (tot && lane == 0) atomicAdd(A.algo_bytes, (unsigned long long)tot);
+    }
+    const uint32_t w = seg * kSegWords + lane;
+    uint32_t t = 0;
+    while (t < cnt) {
+        const uint32_t cur = rdlane(my_key, t);
+        // pairs are sorted by key, so equal keys occupy lanes t .. end-1
+        uint64_t same = __ballot(my_key == cur);
+        uint32_t end = 64 - __clzll((unsigned long long)same);
+        uint64_t acc = 0;
+        uint32_t u = t;
+        // eight independent partner loads in flight per batch
+        for (; u + 8 <= end; u += 8) {
+            uint64_t v[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                uint64_t sm = rdlane64(my_sm, u + q);
+                uint32_t k = rdlane(my_k, u + q);
+                v[q] = ((sm >> lane) & 1) ? P[(uint64_t)k * Wp + w] : 0;
+            }
+            acc |= ((v[0] | v[1]) | (v[2] | v[3])) | ((v[4] | v[5]) | (v[6] | v[7]));
+        }
+        for (; u < end; u++) {
+            uint64_t sm = rdlane64(my_sm, u);
+            uint32_t k = rdlane(my_k, u);
+            if ((sm >> lane) & 1) acc |= P[(uint64_t)k * Wp + w];
+        }
+        flush<COL, STATS>(A, ch, inst, I, Mc, E.c, cur, seg, acc, Wp);
+        t = end;
+    }
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(64) void product_kernel(ProductArgs A) {
+    const uint64_t total = A.item_prefix[A.nent];
+    SlotChunk ch;
+    // items are handed out statically (item = block + t * grid): every item
+    // is one block of at most 64 pairs on one row segment, so they cost about
+    // the same, and no device-wide counter is contended
+    for (uint64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        // after an overflow the round is re-run: stop early
+        if (__hip_atomic_load(A.halt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        uint32_t lo = 0, hi = A.nent;  // item_prefix[lo] <= item < item_prefix[hi]
+        while (hi - lo > 1) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (A.item_prefix[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        const EntryDev E = A.ent[lo];
+        const InstDev I = A.inst[E.inst];
+        const uint64_t local = item - A.item_prefix[lo];
+        const uint32_t seg = (uint32_t)(local % I.S);
+        const uint32_t blk = (uint32_t)(local / I.S);
+        const uint32_t start = A.ent_start[lo] + blk * kPairsPerItem;
+        const uint32_t left = A.ent_cnt[lo] - blk * kPairsPerItem;
+        const uint32_t cnt = left < kPairsPerItem ? left : kPairsPerItem;
+        if (E.part == 0)
+            process_block<false, STATS>(A, ch, E.inst, I, E, start, cnt, seg, seg == 0);
+        else
+            process_block<true, STATS>(A, ch, E.inst, I, E, start, cnt, seg, seg == 0);
+    }
+    retire_chunk(A, ch);
+}
+
+// ------------------------------------------------------------- work table
+
+
+// One workgroup of 1024 threads: items of every entry and their prefix sum.
+__global__ __launch_bounds__(1024) void prep_kernel(PrepArgs A) {
+    __shared__ uint64_t part[1024];
+    __shared__ uint64_t carry;
+    const uint32_t t = threadIdx.x;
+    if (t == 0) {
+        carry = 0;
+        *A.work_counter = 0;
+    }
+    __syncthreads();
+    for (uint32_t base = 0; base < A.nent; base += 1024) {
+        uint32_t e = base + t;
+        uint64_t items = 0;
+        if (e < A.nent && !*A.halt) {
+            const EntryDev E = A.ent[e];
+            const InstDev I = A.inst[E.inst];
+            const uint32_t mat = E.part == 0 ? E.a : E.b;
+            const uint32_t *ptr = E.part == 0 ? A.rptr : A.cptr;
+            const uint32_t r0 = I.rowbase + mat * I.n;
+            const uint32_t s = ptr[r0], f = ptr[r0 + I.n];
+            A.ent_start[e] = s;
+            A.ent_cnt[e] = f - s;
+            items = (uint64_t)((f - s + kPairsPerItem - 1) / kPairsPerItem) * I.S;
+        }
+        part[t] = items;
+        __syncthreads();
+        for (uint32_t d = 1; d < 1024; d <<= 1) {  // inclusive scan (Hillis-Steele)
+            uint64_t v = t >= d ? part[t - d] : 0;
+            __syncthreads();
+            part[t] += v;
+            __syncthreads();
+        }
+        if (e < A.nent) A.item_prefix[e] = carry + part[t] - items;
+        __syncthreads();
+        if (t == 1023) carry += part[1023];
+        __syncthreads();
+    }
+    if (t == 0) A.item_prefix[A.nent] = carry;
+}
+
+// ------------------------------------------------------------- new-pair sort
+
+__global__ void fill_u32_kernel(uint32_t *a, uint64_t n, uint32_t v) {
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
+         x += (uint64_t)gridDim.x * blockDim.x)
+        a[x] = v;
+}
+
+__global__ void fill_u64_kernel(unsigned long long *a, uint64_t n, unsigned long long v) {
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
+         x += (uint64_t)gridDim.x * blockDim.x)
+        a[x] = v;
+}
+
+
+__global__ __launch_bounds__(256) void settle_kernel(SettleArgs A) {
+    if (*A.halt) return;
+    uint64_t n = *A.ap_count;
+    if (n > A.ap_cap) n = A.ap_cap;
+    // survivors are counted per thread and flushed when the instance changes
+    uint32_t run_slot = kHole;
+    unsigned long long run_cnt = 0;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t key = A.ap_key[x];
+        if (key == kHole || (key & kSettled)) continue;
+        const uint32_t slot = key_slot(key);
+        const InstDev I = A.inst[slot];
+        const MatDev M = A.mats[I.mat_off + key_mat(key)];
+        const uint64_t Wp = (uint64_t)I.S * kSegWords;
+        const uint32_t i = A.ap_i[x], j = A.ap_j[x];
+        bool keep = true;
+        if (key & kColFound) {
+            // the row-major copy decides: set there already means the row
+            // part found the pair too, and its entry is the one kept
+            const uint64_t bit = 1ull << (j & 63);
+            unsigned long long old = atomicOr((unsigned long long *)&M.R[(uint64_t)i * Wp + (j >> 6)], bit);
+            keep = !(old & bit);
+            if (keep && old == 0)
+                atomicOr((unsigned long long *)&M.RS[(uint64_t)i * I.S + (j >> 12)], 1ull << ((j >> 6) & 63));
+            if (!keep) A.ap_key[x] = kHole;
+        } else {
+            atomicOr((unsigned long long *)&M.C[(uint64_t)j * Wp + (i >> 6)], 1ull << (i & 63));
+            atomicOr((unsigned long long *)&M.CS[(uint64_t)j * I.S + (i >> 12)], 1ull << ((i >> 6) & 63));
+        }
+        if (!keep) continue;
+        if (slot != run_slot) {
+            if (run_cnt) atomicAdd(&A.inst_new[run_slot], run_cnt);
+            run_slot = slot;
+            run_cnt = 0;
+        }
+        run_cnt++;
+    }
+    if (run_cnt) atomicAdd(&A.inst_new[run_slot], run_cnt);
+}
+
+__global__ void count_kernel(SortArgs A) {
+    if (*A.halt) return;
+    uint64_t n = *A.ap_count;
+    if (n > A.ap_cap) n = A.ap_cap;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t key = A.ap_key[x];
+        if (key == kHole) continue;
+        const InstDev I = A.inst[key_slot(key)];
+        uint32_t b = I.rowbase + key_mat(key) * I.n;
+        atomicAdd(&A.rcnt[b + A.ap_i[x]], 1u);
+        atomicAdd(&A.ccnt[b + A.ap_j[x]], 1u);
+    }
+}
+
+__global__ void scatter_kernel(SortArgs A) {
+    if (*A.halt) return;
+    uint64_t n = *A.ap_count;
+    if (n > A.ap_cap) n = A.ap_cap;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t key = A.ap_key[x];
+        if (key == kHole) continue;
+        const InstDev I = A.inst[key_slot(key)];
+        uint32_t b = I.rowbase + key_mat(key) * I.n;
+        uint32_t i = A.ap_i[x], j = A.ap_j[x];
+        uint32_t p = atomicSub(&A.rcnt[b + i], 1u) - 1;
+        A.rs_i[p] = i;
+        A.rs_k[p] = j;
+        uint32_t q = atomicSub(&A.ccnt[b + j], 1u) - 1;
+        A.cs_j[q] = j;
+        A.cs_k[q] = i;
+    }
+}
+
+// Inclusive scan of two u32 arrays (blockIdx.y selects), 3 phases.
+constexpr uint32_t kScanThreads = 256, kScanItems = 16, kScanTile = kScanThreads * kScanItems;
+
+__global__ __launch_bounds__(256) void scan_reduce_kernel(uint32_t *a0, uint32_t *a1, uint64_t n,
+                                                          uint32_t *bsum, uint32_t nblk,
+                                                          const uint32_t *halt) {
+    if (halt && *halt) return;
+    uint32_t *a = blockIdx.y ? a1 : a0;
+    __shared__ uint32_t red[kScanThreads];
+    uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+    for (uint32_t q = 0; q < kScanItems; q++) {
+        uint64_t x = base + q * kScanThreads + threadIdx.x;
+        if (x < n) s += a[x];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (uint32_t d = kScanThreads / 2; d; d >>= 1) {
+        if (threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.y * nblk + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(1024) void scan_blocks_kernel(uint32_t *bsum, uint32_t nblk,
+                                                           const uint32_t *halt) {
+    if (halt && *halt) return;
+    uint32_t *b = bsum + blockIdx.x * nblk;  // exclusive scan of block sums
+    __shared__ uint32_t part[1024];
+    __shared__ uint32_t carry;
+    const uint32_t t = threadIdx.x;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < nblk; base += 1024) {
+        uint32_t v = base + t < nblk ? b[base + t] : 0;
+        part[t] = v;
+        __syncthreads();
+        for (uint32_t d = 1; d < 1024; d <<= 1) {
+            uint32_t u = t >= d ? part[t - d] : 0;
+            __syncthreads();
+            part[t] += u;
+            __syncthreads();
+        }
+        if (base + t < nblk) b[base + t] = carry + part[t] - v;
+        __syncthreads();
+        if (t == 1023) carry += part[1023];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void scan_apply_kernel(uint32_t *a0, uint32_t *a1, uint64_t n,
+                                                         const uint32_t *bsum, uint32_t nblk,
+                                                         const uint32_t *halt) {
+    if (halt && *halt) return;
+    uint32_t *a = blockIdx.y ? a1 : a0;
+    __shared__ uint32_t tile[kScanTile];
+    __shared__ uint32_t tsum[kScanThreads];
+    uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    for (uint32_t q = 0; q < kScanItems; q++) {
+        uint64_t x = base + q * kScanThreads + threadIdx.x;
+        tile[q * kScanThreads + threadIdx.x] = x < n ? a[x] : 0;
+    }
+    __syncthreads();
+    // each thread scans its own run of kScanItems consecutive elements
+    uint32_t *mine = tile + threadIdx.x * kScanItems;
+    uint32_t s = 0;
+    for (uint32_t q = 0; q < kScanItems; q++) {
+        s += mine[q];
+        mine[q] = s;
+    }
+    tsum[threadIdx.x] = s;
+    __syncthreads();
+    for (uint32_t d = 1; d < kScanThreads; d <<= 1) {
+        uint32_t u = threadIdx.x >= d ? tsum[threadIdx.x - d] : 0;
+        __syncthreads();
+        tsum[threadIdx.x] += u;
+        __syncthreads();
+    }
+    uint32_t off = bsum[blockIdx.y * nblk + blockIdx.x] + tsum[threadIdx.x] - s;
+    for (uint32_t q = 0; q < kScanItems; q++) mine[q] += off;
+    __syncthreads();
+    for (uint32_t q = 0; q < kScanItems; q++) {
+        uint64_t x = base + q * kScanThreads + threadIdx.x;
+        if (x < n) a[x] = tile[q * kScanThreads + threadIdx.x];
+    }
+}
+
+// ------------------------------------------------------------------ seeding
+
+
+// Set (i, j) in matrix x if absent; on success keep C in step and append it.
+__device__ __forceinline__ void seed_pair(const SeedArgs &A, uint32_t x, uint32_t i, uint32_t j) {
+    const uint64_t Wp = (uint64_t)A.I.S * kSegWords;
+    const MatDev M = A.mats[x];
+    uint64_t bit = 1ull << (j & 63);
+    unsigned long long o = atomicOr((unsigned long long *)&M.R[(uint64_t)i * Wp + (j >> 6)], bit);
+    if (o & bit) return;
+    if (o == 0)
+        atomicOr((unsigned long long *)&M.RS[(uint64_t)i * A.I.S + (j >> 12)],
+                 1ull << ((j >> 6) & 63));
+    if (M.C) {
+        unsigned long long o2 =
+            atomicOr((unsigned long long *)&M.C[(uint64_t)j * Wp + (i >> 6)], 1ull << (i & 63));
+        if (o2 == 0)
+            atomicOr((unsigned long long *)&M.CS[(uint64_t)j * A.I.S + (i >> 12)],
+                     1ull << ((i >> 6) & 63));
+    }
+    unsigned long long p = atomicAdd(A.ap_count, 1ull);
+    atomicAdd(&A.inst_new[A.inst], 1ull);
+    if (p < A.ap_cap) {
+        A.ap_key[p] = pair_key(A.inst, x, kSettled);
+        A.ap_i[p] = i;
+        A.ap_j[p] = j;
+    } else {
+        atomicOr(&A.inst_overflow[A.inst], 1u);
+    }
+}
+
+__global__ void seed_edges_kernel(SeedArgs A) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < A.m;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t l = A.lab[e];
+        for (uint32_t q = A.lm_ptr[l]; q < A.lm_ptr[l + 1]; q++)
+            seed_pair(A, A.lm_mat[q], A.src[e], A.dst[e]);
+    }
+}
+
+__global__ void seed_eps_kernel(SeedArgs A) {
+    uint64_t total = (uint64_t)A.n_eps * A.I.n;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < total;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t e = (uint32_t)(x / A.I.n), i = (uint32_t)(x % A.I.n);
+        seed_pair(A, A.eps_mat[e], i, i);
+    }
+}
+
+// Every pair of every matrix becomes "new" (restart from M, or the naive
+// variant where each round multiplies all of M).  Both layouts already hold
+// these pairs, so they are appended as settled.
+__global__ __launch_bounds__(64) void extract_all_kernel(const MatDev *mats, InstDev I, uint32_t slot,
+                                                         uint32_t nmat, uint32_t *ap_key, uint32_t *ap_i,
+                                                         uint32_t *ap_j, unsigned long long *ap_count,
+                                                         uint64_t ap_cap, uint32_t *overflow) {
+    const uint32_t lane = lane_id();
+    const uint64_t Wp = (uint64_t)I.S * kSegWords;
+    const uint64_t rows = (uint64_t)nmat * I.n * I.S;
+    for (uint64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        uint32_t seg = (uint32_t)(r % I.S);
+        uint64_t rr = r / I.S;
+        uint32_t i = (uint32_t)(rr % I.n), x = (uint32_t)(rr / I.n);
+        uint64_t v = mats[x].R[(uint64_t)i * Wp + seg * kSegWords + lane];
+        uint32_t total;
+        uint32_t pre = wave_excl_scan((uint32_t)__popcll(v), &total);
+        if (!total) continue;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(ap_count, (unsigned long long)total);
+        base = first_lane64(base);
+        uint64_t p = base + pre;
+        while (v) {
+            uint32_t b = __ffsll((unsigned long long)v) - 1;
+            v &= v - 1;
+            if (p < ap_cap) {
+                ap_key[p] = pair_key(slot, x, kSettled);
+                ap_i[p] = i;
+                ap_j[p] = (seg * kSegWords + lane) * 64 + b;
+            } else {
+                atomicOr(overflow, 1u);
+            }
+            p++;
+        }
+    }
+}
+
+// Drop the pending pairs of a retired instance (their slot may be reused).
+__global__ void purge_slot_kernel(uint32_t *ap_key, const unsigned long long *ap_count, uint64_t ap_cap,
+                                  uint32_t slot) {
+    uint64_t n = *ap_count;
+    if (n > ap_cap) n = ap_cap;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t k = ap_key[x];
+        if (k != kHole && key_slot(k) == slot) ap_key[x] = kHole;
+    }
+}
+
+// ------------------------------------------------------------------ readout
+
+__global__ __launch_bounds__(64) void row_count_kernel(const uint64_t *R, uint32_t n, uint32_t S,
+                                                       uint32_t *cnt, unsigned long long *total) {
+    const uint32_t lane = lane_id();
+    const uint64_t Wp = (uint64_t)S * kSegWords;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        uint32_t c = 0;
+        for (uint32_t s = 0; s < S; s++) c += (uint32_t)__popcll(R[(uint64_t)i * Wp + s * kSegWords + lane]);
+        c = wave_sum(c);
+        if (lane == 0) {
+            cnt[i] = c;
+            if (total) atomicAdd(total, (unsigned long long)c);
+        }
+    }
+}
+
+// off: exclusive start of each row in the output (64-bit: counts may pass 2^32)
+__global__ __launch_bounds__(64) void row_write_kernel(const uint64_t *R, uint32_t n, uint32_t S,
+                                                       const uint64_t *off, uint32_t *src,
+                                                       uint32_t *dst) {
+    const uint32_t lane = lane_id();
+    const uint64_t Wp = (uint64_t)S * kSegWords;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        uint64_t pos = off[i];
+        for (uint32_t s = 0; s < S; s++) {
+            uint32_t w = s * kSegWords + lane;
+            uint64_t v = R[(uint64_t)i * Wp + w];
+            uint32_t total;
+            uint32_t pre = wave_excl_scan((uint32_t)__popcll(v), &total);
+            uint64_t p = pos + pre;
+            while (v) {
+                uint32_t b = __ffsll((unsigned long long)v) - 1;
+                v &= v - 1;
+                src[p] = i;
+                dst[p] = w * 64 + b;
+                p++;
+            }
+            pos += total;
+        }
+    }
+}
+
+// exclusive scan of u32 row counts into u64 offsets, one workgroup
+__global__ __launch_bounds__(1024) void offsets_kernel(const uint32_t *cnt, uint32_t n, uint64_t *off) {
+    __shared__ uint64_t part[1024];
+    __shared__ uint64_t carry;
+    const uint32_t t = threadIdx.x;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < n; base += 1024) {
+        uint64_t v = base + t < n ? cnt[base + t] : 0;
+        part[t] = v;
+        __syncthreads();
+        for (uint32_t d = 1; d < 1024; d <<= 1) {
+            uint64_t u = t >= d ? part[t - d] : 0;
+            __syncthreads();
+            part[t] += u;
+            __syncthreads();
+        }
+        if (base + t < n) off[base + t] = carry + part[t] - v;
+        __syncthreads();
+        if (t == 1023) carry += part[1023];
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ host launchers
+
+#define CFLR_LAUNCH_CHECK()                                     \
+    do {                                                        \
+        hipError_t e_ = hipGetLastError();                      \
+        if (e_ != hipSuccess) return e_;                        \
+    } while (0)
+
+hipError_t launch_product(const ProductArgs &A, uint32_t grid, bool stats, hipStream_t s) {
+    if (stats) product_kernel<true><<<grid, 64, 0, s>>>(A);
+    else product_kernel<false><<<grid, 64, 0, s>>>(A);
+    CFLR_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_prep(const PrepArgs &A, hipStream_t s) {
+    prep_kernel<<<1, 1024, 0, s>>>(A);
+    CFLR_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_fill_u32(uint32_t *a, uint64_t n, uint32_t v, hipStream_t s) {
+    if (!n) return hipSuccess;
+    uint64_t g = (n + 255) / 256;
+    if (g > 8192) g = 8192;
+    fill_u32_kernel<<<(uint32_t)g, 256, 0, s>>>(a, n, v);
+    CFLR_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long v, hipStream_t s) {
+    if (!n) return hipSuccess;
+    uint64_t g = (n + 255) / 256;
+    if (g > 8192) g = 8192;
+    fill_u64_kernel<<<(uint32_t)g, 256, 0, s>>>(a, n, v);
+    CFLR_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+// counting sort of the appended pairs; rows: [0, nrows] (nrows + 1 counters)
+hipError_t launch_sort(const SortArgs &A, uint64_t nrows, uint32_t *bsum, uint32_t sort_grid,
+                       hipStream_t s) {
+    const uint64_t len = nrows + 1;
+    hipError_t e = launch_fill_u32(A.rcnt, len, 0, s);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u32(A.ccnt, len, 0, s);
+    if (e != hipSuccess) return e;
+    count_kernel<<<sort_grid, 256, 0, s>>>(A);
+    CFLR_LAUNCH_CHECK();
+    uint32_t nblk = (uint32_t)((len + kScanTile - 1) / kScanTile);
+    scan_reduce_kernel<<<dim3(nblk, 2), 256, 0, s>>>(A.rcnt, A.ccnt, len, bsum, nblk, A.halt);
+    CFLR_LAUNCH_CHECK();
+    scan_blocks_kernel<<<2, 1024, 0, s>>>(bsum, nblk, A.halt);
+    CFLR_LAUNCH_CHECK();
+    scan_apply_kernel<<<dim3(nblk, 2), 256, 0, s>>>(A.rcnt, A.ccnt, len, bsum, nblk, A.halt);
+    CFLR_LAUNCH_CHECK();
+    scatter_kernel<<<sort_grid, 256, 0, s>>>(A);
+    CFLR_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+uint32_t scan_block_count(uint64_t nrows) {
+    return (uint32_t)((nrows + 1 + kScanTile - 1) / kScanTile);
+}
+
+hipError_t launch_seed(const SeedArgs &A, hipStream_t s) {
+    if (A.m) {
+        uint64_t g = (A.m + 255) / 256;
+        if (g > 16384) g = 16384;
+        seed_edges_kernel<<<(uint32_t)g, 256, 0, s>>>(A);
+        CFLR_LAUNCH_CHECK();
+    }
+    uint64_t e = (uint64_t)A.n_eps * A.I.n;
+    if (e) {
+        uint64_t g = (e + 255) / 256;
+        if (g > 16384) g = 16384;
+        seed_eps_kernel<<<(uint32_t)g, 256, 0, s>>>(A);
+        CFLR_LAUNCH_CHECK();
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_purge_slot(uint32_t *ap_key, const unsigned long long *ap_count, uint64_t ap_cap,
+                             uint32_t slot, uint32_t grid, hipStream_t s) {
+    purge_slot_kernel<<<grid, 256, 0, s>>>(ap_key, ap_count, ap_cap, slot);
+    CFLR_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_settle(const SettleArgs &A, uint32_t grid, hipStream_t s) {
+    settle_kernel<<<grid, 256, 0, s>>>(A);
+    CFLR_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_extract_all(const MatDev *mats, const InstDev &I, uint32_t slot, uint32_t nmat,
+                              uint32_t *ap_key, uint32_t *ap_i, uint32_t *ap_j, unsigned long long *ap_count,
+                              uint64_t ap_cap, uint32_t *overflow, hipStream_t s) {
+    uint64_t rows = (uint64_t)nmat * I.n * I.S;
+    if (!rows) return hipSuccess;
+    uint64_t g = rows < 65536 ? rows : 65536;
+    extract_all_kernel<<<(uint32_t)g, 64, 0, s>>>(mats, I, slot, nmat, ap_key, ap_i, ap_j, ap_count, ap_cap,
+                                                  overflow);
+    CFLR_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_row_count(const uint64_t *R, uint32_t n, uint32_t S, uint32_t *cnt,
+                            unsigned long long *total, hipStream_t s) {
+    if (!n) return hipSuccess;
+    uint32_t g = n < 65536 ? n : 65536;
+    row_count_kernel<<<g, 64, 0, s>>>(R, n, S, cnt, total);
+    CFLR_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_row_write(const uint64_t *R, uint32_t n, uint32_t S, const uint32_t *cnt,
+                            uint64_t *off, uint32_t *src, uint32_t *dst, hipStream_t s) {
+    if (!n) return hipSuccess;
+    offsets_kernel<<<1, 1024, 0, s>>>(cnt, n, off);
+    CFLR_LAUNCH_CHECK();
+    uint32_t g = n < 65536 ? n : 65536;
+    row_write_kernel<<<g, 64, 0, s>>>(R, n, S, off, src, dst);
+    CFLR_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+}  // namespace cflr

@@ -1,0 +1,265 @@
+// server.cpp -- continuous batching of CFL-reachability requests.
+//
+// A worker thread owns one Run.  Between rounds it retires the instances that
+// converged (their matrices are compacted to the user non-terminals and
+// handed to the waiting caller) and admits queued requests, first come first
+// served, while the estimated device footprint of the running instances plus
+// the next one fits the budget and a slot is free.  Every round is one fused
+// product launch over all running instances, so a request that arrives while
+// others are on the device starts at the next round boundary and shares the
+// device with them.  Each instance's arithmetic is independent of the others
+// (its own matrices, rows and new pairs), so its result equals a solo solve.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+
+#include "engine.h"
+
+using namespace cflr;
+
+namespace {
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+    uint64_t ticket = 0;
+    const cflr_grammar *g = nullptr;
+    const cflr_graph *graph = nullptr;
+    double t_submit = 0, t_admit = 0, t_finish = 0;
+    bool finished = false;
+    bool taken = false;
+    cflr_status status = CFLR_OK;
+    std::string error;
+    std::shared_ptr<Instance> inst;
+    uint64_t footprint = 0;
+};
+
+}  // namespace
+
+struct cflr_server {
+    CtxRef hold;  // first member: released last
+    cflr_ctx *ctx = nullptr;
+    cflr_opts opts{};
+    uint64_t budget = 0;
+    uint32_t max_slots = 0;
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> queue;
+    std::map<uint64_t, std::unique_ptr<Request>> reqs;
+    std::map<Instance *, Request *> running;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    uint64_t in_use = 0;
+    std::unique_ptr<Run> run;
+    std::string fatal;
+
+    void loop();
+};
+
+void cflr_server::loop() {
+    (void)hipSetDevice(ctx->device);
+    while (true) {
+        std::vector<Request *> admit;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_work.wait(lk, [&] { return stop || !queue.empty() || !running.empty(); });
+            if (stop && queue.empty() && running.empty()) break;
+            uint64_t planned = in_use;
+            size_t slots = running.size();
+            while (!queue.empty() && slots < max_slots) {
+                Request *r = queue.front();
+                if (r->footprint > budget) {
+                    queue.pop_front();
+                    r->status = CFLR_ENOMEM;
+                    r->error = "request footprint exceeds the server budget";
+                    r->finished = true;
+                    r->t_finish = now_s();
+                    cv_done.notify_all();
+                    continue;
+                }
+                if (slots && planned + r->footprint > budget) break;
+                queue.pop_front();
+                admit.push_back(r);
+                planned += r->footprint;
+                slots++;
+            }
+        }
+        for (Request *r : admit) {
+            try {
+                auto inst = make_instance(ctx, r->g->low, r->graph);
+                run->add(inst);
+                std::lock_guard<std::mutex> lk(mu);
+                r->inst = inst;
+                r->t_admit = now_s();
+                running[inst.get()] = r;
+                in_use += r->footprint;
+            } catch (const Error &e) {
+                std::lock_guard<std::mutex> lk(mu);
+                if (e.status == CFLR_ENOMEM && !running.empty()) {
+                    queue.push_front(r);  // wait for memory to free up
+                } else {
+                    r->status = e.status;
+                    r->error = e.what();
+                    r->finished = true;
+                    r->t_finish = now_s();
+                    cv_done.notify_all();
+                }
+            }
+        }
+        if (run->size() == 0) continue;
+        try {
+            run->round();
+            std::vector<std::shared_ptr<Instance>> done;
+            for (auto &ip : run->instances())
+                if (ip->done || (opts.max_rounds && ip->rounds >= opts.max_rounds)) done.push_back(ip);
+            for (auto &ip : done) {
+                run->remove(ip.get());
+                ip->stats.rounds = ip->rounds;
+                cflr_status st = ip->done ? CFLR_OK : CFLR_ETIMEOUT;
+                compact_instance(*ip);
+                instance_counts(*ip);
+                std::lock_guard<std::mutex> lk(mu);
+                Request *r = running[ip.get()];
+                running.erase(ip.get());
+                in_use -= r->footprint;
+                r->status = st;
+                if (st != CFLR_OK) r->error = "round limit reached before the fixpoint";
+                r->t_finish = now_s();
+                r->inst->stats.fixpoint_ms = (r->t_finish - r->t_admit) * 1e3;
+                r->finished = true;
+            }
+            if (!done.empty()) cv_done.notify_all();
+        } catch (const std::exception &e) {
+            // a device failure ends every running request
+            std::lock_guard<std::mutex> lk(mu);
+            fatal = e.what();
+            for (auto &kv : running) {
+                kv.second->status = CFLR_EDEVICE;
+                kv.second->error = fatal;
+                kv.second->finished = true;
+                kv.second->t_finish = now_s();
+            }
+            running.clear();
+            for (Request *r : queue) {
+                r->status = CFLR_EDEVICE;
+                r->error = fatal;
+                r->finished = true;
+            }
+            queue.clear();
+            stop = true;
+            cv_done.notify_all();
+            break;
+        }
+    }
+}
+
+extern "C" {
+
+cflr_status cflr_server_create(cflr_ctx *ctx, uint64_t hbm_budget_bytes, uint32_t max_slots,
+                               const cflr_opts *opts, cflr_server **out) {
+    if (!ctx || !out || !max_slots) return CFLR_EINVAL;
+    *out = nullptr;
+    try {
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        auto s = std::make_unique<cflr_server>();
+        s->hold = CtxRef(ctx);
+        s->ctx = ctx;
+        cflr_opts_default(&s->opts);
+        if (opts) s->opts = *opts;
+        s->budget = hbm_budget_bytes;
+        s->max_slots = max_slots;
+        // row space for every instance that can run at once
+        uint64_t rows = std::min<uint64_t>(1ull << 27, std::max<uint64_t>(1ull << 20, hbm_budget_bytes / 512));
+        s->run = std::make_unique<Run>(ctx, s->opts, rows, max_slots);
+        s->worker = std::thread([p = s.get()] { p->loop(); });
+        *out = s.release();
+        return CFLR_OK;
+    } catch (const Error &e) {
+        return e.status;
+    } catch (...) {
+        return CFLR_EDEVICE;
+    }
+}
+
+cflr_status cflr_server_submit(cflr_server *s, const cflr_grammar *g, const cflr_graph *graph, uint64_t *ticket) {
+    if (!s || !g || !graph || !ticket) return CFLR_EINVAL;
+    if (graph->ctx != s->ctx) return CFLR_EINVAL;
+    auto r = std::make_unique<Request>();
+    r->g = g;
+    r->graph = graph;
+    r->t_submit = now_s();
+    r->footprint = instance_footprint(g->low, graph->n);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return CFLR_EDEVICE;
+    r->ticket = s->next_ticket++;
+    *ticket = r->ticket;
+    s->queue.push_back(r.get());
+    s->reqs[r->ticket] = std::move(r);
+    s->cv_work.notify_one();
+    return CFLR_OK;
+}
+
+static cflr_status take(cflr_server *s, Request *r, cflr_result **out) {
+    if (r->taken) return CFLR_EINVAL;
+    r->taken = true;
+    if (r->status != CFLR_OK) set_last_error(r->error);
+    if (r->status != CFLR_OK && r->status != CFLR_ETIMEOUT) return r->status;
+    *out = new cflr_result{r->inst};
+    (void)s;
+    return r->status;
+}
+
+cflr_status cflr_server_poll(cflr_server *s, uint64_t ticket, cflr_result **out) {
+    if (!s || !out) return CFLR_EINVAL;
+    *out = nullptr;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return CFLR_EINVAL;
+    if (!it->second->finished) return CFLR_PENDING;
+    return take(s, it->second.get(), out);
+}
+
+cflr_status cflr_server_wait(cflr_server *s, uint64_t ticket, uint64_t timeout_ns, cflr_result **out) {
+    if (!s || !out) return CFLR_EINVAL;
+    *out = nullptr;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return CFLR_EINVAL;
+    Request *r = it->second.get();
+    bool ok = s->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), [&] { return r->finished; });
+    if (!ok) return CFLR_ETIMEOUT;
+    return take(s, r, out);
+}
+
+cflr_status cflr_server_times(cflr_server *s, uint64_t ticket, double *submitted, double *admitted,
+                              double *finished) {
+    if (!s) return CFLR_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return CFLR_EINVAL;
+    Request *r = it->second.get();
+    if (!r->finished) return CFLR_PENDING;
+    if (submitted) *submitted = r->t_submit;
+    if (admitted) *admitted = r->t_admit;
+    if (finished) *finished = r->t_finish;
+    return CFLR_OK;
+}
+
+void cflr_server_free(cflr_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    s->run.reset();
+    delete s;
+}
+
+}  // extern "C"

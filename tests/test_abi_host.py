@@ -1,0 +1,98 @@
+"""Host-only checks of libcflr (no GPU): every symbol of include/cflr.h is
+exported, the grammar parser rejects malformed text, and the lowering to
+strict weak Chomsky normal form has the expected shape."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from workloads import grammars as G
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "cflr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cflr_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function(cflr_lib):
+    names = header_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(cflr_lib, name), name
+
+
+def test_binding_declares_every_function():
+    from paper_2401_11029_amd._lib import SIGNATURES
+    assert sorted(SIGNATURES) == header_functions()
+
+
+def test_version_and_defaults(cflr_lib):
+    import paper_2401_11029_amd as cflr
+    assert b"gfx950" in cflr_lib.cflr_version()
+    o = cflr.opts()
+    assert o.semi_naive == 1 and o.max_rounds == 0
+
+
+def info(text):
+    import paper_2401_11029_amd as cflr
+    g = cflr.Grammar(text)
+    return g.nonterminals, g.info()
+
+
+def test_lowering_dyck1(cflr_lib):
+    nts, i = info(G.DYCK1)
+    assert nts == ["S", "X", "A", "B"]
+    assert i == dict(user_nonterminals=4, wrappers=0, matrices=4, binary=4,
+                     terminal_rules=2, eps_rules=1, terminals=2)
+
+
+def test_lowering_alias_fig5a(cflr_lib):
+    # V2 -> M is removed by giving V2 the rule M -> d_bar Y1; four wrappers
+    nts, i = info(G.ALIAS_FIG5A_WCNF)
+    assert nts == ["M", "Y1", "V", "Y2", "V1", "Y3", "V2", "V3", "Y4"]
+    assert i["wrappers"] == 4 and i["matrices"] == 13
+    assert i["binary"] == 8 + 1 and i["eps_rules"] == 4 and i["terminal_rules"] == 4
+
+
+def test_lowering_alias_fig5b(cflr_lib):
+    nts, i = info(G.ALIAS_FIG5B)
+    assert nts == ["M", "N1", "N2", "N3", "AM"]
+    assert i["wrappers"] == 2 and i["binary"] == 8
+
+
+def test_lowering_pointsto_64_fields(cflr_lib):
+    nts, i = info(G.pointsto_fig4b(64))
+    assert len(nts) == 2 + 6 * 64
+    assert i["wrappers"] == 2 + 4 * 64
+    assert i["binary"] == 2 + 8 * 64
+    assert i["matrices"] == 386 + 258
+
+
+def test_lowering_unit_cycle_and_chain(cflr_lib):
+    nts, i = info("A -> B\nB -> A | C\nC -> c | A A\n")
+    # A, B, C all reach each other: each gets C's two productions
+    assert i["terminal_rules"] == 3 and i["binary"] == 3
+
+
+@pytest.mark.parametrize("bad", [
+    "", "S", "S -> a b c", "S -> -> a", "S T -> a", "S -> a eps",
+    "S -> |", "eps -> a",
+])
+def test_parse_errors(cflr_lib, bad):
+    import paper_2401_11029_amd as cflr
+    with pytest.raises(cflr.CflrError) as e:
+        cflr.Grammar(bad)
+    assert e.value.status == 2  # CFLR_EPARSE
+
+
+def test_null_arguments_are_rejected(cflr_lib):
+    out = C.c_void_p()
+    assert cflr_lib.cflr_grammar_parse(None, 5, C.byref(out)) == 1
+    assert cflr_lib.cflr_grammar_info_get(None, None) == 1
+    assert cflr_lib.cflr_result_count(None, 0, None) == 1
+    assert cflr_lib.cflr_grammar_nonterminal_name(None, 0) is None

@@ -1,0 +1,222 @@
+"""GPU path vs the CPU oracle, pair for pair (tolerance 0: the result is a set
+of integer pairs).  Every call goes through libcflr's C interface."""
+
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from workloads import grammars as G
+from workloads import graphs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def cflr():
+    import paper_2401_11029_amd as m
+    return m
+
+
+def gpu_solve(ctx, text, g, **kw):
+    m = cflr()
+    gr = m.Grammar(text)
+    graph = m.Graph.from_workload(ctx, g)
+    return m.solve(ctx, gr, graph, **kw)
+
+
+def assert_matches_oracle(res, text, g, tag=""):
+    o = oracle.solve(text, g)
+    assert res.grammar.nonterminals == o.order
+    for x in o.order:
+        s, d = res.pairs(x)
+        want = o.pairs[x]
+        assert s.shape[0] == want.shape[0], (tag, x, s.shape[0], want.shape[0])
+        assert np.array_equal(s, want[:, 0]) and np.array_equal(d, want[:, 1]), (tag, x)
+
+
+def digest(s, d):
+    buf = np.empty((s.shape[0], 2), dtype="<u4")
+    buf[:, 0] = s
+    buf[:, 1] = d
+    return hashlib.sha256(buf.tobytes()).hexdigest()
+
+
+def test_dyck1_erdos_renyi_256(ctx):
+    text, g = workloads.config("dyck_er")
+    r = gpu_solve(ctx, text, g)
+    assert_matches_oracle(r, text, g)
+    st = r.stats()
+    assert st["rounds"] >= 2 and st["total_pairs"] == sum(r.counts().values())
+
+
+SWEEP = [
+    ("dyck1", G.DYCK1, ["a", "b"]),
+    ("alias5a", G.ALIAS_FIG5A_WCNF, ["a", "d", "a_bar", "d_bar"]),
+    ("alias5b", G.ALIAS_FIG5B, ["a", "d", "a_bar", "d_bar"]),
+    ("pointsto4b", G.pointsto_fig4b(3), G.symbols_of(G.pointsto_fig4b(3))[1]),
+    ("pointsto4a", G.pointsto_fig4a(3), G.symbols_of(G.pointsto_fig4a(3))[1]),
+    ("valueflow7a", G.cscvf_fig7a(3), G.symbols_of(G.cscvf_fig7a(3))[1]),
+    ("fsca6b", G.fsca_fig6b(2), G.symbols_of(G.fsca_fig6b(2))[1]),
+    ("refl_trans", G.REFLEXIVE_TRANSITIVE, ["a"]),
+]
+
+
+@pytest.mark.parametrize("case", SWEEP, ids=[c[0] for c in SWEEP])
+def test_random_sweep(ctx, case):
+    name, text, labels = case
+    for k, (n, m) in enumerate([(1, 3), (5, 12), (33, 90), (64, 200), (65, 260),
+                                (200, 600)]):
+        g = graphs.random_graph(n, m, labels, seed=1000 + 17 * k, self_loops=True)
+        assert_matches_oracle(gpu_solve(ctx, text, g), text, g, f"{name} n={n}")
+
+
+@pytest.mark.parametrize("n", [4095, 4096, 4097, 8193])
+def test_row_segment_boundaries(ctx, n):
+    # the alias grammar at n around multiples of 4096 columns (one segment)
+    g = graphs.alias_graph(n, m_fwd=n // 2, seed=n)
+    assert_matches_oracle(gpu_solve(ctx, G.ALIAS_FIG5A_WCNF, g), G.ALIAS_FIG5A_WCNF, g)
+
+
+@pytest.mark.parametrize("name", ["alias_8k", "alias5b_8k", "pointsto_4k", "pointsto_12k"])
+def test_golden_digests(ctx, name):
+    from tests.golden.make_goldens import GOLDENS
+    with open(os.path.join(GOLDEN, f"{name}.json")) as f:
+        gold = json.load(f)
+    text, g = GOLDENS[name]()
+    r = gpu_solve(ctx, text, g)
+    assert r.grammar.nonterminals == gold["order"]
+    for x in gold["order"]:
+        s, d = r.pairs(x)
+        assert s.shape[0] == gold["count"][x], x
+        assert digest(s, d) == gold["sha256"][x], x
+
+
+def test_edge_cases(ctx):
+    m = cflr()
+    # no vertices
+    g = graphs.make_graph(0, [], label_names=["a", "b"])
+    r = gpu_solve(ctx, G.DYCK1, g)
+    assert all(v == 0 for v in r.counts().values())
+    # vertices but no edges: only eps pairs
+    g = graphs.make_graph(70, [], label_names=["a"])
+    r = gpu_solve(ctx, G.DYCK1, g)
+    assert r.pair_set("S") == {(i, i) for i in range(70)}
+    assert r.count("X") == 0
+    # labels the grammar does not use are ignored; duplicates collapse
+    g = graphs.make_graph(4, [(0, "a", 1), (0, "a", 1), (1, "zz", 2), (1, "b", 3),
+                              (2, "b", 2)], label_names=["a", "b", "zz"])
+    assert_matches_oracle(gpu_solve(ctx, G.DYCK1, g), G.DYCK1, g)
+    # a grammar with only terminal rules (no binary productions)
+    text = "A -> a\nB -> b | a\n"
+    g = graphs.random_graph(50, 120, ["a", "b"], seed=3)
+    assert_matches_oracle(gpu_solve(ctx, text, g), text, g)
+    # eps only
+    r = gpu_solve(ctx, "E -> eps\n", graphs.random_graph(9, 5, ["a"], seed=1))
+    assert r.pair_set("E") == {(i, i) for i in range(9)}
+    # invalid graphs are rejected
+    with pytest.raises(m.CflrError) as e:
+        m.Graph(ctx, 3, [0], [3], [0], ["a"])
+    assert e.value.status == 1
+    with pytest.raises(m.CflrError) as e:
+        m.Graph(ctx, 3, [0], [1], [1], ["a"])
+    assert e.value.status == 1
+
+
+def test_naive_variant_matches(ctx):
+    for seed in range(3):
+        g = graphs.random_graph(120, 300, ["a", "d", "a_bar", "d_bar"], seed=40 + seed)
+        r = gpu_solve(ctx, G.ALIAS_FIG5B, g, semi_naive=0)
+        assert_matches_oracle(r, G.ALIAS_FIG5B, g, "naive")
+
+
+def test_overflowing_new_pair_buffer_reruns_round(ctx):
+    g = graphs.alias_graph(2000, seed=77)
+    r = gpu_solve(ctx, G.ALIAS_FIG5A_WCNF, g, delta_capacity=256)
+    assert r.stats()["reruns"] > 0
+    assert_matches_oracle(r, G.ALIAS_FIG5A_WCNF, g, "overflow")
+
+
+def test_repeat_solves_are_identical(ctx):
+    text, g = workloads.config("alias_50k", n=3000)
+    first = None
+    for _ in range(3):
+        r = gpu_solve(ctx, text, g)
+        d = {x: digest(*r.pairs(x)) for x in r.grammar.nonterminals}
+        if first is None:
+            first = d
+        assert d == first
+
+
+def test_device_pointer_io(ctx):
+    import torch
+    m = cflr()
+    g = graphs.erdos_renyi(300, 900, seed=8)
+    dev = torch.device("cuda", 0)
+    graph = m.Graph(ctx, g.n, torch.from_numpy(g.src.astype(np.int32)).to(dev),
+                    torch.from_numpy(g.dst.astype(np.int32)).to(dev),
+                    torch.from_numpy(g.label.astype(np.int32)).to(dev), g.label_names)
+    r = m.solve(ctx, m.Grammar(G.DYCK1), graph)
+    s, d = r.pairs("S", device=dev)
+    assert s.is_cuda
+    hs, hd = r.pairs("S")
+    assert np.array_equal(s.cpu().numpy().astype(np.uint32), hs)
+    assert np.array_equal(d.cpu().numpy().astype(np.uint32), hd)
+
+
+def test_batch_matches_single_solves(ctx):
+    m = cflr()
+    cases = [(G.DYCK1, graphs.erdos_renyi(n, 3 * n, seed=s)) for s, n in
+             [(1, 100), (2, 700), (3, 64)]]
+    cases += [(G.ALIAS_FIG5A_WCNF, graphs.alias_graph(n, seed=s)) for s, n in
+              [(4, 1500), (5, 300), (6, 5000)]]
+    cases += [(G.pointsto_fig4b(4), graphs.pointsto_graph(n, fields=4, seed=s))
+              for s, n in [(7, 900), (8, 2500)]]
+    cases.append((G.DYCK1, graphs.make_graph(0, [], label_names=["a"])))
+    grams = {t: m.Grammar(t) for t, _ in cases}
+    graph_objs = [m.Graph.from_workload(ctx, g) for _, g in cases]
+    res = m.solve_batch(ctx, [grams[t] for t, _ in cases], graph_objs)
+    for (text, g), r in zip(cases, res):
+        assert_matches_oracle(r, text, g, "batch")
+
+
+def test_server_results_equal_alone_and_in_the_mix(ctx):
+    m = cflr()
+    cases = [(G.DYCK1, graphs.erdos_renyi(400, 1200, seed=21)),
+             (G.ALIAS_FIG5A_WCNF, graphs.alias_graph(3000, seed=22)),
+             (G.pointsto_fig4b(4), graphs.pointsto_graph(2000, fields=4, seed=23)),
+             (G.ALIAS_FIG5B, graphs.alias_graph(1000, seed=24))] * 2
+    grams = {t: m.Grammar(t) for t, _ in cases}
+    objs = [m.Graph.from_workload(ctx, g) for _, g in cases]
+    srv = m.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=5)
+    tickets = [srv.submit(grams[t], o) for (t, _), o in zip(cases, objs)]
+    mixed = [srv.wait(t, timeout_s=300) for t in tickets]
+    times = [srv.times(t) for t in tickets]
+    srv.close()
+    for (text, g), r in zip(cases, mixed):
+        alone = m.solve(ctx, grams[text], m.Graph.from_workload(ctx, g))
+        for x in r.grammar.nonterminals:
+            sa, da = alone.pairs(x)
+            sm, dm = r.pairs(x)
+            assert np.array_equal(sa, sm) and np.array_equal(da, dm), x
+        assert_matches_oracle(r, text, g, "served")
+    # requests overlapped on the device: some admitted before others finished
+    admits = sorted(t[1] for t in times)
+    finishes = sorted(t[2] for t in times)
+    assert admits[1] < finishes[0]
+
+
+def test_server_rejects_oversized_request(ctx):
+    m = cflr()
+    srv = m.Server(ctx, hbm_budget_bytes=1 << 20, max_slots=2)
+    g = m.Graph.from_workload(ctx, graphs.alias_graph(4000, seed=3))
+    t = srv.submit(m.Grammar(G.ALIAS_FIG5A_WCNF), g)
+    with pytest.raises(m.CflrError) as e:
+        srv.wait(t, timeout_s=60)
+    assert e.value.status == 3
+    srv.close()
