@@ -240,13 +240,15 @@ void Run::ensure_capacity(uint64_t pairs, bool keep) {
     if (ap_cap_ >= limit) throw Error(CFLR_ENOMEM, "new-pair buffer at its 2^32 limit");
     pairs = std::min(pairs, limit);
     DevPool *pool = ctx_->pool.get();
-    DevBuf *bufs[7] = {&d_ap_key_, &d_ap_i_, &d_ap_j_, &d_rs_i_, &d_rs_k_, &d_cs_j_, &d_cs_k_};
-    for (DevBuf *b : bufs) {
-        DevBuf nb(pool, pairs * 4);
-        if (keep && b->ptr) hip_check(hipMemcpyAsync(nb.ptr, b->ptr, ap_cap_ * 4, hipMemcpyDeviceToDevice, s_),
-                                      "D2D");
+    DevBuf *bufs[5] = {&d_ap_key_, &d_ap_i_, &d_ap_j_, &d_rs_, &d_cs_};
+    const size_t width[5] = {4, 4, 4, 8, 8};
+    for (int q = 0; q < 5; q++) {
+        DevBuf nb(pool, pairs * width[q]);
+        if (keep && bufs[q]->ptr)
+            hip_check(hipMemcpyAsync(nb.ptr, bufs[q]->ptr, ap_cap_ * width[q], hipMemcpyDeviceToDevice, s_),
+                      "D2D");
         hip_check(hipStreamSynchronize(s_), "sync");
-        *b = std::move(nb);
+        *bufs[q] = std::move(nb);
     }
     ap_cap_ = pairs;
     ctx_->delta_capacity_hint = std::max(ctx_->delta_capacity_hint, pairs);
@@ -409,10 +411,8 @@ void Run::sort_appended() {
     S.ap_cap = ap_cap_;
     S.rcnt = d_rcnt_.as<uint32_t>();
     S.ccnt = d_ccnt_.as<uint32_t>();
-    S.rs_i = d_rs_i_.as<uint32_t>();
-    S.rs_k = d_rs_k_.as<uint32_t>();
-    S.cs_j = d_cs_j_.as<uint32_t>();
-    S.cs_k = d_cs_k_.as<uint32_t>();
+    S.rs = d_rs_.as<uint64_t>();
+    S.cs = d_cs_.as<uint64_t>();
     S.halt = reinterpret_cast<uint32_t *>(d_counters_.as<unsigned long long>() + 3);
     hip_check(launch_sort(S, row_hi(), d_bsum_.as<uint32_t>(), ctx_->num_cu * 8, s_), "sort");
     // the appended pairs are consumed
@@ -493,10 +493,8 @@ uint32_t Run::round() {
         A.ent_cnt = d_ent_cnt_.as<uint32_t>();
         A.item_prefix = d_prefix_.as<uint64_t>();
         A.nent = nent_;
-        A.rs_i = d_rs_i_.as<uint32_t>();
-        A.rs_k = d_rs_k_.as<uint32_t>();
-        A.cs_j = d_cs_j_.as<uint32_t>();
-        A.cs_k = d_cs_k_.as<uint32_t>();
+        A.rs = d_rs_.as<uint64_t>();
+        A.cs = d_cs_.as<uint64_t>();
         A.ap_key = d_ap_key_.as<uint32_t>();
         A.ap_i = d_ap_i_.as<uint32_t>();
         A.ap_j = d_ap_j_.as<uint32_t>();

@@ -197,7 +197,7 @@ class Run {
     DevBuf d_inst_, d_mats_, d_ent_, d_ent_start_, d_ent_cnt_, d_prefix_;
     uint32_t nent_ = 0;
     DevBuf d_rcnt_, d_ccnt_, d_bsum_;
-    DevBuf d_ap_key_, d_ap_i_, d_ap_j_, d_rs_i_, d_rs_k_, d_cs_j_, d_cs_k_;
+    DevBuf d_ap_key_, d_ap_i_, d_ap_j_, d_rs_, d_cs_;
     uint64_t ap_cap_ = 0;
     DevBuf d_counters_;  // [0] ap_count, [1] work_counter, [2] algo_bytes, [3] halt (u32)
     DevBuf d_inst_new_, d_inst_over_;

@@ -65,8 +65,8 @@ struct ProductArgs {
     const uint32_t *ent_cnt;      // number of new pairs of the operand
     const uint64_t *item_prefix;  // exclusive prefix of items per entry; [nent] = total
     uint32_t nent;
-    const uint32_t *rs_i, *rs_k;  // new pairs (i, k) in row order
-    const uint32_t *cs_j, *cs_k;  // new pairs (k, j) stored as (j, k) in column order
+    const uint64_t *rs;           // new pairs (i, k) in row order, packed (i << 32) | k
+    const uint64_t *cs;           // new pairs (k, j) in column order, packed (j << 32) | k
     uint32_t *ap_key, *ap_i, *ap_j;   // appended new pairs: (key, i, j)
     unsigned long long *ap_count;
     uint64_t ap_cap;
@@ -96,7 +96,7 @@ struct SortArgs {
     const unsigned long long *ap_count;
     uint64_t ap_cap;
     uint32_t *rcnt, *ccnt;       // counts -> inclusive scan -> starts (after scatter)
-    uint32_t *rs_i, *rs_k, *cs_j, *cs_k;
+    uint64_t *rs, *cs;
     const uint32_t *halt;
 };
 

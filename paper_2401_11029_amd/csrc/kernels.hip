@@ -77,6 +77,7 @@ constexpr uint32_t kSlotChunk = 1024;
 
 struct SlotChunk {
     uint64_t pos = 0, end = 0;  // wave-uniform
+    uint64_t bytes = 0;         // traffic accounting (lane 0), added once at exit
 };
 
 __device__ __forceinline__ void retire_chunk(const ProductArgs &A, SlotChunk &ch) {
@@ -146,7 +147,7 @@ __device__ __forceinline__ void flush(const ProductArgs &A, SlotChunk &ch, uint3
     if (STATS) {
         uint64_t lanes = __ballot(acc != 0);
         if (lanes && lane == 0 && first_touch<STATS>(A, inst, c, COL ? 1 : 0, key, seg, I))
-            atomicAdd(A.algo_bytes, 8ull * __popcll(lanes));
+            ch.bytes += 8ull * __popcll(lanes);
     }
     uint64_t pos;
     if (!reserve_slots(A, ch, inst, (uint32_t)__popcll(cand), &pos)) return;
@@ -181,7 +182,7 @@ __device__ __forceinline__ void flush(const ProductArgs &A, SlotChunk &ch, uint3
     }
     if (STATS) {
         uint32_t fresh = wave_sum((uint32_t)__popcll(nw));
-        if (fresh && lane == 0) atomicAdd(A.algo_bytes, 20ull * fresh);
+        if (fresh && lane == 0) ch.bytes += 20ull * fresh;
     }
 }
 
@@ -199,13 +200,13 @@ __device__ __forceinline__ void process_block(const ProductArgs &A, SlotChunk &c
     const MatDev Mp = A.mats[I.mat_off + (COL ? E.a : E.b)];
     const uint64_t *P = COL ? Mp.C : Mp.R;
     const uint64_t *PS = COL ? Mp.CS : Mp.RS;
-    const uint32_t *key = COL ? A.cs_j : A.rs_i;
-    const uint32_t *oth = COL ? A.cs_k : A.rs_k;
+    const uint64_t *pairs = COL ? A.cs : A.rs;
     uint32_t my_key = kHole, my_k = 0;
     uint64_t my_sm = 0;
     if (lane < cnt) {
-        my_key = key[start + lane];
-        my_k = oth[start + lane];
+        const uint64_t pk = pairs[start + lane];
+        my_key = (uint32_t)(pk >> 32);
+        my_k = (uint32_t)pk;
         my_sm = PS[(uint64_t)my_k * I.S + seg];
     }
     if (STATS) {
@@ -217,7 +218,7 @@ __device__ __forceinline__ void process_block(const ProductArgs &A, SlotChunk &c
             bytes = 8u * (uint32_t)__popcll(my_sm);
         if (count_pairs && lane < cnt) bytes += 8;  // the pair itself, once per production
         uint32_t tot = wave_sum(bytes);
-        if (tot && lane == 0) atomicAdd(A.algo_bytes, (unsigned long long)tot);
+        if (tot && lane == 0) ch.bytes += tot;
     }
     const uint32_t w = seg * kSegWords + lane;
     uint32_t t = 0;
@@ -279,6 +280,7 @@ __global__ __launch_bounds__(64) void product_kernel(ProductArgs A) {
             process_block<true, STATS>(A, ch, E.inst, I, E, start, cnt, seg, seg == 0);
     }
     retire_chunk(A, ch);
+    if (STATS && lane_id() == 0 && ch.bytes) atomicAdd(A.algo_bytes, (unsigned long long)ch.bytes);
 }
 
 // ------------------------------------------------------------- work table
@@ -380,38 +382,76 @@ __global__ __launch_bounds__(256) void settle_kernel(SettleArgs A) {
     if (run_cnt) atomicAdd(&A.inst_new[run_slot], run_cnt);
 }
 
-__global__ void count_kernel(SortArgs A) {
+// Runs of equal row ids among the 64 lanes of a wave (consecutive buffer
+// positions): the appended pairs of one flush share their row (row part) or
+// column (column part), so a run takes one atomic and one contiguous range.
+struct LaneRun {
+    bool head;       // first lane of its run
+    uint32_t len;    // run length (head lanes)
+    uint32_t first;  // head lane of this lane's run
+};
+
+__device__ __forceinline__ LaneRun lane_run(uint32_t rid) {
+    const uint32_t lane = lane_id();
+    const uint32_t prev = __shfl_up(rid, 1, 64);
+    LaneRun r;
+    r.head = lane == 0 || rid != prev;
+    const uint64_t H = __ballot(r.head);
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    r.first = 63 - __clzll((unsigned long long)(H & upto));
+    const uint64_t above = H & ~upto;
+    const uint32_t nxt = above ? (uint32_t)__ffsll((unsigned long long)above) - 1 : 64;
+    r.len = nxt - lane;
+    return r;
+}
+
+__device__ __forceinline__ void entry_rows(const SortArgs &A, uint64_t x, uint64_t n, uint32_t *r, uint32_t *c,
+                                           uint32_t *i, uint32_t *j) {
+    *r = *c = kHole;
+    if (x >= n) return;
+    const uint32_t key = A.ap_key[x];
+    if (key == kHole) return;
+    const InstDev I = A.inst[key_slot(key)];
+    const uint32_t b = I.rowbase + key_mat(key) * I.n;
+    *i = A.ap_i[x];
+    *j = A.ap_j[x];
+    *r = b + *i;
+    *c = b + *j;
+}
+
+__global__ __launch_bounds__(256) void count_kernel(SortArgs A) {
     if (*A.halt) return;
     uint64_t n = *A.ap_count;
     if (n > A.ap_cap) n = A.ap_cap;
-    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
-         x += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t key = A.ap_key[x];
-        if (key == kHole) continue;
-        const InstDev I = A.inst[key_slot(key)];
-        uint32_t b = I.rowbase + key_mat(key) * I.n;
-        atomicAdd(&A.rcnt[b + A.ap_i[x]], 1u);
-        atomicAdd(&A.ccnt[b + A.ap_j[x]], 1u);
+    for (uint64_t x0 = blockIdx.x * (uint64_t)blockDim.x; x0 < n; x0 += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t r, c, i = 0, j = 0;
+        entry_rows(A, x0 + threadIdx.x, n, &r, &c, &i, &j);
+        const LaneRun rr = lane_run(r), cr = lane_run(c);
+        if (rr.head && r != kHole) atomicAdd(&A.rcnt[r], rr.len);
+        if (cr.head && c != kHole) atomicAdd(&A.ccnt[c], cr.len);
     }
 }
 
-__global__ void scatter_kernel(SortArgs A) {
+__global__ __launch_bounds__(256) void scatter_kernel(SortArgs A) {
     if (*A.halt) return;
     uint64_t n = *A.ap_count;
     if (n > A.ap_cap) n = A.ap_cap;
-    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
-         x += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t key = A.ap_key[x];
-        if (key == kHole) continue;
-        const InstDev I = A.inst[key_slot(key)];
-        uint32_t b = I.rowbase + key_mat(key) * I.n;
-        uint32_t i = A.ap_i[x], j = A.ap_j[x];
-        uint32_t p = atomicSub(&A.rcnt[b + i], 1u) - 1;
-        A.rs_i[p] = i;
-        A.rs_k[p] = j;
-        uint32_t q = atomicSub(&A.ccnt[b + j], 1u) - 1;
-        A.cs_j[q] = j;
-        A.cs_k[q] = i;
+    const uint32_t lane = lane_id();
+    for (uint64_t x0 = blockIdx.x * (uint64_t)blockDim.x; x0 < n; x0 += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t r, c, i = 0, j = 0;
+        entry_rows(A, x0 + threadIdx.x, n, &r, &c, &i, &j);
+        const LaneRun rr = lane_run(r), cr = lane_run(c);
+        // the counts hold inclusive ends; taking len off the end of a row
+        // gives the run a contiguous range, and leaves the row's start
+        uint32_t p0 = 0, q0 = 0;
+        if (rr.head && r != kHole) p0 = atomicSub(&A.rcnt[r], rr.len) - rr.len;
+        if (cr.head && c != kHole) q0 = atomicSub(&A.ccnt[c], cr.len) - cr.len;
+        p0 = __shfl(p0, rr.first, 64) + (lane - rr.first);
+        q0 = __shfl(q0, cr.first, 64) + (lane - cr.first);
+        if (r != kHole) {
+            A.rs[p0] = ((uint64_t)i << 32) | j;
+            A.cs[q0] = ((uint64_t)j << 32) | i;
+        }
     }
 }
 

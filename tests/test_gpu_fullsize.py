@@ -1,0 +1,47 @@
+"""Full-size parity: the 50,000-vertex memory-alias configuration, solved with
+the launch configuration bench.py times (default options), against the
+oracle's stored per-non-terminal counts and SHA-256 digests
+(tests/golden/alias_50k.json, written by tests/golden/make_goldens.py)."""
+
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "alias_50k.json")
+
+
+def sha_of_pairs(s, d, chunk=1 << 26):
+    h = hashlib.sha256()
+    buf = np.empty((min(chunk, s.shape[0]), 2), dtype="<u4")
+    for a in range(0, s.shape[0], chunk):
+        b = min(a + chunk, s.shape[0])
+        v = buf[: b - a]
+        v[:, 0] = s[a:b]
+        v[:, 1] = d[a:b]
+        h.update(v.tobytes())
+    return h.hexdigest()
+
+
+def test_alias_50k_matches_oracle_digests(ctx):
+    import paper_2401_11029_amd as cflr
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    text, g = workloads.config("alias_50k")
+    r = cflr.solve(ctx, cflr.Grammar(text), cflr.Graph.from_workload(ctx, g))
+    assert r.grammar.nonterminals == gold["order"]
+    st = r.stats()
+    assert st["total_pairs"] == gold["total"]
+    print(f"alias_50k: {st['total_pairs']} pairs, {st['rounds']} rounds, "
+          f"{st['fixpoint_ms']:.0f} ms", flush=True)
+    for x in gold["order"]:
+        assert r.count(x) == gold["count"][x], x
+        s, d = r.pairs(x)
+        assert sha_of_pairs(s, d) == gold["sha256"][x], x
+        del s, d
