@@ -181,6 +181,19 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
                              const cflr_graph *const *graphs, uint32_t count,
                              const cflr_opts *opts, cflr_result **outs);
 
+/* Autotuner: solves graphs[0..count) (as cflr_solve_batch would) once per
+ * candidate launch shape -- product grid of {8, 16, 32, 48} waves per
+ * compute unit, and for batches of more than one graph {1, 2, 4, 8} rounds
+ * per hipGraph replay -- and keeps the fastest in ctx for every later solve
+ * on it that leaves those options at 0.  Results are identical for every
+ * shape (only the interleaving of the atomics changes); they are discarded.
+ * out_grid_waves / out_rounds_per_sync (nullable) receive the choice;
+ * out_best_ms (nullable) its time.  Errors: as cflr_solve_batch. */
+cflr_status cflr_autotune(cflr_ctx *ctx, const cflr_grammar *const *grammars,
+                          const cflr_graph *const *graphs, uint32_t count,
+                          uint32_t *out_grid_waves, uint32_t *out_rounds_per_sync,
+                          double *out_best_ms);
+
 /* ---- results --------------------------------------------------------------
  * nt indexes the user non-terminals of the result's grammar. */
 cflr_status cflr_result_count(const cflr_result *r, uint32_t nt, uint64_t *n_pairs);

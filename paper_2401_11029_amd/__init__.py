@@ -23,7 +23,7 @@ from . import _lib
 from ._lib import Opts, Stats, GrammarInfo, STATUS_NAMES
 
 __all__ = ["CflrError", "Context", "Grammar", "Graph", "Result", "Server",
-           "solve", "solve_batch", "opts", "lib"]
+           "solve", "solve_batch", "autotune", "opts", "lib"]
 
 
 class CflrError(RuntimeError):
@@ -248,6 +248,20 @@ def solve_batch(ctx: Context, grammars, graphs, options: Opts | None = None, **k
            for k in range(n)]
     _check(st)
     return res
+
+
+def autotune(ctx: Context, grammars, graphs):
+    """Pick the product grid (and, for several graphs, rounds per graph
+    replay) by timing each candidate; later solves on ctx use the choice."""
+    graphs = list(graphs)
+    if isinstance(grammars, Grammar):
+        grammars = [grammars] * len(graphs)
+    n = len(graphs)
+    ga = (C.c_void_p * n)(*[g._h.value for g in grammars])
+    gr = (C.c_void_p * n)(*[g._h.value for g in graphs])
+    w, r, ms = C.c_uint32(), C.c_uint32(), C.c_double()
+    _check(lib().cflr_autotune(ctx._h, ga, gr, n, C.byref(w), C.byref(r), C.byref(ms)))
+    return {"grid_waves": w.value, "rounds_per_sync": r.value, "best_ms": ms.value}
 
 
 class Server:

@@ -75,6 +75,9 @@ SIGNATURES = {
     "cflr_solve": (C.c_int, [P, P, P, C.POINTER(Opts), C.POINTER(P)]),
     "cflr_solve_batch": (C.c_int, [P, C.POINTER(P), C.POINTER(P), C.c_uint32,
                                    C.POINTER(Opts), C.POINTER(P)]),
+    "cflr_autotune": (C.c_int, [P, C.POINTER(P), C.POINTER(P), C.c_uint32,
+                                C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                C.POINTER(C.c_double)]),
     "cflr_result_count": (C.c_int, [P, C.c_uint32, C.POINTER(C.c_uint64)]),
     "cflr_result_copy": (C.c_int, [P, C.c_uint32, P, P, C.c_uint64, C.c_int,
                                    C.POINTER(C.c_uint64)]),

@@ -357,7 +357,8 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
                 next++;
             }
             if (!run.size()) break;
-            run.round();
+            run.rounds(o.rounds_per_sync ? o.rounds_per_sync
+                                         : (ctx->rounds_per_sync_tuned ? ctx->rounds_per_sync_tuned : 4));
             // retire finished instances
             std::vector<std::shared_ptr<Instance>> done;
             for (auto &ip : run.instances())
@@ -390,6 +391,57 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
             outs[k] = new cflr_result{all[k]};
         }
         if (status != CFLR_OK) return fail(status, "round limit reached before the fixpoint");
+        return CFLR_OK;
+    });
+}
+
+cflr_status cflr_autotune(cflr_ctx *ctx, const cflr_grammar *const *grammars, const cflr_graph *const *graphs,
+                          uint32_t count, uint32_t *out_grid_waves, uint32_t *out_rounds_per_sync,
+                          double *out_best_ms) {
+    return guard([&]() -> cflr_status {
+        if (!ctx || !count || !grammars || !graphs) return fail(CFLR_EINVAL, "null argument");
+        set_device(ctx);
+        const uint32_t waves[4] = {8, 16, 32, 48};
+        const uint32_t rps_batch[4] = {1, 2, 4, 8};
+        const uint32_t n_rps = count > 1 ? 4 : 1;
+        double best = 1e300;
+        uint32_t best_w = 0, best_r = 0;
+        std::vector<cflr_result *> outs(count, nullptr);
+        for (uint32_t wi = 0; wi < 4; wi++) {
+            for (uint32_t ri = 0; ri < n_rps; ri++) {
+                cflr_opts o;
+                cflr_opts_default(&o);
+                o.grid_waves = waves[wi] * ctx->num_cu;
+                o.rounds_per_sync = count > 1 ? rps_batch[ri] : 1;
+                hipEvent_t e0, e1;
+                hip_check(hipEventCreate(&e0), "event");
+                hip_check(hipEventCreate(&e1), "event");
+                hip_check(hipEventRecord(e0, ctx->stream), "event");
+                cflr_status st = count > 1 ? cflr_solve_batch(ctx, grammars, graphs, count, &o, outs.data())
+                                           : cflr_solve(ctx, grammars[0], graphs[0], &o, outs.data());
+                hip_check(hipEventRecord(e1, ctx->stream), "event");
+                hip_check(hipEventSynchronize(e1), "event");
+                float ms = 0;
+                hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                for (auto &r : outs) {
+                    cflr_result_free(r);
+                    r = nullptr;
+                }
+                if (st != CFLR_OK) return st;
+                if (ms < best) {
+                    best = ms;
+                    best_w = o.grid_waves;
+                    best_r = o.rounds_per_sync;
+                }
+            }
+        }
+        ctx->grid_waves_tuned = best_w;
+        ctx->rounds_per_sync_tuned = best_r;
+        if (out_grid_waves) *out_grid_waves = best_w;
+        if (out_rounds_per_sync) *out_rounds_per_sync = best_r;
+        if (out_best_ms) *out_best_ms = best;
         return CFLR_OK;
     });
 }

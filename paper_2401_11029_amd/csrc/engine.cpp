@@ -141,6 +141,9 @@ std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const
     std::vector<uint8_t> has_col;
     uint64_t bytes;
     plan_layout(low, g->n, &inst->S, &inst->Wp, &has_col, &bytes);
+    // the product kernel addresses a matrix with 32-bit word offsets
+    if ((uint64_t)g->n * inst->Wp >= (1ull << 32))
+        throw Error(CFLR_EUNSUPPORTED, "graph too large for dense bit matrices (n * row words >= 2^32)");
     inst->footprint = bytes;
     inst->counts.assign(low.user_names.size(), -1);
     const uint64_t layout_words = (uint64_t)g->n * inst->Wp;
@@ -208,6 +211,9 @@ Run::Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t row_capacity, uint32_t m
     d_counters_ = DevBuf(pool, 64);
     d_inst_new_ = DevBuf(pool, (uint64_t)max_inst_ * 8);
     d_inst_over_ = DevBuf(pool, (uint64_t)max_inst_ * 4);
+    d_active_ = DevBuf(pool, (uint64_t)max_inst_ * 4);
+    d_slot_stats_ = DevBuf(pool, (uint64_t)max_inst_ * sizeof(SlotStats));
+    hip_check(hipMemsetAsync(d_slot_stats_.ptr, 0, (uint64_t)max_inst_ * sizeof(SlotStats), s_), "memset");
     hip_check(hipMemsetAsync(d_counters_.ptr, 0, 64, s_), "memset");
     hip_check(hipMemsetAsync(d_inst_over_.ptr, 0, (uint64_t)max_inst_ * 4, s_), "memset");
     // the row/column starts must read as "no new pairs" before the first sort
@@ -216,6 +222,7 @@ Run::Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t row_capacity, uint32_t m
     hip_check(hipHostMalloc((void **)&h_new_, (uint64_t)max_inst_ * 8, 0), "hipHostMalloc");
     hip_check(hipHostMalloc((void **)&h_over_, (uint64_t)max_inst_ * 4, 0), "hipHostMalloc");
     hip_check(hipHostMalloc((void **)&h_counters_, 64, 0), "hipHostMalloc");
+    hip_check(hipHostMalloc((void **)&h_stats_, (uint64_t)max_inst_ * sizeof(SlotStats), 0), "hipHostMalloc");
     hip_check(hipEventCreate(&ev0_), "event");
     hip_check(hipEventCreate(&ev1_), "event");
     uint64_t cap = opts_.delta_capacity ? opts_.delta_capacity : ctx->delta_capacity_hint;
@@ -230,6 +237,8 @@ Run::~Run() {
     if (h_new_) (void)hipHostFree(h_new_);
     if (h_over_) (void)hipHostFree(h_over_);
     if (h_counters_) (void)hipHostFree(h_counters_);
+    if (h_stats_) (void)hipHostFree(h_stats_);
+    if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
     if (ev0_) (void)hipEventDestroy(ev0_);
     if (ev1_) (void)hipEventDestroy(ev1_);
 }
@@ -251,6 +260,7 @@ void Run::ensure_capacity(uint64_t pairs, bool keep) {
         *bufs[q] = std::move(nb);
     }
     ap_cap_ = pairs;
+    generation_++;
     ctx_->delta_capacity_hint = std::max(ctx_->delta_capacity_hint, pairs);
 }
 
@@ -332,6 +342,11 @@ void Run::add(const std::shared_ptr<Instance> &inst) {
     inst->stats.seed_pairs = h_new_[slot];
     inst->rounds = 0;
     inst->done = false;
+    // the seeds are not a round's new pairs; the slot's statistics start over
+    hip_check(launch_fill_u64(d_inst_new_.as<unsigned long long>() + slot, 1, 0, s_), "fill");
+    hip_check(launch_fill_u32(reinterpret_cast<uint32_t *>(d_slot_stats_.as<SlotStats>() + slot), 
+                              sizeof(SlotStats) / 4, 0, s_),
+              "fill");
 }
 
 uint64_t Run::row_hi() const {
@@ -381,6 +396,10 @@ void Run::rebuild_tables() {
         tbits += (uint64_t)in.low.nmat() * 2 * in.n * in.S;
     }
     nent_ = (uint32_t)he.size();
+    std::vector<uint32_t> active(max_inst_, 0);
+    for (auto &ip : insts_) active[ip->slot] = 1;
+    copy_sync(d_active_.ptr, active.data(), active.size() * 4, hipMemcpyHostToDevice, s_);
+    generation_++;
     d_inst_ = DevBuf(pool, hi.size() * sizeof(InstDev));
     d_mats_ = DevBuf(pool, std::max<size_t>(1, hm.size()) * sizeof(MatDev));
     d_ent_ = DevBuf(pool, std::max<size_t>(1, he.size()) * sizeof(EntryDev));
@@ -424,51 +443,47 @@ void Run::read_flags() {
     hip_check(hipMemcpyAsync(h_over_, d_inst_over_.ptr, (uint64_t)max_inst_ * 4, hipMemcpyDeviceToHost, s_),
               "D2H");
     hip_check(hipMemcpyAsync(h_counters_, d_counters_.ptr, 32, hipMemcpyDeviceToHost, s_), "D2H");
+    hip_check(hipMemcpyAsync(h_stats_, d_slot_stats_.ptr, (uint64_t)max_inst_ * sizeof(SlotStats),
+                             hipMemcpyDeviceToHost, s_),
+              "D2H");
     hip_check(hipStreamSynchronize(s_), "sync");
 }
 
-uint32_t Run::round() {
-    if (insts_.empty()) return 0;
-    // pairs appended since the last round (seeds of admitted instances, or
-    // the previous round's new pairs) become this round's dA / dB
-    if (!opts_.semi_naive) {
-        // Algorithm 1 as printed: every pair of M takes part in every round,
-        // so the new-pair buffer is refilled with all of M
-        hip_check(launch_fill_u64(d_counters_.as<unsigned long long>(), 1, 0, s_), "fill");
-        uint64_t total_pairs = 0;
-        std::vector<DevBuf> dmats;
-        for (auto &ip : insts_) {
-            DevBuf cnt(ctx_->pool.get(), std::max<uint32_t>(1, ip->n) * 4ull);
-            DevBuf tot(ctx_->pool.get(), 8);
-            hip_check(launch_fill_u64(tot.as<unsigned long long>(), 1, 0, s_), "fill");
-            for (uint32_t x = 0; x < ip->low.nmat(); x++)
-                hip_check(launch_row_count(ip->mats[x].R, ip->n, ip->S, cnt.as<uint32_t>(),
-                                           tot.as<unsigned long long>(), s_),
-                          "count");
-            unsigned long long t = 0;
-            copy_sync(&t, tot.ptr, 8, hipMemcpyDeviceToHost, s_);
-            total_pairs += t;
-        }
-        ensure_capacity(total_pairs, false);
-        for (auto &ip : insts_) {
-            DevBuf dm(ctx_->pool.get(), ip->mats.size() * sizeof(MatDev));
-            copy_sync(dm.ptr, ip->mats.data(), ip->mats.size() * sizeof(MatDev), hipMemcpyHostToDevice, s_);
-            InstDev I{ip->n, ip->S, ip->rowbase, 0};
-            hip_check(launch_extract_all(dm.as<MatDev>(), I, ip->slot, ip->low.nmat(), d_ap_key_.as<uint32_t>(),
-                                         d_ap_i_.as<uint32_t>(), d_ap_j_.as<uint32_t>(),
-                                         d_counters_.as<unsigned long long>(), ap_cap_,
-                                         d_inst_over_.as<uint32_t>() + ip->slot, s_),
-                      "extract");
-            hip_check(hipStreamSynchronize(s_), "sync");
-        }
+// Δ := M for every instance: the naive variant (Algorithm 1 as printed,
+// every pair takes part in every round), done before a round's sort.
+void Run::extract_all_pairs() {
+    hip_check(launch_fill_u64(d_counters_.as<unsigned long long>(), 1, 0, s_), "fill");
+    uint64_t total_pairs = 0;
+    for (auto &ip : insts_) {
+        DevBuf cnt(ctx_->pool.get(), std::max<uint32_t>(1, ip->n) * 4ull);
+        DevBuf tot(ctx_->pool.get(), 8);
+        hip_check(launch_fill_u64(tot.as<unsigned long long>(), 1, 0, s_), "fill");
+        for (uint32_t x = 0; x < ip->low.nmat(); x++)
+            hip_check(launch_row_count(ip->mats[x].R, ip->n, ip->S, cnt.as<uint32_t>(), tot.as<unsigned long long>(),
+                                       s_),
+                      "count");
+        unsigned long long t = 0;
+        copy_sync(&t, tot.ptr, 8, hipMemcpyDeviceToHost, s_);
+        total_pairs += t;
     }
-    rebuild_tables();
-    sort_appended();
-    for (auto &ip : insts_)
-        hip_check(launch_fill_u64(d_inst_new_.as<unsigned long long>() + ip->slot, 1, 0, s_), "fill");
+    ensure_capacity(total_pairs, false);
+    for (auto &ip : insts_) {
+        DevBuf dm(ctx_->pool.get(), ip->mats.size() * sizeof(MatDev));
+        copy_sync(dm.ptr, ip->mats.data(), ip->mats.size() * sizeof(MatDev), hipMemcpyHostToDevice, s_);
+        InstDev I{ip->n, ip->S, ip->rowbase, 0};
+        hip_check(launch_extract_all(dm.as<MatDev>(), I, ip->slot, ip->low.nmat(), d_ap_key_.as<uint32_t>(),
+                                     d_ap_i_.as<uint32_t>(), d_ap_j_.as<uint32_t>(),
+                                     d_counters_.as<unsigned long long>(), ap_cap_,
+                                     d_inst_over_.as<uint32_t>() + ip->slot, s_),
+                  "extract");
+        hip_check(hipStreamSynchronize(s_), "sync");
+    }
+}
 
+void Run::enqueue_product(bool timed) {
     unsigned long long *counters = d_counters_.as<unsigned long long>();
     uint32_t *halt = reinterpret_cast<uint32_t *>(counters + 3);
+    if (!nent_) return;
     PrepArgs P{};
     P.inst = d_inst_.as<InstDev>();
     P.ent = d_ent_.as<EntryDev>();
@@ -480,96 +495,151 @@ uint32_t Run::round() {
     P.item_prefix = d_prefix_.as<uint64_t>();
     P.work_counter = counters + 1;
     P.halt = halt;
+    hip_check(launch_prep(P, s_), "prep");
+    if (opts_.count_traffic && touched_bits_)
+        hip_check(launch_fill_u32(d_touched_.as<uint32_t>(), (touched_bits_ + 31) / 32, 0, s_), "fill");
+    ProductArgs A{};
+    A.inst = d_inst_.as<InstDev>();
+    A.mats = d_mats_.as<MatDev>();
+    A.ent = d_ent_.as<EntryDev>();
+    A.ent_start = d_ent_start_.as<uint32_t>();
+    A.ent_cnt = d_ent_cnt_.as<uint32_t>();
+    A.item_prefix = d_prefix_.as<uint64_t>();
+    A.nent = nent_;
+    A.rs = d_rs_.as<uint64_t>();
+    A.cs = d_cs_.as<uint64_t>();
+    A.ap_key = d_ap_key_.as<uint32_t>();
+    A.ap_i = d_ap_i_.as<uint32_t>();
+    A.ap_j = d_ap_j_.as<uint32_t>();
+    A.ap_count = counters;
+    A.ap_cap = ap_cap_;
+    A.inst_overflow = d_inst_over_.as<uint32_t>();
+    A.halt = halt;
+    A.work_counter = counters + 1;
+    A.touched = d_touched_.as<uint32_t>();
+    A.touched_off = d_touched_off_.as<uint64_t>();
+    A.algo_bytes = counters + 2;
+    if (timed) hip_check(hipEventRecord(ev0_, s_), "event");
+    hip_check(launch_product(A, grid_, opts_.count_traffic != 0, s_), "product");
+    if (timed) hip_check(hipEventRecord(ev1_, s_), "event");
+    product_launches_++;
+}
 
-    for (int attempt = 0;; attempt++) {
-        if (nent_) hip_check(launch_prep(P, s_), "prep");
-        if (opts_.count_traffic && touched_bits_)
-            hip_check(launch_fill_u32(d_touched_.as<uint32_t>(), (touched_bits_ + 31) / 32, 0, s_), "fill");
-        ProductArgs A{};
-        A.inst = d_inst_.as<InstDev>();
-        A.mats = d_mats_.as<MatDev>();
-        A.ent = d_ent_.as<EntryDev>();
-        A.ent_start = d_ent_start_.as<uint32_t>();
-        A.ent_cnt = d_ent_cnt_.as<uint32_t>();
-        A.item_prefix = d_prefix_.as<uint64_t>();
-        A.nent = nent_;
-        A.rs = d_rs_.as<uint64_t>();
-        A.cs = d_cs_.as<uint64_t>();
-        A.ap_key = d_ap_key_.as<uint32_t>();
-        A.ap_i = d_ap_i_.as<uint32_t>();
-        A.ap_j = d_ap_j_.as<uint32_t>();
-        A.ap_count = counters;
-        A.ap_cap = ap_cap_;
-        A.inst_overflow = d_inst_over_.as<uint32_t>();
-        A.halt = halt;
-        A.work_counter = counters + 1;
-        A.touched = d_touched_.as<uint32_t>();
-        A.touched_off = d_touched_off_.as<uint64_t>();
-        A.algo_bytes = counters + 2;
-        if (nent_) {
-            if (opts_.kernel_timing) hip_check(hipEventRecord(ev0_, s_), "event");
-            hip_check(launch_product(A, grid_, opts_.count_traffic != 0, s_), "product");
-            if (opts_.kernel_timing) hip_check(hipEventRecord(ev1_, s_), "event");
-            product_launches_++;
-        }
-        read_flags();
-        if (opts_.kernel_timing && nent_) {
-            float ms = 0;
-            hip_check(hipEventElapsedTime(&ms, ev0_, ev1_), "event");
-            product_ms_ += ms;
-        }
-        uint32_t halted = (uint32_t)(h_counters_[3] & 0xFFFFFFFFu);
-        if (!halted) break;
-        // overflow: keep [0, cap) (pairs and holes), grow, re-run the round
+void Run::enqueue_settle() {
+    unsigned long long *counters = d_counters_.as<unsigned long long>();
+    uint32_t *halt = reinterpret_cast<uint32_t *>(counters + 3);
+    SettleArgs T{};
+    T.inst = d_inst_.as<InstDev>();
+    T.mats = d_mats_.as<MatDev>();
+    T.ap_key = d_ap_key_.as<uint32_t>();
+    T.ap_i = d_ap_i_.as<uint32_t>();
+    T.ap_j = d_ap_j_.as<uint32_t>();
+    T.ap_count = counters;
+    T.ap_cap = ap_cap_;
+    T.inst_new = d_inst_new_.as<unsigned long long>();
+    T.halt = halt;
+    hip_check(launch_settle(T, ctx_->num_cu * 8, s_), "settle");
+    hip_check(launch_round_end(d_active_.as<uint32_t>(), d_inst_new_.as<unsigned long long>(),
+                               d_slot_stats_.as<SlotStats>(), max_inst_, halt, s_),
+              "round_end");
+}
+
+// One round without host synchronisation: sort the pending new pairs into
+// dA / dB, run the product, settle, fold the counts.  Every kernel skips its
+// work once an overflow has set the halt flag.
+void Run::enqueue_round(bool timed) {
+    sort_appended();
+    enqueue_product(timed);
+    enqueue_settle();
+}
+
+// After an overflow: the product of the overflowing round left M unchanged
+// for the candidates it could not append; dA / dB of that round are still in
+// rs / cs.  Grow the buffer (keeping [0, cap)), re-run that product, settle.
+void Run::recover() {
+    unsigned long long *counters = d_counters_.as<unsigned long long>();
+    uint32_t *halt = reinterpret_cast<uint32_t *>(counters + 3);
+    for (int attempt = 0; (uint32_t)(h_counters_[3] & 0xFFFFFFFFu); attempt++) {
+        if (attempt > 64) throw Error(CFLR_ENOMEM, "new-pair buffer keeps overflowing");
         reruns_++;
-        uint64_t asked = h_counters_[0];
-        uint64_t old_cap = ap_cap_;
+        const uint64_t asked = h_counters_[0];
+        const uint64_t old_cap = ap_cap_;
         ensure_capacity(std::max<uint64_t>(2 * old_cap, asked + asked / 2), true);
         unsigned long long v = old_cap;
         copy_sync(counters, &v, 8, hipMemcpyHostToDevice, s_);
         hip_check(launch_fill_u32(halt, 1, 0, s_), "fill");
         hip_check(launch_fill_u32(d_inst_over_.as<uint32_t>(), max_inst_, 0, s_), "fill");
-        if (attempt > 64) throw Error(CFLR_ENOMEM, "new-pair buffer keeps overflowing");
-    }
-    if (opts_.count_traffic) algo_bytes_ = h_counters_[2];
-    {
-        SettleArgs T{};
-        T.inst = d_inst_.as<InstDev>();
-        T.mats = d_mats_.as<MatDev>();
-        T.ap_key = d_ap_key_.as<uint32_t>();
-        T.ap_i = d_ap_i_.as<uint32_t>();
-        T.ap_j = d_ap_j_.as<uint32_t>();
-        T.ap_count = counters;
-        T.ap_cap = ap_cap_;
-        T.inst_new = d_inst_new_.as<unsigned long long>();
-        T.halt = halt;
-        hip_check(launch_settle(T, ctx_->num_cu * 8, s_), "settle");
+        enqueue_product(false);
+        enqueue_settle();
         read_flags();
     }
-    if (log_) {
-        uint64_t items = 0;
-        if (nent_) copy_sync(&items, d_prefix_.as<uint64_t>() + nent_, 8, hipMemcpyDeviceToHost, s_);
-        uint64_t fresh = 0;
-        for (auto &ip : insts_) fresh += h_new_[ip->slot];
-        std::fprintf(stderr, "[cflr] round %u: instances %zu items %llu appended %llu new %llu cap %llu reruns %u\n",
-                     (unsigned)round_no_, insts_.size(), (unsigned long long)items,
-                     (unsigned long long)h_counters_[0], (unsigned long long)fresh,
-                     (unsigned long long)ap_cap_, reruns_);
-    }
-    round_no_++;
+}
 
+uint32_t Run::round() { return rounds(1); }
+
+uint32_t Run::rounds(uint32_t R) {
+    if (insts_.empty()) return 0;
+    rebuild_tables();
+    const bool eager = R <= 1 || !opts_.semi_naive || opts_.kernel_timing || opts_.count_traffic ||
+                       s_ == nullptr;
+    if (eager) {
+        for (uint32_t r = 0; r < std::max<uint32_t>(1, R); r++) {
+            if (!opts_.semi_naive) extract_all_pairs();
+            enqueue_round(opts_.kernel_timing != 0);
+            read_flags();
+            if (opts_.kernel_timing && nent_) {
+                float ms = 0;
+                hip_check(hipEventElapsedTime(&ms, ev0_, ev1_), "event");
+                product_ms_ += ms;
+            }
+            if ((uint32_t)(h_counters_[3] & 0xFFFFFFFFu)) recover();
+            if (log_) log_round();
+            round_no_++;
+        }
+    } else {
+        // capture R rounds once per table/buffer generation, then replay
+        if (!graph_exec_ || graph_gen_ != generation_ || graph_rounds_ != R) {
+            if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
+            graph_exec_ = nullptr;
+            hipGraph_t g = nullptr;
+            hip_check(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal), "capture");
+            for (uint32_t r = 0; r < R; r++) enqueue_round(false);
+            hip_check(hipStreamEndCapture(s_, &g), "capture");
+            hip_check(hipGraphInstantiate(&graph_exec_, g, nullptr, nullptr, 0), "instantiate");
+            (void)hipGraphDestroy(g);
+            graph_gen_ = generation_;
+            graph_rounds_ = R;
+            product_launches_ -= R;  // counted below, per replay
+        }
+        hip_check(hipGraphLaunch(graph_exec_, s_), "graph launch");
+        product_launches_ += nent_ ? R : 0;
+        read_flags();
+        if ((uint32_t)(h_counters_[3] & 0xFFFFFFFFu)) recover();
+        if (log_) log_round();
+        round_no_ += R;
+    }
+    if (opts_.count_traffic) algo_bytes_ = h_counters_[2];
     uint32_t running = 0;
     for (auto &ip : insts_) {
         Instance &in = *ip;
-        if (in.done) continue;
-        in.rounds++;
-        uint64_t fresh = h_new_[in.slot];
-        in.stats.new_pairs += fresh;
-        in.stats.max_delta = std::max<uint64_t>(in.stats.max_delta, fresh);
-        if (fresh == 0) in.done = true;
-        else running++;
+        const SlotStats &st = h_stats_[in.slot];
+        in.rounds = st.rounds;
+        in.stats.new_pairs = st.new_total;
+        in.stats.max_delta = st.max_delta;
+        in.done = st.done != 0;
+        if (!in.done) running++;
     }
     return running;
+}
+
+void Run::log_round() {
+    uint64_t items = 0;
+    if (nent_) copy_sync(&items, d_prefix_.as<uint64_t>() + nent_, 8, hipMemcpyDeviceToHost, s_);
+    uint64_t fresh = 0;
+    for (auto &ip : insts_) fresh += h_stats_[ip->slot].new_total;
+    std::fprintf(stderr, "[cflr] round %u: instances %zu items %llu appended %llu derived-so-far %llu cap %llu reruns %u\n",
+                 (unsigned)round_no_, insts_.size(), (unsigned long long)items, (unsigned long long)h_counters_[0],
+                 (unsigned long long)fresh, (unsigned long long)ap_cap_, reruns_);
 }
 
 // ------------------------------------------------------------------ readout

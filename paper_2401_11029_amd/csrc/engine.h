@@ -79,6 +79,7 @@ struct cflr_ctx {
     std::unique_ptr<cflr::DevPool> pool;
     uint64_t delta_capacity_hint = 0;  // grown new-pair capacity, reused by later solves
     uint32_t grid_waves_tuned = 0;     // autotuned product grid (0 = not yet)
+    uint32_t rounds_per_sync_tuned = 0;  // autotuned rounds per graph replay (batches)
 };
 
 namespace cflr {
@@ -167,6 +168,9 @@ class Run {
     // One round over every admitted instance.  Instances whose round derived
     // nothing are marked done.  Returns the number still running.
     uint32_t round();
+    // R rounds; with R > 1 they are captured once into a hipGraph and
+    // replayed, with one host check per replay.  Returns the number running.
+    uint32_t rounds(uint32_t R);
     size_t size() const { return insts_.size(); }
     const std::vector<std::shared_ptr<Instance>> &instances() const { return insts_; }
     double product_ms() const { return product_ms_; }
@@ -184,6 +188,12 @@ class Run {
     void free_rows(uint64_t base, uint64_t rows);
     void read_flags();
     uint64_t row_hi() const;
+    void extract_all_pairs();
+    void enqueue_product(bool timed);
+    void enqueue_settle();
+    void enqueue_round(bool timed);
+    void recover();
+    void log_round();
 
     cflr_ctx *ctx_;
     cflr_opts opts_;
@@ -200,7 +210,11 @@ class Run {
     DevBuf d_ap_key_, d_ap_i_, d_ap_j_, d_rs_, d_cs_;
     uint64_t ap_cap_ = 0;
     DevBuf d_counters_;  // [0] ap_count, [1] work_counter, [2] algo_bytes, [3] halt (u32)
-    DevBuf d_inst_new_, d_inst_over_;
+    DevBuf d_inst_new_, d_inst_over_, d_active_, d_slot_stats_;
+    SlotStats *h_stats_ = nullptr;
+    hipGraphExec_t graph_exec_ = nullptr;
+    uint64_t generation_ = 1, graph_gen_ = 0;
+    uint32_t graph_rounds_ = 0;
     DevBuf d_touched_, d_touched_off_;
     uint64_t touched_bits_ = 0;
     // host mirrors (pinned)

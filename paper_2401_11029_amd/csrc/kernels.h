@@ -100,10 +100,11 @@ struct SortArgs {
     const uint32_t *halt;
 };
 
-// Second half of a round: the part that did not own a new pair's
-// authoritative layout copies it into the other layout; a pair the column
-// part found that the row part also found this round is dropped.  Counts
-// the surviving new pairs per instance.
+// Second half of a round: a pair the column part found is copied into the
+// row-major layout, which decides: if the row part found it too this round,
+// the column part's entry is dropped.  (Row-found pairs were copied into the
+// column-major layout by the product itself.)  Counts the surviving new
+// pairs per instance.
 struct SettleArgs {
     const InstDev *inst;
     const MatDev *mats;
@@ -131,6 +132,15 @@ struct SeedArgs {
     uint32_t *inst_overflow;
 };
 
+// Per-instance round bookkeeping kept on the device, so that several rounds
+// can be replayed (hipGraph) between host checks.
+struct SlotStats {
+    uint32_t rounds;               // rounds run until (and including) the empty one
+    uint32_t done;                 // a round derived nothing: converged
+    unsigned long long new_total;  // pairs derived by all rounds
+    unsigned long long max_delta;  // most pairs derived in one round
+};
+
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_product(const ProductArgs &A, uint32_t grid, bool stats, hipStream_t s);
@@ -142,6 +152,8 @@ hipError_t launch_sort(const SortArgs &A, uint64_t nrows, uint32_t *bsum, uint32
                        hipStream_t s);
 uint32_t scan_block_count(uint64_t nrows);
 hipError_t launch_settle(const SettleArgs &A, uint32_t grid, hipStream_t s);
+hipError_t launch_round_end(const uint32_t *active, unsigned long long *inst_new, SlotStats *st, uint32_t nslots,
+                            const uint32_t *halt, hipStream_t s);
 hipError_t launch_purge_slot(uint32_t *ap_key, const unsigned long long *ap_count, uint64_t ap_cap,
                              uint32_t slot, uint32_t grid, hipStream_t s);
 hipError_t launch_seed(const SeedArgs &A, hipStream_t s);

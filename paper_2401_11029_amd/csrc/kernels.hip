@@ -61,6 +61,28 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t *total) 
     return x - v;
 }
 
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+    const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
+    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Transpose a 64 x 64 bit matrix held one row per lane: afterwards bit u of
+// lane l is bit l of lane u's input (recursive block swap, 6 stages).
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x) {
+    const uint32_t lane = lane_id();
+    const uint64_t lo_mask[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                                 0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int st = 0; st < 6; st++) {
+        const int j = 32 >> st;
+        const uint64_t m = lo_mask[st];
+        const uint64_t p = shfl_xor64(x, j);
+        x = (lane & j) ? ((x & ~m) | ((p & ~m) >> j)) : ((x & m) | ((p & m) << j));
+    }
+    return x;
+}
+
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
     uint32_t t;
     wave_excl_scan(v, &t);
@@ -68,6 +90,11 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 }
 
 // ----------------------------------------------------------- product kernel
+
+// Matrices live in device global memory; loads through this type compile to
+// global_load (not flat_load, which also counts against the LDS/scalar
+// wait counter and serialises a batch of loads).
+typedef const uint64_t __attribute__((address_space(1))) *global_u64;
 
 
 // Slots of the append buffer are taken from the global counter in chunks
@@ -201,13 +228,14 @@ __device__ __forceinline__ void process_block(const ProductArgs &A, SlotChunk &c
     const uint64_t *P = COL ? Mp.C : Mp.R;
     const uint64_t *PS = COL ? Mp.CS : Mp.RS;
     const uint64_t *pairs = COL ? A.cs : A.rs;
-    uint32_t my_key = kHole, my_k = 0;
+    uint32_t my_key = kHole, my_k = 0, my_off = 0;
     uint64_t my_sm = 0;
     if (lane < cnt) {
         const uint64_t pk = pairs[start + lane];
         my_key = (uint32_t)(pk >> 32);
         my_k = (uint32_t)pk;
         my_sm = PS[(uint64_t)my_k * I.S + seg];
+        my_off = my_k * (uint32_t)Wp + seg * kSegWords;  // < 2^32: checked on the host
     }
     if (STATS) {
         // compulsory partner bytes: non-zero words of each partner segment,
@@ -220,31 +248,47 @@ __device__ __forceinline__ void process_block(const ProductArgs &A, SlotChunk &c
         uint32_t tot = wave_sum(bytes);
         if (tot && lane == 0) ch.bytes += tot;
     }
-    const uint32_t w = seg * kSegWords + lane;
+    // keep only the pairs whose partner segment has a non-zero word, in
+    // order (keys stay sorted): lane p takes the p-th such pair
+    const uint64_t nz = __ballot(my_sm != 0);
+    const uint32_t ncnt = (uint32_t)__popcll(nz);
+    if (!ncnt) return;
+    uint32_t src = 0;
+#pragma unroll
+    for (int b = 32; b; b >>= 1) {  // smallest src with popcount(nz & bits <= src) > lane
+        const uint32_t probe = src + b - 1;
+        const uint64_t below = probe >= 63 ? nz : nz & ((2ull << probe) - 1);
+        if ((uint32_t)__popcll(below) <= lane) src += b;
+    }
+    // every lane must take part in the cross-lane reads (a lane only
+    // receives data from source lanes that execute the read)
+    const uint32_t key_src = __shfl(my_key, src & 63, 64);
+    const uint32_t c_off = __shfl(my_off, src & 63, 64);
+    const uint32_t c_key = lane < ncnt ? key_src : kHole;
+    const global_u64 G = (global_u64)P;
     uint32_t t = 0;
-    while (t < cnt) {
-        const uint32_t cur = rdlane(my_key, t);
+    while (t < ncnt) {
+        const uint32_t cur = rdlane(c_key, t);
         // pairs are sorted by key, so equal keys occupy lanes t .. end-1
-        uint64_t same = __ballot(my_key == cur);
-        uint32_t end = 64 - __clzll((unsigned long long)same);
+        const uint64_t same = __ballot(c_key == cur);
+        const uint32_t end = 64 - __clzll((unsigned long long)same);
         uint64_t acc = 0;
         uint32_t u = t;
-        // eight independent partner loads in flight per batch
-        for (; u + 8 <= end; u += 8) {
-            uint64_t v[8];
+        // sixteen independent partner loads in flight per batch
+        for (; u + 16 <= end; u += 16) {
+            uint64_t v[16];
 #pragma unroll
-            for (int q = 0; q < 8; q++) {
-                uint64_t sm = rdlane64(my_sm, u + q);
-                uint32_t k = rdlane(my_k, u + q);
-                v[q] = ((sm >> lane) & 1) ? P[(uint64_t)k * Wp + w] : 0;
-            }
-            acc |= ((v[0] | v[1]) | (v[2] | v[3])) | ((v[4] | v[5]) | (v[6] | v[7]));
+            for (int q = 0; q < 16; q++) v[q] = G[(uint64_t)rdlane(c_off, u + q) + lane];
+#pragma unroll
+            for (int q = 0; q < 16; q++) acc |= v[q];
         }
-        for (; u < end; u++) {
-            uint64_t sm = rdlane64(my_sm, u);
-            uint32_t k = rdlane(my_k, u);
-            if ((sm >> lane) & 1) acc |= P[(uint64_t)k * Wp + w];
+        for (; u + 4 <= end; u += 4) {
+            uint64_t v[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) v[q] = G[(uint64_t)rdlane(c_off, u + q) + lane];
+            acc |= (v[0] | v[1]) | (v[2] | v[3]);
         }
+        for (; u < end; u++) acc |= G[(uint64_t)rdlane(c_off, u) + lane];
         flush<COL, STATS>(A, ch, inst, I, Mc, E.c, cur, seg, acc, Wp);
         t = end;
     }
@@ -353,12 +397,12 @@ __global__ __launch_bounds__(256) void settle_kernel(SettleArgs A) {
         const uint32_t key = A.ap_key[x];
         if (key == kHole || (key & kSettled)) continue;
         const uint32_t slot = key_slot(key);
-        const InstDev I = A.inst[slot];
-        const MatDev M = A.mats[I.mat_off + key_mat(key)];
-        const uint64_t Wp = (uint64_t)I.S * kSegWords;
-        const uint32_t i = A.ap_i[x], j = A.ap_j[x];
         bool keep = true;
         if (key & kColFound) {
+            const InstDev I = A.inst[slot];
+            const MatDev M = A.mats[I.mat_off + key_mat(key)];
+            const uint64_t Wp = (uint64_t)I.S * kSegWords;
+            const uint32_t i = A.ap_i[x], j = A.ap_j[x];
             // the row-major copy decides: set there already means the row
             // part found the pair too, and its entry is the one kept
             const uint64_t bit = 1ull << (j & 63);
@@ -367,10 +411,9 @@ __global__ __launch_bounds__(256) void settle_kernel(SettleArgs A) {
             if (keep && old == 0)
                 atomicOr((unsigned long long *)&M.RS[(uint64_t)i * I.S + (j >> 12)], 1ull << ((j >> 6) & 63));
             if (!keep) A.ap_key[x] = kHole;
-        } else {
-            atomicOr((unsigned long long *)&M.C[(uint64_t)j * Wp + (i >> 6)], 1ull << (i & 63));
-            atomicOr((unsigned long long *)&M.CS[(uint64_t)j * I.S + (i >> 12)], 1ull << ((i >> 6) & 63));
         }
+        // a row-found pair was already copied into the column-major layout by
+        // the product's flush; it is only counted here
         if (!keep) continue;
         if (slot != run_slot) {
             if (run_cnt) atomicAdd(&A.inst_new[run_slot], run_cnt);
@@ -628,6 +671,28 @@ __global__ __launch_bounds__(64) void extract_all_kernel(const MatDev *mats, Ins
     }
 }
 
+// End of a round: fold each running instance's count of new pairs into its
+// statistics; an instance whose round derived nothing is converged.
+__global__ void round_end_kernel(const uint32_t *active, unsigned long long *inst_new, SlotStats *st,
+                                 uint32_t nslots, const uint32_t *halt) {
+    if (*halt) return;
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nslots; x += gridDim.x * blockDim.x) {
+        if (!active[x]) continue;
+        SlotStats v = st[x];
+        const unsigned long long n = inst_new[x];
+        inst_new[x] = 0;
+        if (v.done) continue;
+        v.rounds++;
+        if (n == 0) {
+            v.done = 1;
+        } else {
+            v.new_total += n;
+            if (n > v.max_delta) v.max_delta = n;
+        }
+        st[x] = v;
+    }
+}
+
 // Drop the pending pairs of a retired instance (their slot may be reused).
 __global__ void purge_slot_kernel(uint32_t *ap_key, const unsigned long long *ap_count, uint64_t ap_cap,
                                   uint32_t slot) {
@@ -786,6 +851,14 @@ hipError_t launch_seed(const SeedArgs &A, hipStream_t s) {
         seed_eps_kernel<<<(uint32_t)g, 256, 0, s>>>(A);
         CFLR_LAUNCH_CHECK();
     }
+    return hipSuccess;
+}
+
+hipError_t launch_round_end(const uint32_t *active, unsigned long long *inst_new, SlotStats *st, uint32_t nslots,
+                            const uint32_t *halt, hipStream_t s) {
+    uint32_t g = (nslots + 255) / 256;
+    round_end_kernel<<<g ? g : 1, 256, 0, s>>>(active, inst_new, st, nslots, halt);
+    CFLR_LAUNCH_CHECK();
     return hipSuccess;
 }
 

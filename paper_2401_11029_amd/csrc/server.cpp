@@ -113,7 +113,7 @@ void cflr_server::loop() {
         }
         if (run->size() == 0) continue;
         try {
-            run->round();
+            run->rounds(opts.rounds_per_sync ? opts.rounds_per_sync : 2);
             std::vector<std::shared_ptr<Instance>> done;
             for (auto &ip : run->instances())
                 if (ip->done || (opts.max_rounds && ip->rounds >= opts.max_rounds)) done.push_back(ip);

@@ -185,6 +185,23 @@ def test_batch_matches_single_solves(ctx):
         assert_matches_oracle(r, text, g, "batch")
 
 
+@pytest.mark.parametrize("rounds_per_sync", [1, 3, 7])
+def test_batch_graph_replay_matches_oracle(ctx, rounds_per_sync):
+    # rounds captured into a hipGraph and replayed rounds_per_sync at a time,
+    # with host reads between replays; instances converge mid-replay
+    m = cflr()
+    cases = [(G.ALIAS_FIG5A_WCNF, graphs.alias_graph(n, seed=s)) for s, n in
+             [(31, 2500), (32, 400), (33, 6000)]]
+    cases.append((G.DYCK1, graphs.erdos_renyi(500, 1500, seed=34)))
+    grams = {t: m.Grammar(t) for t, _ in cases}
+    objs = [m.Graph.from_workload(ctx, g) for _, g in cases]
+    for rep in range(2):
+        res = m.solve_batch(ctx, [grams[t] for t, _ in cases], objs,
+                            rounds_per_sync=rounds_per_sync)
+        for (text, g), r in zip(cases, res):
+            assert_matches_oracle(r, text, g, f"graph R={rounds_per_sync} rep={rep}")
+
+
 def test_server_results_equal_alone_and_in_the_mix(ctx):
     m = cflr()
     cases = [(G.DYCK1, graphs.erdos_renyi(400, 1200, seed=21)),
