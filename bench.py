@@ -173,6 +173,7 @@ def batch(args):
     import torch
     import paper_2401_11029_amd as cflr
     from workloads import graphs, grammars
+    os.environ["CFLR_PROGRESS"] = "1"
     gs = graphs.alias_batch(args.batch_count, n_hi=args.batch_max_n)
     log(f"batch: {len(gs)} graphs, n {min(g.n for g in gs)}..{max(g.n for g in gs)}, "
         f"{sum(g.m for g in gs)} edges")
@@ -181,8 +182,10 @@ def batch(args):
     objs = [cflr.Graph.from_workload(ctx, g) for g in gs]
     for r in cflr.solve_batch(ctx, gr, objs[:8]):   # warm-up
         r.close()
-    # autotune the launch shape on every 8th graph (a 32-graph sample)
-    tuned = cflr.autotune(ctx, gr, objs[::8])
+    log("warm-up done; autotuning on every 16th graph")
+    # autotune the launch shape on a 16-graph sample (one line per candidate)
+    os.environ["CFLR_TUNE_LOG"] = "1"
+    tuned = cflr.autotune(ctx, gr, objs[::16])
     log(f"autotuned: {tuned}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -195,10 +198,12 @@ def batch(args):
     log(f"batched: {tb:.2f} s")
     t0 = time.perf_counter()
     seq_pairs = []
-    for o in objs:
+    for q, o in enumerate(objs):
         r = cflr.solve(ctx, gr, o)
         seq_pairs.append(r.stats()["total_pairs"])
         r.close()
+        if q % 32 == 31:
+            log(f"sequential: {q + 1} solves, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
     log(f"sequential: {ts:.2f} s")

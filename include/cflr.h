@@ -182,8 +182,8 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
                              const cflr_opts *opts, cflr_result **outs);
 
 /* Autotuner: solves graphs[0..count) (as cflr_solve_batch would) once per
- * candidate launch shape -- product grid of {8, 16, 32, 48} waves per
- * compute unit, and for batches of more than one graph {1, 2, 4, 8} rounds
+ * candidate launch shape -- product grid of {16, 32, 48} waves per
+ * compute unit, and for batches of more than one graph {2, 4, 8} rounds
  * per hipGraph replay -- and keeps the fastest in ctx for every later solve
  * on it that leaves those options at 0.  Results are identical for every
  * shape (only the interleaving of the atomics changes); they are discarded.

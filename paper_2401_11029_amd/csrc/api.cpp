@@ -6,6 +6,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -332,13 +334,20 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
         hip_check(hipEventCreate(&e1), "event");
         hip_check(hipEventRecord(e0, ctx->stream), "event");
         Run run(ctx, o, rows, count);
-        const uint64_t budget = (uint64_t)((double)(free_b + ctx->pool->held()) * 0.6);
+        // device memory for matrices: 70 % of what is free, minus the
+        // new-pair buffer (28 bytes a pair, grown on overflow) and headroom
+        // for it to double once
+        const uint64_t avail = (uint64_t)((double)(free_b + ctx->pool->held()) * 0.7);
+        const uint64_t delta_bytes = 3 * 28ull * run.delta_capacity();
+        const uint64_t budget = avail > delta_bytes ? avail - delta_bytes : avail / 4;
         std::vector<std::shared_ptr<Instance>> all(count);
         uint64_t in_use = 0;
         uint32_t next = 0;
         cflr_status status = CFLR_OK;
         std::vector<uint64_t> fp(count);
         for (uint32_t k = 0; k < count; k++) fp[k] = instance_footprint(grammars[k]->low, graphs[k]->n);
+        const bool progress = std::getenv("CFLR_PROGRESS") != nullptr;
+        uint32_t finished = 0;
         while (true) {
             // admit
             while (next < count) {
@@ -373,6 +382,10 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
                 ip->stats.rounds = ip->rounds;
                 compact_instance(*ip);
             }
+            finished += (uint32_t)done.size();
+            if (progress && !done.empty())
+                std::fprintf(stderr, "[cflr] batch: %u of %u graphs done, %zu running\n", finished, count,
+                             run.size());
         }
         hip_check(hipEventRecord(e1, ctx->stream), "event");
         hip_check(hipEventSynchronize(e1), "event");
@@ -401,13 +414,14 @@ cflr_status cflr_autotune(cflr_ctx *ctx, const cflr_grammar *const *grammars, co
     return guard([&]() -> cflr_status {
         if (!ctx || !count || !grammars || !graphs) return fail(CFLR_EINVAL, "null argument");
         set_device(ctx);
-        const uint32_t waves[4] = {8, 16, 32, 48};
-        const uint32_t rps_batch[4] = {1, 2, 4, 8};
-        const uint32_t n_rps = count > 1 ? 4 : 1;
+        const uint32_t waves[3] = {16, 32, 48};
+        const uint32_t rps_batch[3] = {2, 4, 8};
+        const uint32_t n_rps = count > 1 ? 3 : 1;
+        const bool verbose = std::getenv("CFLR_TUNE_LOG") != nullptr;
         double best = 1e300;
         uint32_t best_w = 0, best_r = 0;
         std::vector<cflr_result *> outs(count, nullptr);
-        for (uint32_t wi = 0; wi < 4; wi++) {
+        for (uint32_t wi = 0; wi < 3; wi++) {
             for (uint32_t ri = 0; ri < n_rps; ri++) {
                 cflr_opts o;
                 cflr_opts_default(&o);
@@ -430,6 +444,9 @@ cflr_status cflr_autotune(cflr_ctx *ctx, const cflr_grammar *const *grammars, co
                     r = nullptr;
                 }
                 if (st != CFLR_OK) return st;
+                if (verbose)
+                    std::fprintf(stderr, "[cflr] autotune grid_waves=%u rounds_per_sync=%u: %.1f ms\n", o.grid_waves,
+                                 o.rounds_per_sync, ms);
                 if (ms < best) {
                     best = ms;
                     best_w = o.grid_waves;

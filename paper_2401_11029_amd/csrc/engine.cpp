@@ -209,12 +209,13 @@ Run::Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t row_capacity, uint32_t m
     d_ccnt_ = DevBuf(pool, (row_cap_ + 1) * 4);
     d_bsum_ = DevBuf(pool, 2ull * scan_block_count(row_cap_) * 4);
     d_counters_ = DevBuf(pool, 64);
-    d_inst_new_ = DevBuf(pool, (uint64_t)max_inst_ * 8);
+    d_inst_new_ = DevBuf(pool, (uint64_t)max_inst_ * kCountShards * 8);
     d_inst_over_ = DevBuf(pool, (uint64_t)max_inst_ * 4);
     d_active_ = DevBuf(pool, (uint64_t)max_inst_ * 4);
     d_slot_stats_ = DevBuf(pool, (uint64_t)max_inst_ * sizeof(SlotStats));
     hip_check(hipMemsetAsync(d_slot_stats_.ptr, 0, (uint64_t)max_inst_ * sizeof(SlotStats), s_), "memset");
     hip_check(hipMemsetAsync(d_counters_.ptr, 0, 64, s_), "memset");
+    hip_check(hipMemsetAsync(d_inst_new_.ptr, 0, (uint64_t)max_inst_ * kCountShards * 8, s_), "memset");
     hip_check(hipMemsetAsync(d_inst_over_.ptr, 0, (uint64_t)max_inst_ * 4, s_), "memset");
     // the row/column starts must read as "no new pairs" before the first sort
     hip_check(launch_fill_u32(d_rcnt_.as<uint32_t>(), row_cap_ + 1, 0, s_), "fill");
@@ -310,7 +311,9 @@ void Run::add(const std::shared_ptr<Instance> &inst) {
     unsigned long long cur = 0;
     copy_sync(&cur, d_counters_.ptr, 8, hipMemcpyDeviceToHost, s_);
     ensure_capacity(cur + inst->max_seeds, true);
-    hip_check(launch_fill_u64(d_inst_new_.as<unsigned long long>() + slot, 1, 0, s_), "fill");
+    hip_check(launch_fill_u64(d_inst_new_.as<unsigned long long>() + (uint64_t)slot * kCountShards, kCountShards, 0,
+                              s_),
+              "fill");
     DevBuf dmats(ctx_->pool.get(), inst->mats.size() * sizeof(MatDev));
     hip_check(hipMemcpyAsync(dmats.ptr, inst->mats.data(), inst->mats.size() * sizeof(MatDev),
                              hipMemcpyHostToDevice, s_),
@@ -335,7 +338,7 @@ void Run::add(const std::shared_ptr<Instance> &inst) {
     A.inst_new = d_inst_new_.as<unsigned long long>();
     A.inst_overflow = d_inst_over_.as<uint32_t>();
     hip_check(launch_seed(A, s_), "seed");
-    hip_check(hipMemcpyAsync(h_new_ + slot, d_inst_new_.as<unsigned long long>() + slot, 8,
+    hip_check(hipMemcpyAsync(h_new_ + slot, d_inst_new_.as<unsigned long long>() + (uint64_t)slot * kCountShards, 8,
                              hipMemcpyDeviceToHost, s_),
               "D2H");
     hip_check(hipStreamSynchronize(s_), "sync");
@@ -343,7 +346,9 @@ void Run::add(const std::shared_ptr<Instance> &inst) {
     inst->rounds = 0;
     inst->done = false;
     // the seeds are not a round's new pairs; the slot's statistics start over
-    hip_check(launch_fill_u64(d_inst_new_.as<unsigned long long>() + slot, 1, 0, s_), "fill");
+    hip_check(launch_fill_u64(d_inst_new_.as<unsigned long long>() + (uint64_t)slot * kCountShards, kCountShards, 0,
+                              s_),
+              "fill");
     hip_check(launch_fill_u32(reinterpret_cast<uint32_t *>(d_slot_stats_.as<SlotStats>() + slot), 
                               sizeof(SlotStats) / 4, 0, s_),
               "fill");
@@ -435,11 +440,10 @@ void Run::sort_appended() {
     S.halt = reinterpret_cast<uint32_t *>(d_counters_.as<unsigned long long>() + 3);
     hip_check(launch_sort(S, row_hi(), d_bsum_.as<uint32_t>(), ctx_->num_cu * 8, s_), "sort");
     // the appended pairs are consumed
-    hip_check(launch_fill_u64(d_counters_.as<unsigned long long>(), 1, 0, s_), "fill");
+    hip_check(launch_reset_appends(d_counters_.as<unsigned long long>(), S.halt, s_), "reset");
 }
 
 void Run::read_flags() {
-    hip_check(hipMemcpyAsync(h_new_, d_inst_new_.ptr, (uint64_t)max_inst_ * 8, hipMemcpyDeviceToHost, s_), "D2H");
     hip_check(hipMemcpyAsync(h_over_, d_inst_over_.ptr, (uint64_t)max_inst_ * 4, hipMemcpyDeviceToHost, s_),
               "D2H");
     hip_check(hipMemcpyAsync(h_counters_, d_counters_.ptr, 32, hipMemcpyDeviceToHost, s_), "D2H");

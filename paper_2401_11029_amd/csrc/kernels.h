@@ -19,6 +19,7 @@ namespace cflr {
 constexpr uint32_t kWave = 64;        // lanes per wavefront (CDNA)
 constexpr uint32_t kSegWords = 64;    // words per row segment
 constexpr uint32_t kPairsPerItem = 64;  // new pairs per product work item
+constexpr uint32_t kCountShards = 64;   // counters per instance for new pairs
 
 // Key of an appended pair: bits 0..15 matrix, bits 16..29 instance slot,
 // bit 30 "settled" (both layouts already hold the pair: seeds, restarts),
@@ -112,7 +113,7 @@ struct SettleArgs {
     const uint32_t *ap_i, *ap_j;
     const unsigned long long *ap_count;
     uint64_t ap_cap;
-    unsigned long long *inst_new;
+    unsigned long long *inst_new;  // [slot * kCountShards + shard]
     const uint32_t *halt;
 };
 
@@ -154,6 +155,7 @@ uint32_t scan_block_count(uint64_t nrows);
 hipError_t launch_settle(const SettleArgs &A, uint32_t grid, hipStream_t s);
 hipError_t launch_round_end(const uint32_t *active, unsigned long long *inst_new, SlotStats *st, uint32_t nslots,
                             const uint32_t *halt, hipStream_t s);
+hipError_t launch_reset_appends(unsigned long long *ap_count, const uint32_t *halt, hipStream_t s);
 hipError_t launch_purge_slot(uint32_t *ap_key, const unsigned long long *ap_count, uint64_t ap_cap,
                              uint32_t slot, uint32_t grid, hipStream_t s);
 hipError_t launch_seed(const SeedArgs &A, hipStream_t s);

@@ -389,22 +389,22 @@ __global__ __launch_bounds__(256) void settle_kernel(SettleArgs A) {
     if (*A.halt) return;
     uint64_t n = *A.ap_count;
     if (n > A.ap_cap) n = A.ap_cap;
-    // survivors are counted per thread and flushed when the instance changes
-    uint32_t run_slot = kHole;
-    unsigned long long run_cnt = 0;
-    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
-         x += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t key = A.ap_key[x];
-        if (key == kHole || (key & kSettled)) continue;
-        const uint32_t slot = key_slot(key);
-        bool keep = true;
-        if (key & kColFound) {
+    const uint32_t lane = lane_id();
+    // survivors are counted per wave into one of kCountShards counters of
+    // their instance, so that no single address takes every update
+    const uint32_t shard = (blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) % kCountShards;
+    for (uint64_t x0 = blockIdx.x * (uint64_t)blockDim.x; x0 < n; x0 += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t x = x0 + threadIdx.x;
+        const uint32_t key = x < n ? A.ap_key[x] : kHole;
+        bool keep = key != kHole && !(key & kSettled);
+        const uint32_t slot = keep ? key_slot(key) : 0;
+        if (keep && (key & kColFound)) {
+            // the row-major copy decides: set there already means the row
+            // part found the pair too, and its entry is the one kept
             const InstDev I = A.inst[slot];
             const MatDev M = A.mats[I.mat_off + key_mat(key)];
             const uint64_t Wp = (uint64_t)I.S * kSegWords;
             const uint32_t i = A.ap_i[x], j = A.ap_j[x];
-            // the row-major copy decides: set there already means the row
-            // part found the pair too, and its entry is the one kept
             const uint64_t bit = 1ull << (j & 63);
             unsigned long long old = atomicOr((unsigned long long *)&M.R[(uint64_t)i * Wp + (j >> 6)], bit);
             keep = !(old & bit);
@@ -412,17 +412,19 @@ __global__ __launch_bounds__(256) void settle_kernel(SettleArgs A) {
                 atomicOr((unsigned long long *)&M.RS[(uint64_t)i * I.S + (j >> 12)], 1ull << ((j >> 6) & 63));
             if (!keep) A.ap_key[x] = kHole;
         }
-        // a row-found pair was already copied into the column-major layout by
-        // the product's flush; it is only counted here
-        if (!keep) continue;
-        if (slot != run_slot) {
-            if (run_cnt) atomicAdd(&A.inst_new[run_slot], run_cnt);
-            run_slot = slot;
-            run_cnt = 0;
+        // (a row-found pair was already copied into the column-major layout
+        // by the product's flush; it is only counted here)
+        const uint64_t kept = __ballot(keep);
+        if (!kept) continue;
+        const uint32_t leader = (uint32_t)__ffsll((unsigned long long)kept) - 1;
+        const uint32_t s0 = rdlane(slot, leader);
+        if (__ballot(keep && slot != s0) == 0) {
+            if (lane == leader)
+                atomicAdd(&A.inst_new[(uint64_t)s0 * kCountShards + shard], (unsigned long long)__popcll(kept));
+        } else if (keep) {
+            atomicAdd(&A.inst_new[(uint64_t)slot * kCountShards + shard], 1ull);
         }
-        run_cnt++;
     }
-    if (run_cnt) atomicAdd(&A.inst_new[run_slot], run_cnt);
 }
 
 // Runs of equal row ids among the 64 lanes of a wave (consecutive buffer
@@ -606,7 +608,7 @@ __device__ __forceinline__ void seed_pair(const SeedArgs &A, uint32_t x, uint32_
                      1ull << ((i >> 6) & 63));
     }
     unsigned long long p = atomicAdd(A.ap_count, 1ull);
-    atomicAdd(&A.inst_new[A.inst], 1ull);
+    atomicAdd(&A.inst_new[(uint64_t)A.inst * kCountShards], 1ull);
     if (p < A.ap_cap) {
         A.ap_key[p] = pair_key(A.inst, x, kSettled);
         A.ap_i[p] = i;
@@ -679,8 +681,11 @@ __global__ void round_end_kernel(const uint32_t *active, unsigned long long *ins
     for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nslots; x += gridDim.x * blockDim.x) {
         if (!active[x]) continue;
         SlotStats v = st[x];
-        const unsigned long long n = inst_new[x];
-        inst_new[x] = 0;
+        unsigned long long n = 0;
+        for (uint32_t q = 0; q < kCountShards; q++) {
+            n += inst_new[(uint64_t)x * kCountShards + q];
+            inst_new[(uint64_t)x * kCountShards + q] = 0;
+        }
         if (v.done) continue;
         v.rounds++;
         if (n == 0) {
@@ -691,6 +696,12 @@ __global__ void round_end_kernel(const uint32_t *active, unsigned long long *ins
         }
         st[x] = v;
     }
+}
+
+// The appended pairs have been sorted: empty the buffer.  Skipped after an
+// overflow, so the host still sees how many slots the round asked for.
+__global__ void reset_appends_kernel(unsigned long long *ap_count, const uint32_t *halt) {
+    if (!*halt) *ap_count = 0;
 }
 
 // Drop the pending pairs of a retired instance (their slot may be reused).
@@ -858,6 +869,12 @@ hipError_t launch_round_end(const uint32_t *active, unsigned long long *inst_new
                             const uint32_t *halt, hipStream_t s) {
     uint32_t g = (nslots + 255) / 256;
     round_end_kernel<<<g ? g : 1, 256, 0, s>>>(active, inst_new, st, nslots, halt);
+    CFLR_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_reset_appends(unsigned long long *ap_count, const uint32_t *halt, hipStream_t s) {
+    reset_appends_kernel<<<1, 1, 0, s>>>(ap_count, halt);
     CFLR_LAUNCH_CHECK();
     return hipSuccess;
 }
