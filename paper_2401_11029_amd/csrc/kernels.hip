@@ -378,6 +378,15 @@ __global__ void fill_u32_kernel(uint32_t *a, uint64_t n, uint32_t v) {
         a[x] = v;
 }
 
+// fill that is skipped once an overflow has halted the round (inside a
+// replayed round it must not destroy state the host's re-run still needs)
+__global__ void fill_u32_unless_halted_kernel(uint32_t *a, uint64_t n, uint32_t v, const uint32_t *halt) {
+    if (*halt) return;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
+         x += (uint64_t)gridDim.x * blockDim.x)
+        a[x] = v;
+}
+
 __global__ void fill_u64_kernel(unsigned long long *a, uint64_t n, unsigned long long v) {
     for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
          x += (uint64_t)gridDim.x * blockDim.x)
@@ -826,10 +835,14 @@ hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long
 hipError_t launch_sort(const SortArgs &A, uint64_t nrows, uint32_t *bsum, uint32_t sort_grid,
                        hipStream_t s) {
     const uint64_t len = nrows + 1;
-    hipError_t e = launch_fill_u32(A.rcnt, len, 0, s);
-    if (e != hipSuccess) return e;
-    e = launch_fill_u32(A.ccnt, len, 0, s);
-    if (e != hipSuccess) return e;
+    {
+        uint64_t g = (len + 255) / 256;
+        if (g > 8192) g = 8192;
+        fill_u32_unless_halted_kernel<<<(uint32_t)g, 256, 0, s>>>(A.rcnt, len, 0, A.halt);
+        CFLR_LAUNCH_CHECK();
+        fill_u32_unless_halted_kernel<<<(uint32_t)g, 256, 0, s>>>(A.ccnt, len, 0, A.halt);
+        CFLR_LAUNCH_CHECK();
+    }
     count_kernel<<<sort_grid, 256, 0, s>>>(A);
     CFLR_LAUNCH_CHECK();
     uint32_t nblk = (uint32_t)((len + kScanTile - 1) / kScanTile);

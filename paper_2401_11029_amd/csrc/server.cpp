@@ -120,6 +120,7 @@ void cflr_server::loop() {
             for (auto &ip : done) {
                 run->remove(ip.get());
                 ip->stats.rounds = ip->rounds;
+                ip->stats.reruns = run->reruns();
                 cflr_status st = ip->done ? CFLR_OK : CFLR_ETIMEOUT;
                 compact_instance(*ip);
                 instance_counts(*ip);

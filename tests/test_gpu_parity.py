@@ -202,6 +202,22 @@ def test_batch_graph_replay_matches_oracle(ctx, rounds_per_sync):
             assert_matches_oracle(r, text, g, f"graph R={rounds_per_sync} rep={rep}")
 
 
+@pytest.mark.parametrize("rounds_per_sync", [2, 5])
+def test_overflow_inside_graph_replay_reruns_round(ctx, rounds_per_sync):
+    # a tiny new-pair buffer overflows inside replayed rounds: every kernel
+    # after the overflow must leave the round's state intact for the re-run
+    m = cflr()
+    cases = [(G.ALIAS_FIG5A_WCNF, graphs.alias_graph(n, seed=s)) for s, n in [(41, 3000), (42, 900)]]
+    cases.append((G.DYCK1, graphs.erdos_renyi(700, 2100, seed=43)))
+    grams = {t: m.Grammar(t) for t, _ in cases}
+    objs = [m.Graph.from_workload(ctx, g) for _, g in cases]
+    res = m.solve_batch(ctx, [grams[t] for t, _ in cases], objs,
+                        rounds_per_sync=rounds_per_sync, delta_capacity=512)
+    assert res[0].stats()["reruns"] > 0
+    for (text, g), r in zip(cases, res):
+        assert_matches_oracle(r, text, g, f"overflow in replay R={rounds_per_sync}")
+
+
 def test_server_results_equal_alone_and_in_the_mix(ctx):
     m = cflr()
     cases = [(G.DYCK1, graphs.erdos_renyi(400, 1200, seed=21)),
