@@ -37,6 +37,8 @@ void compact_instance(Instance &in) {
         mats[x].R = p;
         mats[x].RS = nullptr;
         mats[x].C = mats[x].CS = nullptr;
+        mats[x].sort = 0;
+        mats[x].pad = 0;
         p += words;
     }
     hip_check(hipStreamSynchronize(in.ctx->stream), "sync");

@@ -158,6 +158,8 @@ std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const
         M.RS = p;
         p += sum_words;
         M.C = M.CS = nullptr;
+        M.sort = (low.slot_a[x] ? kSortRows : 0u) | (low.slot_b[x] ? kSortCols : 0u);
+        M.pad = 0;
         if (has_col[x]) {
             M.C = p;
             p += layout_words;
@@ -428,6 +430,7 @@ void Run::rebuild_tables() {
 void Run::sort_appended() {
     SortArgs S{};
     S.inst = d_inst_.as<InstDev>();
+    S.mats = d_mats_.as<MatDev>();
     S.ap_key = d_ap_key_.as<uint32_t>();
     S.ap_i = d_ap_i_.as<uint32_t>();
     S.ap_j = d_ap_j_.as<uint32_t>();

@@ -39,7 +39,11 @@ __host__ __device__ inline uint32_t key_mat(uint32_t key) { return key & 0xFFFFu
 struct MatDev {
     uint64_t *R, *RS;  // row-major bits and summaries (always present)
     uint64_t *C, *CS;  // column-major copy (null when no production needs it)
+    uint32_t sort;     // kSortRows: new pairs needed in row order (the matrix
+                       // stands in an a slot); kSortCols: in column order (b slot)
+    uint32_t pad;
 };
+constexpr uint32_t kSortRows = 1u, kSortCols = 2u;
 
 struct InstDev {
     uint32_t n;        // vertices
@@ -93,6 +97,7 @@ struct PrepArgs {
 
 struct SortArgs {
     const InstDev *inst;
+    const MatDev *mats;
     const uint32_t *ap_key, *ap_i, *ap_j;
     const unsigned long long *ap_count;
     uint64_t ap_cap;

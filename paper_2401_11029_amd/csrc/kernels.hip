@@ -459,6 +459,8 @@ __device__ __forceinline__ LaneRun lane_run(uint32_t rid) {
     return r;
 }
 
+// Row ids of entry x in the row-order and column-order sorts (kHole when the
+// entry is a hole or its matrix needs that order for no production).
 __device__ __forceinline__ void entry_rows(const SortArgs &A, uint64_t x, uint64_t n, uint32_t *r, uint32_t *c,
                                            uint32_t *i, uint32_t *j) {
     *r = *c = kHole;
@@ -466,11 +468,12 @@ __device__ __forceinline__ void entry_rows(const SortArgs &A, uint64_t x, uint64
     const uint32_t key = A.ap_key[x];
     if (key == kHole) return;
     const InstDev I = A.inst[key_slot(key)];
+    const uint32_t need = A.mats[I.mat_off + key_mat(key)].sort;
     const uint32_t b = I.rowbase + key_mat(key) * I.n;
     *i = A.ap_i[x];
     *j = A.ap_j[x];
-    *r = b + *i;
-    *c = b + *j;
+    if (need & kSortRows) *r = b + *i;
+    if (need & kSortCols) *c = b + *j;
 }
 
 __global__ __launch_bounds__(256) void count_kernel(SortArgs A) {
@@ -502,10 +505,8 @@ __global__ __launch_bounds__(256) void scatter_kernel(SortArgs A) {
         if (cr.head && c != kHole) q0 = atomicSub(&A.ccnt[c], cr.len) - cr.len;
         p0 = __shfl(p0, rr.first, 64) + (lane - rr.first);
         q0 = __shfl(q0, cr.first, 64) + (lane - cr.first);
-        if (r != kHole) {
-            A.rs[p0] = ((uint64_t)i << 32) | j;
-            A.cs[q0] = ((uint64_t)j << 32) | i;
-        }
+        if (r != kHole) A.rs[p0] = ((uint64_t)i << 32) | j;
+        if (c != kHole) A.cs[q0] = ((uint64_t)j << 32) | i;
     }
 }
 
