@@ -281,7 +281,7 @@ cflr_status cflr_solve(cflr_ctx *ctx, const cflr_grammar *g, const cflr_graph *g
         {
             hip_check(hipEventRecord(e0, ctx->stream), "event");
             inst = make_instance(ctx, g->low, graph);
-            Run run(ctx, o, (uint64_t)g->low.nmat() * graph->n, 1);
+            Run run(ctx, o, instance_buckets(g->low, graph->n), 1);
             run.add(inst);
             while (run.round()) {
                 if (o.max_rounds && inst->rounds >= o.max_rounds) {
@@ -324,18 +324,20 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
         // admission by device memory: instances join as earlier ones finish
         size_t free_b = 0, total_b = 0;
         hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-        uint64_t rows = 0, max_rows = 0;
+        // sort buckets: room for every graph at once, capped (later graphs
+        // wait for earlier ones to retire)
+        uint64_t buckets = 0, max_buckets = 0;
         for (uint32_t k = 0; k < count; k++) {
-            uint64_t r = (uint64_t)grammars[k]->low.nmat() * graphs[k]->n;
-            rows += r;
-            max_rows = std::max(max_rows, r);
+            uint64_t b = instance_buckets(grammars[k]->low, graphs[k]->n);
+            buckets += b;
+            max_buckets = std::max(max_buckets, b);
         }
-        rows = std::min<uint64_t>(rows, std::max<uint64_t>(max_rows, 0x0FFFFFFFull));
+        buckets = std::min<uint64_t>(buckets, std::max<uint64_t>(max_buckets, 0x0FFFFFFFull));
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "event");
         hip_check(hipEventCreate(&e1), "event");
         hip_check(hipEventRecord(e0, ctx->stream), "event");
-        Run run(ctx, o, rows, count);
+        Run run(ctx, o, buckets, count);
         // device memory for matrices: 70 % of what is free, minus the
         // new-pair buffer (28 bytes a pair, grown on overflow) and headroom
         // for it to double once
@@ -354,14 +356,13 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
             // admit
             while (next < count) {
                 uint64_t need = fp[next];
-                uint64_t r = (uint64_t)grammars[next]->low.nmat() * graphs[next]->n;
-                if (run.size() && (in_use + need > budget || r > rows)) break;
+                if (run.size() && in_use + need > budget) break;
                 auto inst = make_instance(ctx, grammars[next]->low, graphs[next]);
                 try {
                     run.add(inst);
                 } catch (const Error &e) {
                     if (!run.size()) throw;
-                    break;  // row space full: wait for a retirement
+                    break;  // bucket space full: wait for a retirement
                 }
                 all[next] = inst;
                 in_use += need;

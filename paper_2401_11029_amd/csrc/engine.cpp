@@ -130,6 +130,10 @@ uint64_t instance_footprint(const Lowered &low, uint32_t n) {
     return bytes;
 }
 
+uint64_t instance_buckets(const Lowered &low, uint32_t n) {
+    return (uint64_t)low.nmat() * key_tiles(n) * n;
+}
+
 std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const cflr_graph *g) {
     if (low.nmat() > kMaxMats) throw Error(CFLR_EUNSUPPORTED, "grammar needs more than 65536 matrices");
     auto inst = std::make_shared<Instance>();
@@ -200,16 +204,17 @@ std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const
 
 // ---------------------------------------------------------------------- Run
 
-Run::Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t row_capacity, uint32_t max_instances)
-    : hold_(ctx), ctx_(ctx), opts_(opts), s_(ctx->stream), row_cap_(row_capacity), max_inst_(max_instances) {
-    if (row_cap_ >= 0xFFFFFFF0ull) throw Error(CFLR_EUNSUPPORTED, "too many matrix rows for one run");
+Run::Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t bucket_capacity, uint32_t max_instances)
+    : hold_(ctx), ctx_(ctx), opts_(opts), s_(ctx->stream), bucket_cap_(bucket_capacity), max_inst_(max_instances) {
+    if (bucket_cap_ >= 0xFFFFFFF0ull)
+        throw Error(CFLR_EUNSUPPORTED, "too many sort buckets for one run (matrices x key tiles x n >= 2^32)");
     if (max_inst_ == 0 || max_inst_ > kMaxSlots)
         throw Error(CFLR_EINVAL, "instances per run must be in [1, " + std::to_string(kMaxSlots) + "]");
     DevPool *pool = ctx->pool.get();
-    free_rows_[0] = row_cap_;
-    d_rcnt_ = DevBuf(pool, (row_cap_ + 1) * 4);
-    d_ccnt_ = DevBuf(pool, (row_cap_ + 1) * 4);
-    d_bsum_ = DevBuf(pool, 2ull * scan_block_count(row_cap_) * 4);
+    free_buckets_[0] = bucket_cap_;
+    d_rcnt_ = DevBuf(pool, (bucket_cap_ + 1) * 4);
+    d_ccnt_ = DevBuf(pool, (bucket_cap_ + 1) * 4);
+    d_bsum_ = DevBuf(pool, 2ull * scan_block_count(bucket_cap_) * 4);
     d_counters_ = DevBuf(pool, 64);
     d_inst_new_ = DevBuf(pool, (uint64_t)max_inst_ * kCountShards * 8);
     d_inst_over_ = DevBuf(pool, (uint64_t)max_inst_ * 4);
@@ -219,9 +224,9 @@ Run::Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t row_capacity, uint32_t m
     hip_check(hipMemsetAsync(d_counters_.ptr, 0, 64, s_), "memset");
     hip_check(hipMemsetAsync(d_inst_new_.ptr, 0, (uint64_t)max_inst_ * kCountShards * 8, s_), "memset");
     hip_check(hipMemsetAsync(d_inst_over_.ptr, 0, (uint64_t)max_inst_ * 4, s_), "memset");
-    // the row/column starts must read as "no new pairs" before the first sort
-    hip_check(launch_fill_u32(d_rcnt_.as<uint32_t>(), row_cap_ + 1, 0, s_), "fill");
-    hip_check(launch_fill_u32(d_ccnt_.as<uint32_t>(), row_cap_ + 1, 0, s_), "fill");
+    // the bucket starts must read as "no new pairs" before the first sort
+    hip_check(launch_fill_u32(d_rcnt_.as<uint32_t>(), bucket_cap_ + 1, 0, s_), "fill");
+    hip_check(launch_fill_u32(d_ccnt_.as<uint32_t>(), bucket_cap_ + 1, 0, s_), "fill");
     hip_check(hipHostMalloc((void **)&h_new_, (uint64_t)max_inst_ * 8, 0), "hipHostMalloc");
     hip_check(hipHostMalloc((void **)&h_over_, (uint64_t)max_inst_ * 4, 0), "hipHostMalloc");
     hip_check(hipHostMalloc((void **)&h_counters_, 64, 0), "hipHostMalloc");
@@ -229,11 +234,12 @@ Run::Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t row_capacity, uint32_t m
     hip_check(hipEventCreate(&ev0_), "event");
     hip_check(hipEventCreate(&ev1_), "event");
     uint64_t cap = opts_.delta_capacity ? opts_.delta_capacity : ctx->delta_capacity_hint;
-    if (!cap) cap = std::max<uint64_t>(1ull << 22, std::min<uint64_t>(16 * row_cap_, 1ull << 28));
+    if (!cap) cap = std::max<uint64_t>(1ull << 22, std::min<uint64_t>(bucket_cap_ / 8, 1ull << 28));
     ensure_capacity(cap, false);
     log_ = std::getenv("CFLR_LOG") != nullptr;
     uint32_t waves = opts_.grid_waves ? opts_.grid_waves : ctx->grid_waves_tuned;
-    grid_ = waves ? waves : ctx->num_cu * 32;
+    if (!waves) waves = ctx->num_cu * 32;
+    grid_ = std::max<uint32_t>(1, waves / kProdWaves);
 }
 
 Run::~Run() {
@@ -267,39 +273,38 @@ void Run::ensure_capacity(uint64_t pairs, bool keep) {
     ctx_->delta_capacity_hint = std::max(ctx_->delta_capacity_hint, pairs);
 }
 
-uint64_t Run::alloc_rows(uint64_t rows) {
-    for (auto it = free_rows_.begin(); it != free_rows_.end(); ++it) {
-        if (it->second >= rows) {
+uint64_t Run::alloc_buckets(uint64_t count) {
+    for (auto it = free_buckets_.begin(); it != free_buckets_.end(); ++it) {
+        if (it->second >= count) {
             uint64_t base = it->first, len = it->second;
-            free_rows_.erase(it);
-            if (len > rows) free_rows_[base + rows] = len - rows;
+            free_buckets_.erase(it);
+            if (len > count) free_buckets_[base + count] = len - count;
             return base;
         }
     }
-    throw Error(CFLR_ENOMEM, "run row space exhausted");
+    throw Error(CFLR_ENOMEM, "run sort-bucket space exhausted");
 }
 
-void Run::free_rows(uint64_t base, uint64_t rows) {
-    if (!rows) return;
-    auto it = free_rows_.insert({base, rows}).first;
+void Run::free_buckets(uint64_t base, uint64_t count) {
+    if (!count) return;
+    auto it = free_buckets_.insert({base, count}).first;
     auto nx = std::next(it);
-    if (nx != free_rows_.end() && it->first + it->second == nx->first) {
+    if (nx != free_buckets_.end() && it->first + it->second == nx->first) {
         it->second += nx->second;
-        free_rows_.erase(nx);
+        free_buckets_.erase(nx);
     }
-    if (it != free_rows_.begin()) {
+    if (it != free_buckets_.begin()) {
         auto pv = std::prev(it);
         if (pv->first + pv->second == it->first) {
             pv->second += it->second;
-            free_rows_.erase(it);
+            free_buckets_.erase(it);
         }
     }
 }
 
 void Run::add(const std::shared_ptr<Instance> &inst) {
     if (insts_.size() >= max_inst_) throw Error(CFLR_EINVAL, "run is full");
-    const uint64_t rows = (uint64_t)inst->low.nmat() * inst->n;
-    inst->rowbase = (uint32_t)alloc_rows(rows);
+    inst->bbase = (uint32_t)alloc_buckets(instance_buckets(inst->low, inst->n));
     // slot: lowest index not used by a running instance
     std::vector<uint8_t> used(max_inst_, 0);
     for (auto &o : insts_) used[o->slot] = 1;
@@ -322,7 +327,7 @@ void Run::add(const std::shared_ptr<Instance> &inst) {
               "H2D");
     SeedArgs A{};
     A.mats = dmats.as<MatDev>();
-    A.I = InstDev{inst->n, inst->S, inst->rowbase, 0};
+    A.I = InstDev{inst->n, inst->S, inst->bbase, 0};
     A.inst = slot;
     A.src = inst->graph->src.as<uint32_t>();
     A.dst = inst->graph->dst.as<uint32_t>();
@@ -356,13 +361,13 @@ void Run::add(const std::shared_ptr<Instance> &inst) {
               "fill");
 }
 
-uint64_t Run::row_hi() const {
-    // rows at or above the last free range's base are unused
-    if (!free_rows_.empty()) {
-        auto last = std::prev(free_rows_.end());
-        if (last->first + last->second == row_cap_) return last->first;
+uint64_t Run::bucket_hi() const {
+    // buckets at or above the last free range's base are unused
+    if (!free_buckets_.empty()) {
+        auto last = std::prev(free_buckets_.end());
+        if (last->first + last->second == bucket_cap_) return last->first;
     }
-    return row_cap_;
+    return bucket_cap_;
 }
 
 void Run::remove(Instance *inst) {
@@ -372,7 +377,7 @@ void Run::remove(Instance *inst) {
                 hip_check(launch_purge_slot(d_ap_key_.as<uint32_t>(), d_counters_.as<unsigned long long>(),
                                             ap_cap_, inst->slot, ctx_->num_cu * 4, s_),
                           "purge");
-            free_rows(inst->rowbase, (uint64_t)inst->low.nmat() * inst->n);
+            free_buckets(inst->bbase, instance_buckets(inst->low, inst->n));
             insts_.erase(insts_.begin() + (long)k);
             dirty_ = true;
             return;
@@ -393,7 +398,7 @@ void Run::rebuild_tables() {
     toff.assign(max_inst_, 0);
     for (auto &ip : insts_) {
         Instance &in = *ip;
-        hi[in.slot] = InstDev{in.n, in.S, in.rowbase, (uint32_t)hm.size()};
+        hi[in.slot] = InstDev{in.n, in.S, in.bbase, (uint32_t)hm.size()};
         for (auto &m : in.mats) hm.push_back(m);
         for (auto &b : in.low.binary) {
             he.push_back(EntryDev{in.slot, b.c, b.a, b.b, 0});
@@ -403,6 +408,16 @@ void Run::rebuild_tables() {
         tbits += (uint64_t)in.low.nmat() * 2 * in.n * in.S;
     }
     nent_ = (uint32_t)he.size();
+    // units: (entry, key tile)
+    std::vector<uint32_t> hue, hut;
+    for (uint32_t e = 0; e < nent_; e++) {
+        const uint32_t nt = key_tiles(hi[he[e].inst].n);
+        for (uint32_t t = 0; t < nt; t++) {
+            hue.push_back(e);
+            hut.push_back(t);
+        }
+    }
+    nunit_ = (uint32_t)hue.size();
     std::vector<uint32_t> active(max_inst_, 0);
     for (auto &ip : insts_) active[ip->slot] = 1;
     copy_sync(d_active_.ptr, active.data(), active.size() * 4, hipMemcpyHostToDevice, s_);
@@ -410,9 +425,15 @@ void Run::rebuild_tables() {
     d_inst_ = DevBuf(pool, hi.size() * sizeof(InstDev));
     d_mats_ = DevBuf(pool, std::max<size_t>(1, hm.size()) * sizeof(MatDev));
     d_ent_ = DevBuf(pool, std::max<size_t>(1, he.size()) * sizeof(EntryDev));
-    d_ent_start_ = DevBuf(pool, std::max<size_t>(1, he.size()) * 4);
-    d_ent_cnt_ = DevBuf(pool, std::max<size_t>(1, he.size()) * 4);
-    d_prefix_ = DevBuf(pool, (he.size() + 1) * 8);
+    d_unit_ent_ = DevBuf(pool, std::max<size_t>(1, hue.size()) * 4);
+    d_unit_tile_ = DevBuf(pool, std::max<size_t>(1, hue.size()) * 4);
+    d_unit_start_ = DevBuf(pool, std::max<size_t>(1, hue.size()) * 4);
+    d_unit_cnt_ = DevBuf(pool, std::max<size_t>(1, hue.size()) * 4);
+    d_prefix_ = DevBuf(pool, (hue.size() + 1) * 8);
+    if (!hue.empty()) {
+        copy_sync(d_unit_ent_.ptr, hue.data(), hue.size() * 4, hipMemcpyHostToDevice, s_);
+        copy_sync(d_unit_tile_.ptr, hut.data(), hut.size() * 4, hipMemcpyHostToDevice, s_);
+    }
     copy_sync(d_inst_.ptr, hi.data(), hi.size() * sizeof(InstDev), hipMemcpyHostToDevice, s_);
     if (!hm.empty())
         copy_sync(d_mats_.ptr, hm.data(), hm.size() * sizeof(MatDev), hipMemcpyHostToDevice, s_);
@@ -441,7 +462,7 @@ void Run::sort_appended() {
     S.rs = d_rs_.as<uint64_t>();
     S.cs = d_cs_.as<uint64_t>();
     S.halt = reinterpret_cast<uint32_t *>(d_counters_.as<unsigned long long>() + 3);
-    hip_check(launch_sort(S, row_hi(), d_bsum_.as<uint32_t>(), ctx_->num_cu * 8, s_), "sort");
+    hip_check(launch_sort(S, bucket_hi(), d_bsum_.as<uint32_t>(), ctx_->num_cu * 8, s_), "sort");
     // the appended pairs are consumed
     hip_check(launch_reset_appends(d_counters_.as<unsigned long long>(), S.halt, s_), "reset");
 }
@@ -477,7 +498,7 @@ void Run::extract_all_pairs() {
     for (auto &ip : insts_) {
         DevBuf dm(ctx_->pool.get(), ip->mats.size() * sizeof(MatDev));
         copy_sync(dm.ptr, ip->mats.data(), ip->mats.size() * sizeof(MatDev), hipMemcpyHostToDevice, s_);
-        InstDev I{ip->n, ip->S, ip->rowbase, 0};
+        InstDev I{ip->n, ip->S, ip->bbase, 0};
         hip_check(launch_extract_all(dm.as<MatDev>(), I, ip->slot, ip->low.nmat(), d_ap_key_.as<uint32_t>(),
                                      d_ap_i_.as<uint32_t>(), d_ap_j_.as<uint32_t>(),
                                      d_counters_.as<unsigned long long>(), ap_cap_,
@@ -490,15 +511,17 @@ void Run::extract_all_pairs() {
 void Run::enqueue_product(bool timed) {
     unsigned long long *counters = d_counters_.as<unsigned long long>();
     uint32_t *halt = reinterpret_cast<uint32_t *>(counters + 3);
-    if (!nent_) return;
+    if (!nunit_) return;
     PrepArgs P{};
     P.inst = d_inst_.as<InstDev>();
     P.ent = d_ent_.as<EntryDev>();
-    P.nent = nent_;
+    P.unit_ent = d_unit_ent_.as<uint32_t>();
+    P.unit_tile = d_unit_tile_.as<uint32_t>();
+    P.nunit = nunit_;
     P.rptr = d_rcnt_.as<uint32_t>();
     P.cptr = d_ccnt_.as<uint32_t>();
-    P.ent_start = d_ent_start_.as<uint32_t>();
-    P.ent_cnt = d_ent_cnt_.as<uint32_t>();
+    P.unit_start = d_unit_start_.as<uint32_t>();
+    P.unit_cnt = d_unit_cnt_.as<uint32_t>();
     P.item_prefix = d_prefix_.as<uint64_t>();
     P.work_counter = counters + 1;
     P.halt = halt;
@@ -509,10 +532,12 @@ void Run::enqueue_product(bool timed) {
     A.inst = d_inst_.as<InstDev>();
     A.mats = d_mats_.as<MatDev>();
     A.ent = d_ent_.as<EntryDev>();
-    A.ent_start = d_ent_start_.as<uint32_t>();
-    A.ent_cnt = d_ent_cnt_.as<uint32_t>();
+    A.unit_ent = d_unit_ent_.as<uint32_t>();
+    A.unit_tile = d_unit_tile_.as<uint32_t>();
+    A.unit_start = d_unit_start_.as<uint32_t>();
+    A.unit_cnt = d_unit_cnt_.as<uint32_t>();
     A.item_prefix = d_prefix_.as<uint64_t>();
-    A.nent = nent_;
+    A.nunit = nunit_;
     A.rs = d_rs_.as<uint64_t>();
     A.cs = d_cs_.as<uint64_t>();
     A.ap_key = d_ap_key_.as<uint32_t>();
@@ -594,7 +619,7 @@ uint32_t Run::rounds(uint32_t R) {
             if (!opts_.semi_naive) extract_all_pairs();
             enqueue_round(opts_.kernel_timing != 0);
             read_flags();
-            if (opts_.kernel_timing && nent_) {
+            if (opts_.kernel_timing && nunit_) {
                 float ms = 0;
                 hip_check(hipEventElapsedTime(&ms, ev0_, ev1_), "event");
                 product_ms_ += ms;
@@ -619,7 +644,7 @@ uint32_t Run::rounds(uint32_t R) {
             product_launches_ -= R;  // counted below, per replay
         }
         hip_check(hipGraphLaunch(graph_exec_, s_), "graph launch");
-        product_launches_ += nent_ ? R : 0;
+        product_launches_ += nunit_ ? R : 0;
         read_flags();
         if ((uint32_t)(h_counters_[3] & 0xFFFFFFFFu)) recover();
         if (log_) log_round();
@@ -641,7 +666,7 @@ uint32_t Run::rounds(uint32_t R) {
 
 void Run::log_round() {
     uint64_t items = 0;
-    if (nent_) copy_sync(&items, d_prefix_.as<uint64_t>() + nent_, 8, hipMemcpyDeviceToHost, s_);
+    if (nunit_) copy_sync(&items, d_prefix_.as<uint64_t>() + nunit_, 8, hipMemcpyDeviceToHost, s_);
     uint64_t fresh = 0;
     for (auto &ip : insts_) fresh += h_stats_[ip->slot].new_total;
     std::fprintf(stderr, "[cflr] round %u: instances %zu items %llu appended %llu derived-so-far %llu cap %llu reruns %u\n",

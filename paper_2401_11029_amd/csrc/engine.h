@@ -138,7 +138,7 @@ struct Instance {
     uint64_t max_seeds = 0;
     const cflr_graph *graph = nullptr;
     // state
-    uint32_t rowbase = 0;
+    uint32_t bbase = 0;  // first sort bucket
     uint32_t slot = 0;
     uint32_t rounds = 0;
     bool done = false;
@@ -151,6 +151,8 @@ struct Instance {
 
 // Device bytes an instance of this grammar on n vertices will hold.
 uint64_t instance_footprint(const Lowered &low, uint32_t n);
+// Sort buckets of such an instance: per matrix, key tiles x n partners.
+uint64_t instance_buckets(const Lowered &low, uint32_t n);
 
 std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const cflr_graph *g);
 
@@ -158,10 +160,12 @@ std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const
 // launch per round over all of them).
 class Run {
    public:
-    Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t row_capacity, uint32_t max_instances);
+    // bucket_capacity: sort buckets for all instances admitted at once
+    // (instance_buckets of each); below 2^32.
+    Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t bucket_capacity, uint32_t max_instances);
     ~Run();
-    // Admit an instance: assigns its rows, seeds its pairs (they become the
-    // next round's new pairs).  Between rounds only.
+    // Admit an instance: assigns its sort buckets, seeds its pairs (they
+    // become the next round's new pairs).  Between rounds only.
     void add(const std::shared_ptr<Instance> &inst);
     // Drop an instance (finished); between rounds only.
     void remove(Instance *inst);
@@ -184,10 +188,10 @@ class Run {
     void rebuild_tables();
     void ensure_capacity(uint64_t pairs, bool keep);
     void sort_appended();
-    uint64_t alloc_rows(uint64_t rows);
-    void free_rows(uint64_t base, uint64_t rows);
+    uint64_t alloc_buckets(uint64_t count);
+    void free_buckets(uint64_t base, uint64_t count);
     void read_flags();
-    uint64_t row_hi() const;
+    uint64_t bucket_hi() const;
     void extract_all_pairs();
     void enqueue_product(bool timed);
     void enqueue_settle();
@@ -200,12 +204,13 @@ class Run {
     hipStream_t s_;
     std::vector<std::shared_ptr<Instance>> insts_;
     bool dirty_ = true;
-    uint64_t row_cap_;
+    uint64_t bucket_cap_;
     uint32_t max_inst_;
-    std::map<uint64_t, uint64_t> free_rows_;  // base -> length
+    std::map<uint64_t, uint64_t> free_buckets_;  // base -> length
     // device tables
-    DevBuf d_inst_, d_mats_, d_ent_, d_ent_start_, d_ent_cnt_, d_prefix_;
-    uint32_t nent_ = 0;
+    DevBuf d_inst_, d_mats_, d_ent_, d_prefix_;
+    DevBuf d_unit_ent_, d_unit_tile_, d_unit_start_, d_unit_cnt_;
+    uint32_t nent_ = 0, nunit_ = 0;
     DevBuf d_rcnt_, d_ccnt_, d_bsum_;
     DevBuf d_ap_key_, d_ap_i_, d_ap_j_, d_rs_, d_cs_;
     uint64_t ap_cap_ = 0;

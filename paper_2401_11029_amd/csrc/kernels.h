@@ -18,8 +18,22 @@ namespace cflr {
 
 constexpr uint32_t kWave = 64;        // lanes per wavefront (CDNA)
 constexpr uint32_t kSegWords = 64;    // words per row segment
-constexpr uint32_t kPairsPerItem = 64;  // new pairs per product work item
 constexpr uint32_t kCountShards = 64;   // counters per instance for new pairs
+
+// Product tiling.  The new pairs of an operand are sorted by (key tile,
+// partner), the key being the row i of a pair (i, k) of dA or the column j
+// of a pair (k, j) of dB, and the partner the other index k.  One work item
+// is (production part, tile of kTileKeys keys, row segment, at most
+// kChunkPairs pairs): a workgroup of kProdWaves waves holds the accumulators
+// of the tile's keys in registers (kKeysPerWave per wave) and stages up to
+// kStageRuns distinct partner segments at a time in LDS, so that a partner
+// segment is read from memory once per tile instead of once per pair.
+constexpr uint32_t kTileKeys = 256;
+constexpr uint32_t kProdWaves = 16;
+constexpr uint32_t kKeysPerWave = kTileKeys / kProdWaves;
+constexpr uint32_t kStageRuns = 64;
+constexpr uint32_t kChunkPairs = 32768;
+__host__ __device__ inline uint32_t key_tiles(uint32_t n) { return (n + kTileKeys - 1) / kTileKeys; }
 
 // Key of an appended pair: bits 0..15 matrix, bits 16..29 instance slot,
 // bit 30 "settled" (both layouts already hold the pair: seeds, restarts),
@@ -48,7 +62,8 @@ constexpr uint32_t kSortRows = 1u, kSortCols = 2u;
 struct InstDev {
     uint32_t n;        // vertices
     uint32_t S;        // segments per row; Wp = 64 * S
-    uint32_t rowbase;  // first row of this instance in the new-pair row space
+    uint32_t bbase;    // first sort bucket of this instance: matrix x, key
+                       // tile t, partner k is bucket bbase + (x * key_tiles(n) + t) * n + k
     uint32_t mat_off;  // first MatDev of this instance
 };
 
@@ -66,12 +81,14 @@ struct ProductArgs {
     const InstDev *inst;
     const MatDev *mats;
     const EntryDev *ent;
-    const uint32_t *ent_start;    // first new pair of the entry's operand
-    const uint32_t *ent_cnt;      // number of new pairs of the operand
-    const uint64_t *item_prefix;  // exclusive prefix of items per entry; [nent] = total
-    uint32_t nent;
-    const uint64_t *rs;           // new pairs (i, k) in row order, packed (i << 32) | k
-    const uint64_t *cs;           // new pairs (k, j) in column order, packed (j << 32) | k
+    // units: (entry, key tile); their pairs and items are set by the prep
+    const uint32_t *unit_ent, *unit_tile;
+    const uint32_t *unit_start;   // first new pair of the unit
+    const uint32_t *unit_cnt;     // number of new pairs of the unit
+    const uint64_t *item_prefix;  // exclusive prefix of items per unit; [nunit] = total
+    uint32_t nunit;
+    const uint64_t *rs;           // new pairs (i, k) in (i tile, k) order, packed (i << 32) | k
+    const uint64_t *cs;           // new pairs (k, j) in (j tile, k) order, packed (j << 32) | k
     uint32_t *ap_key, *ap_i, *ap_j;   // appended new pairs: (key, i, j)
     unsigned long long *ap_count;
     uint64_t ap_cap;
@@ -87,9 +104,10 @@ struct ProductArgs {
 struct PrepArgs {
     const InstDev *inst;
     const EntryDev *ent;
-    uint32_t nent;
-    const uint32_t *rptr, *cptr;  // row / column starts of the new pairs
-    uint32_t *ent_start, *ent_cnt;
+    const uint32_t *unit_ent, *unit_tile;
+    uint32_t nunit;
+    const uint32_t *rptr, *cptr;  // bucket starts of the two sort orders
+    uint32_t *unit_start, *unit_cnt;
     uint64_t *item_prefix;
     unsigned long long *work_counter;
     const uint32_t *halt;
@@ -101,7 +119,7 @@ struct SortArgs {
     const uint32_t *ap_key, *ap_i, *ap_j;
     const unsigned long long *ap_count;
     uint64_t ap_cap;
-    uint32_t *rcnt, *ccnt;       // counts -> inclusive scan -> starts (after scatter)
+    uint32_t *rcnt, *ccnt;       // per bucket: counts -> inclusive scan -> starts (after scatter)
     uint64_t *rs, *cs;
     const uint32_t *halt;
 };
@@ -149,14 +167,15 @@ struct SlotStats {
 
 // ------------------------------------------------------------------ launchers
 
+// grid: workgroups of kProdWaves waves
 hipError_t launch_product(const ProductArgs &A, uint32_t grid, bool stats, hipStream_t s);
 hipError_t launch_prep(const PrepArgs &A, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *a, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long v, hipStream_t s);
-// counting sort of the appended pairs over rows [0, nrows] (nrows + 1 counters)
-hipError_t launch_sort(const SortArgs &A, uint64_t nrows, uint32_t *bsum, uint32_t sort_grid,
+// counting sort of the appended pairs over buckets [0, nbuckets] (nbuckets + 1 counters)
+hipError_t launch_sort(const SortArgs &A, uint64_t nbuckets, uint32_t *bsum, uint32_t sort_grid,
                        hipStream_t s);
-uint32_t scan_block_count(uint64_t nrows);
+uint32_t scan_block_count(uint64_t nbuckets);
 hipError_t launch_settle(const SettleArgs &A, uint32_t grid, hipStream_t s);
 hipError_t launch_round_end(const uint32_t *active, unsigned long long *inst_new, SlotStats *st, uint32_t nslots,
                             const uint32_t *halt, hipStream_t s);

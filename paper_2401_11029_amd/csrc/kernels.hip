@@ -213,115 +213,273 @@ __device__ __forceinline__ void flush(const ProductArgs &A, SlotChunk &ch, uint3
     }
 }
 
-// Process one block of up to 64 new pairs against one row segment.
-// COL = false: pairs (i, k) of dA, partner rows k of B (row-major).
-// COL = true:  pairs (j, k) of dB, partner rows k of A's column-major copy.
+// LDS of the product workgroup.  Stages are double-buffered: while the
+// accumulators take in stage s, stage s + 1 is planned and its partner
+// segments are on their way from memory.
+struct ProductShared {
+    uint64_t stage[2][kStageRuns][kSegWords];  // partner segments of two stages
+    unsigned long long mask[2][kTileKeys];     // per key: runs of the stage it pairs with
+    uint32_t run_k[kStageRuns];                // partner of each run of the stage being planned
+    uint32_t wave_heads[kProdWaves];           // runs starting among each wave's pairs
+    unsigned long long nzr[2];                 // runs whose partner segment is non-zero
+    uint32_t stage_len;                        // pairs taken by the stage being planned (when cut)
+    unsigned long long item;                   // the workgroup's current item
+};
+
+struct StagePlan {
+    uint32_t len;  // pairs of the stage
+    uint32_t nst;  // runs (distinct partners) of the stage, <= kStageRuns
+};
+
+// Pair x of the sorted order (one per thread) and, for lane 0 of a wave,
+// the pair before it (its partner decides whether x starts a run).
+struct PairFetch {
+    uint64_t pk = 0, prev = 0;
+};
+
+__device__ __forceinline__ PairFetch fetch_pairs(const uint64_t *pairs, uint32_t pos, uint32_t p1) {
+    PairFetch f;
+    const uint32_t x = pos + threadIdx.x;
+    if (x < p1) {
+        f.pk = pairs[x];
+        if (lane_id() == 0 && threadIdx.x != 0) f.prev = pairs[x - 1];
+    }
+    return f;
+}
+
+// Plan the stage starting at `pos`: runs of equal partners among the fetched
+// pairs, cut after kStageRuns runs; each key's mask gets a bit per run it
+// pairs with, and run_k the partner of each run.  Two barriers.
+template <bool STATS>
+__device__ __forceinline__ StagePlan plan_stage(ProductShared &sh, SlotChunk &ch, const PairFetch &f,
+                                                uint32_t pos, uint32_t p1, uint32_t key0, uint32_t buf,
+                                                bool count_pairs) {
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const bool valid = pos + tid < p1;
+    const uint32_t key = (uint32_t)(f.pk >> 32);
+    const uint32_t k = valid ? (uint32_t)f.pk : kHole;
+    uint32_t kprev = __shfl_up(k, 1, 64);
+    if (lane == 0) kprev = (tid == 0 || !valid) ? kHole : (uint32_t)f.prev;
+    const bool head = valid && (tid == 0 || k != kprev);
+    const uint64_t hb = __ballot(head);
+    if (lane == 0) sh.wave_heads[wave] = (uint32_t)__popcll(hb);
+    __syncthreads();  // (1) heads counted
+    if (tid == 0) sh.nzr[buf] = 0;
+    uint32_t before = 0, runs = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kProdWaves; w++) {
+        const uint32_t h = sh.wave_heads[w];
+        before += w < wave ? h : 0;
+        runs += h;
+    }
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    const uint32_t run = before + (uint32_t)__popcll(hb & upto) - 1;
+    const bool in_stage = valid && run < kStageRuns;
+    if (runs > kStageRuns && head && run == kStageRuns) sh.stage_len = tid;
+    if (in_stage) {
+        const uint32_t kl = key - key0;
+        if (kl < kTileKeys) atomicOr(&sh.mask[buf][kl], 1ull << run);
+        if (head) sh.run_k[run] = k;
+    }
+    if (STATS && count_pairs) {
+        // the pair itself, read once per production
+        const uint64_t taken = __ballot(in_stage);
+        if (lane == 0) ch.bytes += 8ull * __popcll(taken);
+    }
+    __syncthreads();  // (2) masks, partners and the cut set
+    StagePlan p;
+    const uint32_t nvalid = p1 - pos < kProdWaves * kWave ? p1 - pos : kProdWaves * kWave;
+    p.len = runs > kStageRuns ? sh.stage_len : nvalid;
+    p.nst = runs < kStageRuns ? runs : kStageRuns;
+    return p;
+}
+
+constexpr uint32_t kRunsPerWave = kStageRuns / kProdWaves;
+
+// Partner segments of the planned stage: wave w takes runs w, w + 16, ...
+// A segment that turns out to be all zero is not staged.
+struct PartnerFetch {
+    uint64_t v[kRunsPerWave];
+    uint32_t kk[kRunsPerWave];
+};
+
+__device__ __forceinline__ void fetch_partners(PartnerFetch &pf, const ProductShared &sh, uint32_t nst,
+                                               global_u64 G, uint64_t Wp, uint32_t seg) {
+    const uint32_t wave = threadIdx.x / kWave, lane = lane_id();
+#pragma unroll
+    for (uint32_t q = 0; q < kRunsPerWave; q++) {
+        const uint32_t r = wave + kProdWaves * q;
+        pf.v[q] = 0;
+        pf.kk[q] = 0;
+        if (r < nst) {
+            const uint32_t kk = __builtin_amdgcn_readfirstlane(sh.run_k[r]);
+            pf.kk[q] = kk;
+            pf.v[q] = G[(uint64_t)kk * Wp + seg * kSegWords + lane];
+        }
+    }
+}
+
 template <bool COL, bool STATS>
-__device__ __forceinline__ void process_block(const ProductArgs &A, SlotChunk &ch, uint32_t inst,
-                                              const InstDev &I,
-                                              const EntryDev &E, uint32_t start, uint32_t cnt,
-                                              uint32_t seg, bool count_pairs) {
-    const uint32_t lane = lane_id();
+__device__ __forceinline__ void store_partners(const ProductArgs &A, ProductShared &sh, SlotChunk &ch,
+                                               const PartnerFetch &pf, uint32_t buf, uint32_t inst,
+                                               uint32_t pm, uint32_t seg, const InstDev &I) {
+    const uint32_t wave = threadIdx.x / kWave, lane = lane_id();
+    unsigned long long bits = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kRunsPerWave; q++) {
+        const uint64_t live = __ballot(pf.v[q] != 0);
+        if (live) {
+            const uint32_t r = wave + kProdWaves * q;
+            sh.stage[buf][r][lane] = pf.v[q];
+            bits |= 1ull << r;
+            // compulsory bytes: the segment's non-zero words, at its first touch in the round
+            if (STATS && lane == 0 && first_touch<STATS>(A, inst, pm, COL ? 1 : 0, pf.kk[q], seg, I))
+                ch.bytes += 8ull * __popcll(live);
+        }
+    }
+    if (bits && lane == 0) atomicOr(&sh.nzr[buf], bits);
+}
+
+// acc[q] |= every staged segment key q of this wave pairs with.  The wave's
+// kKeysPerWave masks are read by as many lanes at once, and cleared by them
+// for the stage after next.
+__device__ __forceinline__ void accumulate(ProductShared &sh, uint32_t buf, uint64_t (&acc)[kKeysPerWave]) {
+    const uint32_t wave = threadIdx.x / kWave, lane = lane_id();
+    const unsigned long long nz = sh.nzr[buf];
+    unsigned long long mine = 0;
+    if (lane < kKeysPerWave) {
+        mine = sh.mask[buf][wave * kKeysPerWave + lane];
+        if (mine) sh.mask[buf][wave * kKeysPerWave + lane] = 0;
+    }
+    mine &= nz;
+    const uint64_t(*st)[kSegWords] = sh.stage[buf];
+#pragma unroll
+    for (uint32_t q = 0; q < kKeysPerWave; q++) {
+        unsigned long long m = rdlane64(mine, q);
+        uint64_t a = acc[q];
+        while (m) {
+            const uint32_t c = (uint32_t)__popcll(m);
+            const uint32_t i0 = (uint32_t)__ffsll(m) - 1;
+            m &= m - 1;
+            if (c >= 4) {
+                const uint32_t i1 = (uint32_t)__ffsll(m) - 1;
+                m &= m - 1;
+                const uint32_t i2 = (uint32_t)__ffsll(m) - 1;
+                m &= m - 1;
+                const uint32_t i3 = (uint32_t)__ffsll(m) - 1;
+                m &= m - 1;
+                a |= (st[i0][lane] | st[i1][lane]) | (st[i2][lane] | st[i3][lane]);
+            } else if (c >= 2) {
+                const uint32_t i1 = (uint32_t)__ffsll(m) - 1;
+                m &= m - 1;
+                a |= st[i0][lane] | st[i1][lane];
+            } else {
+                a |= st[i0][lane];
+            }
+        }
+        acc[q] = a;
+    }
+}
+
+// One work item: pairs [p0, p1) of one key tile, sorted by partner, against
+// row segment `seg`.  COL = false: pairs (i, k) of dA, partner rows k of B
+// (row-major); COL = true: pairs (j, k) of dB, partner rows k of A's
+// column-major copy.  A stage is the next pairs, one per thread, up to the
+// first pair of the (kStageRuns + 1)-th distinct partner.  Stage s + 1 is
+// planned and its partner segments fetched before stage s is accumulated,
+// and the pairs of stage s + 2 are fetched too, so the accumulation hides
+// the memory latency.  Every loop bound is uniform over the workgroup, so
+// all waves meet at every barrier.
+template <bool COL, bool STATS>
+__device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared &sh, SlotChunk &ch,
+                                             const EntryDev &E, const InstDev &I, uint32_t tile,
+                                             uint32_t p0, uint32_t p1, uint32_t seg) {
+    const uint32_t wave = threadIdx.x / kWave;
     const uint64_t Wp = (uint64_t)I.S * kSegWords;
-    const MatDev Mc = A.mats[I.mat_off + E.c];
-    const MatDev Mp = A.mats[I.mat_off + (COL ? E.a : E.b)];
-    const uint64_t *P = COL ? Mp.C : Mp.R;
-    const uint64_t *PS = COL ? Mp.CS : Mp.RS;
+    const uint32_t pm = COL ? E.a : E.b;
+    const MatDev Mp = A.mats[I.mat_off + pm];
+    const global_u64 G = (global_u64)(COL ? Mp.C : Mp.R);
     const uint64_t *pairs = COL ? A.cs : A.rs;
-    uint32_t my_key = kHole, my_k = 0, my_off = 0;
-    uint64_t my_sm = 0;
-    if (lane < cnt) {
-        const uint64_t pk = pairs[start + lane];
-        my_key = (uint32_t)(pk >> 32);
-        my_k = (uint32_t)pk;
-        my_sm = PS[(uint64_t)my_k * I.S + seg];
-        my_off = my_k * (uint32_t)Wp + seg * kSegWords;  // < 2^32: checked on the host
-    }
-    if (STATS) {
-        // compulsory partner bytes: non-zero words of each partner segment,
-        // counted at its first touch in the round
-        uint32_t bytes = 0;
-        if (lane < cnt && my_sm &&
-            first_touch<STATS>(A, inst, COL ? E.a : E.b, COL ? 1 : 0, my_k, seg, I))
-            bytes = 8u * (uint32_t)__popcll(my_sm);
-        if (count_pairs && lane < cnt) bytes += 8;  // the pair itself, once per production
-        uint32_t tot = wave_sum(bytes);
-        if (tot && lane == 0) ch.bytes += tot;
-    }
-    // keep only the pairs whose partner segment has a non-zero word, in
-    // order (keys stay sorted): lane p takes the p-th such pair
-    const uint64_t nz = __ballot(my_sm != 0);
-    const uint32_t ncnt = (uint32_t)__popcll(nz);
-    if (!ncnt) return;
-    uint32_t src = 0;
+    const uint32_t key0 = tile * kTileKeys;
+    const bool count_pairs = STATS && seg == 0;
+    uint64_t acc[kKeysPerWave];
 #pragma unroll
-    for (int b = 32; b; b >>= 1) {  // smallest src with popcount(nz & bits <= src) > lane
-        const uint32_t probe = src + b - 1;
-        const uint64_t below = probe >= 63 ? nz : nz & ((2ull << probe) - 1);
-        if ((uint32_t)__popcll(below) <= lane) src += b;
-    }
-    // every lane must take part in the cross-lane reads (a lane only
-    // receives data from source lanes that execute the read)
-    const uint32_t key_src = __shfl(my_key, src & 63, 64);
-    const uint32_t c_off = __shfl(my_off, src & 63, 64);
-    const uint32_t c_key = lane < ncnt ? key_src : kHole;
-    const global_u64 G = (global_u64)P;
-    uint32_t t = 0;
-    while (t < ncnt) {
-        const uint32_t cur = rdlane(c_key, t);
-        // pairs are sorted by key, so equal keys occupy lanes t .. end-1
-        const uint64_t same = __ballot(c_key == cur);
-        const uint32_t end = 64 - __clzll((unsigned long long)same);
-        uint64_t acc = 0;
-        uint32_t u = t;
-        // sixteen independent partner loads in flight per batch
-        for (; u + 16 <= end; u += 16) {
-            uint64_t v[16];
-#pragma unroll
-            for (int q = 0; q < 16; q++) v[q] = G[(uint64_t)rdlane(c_off, u + q) + lane];
-#pragma unroll
-            for (int q = 0; q < 16; q++) acc |= v[q];
+    for (uint32_t q = 0; q < kKeysPerWave; q++) acc[q] = 0;
+    PartnerFetch pf;
+    // prologue: stage 0 planned and staged, the pairs of stage 1 on the way
+    PairFetch f = fetch_pairs(pairs, p0, p1);
+    StagePlan cur = plan_stage<STATS>(sh, ch, f, p0, p1, key0, 0, count_pairs);
+    fetch_partners(pf, sh, cur.nst, G, Wp, seg);
+    store_partners<COL, STATS>(A, sh, ch, pf, 0, E.inst, pm, seg, I);
+    uint32_t next = p0 + cur.len;
+    if (next < p1) f = fetch_pairs(pairs, next, p1);
+    __syncthreads();  // stage 0 staged
+    uint32_t b = 0;
+    while (true) {
+        const bool more = next < p1;
+        StagePlan nx{0, 0};
+        if (more) {
+            nx = plan_stage<STATS>(sh, ch, f, next, p1, key0, b ^ 1, count_pairs);
+            fetch_partners(pf, sh, nx.nst, G, Wp, seg);
+            if (next + nx.len < p1) f = fetch_pairs(pairs, next + nx.len, p1);
         }
-        for (; u + 4 <= end; u += 4) {
-            uint64_t v[4];
+        accumulate(sh, b, acc);
+        if (!more) break;
+        store_partners<COL, STATS>(A, sh, ch, pf, b ^ 1, E.inst, pm, seg, I);
+        __syncthreads();  // (3) stage s + 1 staged; stage s consumed
+        b ^= 1;
+        next += nx.len;
+    }
+    // flush the tile's keys; one flush body, the accumulators rotate through acc[0]
+    const MatDev Mc = A.mats[I.mat_off + E.c];
+#pragma nounroll
+    for (uint32_t q = 0; q < kKeysPerWave; q++) {
+        const uint64_t a = acc[0];
 #pragma unroll
-            for (int q = 0; q < 4; q++) v[q] = G[(uint64_t)rdlane(c_off, u + q) + lane];
-            acc |= (v[0] | v[1]) | (v[2] | v[3]);
-        }
-        for (; u < end; u++) acc |= G[(uint64_t)rdlane(c_off, u) + lane];
-        flush<COL, STATS>(A, ch, inst, I, Mc, E.c, cur, seg, acc, Wp);
-        t = end;
+        for (uint32_t r = 0; r + 1 < kKeysPerWave; r++) acc[r] = acc[r + 1];
+        acc[kKeysPerWave - 1] = 0;
+        if (__ballot(a != 0))
+            flush<COL, STATS>(A, ch, E.inst, I, Mc, E.c, key0 + wave * kKeysPerWave + q, seg, a, Wp);
     }
 }
 
 template <bool STATS>
-__global__ __launch_bounds__(64) void product_kernel(ProductArgs A) {
-    const uint64_t total = A.item_prefix[A.nent];
+__global__ __launch_bounds__(kProdWaves * kWave) void product_kernel(ProductArgs A) {
+    __shared__ ProductShared sh;
+    const uint32_t tid = threadIdx.x;
+    const uint64_t total = A.item_prefix[A.nunit];
     SlotChunk ch;
-    // items are handed out statically (item = block + t * grid): every item
-    // is one block of at most 64 pairs on one row segment, so they cost about
-    // the same, and no device-wide counter is contended
-    for (uint64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    if (tid < kTileKeys) sh.mask[0][tid] = sh.mask[1][tid] = 0;
+    while (true) {
+        // items are taken from a counter, one atomic per workgroup and item;
         // after an overflow the round is re-run: stop early
-        if (__hip_atomic_load(A.halt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-        uint32_t lo = 0, hi = A.nent;  // item_prefix[lo] <= item < item_prefix[hi]
+        if (tid == 0) {
+            unsigned long long it = atomicAdd(A.work_counter, 1ull);
+            if (__hip_atomic_load(A.halt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) it = total;
+            sh.item = it;
+        }
+        __syncthreads();
+        const uint64_t item = sh.item;
+        __syncthreads();  // every thread has read the item before thread 0 takes the next
+        if (item >= total) break;
+        uint32_t lo = 0, hi = A.nunit;  // item_prefix[lo] <= item < item_prefix[hi]
         while (hi - lo > 1) {
-            uint32_t mid = (lo + hi) >> 1;
+            const uint32_t mid = (lo + hi) >> 1;
             if (A.item_prefix[mid] <= item) lo = mid;
             else hi = mid;
         }
-        const EntryDev E = A.ent[lo];
+        const EntryDev E = A.ent[A.unit_ent[lo]];
         const InstDev I = A.inst[E.inst];
         const uint64_t local = item - A.item_prefix[lo];
         const uint32_t seg = (uint32_t)(local % I.S);
-        const uint32_t blk = (uint32_t)(local / I.S);
-        const uint32_t start = A.ent_start[lo] + blk * kPairsPerItem;
-        const uint32_t left = A.ent_cnt[lo] - blk * kPairsPerItem;
-        const uint32_t cnt = left < kPairsPerItem ? left : kPairsPerItem;
+        const uint64_t chunk = local / I.S;
+        const uint64_t start = A.unit_start[lo], end = start + A.unit_cnt[lo];
+        const uint64_t c0 = start + chunk * kChunkPairs;
+        const uint64_t c1 = c0 + kChunkPairs < end ? c0 + kChunkPairs : end;
         if (E.part == 0)
-            process_block<false, STATS>(A, ch, E.inst, I, E, start, cnt, seg, seg == 0);
+            product_tile<false, STATS>(A, sh, ch, E, I, A.unit_tile[lo], (uint32_t)c0, (uint32_t)c1, seg);
         else
-            process_block<true, STATS>(A, ch, E.inst, I, E, start, cnt, seg, seg == 0);
+            product_tile<true, STATS>(A, sh, ch, E, I, A.unit_tile[lo], (uint32_t)c0, (uint32_t)c1, seg);
     }
     retire_chunk(A, ch);
     if (STATS && lane_id() == 0 && ch.bytes) atomicAdd(A.algo_bytes, (unsigned long long)ch.bytes);
@@ -330,7 +488,8 @@ __global__ __launch_bounds__(64) void product_kernel(ProductArgs A) {
 // ------------------------------------------------------------- work table
 
 
-// One workgroup of 1024 threads: items of every entry and their prefix sum.
+// One workgroup of 1024 threads: pairs and items of every unit (entry, key
+// tile) and the prefix sum of the items.
 __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs A) {
     __shared__ uint64_t part[1024];
     __shared__ uint64_t carry;
@@ -340,19 +499,19 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs A) {
         *A.work_counter = 0;
     }
     __syncthreads();
-    for (uint32_t base = 0; base < A.nent; base += 1024) {
-        uint32_t e = base + t;
+    for (uint32_t base = 0; base < A.nunit; base += 1024) {
+        const uint32_t u = base + t;
         uint64_t items = 0;
-        if (e < A.nent && !*A.halt) {
-            const EntryDev E = A.ent[e];
+        if (u < A.nunit && !*A.halt) {
+            const EntryDev E = A.ent[A.unit_ent[u]];
             const InstDev I = A.inst[E.inst];
             const uint32_t mat = E.part == 0 ? E.a : E.b;
             const uint32_t *ptr = E.part == 0 ? A.rptr : A.cptr;
-            const uint32_t r0 = I.rowbase + mat * I.n;
-            const uint32_t s = ptr[r0], f = ptr[r0 + I.n];
-            A.ent_start[e] = s;
-            A.ent_cnt[e] = f - s;
-            items = (uint64_t)((f - s + kPairsPerItem - 1) / kPairsPerItem) * I.S;
+            const uint64_t b0 = I.bbase + ((uint64_t)mat * key_tiles(I.n) + A.unit_tile[u]) * I.n;
+            const uint32_t s = ptr[b0], f = ptr[b0 + I.n];
+            A.unit_start[u] = s;
+            A.unit_cnt[u] = f - s;
+            items = ((uint64_t)(f - s) + kChunkPairs - 1) / kChunkPairs * I.S;
         }
         part[t] = items;
         __syncthreads();
@@ -362,12 +521,12 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs A) {
             part[t] += v;
             __syncthreads();
         }
-        if (e < A.nent) A.item_prefix[e] = carry + part[t] - items;
+        if (u < A.nunit) A.item_prefix[u] = carry + part[t] - items;
         __syncthreads();
         if (t == 1023) carry += part[1023];
         __syncthreads();
     }
-    if (t == 0) A.item_prefix[A.nent] = carry;
+    if (t == 0) A.item_prefix[A.nunit] = carry;
 }
 
 // ------------------------------------------------------------- new-pair sort
@@ -459,8 +618,9 @@ __device__ __forceinline__ LaneRun lane_run(uint32_t rid) {
     return r;
 }
 
-// Row ids of entry x in the row-order and column-order sorts (kHole when the
-// entry is a hole or its matrix needs that order for no production).
+// Buckets of entry x in the two sort orders (kHole when the entry is a hole
+// or its matrix needs that order for no production): row order groups pair
+// (i, j) by (tile of i, j), column order by (tile of j, i).
 __device__ __forceinline__ void entry_rows(const SortArgs &A, uint64_t x, uint64_t n, uint32_t *r, uint32_t *c,
                                            uint32_t *i, uint32_t *j) {
     *r = *c = kHole;
@@ -469,11 +629,11 @@ __device__ __forceinline__ void entry_rows(const SortArgs &A, uint64_t x, uint64
     if (key == kHole) return;
     const InstDev I = A.inst[key_slot(key)];
     const uint32_t need = A.mats[I.mat_off + key_mat(key)].sort;
-    const uint32_t b = I.rowbase + key_mat(key) * I.n;
+    const uint64_t b = I.bbase + (uint64_t)key_mat(key) * key_tiles(I.n) * I.n;
     *i = A.ap_i[x];
     *j = A.ap_j[x];
-    if (need & kSortRows) *r = b + *i;
-    if (need & kSortCols) *c = b + *j;
+    if (need & kSortRows) *r = (uint32_t)(b + (uint64_t)(*i / kTileKeys) * I.n + *j);
+    if (need & kSortCols) *c = (uint32_t)(b + (uint64_t)(*j / kTileKeys) * I.n + *i);
 }
 
 __global__ __launch_bounds__(256) void count_kernel(SortArgs A) {
@@ -802,8 +962,8 @@ __global__ __launch_bounds__(1024) void offsets_kernel(const uint32_t *cnt, uint
     } while (0)
 
 hipError_t launch_product(const ProductArgs &A, uint32_t grid, bool stats, hipStream_t s) {
-    if (stats) product_kernel<true><<<grid, 64, 0, s>>>(A);
-    else product_kernel<false><<<grid, 64, 0, s>>>(A);
+    if (stats) product_kernel<true><<<grid, kProdWaves * kWave, 0, s>>>(A);
+    else product_kernel<false><<<grid, kProdWaves * kWave, 0, s>>>(A);
     CFLR_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -832,10 +992,10 @@ hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long
     return hipSuccess;
 }
 
-// counting sort of the appended pairs; rows: [0, nrows] (nrows + 1 counters)
-hipError_t launch_sort(const SortArgs &A, uint64_t nrows, uint32_t *bsum, uint32_t sort_grid,
+// counting sort of the appended pairs; buckets [0, nbuckets] (nbuckets + 1 counters)
+hipError_t launch_sort(const SortArgs &A, uint64_t nbuckets, uint32_t *bsum, uint32_t sort_grid,
                        hipStream_t s) {
-    const uint64_t len = nrows + 1;
+    const uint64_t len = nbuckets + 1;
     {
         uint64_t g = (len + 255) / 256;
         if (g > 8192) g = 8192;
@@ -858,8 +1018,8 @@ hipError_t launch_sort(const SortArgs &A, uint64_t nrows, uint32_t *bsum, uint32
     return hipSuccess;
 }
 
-uint32_t scan_block_count(uint64_t nrows) {
-    return (uint32_t)((nrows + 1 + kScanTile - 1) / kScanTile);
+uint32_t scan_block_count(uint64_t nbuckets) {
+    return (uint32_t)((nbuckets + 1 + kScanTile - 1) / kScanTile);
 }
 
 hipError_t launch_seed(const SeedArgs &A, hipStream_t s) {
