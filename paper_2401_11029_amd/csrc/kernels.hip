@@ -217,13 +217,13 @@ __device__ __forceinline__ void flush(const ProductArgs &A, SlotChunk &ch, uint3
 // accumulators take in stage s, stage s + 1 is planned and its partner
 // segments are on their way from memory.
 struct ProductShared {
-    uint64_t stage[2][kStageRuns][kSegWords];  // partner segments of two stages
-    unsigned long long mask[2][kTileKeys];     // per key: runs of the stage it pairs with
-    uint32_t run_k[kStageRuns];                // partner of each run of the stage being planned
-    uint32_t wave_heads[kProdWaves];           // runs starting among each wave's pairs
-    unsigned long long nzr[2];                 // runs whose partner segment is non-zero
-    uint32_t stage_len;                        // pairs taken by the stage being planned (when cut)
-    unsigned long long item;                   // the workgroup's current item
+    uint64_t stage[2][kStageRuns][kSegWords];           // partner segments of two stages
+    unsigned long long mask[2][kMaskWords][kTileKeys];  // per key: runs of the stage it pairs with
+    uint32_t run_k[kStageRuns];                         // partner of each run of the stage being planned
+    uint32_t wave_heads[kStageHalves][kProdWaves];      // runs starting among each wave's pairs
+    unsigned long long nzr[2][kMaskWords];              // runs whose partner segment is non-zero
+    uint32_t stage_len;                                 // pairs taken by the stage being planned (when cut)
+    unsigned long long item;                            // the workgroup's current item
 };
 
 struct StagePlan {
@@ -231,18 +231,23 @@ struct StagePlan {
     uint32_t nst;  // runs (distinct partners) of the stage, <= kStageRuns
 };
 
-// Pair x of the sorted order (one per thread) and, for lane 0 of a wave,
-// the pair before it (its partner decides whether x starts a run).
+// Pairs pos + h * 1024 + tid of the sorted order (h < kStageHalves) and, for
+// lane 0 of a wave, the pair before each (its partner decides whether the
+// pair starts a run).
 struct PairFetch {
-    uint64_t pk = 0, prev = 0;
+    uint64_t pk[kStageHalves] = {}, prev[kStageHalves] = {};
 };
 
 __device__ __forceinline__ PairFetch fetch_pairs(const uint64_t *pairs, uint32_t pos, uint32_t p1) {
     PairFetch f;
-    const uint32_t x = pos + threadIdx.x;
-    if (x < p1) {
-        f.pk = pairs[x];
-        if (lane_id() == 0 && threadIdx.x != 0) f.prev = pairs[x - 1];
+#pragma unroll
+    for (uint32_t h = 0; h < kStageHalves; h++) {
+        const uint32_t t = h * kProdWaves * kWave + threadIdx.x;
+        const uint32_t x = pos + t;
+        if (x < p1) {
+            f.pk[h] = pairs[x];
+            if (lane_id() == 0 && t != 0) f.prev[h] = pairs[x - 1];
+        }
     }
     return f;
 }
@@ -255,60 +260,73 @@ __device__ __forceinline__ StagePlan plan_stage(ProductShared &sh, SlotChunk &ch
                                                 uint32_t pos, uint32_t p1, uint32_t key0, uint32_t buf,
                                                 bool count_pairs) {
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    const bool valid = pos + tid < p1;
-    const uint32_t key = (uint32_t)(f.pk >> 32);
-    const uint32_t k = valid ? (uint32_t)f.pk : kHole;
-    uint32_t kprev = __shfl_up(k, 1, 64);
-    if (lane == 0) kprev = (tid == 0 || !valid) ? kHole : (uint32_t)f.prev;
-    const bool head = valid && (tid == 0 || k != kprev);
-    const uint64_t hb = __ballot(head);
-    if (lane == 0) sh.wave_heads[wave] = (uint32_t)__popcll(hb);
-    __syncthreads();  // (1) heads counted
-    if (tid == 0) sh.nzr[buf] = 0;
-    uint32_t before = 0, runs = 0;
+    bool valid[kStageHalves], head[kStageHalves];
+    uint64_t hb[kStageHalves];
 #pragma unroll
-    for (uint32_t w = 0; w < kProdWaves; w++) {
-        const uint32_t h = sh.wave_heads[w];
-        before += w < wave ? h : 0;
-        runs += h;
+    for (uint32_t h = 0; h < kStageHalves; h++) {
+        const uint32_t t = h * kProdWaves * kWave + tid;
+        valid[h] = pos + t < p1;
+        const uint32_t k = valid[h] ? (uint32_t)f.pk[h] : kHole;
+        uint32_t kprev = __shfl_up(k, 1, 64);
+        if (lane == 0) kprev = (t == 0 || !valid[h]) ? kHole : (uint32_t)f.prev[h];
+        head[h] = valid[h] && (t == 0 || k != kprev);
+        hb[h] = __ballot(head[h]);
+        if (lane == 0) sh.wave_heads[h][wave] = (uint32_t)__popcll(hb[h]);
     }
+    __syncthreads();  // (1) heads counted
+    if (tid < kMaskWords) sh.nzr[buf][tid] = 0;
     const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
-    const uint32_t run = before + (uint32_t)__popcll(hb & upto) - 1;
-    const bool in_stage = valid && run < kStageRuns;
-    if (runs > kStageRuns && head && run == kStageRuns) sh.stage_len = tid;
-    if (in_stage) {
-        const uint32_t kl = key - key0;
-        if (kl < kTileKeys) atomicOr(&sh.mask[buf][kl], 1ull << run);
-        if (head) sh.run_k[run] = k;
-    }
-    if (STATS && count_pairs) {
-        // the pair itself, read once per production
-        const uint64_t taken = __ballot(in_stage);
-        if (lane == 0) ch.bytes += 8ull * __popcll(taken);
+    uint32_t runs = 0;
+#pragma unroll
+    for (uint32_t h = 0; h < kStageHalves; h++) {
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < kProdWaves; w++) {
+            const uint32_t c = sh.wave_heads[h][w];
+            before += w < wave ? c : 0;
+            total += c;
+        }
+        // pairs of half h before the half's first head continue the last
+        // run of the half before
+        const uint32_t run = runs + before + (uint32_t)__popcll(hb[h] & upto) - 1;
+        const bool in_stage = valid[h] && run < kStageRuns;
+        if (head[h] && run == kStageRuns) sh.stage_len = h * kProdWaves * kWave + tid;
+        if (in_stage) {
+            const uint32_t kl = (uint32_t)(f.pk[h] >> 32) - key0;
+            if (kl < kTileKeys) atomicOr(&sh.mask[buf][run >> 6][kl], 1ull << (run & 63));
+            if (head[h]) sh.run_k[run] = (uint32_t)f.pk[h];
+        }
+        if (STATS && count_pairs) {
+            // the pair itself, read once per production
+            const uint64_t taken = __ballot(in_stage);
+            if (lane == 0) ch.bytes += 8ull * __popcll(taken);
+        }
+        runs += total;
     }
     __syncthreads();  // (2) masks, partners and the cut set
     StagePlan p;
-    const uint32_t nvalid = p1 - pos < kProdWaves * kWave ? p1 - pos : kProdWaves * kWave;
+    const uint32_t nvalid = p1 - pos < kStagePairs ? p1 - pos : kStagePairs;
     p.len = runs > kStageRuns ? sh.stage_len : nvalid;
     p.nst = runs < kStageRuns ? runs : kStageRuns;
     return p;
 }
 
-constexpr uint32_t kRunsPerWave = kStageRuns / kProdWaves;
+// Partner segments of the planned stage come in kMaskWords batches of 64
+// runs; in batch j wave w takes runs 64 j + w + 16 q.  A segment that turns
+// out to be all zero is not staged.
+constexpr uint32_t kBatchRunsPerWave = 64 / kProdWaves;
 
-// Partner segments of the planned stage: wave w takes runs w, w + 16, ...
-// A segment that turns out to be all zero is not staged.
 struct PartnerFetch {
-    uint64_t v[kRunsPerWave];
-    uint32_t kk[kRunsPerWave];
+    uint64_t v[kBatchRunsPerWave];
+    uint32_t kk[kBatchRunsPerWave];
 };
 
 __device__ __forceinline__ void fetch_partners(PartnerFetch &pf, const ProductShared &sh, uint32_t nst,
-                                               global_u64 G, uint64_t Wp, uint32_t seg) {
+                                               uint32_t batch, global_u64 G, uint64_t Wp, uint32_t seg) {
     const uint32_t wave = threadIdx.x / kWave, lane = lane_id();
 #pragma unroll
-    for (uint32_t q = 0; q < kRunsPerWave; q++) {
-        const uint32_t r = wave + kProdWaves * q;
+    for (uint32_t q = 0; q < kBatchRunsPerWave; q++) {
+        const uint32_t r = 64 * batch + wave + kProdWaves * q;
         pf.v[q] = 0;
         pf.kk[q] = 0;
         if (r < nst) {
@@ -321,62 +339,75 @@ __device__ __forceinline__ void fetch_partners(PartnerFetch &pf, const ProductSh
 
 template <bool COL, bool STATS>
 __device__ __forceinline__ void store_partners(const ProductArgs &A, ProductShared &sh, SlotChunk &ch,
-                                               const PartnerFetch &pf, uint32_t buf, uint32_t inst,
-                                               uint32_t pm, uint32_t seg, const InstDev &I) {
+                                               const PartnerFetch &pf, uint32_t buf, uint32_t batch,
+                                               uint32_t inst, uint32_t pm, uint32_t seg, const InstDev &I) {
     const uint32_t wave = threadIdx.x / kWave, lane = lane_id();
     unsigned long long bits = 0;
 #pragma unroll
-    for (uint32_t q = 0; q < kRunsPerWave; q++) {
+    for (uint32_t q = 0; q < kBatchRunsPerWave; q++) {
         const uint64_t live = __ballot(pf.v[q] != 0);
         if (live) {
-            const uint32_t r = wave + kProdWaves * q;
-            sh.stage[buf][r][lane] = pf.v[q];
+            const uint32_t r = wave + kProdWaves * q;  // within the batch
+            sh.stage[buf][64 * batch + r][lane] = pf.v[q];
             bits |= 1ull << r;
             // compulsory bytes: the segment's non-zero words, at its first touch in the round
             if (STATS && lane == 0 && first_touch<STATS>(A, inst, pm, COL ? 1 : 0, pf.kk[q], seg, I))
                 ch.bytes += 8ull * __popcll(live);
         }
     }
-    if (bits && lane == 0) atomicOr(&sh.nzr[buf], bits);
+    if (bits && lane == 0) atomicOr(&sh.nzr[buf][batch], bits);
 }
 
-// acc[q] |= every staged segment key q of this wave pairs with.  The wave's
-// kKeysPerWave masks are read by as many lanes at once, and cleared by them
-// for the stage after next.
-__device__ __forceinline__ void accumulate(ProductShared &sh, uint32_t buf, uint64_t (&acc)[kKeysPerWave]) {
-    const uint32_t wave = threadIdx.x / kWave, lane = lane_id();
-    const unsigned long long nz = sh.nzr[buf];
-    unsigned long long mine = 0;
-    if (lane < kKeysPerWave) {
-        mine = sh.mask[buf][wave * kKeysPerWave + lane];
-        if (mine) sh.mask[buf][wave * kKeysPerWave + lane] = 0;
-    }
-    mine &= nz;
-    const uint64_t(*st)[kSegWords] = sh.stage[buf];
-#pragma unroll
-    for (uint32_t q = 0; q < kKeysPerWave; q++) {
-        unsigned long long m = rdlane64(mine, q);
-        uint64_t a = acc[q];
-        while (m) {
-            const uint32_t c = (uint32_t)__popcll(m);
-            const uint32_t i0 = (uint32_t)__ffsll(m) - 1;
+// a |= the staged rows of runs m (a 64-run word of a mask)
+__device__ __forceinline__ void or_runs(uint64_t &a, unsigned long long m, const uint64_t (*st)[kSegWords],
+                                        uint32_t lane) {
+    while (m) {
+        const uint32_t c = (uint32_t)__popcll(m);
+        const uint32_t i0 = (uint32_t)__ffsll(m) - 1;
+        m &= m - 1;
+        if (c >= 4) {
+            const uint32_t i1 = (uint32_t)__ffsll(m) - 1;
             m &= m - 1;
-            if (c >= 4) {
-                const uint32_t i1 = (uint32_t)__ffsll(m) - 1;
-                m &= m - 1;
-                const uint32_t i2 = (uint32_t)__ffsll(m) - 1;
-                m &= m - 1;
-                const uint32_t i3 = (uint32_t)__ffsll(m) - 1;
-                m &= m - 1;
-                a |= (st[i0][lane] | st[i1][lane]) | (st[i2][lane] | st[i3][lane]);
-            } else if (c >= 2) {
-                const uint32_t i1 = (uint32_t)__ffsll(m) - 1;
-                m &= m - 1;
-                a |= st[i0][lane] | st[i1][lane];
-            } else {
-                a |= st[i0][lane];
-            }
+            const uint32_t i2 = (uint32_t)__ffsll(m) - 1;
+            m &= m - 1;
+            const uint32_t i3 = (uint32_t)__ffsll(m) - 1;
+            m &= m - 1;
+            a |= (st[i0][lane] | st[i1][lane]) | (st[i2][lane] | st[i3][lane]);
+        } else if (c >= 2) {
+            const uint32_t i1 = (uint32_t)__ffsll(m) - 1;
+            m &= m - 1;
+            a |= st[i0][lane] | st[i1][lane];
+        } else {
+            a |= st[i0][lane];
         }
+    }
+}
+
+// The wave's masks: lane w * kKeysPerWave + q holds mask word w of key q
+// (live runs only); the lanes clear them for the stage after next.
+__device__ __forceinline__ unsigned long long take_masks(ProductShared &sh, uint32_t buf) {
+    const uint32_t wave = threadIdx.x / kWave, lane = lane_id();
+    unsigned long long mine = 0;
+    if (lane < kMaskWords * kKeysPerWave) {
+        const uint32_t w = lane / kKeysPerWave, q = lane % kKeysPerWave;
+        mine = sh.mask[buf][w][wave * kKeysPerWave + q];
+        if (mine) sh.mask[buf][w][wave * kKeysPerWave + q] = 0;
+        mine &= sh.nzr[buf][w];
+    }
+    return mine;
+}
+
+// acc[q] |= every staged segment key q (Q0 <= q < Q1) pairs with.
+template <uint32_t Q0, uint32_t Q1>
+__device__ __forceinline__ void accumulate(const ProductShared &sh, uint32_t buf, unsigned long long mine,
+                                           uint64_t (&acc)[kKeysPerWave]) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (uint32_t q = Q0; q < Q1; q++) {
+        uint64_t a = acc[q];
+#pragma unroll
+        for (uint32_t w = 0; w < kMaskWords; w++)
+            or_runs(a, rdlane64(mine, w * kKeysPerWave + q), sh.stage[buf] + 64 * w, lane);
         acc[q] = a;
     }
 }
@@ -384,16 +415,19 @@ __device__ __forceinline__ void accumulate(ProductShared &sh, uint32_t buf, uint
 // One work item: pairs [p0, p1) of one key tile, sorted by partner, against
 // row segment `seg`.  COL = false: pairs (i, k) of dA, partner rows k of B
 // (row-major); COL = true: pairs (j, k) of dB, partner rows k of A's
-// column-major copy.  A stage is the next pairs, one per thread, up to the
-// first pair of the (kStageRuns + 1)-th distinct partner.  Stage s + 1 is
-// planned and its partner segments fetched before stage s is accumulated,
-// and the pairs of stage s + 2 are fetched too, so the accumulation hides
-// the memory latency.  Every loop bound is uniform over the workgroup, so
-// all waves meet at every barrier.
+// column-major copy.  A stage is the next kStagePairs pairs (kStageHalves
+// per thread), cut before the first pair of the (kStageRuns + 1)-th distinct
+// partner.  Stage s + 1 is planned before stage s is accumulated; its two
+// batches of partner segments are fetched during the two halves of the
+// accumulation (keys 0-7, keys 8-15 of each wave), and the pairs of stage
+// s + 2 too, so the accumulation hides the memory latency.  Every loop bound
+// is uniform over the workgroup, so all waves meet at every barrier.
 template <bool COL, bool STATS>
 __device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared &sh, SlotChunk &ch,
                                              const EntryDev &E, const InstDev &I, uint32_t tile,
                                              uint32_t p0, uint32_t p1, uint32_t seg) {
+    static_assert(kMaskWords == 2 && kKeysPerWave % 2 == 0, "two partner batches, two key halves");
+    constexpr uint32_t kHalfKeys = kKeysPerWave / 2;
     const uint32_t wave = threadIdx.x / kWave;
     const uint64_t Wp = (uint64_t)I.S * kSegWords;
     const uint32_t pm = COL ? E.a : E.b;
@@ -409,8 +443,11 @@ __device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared
     // prologue: stage 0 planned and staged, the pairs of stage 1 on the way
     PairFetch f = fetch_pairs(pairs, p0, p1);
     StagePlan cur = plan_stage<STATS>(sh, ch, f, p0, p1, key0, 0, count_pairs);
-    fetch_partners(pf, sh, cur.nst, G, Wp, seg);
-    store_partners<COL, STATS>(A, sh, ch, pf, 0, E.inst, pm, seg, I);
+#pragma unroll
+    for (uint32_t j = 0; j < kMaskWords; j++) {
+        fetch_partners(pf, sh, cur.nst, j, G, Wp, seg);
+        store_partners<COL, STATS>(A, sh, ch, pf, 0, j, E.inst, pm, seg, I);
+    }
     uint32_t next = p0 + cur.len;
     if (next < p1) f = fetch_pairs(pairs, next, p1);
     __syncthreads();  // stage 0 staged
@@ -420,12 +457,18 @@ __device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared
         StagePlan nx{0, 0};
         if (more) {
             nx = plan_stage<STATS>(sh, ch, f, next, p1, key0, b ^ 1, count_pairs);
-            fetch_partners(pf, sh, nx.nst, G, Wp, seg);
+            fetch_partners(pf, sh, nx.nst, 0, G, Wp, seg);
             if (next + nx.len < p1) f = fetch_pairs(pairs, next + nx.len, p1);
         }
-        accumulate(sh, b, acc);
+        const unsigned long long mine = take_masks(sh, b);
+        accumulate<0, kHalfKeys>(sh, b, mine, acc);
+        if (more) {
+            store_partners<COL, STATS>(A, sh, ch, pf, b ^ 1, 0, E.inst, pm, seg, I);
+            fetch_partners(pf, sh, nx.nst, 1, G, Wp, seg);
+        }
+        accumulate<kHalfKeys, kKeysPerWave>(sh, b, mine, acc);
         if (!more) break;
-        store_partners<COL, STATS>(A, sh, ch, pf, b ^ 1, E.inst, pm, seg, I);
+        store_partners<COL, STATS>(A, sh, ch, pf, b ^ 1, 1, E.inst, pm, seg, I);
         __syncthreads();  // (3) stage s + 1 staged; stage s consumed
         b ^= 1;
         next += nx.len;
@@ -449,7 +492,8 @@ __global__ __launch_bounds__(kProdWaves * kWave) void product_kernel(ProductArgs
     const uint32_t tid = threadIdx.x;
     const uint64_t total = A.item_prefix[A.nunit];
     SlotChunk ch;
-    if (tid < kTileKeys) sh.mask[0][tid] = sh.mask[1][tid] = 0;
+    if (tid < kTileKeys)
+        for (uint32_t w = 0; w < kMaskWords; w++) sh.mask[0][w][tid] = sh.mask[1][w][tid] = 0;
     while (true) {
         // items are taken from a counter, one atomic per workgroup and item;
         // after an overflow the round is re-run: stop early
