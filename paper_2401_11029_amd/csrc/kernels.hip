@@ -420,8 +420,10 @@ __device__ __forceinline__ void accumulate(const ProductShared &sh, uint32_t buf
 // partner.  Stage s + 1 is planned before stage s is accumulated; its two
 // batches of partner segments are fetched during the two halves of the
 // accumulation (keys 0-7, keys 8-15 of each wave), and the pairs of stage
-// s + 2 too, so the accumulation hides the memory latency.  Every loop bound
-// is uniform over the workgroup, so all waves meet at every barrier.
+// s + 2 too, so the accumulation hides the memory latency.  The barriers of
+// planning stage s + 1 also separate the staging of stage s from its
+// accumulation.  Every loop bound is uniform over the workgroup, so all
+// waves meet at every barrier.
 template <bool COL, bool STATS>
 __device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared &sh, SlotChunk &ch,
                                              const EntryDev &E, const InstDev &I, uint32_t tile,
@@ -450,7 +452,10 @@ __device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared
     }
     uint32_t next = p0 + cur.len;
     if (next < p1) f = fetch_pairs(pairs, next, p1);
-    __syncthreads();  // stage 0 staged
+    // stage s is staged (and stage s - 1 consumed) once every wave has passed
+    // the first barrier of planning stage s + 1; with no stage s + 1 to plan
+    // a barrier of its own is needed
+    if (next >= p1) __syncthreads();
     uint32_t b = 0;
     while (true) {
         const bool more = next < p1;
@@ -469,9 +474,9 @@ __device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared
         accumulate<kHalfKeys, kKeysPerWave>(sh, b, mine, acc);
         if (!more) break;
         store_partners<COL, STATS>(A, sh, ch, pf, b ^ 1, 1, E.inst, pm, seg, I);
-        __syncthreads();  // (3) stage s + 1 staged; stage s consumed
         b ^= 1;
         next += nx.len;
+        if (next >= p1) __syncthreads();  // the last stage is staged
     }
     // flush the tile's keys; one flush body, the accumulators rotate through acc[0]
     const MatDev Mc = A.mats[I.mat_off + E.c];
