@@ -83,6 +83,26 @@ def test_row_segment_boundaries(ctx, n):
     assert_matches_oracle(gpu_solve(ctx, G.ALIAS_FIG5A_WCNF, g), G.ALIAS_FIG5A_WCNF, g)
 
 
+@pytest.mark.parametrize("n", [255, 256, 257, 511, 513, 769])
+def test_key_tile_boundaries(ctx, n):
+    # the product works on tiles of 256 keys: n just below, at and above a
+    # multiple of 256 (a last tile with one key, a full last tile)
+    for text, labels in [(G.ALIAS_FIG5A_WCNF, ["a", "d", "a_bar", "d_bar"]), (G.DYCK1, ["a", "b"])]:
+        g = graphs.random_graph(n, 3 * n, labels, seed=4000 + n, self_loops=True)
+        assert_matches_oracle(gpu_solve(ctx, text, g), text, g, f"n={n}")
+
+
+def test_tiles_split_into_pair_chunks(ctx):
+    # a dense relation: in round 2 one key tile holds ~145k new pairs of one
+    # operand, more than one work item takes (several chunks per tile, each
+    # flushing its own partial accumulators), and stages are cut by the pair
+    # limit as well as by the partner limit
+    g = graphs.random_graph(600, 20000, ["a"], seed=4242, self_loops=True)
+    r = gpu_solve(ctx, G.TRANSITIVE, g)
+    assert r.stats()["max_delta"] > 2 * 32768
+    assert_matches_oracle(r, G.TRANSITIVE, g)
+
+
 @pytest.mark.parametrize("name", ["alias_8k", "alias5b_8k", "pointsto_4k", "pointsto_12k"])
 def test_golden_digests(ctx, name):
     from tests.golden.make_goldens import GOLDENS
