@@ -24,7 +24,7 @@ namespace cflr {
 // that readout needs.
 void compact_instance(Instance &in) {
     const uint32_t U = (uint32_t)in.low.user_names.size();
-    const uint64_t words = (uint64_t)in.n * (in.Wp + in.S);
+    const uint64_t words = (uint64_t)in.n * in.Wp;
     const uint64_t bytes = words * 8 * U;
     if (!bytes || bytes >= in.arena.bytes) return;
     DevBuf nb(in.ctx->pool.get(), bytes);
@@ -35,8 +35,7 @@ void compact_instance(Instance &in) {
                                  in.ctx->stream),
                   "D2D");
         mats[x].R = p;
-        mats[x].RS = nullptr;
-        mats[x].C = mats[x].CS = nullptr;
+        mats[x].C = nullptr;
         mats[x].sort = 0;
         mats[x].pad = 0;
         p += words;

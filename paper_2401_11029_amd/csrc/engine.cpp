@@ -109,11 +109,11 @@ static void plan_layout(const Lowered &low, uint32_t n, uint32_t *S, uint64_t *W
     const uint64_t words = ((uint64_t)n + 63) / 64;
     *S = (uint32_t)std::max<uint64_t>(1, (words + kSegWords - 1) / kSegWords);
     *Wp = (uint64_t)*S * kSegWords;
-    const uint64_t layout = (uint64_t)n * (*Wp + *S) * 8;
+    const uint64_t layout = (uint64_t)n * *Wp * 8;
     uint64_t total = 0;
     has_col->assign(low.nmat(), 0);
     for (uint32_t x = 0; x < low.nmat(); x++) {
-        total += layout;  // R + RS
+        total += layout;  // R
         if (low.dynamic[x] || low.slot_a[x]) {
             (*has_col)[x] = 1;
             total += layout;
@@ -151,7 +151,6 @@ std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const
     inst->footprint = bytes;
     inst->counts.assign(low.user_names.size(), -1);
     const uint64_t layout_words = (uint64_t)g->n * inst->Wp;
-    const uint64_t sum_words = (uint64_t)g->n * inst->S;
     if (bytes) inst->arena = DevBuf(ctx->pool.get(), bytes);
     uint64_t *p = inst->arena.as<uint64_t>();
     inst->mats.resize(low.nmat());
@@ -159,16 +158,12 @@ std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const
         MatDev &M = inst->mats[x];
         M.R = p;
         p += layout_words;
-        M.RS = p;
-        p += sum_words;
-        M.C = M.CS = nullptr;
+        M.C = nullptr;
         M.sort = (low.slot_a[x] ? kSortRows : 0u) | (low.slot_b[x] ? kSortCols : 0u);
         M.pad = 0;
         if (has_col[x]) {
             M.C = p;
             p += layout_words;
-            M.CS = p;
-            p += sum_words;
         }
     }
     if (bytes) hip_check(hipMemsetAsync(inst->arena.ptr, 0, bytes, ctx->stream), "zero matrices");
@@ -400,22 +395,24 @@ void Run::rebuild_tables() {
         Instance &in = *ip;
         hi[in.slot] = InstDev{in.n, in.S, in.bbase, (uint32_t)hm.size()};
         for (auto &m : in.mats) hm.push_back(m);
-        for (auto &b : in.low.binary) {
-            he.push_back(EntryDev{in.slot, b.c, b.a, b.b, 0});
-            he.push_back(EntryDev{in.slot, b.c, b.a, b.b, 1});
-        }
         toff[in.slot] = tbits;
         tbits += (uint64_t)in.low.nmat() * 2 * in.n * in.S;
     }
+    // entries: every row part (part 0) first, then every column part
+    for (uint32_t part = 0; part < 2; part++)
+        for (auto &ip : insts_)
+            for (auto &b : ip->low.binary) he.push_back(EntryDev{ip->slot, b.c, b.a, b.b, part});
     nent_ = (uint32_t)he.size();
-    // units: (entry, key tile)
+    // units: (entry, key tile); those of part 0 come first
     std::vector<uint32_t> hue, hut;
+    unit_split_ = 0;
     for (uint32_t e = 0; e < nent_; e++) {
         const uint32_t nt = key_tiles(hi[he[e].inst].n);
         for (uint32_t t = 0; t < nt; t++) {
             hue.push_back(e);
             hut.push_back(t);
         }
+        if (he[e].part == 0) unit_split_ = (uint32_t)hue.size();
     }
     nunit_ = (uint32_t)hue.size();
     std::vector<uint32_t> active(max_inst_, 0);
@@ -523,7 +520,8 @@ void Run::enqueue_product(bool timed) {
     P.unit_start = d_unit_start_.as<uint32_t>();
     P.unit_cnt = d_unit_cnt_.as<uint32_t>();
     P.item_prefix = d_prefix_.as<uint64_t>();
-    P.work_counter = counters + 1;
+    P.work_counter0 = counters + 1;
+    P.work_counter1 = counters + 4;
     P.halt = halt;
     hip_check(launch_prep(P, s_), "prep");
     if (opts_.count_traffic && touched_bits_)
@@ -537,7 +535,6 @@ void Run::enqueue_product(bool timed) {
     A.unit_start = d_unit_start_.as<uint32_t>();
     A.unit_cnt = d_unit_cnt_.as<uint32_t>();
     A.item_prefix = d_prefix_.as<uint64_t>();
-    A.nunit = nunit_;
     A.rs = d_rs_.as<uint64_t>();
     A.cs = d_cs_.as<uint64_t>();
     A.ap_key = d_ap_key_.as<uint32_t>();
@@ -547,47 +544,46 @@ void Run::enqueue_product(bool timed) {
     A.ap_cap = ap_cap_;
     A.inst_overflow = d_inst_over_.as<uint32_t>();
     A.halt = halt;
-    A.work_counter = counters + 1;
+    A.inst_new = d_inst_new_.as<unsigned long long>();
     A.touched = d_touched_.as<uint32_t>();
     A.touched_off = d_touched_off_.as<uint64_t>();
     A.algo_bytes = counters + 2;
     if (timed) hip_check(hipEventRecord(ev0_, s_), "event");
+    // the row parts, then the column parts (a pair derived by both is then
+    // reported once: by the row part)
+    A.unit_lo = 0;
+    A.unit_hi = unit_split_;
+    A.work_counter = counters + 1;
+    hip_check(launch_product(A, grid_, opts_.count_traffic != 0, s_), "product");
+    A.unit_lo = unit_split_;
+    A.unit_hi = nunit_;
+    A.work_counter = counters + 4;
     hip_check(launch_product(A, grid_, opts_.count_traffic != 0, s_), "product");
     if (timed) hip_check(hipEventRecord(ev1_, s_), "event");
-    product_launches_++;
+    product_launches_ += 2;
 }
 
-void Run::enqueue_settle() {
+// End of a round: fold the new-pair counts into the per-instance statistics.
+void Run::enqueue_round_end() {
     unsigned long long *counters = d_counters_.as<unsigned long long>();
     uint32_t *halt = reinterpret_cast<uint32_t *>(counters + 3);
-    SettleArgs T{};
-    T.inst = d_inst_.as<InstDev>();
-    T.mats = d_mats_.as<MatDev>();
-    T.ap_key = d_ap_key_.as<uint32_t>();
-    T.ap_i = d_ap_i_.as<uint32_t>();
-    T.ap_j = d_ap_j_.as<uint32_t>();
-    T.ap_count = counters;
-    T.ap_cap = ap_cap_;
-    T.inst_new = d_inst_new_.as<unsigned long long>();
-    T.halt = halt;
-    hip_check(launch_settle(T, ctx_->num_cu * 8, s_), "settle");
     hip_check(launch_round_end(d_active_.as<uint32_t>(), d_inst_new_.as<unsigned long long>(),
                                d_slot_stats_.as<SlotStats>(), max_inst_, halt, s_),
               "round_end");
 }
 
 // One round without host synchronisation: sort the pending new pairs into
-// dA / dB, run the product, settle, fold the counts.  Every kernel skips its
+// dA / dB, run the product, fold the counts.  Every kernel skips its
 // work once an overflow has set the halt flag.
 void Run::enqueue_round(bool timed) {
     sort_appended();
     enqueue_product(timed);
-    enqueue_settle();
+    enqueue_round_end();
 }
 
 // After an overflow: the product of the overflowing round left M unchanged
 // for the candidates it could not append; dA / dB of that round are still in
-// rs / cs.  Grow the buffer (keeping [0, cap)), re-run that product, settle.
+// rs / cs.  Grow the buffer (keeping [0, cap)), re-run that product.
 void Run::recover() {
     unsigned long long *counters = d_counters_.as<unsigned long long>();
     uint32_t *halt = reinterpret_cast<uint32_t *>(counters + 3);
@@ -602,7 +598,7 @@ void Run::recover() {
         hip_check(launch_fill_u32(halt, 1, 0, s_), "fill");
         hip_check(launch_fill_u32(d_inst_over_.as<uint32_t>(), max_inst_, 0, s_), "fill");
         enqueue_product(false);
-        enqueue_settle();
+        enqueue_round_end();
         read_flags();
     }
 }

@@ -194,7 +194,7 @@ class Run {
     uint64_t bucket_hi() const;
     void extract_all_pairs();
     void enqueue_product(bool timed);
-    void enqueue_settle();
+    void enqueue_round_end();
     void enqueue_round(bool timed);
     void recover();
     void log_round();
@@ -210,11 +210,12 @@ class Run {
     // device tables
     DevBuf d_inst_, d_mats_, d_ent_, d_prefix_;
     DevBuf d_unit_ent_, d_unit_tile_, d_unit_start_, d_unit_cnt_;
-    uint32_t nent_ = 0, nunit_ = 0;
+    uint32_t nent_ = 0, nunit_ = 0, unit_split_ = 0;  // units [0, unit_split_) are row parts
     DevBuf d_rcnt_, d_ccnt_, d_bsum_;
     DevBuf d_ap_key_, d_ap_i_, d_ap_j_, d_rs_, d_cs_;
     uint64_t ap_cap_ = 0;
-    DevBuf d_counters_;  // [0] ap_count, [1] work_counter, [2] algo_bytes, [3] halt (u32)
+    DevBuf d_counters_;  // [0] ap_count, [1] items taken (row parts), [2] algo_bytes, [3] halt (u32),
+                         // [4] items taken (column parts)
     DevBuf d_inst_new_, d_inst_over_, d_active_, d_slot_stats_;
     SlotStats *h_stats_ = nullptr;
     hipGraphExec_t graph_exec_ = nullptr;

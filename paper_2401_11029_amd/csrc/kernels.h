@@ -5,9 +5,7 @@
 // optimisation 2): R (row-major: row i holds bit j for pair (i, j)) and C
 // (column-major: row j holds bit i).  A row is Wp = 64 * S words of 64 bits,
 // cut into S segments of 64 words (4096 columns); one wave of 64 lanes owns
-// one segment, one word per lane.  RS / CS hold one summary word per row
-// segment whose bit l says "word l of this segment is non-zero", so sparse
-// rows are skipped without reading them.
+// one segment, one word per lane.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,26 +37,20 @@ constexpr uint32_t kMaskWords = kStageRuns / 64;
 constexpr uint32_t kChunkPairs = 32768;
 __host__ __device__ inline uint32_t key_tiles(uint32_t n) { return (n + kTileKeys - 1) / kTileKeys; }
 
-// Key of an appended pair: bits 0..15 matrix, bits 16..29 instance slot,
-// bit 30 "settled" (both layouts already hold the pair: seeds, restarts),
-// bit 31 "found by the column part" (only the column-major copy holds it
-// until the settle pass).  kHole marks an unused slot.
+// Key of an appended pair: bits 0..15 matrix, bits 16..29 instance slot.
+// kHole marks an unused slot.
 constexpr uint32_t kHole = 0xFFFFFFFFu;
-constexpr uint32_t kSettled = 0x40000000u;
-constexpr uint32_t kColFound = 0x80000000u;
 constexpr uint32_t kMaxSlots = 0x3FFFu;
 constexpr uint32_t kMaxMats = 0x10000u;
-__host__ __device__ inline uint32_t pair_key(uint32_t slot, uint32_t mat, uint32_t flags) {
-    return flags | (slot << 16) | mat;
-}
+__host__ __device__ inline uint32_t pair_key(uint32_t slot, uint32_t mat) { return (slot << 16) | mat; }
 __host__ __device__ inline uint32_t key_slot(uint32_t key) { return (key >> 16) & kMaxSlots; }
 __host__ __device__ inline uint32_t key_mat(uint32_t key) { return key & 0xFFFFu; }
 
 struct MatDev {
-    uint64_t *R, *RS;  // row-major bits and summaries (always present)
-    uint64_t *C, *CS;  // column-major copy (null when no production needs it)
-    uint32_t sort;     // kSortRows: new pairs needed in row order (the matrix
-                       // stands in an a slot); kSortCols: in column order (b slot)
+    uint64_t *R;    // row-major bits (always present)
+    uint64_t *C;    // column-major copy (null when no production needs it)
+    uint32_t sort;  // kSortRows: new pairs needed in row order (the matrix
+                    // stands in an a slot); kSortCols: in column order (b slot)
     uint32_t pad;
 };
 constexpr uint32_t kSortRows = 1u, kSortCols = 2u;
@@ -73,7 +65,9 @@ struct InstDev {
 
 // One (instance, production, part) of a round; part 0 = rows of the new
 // pairs of a times B (row by row), part 1 = A times the new pairs of b
-// (column by column).
+// (column by column).  The parts of a round run as two launches, every
+// part 0 first: a pair that part 0 derives is in both copies of its matrix
+// before part 1 starts, so the two parts never both report one pair.
 struct EntryDev {
     uint32_t inst, c, a, b, part;
 };
@@ -90,7 +84,7 @@ struct ProductArgs {
     const uint32_t *unit_start;   // first new pair of the unit
     const uint32_t *unit_cnt;     // number of new pairs of the unit
     const uint64_t *item_prefix;  // exclusive prefix of items per unit; [nunit] = total
-    uint32_t nunit;
+    uint32_t unit_lo, unit_hi;    // units of this launch (all of one part)
     const uint64_t *rs;           // new pairs (i, k) in (i tile, k) order, packed (i << 32) | k
     const uint64_t *cs;           // new pairs (k, j) in (j tile, k) order, packed (j << 32) | k
     uint32_t *ap_key, *ap_i, *ap_j;   // appended new pairs: (key, i, j)
@@ -98,7 +92,8 @@ struct ProductArgs {
     uint64_t ap_cap;
     uint32_t *inst_overflow;       // per instance: an append did not fit
     uint32_t *halt;                // any overflow: later kernels of the round skip
-    unsigned long long *work_counter;
+    unsigned long long *work_counter;  // items taken by this launch
+    unsigned long long *inst_new;  // [slot * kCountShards + shard]: new pairs of the round
     // traffic accounting (STATS): first-touch bits per (matrix, layout, row, segment)
     uint32_t *touched;             // bit array
     const uint64_t *touched_off;   // per instance: bit offset of its matrices
@@ -113,7 +108,7 @@ struct PrepArgs {
     const uint32_t *rptr, *cptr;  // bucket starts of the two sort orders
     uint32_t *unit_start, *unit_cnt;
     uint64_t *item_prefix;
-    unsigned long long *work_counter;
+    unsigned long long *work_counter0, *work_counter1;  // reset for the two launches
     const uint32_t *halt;
 };
 
@@ -125,22 +120,6 @@ struct SortArgs {
     uint64_t ap_cap;
     uint32_t *rcnt, *ccnt;       // per bucket: counts -> inclusive scan -> starts (after scatter)
     uint64_t *rs, *cs;
-    const uint32_t *halt;
-};
-
-// Second half of a round: a pair the column part found is copied into the
-// row-major layout, which decides: if the row part found it too this round,
-// the column part's entry is dropped.  (Row-found pairs were copied into the
-// column-major layout by the product itself.)  Counts the surviving new
-// pairs per instance.
-struct SettleArgs {
-    const InstDev *inst;
-    const MatDev *mats;
-    uint32_t *ap_key;
-    const uint32_t *ap_i, *ap_j;
-    const unsigned long long *ap_count;
-    uint64_t ap_cap;
-    unsigned long long *inst_new;  // [slot * kCountShards + shard]
     const uint32_t *halt;
 };
 
@@ -180,7 +159,6 @@ hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long
 hipError_t launch_sort(const SortArgs &A, uint64_t nbuckets, uint32_t *bsum, uint32_t sort_grid,
                        hipStream_t s);
 uint32_t scan_block_count(uint64_t nbuckets);
-hipError_t launch_settle(const SettleArgs &A, uint32_t grid, hipStream_t s);
 hipError_t launch_round_end(const uint32_t *active, unsigned long long *inst_new, SlotStats *st, uint32_t nslots,
                             const uint32_t *halt, hipStream_t s);
 hipError_t launch_reset_appends(unsigned long long *ap_count, const uint32_t *halt, hipStream_t s);

@@ -160,7 +160,8 @@ __device__ __forceinline__ bool first_touch(const ProductArgs &A, uint32_t inst,
 // copy is the authority; COL = true: acc holds candidate rows i of column
 // `key` (= j), and the column-major copy is the authority.  One returning
 // 64-bit atomic OR per word tells which candidates are genuinely new; they
-// are appended (the settle pass updates the other copy after the product).
+// are appended, set in the other copy (no return value needed) and counted
+// for their instance.
 template <bool COL, bool STATS>
 __device__ __forceinline__ void flush(const ProductArgs &A, SlotChunk &ch, uint32_t inst, const InstDev &I,
                                       const MatDev &Mc, uint32_t c, uint32_t key, uint32_t seg,
@@ -168,7 +169,7 @@ __device__ __forceinline__ void flush(const ProductArgs &A, SlotChunk &ch, uint3
     const uint32_t lane = lane_id();
     const uint32_t w = seg * kSegWords + lane;
     uint64_t *own = (COL ? Mc.C : Mc.R) + (uint64_t)key * Wp + w;
-    uint64_t *own_sum = (COL ? Mc.CS : Mc.RS) + (uint64_t)key * I.S + seg;
+    uint64_t *other = COL ? Mc.R : Mc.C;
     uint64_t cand = 0;
     if (acc) cand = acc & ~*own;
     if (STATS) {
@@ -183,33 +184,27 @@ __device__ __forceinline__ void flush(const ProductArgs &A, SlotChunk &ch, uint3
         old = atomicOr((unsigned long long *)own, (unsigned long long)cand);
         nw = cand & ~old;
     }
-    uint64_t made = __ballot(nw != 0 && old == 0);
-    if (made && lane == 0) atomicOr((unsigned long long *)own_sum, (unsigned long long)made);
-    const uint32_t k = pair_key(inst, c, COL ? kColFound : 0u);
+    const uint32_t k = pair_key(inst, c);
     uint64_t bits = cand;
     while (bits) {
         uint32_t b = __ffsll((unsigned long long)bits) - 1;
         bits &= bits - 1;
         if ((nw >> b) & 1) {
+            const uint32_t x = w * 64 + b;  // the other index of the pair
             A.ap_key[pos] = k;
-            A.ap_i[pos] = COL ? w * 64 + b : key;
-            A.ap_j[pos] = COL ? key : w * 64 + b;
-            if (!COL) {
-                // the column part of this round then sees the pair sooner
-                // (fewer pairs found twice); no return value is needed
-                const uint32_t j = w * 64 + b;
-                atomicOr((unsigned long long *)&Mc.C[(uint64_t)j * Wp + (key >> 6)], 1ull << (key & 63));
-                atomicOr((unsigned long long *)&Mc.CS[(uint64_t)j * I.S + (key >> 12)],
-                         1ull << ((key >> 6) & 63));
-            }
+            A.ap_i[pos] = COL ? x : key;
+            A.ap_j[pos] = COL ? key : x;
+            atomicOr((unsigned long long *)&other[(uint64_t)x * Wp + (key >> 6)], 1ull << (key & 63));
         } else {
             A.ap_key[pos] = kHole;
         }
         pos++;
     }
-    if (STATS) {
-        uint32_t fresh = wave_sum((uint32_t)__popcll(nw));
-        if (fresh && lane == 0) ch.bytes += 20ull * fresh;
+    const uint32_t fresh = wave_sum((uint32_t)__popcll(nw));
+    if (fresh && lane == 0) {
+        const uint32_t shard = (blockIdx.x * kProdWaves + threadIdx.x / kWave) % kCountShards;
+        atomicAdd(&A.inst_new[(uint64_t)inst * kCountShards + shard], (unsigned long long)fresh);
+        if (STATS) ch.bytes += 20ull * fresh;
     }
 }
 
@@ -495,7 +490,7 @@ template <bool STATS>
 __global__ __launch_bounds__(kProdWaves * kWave) void product_kernel(ProductArgs A) {
     __shared__ ProductShared sh;
     const uint32_t tid = threadIdx.x;
-    const uint64_t total = A.item_prefix[A.nunit];
+    const uint64_t first = A.item_prefix[A.unit_lo], total = A.item_prefix[A.unit_hi];
     SlotChunk ch;
     if (tid < kTileKeys)
         for (uint32_t w = 0; w < kMaskWords; w++) sh.mask[0][w][tid] = sh.mask[1][w][tid] = 0;
@@ -503,7 +498,7 @@ __global__ __launch_bounds__(kProdWaves * kWave) void product_kernel(ProductArgs
         // items are taken from a counter, one atomic per workgroup and item;
         // after an overflow the round is re-run: stop early
         if (tid == 0) {
-            unsigned long long it = atomicAdd(A.work_counter, 1ull);
+            unsigned long long it = first + atomicAdd(A.work_counter, 1ull);
             if (__hip_atomic_load(A.halt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) it = total;
             sh.item = it;
         }
@@ -511,7 +506,7 @@ __global__ __launch_bounds__(kProdWaves * kWave) void product_kernel(ProductArgs
         const uint64_t item = sh.item;
         __syncthreads();  // every thread has read the item before thread 0 takes the next
         if (item >= total) break;
-        uint32_t lo = 0, hi = A.nunit;  // item_prefix[lo] <= item < item_prefix[hi]
+        uint32_t lo = A.unit_lo, hi = A.unit_hi;  // item_prefix[lo] <= item < item_prefix[hi]
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
             if (A.item_prefix[mid] <= item) lo = mid;
@@ -545,7 +540,8 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs A) {
     const uint32_t t = threadIdx.x;
     if (t == 0) {
         carry = 0;
-        *A.work_counter = 0;
+        *A.work_counter0 = 0;
+        *A.work_counter1 = 0;
     }
     __syncthreads();
     for (uint32_t base = 0; base < A.nunit; base += 1024) {
@@ -601,48 +597,6 @@ __global__ void fill_u64_kernel(unsigned long long *a, uint64_t n, unsigned long
         a[x] = v;
 }
 
-
-__global__ __launch_bounds__(256) void settle_kernel(SettleArgs A) {
-    if (*A.halt) return;
-    uint64_t n = *A.ap_count;
-    if (n > A.ap_cap) n = A.ap_cap;
-    const uint32_t lane = lane_id();
-    // survivors are counted per wave into one of kCountShards counters of
-    // their instance, so that no single address takes every update
-    const uint32_t shard = (blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) % kCountShards;
-    for (uint64_t x0 = blockIdx.x * (uint64_t)blockDim.x; x0 < n; x0 += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t x = x0 + threadIdx.x;
-        const uint32_t key = x < n ? A.ap_key[x] : kHole;
-        bool keep = key != kHole && !(key & kSettled);
-        const uint32_t slot = keep ? key_slot(key) : 0;
-        if (keep && (key & kColFound)) {
-            // the row-major copy decides: set there already means the row
-            // part found the pair too, and its entry is the one kept
-            const InstDev I = A.inst[slot];
-            const MatDev M = A.mats[I.mat_off + key_mat(key)];
-            const uint64_t Wp = (uint64_t)I.S * kSegWords;
-            const uint32_t i = A.ap_i[x], j = A.ap_j[x];
-            const uint64_t bit = 1ull << (j & 63);
-            unsigned long long old = atomicOr((unsigned long long *)&M.R[(uint64_t)i * Wp + (j >> 6)], bit);
-            keep = !(old & bit);
-            if (keep && old == 0)
-                atomicOr((unsigned long long *)&M.RS[(uint64_t)i * I.S + (j >> 12)], 1ull << ((j >> 6) & 63));
-            if (!keep) A.ap_key[x] = kHole;
-        }
-        // (a row-found pair was already copied into the column-major layout
-        // by the product's flush; it is only counted here)
-        const uint64_t kept = __ballot(keep);
-        if (!kept) continue;
-        const uint32_t leader = (uint32_t)__ffsll((unsigned long long)kept) - 1;
-        const uint32_t s0 = rdlane(slot, leader);
-        if (__ballot(keep && slot != s0) == 0) {
-            if (lane == leader)
-                atomicAdd(&A.inst_new[(uint64_t)s0 * kCountShards + shard], (unsigned long long)__popcll(kept));
-        } else if (keep) {
-            atomicAdd(&A.inst_new[(uint64_t)slot * kCountShards + shard], 1ull);
-        }
-    }
-}
 
 // Runs of equal row ids among the 64 lanes of a wave (consecutive buffer
 // positions): the appended pairs of one flush share their row (row part) or
@@ -816,20 +770,11 @@ __device__ __forceinline__ void seed_pair(const SeedArgs &A, uint32_t x, uint32_
     uint64_t bit = 1ull << (j & 63);
     unsigned long long o = atomicOr((unsigned long long *)&M.R[(uint64_t)i * Wp + (j >> 6)], bit);
     if (o & bit) return;
-    if (o == 0)
-        atomicOr((unsigned long long *)&M.RS[(uint64_t)i * A.I.S + (j >> 12)],
-                 1ull << ((j >> 6) & 63));
-    if (M.C) {
-        unsigned long long o2 =
-            atomicOr((unsigned long long *)&M.C[(uint64_t)j * Wp + (i >> 6)], 1ull << (i & 63));
-        if (o2 == 0)
-            atomicOr((unsigned long long *)&M.CS[(uint64_t)j * A.I.S + (i >> 12)],
-                     1ull << ((i >> 6) & 63));
-    }
+    if (M.C) atomicOr((unsigned long long *)&M.C[(uint64_t)j * Wp + (i >> 6)], 1ull << (i & 63));
     unsigned long long p = atomicAdd(A.ap_count, 1ull);
     atomicAdd(&A.inst_new[(uint64_t)A.inst * kCountShards], 1ull);
     if (p < A.ap_cap) {
-        A.ap_key[p] = pair_key(A.inst, x, kSettled);
+        A.ap_key[p] = pair_key(A.inst, x);
         A.ap_i[p] = i;
         A.ap_j[p] = j;
     } else {
@@ -855,9 +800,8 @@ __global__ void seed_eps_kernel(SeedArgs A) {
     }
 }
 
-// Every pair of every matrix becomes "new" (restart from M, or the naive
-// variant where each round multiplies all of M).  Both layouts already hold
-// these pairs, so they are appended as settled.
+// Every pair of every matrix becomes "new" (the naive variant, where each
+// round multiplies all of M).  Both layouts already hold these pairs.
 __global__ __launch_bounds__(64) void extract_all_kernel(const MatDev *mats, InstDev I, uint32_t slot,
                                                          uint32_t nmat, uint32_t *ap_key, uint32_t *ap_i,
                                                          uint32_t *ap_j, unsigned long long *ap_count,
@@ -881,7 +825,7 @@ __global__ __launch_bounds__(64) void extract_all_kernel(const MatDev *mats, Ins
             uint32_t b = __ffsll((unsigned long long)v) - 1;
             v &= v - 1;
             if (p < ap_cap) {
-                ap_key[p] = pair_key(slot, x, kSettled);
+                ap_key[p] = pair_key(slot, x);
                 ap_i[p] = i;
                 ap_j[p] = (seg * kSegWords + lane) * 64 + b;
             } else {
@@ -1105,12 +1049,6 @@ hipError_t launch_reset_appends(unsigned long long *ap_count, const uint32_t *ha
 hipError_t launch_purge_slot(uint32_t *ap_key, const unsigned long long *ap_count, uint64_t ap_cap,
                              uint32_t slot, uint32_t grid, hipStream_t s) {
     purge_slot_kernel<<<grid, 256, 0, s>>>(ap_key, ap_count, ap_cap, slot);
-    CFLR_LAUNCH_CHECK();
-    return hipSuccess;
-}
-
-hipError_t launch_settle(const SettleArgs &A, uint32_t grid, hipStream_t s) {
-    settle_kernel<<<grid, 256, 0, s>>>(A);
     CFLR_LAUNCH_CHECK();
     return hipSuccess;
 }
