@@ -172,9 +172,9 @@ cflr_status cflr_solve(cflr_ctx *ctx, const cflr_grammar *g, const cflr_graph *g
                        const cflr_opts *opts, cflr_result **out);
 
 /* Batched form: graphs[k] is solved with grammars[k] (the same grammar may be
- * passed for every k).  All instances advance together, one fused product
- * launch per round over every (graph, production, block of new pairs), so
- * many uneven graphs share the device.  outs: caller array of count
+ * passed for every k).  All instances advance together: the product of a
+ * round is two launches (row parts, then column parts) over every (graph,
+ * production, tile of new pairs), so many uneven graphs share the device.  outs: caller array of count
  * pointers, each set to a result (or NULL on failure).  Results are
  * identical to cflr_solve of each graph alone. */
 cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
@@ -209,10 +209,12 @@ void cflr_result_free(cflr_result *r);
  * A worker thread keeps the device busy with every admitted request: between
  * rounds it admits queued requests while the estimated device footprint of
  * the running ones plus the new one stays within hbm_budget_bytes and fewer
- * than max_slots run, and retires requests that converged.  Each round is
- * one fused launch over all running requests.  Requests may use different
- * grammars.  Results are identical to cflr_solve of the same input.
- * A request whose footprint alone exceeds the budget fails with ENOMEM.
+ * than max_slots run, and retires requests that converged.  Each round's
+ * product is two launches (row parts, then column parts) over all running
+ * requests.  Requests may use different grammars.  Results are identical to
+ * cflr_solve of the same input.  A request whose footprint alone exceeds the
+ * budget fails with ENOMEM.  Besides the budget the server holds the sort's
+ * bucket counters: 8 bytes per bucket, budget / 16 buckets (at most 2^29).
  * The server uses ctx's device and stream; do not use ctx from another
  * thread while the server lives. */
 cflr_status cflr_server_create(cflr_ctx *ctx, uint64_t hbm_budget_bytes, uint32_t max_slots,

@@ -3,9 +3,11 @@
 // The fixpoint of Algorithm 1 in its semi-naive form (Section 3, opt. 1):
 //   seed      edges and eps rules set the first pairs; they are the first
 //             round's new pairs (M_old = empty);
-//   round     prep (work table) -> product (all productions, both parts,
-//             every admitted instance in one launch) -> sort of the appended
-//             new pairs into row and column order (next round's dA, dB);
+//   round     sort of the appended new pairs by (key tile, partner) into
+//             row and column order (this round's dA, dB) -> prep (work
+//             table) -> product (every production and admitted instance;
+//             one launch for the row parts, then one for the column parts)
+//             -> fold of the new-pair counts;
 //   converge  an instance whose round derived no pair is done (its new-pair
 //             set is empty, so no later round can derive anything for it).
 // If the new-pair buffer overflows, the product leaves the overflowing

@@ -156,8 +156,8 @@ uint64_t instance_buckets(const Lowered &low, uint32_t n);
 
 std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const cflr_graph *g);
 
-// A set of instances advancing round by round together (one fused product
-// launch per round over all of them).
+// A set of instances advancing round by round together (the product
+// launches of a round cover all of them).
 class Run {
    public:
     // bucket_capacity: sort buckets for all instances admitted at once

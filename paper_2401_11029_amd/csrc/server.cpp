@@ -174,7 +174,6 @@ cflr_status cflr_server_create(cflr_ctx *ctx, uint64_t hbm_budget_bytes, uint32_
         if (opts) s->opts = *opts;
         s->budget = hbm_budget_bytes;
         s->max_slots = max_slots;
-        // row space for every instance that can run at once
         // sort buckets: an instance needs at most 1/16 of its footprint in
         // buckets; capped at 2^29 (two 2 GiB counter arrays)
         uint64_t buckets = std::min<uint64_t>(1ull << 29, std::max<uint64_t>(1ull << 20, hbm_budget_bytes / 16));
