@@ -406,17 +406,15 @@ void Run::rebuild_tables() {
             for (auto &b : ip->low.binary) he.push_back(EntryDev{ip->slot, b.c, b.a, b.b, part});
     nent_ = (uint32_t)he.size();
     // units: (entry, key tile); those of part 0 come first
-    std::vector<uint32_t> hue, hut;
+    std::vector<UnitDev> hu;
     unit_split_ = 0;
     for (uint32_t e = 0; e < nent_; e++) {
-        const uint32_t nt = key_tiles(hi[he[e].inst].n);
-        for (uint32_t t = 0; t < nt; t++) {
-            hue.push_back(e);
-            hut.push_back(t);
-        }
-        if (he[e].part == 0) unit_split_ = (uint32_t)hue.size();
+        const InstDev &I = hi[he[e].inst];
+        const uint32_t nt = key_tiles(I.n);
+        for (uint32_t t = 0; t < nt; t++) hu.push_back(UnitDev{he[e], t, 0, 0, I});
+        if (he[e].part == 0) unit_split_ = (uint32_t)hu.size();
     }
-    nunit_ = (uint32_t)hue.size();
+    nunit_ = (uint32_t)hu.size();
     std::vector<uint32_t> active(max_inst_, 0);
     for (auto &ip : insts_) active[ip->slot] = 1;
     copy_sync(d_active_.ptr, active.data(), active.size() * 4, hipMemcpyHostToDevice, s_);
@@ -424,15 +422,9 @@ void Run::rebuild_tables() {
     d_inst_ = DevBuf(pool, hi.size() * sizeof(InstDev));
     d_mats_ = DevBuf(pool, std::max<size_t>(1, hm.size()) * sizeof(MatDev));
     d_ent_ = DevBuf(pool, std::max<size_t>(1, he.size()) * sizeof(EntryDev));
-    d_unit_ent_ = DevBuf(pool, std::max<size_t>(1, hue.size()) * 4);
-    d_unit_tile_ = DevBuf(pool, std::max<size_t>(1, hue.size()) * 4);
-    d_unit_start_ = DevBuf(pool, std::max<size_t>(1, hue.size()) * 4);
-    d_unit_cnt_ = DevBuf(pool, std::max<size_t>(1, hue.size()) * 4);
-    d_prefix_ = DevBuf(pool, (hue.size() + 1) * 8);
-    if (!hue.empty()) {
-        copy_sync(d_unit_ent_.ptr, hue.data(), hue.size() * 4, hipMemcpyHostToDevice, s_);
-        copy_sync(d_unit_tile_.ptr, hut.data(), hut.size() * 4, hipMemcpyHostToDevice, s_);
-    }
+    d_units_ = DevBuf(pool, std::max<size_t>(1, hu.size()) * sizeof(UnitDev));
+    d_prefix_ = DevBuf(pool, (hu.size() + 1) * 8);
+    if (!hu.empty()) copy_sync(d_units_.ptr, hu.data(), hu.size() * sizeof(UnitDev), hipMemcpyHostToDevice, s_);
     copy_sync(d_inst_.ptr, hi.data(), hi.size() * sizeof(InstDev), hipMemcpyHostToDevice, s_);
     if (!hm.empty())
         copy_sync(d_mats_.ptr, hm.data(), hm.size() * sizeof(MatDev), hipMemcpyHostToDevice, s_);
@@ -512,15 +504,10 @@ void Run::enqueue_product(bool timed) {
     uint32_t *halt = reinterpret_cast<uint32_t *>(counters + 3);
     if (!nunit_) return;
     PrepArgs P{};
-    P.inst = d_inst_.as<InstDev>();
-    P.ent = d_ent_.as<EntryDev>();
-    P.unit_ent = d_unit_ent_.as<uint32_t>();
-    P.unit_tile = d_unit_tile_.as<uint32_t>();
+    P.units = d_units_.as<UnitDev>();
     P.nunit = nunit_;
     P.rptr = d_rcnt_.as<uint32_t>();
     P.cptr = d_ccnt_.as<uint32_t>();
-    P.unit_start = d_unit_start_.as<uint32_t>();
-    P.unit_cnt = d_unit_cnt_.as<uint32_t>();
     P.item_prefix = d_prefix_.as<uint64_t>();
     P.work_counter0 = counters + 1;
     P.work_counter1 = counters + 4;
@@ -529,13 +516,8 @@ void Run::enqueue_product(bool timed) {
     if (opts_.count_traffic && touched_bits_)
         hip_check(launch_fill_u32(d_touched_.as<uint32_t>(), (touched_bits_ + 31) / 32, 0, s_), "fill");
     ProductArgs A{};
-    A.inst = d_inst_.as<InstDev>();
     A.mats = d_mats_.as<MatDev>();
-    A.ent = d_ent_.as<EntryDev>();
-    A.unit_ent = d_unit_ent_.as<uint32_t>();
-    A.unit_tile = d_unit_tile_.as<uint32_t>();
-    A.unit_start = d_unit_start_.as<uint32_t>();
-    A.unit_cnt = d_unit_cnt_.as<uint32_t>();
+    A.units = d_units_.as<UnitDev>();
     A.item_prefix = d_prefix_.as<uint64_t>();
     A.rs = d_rs_.as<uint64_t>();
     A.cs = d_cs_.as<uint64_t>();

@@ -209,7 +209,7 @@ class Run {
     std::map<uint64_t, uint64_t> free_buckets_;  // base -> length
     // device tables
     DevBuf d_inst_, d_mats_, d_ent_, d_prefix_;
-    DevBuf d_unit_ent_, d_unit_tile_, d_unit_start_, d_unit_cnt_;
+    DevBuf d_units_;
     uint32_t nent_ = 0, nunit_ = 0, unit_split_ = 0;  // units [0, unit_split_) are row parts
     DevBuf d_rcnt_, d_ccnt_, d_bsum_;
     DevBuf d_ap_key_, d_ap_i_, d_ap_j_, d_rs_, d_cs_;

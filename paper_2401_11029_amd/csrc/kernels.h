@@ -73,16 +73,20 @@ struct EntryDev {
 };
 
 
+// A unit of product work: one key tile of one (instance, production, part),
+// with everything a work item needs, so that it is read in one round trip.
+struct UnitDev {
+    EntryDev e;
+    uint32_t tile;
+    uint32_t start, cnt;  // its new pairs in the sorted order (set by the prep each round)
+    InstDev I;
+};
+
 // ------------------------------------------------------------ kernel arguments
 
 struct ProductArgs {
-    const InstDev *inst;
     const MatDev *mats;
-    const EntryDev *ent;
-    // units: (entry, key tile); their pairs and items are set by the prep
-    const uint32_t *unit_ent, *unit_tile;
-    const uint32_t *unit_start;   // first new pair of the unit
-    const uint32_t *unit_cnt;     // number of new pairs of the unit
+    const UnitDev *units;
     const uint64_t *item_prefix;  // exclusive prefix of items per unit; [nunit] = total
     uint32_t unit_lo, unit_hi;    // units of this launch (all of one part)
     const uint64_t *rs;           // new pairs (i, k) in (i tile, k) order, packed (i << 32) | k
@@ -101,12 +105,9 @@ struct ProductArgs {
 };
 
 struct PrepArgs {
-    const InstDev *inst;
-    const EntryDev *ent;
-    const uint32_t *unit_ent, *unit_tile;
+    UnitDev *units;
     uint32_t nunit;
     const uint32_t *rptr, *cptr;  // bucket starts of the two sort orders
-    uint32_t *unit_start, *unit_cnt;
     uint64_t *item_prefix;
     unsigned long long *work_counter0, *work_counter1;  // reset for the two launches
     const uint32_t *halt;

@@ -219,6 +219,7 @@ struct ProductShared {
     unsigned long long nzr[2][kMaskWords];              // runs whose partner segment is non-zero
     uint32_t stage_len;                                 // pairs taken by the stage being planned (when cut)
     unsigned long long item;                            // the workgroup's current item
+    uint32_t unit;                                      // and its unit
 };
 
 struct StagePlan {
@@ -490,40 +491,53 @@ template <bool STATS>
 __global__ __launch_bounds__(kProdWaves * kWave) void product_kernel(ProductArgs A) {
     __shared__ ProductShared sh;
     const uint32_t tid = threadIdx.x;
+    const uint32_t lane = lane_id(), wave = tid / kWave;
     const uint64_t first = A.item_prefix[A.unit_lo], total = A.item_prefix[A.unit_hi];
     SlotChunk ch;
     if (tid < kTileKeys)
         for (uint32_t w = 0; w < kMaskWords; w++) sh.mask[0][w][tid] = sh.mask[1][w][tid] = 0;
+    // items are taken from a counter, one atomic per workgroup and item; the
+    // next one is requested when an item starts, so its round trip overlaps
+    // the work.  After an overflow the round is re-run: stop early.
+    unsigned long long nxt = 0;
+    if (tid == 0) nxt = first + atomicAdd(A.work_counter, 1ull);
     while (true) {
-        // items are taken from a counter, one atomic per workgroup and item;
-        // after an overflow the round is re-run: stop early
         if (tid == 0) {
-            unsigned long long it = first + atomicAdd(A.work_counter, 1ull);
+            unsigned long long it = nxt;
             if (__hip_atomic_load(A.halt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) it = total;
             sh.item = it;
+            if (it < total) nxt = first + atomicAdd(A.work_counter, 1ull);
         }
         __syncthreads();
-        const uint64_t item = sh.item;
-        __syncthreads();  // every thread has read the item before thread 0 takes the next
+        const uint64_t item = first_lane64(sh.item);  // uniform: kept in scalar registers
         if (item >= total) break;
-        uint32_t lo = A.unit_lo, hi = A.unit_hi;  // item_prefix[lo] <= item < item_prefix[hi]
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (A.item_prefix[mid] <= item) lo = mid;
-            else hi = mid;
+        if (wave == 0) {
+            // the unit holding the item, item_prefix[lo] <= item < item_prefix[hi]:
+            // a 64-way search, one round trip per factor of 64
+            uint32_t lo = A.unit_lo, hi = A.unit_hi;
+            while (hi - lo > 1) {
+                const uint32_t step = (hi - lo + kWave - 1) / kWave;
+                const uint32_t probe = lo + lane * step;
+                const bool ok = probe < hi && A.item_prefix[probe] <= item;
+                const uint64_t m = __ballot(ok);  // lane 0 (probe lo) is always set
+                lo += (63 - (uint32_t)__clzll((unsigned long long)m)) * step;
+                if (lo + step < hi) hi = lo + step;
+            }
+            if (lane == 0) sh.unit = lo;
         }
-        const EntryDev E = A.ent[A.unit_ent[lo]];
-        const InstDev I = A.inst[E.inst];
-        const uint64_t local = item - A.item_prefix[lo];
-        const uint32_t seg = (uint32_t)(local % I.S);
-        const uint64_t chunk = local / I.S;
-        const uint64_t start = A.unit_start[lo], end = start + A.unit_cnt[lo];
-        const uint64_t c0 = start + chunk * kChunkPairs;
+        __syncthreads();  // the unit is known; every thread has read the item
+        const uint32_t u = first_lane(sh.unit);
+        const UnitDev U = A.units[u];
+        const uint64_t local = item - A.item_prefix[u];
+        const uint32_t seg = (uint32_t)(local % U.I.S);
+        const uint64_t chunk = local / U.I.S;
+        const uint64_t end = (uint64_t)U.start + U.cnt;
+        const uint64_t c0 = U.start + chunk * kChunkPairs;
         const uint64_t c1 = c0 + kChunkPairs < end ? c0 + kChunkPairs : end;
-        if (E.part == 0)
-            product_tile<false, STATS>(A, sh, ch, E, I, A.unit_tile[lo], (uint32_t)c0, (uint32_t)c1, seg);
+        if (U.e.part == 0)
+            product_tile<false, STATS>(A, sh, ch, U.e, U.I, U.tile, (uint32_t)c0, (uint32_t)c1, seg);
         else
-            product_tile<true, STATS>(A, sh, ch, E, I, A.unit_tile[lo], (uint32_t)c0, (uint32_t)c1, seg);
+            product_tile<true, STATS>(A, sh, ch, U.e, U.I, U.tile, (uint32_t)c0, (uint32_t)c1, seg);
     }
     retire_chunk(A, ch);
     if (STATS && lane_id() == 0 && ch.bytes) atomicAdd(A.algo_bytes, (unsigned long long)ch.bytes);
@@ -548,15 +562,14 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs A) {
         const uint32_t u = base + t;
         uint64_t items = 0;
         if (u < A.nunit && !*A.halt) {
-            const EntryDev E = A.ent[A.unit_ent[u]];
-            const InstDev I = A.inst[E.inst];
-            const uint32_t mat = E.part == 0 ? E.a : E.b;
-            const uint32_t *ptr = E.part == 0 ? A.rptr : A.cptr;
-            const uint64_t b0 = I.bbase + ((uint64_t)mat * key_tiles(I.n) + A.unit_tile[u]) * I.n;
-            const uint32_t s = ptr[b0], f = ptr[b0 + I.n];
-            A.unit_start[u] = s;
-            A.unit_cnt[u] = f - s;
-            items = ((uint64_t)(f - s) + kChunkPairs - 1) / kChunkPairs * I.S;
+            UnitDev &U = A.units[u];
+            const uint32_t mat = U.e.part == 0 ? U.e.a : U.e.b;
+            const uint32_t *ptr = U.e.part == 0 ? A.rptr : A.cptr;
+            const uint64_t b0 = U.I.bbase + ((uint64_t)mat * key_tiles(U.I.n) + U.tile) * U.I.n;
+            const uint32_t s = ptr[b0], f = ptr[b0 + U.I.n];
+            U.start = s;
+            U.cnt = f - s;
+            items = ((uint64_t)(f - s) + kChunkPairs - 1) / kChunkPairs * U.I.S;
         }
         part[t] = items;
         __syncthreads();
