@@ -22,7 +22,10 @@ The JSON line also carries:
 --mode batch reports the batched form (256 alias graphs in one call vs one
 plain solve after another); --mode serve reports the served form (Poisson
 arrivals of mixed queries, solves/s and p50/p99 latency against a
-one-at-a-time plain path).  Neither is the default line.
+one-at-a-time plain path); --mode grammars times the paper's hand-normalised
+grammars against the automatically normalised ones on the same graphs
+(Fig. 5b vs 5a on the alias graph, Fig. 4b vs 4a on a points-to graph).
+None of them is the default line.
 """
 
 from __future__ import annotations
@@ -64,6 +67,17 @@ def measured_traffic():
     return p.get("hbm_bytes_per_launch")
 
 
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def cpu_baseline():
     """The oracle, as it is, on the same generator at 6,000 vertices."""
     import oracle
@@ -75,7 +89,8 @@ def cpu_baseline():
     return {"value": derived / r.seconds, "unit": "pairs/s", "cores": 1,
             "kind": "oracle",
             "sample": f"alias generator at n={n} (seed 1), one full solve: "
-                      f"{derived} derived pairs in {r.seconds:.1f} s on one host thread"}
+                      f"{derived} derived pairs in {r.seconds:.1f} s on one host thread "
+                      f"({host_cpu()}, {os.cpu_count()} logical CPUs visible)"}
 
 
 def seeded_user_pairs(text, g):
@@ -129,6 +144,9 @@ def single(args):
     # only ever hold seeded edges), so new_pairs is the derived-pair count
     derived = sum(s["new_pairs"] for s in stats)
     value = derived / secs
+    fix = sorted(s["fixpoint_ms"] for s in stats)
+    fix_mean = sum(fix) / len(fix)
+    fix_std = (sum((x - fix_mean) ** 2 for x in fix) / max(1, len(fix) - 1)) ** 0.5
     launches = sum(s["product_launches"] for s in stats)
     prod_ms = sum(s["product_ms"] for s in stats)
     avg_launch_s = prod_ms / 1e3 / max(1, launches)
@@ -153,10 +171,13 @@ def single(args):
                    "vertices": g.n, "edges": g.m,
                    "pairs": stats[-1]["total_pairs"],
                    "rounds": stats[-1]["rounds"],
-                   "fixpoint_ms": stats[-1]["fixpoint_ms"]},
+                   "fixpoint_ms_mean": fix_mean,
+                   "fixpoint_ms_median": fix[len(fix) // 2],
+                   "fixpoint_ms_std": fix_std},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
+                     "amplification": (traffic / bytes_per_launch) if traffic and bytes_per_launch else None,
                      "kernel": "product_kernel",
                      "algo_bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": avg_launch_s * 1e3},
@@ -321,12 +342,59 @@ def serve(args):
           flush=True)
 
 
+def grammars_mode(args):
+    """The paper's hand-normalised grammars (opt. 5) against the automatically
+    normalised ones, on the same graph: the alias pair (Fig. 5a, 5b) on the
+    50,000-vertex alias graph, the points-to pair (Fig. 4a, 4b at 64 fields)
+    on a 12,000-vertex points-to graph.  Both grammars of a pair define the
+    same relation on the shared non-terminals, checked here by pair counts."""
+    import torch
+    import paper_2401_11029_amd as cflr
+    import workloads
+    from workloads import grammars as G, graphs
+    ctx = cflr.Context(0)
+    cases = [("alias", workloads.config("alias_50k")[1], "M",
+              [("Fig. 5a (automatic WCNF)", G.ALIAS_FIG5A_WCNF), ("Fig. 5b (by hand)", G.ALIAS_FIG5B)]),
+             ("pointsto", graphs.pointsto_graph(12000, seed=2), "PT",
+              [("Fig. 4a (automatic WCNF)", G.pointsto_fig4a(64)), ("Fig. 4b (by hand)", G.pointsto_fig4b(64))])]
+    rows = []
+    for name, g, shared, variants in cases:
+        graph = cflr.Graph.from_workload(ctx, g)
+        counts = {}
+        for label, text in variants:
+            gr = cflr.Grammar(text)
+            info = gr.info()
+            r = cflr.solve(ctx, gr, graph)  # warm-up
+            r.close()
+            ms = []
+            for k in range(max(1, args.steps)):
+                r = cflr.solve(ctx, gr, graph)
+                st = r.stats()
+                ms.append(st["fixpoint_ms"])
+                counts[label] = r.count(shared)
+                r.close()
+            torch.cuda.synchronize()
+            ms.sort()
+            log(f"{name} {label}: median {ms[len(ms) // 2]:.1f} ms, {st['rounds']} rounds, "
+                f"{info['matrices']} matrices, {counts[label]} {shared} pairs")
+            rows.append({"graph": name, "vertices": g.n, "edges": g.m, "grammar": label,
+                         "matrices": info["matrices"], "binary": info["binary"],
+                         "fixpoint_ms_median": ms[len(ms) // 2], "rounds": st["rounds"],
+                         "pairs": st["total_pairs"], "shared_nt": shared,
+                         "shared_nt_pairs": counts[label]})
+        rows[-1]["same_shared_pairs"] = len(set(counts.values())) == 1
+        rows[-2]["same_shared_pairs"] = rows[-1]["same_shared_pairs"]
+    print(json.dumps({"metric": "fixpoint ms, hand vs automatic WCNF", "unit": "ms",
+                      "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                      "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"])
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "grammars"])
     ap.add_argument("--serve-per-grammar", type=int, default=30)
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[0.5, 1.0, 2.0, 4.0, 8.0])
     ap.add_argument("--no-cpu", action="store_true")
@@ -344,6 +412,8 @@ def main():
         single(args)
     elif args.mode == "batch":
         batch(args)
+    elif args.mode == "grammars":
+        grammars_mode(args)
     else:
         serve(args)
     if args.copy_calibration:
