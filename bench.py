@@ -343,20 +343,25 @@ def serve(args):
 
 
 def grammars_mode(args):
-    """The paper's hand-normalised grammars (opt. 5) against the automatically
-    normalised ones, on the same graph: the alias pair (Fig. 5a, 5b) on the
-    50,000-vertex alias graph, the points-to pair (Fig. 4a, 4b at 64 fields)
-    on a 12,000-vertex points-to graph.  Both grammars of a pair define the
-    same relation on the shared non-terminals, checked here by pair counts."""
+    """The paper's hand-normalised grammars (opt. 5) against the CFPQ Data
+    grammars normalised automatically, on the same graph: Fig. 5a as given
+    (the library binarises it), Fig. 5a binarised in the text, and Fig. 5b on
+    the 50,000-vertex alias graph; the same three forms of Fig. 4a/4b at 64
+    fields on a 12,000-vertex points-to graph.  All forms define the same
+    relation on the shared non-terminal, checked here by pair counts."""
     import torch
     import paper_2401_11029_amd as cflr
     import workloads
     from workloads import grammars as G, graphs
     ctx = cflr.Context(0)
     cases = [("alias", workloads.config("alias_50k")[1], "M",
-              [("Fig. 5a (automatic WCNF)", G.ALIAS_FIG5A_WCNF), ("Fig. 5b (by hand)", G.ALIAS_FIG5B)]),
+              [("Fig. 5a as given, normalised by the library", G.ALIAS_FIG5A),
+               ("Fig. 5a binarised (helpers Y1..Y4)", G.ALIAS_FIG5A_WCNF),
+               ("Fig. 5b (WCNF by hand)", G.ALIAS_FIG5B)]),
              ("pointsto", graphs.pointsto_graph(12000, seed=2), "PT",
-              [("Fig. 4a (automatic WCNF)", G.pointsto_fig4a(64)), ("Fig. 4b (by hand)", G.pointsto_fig4b(64))])]
+              [("Fig. 4a as given, normalised by the library", G.pointsto_fig4a_cfg(64)),
+               ("Fig. 4a binarised", G.pointsto_fig4a(64)),
+               ("Fig. 4b (WCNF by hand)", G.pointsto_fig4b(64))])]
     rows = []
     for name, g, shared, variants in cases:
         graph = cflr.Graph.from_workload(ctx, g)
@@ -382,8 +387,8 @@ def grammars_mode(args):
                          "fixpoint_ms_median": ms[len(ms) // 2], "rounds": st["rounds"],
                          "pairs": st["total_pairs"], "shared_nt": shared,
                          "shared_nt_pairs": counts[label]})
-        rows[-1]["same_shared_pairs"] = len(set(counts.values())) == 1
-        rows[-2]["same_shared_pairs"] = rows[-1]["same_shared_pairs"]
+        for row in rows[-len(variants):]:
+            row["same_shared_pairs"] = len(set(counts.values())) == 1
     print(json.dumps({"metric": "fixpoint ms, hand vs automatic WCNF", "unit": "ms",
                       "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
                       "rows": rows}), flush=True)

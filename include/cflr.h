@@ -120,13 +120,16 @@ cflr_status cflr_ctx_mem_info(cflr_ctx *ctx, uint64_t *free_bytes, uint64_t *tot
 
 /* ---- grammar (host only; needs no device) -----------------------------
  * Text format: one production per line, "LHS -> ALT | ALT ...", where ALT is
- * "eps", one symbol, or two symbols; "#" starts a comment.  Left-hand sides
- * are the non-terminals; every other symbol is a terminal (edge label).  This
- * is weak Chomsky normal form (Definition 1) relaxed as the paper's appendix
- * figures use it: terminals may appear in binary right-hand sides and unit
- * rules x -> y are allowed; the library lowers both (a terminal t in a binary
- * position becomes a wrapper non-terminal with T_t -> t; unit rules are
- * removed by copying the productions of every non-terminal they reach).
+ * "eps" or a sequence of one or more symbols; "#" starts a comment.
+ * Left-hand sides are the non-terminals; every other symbol is a terminal
+ * (edge label).  Weak Chomsky normal form (Definition 1) is the case of
+ * right sides of at most two non-terminals; the library normalises the rest
+ * as the paper does for its CFPQ Data grammars (Figs. 4a-7a): a right side
+ * y1 ... yk with k >= 3 becomes y1 H with hidden helper matrices for its
+ * suffixes (shared between rules), a terminal t in a longer right side
+ * becomes a wrapper non-terminal with T_t -> t, and unit rules x -> y are
+ * removed by copying the productions of every non-terminal they reach.
+ * Only the non-terminals of the text are results.
  * len: bytes of text (need not be NUL-terminated).
  * Errors: EINVAL (null), EPARSE (message names the line). */
 cflr_status cflr_grammar_parse(const char *text, size_t len, cflr_grammar **out);
@@ -140,11 +143,12 @@ const char *cflr_grammar_nonterminal_name(const cflr_grammar *g, uint32_t nt);
 typedef struct cflr_grammar_info {
     uint32_t user_nonterminals;  /* non-terminals of the text */
     uint32_t wrappers;           /* T_t helpers for terminals in binary slots */
-    uint32_t matrices;           /* user_nonterminals + wrappers */
+    uint32_t matrices;           /* user_nonterminals + wrappers + helpers */
     uint32_t binary;             /* binary productions after lowering */
     uint32_t terminal_rules;     /* x -> t after lowering */
     uint32_t eps_rules;          /* x -> eps after lowering */
     uint32_t terminals;          /* distinct terminal names */
+    uint32_t helpers;            /* matrices for suffixes of right sides longer than two */
 } cflr_grammar_info;
 cflr_status cflr_grammar_info_get(const cflr_grammar *g, cflr_grammar_info *out);
 

@@ -24,12 +24,14 @@ class _Cyk:
         self.g = g
         self.null = frozenset(g.nullable())
         self.unit = g.unit
-        self.binary = g.binary
+        self.seqs = g.sequences()
 
-    def _close(self, cell, left_cells, right_cells):
-        # cell: symbols deriving w[s:e]; left_cells[m] = T[s][m],
-        # right_cells[m] = T[m][e] for s <= m <= e (m = e / m = s included:
-        # those are empty spans or the cell itself).
+    def _close(self, cell, span, s, e):
+        # cell: symbols deriving w[s:e]; span(a, b) = T[a][b] for
+        # s <= a <= b <= e (span(s, e) is the cell itself).  x -> y1 ... yk
+        # holds when split points s = m0 <= m1 <= ... <= mk = e exist with
+        # yq in T[m(q-1)][mq]: the set of reachable m is carried symbol by
+        # symbol.
         changed = True
         while changed:
             changed = False
@@ -37,14 +39,17 @@ class _Cyk:
                 if y in cell and x not in cell:
                     cell.add(x)
                     changed = True
-            for x, y, z in self.binary:
+            for x, ys in self.seqs:
                 if x in cell:
                     continue
-                for lc, rc in zip(left_cells, right_cells):
-                    if y in lc and z in rc:
-                        cell.add(x)
-                        changed = True
+                reach = {s}
+                for y in ys:
+                    reach = {b for a in reach for b in range(a, e + 1) if y in span(a, b)}
+                    if not reach:
                         break
+                if e in reach:
+                    cell.add(x)
+                    changed = True
         return cell
 
     def extend(self, cols, terminal):
@@ -54,14 +59,14 @@ class _Cyk:
         col[e] = set(self.null)  # empty span T[e][e]
         for s in range(e - 1, -1, -1):
             cell = {terminal} if s == e - 1 else set()
-            # split points m in [s, e]: T[s][m] (earlier columns or the cell)
-            # and T[m][e] (this column, computed for m > s already).
-            left = []
-            right = []
-            for m in range(s, e + 1):
-                left.append(cols[m][s] if m < e else cell)
-                right.append(col[m] if m > s else cell)
-            col[s] = self._close(cell, left, right)
+
+            # T[a][b]: earlier columns for b < e, this column (computed for
+            # a > s already) for b = e, the cell for (s, e)
+            def span(a, b, cell=cell, s=s):
+                if b < e:
+                    return cols[b][a]
+                return cell if a == s else col[a]
+            col[s] = self._close(cell, span, s, e)
         return col
 
 

@@ -47,6 +47,8 @@ def check_certificate(grammar_text: str, graph, cert_path: str):
     """Verify soundness of the certificate; returns {nt: set of pairs} of
     the certified facts.  Raises AssertionError on any defect."""
     g = TextGrammar(grammar_text)
+    if g.long:
+        raise ValueError("certificates are checked for grammars with right sides of at most two symbols")
     names, is_nt, rules, facts = read_certificate(cert_path)
     # every rule the solver used must be a rule of the grammar text
     allowed = {("eps", x, None, None) for x in g.eps}

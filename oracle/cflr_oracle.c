@@ -14,8 +14,13 @@
  * the empty path included (so (i, i) is in R_x for every vertex i when x
  * derives the empty word).  The grammar is in weak Chomsky normal form
  * (Definition 1) relaxed as in the paper's appendix figures: a binary
- * right-hand side may hold terminals, and a right-hand side may be a single
- * symbol (terminal or non-terminal).
+ * right-hand side may hold terminals, a right-hand side may be a single
+ * symbol (terminal or non-terminal), and a right-hand side may be longer
+ * than two symbols (the CFPQ Data grammars, Figs. 4a-7a).  A long rule
+ * x -> y1 y2 ... yk is read as a chain of prefixes: an internal symbol for
+ * y1 y2, one for (y1 y2) y3, and so on, with x -> (y1 ... y(k-1)) yk, so a
+ * fact of a prefix symbol says that a path spells a word of the prefix.
+ * The internal symbols are never printed.
  *
  * How: the least set of facts (s, i, j) closed under the grammar, computed by
  * a worklist.  Terminal facts are the graph's edges.  Every fact is popped
@@ -78,7 +83,8 @@ enum { R_EPS = 0, R_UNIT = 1, R_BIN = 2, R_EDGE = 3 };
 typedef struct { uint32_t kind, lhs, r1, r2; } rule_t;
 
 static char **sym_name;      /* symbol id -> name */
-static int *sym_is_nt;       /* 1 if the symbol is some rule's left side */
+static int *sym_is_nt;       /* 1 if the symbol is some rule's left side,
+                                2 for an internal prefix of a long rule */
 static uint32_t nsym;
 static rule_t *rules;
 static uint32_t nrules;
@@ -139,25 +145,33 @@ static void parse_grammar(const char *path) {
             char *save_alt = NULL;
             for (char *alt = strtok_r(arrow + 2, "|", &save_alt); alt;
                  alt = strtok_r(NULL, "|", &save_alt)) {
-                char *tok[3];
+                char *tok[256];
                 int nt = 0;
                 char *save_tok = NULL;
                 for (char *t = strtok_r(alt, " \t\r", &save_tok); t;
                      t = strtok_r(NULL, " \t\r", &save_tok)) {
-                    if (nt == 3) die("right side longer than two symbols", lhs);
+                    if (nt == 256) die("right side longer than 256 symbols", lhs);
                     tok[nt++] = t;
                 }
-                if (nt == 0 || nt == 3) die("bad right side", lhs);
+                if (nt == 0) die("bad right side", lhs);
                 if (nt == 1 && strcmp(tok[0], "eps") == 0) {
                     add_rule(R_EPS, x, 0, 0);
                 } else if (nt == 1) {
                     add_rule(R_UNIT, x, sym_lookup(tok[0], 1), 0);
                 } else {
-                    if (!strcmp(tok[0], "eps") || !strcmp(tok[1], "eps"))
-                        die("eps inside a binary right side", lhs);
-                    uint32_t a = sym_lookup(tok[0], 1);
-                    uint32_t b = sym_lookup(tok[1], 1);
-                    add_rule(R_BIN, x, a, b);
+                    for (int q = 0; q < nt; q++)
+                        if (!strcmp(tok[q], "eps")) die("eps inside a longer right side", lhs);
+                    /* prefix chain: p1 = tok0 tok1, p(q) = p(q-1) tok(q), x = p(nt-2) tok(nt-1) */
+                    uint32_t left = sym_lookup(tok[0], 1);
+                    for (int q = 1; q < nt - 1; q++) {
+                        char name[64];
+                        snprintf(name, sizeof name, "prefix %u.%d", nrules, q);
+                        uint32_t p = sym_lookup(name, 1);
+                        sym_is_nt[p] = 2;
+                        add_rule(R_BIN, p, left, sym_lookup(tok[q], 1));
+                        left = p;
+                    }
+                    add_rule(R_BIN, x, left, sym_lookup(tok[nt - 1], 1));
                 }
             }
         }
@@ -510,7 +524,7 @@ int main(int argc, char **argv) {
     if (stats) printf("stats facts %llu seconds %.6f\n", (unsigned long long)total, secs);
     if (digest) {
         for (uint32_t s = 0; s < nsym; s++) {
-            if (!sym_is_nt[s]) continue;
+            if (sym_is_nt[s] != 1) continue;
             sha256_t c;
             sha_init(&c);
             for_pairs(s, sha_pair, &c);
@@ -523,10 +537,10 @@ int main(int argc, char **argv) {
         FILE *f = fopen(pairs_path, "wb");
         if (!f) die("cannot write", pairs_path);
         uint32_t k = 0;
-        for (uint32_t s = 0; s < nsym; s++) k += (uint32_t)sym_is_nt[s];
+        for (uint32_t s = 0; s < nsym; s++) k += (uint32_t)(sym_is_nt[s] == 1);
         fwrite(&k, 4, 1, f);
         for (uint32_t s = 0; s < nsym; s++) {
-            if (!sym_is_nt[s]) continue;
+            if (sym_is_nt[s] != 1) continue;
             uint32_t len = (uint32_t)strlen(sym_name[s]);
             fwrite(&len, 4, 1, f);
             fwrite(sym_name[s], 1, len, f);

@@ -21,6 +21,8 @@ from .textgrammar import TextGrammar
 
 def naive_closure(grammar_text: str, graph, max_iter: int = 100000):
     g = TextGrammar(grammar_text)
+    if g.long:
+        raise ValueError("Algorithm 1 works on WCNF: right sides of at most two symbols")
     n = graph.n
     adj = {t: np.zeros((n, n), dtype=bool) for t in g.terminals}
     for u, t, v in graph.edges():

@@ -47,7 +47,8 @@ class GrammarInfo(C.Structure):
                 ("binary", C.c_uint32),
                 ("terminal_rules", C.c_uint32),
                 ("eps_rules", C.c_uint32),
-                ("terminals", C.c_uint32)]
+                ("terminals", C.c_uint32),
+                ("helpers", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

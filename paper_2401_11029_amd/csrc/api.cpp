@@ -193,6 +193,7 @@ cflr_status cflr_grammar_info_get(const cflr_grammar *g, cflr_grammar_info *out)
         out->terminal_rules = (uint32_t)g->low.term.size();
         out->eps_rules = (uint32_t)g->low.eps.size();
         out->terminals = (uint32_t)g->low.terminals.size();
+        out->helpers = g->low.helpers;
         return CFLR_OK;
     });
 }

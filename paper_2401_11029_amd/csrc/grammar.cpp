@@ -2,9 +2,15 @@
 //
 // Definition 1 of the paper allows only x -> t, x -> eps and x -> y z with
 // y, z non-terminals; its appendix grammars (Figs. 4b-7b) also put terminals
-// in binary right-hand sides and use the unit rule V -> M (Fig. 6b).  Both
-// relaxations are removed here, on the host, before anything reaches the
-// device:
+// in binary right-hand sides and use the unit rule V -> M (Fig. 6b), and the
+// grammars taken from CFPQ Data (Figs. 4a-7a) have right-hand sides of three
+// or more symbols, which the paper normalises automatically for the matrix
+// algorithm.  All of it is removed here, on the host, before anything
+// reaches the device:
+//   * a right-hand side y1 y2 ... yk (k >= 3) becomes y1 H, where the helper
+//     matrix H stands for the suffix y2 ... yk (H -> y2 H' and so on, down to
+//     a pair); rules that share a suffix share its helper, so L(H) is the
+//     concatenation of the suffix's languages whatever rule uses it;
 //   * a terminal t in a binary position is replaced by a wrapper matrix T_t
 //     with the single production T_t -> t (its matrix is the adjacency of
 //     label t and never changes after seeding);
@@ -13,6 +19,7 @@
 //     and binary productions.  L(x) is unchanged.
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <set>
 #include <sstream>
 #include <tuple>
@@ -76,13 +83,11 @@ Lowered parse_and_lower(const char *text, size_t len) {
                 size_t bar = body.find('|', start);
                 auto alt = split_ws(body.substr(start, bar == std::string::npos ? std::string::npos : bar - start));
                 if (alt.empty()) throw Error(CFLR_EPARSE, "empty alternative (write eps)" + where);
-                if (alt.size() > 2)
-                    throw Error(CFLR_EPARSE, "right side longer than two symbols" + where);
                 for (auto &s : alt)
                     if (!valid_symbol(s)) throw Error(CFLR_EPARSE, "bad symbol '" + s + "'" + where);
                 if (alt.size() == 1 && alt[0] == "eps") alt.clear();
                 else if (std::find(alt.begin(), alt.end(), "eps") != alt.end())
-                    throw Error(CFLR_EPARSE, "eps inside a binary right side" + where);
+                    throw Error(CFLR_EPARSE, "eps inside a longer right side" + where);
                 raw.push_back({lhs[0], alt, lineno});
                 if (bar == std::string::npos) break;
                 start = bar + 1;
@@ -117,6 +122,27 @@ Lowered parse_and_lower(const char *text, size_t len) {
         return m;
     };
 
+    // helpers for suffixes of long right-hand sides: helper(s) has the
+    // production helper(s) -> op(s[0]) op(s[1..]) (a helper for the rest
+    // when it is longer than one symbol)
+    std::map<std::vector<std::string>, uint32_t> helper;
+    std::set<std::tuple<uint32_t, uint32_t, uint32_t>> helper_bins;
+    std::function<uint32_t(const std::vector<std::string> &)> suffix_matrix =
+        [&](const std::vector<std::string> &s) -> uint32_t {
+        auto it = helper.find(s);
+        if (it != helper.end()) return it->second;
+        const uint32_t a = operand(s[0]);
+        const std::vector<std::string> rest(s.begin() + 1, s.end());
+        const uint32_t b = rest.size() == 1 ? operand(rest[0]) : suffix_matrix(rest);
+        std::string name = "<";
+        for (size_t q = 0; q < s.size(); q++) name += (q ? " " : "") + s[q];
+        const uint32_t m = (uint32_t)L.mat_names.size();
+        L.mat_names.push_back(name + ">");
+        helper[s] = m;
+        helper_bins.insert({m, a, b});
+        return m;
+    };
+
     const uint32_t U = (uint32_t)nts.size();
     // per user non-terminal: its own non-unit productions
     std::vector<std::set<std::pair<uint32_t, uint32_t>>> own_bin(U);
@@ -130,9 +156,13 @@ Lowered parse_and_lower(const char *text, size_t len) {
         } else if (r.rhs.size() == 1) {
             if (is_nt(r.rhs[0])) unit[x].insert(nt_index[r.rhs[0]]);
             else own_term[x].insert(terminal(r.rhs[0]));
-        } else {
+        } else if (r.rhs.size() == 2) {
             uint32_t a = operand(r.rhs[0]);
             uint32_t b = operand(r.rhs[1]);
+            own_bin[x].insert({a, b});
+        } else {
+            uint32_t a = operand(r.rhs[0]);
+            uint32_t b = suffix_matrix(std::vector<std::string>(r.rhs.begin() + 1, r.rhs.end()));
             own_bin[x].insert({a, b});
         }
     }
@@ -157,11 +187,13 @@ Lowered parse_and_lower(const char *text, size_t len) {
         }
     }
     for (auto &w : wrapper) terms.insert({term_index[w.first], w.second});
+    for (auto &h : helper_bins) bins.insert(h);
 
     for (auto &b : bins) L.binary.push_back({std::get<0>(b), std::get<1>(b), std::get<2>(b)});
     for (auto &t : terms) L.term.push_back(t);
     L.eps.assign(epss.begin(), epss.end());
     L.wrappers = (uint32_t)wrapper.size();
+    L.helpers = (uint32_t)helper.size();
     const uint32_t M = L.nmat();
     L.dynamic.assign(M, 0);
     L.slot_a.assign(M, 0);

@@ -23,7 +23,8 @@ struct Error : std::runtime_error {
 // them come wrappers T_t for terminals that stood in binary positions.
 struct Lowered {
     std::vector<std::string> user_names;       // first-appearance order
-    std::vector<std::string> mat_names;        // user names, then "<t>" wrappers
+    std::vector<std::string> mat_names;        // user names, then "<t>" wrappers and
+                                               // "<y ... z>" suffix helpers
     std::vector<std::string> terminals;        // distinct terminal names
     struct Bin { uint32_t c, a, b; };
     std::vector<Bin> binary;                   // deduplicated
@@ -32,7 +33,7 @@ struct Lowered {
     // per matrix: receives pairs from binary productions / used in slot a
     // (needs the column-major copy) / used in slot b (row-major copy)
     std::vector<uint8_t> dynamic, slot_a, slot_b;
-    uint32_t wrappers = 0;
+    uint32_t wrappers = 0, helpers = 0;
     uint32_t nmat() const { return (uint32_t)mat_names.size(); }
 };
 

@@ -48,7 +48,20 @@ def test_lowering_dyck1(cflr_lib):
     nts, i = info(G.DYCK1)
     assert nts == ["S", "X", "A", "B"]
     assert i == dict(user_nonterminals=4, wrappers=0, matrices=4, binary=4,
-                     terminal_rules=2, eps_rules=1, terminals=2)
+                     terminal_rules=2, eps_rules=1, terminals=2, helpers=0)
+
+
+def test_lowering_long_right_sides(cflr_lib):
+    # Fig. 5a as given: M -> d_bar V d, V -> V1 V2 V3, V1 -> V2 a_bar V1 and
+    # V3 -> a V2 V3 need helpers for the suffixes "V d", "V2 V3" (shared by two
+    # rules) and "a_bar V1"; four wrappers; V2 -> M is removed by copying
+    nts, i = info(G.ALIAS_FIG5A)
+    assert nts == ["M", "V", "V1", "V2", "V3"]
+    assert i == dict(user_nonterminals=5, wrappers=4, matrices=12, binary=8,
+                     terminal_rules=4, eps_rules=4, terminals=4, helpers=3)
+    # a right side of four symbols: two helpers per distinct suffix chain
+    nts, i = info("S -> a S b S | eps")
+    assert nts == ["S"] and i["helpers"] == 2 and i["binary"] == 3 and i["wrappers"] == 2
 
 
 def test_lowering_alias_fig5a(cflr_lib):
@@ -80,7 +93,7 @@ def test_lowering_unit_cycle_and_chain(cflr_lib):
 
 
 @pytest.mark.parametrize("bad", [
-    "", "S", "S -> a b c", "S -> -> a", "S T -> a", "S -> a eps",
+    "", "S", "S -> a b eps c", "S -> -> a", "S T -> a", "S -> a eps",
     "S -> |", "eps -> a",
 ])
 def test_parse_errors(cflr_lib, bad):

@@ -4,7 +4,8 @@ Each pin is independent of the oracle's code: brute force over paths with
 CYK membership (exact on acyclic graphs), Algorithm 1 run as printed on dense
 matrices, closed forms (Dyck-1 on a path, transitive closure by BFS, a
 right-linear language by BFS on a product automaton), the paper's pairs of
-equivalent grammars (Figs. 4a/4b, 5a/5b, 6a/6b, 7a/7b), and a derivation
+equivalent grammars (Figs. 4a/4b, 5a/5b, 6a/6b, 7a/7b), the CFPQ Data forms
+with long right sides against their hand-binarised forms, and a derivation
 certificate plus closure check that pins the exact least fixpoint at any
 size.
 """
@@ -45,6 +46,20 @@ def grammar_cases(fields=2):
     }
 
 
+def long_cases(fields=2):
+    """Grammars with right sides of three or more symbols (the paper's CFPQ
+    Data forms, plus two textbook ones)."""
+    return {
+        "alias5a_long": (G.ALIAS_FIG5A, ["a", "d", "a_bar", "d_bar"]),
+        "pointsto4a_long": (G.pointsto_fig4a_cfg(fields),
+                            G.symbols_of(G.pointsto_fig4a_cfg(fields))[1]),
+        "valueflow7a_long": (G.cscvf_fig7a_cfg(fields), G.symbols_of(G.cscvf_fig7a_cfg(fields))[1]),
+        "fsca6a_long": (G.fsca_fig6a_cfg(fields), G.symbols_of(G.fsca_fig6a_cfg(fields))[1]),
+        "dyck_long": ("S -> a S b S | eps\n", ["a", "b"]),
+        "five_symbols": ("S -> a T b T c | d\nT -> S | eps\n", ["a", "b", "c", "d"]),
+    }
+
+
 def assert_same(oracle_res, expected, nts=None):
     for x in nts or oracle_res.order:
         got = oracle_res.pair_set(x)
@@ -58,6 +73,60 @@ def test_oracle_equals_brute_force_on_dags(name, oracle_bin):
         g = graphs.random_graph(6, 10, labels, seed=100 + seed, dag=True)
         exact = brute_force(text, g, max_len=g.n)   # every path of a DAG
         assert_same(oracle.solve(text, g), exact)
+
+
+@pytest.mark.parametrize("name", list(long_cases()))
+def test_oracle_equals_brute_force_on_dags_long_rules(name, oracle_bin):
+    text, labels = long_cases()[name]
+    for seed in range(6):
+        g = graphs.random_graph(7, 12, labels, seed=150 + seed, dag=True)
+        exact = brute_force(text, g, max_len=g.n)
+        assert_same(oracle.solve(text, g), exact)
+
+
+def balanced(word):
+    depth = 0
+    for t in word:
+        depth += 1 if t == "a" else -1
+        if depth < 0:
+            return False
+    return depth == 0
+
+
+def test_cyk_long_rules_closed_form():
+    # S -> a S b S | eps is the Dyck language: every word over {a, b} up to
+    # length 8 is in it exactly when it is balanced
+    import itertools
+    text = "S -> a S b S | eps\n"
+    for n in range(9):
+        for word in itertools.product("ab", repeat=n):
+            assert word_in(text, "S", list(word)) == balanced(word), word
+
+
+LONG_EQUIVALENT = [
+    ("alias 5a", G.ALIAS_FIG5A, G.ALIAS_FIG5A_WCNF, ["M", "V", "V1", "V2", "V3"],
+     lambda s: graphs.alias_graph(300, seed=s)),
+    ("points-to 4a", G.pointsto_fig4a_cfg(6), G.pointsto_fig4a(6), ["PT", "FT", "PTH", "FTH", "Al"],
+     lambda s: graphs.pointsto_graph(400, fields=6, seed=s)),
+    ("value-flow 7a", G.cscvf_fig7a_cfg(5), G.cscvf_fig7a(5), ["A"],
+     lambda s: graphs.valueflow_graph(300, calls=5, p_call=0.3, seed=s)),
+    ("fsca 6a", G.fsca_fig6a_cfg(3), G.fsca_fig6a(3), ["M", "V", "A", "Abar"],
+     lambda s: graphs.random_graph(40, 90, G.symbols_of(G.fsca_fig6b(3))[1], seed=s,
+                                   self_loops=True)),
+]
+
+
+@pytest.mark.parametrize("case", LONG_EQUIVALENT, ids=[c[0] for c in LONG_EQUIVALENT])
+def test_long_rules_equal_their_binarised_forms(case, oracle_bin):
+    # the same grammar with each long right side written out by hand as a
+    # chain of helpers (bracketed to the right) on cyclic graphs
+    _, long_text, bin_text, shared, make = case
+    for seed in range(3):
+        g = make(800 + seed)
+        r1, r2 = oracle.solve(long_text, g), oracle.solve(bin_text, g)
+        for x in shared:
+            assert r1.pair_set(x) == r2.pair_set(x), x
+        assert any(r1.count[x] for x in shared)
 
 
 @pytest.mark.parametrize("name", ["dyck1", "alias5a", "valueflow7b", "transitive"])
@@ -266,6 +335,10 @@ MUTANTS = {
                               "for (uint32_t i = 0; i < 1 && i < n_vert; i++) add_fact(rules[r].lhs, i, i, r, UINT32_MAX);"),
     "unit_rules_ignored": ("add_fact(rules[r].lhs, i, j, r, UINT32_MAX);\n        }",
                            "(void)r;\n        }"),
+    "long_rule_reversed": ("add_rule(R_BIN, p, left, sym_lookup(tok[q], 1));",
+                           "add_rule(R_BIN, p, sym_lookup(tok[q], 1), left);"),
+    "long_rule_last_dropped": ("add_rule(R_BIN, x, left, sym_lookup(tok[nt - 1], 1));",
+                               "add_rule(R_UNIT, x, left, 0);"),
 }
 
 
@@ -285,8 +358,10 @@ def test_planted_oracle_mistakes_are_caught(mutant, oracle_bin, monkeypatch):
     monkeypatch.setattr(oracle, "_ensure_built", lambda: None)
     caught = False
     try:
-        for name in ["dyck1", "alias5a", "alias5b", "fsca6b", "refl_trans"]:
-            text, labels = grammar_cases()[name]
+        cases = {**grammar_cases(), **long_cases()}
+        for name in ["dyck1", "alias5a", "alias5b", "fsca6b", "refl_trans", "dyck_long",
+                     "five_symbols"]:
+            text, labels = cases[name]
             for seed in range(3):
                 g = graphs.random_graph(6, 10, labels, seed=100 + seed, dag=True)
                 exact = brute_force(text, g, max_len=g.n)

@@ -4,8 +4,9 @@ Text format, shared by every consumer (each parses it with its own code):
 
 * one production per line, ``LHS -> RHS``; alternatives may be joined with
   ``|`` on one line;
-* ``RHS`` is ``eps`` (the empty word), one symbol, or two symbols separated by
-  whitespace;
+* ``RHS`` is ``eps`` (the empty word) or one or more symbols separated by
+  whitespace (right sides longer than two symbols are the CFPQ Data form of
+  Figs. 4a-7a; each consumer normalises them with its own code);
 * every symbol that appears as a left-hand side is a non-terminal, every other
   symbol is a terminal (an edge label);
 * ``#`` starts a comment.
@@ -58,6 +59,17 @@ ALIAS_FIG5A_WCNF = _join([
     "Y4 -> V2 V3",
 ])
 
+# Field-insensitive C/C++ memory alias, Fig. 5a as given (CFPQ Data form,
+# right sides of three symbols).
+ALIAS_FIG5A = _join([
+    "# memory alias (Fig. 5a)",
+    "M -> d_bar V d",
+    "V -> eps | V1 V2 V3",
+    "V1 -> eps | V2 a_bar V1",
+    "V2 -> eps | M",
+    "V3 -> eps | a V2 V3",
+])
+
 # Field-insensitive C/C++ memory alias, hand-made WCNF of Fig. 5b.
 ALIAS_FIG5B = _join([
     "# memory alias, hand WCNF (Fig. 5b)",
@@ -74,6 +86,14 @@ def cscvf_fig7a(fields: int) -> str:
     for i in range(fields):
         lines.append(f"A -> call_{i} C_{i}")
         lines.append(f"C_{i} -> A ret_{i}")
+    return _join(lines)
+
+
+# Context-sensitive value flow, Fig. 7a as given (call_i A ret_i).
+def cscvf_fig7a_cfg(fields: int) -> str:
+    lines = ["# value flow (Fig. 7a)", "A -> A A | a | eps"]
+    for i in range(fields):
+        lines.append(f"A -> call_{i} A ret_{i}")
     return _join(lines)
 
 
@@ -132,6 +152,25 @@ def pointsto_fig4a(fields: int) -> str:
     return _join(lines)
 
 
+# Field-sensitive Java points-to, Fig. 4a as given (right sides of up to
+# four symbols).
+def pointsto_fig4a_cfg(fields: int) -> str:
+    lines = [
+        f"# field-sensitive points-to (Fig. 4a), {fields} fields",
+        "PT -> PTH alloc",
+        "PTH -> eps | assign PTH",
+        "FT -> alloc_bar FTH",
+        "FTH -> eps | assign_bar FTH",
+        "Al -> PT FT",
+    ]
+    for i in range(fields):
+        lines += [
+            f"PTH -> load_{i} Al store_{i} PTH",
+            f"FTH -> store_bar_{i} Al load_bar_{i} FTH",
+        ]
+    return _join(lines)
+
+
 # Field-sensitive C/C++ alias, Fig. 6b (includes the unit rule V -> M).
 def fsca_fig6b(fields: int) -> str:
     lines = [
@@ -163,6 +202,21 @@ def fsca_fig6a(fields: int) -> str:
     for i in range(fields):
         lines.append(f"V -> f_bar_{i} Q_{i}")
         lines.append(f"Q_{i} -> V f_{i}")
+    return _join(lines)
+
+
+# Field-sensitive C/C++ alias, Fig. 6a as given, the optional "M?" expanded
+# into its two alternatives.
+def fsca_fig6a_cfg(fields: int) -> str:
+    lines = [
+        "# field-sensitive alias (Fig. 6a)",
+        "M -> d_bar V d",
+        "V -> Abar V A | M | eps",
+        "A -> a M | a | eps",
+        "Abar -> M a_bar | a_bar | eps",
+    ]
+    for i in range(fields):
+        lines.append(f"V -> f_bar_{i} V f_{i}")
     return _join(lines)
 
 
