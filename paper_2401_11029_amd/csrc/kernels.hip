@@ -208,283 +208,107 @@ __device__ __forceinline__ void flush(const ProductArgs &A, SlotChunk &ch, uint3
     }
 }
 
-// LDS of the product workgroup.  Stages are double-buffered: while the
-// accumulators take in stage s, stage s + 1 is planned and its partner
-// segments are on their way from memory.
+// LDS of the product workgroup: the accumulators of the tile's keys for the
+// item's row segment (kept all zero between items).
 struct ProductShared {
-    uint64_t stage[2][kStageRuns][kSegWords];           // partner segments of two stages
-    unsigned long long mask[2][kMaskWords][kTileKeys];  // per key: runs of the stage it pairs with
-    uint32_t run_k[kStageRuns];                         // partner of each run of the stage being planned
-    uint32_t wave_heads[kStageHalves][kProdWaves];      // runs starting among each wave's pairs
-    unsigned long long nzr[2][kMaskWords];              // runs whose partner segment is non-zero
-    uint32_t stage_len;                                 // pairs taken by the stage being planned (when cut)
-    unsigned long long item;                            // the workgroup's current item
-    uint32_t unit;                                      // and its unit
+    uint64_t acc[kTileKeys][kSegWords];
+    unsigned long long item;  // the workgroup's current item
+    uint32_t unit;            // and its unit
+    uint32_t next_window;     // windows of the item taken so far
 };
 
-struct StagePlan {
-    uint32_t len;  // pairs of the stage
-    uint32_t nst;  // runs (distinct partners) of the stage, <= kStageRuns
-};
-
-// Pairs pos + h * 1024 + tid of the sorted order (h < kStageHalves) and, for
-// lane 0 of a wave, the pair before each (its partner decides whether the
-// pair starts a run).
-struct PairFetch {
-    uint64_t pk[kStageHalves] = {}, prev[kStageHalves] = {};
-};
-
-__device__ __forceinline__ PairFetch fetch_pairs(const uint64_t *pairs, uint32_t pos, uint32_t p1) {
-    PairFetch f;
-#pragma unroll
-    for (uint32_t h = 0; h < kStageHalves; h++) {
-        const uint32_t t = h * kProdWaves * kWave + threadIdx.x;
-        const uint32_t x = pos + t;
-        if (x < p1) {
-            f.pk[h] = pairs[x];
-            if (lane_id() == 0 && t != 0) f.prev[h] = pairs[x - 1];
-        }
-    }
-    return f;
-}
-
-// Plan the stage starting at `pos`: runs of equal partners among the fetched
-// pairs, cut after kStageRuns runs; each key's mask gets a bit per run it
-// pairs with, and run_k the partner of each run.  Two barriers.
-template <bool STATS>
-__device__ __forceinline__ StagePlan plan_stage(ProductShared &sh, SlotChunk &ch, const PairFetch &f,
-                                                uint32_t pos, uint32_t p1, uint32_t key0, uint32_t buf,
-                                                bool count_pairs) {
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    bool valid[kStageHalves], head[kStageHalves];
-    uint64_t hb[kStageHalves];
-#pragma unroll
-    for (uint32_t h = 0; h < kStageHalves; h++) {
-        const uint32_t t = h * kProdWaves * kWave + tid;
-        valid[h] = pos + t < p1;
-        const uint32_t k = valid[h] ? (uint32_t)f.pk[h] : kHole;
-        uint32_t kprev = __shfl_up(k, 1, 64);
-        if (lane == 0) kprev = (t == 0 || !valid[h]) ? kHole : (uint32_t)f.prev[h];
-        head[h] = valid[h] && (t == 0 || k != kprev);
-        hb[h] = __ballot(head[h]);
-        if (lane == 0) sh.wave_heads[h][wave] = (uint32_t)__popcll(hb[h]);
-    }
-    __syncthreads();  // (1) heads counted
-    if (tid < kMaskWords) sh.nzr[buf][tid] = 0;
-    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
-    uint32_t runs = 0;
-#pragma unroll
-    for (uint32_t h = 0; h < kStageHalves; h++) {
-        uint32_t before = 0, total = 0;
-#pragma unroll
-        for (uint32_t w = 0; w < kProdWaves; w++) {
-            const uint32_t c = sh.wave_heads[h][w];
-            before += w < wave ? c : 0;
-            total += c;
-        }
-        // pairs of half h before the half's first head continue the last
-        // run of the half before
-        const uint32_t run = runs + before + (uint32_t)__popcll(hb[h] & upto) - 1;
-        const bool in_stage = valid[h] && run < kStageRuns;
-        if (head[h] && run == kStageRuns) sh.stage_len = h * kProdWaves * kWave + tid;
-        if (in_stage) {
-            const uint32_t kl = (uint32_t)(f.pk[h] >> 32) - key0;
-            if (kl < kTileKeys) atomicOr(&sh.mask[buf][run >> 6][kl], 1ull << (run & 63));
-            if (head[h]) sh.run_k[run] = (uint32_t)f.pk[h];
-        }
-        if (STATS && count_pairs) {
-            // the pair itself, read once per production
-            const uint64_t taken = __ballot(in_stage);
-            if (lane == 0) ch.bytes += 8ull * __popcll(taken);
-        }
-        runs += total;
-    }
-    __syncthreads();  // (2) masks, partners and the cut set
-    StagePlan p;
-    const uint32_t nvalid = p1 - pos < kStagePairs ? p1 - pos : kStagePairs;
-    p.len = runs > kStageRuns ? sh.stage_len : nvalid;
-    p.nst = runs < kStageRuns ? runs : kStageRuns;
-    return p;
-}
-
-// Partner segments of the planned stage come in kMaskWords batches of 64
-// runs; in batch j wave w takes runs 64 j + w + 16 q.  A segment that turns
-// out to be all zero is not staged.
-constexpr uint32_t kBatchRunsPerWave = 64 / kProdWaves;
-
-struct PartnerFetch {
-    uint64_t v[kBatchRunsPerWave];
-    uint32_t kk[kBatchRunsPerWave];
-};
-
-__device__ __forceinline__ void fetch_partners(PartnerFetch &pf, const ProductShared &sh, uint32_t nst,
-                                               uint32_t batch, global_u64 G, uint64_t Wp, uint32_t seg) {
-    const uint32_t wave = threadIdx.x / kWave, lane = lane_id();
-#pragma unroll
-    for (uint32_t q = 0; q < kBatchRunsPerWave; q++) {
-        const uint32_t r = 64 * batch + wave + kProdWaves * q;
-        pf.v[q] = 0;
-        pf.kk[q] = 0;
-        if (r < nst) {
-            const uint32_t kk = __builtin_amdgcn_readfirstlane(sh.run_k[r]);
-            pf.kk[q] = kk;
-            pf.v[q] = G[(uint64_t)kk * Wp + seg * kSegWords + lane];
-        }
-    }
-}
-
-template <bool COL, bool STATS>
-__device__ __forceinline__ void store_partners(const ProductArgs &A, ProductShared &sh, SlotChunk &ch,
-                                               const PartnerFetch &pf, uint32_t buf, uint32_t batch,
-                                               uint32_t inst, uint32_t pm, uint32_t seg, const InstDev &I) {
-    const uint32_t wave = threadIdx.x / kWave, lane = lane_id();
-    unsigned long long bits = 0;
-#pragma unroll
-    for (uint32_t q = 0; q < kBatchRunsPerWave; q++) {
-        const uint64_t live = __ballot(pf.v[q] != 0);
-        if (live) {
-            const uint32_t r = wave + kProdWaves * q;  // within the batch
-            sh.stage[buf][64 * batch + r][lane] = pf.v[q];
-            bits |= 1ull << r;
-            // compulsory bytes: the segment's non-zero words, at its first touch in the round
-            if (STATS && lane == 0 && first_touch<STATS>(A, inst, pm, COL ? 1 : 0, pf.kk[q], seg, I))
-                ch.bytes += 8ull * __popcll(live);
-        }
-    }
-    if (bits && lane == 0) atomicOr(&sh.nzr[buf][batch], bits);
-}
-
-// a |= the staged rows of runs m (a 64-run word of a mask)
-__device__ __forceinline__ void or_runs(uint64_t &a, unsigned long long m, const uint64_t (*st)[kSegWords],
-                                        uint32_t lane) {
-    while (m) {
-        const uint32_t c = (uint32_t)__popcll(m);
-        const uint32_t i0 = (uint32_t)__ffsll(m) - 1;
-        m &= m - 1;
-        if (c >= 4) {
-            const uint32_t i1 = (uint32_t)__ffsll(m) - 1;
-            m &= m - 1;
-            const uint32_t i2 = (uint32_t)__ffsll(m) - 1;
-            m &= m - 1;
-            const uint32_t i3 = (uint32_t)__ffsll(m) - 1;
-            m &= m - 1;
-            a |= (st[i0][lane] | st[i1][lane]) | (st[i2][lane] | st[i3][lane]);
-        } else if (c >= 2) {
-            const uint32_t i1 = (uint32_t)__ffsll(m) - 1;
-            m &= m - 1;
-            a |= st[i0][lane] | st[i1][lane];
-        } else {
-            a |= st[i0][lane];
-        }
-    }
-}
-
-// The wave's masks: lane w * kKeysPerWave + q holds mask word w of key q
-// (live runs only); the lanes clear them for the stage after next.
-__device__ __forceinline__ unsigned long long take_masks(ProductShared &sh, uint32_t buf) {
-    const uint32_t wave = threadIdx.x / kWave, lane = lane_id();
-    unsigned long long mine = 0;
-    if (lane < kMaskWords * kKeysPerWave) {
-        const uint32_t w = lane / kKeysPerWave, q = lane % kKeysPerWave;
-        mine = sh.mask[buf][w][wave * kKeysPerWave + q];
-        if (mine) sh.mask[buf][w][wave * kKeysPerWave + q] = 0;
-        mine &= sh.nzr[buf][w];
-    }
-    return mine;
-}
-
-// acc[q] |= every staged segment key q (Q0 <= q < Q1) pairs with.
-template <uint32_t Q0, uint32_t Q1>
-__device__ __forceinline__ void accumulate(const ProductShared &sh, uint32_t buf, unsigned long long mine,
-                                           uint64_t (&acc)[kKeysPerWave]) {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (uint32_t q = Q0; q < Q1; q++) {
-        uint64_t a = acc[q];
-#pragma unroll
-        for (uint32_t w = 0; w < kMaskWords; w++)
-            or_runs(a, rdlane64(mine, w * kKeysPerWave + q), sh.stage[buf] + 64 * w, lane);
-        acc[q] = a;
-    }
-}
+constexpr uint32_t kRunBatch = 8;  // partner segments in flight per wave
 
 // One work item: pairs [p0, p1) of one key tile, sorted by partner, against
 // row segment `seg`.  COL = false: pairs (i, k) of dA, partner rows k of B
 // (row-major); COL = true: pairs (j, k) of dB, partner rows k of A's
-// column-major copy.  A stage is the next kStagePairs pairs (kStageHalves
-// per thread), cut before the first pair of the (kStageRuns + 1)-th distinct
-// partner.  Stage s + 1 is planned before stage s is accumulated; its two
-// batches of partner segments are fetched during the two halves of the
-// accumulation (keys 0-7, keys 8-15 of each wave), and the pairs of stage
-// s + 2 too, so the accumulation hides the memory latency.  The barriers of
-// planning stage s + 1 also separate the staging of stage s from its
-// accumulation.  Every loop bound is uniform over the workgroup, so all
-// waves meet at every barrier.
+// column-major copy.  The waves take windows of 64 consecutive pairs from
+// an LDS counter.  In a window, pairs with the same partner k are adjacent
+// (a run): the wave loads the partner segment once per run (up to kRunBatch
+// runs in flight) and ORs it into the LDS accumulator of every key of the
+// run (atomic OR in LDS, no return value); an all-zero segment is skipped.
+// After the last window the waves flush the tile's keys and zero their
+// accumulators.  Every wave meets the two barriers of the item.
 template <bool COL, bool STATS>
 __device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared &sh, SlotChunk &ch,
                                              const EntryDev &E, const InstDev &I, uint32_t tile,
                                              uint32_t p0, uint32_t p1, uint32_t seg) {
-    static_assert(kMaskWords == 2 && kKeysPerWave % 2 == 0, "two partner batches, two key halves");
-    constexpr uint32_t kHalfKeys = kKeysPerWave / 2;
-    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
     const uint64_t Wp = (uint64_t)I.S * kSegWords;
     const uint32_t pm = COL ? E.a : E.b;
     const MatDev Mp = A.mats[I.mat_off + pm];
     const global_u64 G = (global_u64)(COL ? Mp.C : Mp.R);
     const uint64_t *pairs = COL ? A.cs : A.rs;
     const uint32_t key0 = tile * kTileKeys;
-    const bool count_pairs = STATS && seg == 0;
-    uint64_t acc[kKeysPerWave];
-#pragma unroll
-    for (uint32_t q = 0; q < kKeysPerWave; q++) acc[q] = 0;
-    PartnerFetch pf;
-    // prologue: stage 0 planned and staged, the pairs of stage 1 on the way
-    PairFetch f = fetch_pairs(pairs, p0, p1);
-    StagePlan cur = plan_stage<STATS>(sh, ch, f, p0, p1, key0, 0, count_pairs);
-#pragma unroll
-    for (uint32_t j = 0; j < kMaskWords; j++) {
-        fetch_partners(pf, sh, cur.nst, j, G, Wp, seg);
-        store_partners<COL, STATS>(A, sh, ch, pf, 0, j, E.inst, pm, seg, I);
-    }
-    uint32_t next = p0 + cur.len;
-    if (next < p1) f = fetch_pairs(pairs, next, p1);
-    // stage s is staged (and stage s - 1 consumed) once every wave has passed
-    // the first barrier of planning stage s + 1; with no stage s + 1 to plan
-    // a barrier of its own is needed
-    if (next >= p1) __syncthreads();
-    uint32_t b = 0;
+    const uint32_t nwin = (p1 - p0 + kWave - 1) / kWave;
     while (true) {
-        const bool more = next < p1;
-        StagePlan nx{0, 0};
-        if (more) {
-            nx = plan_stage<STATS>(sh, ch, f, next, p1, key0, b ^ 1, count_pairs);
-            fetch_partners(pf, sh, nx.nst, 0, G, Wp, seg);
-            if (next + nx.len < p1) f = fetch_pairs(pairs, next + nx.len, p1);
+        uint32_t win = 0;
+        if (lane == 0) win = atomicAdd(&sh.next_window, 1u);
+        win = first_lane(win);
+        if (win >= nwin) break;
+        const uint32_t x = p0 + win * kWave + lane;
+        const bool valid = x < p1;
+        uint32_t key = 0, k = kHole;
+        if (valid) {
+            const uint64_t pk = pairs[x];
+            key = (uint32_t)(pk >> 32);
+            k = (uint32_t)pk;
         }
-        const unsigned long long mine = take_masks(sh, b);
-        accumulate<0, kHalfKeys>(sh, b, mine, acc);
-        if (more) {
-            store_partners<COL, STATS>(A, sh, ch, pf, b ^ 1, 0, E.inst, pm, seg, I);
-            fetch_partners(pf, sh, nx.nst, 1, G, Wp, seg);
+        if (STATS && seg == 0) {
+            // the pair itself, read once per production
+            const uint64_t taken = __ballot(valid);
+            if (lane == 0) ch.bytes += 8ull * __popcll(taken);
         }
-        accumulate<kHalfKeys, kKeysPerWave>(sh, b, mine, acc);
-        if (!more) break;
-        store_partners<COL, STATS>(A, sh, ch, pf, b ^ 1, 1, E.inst, pm, seg, I);
-        b ^= 1;
-        next += nx.len;
-        if (next >= p1) __syncthreads();  // the last stage is staged
-    }
-    // flush the tile's keys; one flush body, the accumulators rotate through acc[0]
-    const MatDev Mc = A.mats[I.mat_off + E.c];
-#pragma nounroll
-    for (uint32_t q = 0; q < kKeysPerWave; q++) {
-        const uint64_t a = acc[0];
+        const uint32_t kprev = __shfl_up(k, 1, 64);
+        const uint64_t heads = __ballot(valid && (lane == 0 || k != kprev));
+        const uint32_t nvalid = (uint32_t)__popcll(__ballot(valid));
+        uint64_t todo = heads;
+        while (todo) {
+            // up to kRunBatch runs: their partner segments requested together
+            uint32_t start[kRunBatch];
+            uint64_t v[kRunBatch];
+            uint32_t nb = 0;
 #pragma unroll
-        for (uint32_t r = 0; r + 1 < kKeysPerWave; r++) acc[r] = acc[r + 1];
-        acc[kKeysPerWave - 1] = 0;
-        if (__ballot(a != 0))
-            flush<COL, STATS>(A, ch, E.inst, I, Mc, E.c, key0 + wave * kKeysPerWave + q, seg, a, Wp);
+            for (uint32_t q = 0; q < kRunBatch; q++) {
+                start[q] = 64;
+                v[q] = 0;
+                if (todo) {
+                    start[q] = (uint32_t)__ffsll((unsigned long long)todo) - 1;
+                    todo &= todo - 1;
+                    nb = q + 1;
+                    const uint32_t kk = rdlane(k, start[q]);
+                    v[q] = G[(uint64_t)kk * Wp + seg * kSegWords + lane];
+                }
+            }
+#pragma unroll
+            for (uint32_t q = 0; q < kRunBatch; q++) {
+                if (q >= nb) break;
+                const uint64_t live = __ballot(v[q] != 0);
+                if (!live) continue;
+                if (STATS && lane == 0 &&
+                    first_touch<STATS>(A, E.inst, pm, COL ? 1 : 0, rdlane(k, start[q]), seg, I))
+                    ch.bytes += 8ull * __popcll(live);
+                // the run ends where the next run starts (or the window's pairs end)
+                const uint64_t later = start[q] == 63 ? 0 : heads & (~0ull << (start[q] + 1));
+                const uint32_t end = later ? (uint32_t)__ffsll((unsigned long long)later) - 1 : nvalid;
+                for (uint32_t t = start[q]; t < end; t++) {
+                    const uint32_t kl = rdlane(key, t) - key0;
+                    if (kl < kTileKeys) atomicOr((unsigned long long *)&sh.acc[kl][lane], (unsigned long long)v[q]);
+                }
+            }
+        }
     }
+    __syncthreads();  // every window's ORs are in the accumulators
+    const MatDev Mc = A.mats[I.mat_off + E.c];
+    for (uint32_t q = 0; q < kKeysPerWave; q++) {
+        const uint32_t kl = wave + kProdWaves * q;
+        const uint64_t a = sh.acc[kl][lane];
+        if (__ballot(a != 0)) {
+            sh.acc[kl][lane] = 0;
+            flush<COL, STATS>(A, ch, E.inst, I, Mc, E.c, key0 + kl, seg, a, Wp);
+        }
+    }
+    __syncthreads();  // the accumulators are zero again before the next item
 }
 
 template <bool STATS>
@@ -494,8 +318,7 @@ __global__ __launch_bounds__(kProdWaves * kWave) void product_kernel(ProductArgs
     const uint32_t lane = lane_id(), wave = tid / kWave;
     const uint64_t first = A.item_prefix[A.unit_lo], total = A.item_prefix[A.unit_hi];
     SlotChunk ch;
-    if (tid < kTileKeys)
-        for (uint32_t w = 0; w < kMaskWords; w++) sh.mask[0][w][tid] = sh.mask[1][w][tid] = 0;
+    for (uint32_t x = tid; x < kTileKeys * kSegWords; x += kProdWaves * kWave) sh.acc[x / kSegWords][x % kSegWords] = 0;
     // items are taken from a counter, one atomic per workgroup and item; the
     // next one is requested when an item starts, so its round trip overlaps
     // the work.  After an overflow the round is re-run: stop early.
@@ -506,6 +329,7 @@ __global__ __launch_bounds__(kProdWaves * kWave) void product_kernel(ProductArgs
             unsigned long long it = nxt;
             if (__hip_atomic_load(A.halt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) it = total;
             sh.item = it;
+            sh.next_window = 0;
             if (it < total) nxt = first + atomicAdd(A.work_counter, 1ull);
         }
         __syncthreads();
