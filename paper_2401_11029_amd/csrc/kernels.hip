@@ -61,6 +61,13 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t *total) 
     return x - v;
 }
 
+// 64-bit value of lane l (each lane its own l; every lane must take part)
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, uint32_t l) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, (int)l, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), (int)l, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
     const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
     const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
@@ -155,56 +162,50 @@ __device__ __forceinline__ bool first_touch(const ProductArgs &A, uint32_t inst,
     return !(old & m);
 }
 
-// Flush of one accumulator row segment.  COL = false: acc holds candidate
-// bits j of row `key` (= i) of c, word w = 64*seg + lane, and the row-major
-// copy is the authority; COL = true: acc holds candidate rows i of column
-// `key` (= j), and the column-major copy is the authority.  One returning
-// 64-bit atomic OR per word tells which candidates are genuinely new; they
-// are appended, set in the other copy (no return value needed) and counted
-// for their instance.
-template <bool COL, bool STATS>
-__device__ __forceinline__ void flush(const ProductArgs &A, SlotChunk &ch, uint32_t inst, const InstDev &I,
-                                      const MatDev &Mc, uint32_t c, uint32_t key, uint32_t seg,
-                                      uint64_t acc, uint64_t Wp) {
+// Append the candidates of one key: slots [base + pre_l, base + pre_l +
+// popc(cand_l)) belong to lane l.  The wave fills them together, 64
+// consecutive slots per pass: slot t goes to lane t % 64, which finds the
+// lane and the bit that own it (binary searches over the lanes' prefix sums
+// and over the bits of the word), so the stores are contiguous.  A new pair
+// is also set in the other layout (no return value needed); a candidate
+// that turned out not to be new leaves a hole.
+template <bool COL>
+__device__ __forceinline__ void append_key(const ProductArgs &A, uint32_t k, uint32_t key, uint32_t seg,
+                                           uint64_t cand, uint64_t fresh, uint64_t base, uint32_t pre,
+                                           uint32_t total, uint64_t *other, uint64_t Wp) {
     const uint32_t lane = lane_id();
-    const uint32_t w = seg * kSegWords + lane;
-    uint64_t *own = (COL ? Mc.C : Mc.R) + (uint64_t)key * Wp + w;
-    uint64_t *other = COL ? Mc.R : Mc.C;
-    uint64_t cand = 0;
-    if (acc) cand = acc & ~*own;
-    if (STATS) {
-        uint64_t lanes = __ballot(acc != 0);
-        if (lanes && lane == 0 && first_touch<STATS>(A, inst, c, COL ? 1 : 0, key, seg, I))
-            ch.bytes += 8ull * __popcll(lanes);
-    }
-    uint64_t pos;
-    if (!reserve_slots(A, ch, inst, (uint32_t)__popcll(cand), &pos)) return;
-    uint64_t nw = 0, old = 0;
-    if (cand) {
-        old = atomicOr((unsigned long long *)own, (unsigned long long)cand);
-        nw = cand & ~old;
-    }
-    const uint32_t k = pair_key(inst, c);
-    uint64_t bits = cand;
-    while (bits) {
-        uint32_t b = __ffsll((unsigned long long)bits) - 1;
-        bits &= bits - 1;
-        if ((nw >> b) & 1) {
-            const uint32_t x = w * 64 + b;  // the other index of the pair
-            A.ap_key[pos] = k;
-            A.ap_i[pos] = COL ? x : key;
-            A.ap_j[pos] = COL ? key : x;
-            atomicOr((unsigned long long *)&other[(uint64_t)x * Wp + (key >> 6)], 1ull << (key & 63));
-        } else {
-            A.ap_key[pos] = kHole;
+    for (uint32_t r = 0; r < total; r += kWave) {
+        const uint32_t t = r + lane;
+        uint32_t src = 0;  // last lane whose first slot is <= t
+#pragma unroll
+        for (uint32_t step = 32; step; step >>= 1) {
+            const uint32_t probe = src + step;
+            if ((uint32_t)__shfl(pre, probe, 64) <= t) src = probe;
         }
-        pos++;
-    }
-    const uint32_t fresh = wave_sum((uint32_t)__popcll(nw));
-    if (fresh && lane == 0) {
-        const uint32_t shard = (blockIdx.x * kProdWaves + threadIdx.x / kWave) % kCountShards;
-        atomicAdd(&A.inst_new[(uint64_t)inst * kCountShards + shard], (unsigned long long)fresh);
-        if (STATS) ch.bytes += 20ull * fresh;
+        const uint64_t word = shfl64(cand, src);
+        const uint64_t fresh_bits = shfl64(fresh, src);
+        uint32_t rank = t - (uint32_t)__shfl(pre, src, 64);
+        uint32_t b = 0;  // position of the rank-th set bit of word
+#pragma unroll
+        for (uint32_t width = 32; width; width >>= 1) {
+            const uint32_t c2 = (uint32_t)__popcll((word >> b) & ((1ull << width) - 1));
+            if (rank >= c2) {
+                rank -= c2;
+                b += width;
+            }
+        }
+        if (t < total) {
+            const uint64_t slot = base + t;
+            if ((fresh_bits >> b) & 1) {
+                const uint32_t x = (seg * kSegWords + src) * 64 + b;  // the other index of the pair
+                A.ap_key[slot] = k;
+                A.ap_i[slot] = COL ? x : key;
+                A.ap_j[slot] = COL ? key : x;
+                atomicOr((unsigned long long *)&other[(uint64_t)x * Wp + (key >> 6)], 1ull << (key & 63));
+            } else {
+                A.ap_key[slot] = kHole;
+            }
+        }
     }
 }
 
@@ -216,6 +217,90 @@ struct ProductShared {
     uint32_t unit;            // and its unit
     uint32_t next_window;     // windows of the item taken so far
 };
+
+// Flush of the wave's keys kl = wave + 16 q of the tile: each accumulator
+// word holds candidate bits of row `key` (COL = false: pairs (key, j), the
+// row-major copy is the authority) or of column `key` (COL = true: pairs
+// (i, key), the column-major copy).  The authority segments of all the
+// wave's keys are read at once, append slots are reserved once for the
+// wave, and the returning 64-bit atomic ORs that tell which candidates are
+// new are issued back to back (in groups of eight keys); then the new pairs
+// are appended, set in the other layout and counted for the instance.  Every
+// accumulator row is left zero, also after an overflow.
+template <bool COL, bool STATS>
+__device__ __forceinline__ void flush_keys(const ProductArgs &A, ProductShared &sh, SlotChunk &ch,
+                                           uint32_t inst, const InstDev &I, const MatDev &Mc, uint32_t c,
+                                           uint32_t key0, uint32_t seg, uint64_t Wp) {
+    constexpr uint32_t kGroup = 8;  // keys whose round trips overlap
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    const uint32_t w = seg * kSegWords + lane;
+    uint64_t *own = COL ? Mc.C : Mc.R;
+    uint64_t *other = COL ? Mc.R : Mc.C;
+    const uint32_t k = pair_key(inst, c);
+    uint32_t fresh = 0;
+    bool failed = false;  // an append did not fit: later groups only clear their accumulators
+#pragma unroll 1
+    for (uint32_t g0 = 0; g0 < kKeysPerWave; g0 += kGroup) {
+        uint64_t cand[kGroup], old[kGroup];
+        uint32_t live = 0;  // keys with a non-zero accumulator (the same in every lane)
+#pragma unroll
+        for (uint32_t q = 0; q < kGroup; q++) {
+            const uint32_t kl = wave + kProdWaves * (g0 + q);
+            cand[q] = sh.acc[kl][lane];
+            const uint64_t lanes = __ballot(cand[q] != 0);
+            if (lanes) {
+                live |= 1u << q;
+                sh.acc[kl][lane] = 0;
+                if (STATS && lane == 0 && first_touch<STATS>(A, inst, c, COL ? 1 : 0, key0 + kl, seg, I))
+                    ch.bytes += 8ull * __popcll(lanes);
+            }
+        }
+        if (!live || failed) continue;
+#pragma unroll
+        for (uint32_t q = 0; q < kGroup; q++) {
+            old[q] = 0;
+            if ((live >> q) & 1) old[q] = own[(uint64_t)(key0 + wave + kProdWaves * (g0 + q)) * Wp + w];
+        }
+        uint32_t need = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < kGroup; q++) {
+            cand[q] &= ~old[q];
+            need += (uint32_t)__popcll(cand[q]);
+        }
+        // one reservation for the group's candidates (on overflow nothing
+        // is set: the host re-runs the round with a larger buffer)
+        uint32_t grand;
+        const uint32_t pre_all = wave_excl_scan(need, &grand);
+        uint64_t pos;
+        if (!reserve_slots(A, ch, inst, need, &pos)) {
+            failed = true;
+            continue;
+        }
+        if (!grand) continue;
+        uint64_t base = first_lane64(pos - pre_all);
+#pragma unroll
+        for (uint32_t q = 0; q < kGroup; q++)
+            if (cand[q])
+                old[q] = atomicOr((unsigned long long *)&own[(uint64_t)(key0 + wave + kProdWaves * (g0 + q)) * Wp + w],
+                                  (unsigned long long)cand[q]);
+#pragma unroll
+        for (uint32_t q = 0; q < kGroup; q++) {
+            uint32_t total;
+            const uint32_t pre = wave_excl_scan((uint32_t)__popcll(cand[q]), &total);
+            if (!total) continue;
+            const uint64_t nw = cand[q] & ~old[q];
+            fresh += (uint32_t)__popcll(nw);
+            append_key<COL>(A, k, key0 + wave + kProdWaves * (g0 + q), seg, cand[q], nw, base, pre, total, other, Wp);
+            base += total;
+        }
+    }
+    fresh = wave_sum(fresh);
+    if (fresh && lane == 0) {
+        const uint32_t shard = (blockIdx.x * kProdWaves + wave) % kCountShards;
+        atomicAdd(&A.inst_new[(uint64_t)inst * kCountShards + shard], (unsigned long long)fresh);
+        if (STATS) ch.bytes += 20ull * fresh;
+    }
+}
 
 constexpr uint32_t kRunBatch = 8;  // partner segments in flight per wave
 
@@ -299,15 +384,7 @@ __device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared
         }
     }
     __syncthreads();  // every window's ORs are in the accumulators
-    const MatDev Mc = A.mats[I.mat_off + E.c];
-    for (uint32_t q = 0; q < kKeysPerWave; q++) {
-        const uint32_t kl = wave + kProdWaves * q;
-        const uint64_t a = sh.acc[kl][lane];
-        if (__ballot(a != 0)) {
-            sh.acc[kl][lane] = 0;
-            flush<COL, STATS>(A, ch, E.inst, I, Mc, E.c, key0 + kl, seg, a, Wp);
-        }
-    }
+    flush_keys<COL, STATS>(A, sh, ch, E.inst, I, A.mats[I.mat_off + E.c], E.c, key0, seg, Wp);
     __syncthreads();  // the accumulators are zero again before the next item
 }
 
