@@ -24,8 +24,9 @@ plain solve after another); --mode serve reports the served form (Poisson
 arrivals of mixed queries, solves/s and p50/p99 latency against a
 one-at-a-time plain path); --mode grammars times the paper's hand-normalised
 grammars against the automatically normalised ones on the same graphs
-(Fig. 5b vs 5a on the alias graph, Fig. 4b vs 4a on a points-to graph).
-None of them is the default line.
+(Fig. 5b vs 5a on the alias graph, Fig. 4b vs 4a on a points-to graph);
+--mode analyses times the field-sensitive alias and value-flow analyses
+(Figs. 6, 7) on graphs of their shapes.  None of them is the default line.
 """
 
 from __future__ import annotations
@@ -342,26 +343,13 @@ def serve(args):
           flush=True)
 
 
-def grammars_mode(args):
-    """The paper's hand-normalised grammars (opt. 5) against the CFPQ Data
-    grammars normalised automatically, on the same graph: Fig. 5a as given
-    (the library binarises it), Fig. 5a binarised in the text, and Fig. 5b on
-    the 50,000-vertex alias graph; the same three forms of Fig. 4a/4b at 64
-    fields on a 12,000-vertex points-to graph.  All forms define the same
-    relation on the shared non-terminal, checked here by pair counts."""
+def compare_forms(cases, steps, metric):
+    """Time each grammar form of each case on the case's graph (median of
+    `steps` solves after one warm-up); check that the forms agree on the
+    shared non-terminal (pair counts)."""
     import torch
     import paper_2401_11029_amd as cflr
-    import workloads
-    from workloads import grammars as G, graphs
     ctx = cflr.Context(0)
-    cases = [("alias", workloads.config("alias_50k")[1], "M",
-              [("Fig. 5a as given, normalised by the library", G.ALIAS_FIG5A),
-               ("Fig. 5a binarised (helpers Y1..Y4)", G.ALIAS_FIG5A_WCNF),
-               ("Fig. 5b (WCNF by hand)", G.ALIAS_FIG5B)]),
-             ("pointsto", graphs.pointsto_graph(12000, seed=2), "PT",
-              [("Fig. 4a as given, normalised by the library", G.pointsto_fig4a_cfg(64)),
-               ("Fig. 4a binarised", G.pointsto_fig4a(64)),
-               ("Fig. 4b (WCNF by hand)", G.pointsto_fig4b(64))])]
     rows = []
     for name, g, shared, variants in cases:
         graph = cflr.Graph.from_workload(ctx, g)
@@ -372,7 +360,7 @@ def grammars_mode(args):
             r = cflr.solve(ctx, gr, graph)  # warm-up
             r.close()
             ms = []
-            for k in range(max(1, args.steps)):
+            for k in range(max(1, steps)):
                 r = cflr.solve(ctx, gr, graph)
                 st = r.stats()
                 ms.append(st["fixpoint_ms"])
@@ -380,18 +368,56 @@ def grammars_mode(args):
                 r.close()
             torch.cuda.synchronize()
             ms.sort()
-            log(f"{name} {label}: median {ms[len(ms) // 2]:.1f} ms, {st['rounds']} rounds, "
+            med = ms[len(ms) // 2]
+            log(f"{name} {label}: median {med:.1f} ms, {st['rounds']} rounds, "
                 f"{info['matrices']} matrices, {counts[label]} {shared} pairs")
             rows.append({"graph": name, "vertices": g.n, "edges": g.m, "grammar": label,
                          "matrices": info["matrices"], "binary": info["binary"],
-                         "fixpoint_ms_median": ms[len(ms) // 2], "rounds": st["rounds"],
-                         "pairs": st["total_pairs"], "shared_nt": shared,
-                         "shared_nt_pairs": counts[label]})
+                         "fixpoint_ms_median": med, "rounds": st["rounds"],
+                         "pairs": st["total_pairs"],
+                         "derived_pairs_per_s": st["new_pairs"] / (med / 1e3) if med > 0 else None,
+                         "shared_nt": shared, "shared_nt_pairs": counts[label]})
         for row in rows[-len(variants):]:
             row["same_shared_pairs"] = len(set(counts.values())) == 1
-    print(json.dumps({"metric": "fixpoint ms, hand vs automatic WCNF", "unit": "ms",
-                      "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
-                      "rows": rows}), flush=True)
+        del graph
+    print(json.dumps({"metric": metric, "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+                      "data": "synthetic", "rows": rows}), flush=True)
+
+
+def analyses_mode(args):
+    """The two further analyses of the paper on graphs of their Table 3
+    shapes, scaled to 40,000 vertices: field-sensitive C/C++ alias (Fig. 6b
+    by hand, Fig. 6a as given; 64 fields, 2.7 stored edges per vertex) and
+    context-sensitive value flow (Fig. 7b by hand, Fig. 7a as given; 64 call
+    sites, 1.7 edges per vertex)."""
+    from workloads import grammars as G, graphs
+    cases = [("fsca", graphs.fsca_graph(40000, fields=64), "M",
+              [("Fig. 6b (WCNF by hand)", G.fsca_fig6b(64)),
+               ("Fig. 6a as given, normalised by the library", G.fsca_fig6a_cfg(64))]),
+             ("cscvf", graphs.valueflow_graph(40000, m_fwd=68000, calls=64), "A",
+              [("Fig. 7b (WCNF by hand)", G.cscvf_fig7b(64)),
+               ("Fig. 7a as given, normalised by the library", G.cscvf_fig7a_cfg(64))])]
+    compare_forms(cases, args.steps, "fixpoint ms, field-sensitive alias and value-flow analyses")
+
+
+def grammars_mode(args):
+    """The paper's hand-normalised grammars (opt. 5) against the CFPQ Data
+    grammars normalised automatically, on the same graph: Fig. 5a as given
+    (the library binarises it), Fig. 5a binarised in the text, and Fig. 5b on
+    the 50,000-vertex alias graph; the same three forms of Fig. 4a/4b at 64
+    fields on a 12,000-vertex points-to graph.  All forms define the same
+    relation on the shared non-terminal, checked here by pair counts."""
+    import workloads
+    from workloads import grammars as G, graphs
+    cases = [("alias", workloads.config("alias_50k")[1], "M",
+              [("Fig. 5a as given, normalised by the library", G.ALIAS_FIG5A),
+               ("Fig. 5a binarised (helpers Y1..Y4)", G.ALIAS_FIG5A_WCNF),
+               ("Fig. 5b (WCNF by hand)", G.ALIAS_FIG5B)]),
+             ("pointsto", graphs.pointsto_graph(12000, seed=2), "PT",
+              [("Fig. 4a as given, normalised by the library", G.pointsto_fig4a_cfg(64)),
+               ("Fig. 4a binarised", G.pointsto_fig4a(64)),
+               ("Fig. 4b (WCNF by hand)", G.pointsto_fig4b(64))])]
+    compare_forms(cases, args.steps, "fixpoint ms, hand vs automatic WCNF")
 
 
 def main():
@@ -399,7 +425,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "grammars"])
+    ap.add_argument("--mode", default="single",
+                    choices=["single", "batch", "serve", "grammars", "analyses"])
     ap.add_argument("--serve-per-grammar", type=int, default=30)
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[0.5, 1.0, 2.0, 4.0, 8.0])
     ap.add_argument("--no-cpu", action="store_true")
@@ -419,6 +446,8 @@ def main():
         batch(args)
     elif args.mode == "grammars":
         grammars_mode(args)
+    elif args.mode == "analyses":
+        analyses_mode(args)
     else:
         serve(args)
     if args.copy_calibration:

@@ -122,6 +122,19 @@ def test_golden_digests(ctx, name):
         assert digest(s, d) == gold["sha256"][x], x
 
 
+@pytest.mark.parametrize("case", ["fsca6b", "fsca6a_long", "cscvf7b", "cscvf7a_long"])
+def test_analyses_on_their_graph_shapes(ctx, case):
+    # field-sensitive alias (Fig. 6) and value flow (Fig. 7) on graphs of
+    # their Table 3 shapes at 3,000 vertices (the bench times them at 40,000)
+    if case.startswith("fsca"):
+        g = graphs.fsca_graph(3000, fields=8)
+        text = G.fsca_fig6b(8) if case == "fsca6b" else G.fsca_fig6a_cfg(8)
+    else:
+        g = graphs.valueflow_graph(3000, m_fwd=5100, calls=8)
+        text = G.cscvf_fig7b(8) if case == "cscvf7b" else G.cscvf_fig7a_cfg(8)
+    assert_matches_oracle(gpu_solve(ctx, text, g), text, g, case)
+
+
 def test_long_right_sides_match_binarised_golden(ctx):
     # Fig. 5a as given (right sides of three symbols, normalised by the
     # library) on the 8,000-vertex alias graph: its five non-terminals equal

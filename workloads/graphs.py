@@ -171,6 +171,37 @@ def pointsto_graph(n, m_fwd=None, fields=64, alpha=2.1, zipf_s=1.1,
                   "class_p": list(class_p), "seed": seed})
 
 
+def fsca_graph(n, m_fwd=None, fields=64, p_field=0.3, p_d=0.4, alpha=2.1,
+               zipf_s=1.1, seed=6) -> Graph:
+    """Field-sensitive C/C++ alias shaped graph (the labels of Fig. 6):
+    forward edges are field edges f_i with probability p_field (i Zipf over
+    [0, fields)), else dereference d with probability p_d or assignment a;
+    sources power-law (Chung-Lu, alpha), targets uniform; every forward edge
+    (u, t, v) is also stored reversed as (v, t_bar, u).  Default m_fwd =
+    1.35 n, i.e. 2.7 stored labelled edges per vertex (Table 3's FSCA graphs:
+    111,550 edges on 41,652 vertices, 110,874 on 38,091)."""
+    if m_fwd is None:
+        m_fwd = (27 * n) // 20
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u, v = _distinct_pairs(rng, n, m_fwd, _chung_lu_sources(rng, n, alpha))
+    k = u.shape[0]
+    r = rng.random(k)
+    is_f = r < p_field
+    is_d = ~is_f & (rng.random(k) < p_d)
+    fld = _zipf_fields(rng, k, fields, zipf_s)
+    names = ["a", "d", "a_bar", "d_bar"]
+    names += [f"f_{i}" for i in range(fields)]
+    names += [f"f_bar_{i}" for i in range(fields)]
+    fwd = np.where(is_f, 4 + fld, np.where(is_d, 1, 0))
+    rev = np.where(is_f, 4 + fields + fld, np.where(is_d, 3, 2))
+    src = np.concatenate([u, v])
+    dst = np.concatenate([v, u])
+    lab = np.concatenate([fwd, rev])
+    return Graph(n, _u32(src), _u32(dst), _u32(lab), names,
+                 {"kind": "fsca", "n": n, "m_fwd": m_fwd, "fields": fields,
+                  "p_field": p_field, "p_d": p_d, "alpha": alpha, "seed": seed})
+
+
 def valueflow_graph(n, m_fwd=None, calls=16, p_call=0.1, alpha=2.1,
                     seed=5) -> Graph:
     """Context-sensitive value-flow shaped graph: plain flow edges 'a' and
