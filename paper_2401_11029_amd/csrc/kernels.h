@@ -22,18 +22,12 @@ constexpr uint32_t kCountShards = 64;   // counters per instance for new pairs
 // partner), the key being the row i of a pair (i, k) of dA or the column j
 // of a pair (k, j) of dB, and the partner the other index k.  One work item
 // is (production part, tile of kTileKeys keys, row segment, at most
-// kChunkPairs pairs): a workgroup of kProdWaves waves holds the accumulators
-// of the tile's keys in registers (kKeysPerWave per wave) and stages up to
-// kStageRuns distinct partner segments of up to kStagePairs pairs at a time
-// in LDS, so that a partner segment is read from memory once per tile
-// instead of once per pair.
+// kChunkPairs pairs): a workgroup of kProdWaves waves keeps the accumulators
+// of the tile's keys in LDS; a partner segment is read once per run of
+// pairs that share it (within a window of 64 pairs), not once per pair.
 constexpr uint32_t kTileKeys = 256;
 constexpr uint32_t kProdWaves = 16;
-constexpr uint32_t kKeysPerWave = kTileKeys / kProdWaves;
-constexpr uint32_t kStageHalves = 2;                             // pairs per thread per stage
-constexpr uint32_t kStagePairs = kStageHalves * kProdWaves * 64;  // 2048
-constexpr uint32_t kStageRuns = 128;
-constexpr uint32_t kMaskWords = kStageRuns / 64;
+constexpr uint32_t kKeysPerWave = kTileKeys / kProdWaves;  // keys each wave flushes
 constexpr uint32_t kChunkPairs = 32768;
 __host__ __device__ inline uint32_t key_tiles(uint32_t n) { return (n + kTileKeys - 1) / kTileKeys; }
 

@@ -38,9 +38,6 @@ __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1)
 __device__ __forceinline__ uint32_t rdlane(uint32_t v, uint32_t l) {
     return __builtin_amdgcn_readlane(v, l);
 }
-__device__ __forceinline__ uint64_t rdlane64(uint64_t v, uint32_t l) {
-    return ((uint64_t)rdlane((uint32_t)(v >> 32), l) << 32) | rdlane((uint32_t)v, l);
-}
 __device__ __forceinline__ uint32_t first_lane(uint32_t v) {
     return __builtin_amdgcn_readfirstlane(v);
 }
@@ -68,27 +65,6 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, uint32_t l) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
-    const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
-    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// Transpose a 64 x 64 bit matrix held one row per lane: afterwards bit u of
-// lane l is bit l of lane u's input (recursive block swap, 6 stages).
-__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x) {
-    const uint32_t lane = lane_id();
-    const uint64_t lo_mask[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
-                                 0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
-#pragma unroll
-    for (int st = 0; st < 6; st++) {
-        const int j = 32 >> st;
-        const uint64_t m = lo_mask[st];
-        const uint64_t p = shfl_xor64(x, j);
-        x = (lane & j) ? ((x & ~m) | ((p & ~m) >> j)) : ((x & m) | ((p & m) << j));
-    }
-    return x;
-}
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
     uint32_t t;
