@@ -182,6 +182,55 @@ def test_edge_cases(ctx):
     assert e.value.status == 1
 
 
+def test_round_limit_and_argument_errors(ctx):
+    import ctypes as C
+    m = cflr()
+    L = m.lib()
+    text, g = G.ALIAS_FIG5A_WCNF, graphs.alias_graph(2000, seed=11)
+    gr = m.Grammar(text)
+    graph = m.Graph.from_workload(ctx, g)
+    # round limit: ETIMEOUT with a partial result, every pair of which lies
+    # in the least fixpoint
+    o = m.opts(max_rounds=2)
+    h = C.c_void_p()
+    assert L.cflr_solve(ctx._h, gr._h, graph._h, C.byref(o), C.byref(h)) == 6  # CFLR_ETIMEOUT
+    assert h.value
+    res = m.Result(h, gr)
+    orc = oracle.solve(text, g)
+    for x in orc.order:
+        assert res.pair_set(x) <= orc.pair_set(x), x
+    assert sum(res.counts().values()) < sum(orc.count.values())
+    # copy into too small a buffer, non-terminal out of range
+    cnt = res.count("M")
+    assert cnt > 0
+    buf = np.empty(cnt, dtype=np.uint32)
+    w = C.c_uint64()
+    p = C.c_void_p(buf.ctypes.data)
+    assert L.cflr_result_copy(res._h, 0, p, p, cnt - 1, 0, C.byref(w)) == 1  # CFLR_EINVAL
+    c = C.c_uint64()
+    assert L.cflr_result_count(res._h, 99, C.byref(c)) == 1
+    # a graph of another context
+    ctx2 = m.Context(0)
+    g2 = m.Graph.from_workload(ctx2, g)
+    with pytest.raises(m.CflrError) as e:
+        m.solve(ctx, gr, g2)
+    assert e.value.status == 1
+    res.close()
+
+
+def test_autotune_then_batch_matches_oracle():
+    m = cflr()
+    own = m.Context(0)  # the tuned launch shape stays in this context
+    gs = [graphs.alias_graph(1500 + 400 * k, seed=20 + k) for k in range(3)]
+    gr = m.Grammar(G.ALIAS_FIG5A_WCNF)
+    gg = [m.Graph.from_workload(own, g) for g in gs]
+    t = m.autotune(own, gr, gg)
+    assert t["grid_waves"] > 0 and t["rounds_per_sync"] in (2, 4, 8) and t["best_ms"] > 0
+    res = m.solve_batch(own, gr, gg)
+    for r, g in zip(res, gs):
+        assert_matches_oracle(r, G.ALIAS_FIG5A_WCNF, g, "tuned batch")
+
+
 def test_naive_variant_matches(ctx):
     for seed in range(3):
         g = graphs.random_graph(120, 300, ["a", "d", "a_bar", "d_bar"], seed=40 + seed)
