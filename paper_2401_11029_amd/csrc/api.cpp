@@ -36,6 +36,7 @@ void compact_instance(Instance &in) {
                   "D2D");
         mats[x].R = p;
         mats[x].C = nullptr;
+        mats[x].Rm = mats[x].Cm = nullptr;
         mats[x].sort = 0;
         mats[x].pad = 0;
         p += words;

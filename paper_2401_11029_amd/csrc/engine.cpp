@@ -112,13 +112,14 @@ static void plan_layout(const Lowered &low, uint32_t n, uint32_t *S, uint64_t *W
     *S = (uint32_t)std::max<uint64_t>(1, (words + kSegWords - 1) / kSegWords);
     *Wp = (uint64_t)*S * kSegWords;
     const uint64_t layout = (uint64_t)n * *Wp * 8;
+    const uint64_t mask = (uint64_t)n * 8;  // one segment-mask word per row
     uint64_t total = 0;
     has_col->assign(low.nmat(), 0);
     for (uint32_t x = 0; x < low.nmat(); x++) {
-        total += layout;  // R
+        total += layout + mask;  // R
         if (low.dynamic[x] || low.slot_a[x]) {
             (*has_col)[x] = 1;
-            total += layout;
+            total += layout + mask;
         }
     }
     *bytes = total;
@@ -161,11 +162,22 @@ std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const
         M.R = p;
         p += layout_words;
         M.C = nullptr;
+        M.Rm = M.Cm = nullptr;
         M.sort = (low.slot_a[x] ? kSortRows : 0u) | (low.slot_b[x] ? kSortCols : 0u);
         M.pad = 0;
         if (has_col[x]) {
             M.C = p;
             p += layout_words;
+        }
+    }
+    // the segment masks follow the matrices (every row start stays 512-byte aligned)
+    for (uint32_t x = 0; x < low.nmat(); x++) {
+        MatDev &M = inst->mats[x];
+        M.Rm = p;
+        p += g->n;
+        if (M.C) {
+            M.Cm = p;
+            p += g->n;
         }
     }
     if (bytes) hip_check(hipMemsetAsync(inst->arena.ptr, 0, bytes, ctx->stream), "zero matrices");

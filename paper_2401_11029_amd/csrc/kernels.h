@@ -40,13 +40,24 @@ __host__ __device__ inline uint32_t pair_key(uint32_t slot, uint32_t mat) { retu
 __host__ __device__ inline uint32_t key_slot(uint32_t key) { return (key >> 16) & kMaxSlots; }
 __host__ __device__ inline uint32_t key_mat(uint32_t key) { return key & 0xFFFFu; }
 
+// Segment masks: word r of Rm has bit s % 64 set when segment s of row r of
+// R may hold a pair; a clear bit means every segment s' with s' % 64 == s
+// of that row is zero.  Bits are set together with the pairs (seeding and
+// the product's flush) and never cleared, so at the start of a round the
+// masks cover every pair derived before it; the product uses them to skip
+// partner segments that are zero.  Cm is the same for the rows of C.
 struct MatDev {
     uint64_t *R;    // row-major bits (always present)
     uint64_t *C;    // column-major copy (null when no production needs it)
+    uint64_t *Rm;   // n mask words for R
+    uint64_t *Cm;   // n mask words for C (null with C)
     uint32_t sort;  // kSortRows: new pairs needed in row order (the matrix
                     // stands in an a slot); kSortCols: in column order (b slot)
     uint32_t pad;
 };
+constexpr uint32_t kSegCols = kSegWords * 64;  // columns per row segment
+// mask bit of the segment holding column (or row) index x
+__host__ __device__ inline uint64_t seg_flag(uint32_t x) { return 1ull << ((x / kSegCols) & 63); }
 constexpr uint32_t kSortRows = 1u, kSortCols = 2u;
 
 struct InstDev {

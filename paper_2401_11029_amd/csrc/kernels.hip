@@ -143,12 +143,13 @@ __device__ __forceinline__ bool first_touch(const ProductArgs &A, uint32_t inst,
 // consecutive slots per pass: slot t goes to lane t % 64, which finds the
 // lane and the bit that own it (binary searches over the lanes' prefix sums
 // and over the bits of the word), so the stores are contiguous.  A new pair
-// is also set in the other layout (no return value needed); a candidate
-// that turned out not to be new leaves a hole.
+// is also set in the other layout and its segment mask (no return values
+// needed); a candidate that turned out not to be new leaves a hole.
 template <bool COL>
 __device__ __forceinline__ void append_key(const ProductArgs &A, uint32_t k, uint32_t key, uint32_t seg,
                                            uint64_t cand, uint64_t fresh, uint64_t base, uint32_t pre,
-                                           uint32_t total, uint64_t *other, uint64_t Wp) {
+                                           uint32_t total, uint64_t *other, uint64_t *other_mask,
+                                           uint64_t Wp) {
     const uint32_t lane = lane_id();
     for (uint32_t r = 0; r < total; r += kWave) {
         const uint32_t t = r + lane;
@@ -178,6 +179,7 @@ __device__ __forceinline__ void append_key(const ProductArgs &A, uint32_t k, uin
                 A.ap_i[slot] = COL ? x : key;
                 A.ap_j[slot] = COL ? key : x;
                 atomicOr((unsigned long long *)&other[(uint64_t)x * Wp + (key >> 6)], 1ull << (key & 63));
+                atomicOr((unsigned long long *)&other_mask[x], (unsigned long long)seg_flag(key));
             } else {
                 A.ap_key[slot] = kHole;
             }
@@ -212,6 +214,8 @@ __device__ __forceinline__ void flush_keys(const ProductArgs &A, ProductShared &
     const uint32_t w = seg * kSegWords + lane;
     uint64_t *own = COL ? Mc.C : Mc.R;
     uint64_t *other = COL ? Mc.R : Mc.C;
+    uint64_t *own_mask = COL ? Mc.Cm : Mc.Rm;
+    uint64_t *other_mask = COL ? Mc.Rm : Mc.Cm;
     const uint32_t k = pair_key(inst, c);
     uint32_t fresh = 0;
     bool failed = false;  // an append did not fit: later groups only clear their accumulators
@@ -266,7 +270,10 @@ __device__ __forceinline__ void flush_keys(const ProductArgs &A, ProductShared &
             if (!total) continue;
             const uint64_t nw = cand[q] & ~old[q];
             fresh += (uint32_t)__popcll(nw);
-            append_key<COL>(A, k, key0 + wave + kProdWaves * (g0 + q), seg, cand[q], nw, base, pre, total, other, Wp);
+            const uint32_t key = key0 + wave + kProdWaves * (g0 + q);
+            if (__ballot(nw != 0) && lane == 0)
+                atomicOr((unsigned long long *)&own_mask[key], 1ull << (seg & 63));
+            append_key<COL>(A, k, key, seg, cand[q], nw, base, pre, total, other, other_mask, Wp);
             base += total;
         }
     }
@@ -285,9 +292,11 @@ constexpr uint32_t kRunBatch = 8;  // partner segments in flight per wave
 // (row-major); COL = true: pairs (j, k) of dB, partner rows k of A's
 // column-major copy.  The waves take windows of 64 consecutive pairs from
 // an LDS counter.  In a window, pairs with the same partner k are adjacent
-// (a run): the wave loads the partner segment once per run (up to kRunBatch
-// runs in flight) and ORs it into the LDS accumulator of every key of the
-// run (atomic OR in LDS, no return value); an all-zero segment is skipped.
+// (a run): the first lane of a run reads the partner row's segment mask, and
+// only runs whose segment may be non-zero load it, once per run (up to
+// kRunBatch runs in flight), and OR it into the LDS accumulator of every key
+// of the run (atomic OR in LDS, no return value); a loaded segment that is
+// zero after all is skipped too.
 // After the last window the waves flush the tile's keys and zero their
 // accumulators.  Every wave meets the two barriers of the item.
 template <bool COL, bool STATS>
@@ -299,6 +308,8 @@ __device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared
     const uint32_t pm = COL ? E.a : E.b;
     const MatDev Mp = A.mats[I.mat_off + pm];
     const global_u64 G = (global_u64)(COL ? Mp.C : Mp.R);
+    const global_u64 Gm = (global_u64)(COL ? Mp.Cm : Mp.Rm);
+    const uint64_t seg_bit = 1ull << (seg & 63);
     const uint64_t *pairs = COL ? A.cs : A.rs;
     const uint32_t key0 = tile * kTileKeys;
     const uint32_t nwin = (p1 - p0 + kWave - 1) / kWave;
@@ -321,9 +332,12 @@ __device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared
             if (lane == 0) ch.bytes += 8ull * __popcll(taken);
         }
         const uint32_t kprev = __shfl_up(k, 1, 64);
-        const uint64_t heads = __ballot(valid && (lane == 0 || k != kprev));
+        const bool head = valid && (lane == 0 || k != kprev);
+        const uint64_t heads = __ballot(head);
         const uint32_t nvalid = (uint32_t)__popcll(__ballot(valid));
-        uint64_t todo = heads;
+        uint64_t m = 0;
+        if (head) m = Gm[k];
+        uint64_t todo = __ballot(head && (m & seg_bit));
         while (todo) {
             // up to kRunBatch runs: their partner segments requested together
             uint32_t start[kRunBatch];
@@ -660,7 +674,11 @@ __device__ __forceinline__ void seed_pair(const SeedArgs &A, uint32_t x, uint32_
     uint64_t bit = 1ull << (j & 63);
     unsigned long long o = atomicOr((unsigned long long *)&M.R[(uint64_t)i * Wp + (j >> 6)], bit);
     if (o & bit) return;
-    if (M.C) atomicOr((unsigned long long *)&M.C[(uint64_t)j * Wp + (i >> 6)], 1ull << (i & 63));
+    atomicOr((unsigned long long *)&M.Rm[i], (unsigned long long)seg_flag(j));
+    if (M.C) {
+        atomicOr((unsigned long long *)&M.C[(uint64_t)j * Wp + (i >> 6)], 1ull << (i & 63));
+        atomicOr((unsigned long long *)&M.Cm[j], (unsigned long long)seg_flag(i));
+    }
     unsigned long long p = atomicAdd(A.ap_count, 1ull);
     atomicAdd(&A.inst_new[(uint64_t)A.inst * kCountShards], 1ull);
     if (p < A.ap_cap) {
