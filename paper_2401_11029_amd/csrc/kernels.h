@@ -29,6 +29,7 @@ constexpr uint32_t kTileKeys = 256;
 constexpr uint32_t kProdWaves = 16;
 constexpr uint32_t kKeysPerWave = kTileKeys / kProdWaves;  // keys each wave flushes
 constexpr uint32_t kChunkPairs = 32768;
+static_assert(kSegWords % kProdWaves == 0, "each product wave takes whole words of a segment");
 __host__ __device__ inline uint32_t key_tiles(uint32_t n) { return (n + kTileKeys - 1) / kTileKeys; }
 
 // Key of an appended pair: bits 0..15 matrix, bits 16..29 instance slot.

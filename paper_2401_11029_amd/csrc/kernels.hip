@@ -143,13 +143,12 @@ __device__ __forceinline__ bool first_touch(const ProductArgs &A, uint32_t inst,
 // consecutive slots per pass: slot t goes to lane t % 64, which finds the
 // lane and the bit that own it (binary searches over the lanes' prefix sums
 // and over the bits of the word), so the stores are contiguous.  A new pair
-// is also set in the other layout and its segment mask (no return values
-// needed); a candidate that turned out not to be new leaves a hole.
+// is also set in the other layout (no return value needed); a candidate
+// that turned out not to be new leaves a hole.
 template <bool COL>
 __device__ __forceinline__ void append_key(const ProductArgs &A, uint32_t k, uint32_t key, uint32_t seg,
                                            uint64_t cand, uint64_t fresh, uint64_t base, uint32_t pre,
-                                           uint32_t total, uint64_t *other, uint64_t *other_mask,
-                                           uint64_t Wp) {
+                                           uint32_t total, uint64_t *other, uint64_t Wp) {
     const uint32_t lane = lane_id();
     for (uint32_t r = 0; r < total; r += kWave) {
         const uint32_t t = r + lane;
@@ -179,7 +178,6 @@ __device__ __forceinline__ void append_key(const ProductArgs &A, uint32_t k, uin
                 A.ap_i[slot] = COL ? x : key;
                 A.ap_j[slot] = COL ? key : x;
                 atomicOr((unsigned long long *)&other[(uint64_t)x * Wp + (key >> 6)], 1ull << (key & 63));
-                atomicOr((unsigned long long *)&other_mask[x], (unsigned long long)seg_flag(key));
             } else {
                 A.ap_key[slot] = kHole;
             }
@@ -191,6 +189,7 @@ __device__ __forceinline__ void append_key(const ProductArgs &A, uint32_t k, uin
 // item's row segment (kept all zero between items).
 struct ProductShared {
     uint64_t acc[kTileKeys][kSegWords];
+    uint64_t fresh_cols[kSegWords];  // the item's new pairs: their other indexes, as a bit set
     unsigned long long item;  // the workgroup's current item
     uint32_t unit;            // and its unit
     uint32_t next_window;     // windows of the item taken so far
@@ -215,7 +214,6 @@ __device__ __forceinline__ void flush_keys(const ProductArgs &A, ProductShared &
     uint64_t *own = COL ? Mc.C : Mc.R;
     uint64_t *other = COL ? Mc.R : Mc.C;
     uint64_t *own_mask = COL ? Mc.Cm : Mc.Rm;
-    uint64_t *other_mask = COL ? Mc.Rm : Mc.Cm;
     const uint32_t k = pair_key(inst, c);
     uint32_t fresh = 0;
     bool failed = false;  // an append did not fit: later groups only clear their accumulators
@@ -271,9 +269,11 @@ __device__ __forceinline__ void flush_keys(const ProductArgs &A, ProductShared &
             const uint64_t nw = cand[q] & ~old[q];
             fresh += (uint32_t)__popcll(nw);
             const uint32_t key = key0 + wave + kProdWaves * (g0 + q);
-            if (__ballot(nw != 0) && lane == 0)
-                atomicOr((unsigned long long *)&own_mask[key], 1ull << (seg & 63));
-            append_key<COL>(A, k, key, seg, cand[q], nw, base, pre, total, other, other_mask, Wp);
+            if (__ballot(nw != 0)) {
+                if (lane == 0) atomicOr((unsigned long long *)&own_mask[key], 1ull << (seg & 63));
+                if (nw) atomicOr((unsigned long long *)&sh.fresh_cols[lane], (unsigned long long)nw);
+            }
+            append_key<COL>(A, k, key, seg, cand[q], nw, base, pre, total, other, Wp);
             base += total;
         }
     }
@@ -286,24 +286,71 @@ __device__ __forceinline__ void flush_keys(const ProductArgs &A, ProductShared &
 }
 
 constexpr uint32_t kRunBatch = 8;  // partner segments in flight per wave
+constexpr uint32_t kWinGroup = 4;  // windows a wave takes at once
+
+// The runs of one window of 64 pairs (lane l holds key key_l and partner
+// k_l; `heads` marks the first lane of each run, `todo` the runs whose
+// partner segment may be non-zero): their partner segments are loaded, up to
+// kRunBatch at a time, and ORed into the accumulators of the run's keys.
+template <bool COL, bool STATS>
+__device__ __forceinline__ void or_runs(const ProductArgs &A, ProductShared &sh, SlotChunk &ch,
+                                        const EntryDev &E, const InstDev &I, uint32_t pm, global_u64 G,
+                                        uint64_t Wp, uint32_t key0, uint32_t seg, uint32_t key, uint32_t k,
+                                        uint64_t heads, uint32_t nvalid, uint64_t todo) {
+    const uint32_t lane = lane_id();
+    while (todo) {
+        // up to kRunBatch runs: their partner segments requested together
+        uint32_t start[kRunBatch];
+        uint64_t v[kRunBatch];
+        uint32_t nb = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < kRunBatch; q++) {
+            start[q] = 64;
+            v[q] = 0;
+            if (todo) {
+                start[q] = (uint32_t)__ffsll((unsigned long long)todo) - 1;
+                todo &= todo - 1;
+                nb = q + 1;
+                const uint32_t kk = rdlane(k, start[q]);
+                v[q] = G[(uint64_t)kk * Wp + seg * kSegWords + lane];
+            }
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < kRunBatch; q++) {
+            if (q >= nb) break;
+            const uint64_t live = __ballot(v[q] != 0);
+            if (!live) continue;
+            if (STATS && lane == 0 &&
+                first_touch<STATS>(A, E.inst, pm, COL ? 1 : 0, rdlane(k, start[q]), seg, I))
+                ch.bytes += 8ull * __popcll(live);
+            // the run ends where the next run starts (or the window's pairs end)
+            const uint64_t later = start[q] == 63 ? 0 : heads & (~0ull << (start[q] + 1));
+            const uint32_t end = later ? (uint32_t)__ffsll((unsigned long long)later) - 1 : nvalid;
+            for (uint32_t t = start[q]; t < end; t++) {
+                const uint32_t kl = rdlane(key, t) - key0;
+                if (kl < kTileKeys) atomicOr((unsigned long long *)&sh.acc[kl][lane], (unsigned long long)v[q]);
+            }
+        }
+    }
+}
 
 // One work item: pairs [p0, p1) of one key tile, sorted by partner, against
 // row segment `seg`.  COL = false: pairs (i, k) of dA, partner rows k of B
 // (row-major); COL = true: pairs (j, k) of dB, partner rows k of A's
-// column-major copy.  The waves take windows of 64 consecutive pairs from
-// an LDS counter.  In a window, pairs with the same partner k are adjacent
-// (a run): the first lane of a run reads the partner row's segment mask, and
-// only runs whose segment may be non-zero load it, once per run (up to
-// kRunBatch runs in flight), and OR it into the LDS accumulator of every key
-// of the run (atomic OR in LDS, no return value); a loaded segment that is
-// zero after all is skipped too.
-// After the last window the waves flush the tile's keys and zero their
-// accumulators.  Every wave meets the two barriers of the item.
+// column-major copy.  The waves take kWinGroup windows of 64 consecutive
+// pairs at a time from an LDS counter and request their pairs together, then
+// the segment masks of their partners together.  In a window, pairs with
+// the same partner k are adjacent (a run): only runs whose partner segment
+// may be non-zero load it, once per run, and OR it into the LDS accumulator
+// of every key of the run (atomic OR in LDS, no return value); a loaded
+// segment that is zero after all is skipped too.  After the last window the
+// waves flush the tile's keys and zero their accumulators.  Every wave meets
+// the two barriers of the item.
 template <bool COL, bool STATS>
 __device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared &sh, SlotChunk &ch,
                                              const EntryDev &E, const InstDev &I, uint32_t tile,
                                              uint32_t p0, uint32_t p1, uint32_t seg) {
-    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    const uint32_t lane = lane_id();
     const uint64_t Wp = (uint64_t)I.S * kSegWords;
     const uint32_t pm = COL ? E.a : E.b;
     const MatDev Mp = A.mats[I.mat_off + pm];
@@ -315,67 +362,66 @@ __device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared
     const uint32_t nwin = (p1 - p0 + kWave - 1) / kWave;
     while (true) {
         uint32_t win = 0;
-        if (lane == 0) win = atomicAdd(&sh.next_window, 1u);
+        if (lane == 0) win = atomicAdd(&sh.next_window, kWinGroup);
         win = first_lane(win);
         if (win >= nwin) break;
-        const uint32_t x = p0 + win * kWave + lane;
-        const bool valid = x < p1;
-        uint32_t key = 0, k = kHole;
-        if (valid) {
-            const uint64_t pk = pairs[x];
-            key = (uint32_t)(pk >> 32);
-            k = (uint32_t)pk;
-        }
-        if (STATS && seg == 0) {
-            // the pair itself, read once per production
-            const uint64_t taken = __ballot(valid);
-            if (lane == 0) ch.bytes += 8ull * __popcll(taken);
-        }
-        const uint32_t kprev = __shfl_up(k, 1, 64);
-        const bool head = valid && (lane == 0 || k != kprev);
-        const uint64_t heads = __ballot(head);
-        const uint32_t nvalid = (uint32_t)__popcll(__ballot(valid));
-        uint64_t m = 0;
-        if (head) m = Gm[k];
-        uint64_t todo = __ballot(head && (m & seg_bit));
-        while (todo) {
-            // up to kRunBatch runs: their partner segments requested together
-            uint32_t start[kRunBatch];
-            uint64_t v[kRunBatch];
-            uint32_t nb = 0;
+        uint64_t pk[kWinGroup];
 #pragma unroll
-            for (uint32_t q = 0; q < kRunBatch; q++) {
-                start[q] = 64;
-                v[q] = 0;
-                if (todo) {
-                    start[q] = (uint32_t)__ffsll((unsigned long long)todo) - 1;
-                    todo &= todo - 1;
-                    nb = q + 1;
-                    const uint32_t kk = rdlane(k, start[q]);
-                    v[q] = G[(uint64_t)kk * Wp + seg * kSegWords + lane];
-                }
-            }
+        for (uint32_t q = 0; q < kWinGroup; q++) {
+            const uint64_t x = (uint64_t)p0 + (uint64_t)(win + q) * kWave + lane;
+            pk[q] = ~0ull;
+            if (x < p1) pk[q] = pairs[x];
+        }
+        uint32_t key[kWinGroup], k[kWinGroup], nvalid[kWinGroup];
+        uint64_t heads[kWinGroup], m[kWinGroup];
 #pragma unroll
-            for (uint32_t q = 0; q < kRunBatch; q++) {
-                if (q >= nb) break;
-                const uint64_t live = __ballot(v[q] != 0);
-                if (!live) continue;
-                if (STATS && lane == 0 &&
-                    first_touch<STATS>(A, E.inst, pm, COL ? 1 : 0, rdlane(k, start[q]), seg, I))
-                    ch.bytes += 8ull * __popcll(live);
-                // the run ends where the next run starts (or the window's pairs end)
-                const uint64_t later = start[q] == 63 ? 0 : heads & (~0ull << (start[q] + 1));
-                const uint32_t end = later ? (uint32_t)__ffsll((unsigned long long)later) - 1 : nvalid;
-                for (uint32_t t = start[q]; t < end; t++) {
-                    const uint32_t kl = rdlane(key, t) - key0;
-                    if (kl < kTileKeys) atomicOr((unsigned long long *)&sh.acc[kl][lane], (unsigned long long)v[q]);
-                }
-            }
+        for (uint32_t q = 0; q < kWinGroup; q++) {
+            const bool valid = (uint64_t)p0 + (uint64_t)(win + q) * kWave + lane < p1;
+            key[q] = (uint32_t)(pk[q] >> 32);
+            k[q] = (uint32_t)pk[q];
+            const uint32_t kprev = __shfl_up(k[q], 1, 64);
+            const bool head = valid && (lane == 0 || k[q] != kprev);
+            heads[q] = __ballot(head);
+            nvalid[q] = (uint32_t)__popcll(__ballot(valid));
+            m[q] = 0;
+            if (head) m[q] = Gm[k[q]];
+        }
+        if (STATS && seg == 0 && lane == 0) {
+            // the pairs themselves, read once per production
+            uint32_t taken = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < kWinGroup; q++) taken += nvalid[q];
+            ch.bytes += 8ull * taken;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < kWinGroup; q++) {
+            const uint64_t todo = __ballot(((heads[q] >> lane) & 1) && (m[q] & seg_bit));
+            if (todo)
+                or_runs<COL, STATS>(A, sh, ch, E, I, pm, G, Wp, key0, seg, key[q], k[q], heads[q], nvalid[q], todo);
         }
     }
     __syncthreads();  // every window's ORs are in the accumulators
     flush_keys<COL, STATS>(A, sh, ch, E.inst, I, A.mats[I.mat_off + E.c], E.c, key0, seg, Wp);
     __syncthreads();  // the accumulators are zero again before the next item
+    // Segment masks of the other layout: every new pair of the item has its
+    // key in the tile, so row x of the other layout gains the same segment
+    // bit for every x in fresh_cols.  Each wave takes four words of the set,
+    // reads the 64 masks of a word at once and sets the bit where it is
+    // missing, then clears the word (before the next item's flush).
+    uint64_t *other_mask = COL ? A.mats[I.mat_off + E.c].Rm : A.mats[I.mat_off + E.c].Cm;
+    const uint64_t flag = seg_flag(key0);
+    const uint32_t wave = threadIdx.x / kWave;
+#pragma unroll 1
+    for (uint32_t r = 0; r < kSegWords / kProdWaves; r++) {
+        const uint32_t w = wave * (kSegWords / kProdWaves) + r;
+        const uint64_t bits = first_lane64(sh.fresh_cols[w]);
+        if (!bits) continue;
+        const uint32_t x = (seg * kSegWords + w) * 64 + lane;
+        if ((bits >> lane) & 1) {
+            if (!(other_mask[x] & flag)) atomicOr((unsigned long long *)&other_mask[x], (unsigned long long)flag);
+        }
+        if (lane == 0) sh.fresh_cols[w] = 0;
+    }
 }
 
 template <bool STATS>
@@ -386,6 +432,7 @@ __global__ __launch_bounds__(kProdWaves * kWave) void product_kernel(ProductArgs
     const uint64_t first = A.item_prefix[A.unit_lo], total = A.item_prefix[A.unit_hi];
     SlotChunk ch;
     for (uint32_t x = tid; x < kTileKeys * kSegWords; x += kProdWaves * kWave) sh.acc[x / kSegWords][x % kSegWords] = 0;
+    if (tid < kSegWords) sh.fresh_cols[tid] = 0;
     // items are taken from a counter, one atomic per workgroup and item; the
     // next one is requested when an item starts, so its round trip overlaps
     // the work.  After an overflow the round is re-run: stop early.
