@@ -38,7 +38,7 @@ void compact_instance(Instance &in) {
         mats[x].C = nullptr;
         mats[x].Rm = mats[x].Cm = nullptr;
         mats[x].sort = 0;
-        mats[x].pad = 0;
+        mats[x].rrank = mats[x].crank = 0;
         p += words;
     }
     hip_check(hipStreamSynchronize(in.ctx->stream), "sync");

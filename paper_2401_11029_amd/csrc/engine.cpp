@@ -134,7 +134,14 @@ uint64_t instance_footprint(const Lowered &low, uint32_t n) {
 }
 
 uint64_t instance_buckets(const Lowered &low, uint32_t n) {
-    return (uint64_t)low.nmat() * key_tiles(n) * n;
+    // the row-order and column-order counters share the instance's range:
+    // it holds the larger of the two sets of sorted matrices
+    uint64_t rows = 0, cols = 0;
+    for (uint32_t x = 0; x < low.nmat(); x++) {
+        rows += low.slot_a[x] ? 1 : 0;
+        cols += low.slot_b[x] ? 1 : 0;
+    }
+    return std::max(rows, cols) * key_tiles(n) * n;
 }
 
 std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const cflr_graph *g) {
@@ -157,6 +164,7 @@ std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const
     if (bytes) inst->arena = DevBuf(ctx->pool.get(), bytes);
     uint64_t *p = inst->arena.as<uint64_t>();
     inst->mats.resize(low.nmat());
+    uint16_t rrank = 0, crank = 0;
     for (uint32_t x = 0; x < low.nmat(); x++) {
         MatDev &M = inst->mats[x];
         M.R = p;
@@ -164,7 +172,8 @@ std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const
         M.C = nullptr;
         M.Rm = M.Cm = nullptr;
         M.sort = (low.slot_a[x] ? kSortRows : 0u) | (low.slot_b[x] ? kSortCols : 0u);
-        M.pad = 0;
+        M.rrank = low.slot_a[x] ? rrank++ : 0;
+        M.crank = low.slot_b[x] ? crank++ : 0;
         if (has_col[x]) {
             M.C = p;
             p += layout_words;
@@ -423,7 +432,9 @@ void Run::rebuild_tables() {
     for (uint32_t e = 0; e < nent_; e++) {
         const InstDev &I = hi[he[e].inst];
         const uint32_t nt = key_tiles(I.n);
-        for (uint32_t t = 0; t < nt; t++) hu.push_back(UnitDev{he[e], t, 0, 0, I});
+        const MatDev &op = hm[I.mat_off + (he[e].part == 0 ? he[e].a : he[e].b)];
+        const uint32_t rank = he[e].part == 0 ? op.rrank : op.crank;
+        for (uint32_t t = 0; t < nt; t++) hu.push_back(UnitDev{he[e], t, rank, 0, 0, I});
         if (he[e].part == 0) unit_split_ = (uint32_t)hu.size();
     }
     nunit_ = (uint32_t)hu.size();

@@ -54,7 +54,8 @@ struct MatDev {
     uint64_t *Cm;   // n mask words for C (null with C)
     uint32_t sort;  // kSortRows: new pairs needed in row order (the matrix
                     // stands in an a slot); kSortCols: in column order (b slot)
-    uint32_t pad;
+    uint16_t rrank;  // index among the instance's matrices sorted in row order
+    uint16_t crank;  // index among those sorted in column order
 };
 constexpr uint32_t kSegCols = kSegWords * 64;  // columns per row segment
 // mask bit of the segment holding column (or row) index x
@@ -64,8 +65,10 @@ constexpr uint32_t kSortRows = 1u, kSortCols = 2u;
 struct InstDev {
     uint32_t n;        // vertices
     uint32_t S;        // segments per row; Wp = 64 * S
-    uint32_t bbase;    // first sort bucket of this instance: matrix x, key
-                       // tile t, partner k is bucket bbase + (x * key_tiles(n) + t) * n + k
+    uint32_t bbase;    // first sort bucket of this instance: in the row-order
+                       // counters, matrix x (row rank r), key tile t, partner k
+                       // is bucket bbase + (r * key_tiles(n) + t) * n + k; the
+                       // column-order counters use the column rank
     uint32_t mat_off;  // first MatDev of this instance
 };
 
@@ -84,6 +87,7 @@ struct EntryDev {
 struct UnitDev {
     EntryDev e;
     uint32_t tile;
+    uint32_t rank;        // the sorted operand's rank in its order (row rank of a, column rank of b)
     uint32_t start, cnt;  // its new pairs in the sorted order (set by the prep each round)
     InstDev I;
 };

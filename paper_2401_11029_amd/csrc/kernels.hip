@@ -326,9 +326,12 @@ __device__ __forceinline__ void or_runs(const ProductArgs &A, ProductShared &sh,
             // the run ends where the next run starts (or the window's pairs end)
             const uint64_t later = start[q] == 63 ? 0 : heads & (~0ull << (start[q] + 1));
             const uint32_t end = later ? (uint32_t)__ffsll((unsigned long long)later) - 1 : nvalid;
+            // every key of the unit's pairs lies in its tile (they are
+            // bucketed by key tile); the mask keeps the row inside the
+            // accumulators without a branch
             for (uint32_t t = start[q]; t < end; t++) {
-                const uint32_t kl = rdlane(key, t) - key0;
-                if (kl < kTileKeys) atomicOr((unsigned long long *)&sh.acc[kl][lane], (unsigned long long)v[q]);
+                const uint32_t kl = (rdlane(key, t) - key0) & (kTileKeys - 1);
+                atomicOr((unsigned long long *)&sh.acc[kl][lane], (unsigned long long)v[q]);
             }
         }
     }
@@ -501,9 +504,8 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs A) {
         uint64_t items = 0;
         if (u < A.nunit && !*A.halt) {
             UnitDev &U = A.units[u];
-            const uint32_t mat = U.e.part == 0 ? U.e.a : U.e.b;
             const uint32_t *ptr = U.e.part == 0 ? A.rptr : A.cptr;
-            const uint64_t b0 = U.I.bbase + ((uint64_t)mat * key_tiles(U.I.n) + U.tile) * U.I.n;
+            const uint64_t b0 = U.I.bbase + ((uint64_t)U.rank * key_tiles(U.I.n) + U.tile) * U.I.n;
             const uint32_t s = ptr[b0], f = ptr[b0 + U.I.n];
             U.start = s;
             U.cnt = f - s;
@@ -582,12 +584,13 @@ __device__ __forceinline__ void entry_rows(const SortArgs &A, uint64_t x, uint64
     const uint32_t key = A.ap_key[x];
     if (key == kHole) return;
     const InstDev I = A.inst[key_slot(key)];
-    const uint32_t need = A.mats[I.mat_off + key_mat(key)].sort;
-    const uint64_t b = I.bbase + (uint64_t)key_mat(key) * key_tiles(I.n) * I.n;
+    const MatDev &M = A.mats[I.mat_off + key_mat(key)];
+    const uint32_t need = M.sort;
+    const uint64_t span = (uint64_t)key_tiles(I.n) * I.n;  // buckets of one matrix
     *i = A.ap_i[x];
     *j = A.ap_j[x];
-    if (need & kSortRows) *r = (uint32_t)(b + (uint64_t)(*i / kTileKeys) * I.n + *j);
-    if (need & kSortCols) *c = (uint32_t)(b + (uint64_t)(*j / kTileKeys) * I.n + *i);
+    if (need & kSortRows) *r = (uint32_t)(I.bbase + M.rrank * span + (uint64_t)(*i / kTileKeys) * I.n + *j);
+    if (need & kSortCols) *c = (uint32_t)(I.bbase + M.crank * span + (uint64_t)(*j / kTileKeys) * I.n + *i);
 }
 
 __global__ __launch_bounds__(256) void count_kernel(SortArgs A) {
