@@ -81,6 +81,10 @@ typedef struct cflr_opts {
     uint32_t rounds_per_sync;  /* rounds replayed per host check of the
                                   changed flag (batched and served forms);
                                   0 = automatic */
+    uint32_t chunk_pairs;      /* new pairs of one key tile that one product
+                                  work item takes at most (a tile with more
+                                  is split, and each part flushes the tile's
+                                  keys again); 0 = 2^20 */
 } cflr_opts;
 
 /* Per-solve statistics. */

@@ -20,7 +20,8 @@ class Opts(C.Structure):
                 ("count_traffic", C.c_uint32),
                 ("delta_capacity", C.c_uint64),
                 ("grid_waves", C.c_uint32),
-                ("rounds_per_sync", C.c_uint32)]
+                ("rounds_per_sync", C.c_uint32),
+                ("chunk_pairs", C.c_uint32)]
 
 
 class Stats(C.Structure):

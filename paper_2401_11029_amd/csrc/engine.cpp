@@ -535,6 +535,7 @@ void Run::enqueue_product(bool timed) {
     P.work_counter0 = counters + 1;
     P.work_counter1 = counters + 4;
     P.halt = halt;
+    P.chunk = opts_.chunk_pairs ? opts_.chunk_pairs : kChunkPairs;
     hip_check(launch_prep(P, s_), "prep");
     if (opts_.count_traffic && touched_bits_)
         hip_check(launch_fill_u32(d_touched_.as<uint32_t>(), (touched_bits_ + 31) / 32, 0, s_), "fill");
@@ -555,6 +556,7 @@ void Run::enqueue_product(bool timed) {
     A.touched = d_touched_.as<uint32_t>();
     A.touched_off = d_touched_off_.as<uint64_t>();
     A.algo_bytes = counters + 2;
+    A.chunk = P.chunk;
     if (timed) hip_check(hipEventRecord(ev0_, s_), "event");
     // the row parts, then the column parts (a pair derived by both is then
     // reported once: by the row part)

@@ -22,13 +22,13 @@ constexpr uint32_t kCountShards = 64;   // counters per instance for new pairs
 // partner), the key being the row i of a pair (i, k) of dA or the column j
 // of a pair (k, j) of dB, and the partner the other index k.  One work item
 // is (production part, tile of kTileKeys keys, row segment, at most
-// kChunkPairs pairs): a workgroup of kProdWaves waves keeps the accumulators
+// `chunk` pairs, by default kChunkPairs): a workgroup of kProdWaves waves keeps the accumulators
 // of the tile's keys in LDS; a partner segment is read once per run of
 // pairs that share it (within a window of 64 pairs), not once per pair.
 constexpr uint32_t kTileKeys = 256;
 constexpr uint32_t kProdWaves = 16;
 constexpr uint32_t kKeysPerWave = kTileKeys / kProdWaves;  // keys each wave flushes
-constexpr uint32_t kChunkPairs = 32768;
+constexpr uint32_t kChunkPairs = 1u << 20;
 static_assert(kSegWords % kProdWaves == 0, "each product wave takes whole words of a segment");
 __host__ __device__ inline uint32_t key_tiles(uint32_t n) { return (n + kTileKeys - 1) / kTileKeys; }
 
@@ -112,6 +112,7 @@ struct ProductArgs {
     uint32_t *touched;             // bit array
     const uint64_t *touched_off;   // per instance: bit offset of its matrices
     unsigned long long *algo_bytes;
+    uint32_t chunk;  // pairs per work item at most (as in the prep)
 };
 
 struct PrepArgs {
@@ -121,6 +122,7 @@ struct PrepArgs {
     uint64_t *item_prefix;
     unsigned long long *work_counter0, *work_counter1;  // reset for the two launches
     const uint32_t *halt;
+    uint32_t chunk;  // pairs per work item at most
 };
 
 struct SortArgs {

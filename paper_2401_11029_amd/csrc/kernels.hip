@@ -473,8 +473,8 @@ __global__ __launch_bounds__(kProdWaves * kWave) void product_kernel(ProductArgs
         const uint32_t seg = (uint32_t)(local % U.I.S);
         const uint64_t chunk = local / U.I.S;
         const uint64_t end = (uint64_t)U.start + U.cnt;
-        const uint64_t c0 = U.start + chunk * kChunkPairs;
-        const uint64_t c1 = c0 + kChunkPairs < end ? c0 + kChunkPairs : end;
+        const uint64_t c0 = U.start + chunk * A.chunk;
+        const uint64_t c1 = c0 + A.chunk < end ? c0 + A.chunk : end;
         if (U.e.part == 0)
             product_tile<false, STATS>(A, sh, ch, U.e, U.I, U.tile, (uint32_t)c0, (uint32_t)c1, seg);
         else
@@ -509,7 +509,7 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs A) {
             const uint32_t s = ptr[b0], f = ptr[b0 + U.I.n];
             U.start = s;
             U.cnt = f - s;
-            items = ((uint64_t)(f - s) + kChunkPairs - 1) / kChunkPairs * U.I.S;
+            items = ((uint64_t)(f - s) + A.chunk - 1) / A.chunk * U.I.S;
         }
         part[t] = items;
         __syncthreads();

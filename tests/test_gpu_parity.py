@@ -97,13 +97,14 @@ def test_key_tile_boundaries(ctx, n):
         assert_matches_oracle(gpu_solve(ctx, text, g), text, g, f"n={n}")
 
 
-def test_tiles_split_into_pair_chunks(ctx):
+@pytest.mark.parametrize("chunk", [0, 32768, 1000])
+def test_tiles_split_into_pair_chunks(ctx, chunk):
     # a dense relation: in round 2 one key tile holds ~145k new pairs of one
-    # operand, more than one work item takes (several chunks per tile, each
-    # flushing its own partial accumulators), and stages are cut by the pair
-    # limit as well as by the partner limit
+    # operand; with a small chunk_pairs the tile is split into several work
+    # items, each flushing its own partial accumulators (1000 also ends a
+    # chunk inside a window of 64 pairs)
     g = graphs.random_graph(600, 20000, ["a"], seed=4242, self_loops=True)
-    r = gpu_solve(ctx, G.TRANSITIVE, g)
+    r = gpu_solve(ctx, G.TRANSITIVE, g, chunk_pairs=chunk)
     assert r.stats()["max_delta"] > 2 * 32768
     assert_matches_oracle(r, G.TRANSITIVE, g)
 
