@@ -340,10 +340,11 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
         hip_check(hipEventRecord(e0, ctx->stream), "event");
         Run run(ctx, o, buckets, count);
         // device memory for matrices: 70 % of what is free, minus the
-        // new-pair buffer (28 bytes a pair, grown on overflow) and headroom
-        // for it to double once
+        // new-pair buffer (44 bytes a pair: the append, two sort stages and
+        // two sorted orders; grown on overflow) and headroom for it to
+        // double once
         const uint64_t avail = (uint64_t)((double)(free_b + ctx->pool->held()) * 0.7);
-        const uint64_t delta_bytes = 3 * 28ull * run.delta_capacity();
+        const uint64_t delta_bytes = 3 * 44ull * run.delta_capacity();
         const uint64_t budget = avail > delta_bytes ? avail - delta_bytes : avail / 4;
         std::vector<std::shared_ptr<Instance>> all(count);
         uint64_t in_use = 0;

@@ -135,13 +135,15 @@ uint64_t instance_footprint(const Lowered &low, uint32_t n) {
 
 uint64_t instance_buckets(const Lowered &low, uint32_t n) {
     // the row-order and column-order counters share the instance's range:
-    // it holds the larger of the two sets of sorted matrices
+    // it holds the larger of the two sets of sorted matrices, one bucket per
+    // (key tile, partner segment)
     uint64_t rows = 0, cols = 0;
     for (uint32_t x = 0; x < low.nmat(); x++) {
         rows += low.slot_a[x] ? 1 : 0;
         cols += low.slot_b[x] ? 1 : 0;
     }
-    return std::max(rows, cols) * key_tiles(n) * n;
+    const uint64_t segs = std::max<uint64_t>(1, ((uint64_t)n + kSegCols - 1) / kSegCols);
+    return std::max(rows, cols) * key_tiles(n) * segs;
 }
 
 std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const cflr_graph *g) {
@@ -225,7 +227,7 @@ std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const
 Run::Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t bucket_capacity, uint32_t max_instances)
     : hold_(ctx), ctx_(ctx), opts_(opts), s_(ctx->stream), bucket_cap_(bucket_capacity), max_inst_(max_instances) {
     if (bucket_cap_ >= 0xFFFFFFF0ull)
-        throw Error(CFLR_EUNSUPPORTED, "too many sort buckets for one run (matrices x key tiles x n >= 2^32)");
+        throw Error(CFLR_EUNSUPPORTED, "too many sort buckets for one run (matrices x key tiles x segments >= 2^32)");
     if (max_inst_ == 0 || max_inst_ > kMaxSlots)
         throw Error(CFLR_EINVAL, "instances per run must be in [1, " + std::to_string(kMaxSlots) + "]");
     DevPool *pool = ctx->pool.get();
@@ -252,7 +254,8 @@ Run::Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t bucket_capacity, uint32_
     hip_check(hipEventCreate(&ev0_), "event");
     hip_check(hipEventCreate(&ev1_), "event");
     uint64_t cap = opts_.delta_capacity ? opts_.delta_capacity : ctx->delta_capacity_hint;
-    if (!cap) cap = std::max<uint64_t>(1ull << 22, std::min<uint64_t>(bucket_cap_ / 8, 1ull << 28));
+    // first guess: an eighth of a pair per (key tile, partner) of the run
+    if (!cap) cap = std::max<uint64_t>(1ull << 22, std::min<uint64_t>(bucket_cap_ * (kSegCols / 8), 1ull << 28));
     ensure_capacity(cap, false);
     log_ = std::getenv("CFLR_LOG") != nullptr;
     uint32_t waves = opts_.grid_waves ? opts_.grid_waves : ctx->grid_waves_tuned;
@@ -276,11 +279,11 @@ void Run::ensure_capacity(uint64_t pairs, bool keep) {
     if (ap_cap_ >= limit) throw Error(CFLR_ENOMEM, "new-pair buffer at its 2^32 limit");
     pairs = std::min(pairs, limit);
     DevPool *pool = ctx_->pool.get();
-    DevBuf *bufs[5] = {&d_ap_key_, &d_ap_i_, &d_ap_j_, &d_rs_, &d_cs_};
-    const size_t width[5] = {4, 4, 4, 8, 8};
-    for (int q = 0; q < 5; q++) {
+    DevBuf *bufs[7] = {&d_ap_key_, &d_ap_i_, &d_ap_j_, &d_rs_, &d_cs_, &d_rs_stage_, &d_cs_stage_};
+    const size_t width[7] = {4, 4, 4, 8, 8, 8, 8};
+    for (int q = 0; q < 7; q++) {
         DevBuf nb(pool, pairs * width[q]);
-        if (keep && bufs[q]->ptr)
+        if (keep && q < 5 && bufs[q]->ptr)
             hip_check(hipMemcpyAsync(nb.ptr, bufs[q]->ptr, ap_cap_ * width[q], hipMemcpyDeviceToDevice, s_),
                       "D2D");
         hip_check(hipStreamSynchronize(s_), "sync");
@@ -475,6 +478,8 @@ void Run::sort_appended() {
     S.ccnt = d_ccnt_.as<uint32_t>();
     S.rs = d_rs_.as<uint64_t>();
     S.cs = d_cs_.as<uint64_t>();
+    S.rs_stage = d_rs_stage_.as<uint64_t>();
+    S.cs_stage = d_cs_stage_.as<uint64_t>();
     S.halt = reinterpret_cast<uint32_t *>(d_counters_.as<unsigned long long>() + 3);
     hip_check(launch_sort(S, bucket_hi(), d_bsum_.as<uint32_t>(), ctx_->num_cu * 8, s_), "sort");
     // the appended pairs are consumed

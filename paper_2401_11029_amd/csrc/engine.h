@@ -212,7 +212,7 @@ class Run {
     DevBuf d_units_;
     uint32_t nent_ = 0, nunit_ = 0, unit_split_ = 0;  // units [0, unit_split_) are row parts
     DevBuf d_rcnt_, d_ccnt_, d_bsum_;
-    DevBuf d_ap_key_, d_ap_i_, d_ap_j_, d_rs_, d_cs_;
+    DevBuf d_ap_key_, d_ap_i_, d_ap_j_, d_rs_, d_cs_, d_rs_stage_, d_cs_stage_;
     uint64_t ap_cap_ = 0;
     DevBuf d_counters_;  // [0] ap_count, [1] items taken (row parts), [2] algo_bytes, [3] halt (u32),
                          // [4] items taken (column parts)

@@ -66,9 +66,10 @@ struct InstDev {
     uint32_t n;        // vertices
     uint32_t S;        // segments per row; Wp = 64 * S
     uint32_t bbase;    // first sort bucket of this instance: in the row-order
-                       // counters, matrix x (row rank r), key tile t, partner k
-                       // is bucket bbase + (r * key_tiles(n) + t) * n + k; the
-                       // column-order counters use the column rank
+                       // counters, matrix x (row rank r), key tile t, partner
+                       // segment s (partners s*4096 .. s*4096+4095) is bucket
+                       // bbase + (r * key_tiles(n) + t) * S + s; the column-order
+                       // counters use the column rank
     uint32_t mat_off;  // first MatDev of this instance
 };
 
@@ -132,6 +133,7 @@ struct SortArgs {
     const unsigned long long *ap_count;
     uint64_t ap_cap;
     uint32_t *rcnt, *ccnt;       // per bucket: counts -> inclusive scan -> starts (after scatter)
+    uint64_t *rs_stage, *cs_stage;  // pairs grouped by bucket (second pass: ordered by partner)
     uint64_t *rs, *cs;
     const uint32_t *halt;
 };

@@ -27,6 +27,8 @@
 //   readout         bit rows -> (i, j) pairs in (i, j) order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace cflr {
@@ -505,8 +507,8 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs A) {
         if (u < A.nunit && !*A.halt) {
             UnitDev &U = A.units[u];
             const uint32_t *ptr = U.e.part == 0 ? A.rptr : A.cptr;
-            const uint64_t b0 = U.I.bbase + ((uint64_t)U.rank * key_tiles(U.I.n) + U.tile) * U.I.n;
-            const uint32_t s = ptr[b0], f = ptr[b0 + U.I.n];
+            const uint64_t b0 = U.I.bbase + ((uint64_t)U.rank * key_tiles(U.I.n) + U.tile) * U.I.S;
+            const uint32_t s = ptr[b0], f = ptr[b0 + U.I.S];
             U.start = s;
             U.cnt = f - s;
             items = ((uint64_t)(f - s) + A.chunk - 1) / A.chunk * U.I.S;
@@ -576,7 +578,8 @@ __device__ __forceinline__ LaneRun lane_run(uint32_t rid) {
 
 // Buckets of entry x in the two sort orders (kHole when the entry is a hole
 // or its matrix needs that order for no production): row order groups pair
-// (i, j) by (tile of i, j), column order by (tile of j, i).
+// (i, j) by (tile of i, segment of j), column order by (tile of j, segment
+// of i); a second pass orders each bucket by the partner (j, resp. i).
 __device__ __forceinline__ void entry_rows(const SortArgs &A, uint64_t x, uint64_t n, uint32_t *r, uint32_t *c,
                                            uint32_t *i, uint32_t *j) {
     *r = *c = kHole;
@@ -586,11 +589,11 @@ __device__ __forceinline__ void entry_rows(const SortArgs &A, uint64_t x, uint64
     const InstDev I = A.inst[key_slot(key)];
     const MatDev &M = A.mats[I.mat_off + key_mat(key)];
     const uint32_t need = M.sort;
-    const uint64_t span = (uint64_t)key_tiles(I.n) * I.n;  // buckets of one matrix
+    const uint64_t tiles = key_tiles(I.n);
     *i = A.ap_i[x];
     *j = A.ap_j[x];
-    if (need & kSortRows) *r = (uint32_t)(I.bbase + M.rrank * span + (uint64_t)(*i / kTileKeys) * I.n + *j);
-    if (need & kSortCols) *c = (uint32_t)(I.bbase + M.crank * span + (uint64_t)(*j / kTileKeys) * I.n + *i);
+    if (need & kSortRows) *r = (uint32_t)(I.bbase + ((uint64_t)M.rrank * tiles + *i / kTileKeys) * I.S + *j / kSegCols);
+    if (need & kSortCols) *c = (uint32_t)(I.bbase + ((uint64_t)M.crank * tiles + *j / kTileKeys) * I.S + *i / kSegCols);
 }
 
 __global__ __launch_bounds__(256) void count_kernel(SortArgs A) {
@@ -622,8 +625,77 @@ __global__ __launch_bounds__(256) void scatter_kernel(SortArgs A) {
         if (cr.head && c != kHole) q0 = atomicSub(&A.ccnt[c], cr.len) - cr.len;
         p0 = __shfl(p0, rr.first, 64) + (lane - rr.first);
         q0 = __shfl(q0, cr.first, 64) + (lane - cr.first);
-        if (r != kHole) A.rs[p0] = ((uint64_t)i << 32) | j;
-        if (c != kHole) A.cs[q0] = ((uint64_t)j << 32) | i;
+        if (r != kHole) A.rs_stage[p0] = ((uint64_t)i << 32) | j;
+        if (c != kHole) A.cs_stage[q0] = ((uint64_t)j << 32) | i;
+    }
+}
+
+// Second pass: each bucket (key tile, partner segment) of each order is
+// ordered by the partner (the low 32 bits of a packed pair; its offset in
+// the segment, 12 bits) so that the pairs sharing a partner are adjacent;
+// their relative order is arbitrary.  One workgroup per bucket: up to 256
+// pairs are ranked by comparison in LDS, larger buckets by a counting sort
+// over the 4096 partners of the segment (LDS histogram, block scan).
+constexpr uint32_t kSegSortThreads = 1024, kSegSortSmall = 256;
+__global__ __launch_bounds__(kSegSortThreads) void segsort_kernel(SortArgs A, uint32_t nbuckets) {
+    if (*A.halt) return;
+    __shared__ uint32_t hist[kSegCols];
+    __shared__ uint64_t small[kSegSortSmall];
+    __shared__ uint32_t wsum[kSegSortThreads / kWave];
+    const uint32_t *ptr = blockIdx.y ? A.ccnt : A.rcnt;
+    const uint64_t *src = blockIdx.y ? A.cs_stage : A.rs_stage;
+    uint64_t *dst = blockIdx.y ? A.cs : A.rs;
+    const uint32_t t = threadIdx.x, lane = lane_id(), wave = t / kWave;
+    for (uint32_t b = blockIdx.x; b < nbuckets; b += gridDim.x) {
+        const uint32_t s = ptr[b], e = ptr[b + 1];
+        if (e <= s) continue;
+        const uint32_t m = e - s;
+        if (m <= kSegSortSmall) {
+            if (t < m) small[t] = src[s + t];
+            __syncthreads();
+            if (t < m) {
+                const uint64_t v = small[t];
+                const uint32_t p = (uint32_t)v & (kSegCols - 1);
+                uint32_t rank = 0;
+                for (uint32_t u = 0; u < m; u++) {
+                    const uint32_t pu = (uint32_t)small[u] & (kSegCols - 1);
+                    rank += (pu < p || (pu == p && u < t)) ? 1u : 0u;
+                }
+                dst[s + rank] = v;
+            }
+            __syncthreads();
+            continue;
+        }
+        for (uint32_t x = t; x < kSegCols; x += kSegSortThreads) hist[x] = 0;
+        __syncthreads();
+        for (uint32_t q = s + t; q < e; q += kSegSortThreads)
+            atomicAdd(&hist[(uint32_t)src[q] & (kSegCols - 1)], 1u);
+        __syncthreads();
+        // exclusive scan of the histogram: four bins per thread
+        constexpr uint32_t kPer = kSegCols / kSegSortThreads;
+        uint32_t c[kPer], sum = 0;
+#pragma unroll
+        for (uint32_t z = 0; z < kPer; z++) {
+            c[z] = hist[t * kPer + z];
+            sum += c[z];
+        }
+        uint32_t wtot;
+        const uint32_t wex = wave_excl_scan(sum, &wtot);
+        if (lane == 0) wsum[wave] = wtot;
+        __syncthreads();
+        uint32_t off = wex;
+        for (uint32_t w = 0; w < wave; w++) off += wsum[w];
+#pragma unroll
+        for (uint32_t z = 0; z < kPer; z++) {
+            hist[t * kPer + z] = off;
+            off += c[z];
+        }
+        __syncthreads();
+        for (uint32_t q = s + t; q < e; q += kSegSortThreads) {
+            const uint64_t v = src[q];
+            dst[s + atomicAdd(&hist[(uint32_t)v & (kSegCols - 1)], 1u)] = v;
+        }
+        __syncthreads();
     }
 }
 
@@ -966,6 +1038,11 @@ hipError_t launch_sort(const SortArgs &A, uint64_t nbuckets, uint32_t *bsum, uin
     CFLR_LAUNCH_CHECK();
     scatter_kernel<<<sort_grid, 256, 0, s>>>(A);
     CFLR_LAUNCH_CHECK();
+    if (nbuckets) {
+        const uint32_t g = (uint32_t)std::min<uint64_t>(nbuckets, sort_grid);
+        segsort_kernel<<<dim3(g, 2), kSegSortThreads, 0, s>>>(A, (uint32_t)nbuckets);
+        CFLR_LAUNCH_CHECK();
+    }
     return hipSuccess;
 }
 

@@ -174,9 +174,12 @@ cflr_status cflr_server_create(cflr_ctx *ctx, uint64_t hbm_budget_bytes, uint32_
         if (opts) s->opts = *opts;
         s->budget = hbm_budget_bytes;
         s->max_slots = max_slots;
-        // sort buckets: an instance needs at most 1/16 of its footprint in
-        // buckets; capped at 2^29 (two 2 GiB counter arrays)
-        uint64_t buckets = std::min<uint64_t>(1ull << 29, std::max<uint64_t>(1ull << 20, hbm_budget_bytes / 16));
+        // sort buckets: an instance needs far less than 1/65536 of its
+        // footprint in buckets (one per key tile and 4096-partner segment of
+        // a sorted matrix); capped at 2^26.  The new-pair buffer starts at
+        // 2^26 pairs unless the options say otherwise (it grows on overflow).
+        uint64_t buckets = std::min<uint64_t>(1ull << 26, std::max<uint64_t>(1ull << 20, hbm_budget_bytes / 65536));
+        if (!s->opts.delta_capacity) s->opts.delta_capacity = 1ull << 26;
         s->run = std::make_unique<Run>(ctx, s->opts, buckets, max_slots);
         s->worker = std::thread([p = s.get()] { p->loop(); });
         *out = s.release();
