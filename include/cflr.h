@@ -180,11 +180,15 @@ cflr_status cflr_solve(cflr_ctx *ctx, const cflr_grammar *g, const cflr_graph *g
                        const cflr_opts *opts, cflr_result **out);
 
 /* Batched form: graphs[k] is solved with grammars[k] (the same grammar may be
- * passed for every k).  All instances advance together: the product of a
- * round is two launches (row parts, then column parts) over every (graph,
- * production, tile of new pairs), so many uneven graphs share the device.  outs: caller array of count
- * pointers, each set to a result (or NULL on failure).  Results are
- * identical to cflr_solve of each graph alone. */
+ * passed for every k).  Admitted instances advance together: the product of
+ * a round is two launches (row parts, then column parts) over every (graph,
+ * production, tile of new pairs), so many uneven graphs share the device.
+ * Graphs are admitted in order while their matrices fit in 70 % of the free
+ * device memory and their (key tile, partner) slots -- key tiles of 256
+ * vertices x n partners per sorted matrix -- sum to at most the larger of
+ * 2^28 and the largest single graph's; the others wait for retirements.
+ * outs: caller array of count pointers, each set to a result (or NULL on
+ * failure).  Results are identical to cflr_solve of each graph alone. */
 cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
                              const cflr_graph *const *graphs, uint32_t count,
                              const cflr_opts *opts, cflr_result **outs);
@@ -222,7 +226,10 @@ void cflr_result_free(cflr_result *r);
  * requests.  Requests may use different grammars.  Results are identical to
  * cflr_solve of the same input.  A request whose footprint alone exceeds the
  * budget fails with ENOMEM.  Besides the budget the server holds the sort's
- * bucket counters: 8 bytes per bucket, budget / 16 buckets (at most 2^29).
+ * bucket counters (8 bytes per bucket, budget / 65536 buckets, at least 2^20
+ * and at most 2^26) and a new-pair buffer of 44 bytes per pair, 2^26 pairs
+ * to start with unless opts->delta_capacity says otherwise (it grows when a
+ * round overflows it).
  * The server uses ctx's device and stream; do not use ctx from another
  * thread while the server lives. */
 cflr_status cflr_server_create(cflr_ctx *ctx, uint64_t hbm_budget_bytes, uint32_t max_slots,

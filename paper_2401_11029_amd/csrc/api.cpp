@@ -350,15 +350,23 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
         uint64_t in_use = 0;
         uint32_t next = 0;
         cflr_status status = CFLR_OK;
-        std::vector<uint64_t> fp(count);
-        for (uint32_t k = 0; k < count; k++) fp[k] = instance_footprint(grammars[k]->low, graphs[k]->n);
+        std::vector<uint64_t> fp(count), wt(count);
+        uint64_t max_wt = 0;
+        for (uint32_t k = 0; k < count; k++) {
+            fp[k] = instance_footprint(grammars[k]->low, graphs[k]->n);
+            wt[k] = instance_pair_slots(grammars[k]->low, graphs[k]->n);
+            max_wt = std::max(max_wt, wt[k]);
+        }
+        // running instances: their (key tile, partner) slots sum to at most this
+        const uint64_t wt_cap = std::max<uint64_t>(max_wt, 0x0FFFFFFFull);
+        uint64_t wt_in = 0;
         const bool progress = std::getenv("CFLR_PROGRESS") != nullptr;
         uint32_t finished = 0;
         while (true) {
             // admit
             while (next < count) {
                 uint64_t need = fp[next];
-                if (run.size() && in_use + need > budget) break;
+                if (run.size() && (in_use + need > budget || wt_in + wt[next] > wt_cap)) break;
                 auto inst = make_instance(ctx, grammars[next]->low, graphs[next]);
                 try {
                     run.add(inst);
@@ -368,6 +376,7 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
                 }
                 all[next] = inst;
                 in_use += need;
+                wt_in += wt[next];
                 next++;
             }
             if (!run.size()) break;
@@ -384,6 +393,7 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
                 }
                 run.remove(ip.get());
                 in_use -= ip->footprint;
+                wt_in -= instance_pair_slots(ip->low, ip->n);
                 ip->stats.rounds = ip->rounds;
                 compact_instance(*ip);
             }

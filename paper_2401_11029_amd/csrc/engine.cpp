@@ -146,6 +146,11 @@ uint64_t instance_buckets(const Lowered &low, uint32_t n) {
     return std::max(rows, cols) * key_tiles(n) * segs;
 }
 
+uint64_t instance_pair_slots(const Lowered &low, uint32_t n) {
+    const uint64_t segs = std::max<uint64_t>(1, ((uint64_t)n + kSegCols - 1) / kSegCols);
+    return instance_buckets(low, n) / segs * n;
+}
+
 std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const cflr_graph *g) {
     if (low.nmat() > kMaxMats) throw Error(CFLR_EUNSUPPORTED, "grammar needs more than 65536 matrices");
     auto inst = std::make_shared<Instance>();

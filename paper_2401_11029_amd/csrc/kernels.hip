@@ -11,19 +11,23 @@
 // first product already covers, and saves materialising M_old.
 //
 // Kernels:
-//   product_kernel  persistent; one wave per work item = (instance,
-//                   production, part, block of 64 new pairs, row segment).
-//                   Part 0 ORs the B row segments named by a block of dA pairs
-//                   (i, k) into a per-lane register accumulator for row i;
-//                   part 1 ORs the A column segments named by dB pairs (k, j)
-//                   into the accumulator for column j.  The flush masks the
-//                   accumulator with M_c, ORs it in with 64-bit atomics whose
-//                   return value identifies the genuinely new bits, keeps the
-//                   other layout in step, and appends the new pairs.
+//   product_kernel  persistent; one workgroup of 16 waves per work item =
+//                   (instance, production, part, key tile of 256 rows or
+//                   columns, row segment of 4096 columns, chunk of new pairs).
+//                   The tile's accumulators live in LDS; part 0 ORs the B row
+//                   segments named by the tile's dA pairs (i, k) into the
+//                   accumulator of row i, part 1 the A column segments named
+//                   by dB pairs (k, j) into that of column j, skipping
+//                   partner segments whose mask says they are zero.  The
+//                   flush masks each accumulator with M_c, ORs it in with
+//                   64-bit atomics whose return value identifies the
+//                   genuinely new bits, keeps the other layout and the
+//                   segment masks in step, and appends the new pairs.
 //   seed kernels    edges and eps rules -> initial pairs (Algorithm 1's
 //                   seeding, and (i, i) for every x -> eps).
-//   delta kernels   counting sort of the appended pairs into row order and
-//                   column order (the next round's dA and dB).
+//   sort kernels    two-level counting sort of the appended pairs into row
+//                   order and column order, grouped by (key tile, partner)
+//                   (the next round's dA and dB).
 //   readout         bit rows -> (i, j) pairs in (i, j) order.
 #include <hip/hip_runtime.h>
 
