@@ -185,7 +185,7 @@ cflr_status cflr_solve(cflr_ctx *ctx, const cflr_grammar *g, const cflr_graph *g
  * production, tile of new pairs), so many uneven graphs share the device.
  * Graphs are admitted in order while their matrices fit in 70 % of the free
  * device memory and their (key tile, partner) slots -- key tiles of 256
- * vertices x n partners per sorted matrix -- sum to at most the larger of
+ * vertices x n partners per matrix -- sum to at most the larger of
  * 2^28 and the largest single graph's; the others wait for retirements.
  * outs: caller array of count pointers, each set to a result (or NULL on
  * failure).  Results are identical to cflr_solve of each graph alone. */
@@ -220,16 +220,21 @@ void cflr_result_free(cflr_result *r);
 /* ---- server (continuous batching) --------------------------------------
  * A worker thread keeps the device busy with every admitted request: between
  * rounds it admits queued requests while the estimated device footprint of
- * the running ones plus the new one stays within hbm_budget_bytes and fewer
- * than max_slots run, and retires requests that converged.  Each round's
+ * the running ones plus the new one stays within hbm_budget_bytes, their
+ * (key tile, partner) slots (key tiles of 256 vertices x n partners per
+ * matrix) stay within hbm_budget_bytes / 16 (between 2^20 and 2^29), and
+ * fewer than max_slots run, and retires requests that converged.  Each round's
  * product is two launches (row parts, then column parts) over all running
  * requests.  Requests may use different grammars.  Results are identical to
  * cflr_solve of the same input.  A request whose footprint alone exceeds the
  * budget fails with ENOMEM.  Besides the budget the server holds the sort's
  * bucket counters (8 bytes per bucket, budget / 65536 buckets, at least 2^20
- * and at most 2^26) and a new-pair buffer of 44 bytes per pair, 2^26 pairs
- * to start with unless opts->delta_capacity says otherwise (it grows when a
- * round overflows it).
+ * and at most 2^26) and a new-pair buffer of 44 bytes per pair, starting at
+ * the size earlier solves on ctx grew it to (else 2^26 pairs) unless
+ * opts->delta_capacity says otherwise (it grows when a round overflows it).
+ * It also admits a request only while the running requests' (key tile,
+ * partner) slots -- key tiles of 256 vertices x n partners per matrix --
+ * stay within hbm_budget_bytes / 16 (between 2^20 and 2^29).
  * The server uses ctx's device and stream; do not use ctx from another
  * thread while the server lives. */
 cflr_status cflr_server_create(cflr_ctx *ctx, uint64_t hbm_budget_bytes, uint32_t max_slots,

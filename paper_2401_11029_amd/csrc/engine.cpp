@@ -147,8 +147,7 @@ uint64_t instance_buckets(const Lowered &low, uint32_t n) {
 }
 
 uint64_t instance_pair_slots(const Lowered &low, uint32_t n) {
-    const uint64_t segs = std::max<uint64_t>(1, ((uint64_t)n + kSegCols - 1) / kSegCols);
-    return instance_buckets(low, n) / segs * n;
+    return (uint64_t)low.nmat() * key_tiles(n) * n;
 }
 
 std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const cflr_graph *g) {

@@ -154,9 +154,9 @@ uint64_t instance_footprint(const Lowered &low, uint32_t n);
 // Sort buckets of such an instance: per sorted matrix, key tiles x partner
 // segments.
 uint64_t instance_buckets(const Lowered &low, uint32_t n);
-// (key tile, partner) slots of its sorted matrices: a batch admits instances
+// (key tile, partner) slots of all its matrices: a batch admits instances
 // while these sum to at most max(largest, 2^28), which keeps one round's new
-// pairs well inside the 2^32-entry new-pair buffer.
+// pairs inside the 2^32-entry new-pair buffer.
 uint64_t instance_pair_slots(const Lowered &low, uint32_t n);
 
 std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const cflr_graph *g);

@@ -36,6 +36,7 @@ struct Request {
     std::string error;
     std::shared_ptr<Instance> inst;
     uint64_t footprint = 0;
+    uint64_t slots = 0;  // (key tile, partner) slots of its matrices (instance_pair_slots)
 };
 
 }  // namespace
@@ -55,6 +56,7 @@ struct cflr_server {
     bool stop = false;
     uint64_t next_ticket = 1;
     uint64_t in_use = 0;
+    uint64_t slots_in_use = 0, slot_cap = 0;  // running requests' pair slots, and their bound
     std::unique_ptr<Run> run;
     std::string fatal;
 
@@ -69,7 +71,7 @@ void cflr_server::loop() {
             std::unique_lock<std::mutex> lk(mu);
             cv_work.wait(lk, [&] { return stop || !queue.empty() || !running.empty(); });
             if (stop && queue.empty() && running.empty()) break;
-            uint64_t planned = in_use;
+            uint64_t planned = in_use, planned_slots = slots_in_use;
             size_t slots = running.size();
             while (!queue.empty() && slots < max_slots) {
                 Request *r = queue.front();
@@ -82,10 +84,13 @@ void cflr_server::loop() {
                     cv_done.notify_all();
                     continue;
                 }
-                if (slots && planned + r->footprint > budget) break;
+                // the pair-slot bound keeps one round's new pairs inside the
+                // 2^32-entry buffer and a round short enough for latency
+                if (slots && (planned + r->footprint > budget || planned_slots + r->slots > slot_cap)) break;
                 queue.pop_front();
                 admit.push_back(r);
                 planned += r->footprint;
+                planned_slots += r->slots;
                 slots++;
             }
         }
@@ -98,6 +103,7 @@ void cflr_server::loop() {
                 r->t_admit = now_s();
                 running[inst.get()] = r;
                 in_use += r->footprint;
+                slots_in_use += r->slots;
             } catch (const Error &e) {
                 std::lock_guard<std::mutex> lk(mu);
                 if (e.status == CFLR_ENOMEM && !running.empty()) {
@@ -128,6 +134,7 @@ void cflr_server::loop() {
                 Request *r = running[ip.get()];
                 running.erase(ip.get());
                 in_use -= r->footprint;
+                slots_in_use -= r->slots;
                 r->status = st;
                 if (st != CFLR_OK) r->error = "round limit reached before the fixpoint";
                 r->t_finish = now_s();
@@ -173,13 +180,15 @@ cflr_status cflr_server_create(cflr_ctx *ctx, uint64_t hbm_budget_bytes, uint32_
         cflr_opts_default(&s->opts);
         if (opts) s->opts = *opts;
         s->budget = hbm_budget_bytes;
+        s->slot_cap = std::min<uint64_t>(1ull << 29, std::max<uint64_t>(1ull << 20, hbm_budget_bytes / 16));
         s->max_slots = max_slots;
         // sort buckets: an instance needs far less than 1/65536 of its
         // footprint in buckets (one per key tile and 4096-partner segment of
         // a sorted matrix); capped at 2^26.  The new-pair buffer starts at
-        // 2^26 pairs unless the options say otherwise (it grows on overflow).
+        // the size earlier solves on ctx grew it to, else at 2^26 pairs,
+        // unless the options say otherwise (it grows on overflow).
         uint64_t buckets = std::min<uint64_t>(1ull << 26, std::max<uint64_t>(1ull << 20, hbm_budget_bytes / 65536));
-        if (!s->opts.delta_capacity) s->opts.delta_capacity = 1ull << 26;
+        if (!s->opts.delta_capacity && !ctx->delta_capacity_hint) s->opts.delta_capacity = 1ull << 26;
         s->run = std::make_unique<Run>(ctx, s->opts, buckets, max_slots);
         s->worker = std::thread([p = s.get()] { p->loop(); });
         *out = s.release();
@@ -199,6 +208,7 @@ cflr_status cflr_server_submit(cflr_server *s, const cflr_grammar *g, const cflr
     r->graph = graph;
     r->t_submit = now_s();
     r->footprint = instance_footprint(g->low, graph->n);
+    r->slots = instance_pair_slots(g->low, graph->n);
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return CFLR_EDEVICE;
     r->ticket = s->next_ticket++;
