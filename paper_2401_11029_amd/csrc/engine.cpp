@@ -368,6 +368,8 @@ void Run::add(const std::shared_ptr<Instance> &inst) {
     A.ap_count = d_counters_.as<unsigned long long>();
     A.ap_cap = ap_cap_;
     A.inst_new = d_inst_new_.as<unsigned long long>();
+    A.rcnt = d_rcnt_.as<uint32_t>();
+    A.ccnt = d_ccnt_.as<uint32_t>();
     A.inst_overflow = d_inst_over_.as<uint32_t>();
     hip_check(launch_seed(A, s_), "seed");
     hip_check(hipMemcpyAsync(h_new_ + slot, d_inst_new_.as<unsigned long long>() + (uint64_t)slot * kCountShards, 8,
@@ -398,10 +400,17 @@ uint64_t Run::bucket_hi() const {
 void Run::remove(Instance *inst) {
     for (size_t k = 0; k < insts_.size(); k++) {
         if (insts_[k].get() == inst) {
-            if (!inst->done)
+            if (!inst->done) {
+                // its pending pairs become holes, and the counts the flush
+                // made for them leave its bucket range (which may be reused)
                 hip_check(launch_purge_slot(d_ap_key_.as<uint32_t>(), d_counters_.as<unsigned long long>(),
                                             ap_cap_, inst->slot, ctx_->num_cu * 4, s_),
                           "purge");
+                hip_check(launch_zero_counts(d_rcnt_.as<uint32_t>() + inst->bbase, d_ccnt_.as<uint32_t>() + inst->bbase,
+                                             instance_buckets(inst->low, inst->n),
+                                             reinterpret_cast<uint32_t *>(d_counters_.as<unsigned long long>() + 3), s_),
+                          "zero counts");
+            }
             free_buckets(inst->bbase, instance_buckets(inst->low, inst->n));
             insts_.erase(insts_.begin() + (long)k);
             dirty_ = true;
@@ -504,6 +513,10 @@ void Run::read_flags() {
 // every pair takes part in every round), done before a round's sort.
 void Run::extract_all_pairs() {
     hip_check(launch_fill_u64(d_counters_.as<unsigned long long>(), 1, 0, s_), "fill");
+    // the pending pairs are dropped (every pair of M is new again): so are their counts
+    hip_check(launch_zero_counts(d_rcnt_.as<uint32_t>(), d_ccnt_.as<uint32_t>(), bucket_hi() + 1,
+                                 reinterpret_cast<uint32_t *>(d_counters_.as<unsigned long long>() + 3), s_),
+              "zero counts");
     uint64_t total_pairs = 0;
     for (auto &ip : insts_) {
         DevBuf cnt(ctx_->pool.get(), std::max<uint32_t>(1, ip->n) * 4ull);
@@ -525,13 +538,14 @@ void Run::extract_all_pairs() {
         hip_check(launch_extract_all(dm.as<MatDev>(), I, ip->slot, ip->low.nmat(), d_ap_key_.as<uint32_t>(),
                                      d_ap_i_.as<uint32_t>(), d_ap_j_.as<uint32_t>(),
                                      d_counters_.as<unsigned long long>(), ap_cap_,
-                                     d_inst_over_.as<uint32_t>() + ip->slot, s_),
+                                     d_inst_over_.as<uint32_t>() + ip->slot, d_rcnt_.as<uint32_t>(),
+                                     d_ccnt_.as<uint32_t>(), s_),
                   "extract");
         hip_check(hipStreamSynchronize(s_), "sync");
     }
 }
 
-void Run::enqueue_product(bool timed) {
+void Run::enqueue_product(bool timed, bool rerun) {
     unsigned long long *counters = d_counters_.as<unsigned long long>();
     uint32_t *halt = reinterpret_cast<uint32_t *>(counters + 3);
     if (!nunit_) return;
@@ -545,7 +559,17 @@ void Run::enqueue_product(bool timed) {
     P.work_counter1 = counters + 4;
     P.halt = halt;
     P.chunk = opts_.chunk_pairs ? opts_.chunk_pairs : kChunkPairs;
-    hip_check(launch_prep(P, s_), "prep");
+    P.ap_cap = ap_cap_;
+    if (!rerun) {
+        // the prep reads the bucket starts of this round's new pairs; then
+        // the counters are cleared and the product counts the next round's
+        hip_check(launch_prep(P, s_), "prep");
+        hip_check(launch_zero_counts(d_rcnt_.as<uint32_t>(), d_ccnt_.as<uint32_t>(), bucket_hi() + 1, halt, s_),
+                  "zero counts");
+    } else {
+        hip_check(launch_fill_u64(counters + 1, 1, 0, s_), "fill");
+        hip_check(launch_fill_u64(counters + 4, 1, 0, s_), "fill");
+    }
     if (opts_.count_traffic && touched_bits_)
         hip_check(launch_fill_u32(d_touched_.as<uint32_t>(), (touched_bits_ + 31) / 32, 0, s_), "fill");
     ProductArgs A{};
@@ -566,6 +590,8 @@ void Run::enqueue_product(bool timed) {
     A.touched_off = d_touched_off_.as<uint64_t>();
     A.algo_bytes = counters + 2;
     A.chunk = P.chunk;
+    A.rcnt = d_rcnt_.as<uint32_t>();
+    A.ccnt = d_ccnt_.as<uint32_t>();
     if (timed) hip_check(hipEventRecord(ev0_, s_), "event");
     // the row parts, then the column parts (a pair derived by both is then
     // reported once: by the row part)
@@ -615,7 +641,7 @@ void Run::recover() {
         copy_sync(counters, &v, 8, hipMemcpyHostToDevice, s_);
         hip_check(launch_fill_u32(halt, 1, 0, s_), "fill");
         hip_check(launch_fill_u32(d_inst_over_.as<uint32_t>(), max_inst_, 0, s_), "fill");
-        enqueue_product(false);
+        enqueue_product(false, true);
         enqueue_round_end();
         read_flags();
     }

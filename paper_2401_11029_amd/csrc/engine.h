@@ -198,7 +198,9 @@ class Run {
     void read_flags();
     uint64_t bucket_hi() const;
     void extract_all_pairs();
-    void enqueue_product(bool timed);
+    // rerun: the product of an overflowing round again (the work table and
+    // the counts of the pairs appended so far are kept)
+    void enqueue_product(bool timed, bool rerun = false);
     void enqueue_round_end();
     void enqueue_round(bool timed);
     void recover();

@@ -73,6 +73,15 @@ struct InstDev {
     uint32_t mat_off;  // first MatDev of this instance
 };
 
+// Sort buckets of pair (i, j) of matrix M: row order by (key tile of i,
+// partner segment of j), column order by (key tile of j, partner segment of i).
+__host__ __device__ inline uint32_t row_bucket(const InstDev &I, const MatDev &M, uint32_t i, uint32_t j) {
+    return (uint32_t)(I.bbase + ((uint64_t)M.rrank * key_tiles(I.n) + i / kTileKeys) * I.S + j / kSegCols);
+}
+__host__ __device__ inline uint32_t col_bucket(const InstDev &I, const MatDev &M, uint32_t i, uint32_t j) {
+    return (uint32_t)(I.bbase + ((uint64_t)M.crank * key_tiles(I.n) + j / kTileKeys) * I.S + i / kSegCols);
+}
+
 // One (instance, production, part) of a round; part 0 = rows of the new
 // pairs of a times B (row by row), part 1 = A times the new pairs of b
 // (column by column).  The parts of a round run as two launches, every
@@ -114,6 +123,7 @@ struct ProductArgs {
     const uint64_t *touched_off;   // per instance: bit offset of its matrices
     unsigned long long *algo_bytes;
     uint32_t chunk;  // pairs per work item at most (as in the prep)
+    uint32_t *rcnt, *ccnt;  // sort counters: the new pairs are counted into their buckets
 };
 
 struct PrepArgs {
@@ -124,6 +134,7 @@ struct PrepArgs {
     unsigned long long *work_counter0, *work_counter1;  // reset for the two launches
     const uint32_t *halt;
     uint32_t chunk;  // pairs per work item at most
+    uint64_t ap_cap;  // sorted pairs the buffers hold (ranges are clamped to it)
 };
 
 struct SortArgs {
@@ -152,6 +163,7 @@ struct SeedArgs {
     uint64_t ap_cap;
     unsigned long long *inst_new;
     uint32_t *inst_overflow;
+    uint32_t *rcnt, *ccnt;  // sort counters (each seeded pair is counted)
 };
 
 // Per-instance round bookkeeping kept on the device, so that several rounds
@@ -171,6 +183,8 @@ hipError_t launch_prep(const PrepArgs &A, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *a, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long v, hipStream_t s);
 // counting sort of the appended pairs over buckets [0, nbuckets] (nbuckets + 1 counters)
+// zero the sort counters [0, len) of both orders (skipped once halted)
+hipError_t launch_zero_counts(uint32_t *rcnt, uint32_t *ccnt, uint64_t len, const uint32_t *halt, hipStream_t s);
 hipError_t launch_sort(const SortArgs &A, uint64_t nbuckets, uint32_t *bsum, uint32_t sort_grid,
                        hipStream_t s);
 uint32_t scan_block_count(uint64_t nbuckets);
@@ -183,7 +197,8 @@ hipError_t launch_seed(const SeedArgs &A, hipStream_t s);
 hipError_t launch_extract_all(const MatDev *mats, const InstDev &I, uint32_t slot, uint32_t nmat,
                               uint32_t *ap_key,
                               uint32_t *ap_i, uint32_t *ap_j, unsigned long long *ap_count,
-                              uint64_t ap_cap, uint32_t *overflow, hipStream_t s);
+                              uint64_t ap_cap, uint32_t *overflow, uint32_t *rcnt, uint32_t *ccnt,
+                              hipStream_t s);
 hipError_t launch_row_count(const uint64_t *R, uint32_t n, uint32_t S, uint32_t *cnt,
                             unsigned long long *total, hipStream_t s);
 hipError_t launch_row_write(const uint64_t *R, uint32_t n, uint32_t S, const uint32_t *cnt,

@@ -283,8 +283,25 @@ __device__ __forceinline__ void flush_keys(const ProductArgs &A, ProductShared &
             base += total;
         }
     }
+    // count the new pairs into next round's sort buckets: in the key's own
+    // order every pair of the item shares one bucket (key tile, this
+    // segment); in the other order lane l's pairs share (tile of its 64
+    // other indexes, segment of the key), four lanes per tile
+    const uint32_t x0 = (seg * kSegWords + lane) * 64;  // lane's first other index
+    const uint32_t need = Mc.sort;
+    uint32_t group = fresh;
+    group += (uint32_t)__shfl_xor((int)group, 1, 64);
+    group += (uint32_t)__shfl_xor((int)group, 2, 64);
     fresh = wave_sum(fresh);
-    if (fresh && lane == 0) {
+    if (!fresh) return;
+    if (COL) {
+        if ((need & kSortCols) && lane == 0) atomicAdd(&A.ccnt[col_bucket(I, Mc, x0, key0)], fresh);
+        if ((need & kSortRows) && (lane & 3) == 0 && group) atomicAdd(&A.rcnt[row_bucket(I, Mc, x0, key0)], group);
+    } else {
+        if ((need & kSortRows) && lane == 0) atomicAdd(&A.rcnt[row_bucket(I, Mc, key0, x0)], fresh);
+        if ((need & kSortCols) && (lane & 3) == 0 && group) atomicAdd(&A.ccnt[col_bucket(I, Mc, key0, x0)], group);
+    }
+    if (lane == 0) {
         const uint32_t shard = (blockIdx.x * kProdWaves + wave) % kCountShards;
         atomicAdd(&A.inst_new[(uint64_t)inst * kCountShards + shard], (unsigned long long)fresh);
         if (STATS) ch.bytes += 20ull * fresh;
@@ -385,9 +402,9 @@ __device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared
         uint64_t heads[kWinGroup], m[kWinGroup];
 #pragma unroll
         for (uint32_t q = 0; q < kWinGroup; q++) {
-            const bool valid = (uint64_t)p0 + (uint64_t)(win + q) * kWave + lane < p1;
             key[q] = (uint32_t)(pk[q] >> 32);
             k[q] = (uint32_t)pk[q];
+            const bool valid = (uint64_t)p0 + (uint64_t)(win + q) * kWave + lane < p1 && k[q] < I.n;
             const uint32_t kprev = __shfl_up(k[q], 1, 64);
             const bool head = valid && (lane == 0 || k[q] != kprev);
             heads[q] = __ballot(head);
@@ -496,6 +513,9 @@ __global__ __launch_bounds__(kProdWaves * kWave) void product_kernel(ProductArgs
 // One workgroup of 1024 threads: pairs and items of every unit (entry, key
 // tile) and the prefix sum of the items.
 __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs A) {
+    // once a round has halted, its work table must survive for the host's
+    // re-run of that round's product: a later captured round writes nothing
+    if (*A.halt) return;
     __shared__ uint64_t part[1024];
     __shared__ uint64_t carry;
     const uint32_t t = threadIdx.x;
@@ -508,11 +528,13 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs A) {
     for (uint32_t base = 0; base < A.nunit; base += 1024) {
         const uint32_t u = base + t;
         uint64_t items = 0;
-        if (u < A.nunit && !*A.halt) {
+        if (u < A.nunit) {
             UnitDev &U = A.units[u];
             const uint32_t *ptr = U.e.part == 0 ? A.rptr : A.cptr;
             const uint64_t b0 = U.I.bbase + ((uint64_t)U.rank * key_tiles(U.I.n) + U.tile) * U.I.S;
-            const uint32_t s = ptr[b0], f = ptr[b0 + U.I.S];
+            uint64_t s = ptr[b0], f = ptr[b0 + U.I.S];
+            if (f > A.ap_cap) f = A.ap_cap;
+            if (s > f) s = f;
             U.start = s;
             U.cnt = f - s;
             items = ((uint64_t)(f - s) + A.chunk - 1) / A.chunk * U.I.S;
@@ -593,24 +615,10 @@ __device__ __forceinline__ void entry_rows(const SortArgs &A, uint64_t x, uint64
     const InstDev I = A.inst[key_slot(key)];
     const MatDev &M = A.mats[I.mat_off + key_mat(key)];
     const uint32_t need = M.sort;
-    const uint64_t tiles = key_tiles(I.n);
     *i = A.ap_i[x];
     *j = A.ap_j[x];
-    if (need & kSortRows) *r = (uint32_t)(I.bbase + ((uint64_t)M.rrank * tiles + *i / kTileKeys) * I.S + *j / kSegCols);
-    if (need & kSortCols) *c = (uint32_t)(I.bbase + ((uint64_t)M.crank * tiles + *j / kTileKeys) * I.S + *i / kSegCols);
-}
-
-__global__ __launch_bounds__(256) void count_kernel(SortArgs A) {
-    if (*A.halt) return;
-    uint64_t n = *A.ap_count;
-    if (n > A.ap_cap) n = A.ap_cap;
-    for (uint64_t x0 = blockIdx.x * (uint64_t)blockDim.x; x0 < n; x0 += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t r, c, i = 0, j = 0;
-        entry_rows(A, x0 + threadIdx.x, n, &r, &c, &i, &j);
-        const LaneRun rr = lane_run(r), cr = lane_run(c);
-        if (rr.head && r != kHole) atomicAdd(&A.rcnt[r], rr.len);
-        if (cr.head && c != kHole) atomicAdd(&A.ccnt[c], cr.len);
-    }
+    if (need & kSortRows) *r = row_bucket(I, M, *i, *j);
+    if (need & kSortCols) *c = col_bucket(I, M, *i, *j);
 }
 
 __global__ __launch_bounds__(256) void scatter_kernel(SortArgs A) {
@@ -629,8 +637,10 @@ __global__ __launch_bounds__(256) void scatter_kernel(SortArgs A) {
         if (cr.head && c != kHole) q0 = atomicSub(&A.ccnt[c], cr.len) - cr.len;
         p0 = __shfl(p0, rr.first, 64) + (lane - rr.first);
         q0 = __shfl(q0, cr.first, 64) + (lane - cr.first);
-        if (r != kHole) A.rs_stage[p0] = ((uint64_t)i << 32) | j;
-        if (c != kHole) A.cs_stage[q0] = ((uint64_t)j << 32) | i;
+        // (positions outside the buffer would mean counts that disagree with
+        // the appended pairs; they are dropped rather than written)
+        if (r != kHole && p0 < A.ap_cap) A.rs_stage[p0] = ((uint64_t)i << 32) | j;
+        if (c != kHole && q0 < A.ap_cap) A.cs_stage[q0] = ((uint64_t)j << 32) | i;
     }
 }
 
@@ -651,7 +661,8 @@ __global__ __launch_bounds__(kSegSortThreads) void segsort_kernel(SortArgs A, ui
     uint64_t *dst = blockIdx.y ? A.cs : A.rs;
     const uint32_t t = threadIdx.x, lane = lane_id(), wave = t / kWave;
     for (uint32_t b = blockIdx.x; b < nbuckets; b += gridDim.x) {
-        const uint32_t s = ptr[b], e = ptr[b + 1];
+        uint32_t s = ptr[b], e = ptr[b + 1];
+        if (e > A.ap_cap) e = (uint32_t)A.ap_cap;
         if (e <= s) continue;
         const uint32_t m = e - s;
         if (m <= kSegSortSmall) {
@@ -811,6 +822,8 @@ __device__ __forceinline__ void seed_pair(const SeedArgs &A, uint32_t x, uint32_
         A.ap_key[p] = pair_key(A.inst, x);
         A.ap_i[p] = i;
         A.ap_j[p] = j;
+        if (M.sort & kSortRows) atomicAdd(&A.rcnt[row_bucket(A.I, M, i, j)], 1u);
+        if (M.sort & kSortCols) atomicAdd(&A.ccnt[col_bucket(A.I, M, i, j)], 1u);
     } else {
         atomicOr(&A.inst_overflow[A.inst], 1u);
     }
@@ -839,7 +852,8 @@ __global__ void seed_eps_kernel(SeedArgs A) {
 __global__ __launch_bounds__(64) void extract_all_kernel(const MatDev *mats, InstDev I, uint32_t slot,
                                                          uint32_t nmat, uint32_t *ap_key, uint32_t *ap_i,
                                                          uint32_t *ap_j, unsigned long long *ap_count,
-                                                         uint64_t ap_cap, uint32_t *overflow) {
+                                                         uint64_t ap_cap, uint32_t *overflow, uint32_t *rcnt,
+                                                         uint32_t *ccnt) {
     const uint32_t lane = lane_id();
     const uint64_t Wp = (uint64_t)I.S * kSegWords;
     const uint64_t rows = (uint64_t)nmat * I.n * I.S;
@@ -859,9 +873,12 @@ __global__ __launch_bounds__(64) void extract_all_kernel(const MatDev *mats, Ins
             uint32_t b = __ffsll((unsigned long long)v) - 1;
             v &= v - 1;
             if (p < ap_cap) {
+                const uint32_t j = (seg * kSegWords + lane) * 64 + b;
                 ap_key[p] = pair_key(slot, x);
                 ap_i[p] = i;
-                ap_j[p] = (seg * kSegWords + lane) * 64 + b;
+                ap_j[p] = j;
+                if (mats[x].sort & kSortRows) atomicAdd(&rcnt[row_bucket(I, mats[x], i, j)], 1u);
+                if (mats[x].sort & kSortCols) atomicAdd(&ccnt[col_bucket(I, mats[x], i, j)], 1u);
             } else {
                 atomicOr(overflow, 1u);
             }
@@ -1023,16 +1040,6 @@ hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long
 hipError_t launch_sort(const SortArgs &A, uint64_t nbuckets, uint32_t *bsum, uint32_t sort_grid,
                        hipStream_t s) {
     const uint64_t len = nbuckets + 1;
-    {
-        uint64_t g = (len + 255) / 256;
-        if (g > 8192) g = 8192;
-        fill_u32_unless_halted_kernel<<<(uint32_t)g, 256, 0, s>>>(A.rcnt, len, 0, A.halt);
-        CFLR_LAUNCH_CHECK();
-        fill_u32_unless_halted_kernel<<<(uint32_t)g, 256, 0, s>>>(A.ccnt, len, 0, A.halt);
-        CFLR_LAUNCH_CHECK();
-    }
-    count_kernel<<<sort_grid, 256, 0, s>>>(A);
-    CFLR_LAUNCH_CHECK();
     uint32_t nblk = (uint32_t)((len + kScanTile - 1) / kScanTile);
     scan_reduce_kernel<<<dim3(nblk, 2), 256, 0, s>>>(A.rcnt, A.ccnt, len, bsum, nblk, A.halt);
     CFLR_LAUNCH_CHECK();
@@ -1047,6 +1054,17 @@ hipError_t launch_sort(const SortArgs &A, uint64_t nbuckets, uint32_t *bsum, uin
         segsort_kernel<<<dim3(g, 2), kSegSortThreads, 0, s>>>(A, (uint32_t)nbuckets);
         CFLR_LAUNCH_CHECK();
     }
+    return hipSuccess;
+}
+
+hipError_t launch_zero_counts(uint32_t *rcnt, uint32_t *ccnt, uint64_t len, const uint32_t *halt, hipStream_t s) {
+    if (!len) return hipSuccess;
+    uint64_t g = (len + 255) / 256;
+    if (g > 8192) g = 8192;
+    fill_u32_unless_halted_kernel<<<(uint32_t)g, 256, 0, s>>>(rcnt, len, 0, halt);
+    CFLR_LAUNCH_CHECK();
+    fill_u32_unless_halted_kernel<<<(uint32_t)g, 256, 0, s>>>(ccnt, len, 0, halt);
+    CFLR_LAUNCH_CHECK();
     return hipSuccess;
 }
 
@@ -1094,12 +1112,13 @@ hipError_t launch_purge_slot(uint32_t *ap_key, const unsigned long long *ap_coun
 
 hipError_t launch_extract_all(const MatDev *mats, const InstDev &I, uint32_t slot, uint32_t nmat,
                               uint32_t *ap_key, uint32_t *ap_i, uint32_t *ap_j, unsigned long long *ap_count,
-                              uint64_t ap_cap, uint32_t *overflow, hipStream_t s) {
+                              uint64_t ap_cap, uint32_t *overflow, uint32_t *rcnt, uint32_t *ccnt,
+                              hipStream_t s) {
     uint64_t rows = (uint64_t)nmat * I.n * I.S;
     if (!rows) return hipSuccess;
     uint64_t g = rows < 65536 ? rows : 65536;
     extract_all_kernel<<<(uint32_t)g, 64, 0, s>>>(mats, I, slot, nmat, ap_key, ap_i, ap_j, ap_count, ap_cap,
-                                                  overflow);
+                                                  overflow, rcnt, ccnt);
     CFLR_LAUNCH_CHECK();
     return hipSuccess;
 }
