@@ -182,9 +182,10 @@ hipError_t launch_product(const ProductArgs &A, uint32_t grid, bool stats, hipSt
 hipError_t launch_prep(const PrepArgs &A, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *a, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long v, hipStream_t s);
-// counting sort of the appended pairs over buckets [0, nbuckets] (nbuckets + 1 counters)
 // zero the sort counters [0, len) of both orders (skipped once halted)
 hipError_t launch_zero_counts(uint32_t *rcnt, uint32_t *ccnt, uint64_t len, const uint32_t *halt, hipStream_t s);
+// counting sort of the appended pairs over buckets [0, nbuckets] (nbuckets + 1
+// counters, already holding the counts): scan, scatter, order by partner
 hipError_t launch_sort(const SortArgs &A, uint64_t nbuckets, uint32_t *bsum, uint32_t sort_grid,
                        hipStream_t s);
 uint32_t scan_block_count(uint64_t nbuckets);
