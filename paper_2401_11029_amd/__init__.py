@@ -52,30 +52,11 @@ def opts(**kw) -> Opts:
     return o
 
 
-def _torch_first():
-    """torch carries its own HIP runtime; when the library's runtime starts
-    first in a process, torch's finds no device afterwards.  So torch's is
-    started before the first context (if torch is installed)."""
-    global _torch_started
-    if _torch_started:
-        return
-    _torch_started = True
-    try:
-        import torch
-    except ImportError:
-        return
-    torch.cuda.is_available()
-
-
-_torch_started = False
-
-
 class Context:
     """A HIP device and stream.  stream: a torch.cuda.Stream, a raw
     hipStream_t (int), or None for a stream the library creates."""
 
     def __init__(self, device: int = 0, stream=None):
-        _torch_first()
         ptr = None
         if stream is not None:
             ptr = getattr(stream, "cuda_stream", stream)

@@ -98,6 +98,18 @@ SIGNATURES = {
 _lib = None
 
 
+def _torch_first():
+    """torch carries its own HIP runtime.  Loaded and started after the
+    library's, it leaves one of the two without a device; so, when torch is
+    installed, it is imported and its runtime started before the library is
+    loaded."""
+    try:
+        import torch
+    except ImportError:
+        return
+    torch.cuda.is_available()
+
+
 def load(path: str = LIB_PATH):
     """Load libcflr.so; raises if it has not been built (there is no other
     implementation to fall back to)."""
@@ -108,6 +120,7 @@ def load(path: str = LIB_PATH):
         raise ImportError(
             f"{path} is missing: build it with "
             "`python -m paper_2401_11029_amd.build` (hipcc, gfx950)")
+    _torch_first()
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
