@@ -148,13 +148,13 @@ __device__ __forceinline__ bool first_touch(const ProductArgs &A, uint32_t inst,
 // popc(cand_l)) belong to lane l.  The wave fills them together, 64
 // consecutive slots per pass: slot t goes to lane t % 64, which finds the
 // lane and the bit that own it (binary searches over the lanes' prefix sums
-// and over the bits of the word), so the stores are contiguous.  A new pair
-// is also set in the other layout (no return value needed); a candidate
-// that turned out not to be new leaves a hole.
+// and over the bits of the word), so the stores are contiguous.  A
+// candidate that turned out not to be new leaves a hole.  (The other layout
+// is updated for the whole tile afterwards, other_layout_tile.)
 template <bool COL>
 __device__ __forceinline__ void append_key(const ProductArgs &A, uint32_t k, uint32_t key, uint32_t seg,
                                            uint64_t cand, uint64_t fresh, uint64_t base, uint32_t pre,
-                                           uint32_t total, uint64_t *other, uint64_t Wp) {
+                                           uint32_t total) {
     const uint32_t lane = lane_id();
     for (uint32_t r = 0; r < total; r += kWave) {
         const uint32_t t = r + lane;
@@ -183,7 +183,6 @@ __device__ __forceinline__ void append_key(const ProductArgs &A, uint32_t k, uin
                 A.ap_key[slot] = k;
                 A.ap_i[slot] = COL ? x : key;
                 A.ap_j[slot] = COL ? key : x;
-                atomicOr((unsigned long long *)&other[(uint64_t)x * Wp + (key >> 6)], 1ull << (key & 63));
             } else {
                 A.ap_key[slot] = kHole;
             }
@@ -194,12 +193,72 @@ __device__ __forceinline__ void append_key(const ProductArgs &A, uint32_t k, uin
 // LDS of the product workgroup: the accumulators of the tile's keys for the
 // item's row segment (kept all zero between items).
 struct ProductShared {
-    uint64_t acc[kTileKeys][kSegWords];
-    uint64_t fresh_cols[kSegWords];  // the item's new pairs: their other indexes, as a bit set
+    // rows padded by one word, so that the column reads of other_layout_tile
+    // spread over the banks
+    uint64_t acc[kTileKeys][kSegWords + 1];
     unsigned long long item;  // the workgroup's current item
     uint32_t unit;            // and its unit
     uint32_t next_window;     // windows of the item taken so far
 };
+
+// Zero the accumulator rows of the live keys of one flush group.
+__device__ __forceinline__ void clear_rows(ProductShared &sh, uint32_t wave, uint32_t g0, uint32_t live) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (uint32_t q = 0; q < 8; q++)
+        if ((live >> q) & 1) sh.acc[wave + kProdWaves * (g0 + q)][lane] = 0;
+}
+
+// Transpose of a 64 x 64 bit block held one row per lane: afterwards lane b
+// holds column b (bit l = bit b of lane l's row).  Six butterfly stages, each
+// swapping the off-diagonal sub-blocks of size s between lanes l and l ^ s.
+__device__ __forceinline__ uint64_t transpose64(uint64_t v) {
+    const uint32_t lane = lane_id();
+    const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                               0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (uint32_t st = 0; st < 6; st++) {
+        const uint32_t s = 32u >> st;
+        const uint64_t m = masks[st];
+        const uint64_t p = shfl64(v, lane ^ s);
+        v = (lane & s) ? (((p >> s) & m) | (v & ~m)) : ((v & m) | ((p & m) << s));
+    }
+    return v;
+}
+
+// The other layout's update for a whole tile, after the flush left each
+// key's new bits in its accumulator row: wave w takes the column words
+// 4w .. 4w + 3 of the segment; for each and each group of 64 keys it
+// transposes the 64 x 64 block, so that lane b holds, for other index
+// x = 64 (64 seg + word) + b, the word of its other-layout row that covers
+// those 64 keys, and ORs it in with one atomic (instead of one per pair);
+// the four key groups of x are adjacent words.  The same pass sets the
+// other layout's segment mask of every x that gained a pair (read first,
+// set only where missing) and zeroes what it read.
+template <bool COL>
+__device__ __forceinline__ void other_layout_tile(ProductShared &sh, const MatDev &Mc, uint32_t key0,
+                                                  uint32_t seg, uint64_t Wp) {
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    uint64_t *other = COL ? Mc.R : Mc.C;
+    uint64_t *other_mask = COL ? Mc.Rm : Mc.Cm;
+    const uint64_t flag = seg_flag(key0);
+#pragma unroll 1
+    for (uint32_t r = 0; r < kSegWords / kProdWaves; r++) {
+        const uint32_t w = wave * (kSegWords / kProdWaves) + r;
+        const uint32_t x = (seg * kSegWords + w) * 64 + lane;
+        uint64_t any = 0;
+#pragma unroll
+        for (uint32_t g = 0; g < kTileKeys / 64; g++) {
+            uint64_t v = sh.acc[g * 64 + lane][w];
+            if (!__ballot(v != 0)) continue;
+            sh.acc[g * 64 + lane][w] = 0;
+            v = transpose64(v);
+            if (v) atomicOr((unsigned long long *)&other[(uint64_t)x * Wp + (key0 >> 6) + g], (unsigned long long)v);
+            any |= v;
+        }
+        if (any && !(other_mask[x] & flag)) atomicOr((unsigned long long *)&other_mask[x], (unsigned long long)flag);
+    }
+}
 
 // Flush of the wave's keys kl = wave + 16 q of the tile: each accumulator
 // word holds candidate bits of row `key` (COL = false: pairs (key, j), the
@@ -218,7 +277,6 @@ __device__ __forceinline__ void flush_keys(const ProductArgs &A, ProductShared &
     const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
     const uint32_t w = seg * kSegWords + lane;
     uint64_t *own = COL ? Mc.C : Mc.R;
-    uint64_t *other = COL ? Mc.R : Mc.C;
     uint64_t *own_mask = COL ? Mc.Cm : Mc.Rm;
     const uint32_t k = pair_key(inst, c);
     uint32_t fresh = 0;
@@ -234,12 +292,15 @@ __device__ __forceinline__ void flush_keys(const ProductArgs &A, ProductShared &
             const uint64_t lanes = __ballot(cand[q] != 0);
             if (lanes) {
                 live |= 1u << q;
-                sh.acc[kl][lane] = 0;
                 if (STATS && lane == 0 && first_touch<STATS>(A, inst, c, COL ? 1 : 0, key0 + kl, seg, I))
                     ch.bytes += 8ull * __popcll(lanes);
             }
         }
-        if (!live || failed) continue;
+        if (!live) continue;
+        if (failed) {
+            clear_rows(sh, wave, g0, live);
+            continue;
+        }
 #pragma unroll
         for (uint32_t q = 0; q < kGroup; q++) {
             old[q] = 0;
@@ -258,9 +319,13 @@ __device__ __forceinline__ void flush_keys(const ProductArgs &A, ProductShared &
         uint64_t pos;
         if (!reserve_slots(A, ch, inst, need, &pos)) {
             failed = true;
+            clear_rows(sh, wave, g0, live);
             continue;
         }
-        if (!grand) continue;
+        if (!grand) {
+            clear_rows(sh, wave, g0, live);
+            continue;
+        }
         uint64_t base = first_lane64(pos - pre_all);
 #pragma unroll
         for (uint32_t q = 0; q < kGroup; q++)
@@ -269,17 +334,18 @@ __device__ __forceinline__ void flush_keys(const ProductArgs &A, ProductShared &
                                   (unsigned long long)cand[q]);
 #pragma unroll
         for (uint32_t q = 0; q < kGroup; q++) {
+            const uint32_t kl = wave + kProdWaves * (g0 + q);
             uint32_t total;
             const uint32_t pre = wave_excl_scan((uint32_t)__popcll(cand[q]), &total);
-            if (!total) continue;
             const uint64_t nw = cand[q] & ~old[q];
+            // the row keeps the new bits for the other layout's update
+            if ((live >> q) & 1) sh.acc[kl][lane] = nw;
+            if (!total) continue;
             fresh += (uint32_t)__popcll(nw);
-            const uint32_t key = key0 + wave + kProdWaves * (g0 + q);
-            if (__ballot(nw != 0)) {
-                if (lane == 0) atomicOr((unsigned long long *)&own_mask[key], 1ull << (seg & 63));
-                if (nw) atomicOr((unsigned long long *)&sh.fresh_cols[lane], (unsigned long long)nw);
-            }
-            append_key<COL>(A, k, key, seg, cand[q], nw, base, pre, total, other, Wp);
+            const uint32_t key = key0 + kl;
+            if (__ballot(nw != 0) && lane == 0)
+                atomicOr((unsigned long long *)&own_mask[key], 1ull << (seg & 63));
+            append_key<COL>(A, k, key, seg, cand[q], nw, base, pre, total);
             base += total;
         }
     }
@@ -428,26 +494,10 @@ __device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared
     }
     __syncthreads();  // every window's ORs are in the accumulators
     flush_keys<COL, STATS>(A, sh, ch, E.inst, I, A.mats[I.mat_off + E.c], E.c, key0, seg, Wp);
-    __syncthreads();  // the accumulators are zero again before the next item
-    // Segment masks of the other layout: every new pair of the item has its
-    // key in the tile, so row x of the other layout gains the same segment
-    // bit for every x in fresh_cols.  Each wave takes four words of the set,
-    // reads the 64 masks of a word at once and sets the bit where it is
-    // missing, then clears the word (before the next item's flush).
-    uint64_t *other_mask = COL ? A.mats[I.mat_off + E.c].Rm : A.mats[I.mat_off + E.c].Cm;
-    const uint64_t flag = seg_flag(key0);
-    const uint32_t wave = threadIdx.x / kWave;
-#pragma unroll 1
-    for (uint32_t r = 0; r < kSegWords / kProdWaves; r++) {
-        const uint32_t w = wave * (kSegWords / kProdWaves) + r;
-        const uint64_t bits = first_lane64(sh.fresh_cols[w]);
-        if (!bits) continue;
-        const uint32_t x = (seg * kSegWords + w) * 64 + lane;
-        if ((bits >> lane) & 1) {
-            if (!(other_mask[x] & flag)) atomicOr((unsigned long long *)&other_mask[x], (unsigned long long)flag);
-        }
-        if (lane == 0) sh.fresh_cols[w] = 0;
-    }
+    __syncthreads();  // every key's new bits are in its accumulator row
+    other_layout_tile<COL>(sh, A.mats[I.mat_off + E.c], key0, seg, Wp);
+    // the accumulators are zero again before the next item (its first
+    // barrier orders this before any of its ORs)
 }
 
 template <bool STATS>
@@ -458,7 +508,6 @@ __global__ __launch_bounds__(kProdWaves * kWave) void product_kernel(ProductArgs
     const uint64_t first = A.item_prefix[A.unit_lo], total = A.item_prefix[A.unit_hi];
     SlotChunk ch;
     for (uint32_t x = tid; x < kTileKeys * kSegWords; x += kProdWaves * kWave) sh.acc[x / kSegWords][x % kSegWords] = 0;
-    if (tid < kSegWords) sh.fresh_cols[tid] = 0;
     // items are taken from a counter, one atomic per workgroup and item; the
     // next one is requested when an item starts, so its round trip overlaps
     // the work.  After an overflow the round is re-run: stop early.
