@@ -375,7 +375,7 @@ __device__ __forceinline__ void flush_keys(const ProductArgs &A, ProductShared &
 }
 
 constexpr uint32_t kRunBatch = 8;  // partner segments in flight per wave
-constexpr uint32_t kWinGroup = 4;  // windows a wave takes at once
+constexpr uint32_t kWinGroup = 8;  // windows a wave takes at once
 
 // The runs of one window of 64 pairs (lane l holds key key_l and partner
 // k_l; `heads` marks the first lane of each run, `todo` the runs whose
