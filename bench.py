@@ -202,7 +202,9 @@ def batch(args):
     ctx = cflr.Context(0)
     gr = cflr.Grammar(grammars.ALIAS_FIG5A_WCNF)
     objs = [cflr.Graph.from_workload(ctx, g) for g in gs]
-    for r in cflr.solve_batch(ctx, gr, objs[:8]):   # warm-up
+    # warm-up: one full untimed batch, so that the timed one starts with the
+    # new-pair buffer already grown to what the batch needs
+    for r in cflr.solve_batch(ctx, gr, objs):
         r.close()
     log("warm-up done; autotuning on every 16th graph")
     # autotune the launch shape on a 16-graph sample (one line per candidate)
@@ -218,10 +220,21 @@ def batch(args):
     for r in res:
         r.close()
     log(f"batched: {tb:.2f} s")
+    # the plain solves get a context of their own: a context starts its
+    # new-pair buffer at the largest size an earlier run on it needed, and
+    # the batch's would oversize every single solve.  The batch's context
+    # (and the memory its pool caches) goes first.
+    del objs, res
+    ctx.close()
+    seq_ctx = cflr.Context(0)
+    seq_objs = [cflr.Graph.from_workload(seq_ctx, g) for g in gs]
+    # warm-up on the largest graph (its buffer size serves every smaller one)
+    cflr.solve(seq_ctx, gr, seq_objs[max(range(len(gs)), key=lambda k: gs[k].n)]).close()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     seq_pairs = []
-    for q, o in enumerate(objs):
-        r = cflr.solve(ctx, gr, o)
+    for q, o in enumerate(seq_objs):
+        r = cflr.solve(seq_ctx, gr, o)
         seq_pairs.append(r.stats()["total_pairs"])
         r.close()
         if q % 32 == 31:
