@@ -387,6 +387,8 @@ __device__ __forceinline__ void or_runs(const ProductArgs &A, ProductShared &sh,
                                         uint64_t Wp, uint32_t key0, uint32_t seg, uint32_t key, uint32_t k,
                                         uint64_t heads, uint32_t nvalid, uint64_t todo) {
     const uint32_t lane = lane_id();
+    const uint32_t row_bytes = (key & (kTileKeys - 1)) * (uint32_t)sizeof(sh.acc[0]);
+    char *acc_lane = (char *)&sh.acc[0][lane];
     while (todo) {
         // up to kRunBatch runs: their partner segments requested together
         uint32_t start[kRunBatch];
@@ -416,12 +418,11 @@ __device__ __forceinline__ void or_runs(const ProductArgs &A, ProductShared &sh,
             const uint64_t later = start[q] == 63 ? 0 : heads & (~0ull << (start[q] + 1));
             const uint32_t end = later ? (uint32_t)__ffsll((unsigned long long)later) - 1 : nvalid;
             // every key of the unit's pairs lies in its tile (they are
-            // bucketed by key tile); the mask keeps the row inside the
-            // accumulators without a branch
-            for (uint32_t t = start[q]; t < end; t++) {
-                const uint32_t kl = (rdlane(key, t) - key0) & (kTileKeys - 1);
-                atomicOr((unsigned long long *)&sh.acc[kl][lane], (unsigned long long)v[q]);
-            }
+            // bucketed by key tile, key0 a multiple of kTileKeys); the mask
+            // keeps the row inside the accumulators without a branch, and
+            // the row's byte offset is read straight out of lane t
+            for (uint32_t t = start[q]; t < end; t++)
+                atomicOr((unsigned long long *)(acc_lane + rdlane(row_bytes, t)), (unsigned long long)v[q]);
         }
     }
 }
