@@ -384,7 +384,7 @@ constexpr uint32_t kWinGroup = 8;  // windows a wave takes at once
 template <bool COL, bool STATS>
 __device__ __forceinline__ void or_runs(const ProductArgs &A, ProductShared &sh, SlotChunk &ch,
                                         const EntryDev &E, const InstDev &I, uint32_t pm, global_u64 G,
-                                        uint64_t Wp, uint32_t key0, uint32_t seg, uint32_t key, uint32_t k,
+                                        uint64_t Wp, uint32_t seg, uint32_t key, uint32_t k,
                                         uint64_t heads, uint32_t nvalid, uint64_t todo) {
     const uint32_t lane = lane_id();
     const uint32_t row_bytes = (key & (kTileKeys - 1)) * (uint32_t)sizeof(sh.acc[0]);
@@ -418,7 +418,7 @@ __device__ __forceinline__ void or_runs(const ProductArgs &A, ProductShared &sh,
             const uint64_t later = start[q] == 63 ? 0 : heads & (~0ull << (start[q] + 1));
             const uint32_t end = later ? (uint32_t)__ffsll((unsigned long long)later) - 1 : nvalid;
             // every key of the unit's pairs lies in its tile (they are
-            // bucketed by key tile, key0 a multiple of kTileKeys); the mask
+            // bucketed by key tile, tiles start at multiples of kTileKeys); the mask
             // keeps the row inside the accumulators without a branch, and
             // the row's byte offset is read straight out of lane t
             for (uint32_t t = start[q]; t < end; t++)
@@ -490,7 +490,7 @@ __device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared
         for (uint32_t q = 0; q < kWinGroup; q++) {
             const uint64_t todo = __ballot(((heads[q] >> lane) & 1) && (m[q] & seg_bit));
             if (todo)
-                or_runs<COL, STATS>(A, sh, ch, E, I, pm, G, Wp, key0, seg, key[q], k[q], heads[q], nvalid[q], todo);
+                or_runs<COL, STATS>(A, sh, ch, E, I, pm, G, Wp, seg, key[q], k[q], heads[q], nvalid[q], todo);
         }
     }
     __syncthreads();  // every window's ORs are in the accumulators
