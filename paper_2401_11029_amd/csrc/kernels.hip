@@ -375,7 +375,7 @@ __device__ __forceinline__ void flush_keys(const ProductArgs &A, ProductShared &
 }
 
 constexpr uint32_t kRunBatch = 8;  // partner segments in flight per wave
-constexpr uint32_t kWinGroup = 8;  // windows a wave takes at once
+constexpr uint32_t kWinGroup = 4;  // windows a wave takes at once
 
 // The runs of one window of 64 pairs (lane l holds key key_l and partner
 // k_l; `heads` marks the first lane of each run, `todo` the runs whose
@@ -431,8 +431,10 @@ __device__ __forceinline__ void or_runs(const ProductArgs &A, ProductShared &sh,
 // row segment `seg`.  COL = false: pairs (i, k) of dA, partner rows k of B
 // (row-major); COL = true: pairs (j, k) of dB, partner rows k of A's
 // column-major copy.  The waves take kWinGroup windows of 64 consecutive
-// pairs at a time from an LDS counter and request their pairs together, then
-// the segment masks of their partners together.  In a window, pairs with
+// pairs at a time from an LDS counter; a wave requests a group's pairs, then
+// (one group later) the segment masks of its run heads' partners, and (one
+// group later again) loads its runs, so that two groups' requests are in
+// flight while it ORs the runs of a third.  In a window, pairs with
 // the same partner k are adjacent (a run): only runs whose partner segment
 // may be non-zero load it, once per run, and OR it into the LDS accumulator
 // of every key of the run (atomic OR in LDS, no return value); a loaded
@@ -453,45 +455,91 @@ __device__ __forceinline__ void product_tile(const ProductArgs &A, ProductShared
     const uint64_t *pairs = COL ? A.cs : A.rs;
     const uint32_t key0 = tile * kTileKeys;
     const uint32_t nwin = (p1 - p0 + kWave - 1) / kWave;
-    while (true) {
-        uint32_t win = 0;
-        if (lane == 0) win = atomicAdd(&sh.next_window, kWinGroup);
-        win = first_lane(win);
-        if (win >= nwin) break;
-        uint64_t pk[kWinGroup];
+    // Two-stage pipeline per wave: while the runs of the current group of
+    // windows are ORed, the segment masks of the next group and the pairs of
+    // the group after it are in flight.
+    constexpr uint32_t P = kWinGroup;
+    uint32_t wr = 0;  // group whose pairs are being loaded
+    if (lane == 0) wr = atomicAdd(&sh.next_window, P);
+    wr = first_lane(wr);
+    uint64_t raw[P];
 #pragma unroll
-        for (uint32_t q = 0; q < kWinGroup; q++) {
-            const uint64_t x = (uint64_t)p0 + (uint64_t)(win + q) * kWave + lane;
-            pk[q] = ~0ull;
-            if (x < p1) pk[q] = pairs[x];
+    for (uint32_t q = 0; q < P; q++) {
+        const uint64_t x = (uint64_t)p0 + (uint64_t)(wr + q) * kWave + lane;
+        raw[q] = ~0ull;
+        if (x < p1) raw[q] = pairs[x];
+    }
+    uint32_t wn = wr;  // group decoded, masks in flight
+    uint32_t kn[P], pn[P], nvn[P];
+    uint64_t hn[P], mn[P];
+#pragma unroll
+    for (uint32_t q = 0; q < P; q++) {
+        kn[q] = (uint32_t)(raw[q] >> 32);
+        pn[q] = (uint32_t)raw[q];
+        const bool valid = (uint64_t)p0 + (uint64_t)(wn + q) * kWave + lane < p1 && pn[q] < I.n;
+        const uint32_t kprev = __shfl_up(pn[q], 1, 64);
+        const bool head = valid && (lane == 0 || pn[q] != kprev);
+        hn[q] = __ballot(head);
+        nvn[q] = (uint32_t)__popcll(__ballot(valid));
+        mn[q] = head ? Gm[pn[q]] : 0ull;
+    }
+    if (wn < nwin) {
+        if (lane == 0) wr = atomicAdd(&sh.next_window, P);
+        wr = first_lane(wr);
+#pragma unroll
+        for (uint32_t q = 0; q < P; q++) {
+            const uint64_t x = (uint64_t)p0 + (uint64_t)(wr + q) * kWave + lane;
+            raw[q] = ~0ull;
+            if (x < p1) raw[q] = pairs[x];
         }
-        uint32_t key[kWinGroup], k[kWinGroup], nvalid[kWinGroup];
-        uint64_t heads[kWinGroup], m[kWinGroup];
+    }
+    while (wn < nwin) {
+        // the current group: its runs to load, from the gathered masks
+        uint32_t kc[P], pc[P], nvc[P];
+        uint64_t hc[P], tc[P];
 #pragma unroll
-        for (uint32_t q = 0; q < kWinGroup; q++) {
-            key[q] = (uint32_t)(pk[q] >> 32);
-            k[q] = (uint32_t)pk[q];
-            const bool valid = (uint64_t)p0 + (uint64_t)(win + q) * kWave + lane < p1 && k[q] < I.n;
-            const uint32_t kprev = __shfl_up(k[q], 1, 64);
-            const bool head = valid && (lane == 0 || k[q] != kprev);
-            heads[q] = __ballot(head);
-            nvalid[q] = (uint32_t)__popcll(__ballot(valid));
-            m[q] = 0;
-            if (head) m[q] = Gm[k[q]];
+        for (uint32_t q = 0; q < P; q++) {
+            kc[q] = kn[q];
+            pc[q] = pn[q];
+            nvc[q] = nvn[q];
+            hc[q] = hn[q];
+            tc[q] = __ballot(((hn[q] >> lane) & 1) && (mn[q] & seg_bit));
         }
         if (STATS && seg == 0 && lane == 0) {
             // the pairs themselves, read once per production
             uint32_t taken = 0;
 #pragma unroll
-            for (uint32_t q = 0; q < kWinGroup; q++) taken += nvalid[q];
+            for (uint32_t q = 0; q < P; q++) taken += nvc[q];
             ch.bytes += 8ull * taken;
         }
+        // the next group: decoded, its masks requested
+        wn = wr;
 #pragma unroll
-        for (uint32_t q = 0; q < kWinGroup; q++) {
-            const uint64_t todo = __ballot(((heads[q] >> lane) & 1) && (m[q] & seg_bit));
-            if (todo)
-                or_runs<COL, STATS>(A, sh, ch, E, I, pm, G, Wp, seg, key[q], k[q], heads[q], nvalid[q], todo);
+        for (uint32_t q = 0; q < P; q++) {
+            kn[q] = (uint32_t)(raw[q] >> 32);
+            pn[q] = (uint32_t)raw[q];
+            const bool valid = (uint64_t)p0 + (uint64_t)(wn + q) * kWave + lane < p1 && pn[q] < I.n;
+            const uint32_t kprev = __shfl_up(pn[q], 1, 64);
+            const bool head = valid && (lane == 0 || pn[q] != kprev);
+            hn[q] = __ballot(head);
+            nvn[q] = (uint32_t)__popcll(__ballot(valid));
+            mn[q] = head ? Gm[pn[q]] : 0ull;
         }
+        // the group after it: its pairs requested
+        if (wn < nwin) {
+            if (lane == 0) wr = atomicAdd(&sh.next_window, P);
+            wr = first_lane(wr);
+#pragma unroll
+            for (uint32_t q = 0; q < P; q++) {
+                const uint64_t x = (uint64_t)p0 + (uint64_t)(wr + q) * kWave + lane;
+                raw[q] = ~0ull;
+                if (x < p1) raw[q] = pairs[x];
+            }
+        }
+        // the current group's runs, while those are in flight
+#pragma unroll
+        for (uint32_t q = 0; q < P; q++)
+            if (tc[q]) or_runs<COL, STATS>(A, sh, ch, E, I, pm, G, Wp, seg, kc[q], pc[q], hc[q], nvc[q], tc[q]);
     }
     __syncthreads();  // every window's ORs are in the accumulators
     flush_keys<COL, STATS>(A, sh, ch, E.inst, I, A.mats[I.mat_off + E.c], E.c, key0, seg, Wp);
