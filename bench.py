@@ -450,7 +450,7 @@ def main():
     ap.add_argument("--batch-max-n", type=int, default=40000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(each solve, batch or served request lives on one device)", file=sys.stderr)
         sys.exit(2)
     if args.mode == "single":

@@ -25,7 +25,7 @@ class DevPool {
     ~DevPool();
     void *alloc(size_t bytes);
     void release(void *p);
-    void trim();  // return cached blocks to the driver
+    void trim();  // hand cached blocks back to the HIP runtime (hipFree)
     uint64_t held() const { return held_; }
 
    private:
