@@ -357,3 +357,28 @@ def test_server_rejects_oversized_request(ctx):
         srv.wait(t, timeout_s=60)
     assert e.value.status == 3
     srv.close()
+
+
+def test_library_loaded_before_torch_still_leaves_torch_a_device():
+    # torch carries its own HIP runtime: the binding starts it before loading
+    # libcflr.so, so a process that loads the library first still solves and
+    # still gives torch the device (a child process, so the order is real)
+    import subprocess
+    import sys
+    code = (
+        "from paper_2401_11029_amd import _lib\n"
+        "_lib.load()\n"
+        "import paper_2401_11029_amd as m\n"
+        "import numpy as np\n"
+        "ctx = m.Context(0)\n"
+        "g = m.Grammar('S -> S S | a')\n"
+        "src = np.arange(5, dtype=np.uint32); dst = src + 1\n"
+        "gr = m.Graph(ctx, 6, src, dst, np.zeros(5, dtype=np.uint32), ['a'])\n"
+        "r = m.solve(ctx, g, gr)\n"
+        "assert r.count('S') == 15, r.count('S')\n"
+        "import torch\n"
+        "assert torch.cuda.is_available()\n"
+        "print('ok')\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0 and out.stdout.strip().endswith("ok"), out.stderr[-2000:]
