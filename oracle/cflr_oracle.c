@@ -34,9 +34,10 @@
  * A fact added after another was popped is itself popped later and meets it
  * then, so at exhaustion the set is closed; every added fact has a
  * derivation, so it is also the least such set.  The sets "for each k with
- * (z, j, k)" are read from per-row bit sets (one bit per vertex), 64 at a
- * time; this is only a set representation and changes nothing about which
- * facts are produced.
+ * (z, j, k)" are read from per-row sets of vertices: a small hash set of
+ * vertex ids while the row is sparse, a bit set (one bit per vertex, read 64
+ * at a time) once it holds more than n/64 vertices.  This is only a set
+ * representation and changes nothing about which facts are produced.
  *
  * Usage:
  *   cflr_oracle GRAMMAR.txt GRAPH.cflg [--digest] [--pairs OUT]
@@ -221,10 +222,105 @@ static void read_graph(const char *path) {
 
 /* --------------------------------------------------------------- fact store */
 
-static uint32_t n_words;          /* words per bit-set row: ceil(n / 64) */
-static uint64_t ***row_set;       /* row_set[s][i]: bits j with (s, i, j) */
-static uint64_t ***col_set;       /* col_set[s][j]: bits i with (s, i, j) */
+static uint32_t n_words;          /* words of a bit-set row: ceil(n / 64) */
+
+/* A set of vertex ids (one row of one symbol's relation, or one column).
+ * Sparse form: open addressing with linear probing over `cap` slots (a
+ * power of two, at most half full), EMPTY marking a free slot.  Dense form
+ * (bits != NULL): one bit per vertex.  A set turns dense when its count
+ * passes n / 64, where the bit set takes no more memory than the slots. */
+#define EMPTY UINT32_MAX
+typedef struct {
+    uint32_t count;
+    uint32_t cap;
+    uint32_t *slot;
+    uint64_t *bits;
+} vset_t;
+
+static vset_t ***row_set;         /* row_set[s][i]: the j with (s, i, j) */
+static vset_t ***col_set;         /* col_set[s][j]: the i with (s, i, j) */
 static uint64_t *fact_count;      /* per symbol */
+
+static uint32_t vhash(uint32_t v, uint32_t cap) { return (uint32_t)((v * 2654435761u) & (cap - 1)); }
+
+static int vset_has(const vset_t *a, uint32_t v) {
+    if (!a || !a->count) return 0;
+    if (a->bits) return (int)((a->bits[v >> 6] >> (v & 63)) & 1);
+    for (uint32_t h = vhash(v, a->cap);; h = (h + 1) & (a->cap - 1)) {
+        if (a->slot[h] == v) return 1;
+        if (a->slot[h] == EMPTY) return 0;
+    }
+}
+
+static void vset_put_slot(uint32_t *slot, uint32_t cap, uint32_t v) {
+    uint32_t h = vhash(v, cap);
+    while (slot[h] != EMPTY) h = (h + 1) & (cap - 1);
+    slot[h] = v;
+}
+
+/* Insert v (known to be absent). */
+static void vset_insert(vset_t *a, uint32_t v) {
+    a->count++;
+    if (a->bits) {
+        a->bits[v >> 6] |= 1ull << (v & 63);
+        return;
+    }
+    if ((uint64_t)a->count * 64 > n_vert && n_words > 0) {
+        /* dense from now on */
+        a->bits = xcalloc(n_words, sizeof(uint64_t));
+        for (uint32_t h = 0; h < a->cap; h++)
+            if (a->slot[h] != EMPTY) a->bits[a->slot[h] >> 6] |= 1ull << (a->slot[h] & 63);
+        a->bits[v >> 6] |= 1ull << (v & 63);
+        free(a->slot);
+        a->slot = NULL;
+        a->cap = 0;
+        return;
+    }
+    if (2ull * a->count > a->cap) {
+        uint32_t ncap = a->cap ? 2 * a->cap : 4;
+        uint32_t *ns = xcalloc(ncap, sizeof(uint32_t));
+        memset(ns, 0xFF, (size_t)ncap * sizeof(uint32_t));
+        for (uint32_t h = 0; h < a->cap; h++)
+            if (a->slot[h] != EMPTY) vset_put_slot(ns, ncap, a->slot[h]);
+        free(a->slot);
+        a->slot = ns;
+        a->cap = ncap;
+    }
+    vset_put_slot(a->slot, a->cap, v);
+}
+
+static vset_t *set_of(vset_t **sets, uint32_t r) {
+    if (!sets[r]) sets[r] = xcalloc(1, sizeof(vset_t));
+    return sets[r];
+}
+
+/* The members of a set, copied out (the set may grow while the caller
+ * works through them); in increasing order when `sorted`. */
+static uint32_t *snap_buf;
+static uint64_t snap_cap;
+
+static int cmp_u32(const void *a, const void *b) {
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    return (x > y) - (x < y);
+}
+
+static uint32_t vset_snapshot(const vset_t *a, int sorted) {
+    if (!a || !a->count) return 0;
+    if (a->count > snap_cap) {
+        snap_cap = 2ull * a->count;
+        snap_buf = xrealloc(snap_buf, snap_cap * sizeof(uint32_t));
+    }
+    uint32_t k = 0;
+    if (a->bits) {
+        for (uint32_t w = 0; w < n_words; w++)
+            for (uint64_t b = a->bits[w]; b; b &= b - 1) snap_buf[k++] = w * 64 + (uint32_t)__builtin_ctzll(b);
+        return k;
+    }
+    for (uint32_t h = 0; h < a->cap; h++)
+        if (a->slot[h] != EMPTY) snap_buf[k++] = a->slot[h];
+    if (sorted) qsort(snap_buf, k, sizeof(uint32_t), cmp_u32);
+    return k;
+}
 
 static uint32_t *stk_s, *stk_i, *stk_j;
 static uint64_t stk_len, stk_cap;
@@ -232,11 +328,6 @@ static uint64_t stk_len, stk_cap;
 static int want_cert;
 static uint32_t *cert_s, *cert_i, *cert_j, *cert_rule, *cert_mid;
 static uint64_t cert_len, cert_cap;
-
-static uint64_t *row_of(uint64_t **set, uint32_t r) {
-    if (!set[r]) set[r] = xcalloc(n_words, sizeof(uint64_t));
-    return set[r];
-}
 
 static void push(uint32_t s, uint32_t i, uint32_t j) {
     if (stk_len == stk_cap) {
@@ -253,11 +344,10 @@ static void push(uint32_t s, uint32_t i, uint32_t j) {
 
 /* Insert fact (s, i, j) produced by rule `rule` with midpoint `mid`. */
 static void add_fact(uint32_t s, uint32_t i, uint32_t j, uint32_t rule, uint32_t mid) {
-    uint64_t *r = row_of(row_set[s], i);
-    uint64_t bit = 1ull << (j & 63);
-    if (r[j >> 6] & bit) return;
-    r[j >> 6] |= bit;
-    row_of(col_set[s], j)[i >> 6] |= 1ull << (i & 63);
+    vset_t *r = set_of(row_set[s], i);
+    if (vset_has(r, j)) return;
+    vset_insert(r, j);
+    vset_insert(set_of(col_set[s], j), i);
     fact_count[s]++;
     push(s, i, j);
     if (want_cert) {
@@ -293,8 +383,8 @@ static void solve(void) {
     row_set = xcalloc(nsym, sizeof *row_set);
     col_set = xcalloc(nsym, sizeof *col_set);
     for (uint32_t s = 0; s < nsym; s++) {
-        row_set[s] = xcalloc(n_vert, sizeof(uint64_t *));
-        col_set[s] = xcalloc(n_vert, sizeof(uint64_t *));
+        row_set[s] = xcalloc(n_vert, sizeof(vset_t *));
+        col_set[s] = xcalloc(n_vert, sizeof(vset_t *));
     }
     fact_count = xcalloc(nsym, sizeof *fact_count);
     by_left = xcalloc(nsym, sizeof *by_left);
@@ -328,31 +418,48 @@ static void solve(void) {
         /* x -> y z with (y, i, j): every (z, j, k) gives (x, i, k) */
         for (uint32_t t = 0; t < n_left[y]; t++) {
             uint32_t r = by_left[y][t], x = rules[r].lhs, z = rules[r].r2;
-            uint64_t *zr = row_set[z][j];
-            if (!zr) continue;
-            for (uint32_t w = 0; w < n_words; w++) {
-                uint64_t *xr = row_set[x][i];
-                uint64_t fresh = zr[w] & ~(xr ? xr[w] : 0);
-                while (fresh) {
-                    uint32_t k = w * 64 + (uint32_t)__builtin_ctzll(fresh);
-                    fresh &= fresh - 1;
-                    add_fact(x, i, k, r, j);
+            const vset_t *zr = row_set[z][j];
+            if (!zr || !zr->count) continue;
+            const vset_t *xr = row_set[x][i];
+            if (zr->bits && xr && xr->bits) {
+                /* both dense: 64 candidates at a time */
+                for (uint32_t w = 0; w < n_words; w++) {
+                    uint64_t fresh = zr->bits[w] & ~xr->bits[w];
+                    while (fresh) {
+                        uint32_t k = w * 64 + (uint32_t)__builtin_ctzll(fresh);
+                        fresh &= fresh - 1;
+                        add_fact(x, i, k, r, j);
+                    }
                 }
+                continue;
+            }
+            uint32_t cnt = vset_snapshot(zr, 0);
+            for (uint32_t q = 0; q < cnt; q++) {
+                uint32_t k = snap_buf[q];
+                if (!vset_has(row_set[x][i], k)) add_fact(x, i, k, r, j);
             }
         }
         /* x -> z y with (y, i, j): every (z, k, i) gives (x, k, j) */
         for (uint32_t t = 0; t < n_right[y]; t++) {
             uint32_t r = by_right[y][t], x = rules[r].lhs, z = rules[r].r1;
-            uint64_t *zc = col_set[z][i];
-            if (!zc) continue;
-            for (uint32_t w = 0; w < n_words; w++) {
-                uint64_t *xc = col_set[x][j];
-                uint64_t fresh = zc[w] & ~(xc ? xc[w] : 0);
-                while (fresh) {
-                    uint32_t k = w * 64 + (uint32_t)__builtin_ctzll(fresh);
-                    fresh &= fresh - 1;
-                    add_fact(x, k, j, r, i);
+            const vset_t *zc = col_set[z][i];
+            if (!zc || !zc->count) continue;
+            const vset_t *xc = col_set[x][j];
+            if (zc->bits && xc && xc->bits) {
+                for (uint32_t w = 0; w < n_words; w++) {
+                    uint64_t fresh = zc->bits[w] & ~xc->bits[w];
+                    while (fresh) {
+                        uint32_t k = w * 64 + (uint32_t)__builtin_ctzll(fresh);
+                        fresh &= fresh - 1;
+                        add_fact(x, k, j, r, i);
+                    }
                 }
+                continue;
+            }
+            uint32_t cnt = vset_snapshot(zc, 0);
+            for (uint32_t q = 0; q < cnt; q++) {
+                uint32_t k = snap_buf[q];
+                if (!vset_has(col_set[x][j], k)) add_fact(x, k, j, r, i);
             }
         }
     }
@@ -449,15 +556,8 @@ static void le32(uint8_t *o, uint32_t v) {
 typedef void (*pair_fn)(void *ctx, uint32_t i, uint32_t j);
 static void for_pairs(uint32_t s, pair_fn fn, void *ctx) {
     for (uint32_t i = 0; i < n_vert; i++) {
-        uint64_t *r = row_set[s][i];
-        if (!r) continue;
-        for (uint32_t w = 0; w < n_words; w++) {
-            uint64_t b = r[w];
-            while (b) {
-                fn(ctx, i, w * 64 + (uint32_t)__builtin_ctzll(b));
-                b &= b - 1;
-            }
-        }
+        uint32_t cnt = vset_snapshot(row_set[s][i], 1);
+        for (uint32_t q = 0; q < cnt; q++) fn(ctx, i, snap_buf[q]);
     }
 }
 

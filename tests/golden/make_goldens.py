@@ -3,9 +3,11 @@ CPU oracle (``oracle/``) on the seeded inputs of ``workloads``.
 
     python tests/golden/make_goldens.py NAME [NAME ...]
 
-NAME is one of the keys of GOLDENS.  Each writes ``NAME.json`` holding, per
-non-terminal, the pair count and the SHA-256 of its pairs in (i, j) order
-(two little-endian u32 each), plus the oracle's own fixpoint time.
+NAME is one of the keys of GOLDENS or of BATCH_GOLDENS.  A GOLDENS entry
+writes ``NAME.json`` holding, per non-terminal, the pair count and the
+SHA-256 of its pairs in (i, j) order (two little-endian u32 each), plus the
+oracle's own fixpoint time.  A BATCH_GOLDENS entry writes the same record for
+each graph of a batch that its filter selects, keyed by the graph's index.
 """
 
 from __future__ import annotations
@@ -36,6 +38,15 @@ GOLDENS = {
     # Fig. 5b's hand WCNF on the 8,000 vertex alias graph
     "alias5b_8k": lambda: (grammars.ALIAS_FIG5B,
                            graphs.alias_graph(8000, seed=1)),
+    # the points-to configuration at its full size (200,000 vertices)
+    "pointsto_200k": lambda: workloads.config("pointsto_200k"),
+}
+
+# The 256-graph alias batch (the batched configuration): every graph with at
+# most 8,000 vertices, solved one by one.
+BATCH_GOLDENS = {
+    "alias_batch_le8k": (lambda: graphs.alias_batch(256),
+                         grammars.ALIAS_FIG5A_WCNF, lambda g: g.n <= 8000),
 }
 
 
@@ -62,7 +73,30 @@ def make(name):
           flush=True)
 
 
+def make_batch(name):
+    make_graphs, text, keep = BATCH_GOLDENS[name]
+    out = {"name": name, "graphs": {}, "oracle_host": platform.processor() or platform.machine()}
+    secs = 0.0
+    for k, g in enumerate(make_graphs()):
+        if not keep(g):
+            continue
+        r = oracle.solve(text, g, pairs=False, digest=True)
+        secs += r.seconds
+        out["graphs"][str(k)] = {"n": g.n, "m": g.m, "meta": g.meta, "order": r.order,
+                                 "count": r.count, "sha256": r.digest,
+                                 "total": sum(r.count.values()), "oracle_seconds": r.seconds}
+    out["oracle_seconds"] = secs
+    path = os.path.join(HERE, f"{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print(f"{name}: {len(out['graphs'])} graphs, oracle {secs:.1f} s -> {path}", flush=True)
+
+
 if __name__ == "__main__":
     oracle.build(force=False)
     for nm in sys.argv[1:]:
-        make(nm)
+        if nm in BATCH_GOLDENS:
+            make_batch(nm)
+        else:
+            make(nm)

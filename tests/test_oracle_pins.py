@@ -329,8 +329,8 @@ def test_golden_files_reproduce(oracle_bin):
 MUTANTS = {
     "drop_right_products": ("for (uint32_t t = 0; t < n_right[y]; t++) {",
                             "for (uint32_t t = 0; t < 0 * n_right[y]; t++) {"),
-    "transposed_operand": ("uint64_t *zr = row_set[z][j];",
-                           "uint64_t *zr = col_set[z][j];"),
+    "transposed_operand": ("const vset_t *zr = row_set[z][j];",
+                           "const vset_t *zr = col_set[z][j];"),
     "eps_only_first_vertex": ("for (uint32_t i = 0; i < n_vert; i++) add_fact(rules[r].lhs, i, i, r, UINT32_MAX);",
                               "for (uint32_t i = 0; i < 1 && i < n_vert; i++) add_fact(rules[r].lhs, i, i, r, UINT32_MAX);"),
     "unit_rules_ignored": ("add_fact(rules[r].lhs, i, j, r, UINT32_MAX);\n        }",
