@@ -85,7 +85,19 @@ typedef struct cflr_opts {
                                   work item takes at most (a tile with more
                                   is split, and each part flushes the tile's
                                   keys again); 0 = 2^20 */
+    uint32_t storage;          /* single solves: CFLR_STORAGE_AUTO (default),
+                                  _DENSE or _SPARSE (see cflr_solve) */
 } cflr_opts;
+
+/* Storage engines of a single solve (cflr_opts.storage, cflr_stats.storage). */
+enum {
+    CFLR_STORAGE_AUTO = 0,   /* dense while its bit matrices take at most a
+                                quarter of the device memory, else sparse */
+    CFLR_STORAGE_DENSE = 1,  /* one n x n bit matrix per non-terminal (and a
+                                column-major copy where a production needs one) */
+    CFLR_STORAGE_SPARSE = 2  /* pairs: growable adjacency lists per matrix and
+                                layout, a hash set for membership */
+};
 
 /* Per-solve statistics. */
 typedef struct cflr_stats {
@@ -101,6 +113,7 @@ typedef struct cflr_stats {
                                   (count_traffic) */
     uint64_t device_bytes;     /* device memory held for this solve */
     uint64_t max_delta;        /* largest number of new pairs in one round */
+    uint32_t storage;          /* engine that solved: CFLR_STORAGE_DENSE or _SPARSE */
 } cflr_stats;
 
 void cflr_opts_default(cflr_opts *opts);

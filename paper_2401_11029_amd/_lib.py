@@ -21,7 +21,8 @@ class Opts(C.Structure):
                 ("delta_capacity", C.c_uint64),
                 ("grid_waves", C.c_uint32),
                 ("rounds_per_sync", C.c_uint32),
-                ("chunk_pairs", C.c_uint32)]
+                ("chunk_pairs", C.c_uint32),
+                ("storage", C.c_uint32)]
 
 
 class Stats(C.Structure):
@@ -35,7 +36,8 @@ class Stats(C.Structure):
                 ("product_launches", C.c_uint64),
                 ("algo_bytes", C.c_uint64),
                 ("device_bytes", C.c_uint64),
-                ("max_delta", C.c_uint64)]
+                ("max_delta", C.c_uint64),
+                ("storage", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -19,7 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libcflr.so")
-SOURCES = ["kernels.hip", "engine.cpp", "grammar.cpp", "api.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "sparse_kernels.hip", "engine.cpp", "sparse.cpp", "grammar.cpp", "api.cpp",
+           "server.cpp"]
 ARCH = "gfx950"
 
 

@@ -23,6 +23,7 @@ namespace cflr {
 // instance, keeping only the row-major matrices of the user non-terminals
 // that readout needs.
 void compact_instance(Instance &in) {
+    if (in.sp) return;  // sparse storage keeps only lists
     const uint32_t U = (uint32_t)in.low.user_names.size();
     const uint64_t words = (uint64_t)in.n * in.Wp;
     const uint64_t bytes = words * 8 * U;
@@ -93,6 +94,21 @@ cflr_status guard(F &&f) {
 }
 
 void set_device(cflr_ctx *ctx) { hip_check(hipSetDevice(ctx->device), "hipSetDevice"); }
+
+// Storage of a single solve: dense bit matrices while they take at most a
+// quarter of the device memory, else pair storage (cflr_opts.storage).
+bool use_sparse(cflr_ctx *ctx, const cflr_opts &o, const Lowered &low, uint32_t n) {
+    if (o.storage == CFLR_STORAGE_SPARSE) {
+        if (!o.semi_naive) throw Error(CFLR_EUNSUPPORTED, "sparse storage runs the semi-naive rounds only");
+        return true;
+    }
+    if (!o.semi_naive) return false;
+    if (o.storage == CFLR_STORAGE_DENSE) return false;
+    if (o.storage != CFLR_STORAGE_AUTO) throw Error(CFLR_EINVAL, "unknown storage option");
+    size_t f = 0, t = 0;
+    hip_check(hipMemGetInfo(&f, &t), "hipMemGetInfo");
+    return instance_footprint(low, n) > (uint64_t)t / 4;
+}
 
 cflr_opts effective(const cflr_opts *o) {
     cflr_opts r;
@@ -279,7 +295,20 @@ cflr_status cflr_solve(cflr_ctx *ctx, const cflr_grammar *g, const cflr_graph *g
         hip_check(hipEventCreate(&e1), "event");
         std::shared_ptr<Instance> inst;
         cflr_status status = CFLR_OK;
-        {
+        const bool sparse = use_sparse(ctx, o, g->low, graph->n);
+        if (sparse) {
+            hip_check(hipEventRecord(e0, ctx->stream), "event");
+            inst = make_instance(ctx, g->low, graph, false);
+            bool timed_out = false;
+            sparse_solve(ctx, o, *inst, &timed_out);
+            if (timed_out) status = CFLR_ETIMEOUT;
+            hip_check(hipEventRecord(e1, ctx->stream), "event");
+            hip_check(hipEventSynchronize(e1), "event");
+            float ms = 0;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+            inst->stats.fixpoint_ms = ms;
+            inst->stats.storage = CFLR_STORAGE_SPARSE;
+        } else {
             hip_check(hipEventRecord(e0, ctx->stream), "event");
             inst = make_instance(ctx, g->low, graph);
             Run run(ctx, o, instance_buckets(g->low, graph->n), 1);
@@ -300,6 +329,7 @@ cflr_status cflr_solve(cflr_ctx *ctx, const cflr_grammar *g, const cflr_graph *g
             inst->stats.product_launches = run.product_launches();
             inst->stats.algo_bytes = run.algo_bytes();
             inst->stats.reruns = run.reruns();
+            inst->stats.storage = CFLR_STORAGE_DENSE;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -322,6 +352,8 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
         if (!count) return CFLR_OK;
         set_device(ctx);
         cflr_opts o = effective(opts);
+        if (o.storage == CFLR_STORAGE_SPARSE)
+            return fail(CFLR_EUNSUPPORTED, "batched solves use dense storage only");
         // admission by device memory: instances join as earlier ones finish
         size_t free_b = 0, total_b = 0;
         hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");

@@ -150,7 +150,7 @@ uint64_t instance_pair_slots(const Lowered &low, uint32_t n) {
     return (uint64_t)low.nmat() * key_tiles(n) * n;
 }
 
-std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const cflr_graph *g) {
+std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const cflr_graph *g, bool dense) {
     if (low.nmat() > kMaxMats) throw Error(CFLR_EUNSUPPORTED, "grammar needs more than 65536 matrices");
     auto inst = std::make_shared<Instance>();
     inst->hold = CtxRef(ctx);
@@ -161,17 +161,18 @@ std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const
     std::vector<uint8_t> has_col;
     uint64_t bytes;
     plan_layout(low, g->n, &inst->S, &inst->Wp, &has_col, &bytes);
+    if (!dense) bytes = 0;
     // the product kernel addresses a matrix with 32-bit word offsets
-    if ((uint64_t)g->n * inst->Wp >= (1ull << 32))
+    if (dense && (uint64_t)g->n * inst->Wp >= (1ull << 32))
         throw Error(CFLR_EUNSUPPORTED, "graph too large for dense bit matrices (n * row words >= 2^32)");
     inst->footprint = bytes;
     inst->counts.assign(low.user_names.size(), -1);
     const uint64_t layout_words = (uint64_t)g->n * inst->Wp;
     if (bytes) inst->arena = DevBuf(ctx->pool.get(), bytes);
     uint64_t *p = inst->arena.as<uint64_t>();
-    inst->mats.resize(low.nmat());
+    inst->mats.resize(dense ? low.nmat() : 0);
     uint16_t rrank = 0, crank = 0;
-    for (uint32_t x = 0; x < low.nmat(); x++) {
+    for (uint32_t x = 0; x < inst->mats.size(); x++) {
         MatDev &M = inst->mats[x];
         M.R = p;
         p += layout_words;
@@ -186,7 +187,7 @@ std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const
         }
     }
     // the segment masks follow the matrices (every row start stays 512-byte aligned)
-    for (uint32_t x = 0; x < low.nmat(); x++) {
+    for (uint32_t x = 0; x < inst->mats.size(); x++) {
         MatDev &M = inst->mats[x];
         M.Rm = p;
         p += g->n;
@@ -720,6 +721,10 @@ void instance_counts(Instance &inst) {
     bool need = false;
     for (auto c : inst.counts) need |= c < 0;
     if (!need) return;
+    if (inst.sp) {
+        sparse_counts(inst);
+        return;
+    }
     cflr_ctx *ctx = inst.ctx;
     hipStream_t s = ctx->stream;
     const uint32_t U = (uint32_t)inst.low.user_names.size();
@@ -748,6 +753,10 @@ void instance_copy(Instance &inst, uint32_t nt, uint32_t *src, uint32_t *dst, ui
     if (capacity < count) throw Error(CFLR_EINVAL, "capacity smaller than the pair count");
     *written = count;
     if (!count) return;
+    if (inst.sp) {
+        sparse_copy(inst, nt, src, dst, count, on_device);
+        return;
+    }
     cflr_ctx *ctx = inst.ctx;
     hipStream_t s = ctx->stream;
     DevBuf cnt(ctx->pool.get(), (uint64_t)inst.n * 4);

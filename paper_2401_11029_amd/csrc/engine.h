@@ -80,6 +80,9 @@ struct cflr_ctx {
     uint64_t delta_capacity_hint = 0;  // grown new-pair capacity, reused by later solves
     uint32_t grid_waves_tuned = 0;     // autotuned product grid (0 = not yet)
     uint32_t rounds_per_sync_tuned = 0;  // autotuned rounds per graph replay (batches)
+    // sizes the sparse engine grew to (new-pair buffer, list pool, hash
+    // slots), the starting point of later sparse solves on this context
+    uint64_t sparse_delta_hint = 0, sparse_pool_hint = 0, sparse_slots_hint = 0;
 };
 
 namespace cflr {
@@ -122,7 +125,19 @@ struct cflr_graph {
 
 namespace cflr {
 
-// One graph being solved (or solved): its matrices live in `arena`.
+// Pair storage of a solve on the sparse engine (sparse.cpp, layout in
+// sparse.h): the adjacency-list directory and the pool of list entries,
+// kept for readout.
+struct SparseStore {
+    CtxRef hold;  // first member: released after the buffers
+    cflr_ctx *ctx = nullptr;
+    uint32_t n = 0, nlayouts = 0;
+    DevBuf dir, pool;
+    std::vector<uint32_t> row_layout;  // per matrix; every user non-terminal has one
+};
+
+// One graph being solved (or solved): its matrices live in `arena` (dense
+// storage) or in `sp` (sparse storage).
 struct Instance {
     CtxRef hold;
     cflr_ctx *ctx = nullptr;
@@ -147,6 +162,7 @@ struct Instance {
     cflr_stats stats{};
     // readout cache
     std::vector<int64_t> counts;  // per user NT, -1 = unknown
+    std::shared_ptr<SparseStore> sp;  // set when the sparse engine solved it
 };
 
 // Device bytes an instance of this grammar on n vertices will hold.
@@ -159,7 +175,15 @@ uint64_t instance_buckets(const Lowered &low, uint32_t n);
 // pairs inside the 2^32-entry new-pair buffer.
 uint64_t instance_pair_slots(const Lowered &low, uint32_t n);
 
-std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const cflr_graph *g);
+// dense = false: only the seeding tables (the sparse engine keeps its own
+// storage).
+std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const cflr_graph *g, bool dense = true);
+
+// The sparse engine (sparse.cpp): solves one instance made with dense =
+// false; *timed_out when opts.max_rounds stopped it first.
+void sparse_solve(cflr_ctx *ctx, const cflr_opts &opts, Instance &inst, bool *timed_out);
+void sparse_counts(Instance &inst);
+void sparse_copy(Instance &inst, uint32_t nt, uint32_t *src, uint32_t *dst, uint64_t count, bool on_device);
 
 // A set of instances advancing round by round together (the product
 // launches of a round cover all of them).

@@ -1,0 +1,162 @@
+// sparse.h -- device data layout of the sparse storage engine.
+//
+// The dense engine (kernels.h) keeps every matrix as an n x n bit matrix,
+// which cannot hold a grammar with hundreds of non-terminals on a large
+// graph (644 matrices at 200,000 vertices would need terabytes).  This
+// engine stores each relation by its pairs:
+//
+//  * adjacency lists: per matrix a row-major layout (row i lists the j of
+//    its pairs (i, j)) when the matrix stands in a b slot of some production
+//    or is a result, and a column-major layout (column j lists the i) when
+//    it stands in an a slot (Section 3, optimisation 2 and its pruning: b
+//    needs rows, a needs columns).  A list is a block of u32 entries in one
+//    shared pool with a capacity; appending past it moves the list to a block
+//    of twice the size, so adding the sparse new pairs of a round never
+//    rebuilds a matrix (the requirement of Section 3, optimisation 3) and
+//    every entry is copied O(1) times on average;
+//  * membership: one open-addressing hash set over 64-bit keys
+//    (matrix, i, j) for every matrix, probed linearly; inserting a candidate
+//    with a compare-and-swap both masks it against the matrix and adds it,
+//    and tells exactly one thread that the pair is new;
+//  * use masks: for every matrix x and part (x in an a slot: part 0, in a b
+//    slot: part 1), per vertex k a bit per production using x there, set
+//    once the partner list that production would read at k (b's row k, or
+//    a's column k) is non-empty.  A new pair of x reads the partner lists
+//    of the productions whose bits are set, not of all of them: a
+//    non-terminal used by 193 productions (points-to PT, FT) has a few
+//    non-empty partners per vertex.  This is the block directory of an
+//    indexed non-terminal (Section 3, optimisation 4), kept per vertex.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cflr {
+namespace sp {
+
+constexpr uint64_t kEmpty = ~0ull;      // free hash slot
+constexpr uint64_t kTomb = ~0ull - 1;   // slot of a key taken back after an overflow
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kHoleKey = 0xFFFFFFFFu;  // unused entry of a new-pair buffer
+constexpr uint32_t kMaxVertices = 1u << 24;  // vertex ids fit 24 bits of a key
+constexpr uint32_t kMaxMatrices = 0xFFFFu;   // matrix ids fit 16 bits (0xFFFF reserved)
+// New-pair buffer slots a wave reserves at a time; a wave leaves at most one
+// partly used chunk (its unused slots become holes).
+constexpr uint32_t kChunk = 256;
+// Workgroups (of 4 waves) of each seeding kernel at most: the seed buffer
+// needs 2 * 4 * kSeedBlocks * kChunk slots beyond the seeds themselves.
+constexpr uint32_t kSeedBlocks = 2048;
+
+// Hash key of pair (i, j) of matrix m; never equal to kEmpty or kTomb
+// because m < 0xFFFF.
+__host__ __device__ inline uint64_t pair_key(uint32_t m, uint32_t i, uint32_t j) {
+    return ((uint64_t)m << 48) | ((uint64_t)i << 24) | (uint64_t)j;
+}
+
+// One adjacency list: entries pool[off, off + len), room for cap.
+struct Dir {
+    uint64_t off;
+    uint32_t len, cap;
+};
+
+// A production seen from one of its operands: the head c and the partner
+// layout the product reads (part 0: b's row layout; part 1: a's column
+// layout).
+struct Use {
+    uint32_t c;
+    uint32_t layout;
+};
+
+// A use mask to update when a list of some layout becomes non-empty at
+// vertex k: word base + k * words + bit / 64 of the mask array, bit % 64.
+struct Obs {
+    uint64_t base;
+    uint32_t words;
+    uint32_t bit;
+};
+
+struct MatInfo {
+    uint32_t row_layout, col_layout;  // kNone when absent
+    uint32_t use0, nuse0;             // part 0 uses (x in an a slot) in the use table
+    uint32_t use1, nuse1;             // part 1 uses (x in a b slot)
+    uint32_t w0, w1;                  // mask words per vertex for each part
+    uint64_t mask0, mask1;            // first word of each part's masks
+};
+
+// New pairs of a round: (matrix, i, j); kHoleKey marks an unused entry.
+struct PairBuf {
+    uint32_t *key, *i, *j;
+    unsigned long long *count;  // entries taken (may exceed cap after an overflow)
+    uint64_t cap;
+};
+
+// Everything a kernel of a round reads; all device pointers.
+struct State {
+    uint32_t n;
+    uint32_t nlayouts;
+    const MatInfo *mats;
+    const Use *uses;
+    const uint32_t *obs_ptr;  // [nlayouts + 1]
+    const Obs *obs;
+    Dir *dir;                 // [nlayouts * n]
+    uint32_t *cur;            // [nlayouts * n]: pending count, then write cursor
+    uint64_t *mask;           // use masks
+    uint32_t *pool;
+    uint64_t pool_cap;
+    unsigned long long *hash;  // hash slots
+    uint64_t hash_mask;        // slots - 1 (a power of two minus one)
+    // bookkeeping words (kCtl* below)
+    unsigned long long *ctl;
+    uint64_t *touched;  // lists with pending entries: layout * n + row
+    uint64_t touched_cap;
+    uint64_t *moves;    // queued list copies: (from, to, length)
+    uint64_t moves_cap;
+};
+
+constexpr int kCtlPoolTop = 0,   // pool entries handed out
+    kCtlTouched = 1,             // lists touched by this round's new pairs
+    kCtlAlloc = 2,               // pool entries the moves of this round need
+    kCtlHalt = 3,                // an overflow: the rest of the round is skipped
+    kCtlPoolOver = 4,            // the planned moves do not fit the pool
+    kCtlBufOver = 5,             // a new-pair buffer is full
+    kCtlTomb = 6,                // keys taken back after an overflow
+    kCtlTasks = 7,               // product tasks taken
+    kCtlMoves = 8,               // queued list copies
+    kCtlHashFull = 9,            // an insert found no free slot
+    kCtlNew = 10,                // new pairs appended (seeding, or a round's product)
+    kCtlTouchedOver = 11,        // more touched lists than the array holds
+    kCtlProducts = 12,           // boolean products (list entries read) of the products
+    kCtlWords = 13;
+
+// ------------------------------------------------------------------ launchers
+
+// Seeding: every edge (u, t, v) gives (x, u, v) for every x -> t, and every
+// x -> eps gives (x, i, i) for all i; new pairs go to `out`.
+hipError_t launch_seed(const State &S, const uint32_t *src, const uint32_t *dst, const uint32_t *lab, uint64_t m,
+                       const uint32_t *lm_ptr, const uint32_t *lm_mat, const uint32_t *eps_mat, uint32_t n_eps,
+                       PairBuf out, hipStream_t s);
+// Add the new pairs `in` to the adjacency lists (count, plan, check, move, scatter, reset).
+// With resume = true only the steps after the capacity check run (after the
+// host grew an overflowing pool).
+hipError_t launch_integrate(const State &S, PairBuf in, bool resume, uint32_t grid, hipStream_t s);
+// Zero the counters a round starts from (touched lists, planned
+// allocation, tasks, queued copies).
+hipError_t launch_round_start(const State &S, hipStream_t s);
+// The round's product: every pair of `in`, for every use whose mask bit is
+// set, against the partner list; candidates inserted in the hash set; new
+// ones appended to `out`.
+hipError_t launch_product(const State &S, PairBuf in, PairBuf out, uint32_t grid_waves, hipStream_t s);
+// Re-insert every key of `old_tab` (tombstones dropped) into S.hash (empty).
+hipError_t launch_rehash(const State &S, const unsigned long long *old_tab, uint64_t old_slots, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *a, uint64_t n, uint32_t v, hipStream_t s);
+// Readout of one row layout: per-row counts (sum into *total), then the
+// pairs sorted by (i, j) at the exclusive offsets of the counts.
+hipError_t launch_layout_count(const Dir *dir, uint32_t n, unsigned long long *total, hipStream_t s);
+hipError_t launch_layout_write(const Dir *dir, const uint32_t *pool, uint32_t n, uint64_t *off_scratch,
+                               uint64_t *bitmap_scratch, uint32_t sort_grid, uint32_t *src, uint32_t *dst,
+                               hipStream_t s);
+
+}  // namespace sp
+}  // namespace cflr

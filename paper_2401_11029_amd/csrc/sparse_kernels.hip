@@ -1,0 +1,749 @@
+// sparse_kernels.hip -- kernels of the sparse storage engine (gfx950, wave64).
+//
+// A round of the semi-naive fixpoint (Section 3, optimisation 1) on pair
+// storage (layout in sparse.h):
+//
+//   integrate  the previous round's new pairs are appended to the
+//              adjacency lists of their matrix (count per list -> plan the
+//              moves of lists that outgrow their block -> check the pool ->
+//              move -> scatter), and lists that become non-empty set their
+//              bit in the use masks of the productions that read them;
+//   product    every new pair of a matrix x meets, for every production
+//              using x whose mask bit is set at the pair's partner vertex,
+//              the partner list: part 0 (x = a of c -> a b, new pair (i, k))
+//              reads row k of b and yields (c, i, j); part 1 (x = b, new pair
+//              (k, j)) reads column k of a and yields (c, i, j).  Each
+//              candidate is inserted into the hash set; the inserts that
+//              succeed are the round's new pairs of c (New_c = Cand \ M_c and
+//              M_c <- M_c U New_c in one compare-and-swap).
+//
+// A wave expands the lists of its 64 lanes together: the lanes' list
+// lengths are prefix-summed and each pass takes 64 consecutive products, a
+// lane finding the list its product belongs to by a binary search over the
+// prefix sums.  New pairs are appended in chunks reserved per wave.
+#include <hip/hip_runtime.h>
+
+#include "sparse.h"
+
+namespace cflr {
+namespace sp {
+
+namespace {
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+__device__ __forceinline__ uint32_t first_lane(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint64_t first_lane64(uint64_t v) {
+    return ((uint64_t)first_lane((uint32_t)(v >> 32)) << 32) | first_lane((uint32_t)v);
+}
+
+__device__ __forceinline__ uint32_t shfl32(uint32_t v, uint32_t l) { return (uint32_t)__shfl((int)v, (int)l, 64); }
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, uint32_t l) {
+    return ((uint64_t)shfl32((uint32_t)(v >> 32), l) << 32) | shfl32((uint32_t)v, l);
+}
+
+// exclusive prefix sum over the wave; *total = sum over all lanes
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t *total) {
+    const uint32_t lane = lane_id();
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, d, 64);
+        if (lane >= (uint32_t)d) x += y;
+    }
+    *total = __builtin_amdgcn_readlane(x, 63);
+    return x - v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+#pragma unroll
+    for (int d = 32; d; d >>= 1) v += shfl64(v, lane_id() ^ (uint32_t)d);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long load_relaxed(unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// 64-bit finaliser of SplitMix64 (Steele, Lea and Flood, 2014): spreads the
+// packed (matrix, i, j) keys over the table.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+constexpr uint32_t kMaxProbes = 4096;  // the host keeps the load below 0.7
+enum { kPresent = 0, kInserted = 1, kFull = 2 };
+
+// Linear-probing insert.  kInserted: this thread added the key (its slot in
+// *where); kPresent: the key was there (or another thread added it first);
+// kFull: no free slot within kMaxProbes (the host re-runs after a rehash).
+__device__ __forceinline__ int hash_insert(unsigned long long *tab, uint64_t hmask, uint64_t key, uint64_t *where) {
+    uint64_t h = mix64(key) & hmask;
+    for (uint32_t p = 0; p < kMaxProbes; p++) {
+        const unsigned long long v = load_relaxed(&tab[h]);
+        if (v == key) return kPresent;
+        if (v == kEmpty) {
+            const unsigned long long prev = atomicCAS(&tab[h], (unsigned long long)kEmpty, (unsigned long long)key);
+            if (prev == kEmpty) {
+                *where = h;
+                return kInserted;
+            }
+            if (prev == key) return kPresent;
+        }
+        h = (h + 1) & hmask;
+    }
+    return kFull;
+}
+
+// Append slots of a new-pair buffer, reserved per wave in chunks so that one
+// device-scope atomic serves many appends; unused slots of a chunk become
+// holes when the wave moves on or exits (kChunk slots at a time).
+
+struct Chunk {
+    uint64_t pos = 0, end = 0;  // wave-uniform
+};
+
+__device__ __forceinline__ void chunk_retire(const PairBuf &B, Chunk &ch) {
+    for (uint64_t x = ch.pos + lane_id(); x < ch.end; x += 64) B.key[x] = kHoleKey;
+    ch.pos = ch.end;
+}
+
+// Every lane of the wave calls this together.  Lane l gets `need` slots at
+// *pos.  false: the buffer is full (flags set, nothing reserved).
+__device__ __forceinline__ bool chunk_reserve(const PairBuf &B, Chunk &ch, uint32_t need, uint64_t *pos,
+                                              unsigned long long *ctl) {
+    uint32_t total;
+    const uint32_t pre = wave_excl_scan(need, &total);
+    *pos = 0;
+    if (!total) return true;
+    if (ch.pos + total > ch.end) {
+        chunk_retire(B, ch);
+        const uint64_t want = total > kChunk ? total : kChunk;
+        unsigned long long base = 0;
+        if (lane_id() == 0) base = atomicAdd(B.count, (unsigned long long)want);
+        base = first_lane64(base);
+        if (base + want > B.cap) {
+            for (uint64_t x = base + lane_id(); x < B.cap && x < base + want; x += 64) B.key[x] = kHoleKey;
+            ch.pos = ch.end = 0;
+            if (lane_id() == 0) {
+                atomicOr(&ctl[kCtlBufOver], 1ull);
+                atomicOr(&ctl[kCtlHalt], 1ull);
+            }
+            return false;
+        }
+        ch.pos = base;
+        ch.end = base + want;
+    }
+    *pos = ch.pos + pre;
+    ch.pos += total;
+    return true;
+}
+
+// Insert (m, i, j) for the lanes with `has`; append the new ones.  Every
+// lane calls this together.  false: an overflow (this wave's new keys of
+// the call were taken back; the round is re-run).
+__device__ __forceinline__ bool insert_append(const State &S, const PairBuf &out, Chunk &ch, uint64_t &appended,
+                                              bool has, uint32_t m, uint32_t i, uint32_t j) {
+    int ins = kPresent;
+    uint64_t where = 0;
+    if (has) ins = hash_insert(S.hash, S.hash_mask, pair_key(m, i, j), &where);
+    const bool full = __any(ins == kFull);
+    uint64_t pos = 0;
+    bool ok = !full;
+    if (ok) ok = chunk_reserve(out, ch, ins == kInserted ? 1u : 0u, &pos, S.ctl);
+    if (!ok) {
+        if (ins == kInserted) {
+            atomicExch(&S.hash[where], (unsigned long long)kTomb);
+            atomicAdd(&S.ctl[kCtlTomb], 1ull);
+        }
+        if (full && lane_id() == 0) {
+            atomicOr(&S.ctl[kCtlHashFull], 1ull);
+            atomicOr(&S.ctl[kCtlHalt], 1ull);
+        }
+        return false;
+    }
+    if (ins == kInserted) {
+        out.key[pos] = m;
+        out.i[pos] = i;
+        out.j[pos] = j;
+    }
+    appended += (uint64_t)__popcll(__ballot(ins == kInserted));
+    return true;
+}
+
+// A wave's count of appended pairs, added once when it exits.
+__device__ __forceinline__ void add_appended(const State &S, uint64_t appended) {
+    if (lane_id() == 0 && appended) atomicAdd(&S.ctl[kCtlNew], (unsigned long long)appended);
+}
+
+__device__ __forceinline__ uint64_t wave_global_id() {
+    return ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+}
+__device__ __forceinline__ uint64_t waves_in_grid() { return ((uint64_t)gridDim.x * blockDim.x) / 64; }
+
+}  // namespace
+
+// ------------------------------------------------------------------ seeding
+
+__global__ __launch_bounds__(256) void seed_edges_kernel(State S, const uint32_t *src, const uint32_t *dst,
+                                                         const uint32_t *lab, uint64_t m, const uint32_t *lm_ptr,
+                                                         const uint32_t *lm_mat, PairBuf out) {
+    Chunk ch;
+    uint64_t appended = 0;
+    for (uint64_t base = wave_global_id() * 64; base < m; base += waves_in_grid() * 64) {
+        const uint64_t e = base + lane_id();
+        uint32_t q0 = 0, q1 = 0, u = 0, v = 0;
+        if (e < m) {
+            const uint32_t l = lab[e];
+            q0 = lm_ptr[l];
+            q1 = lm_ptr[l + 1];
+            u = src[e];
+            v = dst[e];
+        }
+        for (uint32_t q = q0;; q++) {
+            const bool has = q < q1;
+            if (!__any(has)) break;
+            if (!insert_append(S, out, ch, appended, has, has ? lm_mat[q] : 0u, u, v)) {
+                add_appended(S, appended);
+                return;
+            }
+        }
+    }
+    chunk_retire(out, ch);
+    add_appended(S, appended);
+}
+
+__global__ __launch_bounds__(256) void seed_eps_kernel(State S, const uint32_t *eps_mat, uint32_t n_eps,
+                                                       PairBuf out) {
+    Chunk ch;
+    uint64_t appended = 0;
+    const uint64_t total = (uint64_t)n_eps * S.n;
+    for (uint64_t base = wave_global_id() * 64; base < total; base += waves_in_grid() * 64) {
+        const uint64_t x = base + lane_id();
+        const bool has = x < total;
+        const uint32_t e = has ? (uint32_t)(x / S.n) : 0u, i = has ? (uint32_t)(x % S.n) : 0u;
+        if (!insert_append(S, out, ch, appended, has, has ? eps_mat[e] : 0u, i, i)) {
+            add_appended(S, appended);
+            return;
+        }
+    }
+    chunk_retire(out, ch);
+    add_appended(S, appended);
+}
+
+// --------------------------------------------------------------- integrate
+
+// Reset the round's counters (touched rows, planned allocation, tasks,
+// moves).
+__global__ void round_start_kernel(State S) {
+    S.ctl[kCtlTouched] = 0;
+    S.ctl[kCtlAlloc] = 0;
+    S.ctl[kCtlTasks] = 0;
+    S.ctl[kCtlMoves] = 0;
+    S.ctl[kCtlNew] = 0;
+}
+
+__device__ __forceinline__ void touch(const State &S, uint32_t layout, uint32_t r) {
+    const uint64_t idx = (uint64_t)layout * S.n + r;
+    const uint32_t p = atomicAdd(&S.cur[idx], 1u);
+    if (p == 0) {
+        const unsigned long long t = atomicAdd(&S.ctl[kCtlTouched], 1ull);
+        if (t < S.touched_cap) S.touched[t] = idx;
+        else atomicOr(&S.ctl[kCtlTouchedOver], 1ull);
+    }
+}
+
+__global__ __launch_bounds__(256) void count_kernel(State S, PairBuf in) {
+    uint64_t nin = *in.count;
+    if (nin > in.cap) nin = in.cap;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < nin;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t key = in.key[x];
+        if (key == kHoleKey) continue;
+        const MatInfo mi = S.mats[key];
+        if (mi.row_layout != kNone) touch(S, mi.row_layout, in.i[x]);
+        if (mi.col_layout != kNone) touch(S, mi.col_layout, in.j[x]);
+    }
+}
+
+__device__ __forceinline__ uint32_t grown_cap(uint32_t need) {
+    uint32_t c = 2;
+    while (c < need) c <<= 1;
+    return c;
+}
+
+__device__ __forceinline__ uint64_t touched_count(const State &S) {
+    const uint64_t t = S.ctl[kCtlTouched];
+    return t < S.touched_cap ? t : S.touched_cap;
+}
+
+// The pool entries the lists that outgrow their blocks will take.
+__global__ __launch_bounds__(256) void plan_kernel(State S) {
+    const uint64_t nt = touched_count(S);
+    uint64_t sum = 0;
+    for (uint64_t base = wave_global_id() * 64; base < nt; base += waves_in_grid() * 64) {
+        const uint64_t t = base + lane_id();
+        if (t < nt) {
+            const uint64_t idx = S.touched[t];
+            const Dir d = S.dir[idx];
+            const uint64_t need = (uint64_t)d.len + S.cur[idx];
+            if (need > d.cap) sum += grown_cap((uint32_t)need);
+        }
+    }
+    sum = wave_sum64(sum);
+    if (lane_id() == 0 && sum) atomicAdd(&S.ctl[kCtlAlloc], (unsigned long long)sum);
+}
+
+// One thread: does the planned allocation fit the pool?  If not the round
+// halts before any list moves (the host grows the pool and resumes here).
+__global__ void check_kernel(State S) {
+    if (S.ctl[kCtlTouchedOver]) {
+        S.ctl[kCtlHalt] = 1;  // the host reports an internal error (it sizes the array to rule this out)
+    } else if (S.ctl[kCtlPoolTop] + S.ctl[kCtlAlloc] > S.pool_cap) {
+        S.ctl[kCtlPoolOver] = 1;
+        S.ctl[kCtlHalt] = 1;
+    } else {
+        S.ctl[kCtlAlloc] = 0;
+    }
+}
+
+// Per touched list: new length; a list that outgrows its block gets a block
+// of the next power of two (short lists are copied here, longer ones are
+// queued for the wave-wide copy); the cursor is set to the old length; a
+// list that was empty sets its bit in every use mask that reads it.
+constexpr uint32_t kInlineCopy = 16;
+
+__global__ __launch_bounds__(256) void move_kernel(State S) {
+    if (S.ctl[kCtlHalt]) return;
+    const uint64_t nt = touched_count(S);
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < nt; t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t idx = S.touched[t];
+        const Dir d = S.dir[idx];
+        const uint32_t pend = S.cur[idx];
+        const uint32_t need = d.len + pend;
+        Dir nd = d;
+        nd.len = need;
+        if (need > d.cap) {
+            nd.cap = grown_cap(need);
+            nd.off = atomicAdd(&S.ctl[kCtlPoolTop], (unsigned long long)nd.cap);
+            bool queued = false;
+            if (d.len > kInlineCopy) {
+                const unsigned long long mv = atomicAdd(&S.ctl[kCtlMoves], 1ull);
+                if (mv < S.moves_cap) {
+                    S.moves[3 * mv] = d.off;
+                    S.moves[3 * mv + 1] = nd.off;
+                    S.moves[3 * mv + 2] = d.len;
+                    queued = true;
+                }
+            }
+            if (!queued)
+                for (uint32_t q = 0; q < d.len; q++) S.pool[nd.off + q] = S.pool[d.off + q];
+        }
+        S.dir[idx] = nd;
+        S.cur[idx] = d.len;
+        if (d.len == 0) {
+            const uint32_t layout = (uint32_t)(idx / S.n), r = (uint32_t)(idx % S.n);
+            for (uint32_t o = S.obs_ptr[layout]; o < S.obs_ptr[layout + 1]; o++) {
+                const Obs ob = S.obs[o];
+                atomicOr((unsigned long long *)&S.mask[ob.base + (uint64_t)r * ob.words + ob.bit / 64],
+                         1ull << (ob.bit % 64));
+            }
+        }
+    }
+}
+
+// The queued copies of longer lists, one wave per list.
+__global__ __launch_bounds__(256) void copy_kernel(State S) {
+    if (S.ctl[kCtlHalt]) return;
+    uint64_t nm = S.ctl[kCtlMoves];
+    if (nm > S.moves_cap) nm = S.moves_cap;
+    for (uint64_t w = wave_global_id(); w < nm; w += waves_in_grid()) {
+        const uint64_t from = S.moves[3 * w], to = S.moves[3 * w + 1], len = S.moves[3 * w + 2];
+        for (uint64_t q = lane_id(); q < len; q += 64) S.pool[to + q] = S.pool[from + q];
+    }
+}
+
+__global__ __launch_bounds__(256) void scatter_kernel(State S, PairBuf in) {
+    if (S.ctl[kCtlHalt]) return;
+    uint64_t nin = *in.count;
+    if (nin > in.cap) nin = in.cap;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < nin;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t key = in.key[x];
+        if (key == kHoleKey) continue;
+        const MatInfo mi = S.mats[key];
+        const uint32_t i = in.i[x], j = in.j[x];
+        if (mi.row_layout != kNone) {
+            const uint64_t idx = (uint64_t)mi.row_layout * S.n + i;
+            const uint32_t p = atomicAdd(&S.cur[idx], 1u);
+            const Dir d = S.dir[idx];
+            if (p < d.cap) S.pool[d.off + p] = j;
+        }
+        if (mi.col_layout != kNone) {
+            const uint64_t idx = (uint64_t)mi.col_layout * S.n + j;
+            const uint32_t p = atomicAdd(&S.cur[idx], 1u);
+            const Dir d = S.dir[idx];
+            if (p < d.cap) S.pool[d.off + p] = i;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void unmark_kernel(State S) {
+    if (S.ctl[kCtlHalt]) return;
+    const uint64_t nt = touched_count(S);
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < nt; t += (uint64_t)gridDim.x * blockDim.x)
+        S.cur[S.touched[t]] = 0;
+}
+
+// ------------------------------------------------------------------ product
+
+// Persistent waves; a task is 64 consecutive entries of the new-pair buffer
+// `in`, one per lane.  Each lane walks the set bits of its pair's use masks
+// (part 0 at its column, part 1 at its row), one use per step; per step the
+// wave expands the 64 lanes' partner lists together.
+__global__ __launch_bounds__(256) void product_kernel(State S, PairBuf in, PairBuf out) {
+    const uint32_t lane = lane_id();
+    uint64_t nin = *in.count;
+    if (nin > in.cap) nin = in.cap;
+    const uint64_t ntask = (nin + 63) / 64;
+    Chunk ch;
+    uint64_t appended = 0, products = 0;
+    bool failed = false;
+    while (!failed) {
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(&S.ctl[kCtlTasks], 1ull);
+        t = first_lane64(t);
+        if (t >= ntask) break;
+        if (first_lane64(load_relaxed(&S.ctl[kCtlHalt]))) break;
+        const uint64_t e = t * 64 + lane;
+        uint32_t x = kHoleKey, pi = 0, pj = 0;
+        if (e < nin) {
+            x = in.key[e];
+            pi = in.i[e];
+            pj = in.j[e];
+        }
+        bool more = x != kHoleKey;
+        MatInfo mi{};
+        if (more) mi = S.mats[x];
+        uint32_t part = 0, w = 0;
+        uint64_t bits = 0;
+        while (__any(more)) {
+            // this lane's next use: head c, partner layout, fixed index of
+            // the candidates and the partner vertex k
+            uint32_t c = 0, lay = kNone, fixed = 0, k = 0, col = 0;
+            if (more) {
+                while (!bits) {
+                    if (part == 0) {
+                        if (w < mi.w0) {
+                            bits = S.mask[mi.mask0 + (uint64_t)pj * mi.w0 + w];
+                            w++;
+                        } else {
+                            part = 1;
+                            w = 0;
+                        }
+                    } else if (w < mi.w1) {
+                        bits = S.mask[mi.mask1 + (uint64_t)pi * mi.w1 + w];
+                        w++;
+                    } else {
+                        more = false;
+                        break;
+                    }
+                }
+                if (bits) {
+                    const uint32_t q = (w - 1) * 64 + (uint32_t)__builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    const Use u = S.uses[(part == 0 ? mi.use0 : mi.use1) + q];
+                    c = u.c;
+                    lay = u.layout;
+                    // part 0: pair (i, k) of a meets row k of b -> (c, i, j')
+                    // part 1: pair (k, j) of b meets column k of a -> (c, i', j)
+                    fixed = part == 0 ? pi : pj;
+                    k = part == 0 ? pj : pi;
+                    col = part;
+                }
+            }
+            uint64_t off = 0;
+            uint32_t len = 0;
+            if (lay != kNone) {
+                const Dir d = S.dir[(uint64_t)lay * S.n + k];
+                off = d.off;
+                len = d.len;
+            }
+            uint32_t total;
+            const uint32_t pre = wave_excl_scan(len, &total);
+            products += total;
+            for (uint32_t r = 0; r < total; r += 64) {
+                const uint32_t tt = r + lane;
+                uint32_t src = 0;  // last lane whose first product is <= tt
+#pragma unroll
+                for (uint32_t step = 32; step; step >>= 1)
+                    if (shfl32(pre, src + step) <= tt) src += step;
+                const uint64_t soff = shfl64(off, src);
+                const uint32_t spre = shfl32(pre, src), sc = shfl32(c, src), sfix = shfl32(fixed, src),
+                               scol = shfl32(col, src);
+                const bool has = tt < total;
+                uint32_t ci = 0, cj = 0;
+                if (has) {
+                    const uint32_t v = S.pool[soff + (tt - spre)];
+                    ci = scol ? v : sfix;
+                    cj = scol ? sfix : v;
+                }
+                if (!insert_append(S, out, ch, appended, has, sc, ci, cj)) {
+                    failed = true;
+                    break;
+                }
+            }
+            if (failed) break;
+        }
+    }
+    chunk_retire(out, ch);
+    add_appended(S, appended);
+    if (lane == 0 && products) atomicAdd(&S.ctl[kCtlProducts], (unsigned long long)products);
+}
+
+// ------------------------------------------------------------------- rehash
+
+__global__ __launch_bounds__(256) void rehash_kernel(State S, const unsigned long long *old_tab, uint64_t old_slots) {
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < old_slots;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const unsigned long long v = old_tab[x];
+        if (v == kEmpty || v == kTomb) continue;
+        uint64_t where;
+        if (hash_insert(S.hash, S.hash_mask, v, &where) == kFull) {
+            atomicOr(&S.ctl[kCtlHashFull], 1ull);
+            atomicOr(&S.ctl[kCtlHalt], 1ull);
+        }
+    }
+}
+
+__global__ void fill_u64_kernel(unsigned long long *a, uint64_t n, unsigned long long v) {
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n; x += (uint64_t)gridDim.x * blockDim.x)
+        a[x] = v;
+}
+
+__global__ void fill_u32_kernel(uint32_t *a, uint64_t n, uint32_t v) {
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n; x += (uint64_t)gridDim.x * blockDim.x)
+        a[x] = v;
+}
+
+// ------------------------------------------------------------------ readout
+
+__global__ __launch_bounds__(256) void layout_count_kernel(const Dir *dir, uint32_t n, unsigned long long *total) {
+    uint64_t s = 0;
+    for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x)
+        s += dir[r].len;
+    s = wave_sum64(s);
+    if (lane_id() == 0 && s) atomicAdd(total, (unsigned long long)s);
+}
+
+// exclusive scan of the list lengths into 64-bit offsets, one workgroup
+__global__ __launch_bounds__(1024) void offsets_kernel(const Dir *dir, uint32_t n, uint64_t *off) {
+    __shared__ uint64_t part[1024];
+    __shared__ uint64_t carry;
+    const uint32_t t = threadIdx.x;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < n; base += 1024) {
+        const uint64_t v = base + t < n ? dir[base + t].len : 0;
+        part[t] = v;
+        __syncthreads();
+        for (uint32_t d = 1; d < 1024; d <<= 1) {
+            const uint64_t u = t >= d ? part[t - d] : 0;
+            __syncthreads();
+            part[t] += u;
+            __syncthreads();
+        }
+        if (base + t < n) off[base + t] = carry + part[t] - v;
+        __syncthreads();
+        if (t == 1023) carry += part[1023];
+        __syncthreads();
+    }
+}
+
+// Rows in (i, j) order: one workgroup per row.  A list of at most kSortMax
+// entries is sorted in LDS (bitonic); a longer one is put into a bit set of
+// the n columns (this workgroup's part of `bitmap`, zero between rows) and
+// read back in column order.
+constexpr uint32_t kSortThreads = 256, kSortMax = 2048;
+
+__global__ __launch_bounds__(kSortThreads) void row_write_kernel(const Dir *dir, const uint32_t *pool, uint32_t n,
+                                                                 const uint64_t *off, uint64_t *bitmap,
+                                                                 uint32_t *src, uint32_t *dst) {
+    __shared__ uint32_t v[kSortMax];
+    __shared__ uint32_t cnt[kSortThreads];
+    const uint32_t t = threadIdx.x;
+    const uint64_t nw = ((uint64_t)n + 63) / 64;
+    uint64_t *bm = bitmap + (uint64_t)blockIdx.x * nw;
+    for (uint32_t r = blockIdx.x; r < n; r += gridDim.x) {
+        const Dir d = dir[r];
+        const uint64_t o = off[r];
+        if (d.len == 0) continue;
+        if (d.len <= kSortMax) {
+            uint32_t m = 2;
+            while (m < d.len) m <<= 1;
+            for (uint32_t q = t; q < m; q += kSortThreads) v[q] = q < d.len ? pool[d.off + q] : 0xFFFFFFFFu;
+            __syncthreads();
+            for (uint32_t k = 2; k <= m; k <<= 1) {
+                for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+                    for (uint32_t q = t; q < m; q += kSortThreads) {
+                        const uint32_t p = q ^ jj;
+                        if (p > q) {
+                            const bool up = (q & k) == 0;
+                            const uint32_t a = v[q], b = v[p];
+                            if ((a > b) == up) {
+                                v[q] = b;
+                                v[p] = a;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (uint32_t q = t; q < d.len; q += kSortThreads) {
+                src[o + q] = r;
+                dst[o + q] = v[q];
+            }
+            __syncthreads();
+            continue;
+        }
+        for (uint32_t q = t; q < d.len; q += kSortThreads) {
+            const uint32_t c = pool[d.off + q];
+            atomicOr((unsigned long long *)&bm[c >> 6], 1ull << (c & 63));
+        }
+        __syncthreads();
+        // thread t reads words [w0, w1) in order
+        const uint64_t per = (nw + kSortThreads - 1) / kSortThreads;
+        const uint64_t w0 = (uint64_t)t * per < nw ? (uint64_t)t * per : nw;
+        const uint64_t w1 = w0 + per < nw ? w0 + per : nw;
+        uint32_t c = 0;
+        for (uint64_t w = w0; w < w1; w++) c += (uint32_t)__popcll(bm[w]);
+        cnt[t] = c;
+        __syncthreads();
+        for (uint32_t dd = 1; dd < kSortThreads; dd <<= 1) {
+            const uint32_t u = t >= dd ? cnt[t - dd] : 0;
+            __syncthreads();
+            cnt[t] += u;
+            __syncthreads();
+        }
+        uint64_t p = o + cnt[t] - c;
+        for (uint64_t w = w0; w < w1; w++) {
+            uint64_t b = bm[w];
+            bm[w] = 0;
+            while (b) {
+                src[p] = r;
+                dst[p] = (uint32_t)(w * 64 + (uint64_t)__builtin_ctzll(b));
+                b &= b - 1;
+                p++;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ host launchers
+
+#define SP_LAUNCH_CHECK()                      \
+    do {                                       \
+        hipError_t e_ = hipGetLastError();     \
+        if (e_ != hipSuccess) return e_;       \
+    } while (0)
+
+static uint32_t grid_for(uint64_t items, uint32_t threads, uint32_t cap) {
+    uint64_t g = (items + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (uint32_t)g;
+}
+
+hipError_t launch_seed(const State &S, const uint32_t *src, const uint32_t *dst, const uint32_t *lab, uint64_t m,
+                       const uint32_t *lm_ptr, const uint32_t *lm_mat, const uint32_t *eps_mat, uint32_t n_eps,
+                       PairBuf out, hipStream_t s) {
+    if (m) {
+        seed_edges_kernel<<<grid_for(m, 256, kSeedBlocks), 256, 0, s>>>(S, src, dst, lab, m, lm_ptr, lm_mat, out);
+        SP_LAUNCH_CHECK();
+    }
+    const uint64_t e = (uint64_t)n_eps * S.n;
+    if (e) {
+        seed_eps_kernel<<<grid_for(e, 256, kSeedBlocks), 256, 0, s>>>(S, eps_mat, n_eps, out);
+        SP_LAUNCH_CHECK();
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_round_start(const State &S, hipStream_t s) {
+    round_start_kernel<<<1, 1, 0, s>>>(S);
+    SP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_integrate(const State &S, PairBuf in, bool resume, uint32_t grid, hipStream_t s) {
+    if (!resume) {
+        count_kernel<<<grid, 256, 0, s>>>(S, in);
+        SP_LAUNCH_CHECK();
+        plan_kernel<<<grid, 256, 0, s>>>(S);
+        SP_LAUNCH_CHECK();
+    }
+    check_kernel<<<1, 1, 0, s>>>(S);
+    SP_LAUNCH_CHECK();
+    move_kernel<<<grid, 256, 0, s>>>(S);
+    SP_LAUNCH_CHECK();
+    copy_kernel<<<grid, 256, 0, s>>>(S);
+    SP_LAUNCH_CHECK();
+    scatter_kernel<<<grid, 256, 0, s>>>(S, in);
+    SP_LAUNCH_CHECK();
+    unmark_kernel<<<grid, 256, 0, s>>>(S);
+    SP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_product(const State &S, PairBuf in, PairBuf out, uint32_t grid_waves, hipStream_t s) {
+    const uint32_t blocks = grid_waves / 4 ? grid_waves / 4 : 1;
+    product_kernel<<<blocks, 256, 0, s>>>(S, in, out);
+    SP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_rehash(const State &S, const unsigned long long *old_tab, uint64_t old_slots, hipStream_t s) {
+    rehash_kernel<<<grid_for(old_slots, 256, 65536), 256, 0, s>>>(S, old_tab, old_slots);
+    SP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long v, hipStream_t s) {
+    if (!n) return hipSuccess;
+    fill_u64_kernel<<<grid_for(n, 256, 65536), 256, 0, s>>>(a, n, v);
+    SP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_fill_u32(uint32_t *a, uint64_t n, uint32_t v, hipStream_t s) {
+    if (!n) return hipSuccess;
+    fill_u32_kernel<<<grid_for(n, 256, 65536), 256, 0, s>>>(a, n, v);
+    SP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_layout_count(const Dir *dir, uint32_t n, unsigned long long *total, hipStream_t s) {
+    if (!n) return hipSuccess;
+    layout_count_kernel<<<grid_for(n, 256, 4096), 256, 0, s>>>(dir, n, total);
+    SP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_layout_write(const Dir *dir, const uint32_t *pool, uint32_t n, uint64_t *off_scratch,
+                               uint64_t *bitmap_scratch, uint32_t sort_grid, uint32_t *src, uint32_t *dst,
+                               hipStream_t s) {
+    if (!n) return hipSuccess;
+    offsets_kernel<<<1, 1024, 0, s>>>(dir, n, off_scratch);
+    SP_LAUNCH_CHECK();
+    row_write_kernel<<<sort_grid, kSortThreads, 0, s>>>(dir, pool, n, off_scratch, bitmap_scratch, src, dst);
+    SP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+}  // namespace sp
+}  // namespace cflr
