@@ -82,6 +82,30 @@ struct MatInfo {
     uint32_t use1, nuse1;             // part 1 uses (x in a b slot)
     uint32_t w0, w1;                  // mask words per vertex for each part
     uint64_t mask0, mask1;            // first word of each part's masks
+    uint32_t rank0, rank1;            // index among the matrices with part 0 (part 1) uses; kNone if none
+};
+
+// The new pairs of a round in key order, for the grouped product: a pair
+// (i, j) of a matrix x with part 0 uses goes to bucket rank0(x) * n + i
+// (its key i, its partner j), and with part 1 uses to bucket
+// nb0 + rank1(x) * n + j (key j, partner i).  Buckets are laid out in
+// order, so all part 0 entries come first.  A bucket is one output row (part
+// 0) or column (part 1) of every production using x: its products are the
+// union of the partner lists its entries select.
+struct KeySort {
+    uint64_t nb0, nb;          // buckets of part 0; of both parts
+    uint32_t *start;           // [nb + 1]: counts, then inclusive ends, then (after
+                               // the scatter) the first entry of each bucket; [nb] = entries
+    unsigned long long *work;  // [nb]: products of each bucket (the classification)
+    uint32_t *ework;           // [entry_cap]: products of each sorted entry
+    uint64_t *entry;           // sorted entries: x << 48 | key << 24 | partner
+    uint64_t entry_cap;
+    uint32_t *heavy;           // items of the buckets whose products reach `threshold`: the
+                               // first entry of a run of at most kHeavyRun entries
+    uint64_t heavy_cap;
+    uint64_t threshold;
+    uint32_t big_entry;        // products that make an entry a heavy item of its own
+    uint32_t *bsum;            // scan scratch
 };
 
 // New pairs of a round: (matrix, i, j); kHoleKey marks an unused entry.
@@ -127,7 +151,11 @@ constexpr int kCtlPoolTop = 0,   // pool entries handed out
     kCtlNew = 10,                // new pairs appended (seeding, or a round's product)
     kCtlTouchedOver = 11,        // more touched lists than the array holds
     kCtlProducts = 12,           // boolean products (list entries read) of the products
-    kCtlWords = 13;
+    kCtlHeavy = 13,              // heavy buckets of the grouped product
+    kCtlHeavyTasks = 14,         // heavy buckets taken
+    kCtlHeavyProducts = 15,      // products of the heavy items
+    kCtlHeavyCand = 16,          // candidates the heavy items sent to the hash set
+    kCtlWords = 17;
 
 // ------------------------------------------------------------------ launchers
 
@@ -147,6 +175,20 @@ hipError_t launch_round_start(const State &S, hipStream_t s);
 // set, against the partner list; candidates inserted in the hash set; new
 // ones appended to `out`.
 hipError_t launch_product(const State &S, PairBuf in, PairBuf out, uint32_t grid_waves, hipStream_t s);
+// The grouped product: sort the pending pairs into key order, classify the
+// buckets by their products, then the heavy buckets (one workgroup each, an
+// LDS bit accumulator over the n columns, kHeavyThreads threads) and the
+// light ones (per product, as launch_product).
+constexpr uint32_t kHeavyThreads = 256;
+constexpr uint32_t kHeavyRun = kHeavyThreads;  // entries of a heavy item at most
+
+hipError_t launch_key_sort(const State &S, PairBuf in, const KeySort &K, hipStream_t s);
+hipError_t launch_grouped_product(const State &S, const KeySort &K, PairBuf out, uint32_t grid_waves, hipStream_t s);
+uint64_t key_sort_scan_blocks(uint64_t nb);
+// LDS bytes of a heavy workgroup's accumulator (n bits); the grouped product
+// needs n small enough for it to fit.
+inline uint64_t heavy_lds_bytes(uint32_t n) { return ((uint64_t)n + 31) / 32 * 4; }
+constexpr uint64_t kHeavyMaxLds = 64 * 1024;
 // Re-insert every key of `old_tab` (tombstones dropped) into S.hash (empty).
 hipError_t launch_rehash(const State &S, const unsigned long long *old_tab, uint64_t old_slots, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long v, hipStream_t s);

@@ -245,6 +245,8 @@ __global__ void round_start_kernel(State S) {
     S.ctl[kCtlTasks] = 0;
     S.ctl[kCtlMoves] = 0;
     S.ctl[kCtlNew] = 0;
+    S.ctl[kCtlHeavy] = 0;
+    S.ctl[kCtlHeavyTasks] = 0;
 }
 
 __device__ __forceinline__ void touch(const State &S, uint32_t layout, uint32_t r) {
@@ -401,10 +403,87 @@ __global__ __launch_bounds__(256) void unmark_kernel(State S) {
 
 // ------------------------------------------------------------------ product
 
+// One lane's pair (x, pi, pj) against the partner lists of its uses in
+// parts [p_lo, p_hi): the lane walks the set bits of its use masks (part 0
+// at its column pj, part 1 at its row pi), one use per step; per step the
+// wave expands the 64 lanes' partner lists together, each product a
+// candidate inserted into the hash set.  Every lane calls this together.
+// false: an overflow (the round is re-run).
+__device__ __forceinline__ bool expand_uses(const State &S, const PairBuf &out, Chunk &ch, uint64_t &appended,
+                                            uint64_t &products, bool valid, uint32_t x, uint32_t pi, uint32_t pj,
+                                            uint32_t p_lo, uint32_t p_hi) {
+    const uint32_t lane = lane_id();
+    bool more = valid;
+    MatInfo mi{};
+    if (more) mi = S.mats[x];
+    uint32_t part = p_lo, w = 0;
+    uint64_t bits = 0;
+    while (__any(more)) {
+        // this lane's next use: head c, partner layout, fixed index of the
+        // candidates and the partner vertex k
+        uint32_t c = 0, lay = kNone, fixed = 0, k = 0, col = 0;
+        if (more) {
+            while (!bits) {
+                const uint32_t W = part == 0 ? mi.w0 : mi.w1;
+                if (part < p_hi && w < W) {
+                    bits = part == 0 ? S.mask[mi.mask0 + (uint64_t)pj * mi.w0 + w]
+                                     : S.mask[mi.mask1 + (uint64_t)pi * mi.w1 + w];
+                    w++;
+                } else if (part + 1 < p_hi) {
+                    part++;
+                    w = 0;
+                } else {
+                    more = false;
+                    break;
+                }
+            }
+            if (bits) {
+                const uint32_t q = (w - 1) * 64 + (uint32_t)__builtin_ctzll(bits);
+                bits &= bits - 1;
+                const Use u = S.uses[(part == 0 ? mi.use0 : mi.use1) + q];
+                c = u.c;
+                lay = u.layout;
+                // part 0: pair (i, k) of a meets row k of b -> (c, i, j')
+                // part 1: pair (k, j) of b meets column k of a -> (c, i', j)
+                fixed = part == 0 ? pi : pj;
+                k = part == 0 ? pj : pi;
+                col = part;
+            }
+        }
+        uint64_t off = 0;
+        uint32_t len = 0;
+        if (lay != kNone) {
+            const Dir d = S.dir[(uint64_t)lay * S.n + k];
+            off = d.off;
+            len = d.len;
+        }
+        uint32_t total;
+        const uint32_t pre = wave_excl_scan(len, &total);
+        products += total;
+        for (uint32_t r = 0; r < total; r += 64) {
+            const uint32_t tt = r + lane;
+            uint32_t src = 0;  // last lane whose first product is <= tt
+#pragma unroll
+            for (uint32_t step = 32; step; step >>= 1)
+                if (shfl32(pre, src + step) <= tt) src += step;
+            const uint64_t soff = shfl64(off, src);
+            const uint32_t spre = shfl32(pre, src), sc = shfl32(c, src), sfix = shfl32(fixed, src),
+                           scol = shfl32(col, src);
+            const bool has = tt < total;
+            uint32_t ci = 0, cj = 0;
+            if (has) {
+                const uint32_t v = S.pool[soff + (tt - spre)];
+                ci = scol ? v : sfix;
+                cj = scol ? sfix : v;
+            }
+            if (!insert_append(S, out, ch, appended, has, sc, ci, cj)) return false;
+        }
+    }
+    return true;
+}
+
 // Persistent waves; a task is 64 consecutive entries of the new-pair buffer
-// `in`, one per lane.  Each lane walks the set bits of its pair's use masks
-// (part 0 at its column, part 1 at its row), one use per step; per step the
-// wave expands the 64 lanes' partner lists together.
+// `in`, one per lane, expanded against the uses of both parts.
 __global__ __launch_bounds__(256) void product_kernel(State S, PairBuf in, PairBuf out) {
     const uint32_t lane = lane_id();
     uint64_t nin = *in.count;
@@ -412,8 +491,7 @@ __global__ __launch_bounds__(256) void product_kernel(State S, PairBuf in, PairB
     const uint64_t ntask = (nin + 63) / 64;
     Chunk ch;
     uint64_t appended = 0, products = 0;
-    bool failed = false;
-    while (!failed) {
+    while (true) {
         unsigned long long t = 0;
         if (lane == 0) t = atomicAdd(&S.ctl[kCtlTasks], 1ull);
         t = first_lane64(t);
@@ -426,79 +504,406 @@ __global__ __launch_bounds__(256) void product_kernel(State S, PairBuf in, PairB
             pi = in.i[e];
             pj = in.j[e];
         }
-        bool more = x != kHoleKey;
-        MatInfo mi{};
-        if (more) mi = S.mats[x];
-        uint32_t part = 0, w = 0;
-        uint64_t bits = 0;
-        while (__any(more)) {
-            // this lane's next use: head c, partner layout, fixed index of
-            // the candidates and the partner vertex k
-            uint32_t c = 0, lay = kNone, fixed = 0, k = 0, col = 0;
-            if (more) {
-                while (!bits) {
-                    if (part == 0) {
-                        if (w < mi.w0) {
-                            bits = S.mask[mi.mask0 + (uint64_t)pj * mi.w0 + w];
-                            w++;
-                        } else {
-                            part = 1;
-                            w = 0;
+        if (!expand_uses(S, out, ch, appended, products, x != kHoleKey, x, pi, pj, 0, 2)) break;
+    }
+    chunk_retire(out, ch);
+    add_appended(S, appended);
+    if (lane == 0 && products) atomicAdd(&S.ctl[kCtlProducts], (unsigned long long)products);
+}
+
+// ----------------------------------------------------------- key-order sort
+
+__device__ __forceinline__ uint64_t pack_entry(uint32_t x, uint32_t key, uint32_t partner) {
+    return ((uint64_t)x << 48) | ((uint64_t)key << 24) | (uint64_t)partner;
+}
+
+__global__ __launch_bounds__(256) void key_count_kernel(State S, PairBuf in, KeySort K) {
+    uint64_t nin = *in.count;
+    if (nin > in.cap) nin = in.cap;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < nin;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t key = in.key[x];
+        if (key == kHoleKey) continue;
+        const MatInfo mi = S.mats[key];
+        if (mi.rank0 != kNone) atomicAdd(&K.start[(uint64_t)mi.rank0 * S.n + in.i[x]], 1u);
+        if (mi.rank1 != kNone) atomicAdd(&K.start[K.nb0 + (uint64_t)mi.rank1 * S.n + in.j[x]], 1u);
+    }
+}
+
+// The counts hold inclusive ends: taking one off the end places an entry
+// and leaves the bucket's first position behind.
+__global__ __launch_bounds__(256) void key_scatter_kernel(State S, PairBuf in, KeySort K) {
+    uint64_t nin = *in.count;
+    if (nin > in.cap) nin = in.cap;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < nin;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t key = in.key[x];
+        if (key == kHoleKey) continue;
+        const MatInfo mi = S.mats[key];
+        const uint32_t i = in.i[x], j = in.j[x];
+        if (mi.rank0 != kNone) {
+            const uint32_t p = atomicSub(&K.start[(uint64_t)mi.rank0 * S.n + i], 1u) - 1;
+            if (p < K.entry_cap) K.entry[p] = pack_entry(key, i, j);
+        }
+        if (mi.rank1 != kNone) {
+            const uint32_t p = atomicSub(&K.start[K.nb0 + (uint64_t)mi.rank1 * S.n + j], 1u) - 1;
+            if (p < K.entry_cap) K.entry[p] = pack_entry(key, j, i);
+        }
+    }
+}
+
+// Inclusive scan of one u32 array, three phases (block sums, their scan,
+// apply).
+constexpr uint32_t kScanThreads = 256, kScanItems = 16, kScanTile = kScanThreads * kScanItems;
+
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t *a, uint64_t n, uint32_t *bsum) {
+    __shared__ uint32_t red[kScanThreads];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+    for (uint32_t q = 0; q < kScanItems; q++) {
+        const uint64_t x = base + q * kScanThreads + threadIdx.x;
+        if (x < n) s += a[x];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (uint32_t d = kScanThreads / 2; d; d >>= 1) {
+        if (threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(1024) void scan_blocks_kernel(uint32_t *bsum, uint64_t nblk) {
+    __shared__ uint32_t part[1024];
+    __shared__ uint32_t carry;
+    const uint32_t t = threadIdx.x;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (uint64_t base = 0; base < nblk; base += 1024) {
+        const uint32_t v = base + t < nblk ? bsum[base + t] : 0;
+        part[t] = v;
+        __syncthreads();
+        for (uint32_t d = 1; d < 1024; d <<= 1) {
+            const uint32_t u = t >= d ? part[t - d] : 0;
+            __syncthreads();
+            part[t] += u;
+            __syncthreads();
+        }
+        if (base + t < nblk) bsum[base + t] = carry + part[t] - v;
+        __syncthreads();
+        if (t == 1023) carry += part[1023];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t *a, uint64_t n, const uint32_t *bsum) {
+    __shared__ uint32_t tile[kScanTile];
+    __shared__ uint32_t tsum[kScanThreads];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    for (uint32_t q = 0; q < kScanItems; q++) {
+        const uint64_t x = base + q * kScanThreads + threadIdx.x;
+        tile[q * kScanThreads + threadIdx.x] = x < n ? a[x] : 0;
+    }
+    __syncthreads();
+    uint32_t *mine = tile + threadIdx.x * kScanItems;
+    uint32_t s = 0;
+    for (uint32_t q = 0; q < kScanItems; q++) {
+        s += mine[q];
+        mine[q] = s;
+    }
+    tsum[threadIdx.x] = s;
+    __syncthreads();
+    for (uint32_t d = 1; d < kScanThreads; d <<= 1) {
+        const uint32_t u = threadIdx.x >= d ? tsum[threadIdx.x - d] : 0;
+        __syncthreads();
+        tsum[threadIdx.x] += u;
+        __syncthreads();
+    }
+    const uint32_t off = bsum[blockIdx.x] + tsum[threadIdx.x] - s;
+    for (uint32_t q = 0; q < kScanItems; q++) mine[q] += off;
+    __syncthreads();
+    for (uint32_t q = 0; q < kScanItems; q++) {
+        const uint64_t x = base + q * kScanThreads + threadIdx.x;
+        if (x < n) a[x] = tile[q * kScanThreads + threadIdx.x];
+    }
+}
+
+// Products of every sorted entry (the lengths of the partner lists its use
+// masks select), summed per bucket.
+__global__ __launch_bounds__(256) void classify_kernel(State S, KeySort K) {
+    uint64_t total = K.start[K.nb];
+    if (total > K.entry_cap) total = K.entry_cap;
+    const uint64_t total0 = K.start[K.nb0];
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t v = K.entry[e];
+        const uint32_t x = (uint32_t)(v >> 48), key = (uint32_t)(v >> 24) & 0xFFFFFFu, k = (uint32_t)v & 0xFFFFFFu;
+        const uint32_t order = e >= total0 ? 1u : 0u;
+        const MatInfo mi = S.mats[x];
+        const uint32_t W = order ? mi.w1 : mi.w0, first = order ? mi.use1 : mi.use0;
+        const uint64_t mbase = order ? mi.mask1 : mi.mask0;
+        uint64_t work = 0;
+        for (uint32_t w = 0; w < W; w++) {
+            uint64_t bits = S.mask[mbase + (uint64_t)k * W + w];
+            while (bits) {
+                const uint32_t q = w * 64 + (uint32_t)__builtin_ctzll(bits);
+                bits &= bits - 1;
+                work += S.dir[(uint64_t)S.uses[first + q].layout * S.n + k].len;
+            }
+        }
+        K.ework[e] = work < 0x7FFFFFFFull ? (uint32_t)work : 0x7FFFFFFFu;
+        if (!work) continue;
+        const uint64_t b = order ? K.nb0 + (uint64_t)mi.rank1 * S.n + key : (uint64_t)mi.rank0 * S.n + key;
+        atomicAdd(&K.work[b], (unsigned long long)work);
+    }
+}
+
+// Is entry e of a heavy bucket starting at bstart the first of an item?  Items
+// are runs of at most kHeavyRun entries (restarting every kHeavyRun entries of
+// the bucket), and an entry with kBigEntry products or more is an item of
+// its own (K.big_entry), so that no item holds a workgroup much longer than
+// the others.
+__device__ __forceinline__ bool item_start(const KeySort &K, uint64_t e, uint64_t bstart) {
+    if (e == bstart || (e - bstart) % kHeavyRun == 0) return true;
+    return K.ework[e] >= K.big_entry || K.ework[e - 1] >= K.big_entry;
+}
+
+// The items of the heavy buckets, listed by their first entry.
+__global__ __launch_bounds__(256) void heavy_items_kernel(State S, KeySort K) {
+    uint64_t total = K.start[K.nb];
+    if (total > K.entry_cap) total = K.entry_cap;
+    const uint64_t total0 = K.start[K.nb0];
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t v = K.entry[e];
+        const uint32_t x = (uint32_t)(v >> 48), key = (uint32_t)(v >> 24) & 0xFFFFFFu;
+        const uint32_t order = e >= total0 ? 1u : 0u;
+        const MatInfo mi = S.mats[x];
+        const uint64_t b = order ? K.nb0 + (uint64_t)mi.rank1 * S.n + key : (uint64_t)mi.rank0 * S.n + key;
+        if (K.work[b] < K.threshold || !item_start(K, e, K.start[b])) continue;
+        const unsigned long long h = atomicAdd(&S.ctl[kCtlHeavy], 1ull);
+        if (h < K.heavy_cap) K.heavy[h] = (uint32_t)e;
+    }
+}
+
+// ---------------------------------------------------------- grouped product
+
+// Heavy items, one workgroup each (taken from a counter): a run of at most
+// kHeavyRun entries of one bucket, thread t holding entry t.  For every use
+// q selected by some entry of the item, the partner lists of the entries
+// selecting it are ORed into an LDS bit set over the n columns (the lists'
+// lengths prefix-summed over the workgroup, 256 consecutive products per
+// pass); the pairs the head c already holds at this key are cleared from it
+// (c's list in the same orientation, when c has one); the remaining bits
+// are the item's candidates for c, each inserted into the hash set once.
+// The bit set is left zero for the next use.
+constexpr uint32_t kMaxUseWords = 8;  // uses selected through an LDS OR of the masks (512)
+constexpr uint32_t kUnroll = 4;       // passes of products whose loads are issued together
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total, uint32_t *wsum) {
+    constexpr uint32_t kWaves = kHeavyThreads / 64;
+    const uint32_t wave = threadIdx.x / 64;
+    uint32_t wt;
+    const uint32_t pre = wave_excl_scan(v, &wt);
+    if (lane_id() == 0) wsum[wave] = wt;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kWaves; w++) {
+        if (w < wave) off += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + off;
+}
+
+__global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K, PairBuf out) {
+    extern __shared__ uint32_t acc[];
+    __shared__ uint64_t um[kMaxUseWords];
+    __shared__ uint64_t s_off[kHeavyThreads];
+    __shared__ uint32_t s_pre[kHeavyThreads];
+    __shared__ uint32_t wsum[kHeavyThreads / 64];
+    __shared__ unsigned long long sh_item;
+    __shared__ uint32_t sh_e1, sh_fail;
+    constexpr uint32_t kWaves = kHeavyThreads / 64;
+    const uint32_t t = threadIdx.x, lane = lane_id(), wave = t / 64;
+    const uint32_t nw = (S.n + 31) / 32;
+    uint64_t nheavy = S.ctl[kCtlHeavy];
+    if (nheavy > K.heavy_cap) nheavy = K.heavy_cap;
+    Chunk ch;
+    uint64_t appended = 0, products = 0, cands = 0;
+    for (uint32_t w = t; w < nw; w += kHeavyThreads) acc[w] = 0;
+    if (t == 0) sh_fail = 0;
+    // each wave emits the candidates of words [wave * per, (wave + 1) * per)
+    const uint32_t per = ((nw + kWaves - 1) / kWaves + 63) / 64 * 64;
+    bool stop = false;
+    while (!stop) {
+        __syncthreads();
+        if (t == 0) {
+            unsigned long long it = atomicAdd(&S.ctl[kCtlHeavyTasks], 1ull);
+            if (load_relaxed(&S.ctl[kCtlHalt])) it = nheavy;
+            sh_item = it;
+        }
+        __syncthreads();
+        const uint64_t h = sh_item;
+        if (h >= nheavy || sh_fail) break;
+        // the item: entries [e0, e1) of one bucket
+        const uint32_t e0 = K.heavy[h];
+        const uint64_t head = K.entry[e0];
+        const uint32_t x = (uint32_t)(head >> 48), key = (uint32_t)(head >> 24) & 0xFFFFFFu;
+        const uint32_t order = e0 >= K.start[K.nb0] ? 1u : 0u;
+        const MatInfo mi = S.mats[x];
+        const uint64_t b = order ? K.nb0 + (uint64_t)mi.rank1 * S.n + key : (uint64_t)mi.rank0 * S.n + key;
+        const uint32_t bstart = K.start[b], bend = K.start[b + 1];
+        if (t == 0) sh_e1 = bend - e0 > kHeavyRun ? e0 + kHeavyRun : bend;
+        if (t < kMaxUseWords) um[t] = 0;
+        __syncthreads();
+        if (t > 0 && e0 + t < sh_e1 && item_start(K, e0 + t, bstart)) atomicMin(&sh_e1, e0 + t);
+        __syncthreads();
+        const uint32_t cnt = sh_e1 - e0;
+        const uint32_t W = order ? mi.w1 : mi.w0, first = order ? mi.use1 : mi.use0,
+                       nuse = order ? mi.nuse1 : mi.nuse0;
+        const uint64_t mbase = order ? mi.mask1 : mi.mask0;
+        const bool gathered = W <= kMaxUseWords;
+        const uint32_t k = t < cnt ? (uint32_t)K.entry[e0 + t] & 0xFFFFFFu : 0u;
+        if (gathered && t < cnt)
+            for (uint32_t w = 0; w < W; w++) {
+                const uint64_t m = S.mask[mbase + (uint64_t)k * W + w];
+                if (m) atomicOr((unsigned long long *)&um[w], (unsigned long long)m);
+            }
+        __syncthreads();
+        for (uint32_t w = 0; w < W && !stop; w++) {
+            uint64_t bits = gathered ? um[w] : ~0ull;
+            if (w * 64 + 64 > nuse) bits &= (1ull << (nuse - w * 64)) - 1;  // nuse - 64w < 64 here
+            while (bits && !stop) {
+                const uint32_t q = w * 64 + (uint32_t)__builtin_ctzll(bits);
+                bits &= bits - 1;
+                const Use u = S.uses[first + q];
+                uint64_t off = 0;
+                uint32_t len = 0;
+                if (t < cnt && ((S.mask[mbase + (uint64_t)k * W + q / 64] >> (q % 64)) & 1)) {
+                    const Dir d = S.dir[(uint64_t)u.layout * S.n + k];
+                    off = d.off;
+                    len = d.len;
+                }
+                uint32_t total;
+                const uint32_t pre = block_excl_scan(len, &total, wsum);
+                s_pre[t] = pre;
+                s_off[t] = off;
+                __syncthreads();
+                products += total;
+                for (uint32_t r = 0; r < total; r += kHeavyThreads * kUnroll) {
+                    uint32_t v[kUnroll];
+#pragma unroll
+                    for (uint32_t uu = 0; uu < kUnroll; uu++) {
+                        const uint32_t tt = r + uu * kHeavyThreads + t;
+                        v[uu] = 0xFFFFFFFFu;
+                        if (tt < total) {
+                            uint32_t src = 0;  // last entry whose first product is <= tt
+#pragma unroll
+                            for (uint32_t step = kHeavyThreads / 2; step; step >>= 1)
+                                if (src + step < cnt && s_pre[src + step] <= tt) src += step;
+                            v[uu] = S.pool[s_off[src] + (tt - s_pre[src])];
                         }
-                    } else if (w < mi.w1) {
-                        bits = S.mask[mi.mask1 + (uint64_t)pi * mi.w1 + w];
-                        w++;
-                    } else {
-                        more = false;
-                        break;
+                    }
+#pragma unroll
+                    for (uint32_t uu = 0; uu < kUnroll; uu++)
+                        if (v[uu] != 0xFFFFFFFFu) atomicOr(&acc[v[uu] >> 5], 1u << (v[uu] & 31));
+                }
+                const uint32_t own = order ? S.mats[u.c].col_layout : S.mats[u.c].row_layout;
+                if (own != kNone) {
+                    const Dir d = S.dir[(uint64_t)own * S.n + key];
+                    __syncthreads();  // every product is in the bit set
+                    for (uint32_t p = t; p < d.len; p += kHeavyThreads) {
+                        const uint32_t v = S.pool[d.off + p];
+                        atomicAnd(&acc[v >> 5], ~(1u << (v & 31)));
                     }
                 }
-                if (bits) {
-                    const uint32_t q = (w - 1) * 64 + (uint32_t)__builtin_ctzll(bits);
-                    bits &= bits - 1;
-                    const Use u = S.uses[(part == 0 ? mi.use0 : mi.use1) + q];
-                    c = u.c;
-                    lay = u.layout;
-                    // part 0: pair (i, k) of a meets row k of b -> (c, i, j')
-                    // part 1: pair (k, j) of b meets column k of a -> (c, i', j)
-                    fixed = part == 0 ? pi : pj;
-                    k = part == 0 ? pj : pi;
-                    col = part;
-                }
-            }
-            uint64_t off = 0;
-            uint32_t len = 0;
-            if (lay != kNone) {
-                const Dir d = S.dir[(uint64_t)lay * S.n + k];
-                off = d.off;
-                len = d.len;
-            }
-            uint32_t total;
-            const uint32_t pre = wave_excl_scan(len, &total);
-            products += total;
-            for (uint32_t r = 0; r < total; r += 64) {
-                const uint32_t tt = r + lane;
-                uint32_t src = 0;  // last lane whose first product is <= tt
+                __syncthreads();
+                bool ok = true;
+                const uint32_t w_end = (wave + 1) * per < nw ? (wave + 1) * per : nw;
+                for (uint32_t base = wave * per; base < w_end; base += 64) {
+                    const uint32_t wi = base + lane;
+                    uint32_t word = 0;
+                    if (wi < w_end) {
+                        word = acc[wi];
+                        acc[wi] = 0;
+                    }
+                    if (!ok) continue;
+                    uint32_t ctot;
+                    const uint32_t cpre = wave_excl_scan((uint32_t)__popc(word), &ctot);
+                    cands += ctot;
+                    for (uint32_t r = 0; r < ctot; r += 64) {
+                        const uint32_t tt = r + lane;
+                        uint32_t src = 0;
 #pragma unroll
-                for (uint32_t step = 32; step; step >>= 1)
-                    if (shfl32(pre, src + step) <= tt) src += step;
-                const uint64_t soff = shfl64(off, src);
-                const uint32_t spre = shfl32(pre, src), sc = shfl32(c, src), sfix = shfl32(fixed, src),
-                               scol = shfl32(col, src);
-                const bool has = tt < total;
-                uint32_t ci = 0, cj = 0;
-                if (has) {
-                    const uint32_t v = S.pool[soff + (tt - spre)];
-                    ci = scol ? v : sfix;
-                    cj = scol ? sfix : v;
+                        for (uint32_t step = 32; step; step >>= 1)
+                            if (shfl32(cpre, src + step) <= tt) src += step;
+                        const uint32_t sword = shfl32(word, src);
+                        uint32_t rank = tt - shfl32(cpre, src), bit = 0;
+#pragma unroll
+                        for (uint32_t width = 16; width; width >>= 1) {
+                            const uint32_t c2 = (uint32_t)__popc((sword >> bit) & ((1u << width) - 1));
+                            if (rank >= c2) {
+                                rank -= c2;
+                                bit += width;
+                            }
+                        }
+                        const bool has = tt < ctot;
+                        const uint32_t v = (base + src) * 32 + bit;
+                        if (!insert_append(S, out, ch, appended, has, u.c, order ? v : key, order ? key : v)) {
+                            ok = false;
+                            break;
+                        }
+                    }
                 }
-                if (!insert_append(S, out, ch, appended, has, sc, ci, cj)) {
-                    failed = true;
-                    break;
-                }
+                if (!ok && lane == 0) atomicOr(&sh_fail, 1u);
+                __syncthreads();
+                stop = sh_fail != 0;
             }
-            if (failed) break;
         }
+    }
+    chunk_retire(out, ch);
+    add_appended(S, appended);
+    if (t == 0 && products) {
+        atomicAdd(&S.ctl[kCtlProducts], (unsigned long long)products);
+        atomicAdd(&S.ctl[kCtlHeavyProducts], (unsigned long long)products);
+    }
+    if (lane == 0 && cands) atomicAdd(&S.ctl[kCtlHeavyCand], (unsigned long long)cands);
+}
+
+// Light buckets: 64 sorted entries per task, a lane per entry, expanded
+// against the uses of its own part; entries of heavy buckets are skipped.
+__global__ __launch_bounds__(256) void light_kernel(State S, KeySort K, PairBuf out) {
+    const uint32_t lane = lane_id();
+    uint64_t total = K.start[K.nb];
+    if (total > K.entry_cap) total = K.entry_cap;
+    const uint64_t total0 = K.start[K.nb0];
+    const uint64_t ntask = (total + 63) / 64;
+    Chunk ch;
+    uint64_t appended = 0, products = 0;
+    while (true) {
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(&S.ctl[kCtlTasks], 1ull);
+        t = first_lane64(t);
+        if (t >= ntask) break;
+        if (first_lane64(load_relaxed(&S.ctl[kCtlHalt]))) break;
+        const uint64_t e = t * 64 + lane;
+        bool valid = e < total;
+        uint32_t x = 0, pi = 0, pj = 0, order = 0;
+        if (valid) {
+            const uint64_t v = K.entry[e];
+            x = (uint32_t)(v >> 48);
+            const uint32_t key = (uint32_t)(v >> 24) & 0xFFFFFFu, k = (uint32_t)v & 0xFFFFFFu;
+            order = e >= total0 ? 1u : 0u;
+            pi = order ? k : key;
+            pj = order ? key : k;
+            const MatInfo mi = S.mats[x];
+            const uint64_t b = order ? K.nb0 + (uint64_t)mi.rank1 * S.n + key : (uint64_t)mi.rank0 * S.n + key;
+            if (K.work[b] >= K.threshold) valid = false;
+        }
+        if (!expand_uses(S, out, ch, appended, products, valid, x, pi, pj, order, order + 1)) break;
     }
     chunk_retire(out, ch);
     add_appended(S, appended);
@@ -703,6 +1108,42 @@ hipError_t launch_integrate(const State &S, PairBuf in, bool resume, uint32_t gr
 hipError_t launch_product(const State &S, PairBuf in, PairBuf out, uint32_t grid_waves, hipStream_t s) {
     const uint32_t blocks = grid_waves / 4 ? grid_waves / 4 : 1;
     product_kernel<<<blocks, 256, 0, s>>>(S, in, out);
+    SP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+uint64_t key_sort_scan_blocks(uint64_t nb) { return (nb + 1 + kScanTile - 1) / kScanTile; }
+
+hipError_t launch_key_sort(const State &S, PairBuf in, const KeySort &K, hipStream_t s) {
+    const uint64_t len = K.nb + 1;
+    fill_u32_kernel<<<grid_for(len, 256, 65536), 256, 0, s>>>(K.start, len, 0);
+    SP_LAUNCH_CHECK();
+    fill_u64_kernel<<<grid_for(K.nb, 256, 65536), 256, 0, s>>>(K.work, K.nb, 0);
+    SP_LAUNCH_CHECK();
+    const uint32_t grid = grid_for(in.cap, 256, 8192);
+    key_count_kernel<<<grid, 256, 0, s>>>(S, in, K);
+    SP_LAUNCH_CHECK();
+    const uint64_t nblk = key_sort_scan_blocks(K.nb);
+    scan_reduce_kernel<<<(uint32_t)nblk, kScanThreads, 0, s>>>(K.start, len, K.bsum);
+    SP_LAUNCH_CHECK();
+    scan_blocks_kernel<<<1, 1024, 0, s>>>(K.bsum, nblk);
+    SP_LAUNCH_CHECK();
+    scan_apply_kernel<<<(uint32_t)nblk, kScanThreads, 0, s>>>(K.start, len, K.bsum);
+    SP_LAUNCH_CHECK();
+    key_scatter_kernel<<<grid, 256, 0, s>>>(S, in, K);
+    SP_LAUNCH_CHECK();
+    classify_kernel<<<grid_for(2 * in.cap, 256, 8192), 256, 0, s>>>(S, K);
+    SP_LAUNCH_CHECK();
+    heavy_items_kernel<<<grid_for(2 * in.cap, 256, 8192), 256, 0, s>>>(S, K);
+    SP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_grouped_product(const State &S, const KeySort &K, PairBuf out, uint32_t grid_waves, hipStream_t s) {
+    const uint32_t blocks = grid_waves / 4 ? grid_waves / 4 : 1;
+    heavy_kernel<<<blocks, kHeavyThreads, (uint32_t)heavy_lds_bytes(S.n), s>>>(S, K, out);
+    SP_LAUNCH_CHECK();
+    light_kernel<<<blocks, 256, 0, s>>>(S, K, out);
     SP_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -19,6 +19,25 @@ pytestmark = pytest.mark.gpu
 
 SPARSE = 2
 
+# The product's paths: buckets of new pairs sorted by key, heavy ones through
+# an LDS bit set (default threshold n / 64), every bucket heavy, every
+# bucket light, and the unsorted product.
+MODES = {
+    "grouped": {},
+    "all_heavy": {"CFLR_SPARSE_HEAVY": "1"},
+    "all_light": {"CFLR_SPARSE_HEAVY": str(1 << 62)},
+    "ungrouped": {"CFLR_SPARSE_UNGROUPED": "1"},
+}
+
+
+@pytest.fixture(params=list(MODES))
+def mode(request, monkeypatch):
+    for k in ("CFLR_SPARSE_HEAVY", "CFLR_SPARSE_UNGROUPED"):
+        monkeypatch.delenv(k, raising=False)
+    for k, v in MODES[request.param].items():
+        monkeypatch.setenv(k, v)
+    return request.param
+
 
 def cflr():
     import paper_2401_11029_amd as m
@@ -33,21 +52,21 @@ def sparse_solve(ctx, text, g, **kw):
 
 
 @pytest.mark.parametrize("case", SWEEP, ids=[c[0] for c in SWEEP])
-def test_sparse_random_sweep(ctx, case):
+def test_sparse_random_sweep(ctx, case, mode):
     name, text, labels = case
     for k, (n, m) in enumerate([(1, 3), (5, 12), (33, 90), (64, 200), (65, 260), (200, 600)]):
         g = graphs.random_graph(n, m, labels, seed=1000 + 17 * k, self_loops=True)
-        print(f"sparse sweep {name} n={n} m={m}", flush=True)
+        print(f"sparse sweep {name} n={n} m={m} mode={mode}", flush=True)
         assert_matches_oracle(sparse_solve(ctx, text, g), text, g, f"{name} n={n}")
 
 
 @pytest.mark.parametrize("name", ["pointsto_4k", "pointsto_12k", "alias_8k"])
-def test_sparse_golden_digests(ctx, name):
+def test_sparse_golden_digests(ctx, name, mode):
     from tests.golden.make_goldens import GOLDENS
     with open(os.path.join(GOLDEN, f"{name}.json")) as f:
         gold = json.load(f)
     text, g = GOLDENS[name]()
-    print(f"sparse golden {name}", flush=True)
+    print(f"sparse golden {name} mode={mode}", flush=True)
     r = sparse_solve(ctx, text, g)
     assert r.grammar.nonterminals == gold["order"]
     for x in gold["order"]:
@@ -56,7 +75,7 @@ def test_sparse_golden_digests(ctx, name):
         assert digest(s, d) == gold["sha256"][x], x
 
 
-def test_sparse_long_lists_read_out_in_order(ctx):
+def test_sparse_long_lists_read_out_in_order(ctx, mode):
     # rows of far more than 2,048 pairs take the bit-set readout path: the
     # transitive closure of a dense random relation
     g = graphs.random_graph(3000, 30000, ["a"], seed=5150, self_loops=True)
@@ -83,7 +102,7 @@ def test_sparse_edge_cases(ctx):
     assert r.pair_set("E") == {(i, i) for i in range(9)}
 
 
-def test_sparse_overflows_rerun_exactly(ctx):
+def test_sparse_overflows_rerun_exactly(ctx, mode):
     # a 64-pair new-pair buffer and the smallest pool and hash table: every
     # round overflows at least once and is re-run; the result is unchanged
     g = graphs.alias_graph(2500, seed=77)
