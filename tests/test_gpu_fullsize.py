@@ -1,7 +1,9 @@
-"""Full-size parity: the 50,000-vertex memory-alias configuration, solved with
-the launch configuration bench.py times (default options), against the
-oracle's stored per-non-terminal counts and SHA-256 digests
-(tests/golden/alias_50k.json, written by tests/golden/make_goldens.py)."""
+"""Full-size parity: the 50,000-vertex memory-alias configuration and the
+200,000-vertex field-sensitive points-to configuration (Fig. 4b, 64 fields,
+386 non-terminals), each solved with the launch configuration bench.py times
+(default options), against the oracle's stored per-non-terminal counts and
+SHA-256 digests (tests/golden/alias_50k.json, pointsto_200k.json, written by
+tests/golden/make_goldens.py)."""
 
 import hashlib
 import json
@@ -15,6 +17,7 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "alias_50k.json")
+GOLDEN_PT = os.path.join(os.path.dirname(__file__), "golden", "pointsto_200k.json")
 
 
 def sha_of_pairs(s, d, chunk=1 << 26):
@@ -40,6 +43,25 @@ def test_alias_50k_matches_oracle_digests(ctx):
     assert st["total_pairs"] == gold["total"]
     print(f"alias_50k: {st['total_pairs']} pairs, {st['rounds']} rounds, "
           f"{st['fixpoint_ms']:.0f} ms", flush=True)
+    for x in gold["order"]:
+        assert r.count(x) == gold["count"][x], x
+        s, d = r.pairs(x)
+        assert sha_of_pairs(s, d) == gold["sha256"][x], x
+        del s, d
+
+
+def test_pointsto_200k_matches_oracle_digests(ctx):
+    import paper_2401_11029_amd as cflr
+    with open(GOLDEN_PT) as f:
+        gold = json.load(f)
+    text, g = workloads.config("pointsto_200k")
+    r = cflr.solve(ctx, cflr.Grammar(text), cflr.Graph.from_workload(ctx, g))
+    st = r.stats()
+    print(f"pointsto_200k: {st['total_pairs']} pairs, {st['rounds']} rounds, "
+          f"{st['fixpoint_ms']:.0f} ms, storage {st['storage']}", flush=True)
+    assert st["storage"] == 2  # the dense matrices would not fit: sparse storage
+    assert r.grammar.nonterminals == gold["order"]
+    assert st["total_pairs"] == gold["total"]
     for x in gold["order"]:
         assert r.count(x) == gold["count"][x], x
         s, d = r.pairs(x)
