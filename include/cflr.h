@@ -185,10 +185,21 @@ cflr_status cflr_graph_create(cflr_ctx *ctx, uint32_t n_vertices, uint64_t n_edg
 void cflr_graph_free(cflr_graph *g);
 
 /* ---- solve ----------------------------------------------------------------
- * Runs the fixpoint for one graph.  opts may be NULL (defaults).  The
- * result holds the device matrices until cflr_result_free.
- * Errors: EINVAL, ENOMEM (matrices do not fit), EDEVICE, ETIMEOUT
- * (max_rounds reached; *out is still set and holds the partial state). */
+ * Runs the fixpoint of Algorithm 1 for one graph (its Data: the grammar and
+ * the edge-labelled graph; its Result: every non-terminal's pairs), in the
+ * semi-naive form of Section 3, optimisation 1 (each round multiplies only
+ * the pairs new since the previous one), with row-major copies for the
+ * matrices in b slots and column-major copies for those in a slots
+ * (optimisation 2).  Storage (cflr_opts.storage): dense bit matrices, or
+ * adjacency lists plus a hash set for membership, where adding a round's
+ * new pairs never rebuilds a matrix (the aim of optimisation 3) and per
+ * vertex use masks select the productions a new pair meets (the block
+ * directory of optimisation 4).  opts may be NULL (defaults).  The result
+ * holds the device storage until cflr_result_free.
+ * Errors: EINVAL, ENOMEM (storage does not fit), EDEVICE, EUNSUPPORTED
+ * (sparse storage with semi_naive = 0, more than 2^24 - 1 vertices or 65535
+ * matrices), ETIMEOUT (max_rounds reached; *out is still set and holds the
+ * partial state, a subset of the fixpoint). */
 cflr_status cflr_solve(cflr_ctx *ctx, const cflr_grammar *g, const cflr_graph *graph,
                        const cflr_opts *opts, cflr_result **out);
 
@@ -220,13 +231,21 @@ cflr_status cflr_autotune(cflr_ctx *ctx, const cflr_grammar *const *grammars,
                           double *out_best_ms);
 
 /* ---- results --------------------------------------------------------------
- * nt indexes the user non-terminals of the result's grammar. */
+ * Algorithm 1's Result, read per non-terminal: the set of pairs (i, j)
+ * joined by a path whose word the non-terminal derives (Section 1).  nt
+ * indexes the user non-terminals of the result's grammar (first-appearance
+ * order).  A result stays valid after its context, grammar and graph are
+ * freed.  Errors: EINVAL (null, nt out of range), EDEVICE.
+ * cflr_result_count: *n_pairs = |pairs of nt|. */
 cflr_status cflr_result_count(const cflr_result *r, uint32_t nt, uint64_t *n_pairs);
 /* Copy the pairs of nt, sorted by (src, dst), into src/dst (capacity
- * entries each; host pointers when on_device == 0, device pointers when 1).
- * *written = pairs copied.  EINVAL if capacity is smaller than the count. */
+ * entries each; host pointers when on_device == 0, device pointers of the
+ * result's device when 1; owned by the caller).  *written = pairs copied.
+ * EINVAL if capacity is smaller than the count (nothing is written). */
 cflr_status cflr_result_copy(const cflr_result *r, uint32_t nt, uint32_t *src, uint32_t *dst,
                              uint64_t capacity, int on_device, uint64_t *written);
+/* Statistics of the solve (rounds, pairs seeded and derived, times; see
+ * cflr_stats).  Errors: EINVAL. */
 cflr_status cflr_result_stats(const cflr_result *r, cflr_stats *out);
 void cflr_result_free(cflr_result *r);
 
@@ -248,8 +267,10 @@ void cflr_result_free(cflr_result *r);
  * It also admits a request only while the running requests' (key tile,
  * partner) slots -- key tiles of 256 vertices x n partners per matrix --
  * stay within hbm_budget_bytes / 16 (between 2^20 and 2^29).
- * The server uses ctx's device and stream; do not use ctx from another
- * thread while the server lives. */
+ * The server runs its rounds on a stream of its own on ctx's device, so the
+ * caller's thread may read results and free handles (on ctx's stream) while
+ * it runs; do not start other solves on ctx while the server lives.
+ * Errors (every server call sets cflr_last_error): EINVAL, ENOMEM, EDEVICE. */
 cflr_status cflr_server_create(cflr_ctx *ctx, uint64_t hbm_budget_bytes, uint32_t max_slots,
                                const cflr_opts *opts, cflr_server **out);
 /* Queue a request; the grammar and graph must stay alive until its result is

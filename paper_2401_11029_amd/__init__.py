@@ -64,6 +64,11 @@ class Context:
         _check(lib().cflr_ctx_create(int(device), C.c_void_p(ptr), C.byref(h)))
         self._h = h
         self.device = device
+        self._servers = 0  # servers alive on this context (no other solves meanwhile)
+
+    def _no_server(self):
+        if self._servers:
+            raise RuntimeError("a Server is running on this Context: close it before other solves")
 
     def mem_info(self):
         f, t = C.c_uint64(), C.c_uint64()
@@ -222,6 +227,7 @@ class Result:
 
 def solve(ctx: Context, grammar: Grammar, graph: Graph, options: Opts | None = None,
           **kw) -> Result:
+    ctx._no_server()
     o = options if options is not None else opts(**kw)
     h = C.c_void_p()
     st = lib().cflr_solve(ctx._h, grammar._h, graph._h, C.byref(o), C.byref(h))
@@ -234,6 +240,7 @@ def solve(ctx: Context, grammar: Grammar, graph: Graph, options: Opts | None = N
 
 def solve_batch(ctx: Context, grammars, graphs, options: Opts | None = None, **kw):
     """Solve many graphs together; grammars is one Grammar or one per graph."""
+    ctx._no_server()
     graphs = list(graphs)
     if isinstance(grammars, Grammar):
         grammars = [grammars] * len(graphs)
@@ -253,6 +260,7 @@ def solve_batch(ctx: Context, grammars, graphs, options: Opts | None = None, **k
 def autotune(ctx: Context, grammars, graphs):
     """Pick the product grid (and, for several graphs, rounds per graph
     replay) by timing each candidate; later solves on ctx use the choice."""
+    ctx._no_server()
     graphs = list(graphs)
     if isinstance(grammars, Grammar):
         grammars = [grammars] * len(graphs)
@@ -274,12 +282,16 @@ class Server:
         _check(lib().cflr_server_create(ctx._h, int(hbm_budget_bytes), int(max_slots),
                                         C.byref(o), C.byref(h)))
         self._h = h
-        self._keep = {}
+        self._ctx = ctx
+        ctx._servers += 1
+        self._keep = {}      # ticket -> grammar, until its result is taken
+        self._inputs = []    # every grammar and graph submitted, alive until close()
 
     def submit(self, grammar: Grammar, graph: Graph) -> int:
         t = C.c_uint64()
         _check(lib().cflr_server_submit(self._h, grammar._h, graph._h, C.byref(t)))
         self._keep[t.value] = (grammar, graph)
+        self._inputs.append((grammar, graph))
         return t.value
 
     def poll(self, ticket):
@@ -309,6 +321,8 @@ class Server:
         if getattr(self, "_h", None):
             lib().cflr_server_free(self._h)
             self._h = None
+            self._ctx._servers -= 1
+            self._inputs = []
 
     def __del__(self):
         try:

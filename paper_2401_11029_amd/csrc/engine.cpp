@@ -229,8 +229,9 @@ std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const
 
 // ---------------------------------------------------------------------- Run
 
-Run::Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t bucket_capacity, uint32_t max_instances)
-    : hold_(ctx), ctx_(ctx), opts_(opts), s_(ctx->stream), bucket_cap_(bucket_capacity), max_inst_(max_instances) {
+Run::Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t bucket_capacity, uint32_t max_instances, hipStream_t stream)
+    : hold_(ctx), ctx_(ctx), opts_(opts), s_(stream ? stream : ctx->stream), bucket_cap_(bucket_capacity),
+      max_inst_(max_instances) {
     if (bucket_cap_ >= 0xFFFFFFF0ull)
         throw Error(CFLR_EUNSUPPORTED, "too many sort buckets for one run (matrices x key tiles x segments >= 2^32)");
     if (max_inst_ == 0 || max_inst_ > kMaxSlots)
@@ -330,61 +331,81 @@ void Run::free_buckets(uint64_t base, uint64_t count) {
 
 void Run::add(const std::shared_ptr<Instance> &inst) {
     if (insts_.size() >= max_inst_) throw Error(CFLR_EINVAL, "run is full");
-    inst->bbase = (uint32_t)alloc_buckets(instance_buckets(inst->low, inst->n));
+    const uint64_t nb = instance_buckets(inst->low, inst->n);
+    const uint64_t base = alloc_buckets(nb);
     // slot: lowest index not used by a running instance
     std::vector<uint8_t> used(max_inst_, 0);
     for (auto &o : insts_) used[o->slot] = 1;
     uint32_t slot = 0;
     while (used[slot]) slot++;
-    inst->slot = slot;
-    insts_.push_back(inst);
-    dirty_ = true;
-    // seeds: appended after whatever is already waiting in the buffer
-    hip_check(hipStreamSynchronize(s_), "sync");
-    unsigned long long cur = 0;
-    copy_sync(&cur, d_counters_.ptr, 8, hipMemcpyDeviceToHost, s_);
-    ensure_capacity(cur + inst->max_seeds, true);
-    hip_check(launch_fill_u64(d_inst_new_.as<unsigned long long>() + (uint64_t)slot * kCountShards, kCountShards, 0,
-                              s_),
-              "fill");
-    DevBuf dmats(ctx_->pool.get(), inst->mats.size() * sizeof(MatDev));
-    hip_check(hipMemcpyAsync(dmats.ptr, inst->mats.data(), inst->mats.size() * sizeof(MatDev),
-                             hipMemcpyHostToDevice, s_),
-              "H2D");
-    SeedArgs A{};
-    A.mats = dmats.as<MatDev>();
-    A.I = InstDev{inst->n, inst->S, inst->bbase, 0};
-    A.inst = slot;
-    A.src = inst->graph->src.as<uint32_t>();
-    A.dst = inst->graph->dst.as<uint32_t>();
-    A.lab = inst->graph->lab.as<uint32_t>();
-    A.m = inst->graph->m;
-    A.lm_ptr = inst->lm_ptr.as<uint32_t>();
-    A.lm_mat = inst->lm_mat.as<uint32_t>();
-    A.eps_mat = inst->eps_mat.as<uint32_t>();
-    A.n_eps = inst->n_eps;
-    A.ap_key = d_ap_key_.as<uint32_t>();
-    A.ap_i = d_ap_i_.as<uint32_t>();
-    A.ap_j = d_ap_j_.as<uint32_t>();
-    A.ap_count = d_counters_.as<unsigned long long>();
-    A.ap_cap = ap_cap_;
-    A.inst_new = d_inst_new_.as<unsigned long long>();
-    A.rcnt = d_rcnt_.as<uint32_t>();
-    A.ccnt = d_ccnt_.as<uint32_t>();
-    A.inst_overflow = d_inst_over_.as<uint32_t>();
-    hip_check(launch_seed(A, s_), "seed");
-    hip_check(hipMemcpyAsync(h_new_ + slot, d_inst_new_.as<unsigned long long>() + (uint64_t)slot * kCountShards, 8,
-                             hipMemcpyDeviceToHost, s_),
-              "D2H");
-    hip_check(hipStreamSynchronize(s_), "sync");
+    // The instance joins the run only once it is seeded: if a step throws
+    // (ENOMEM growing the new-pair buffer, a device error), whatever it
+    // appended is purged, its bucket range is released and the run is as
+    // before, so the caller may retry it later.
+    bool launched = false;
+    try {
+        inst->bbase = (uint32_t)base;
+        inst->slot = slot;
+        // seeds: appended after whatever is already waiting in the buffer
+        hip_check(hipStreamSynchronize(s_), "sync");
+        unsigned long long cur = 0;
+        copy_sync(&cur, d_counters_.ptr, 8, hipMemcpyDeviceToHost, s_);
+        ensure_capacity(cur + inst->max_seeds, true);
+        hip_check(launch_fill_u64(d_inst_new_.as<unsigned long long>() + (uint64_t)slot * kCountShards, kCountShards,
+                                  0, s_),
+                  "fill");
+        DevBuf dmats(ctx_->pool.get(), inst->mats.size() * sizeof(MatDev));
+        hip_check(hipMemcpyAsync(dmats.ptr, inst->mats.data(), inst->mats.size() * sizeof(MatDev),
+                                 hipMemcpyHostToDevice, s_),
+                  "H2D");
+        SeedArgs A{};
+        A.mats = dmats.as<MatDev>();
+        A.I = InstDev{inst->n, inst->S, inst->bbase, 0};
+        A.inst = slot;
+        A.src = inst->graph->src.as<uint32_t>();
+        A.dst = inst->graph->dst.as<uint32_t>();
+        A.lab = inst->graph->lab.as<uint32_t>();
+        A.m = inst->graph->m;
+        A.lm_ptr = inst->lm_ptr.as<uint32_t>();
+        A.lm_mat = inst->lm_mat.as<uint32_t>();
+        A.eps_mat = inst->eps_mat.as<uint32_t>();
+        A.n_eps = inst->n_eps;
+        A.ap_key = d_ap_key_.as<uint32_t>();
+        A.ap_i = d_ap_i_.as<uint32_t>();
+        A.ap_j = d_ap_j_.as<uint32_t>();
+        A.ap_count = d_counters_.as<unsigned long long>();
+        A.ap_cap = ap_cap_;
+        A.inst_new = d_inst_new_.as<unsigned long long>();
+        A.rcnt = d_rcnt_.as<uint32_t>();
+        A.ccnt = d_ccnt_.as<uint32_t>();
+        A.inst_overflow = d_inst_over_.as<uint32_t>();
+        launched = true;
+        hip_check(launch_seed(A, s_), "seed");
+        hip_check(hipMemcpyAsync(h_new_ + slot, d_inst_new_.as<unsigned long long>() + (uint64_t)slot * kCountShards,
+                                 8, hipMemcpyDeviceToHost, s_),
+                  "D2H");
+        hip_check(hipStreamSynchronize(s_), "sync");
+    } catch (...) {
+        if (launched) {
+            (void)launch_purge_slot(d_ap_key_.as<uint32_t>(), d_counters_.as<unsigned long long>(), ap_cap_, slot,
+                                    ctx_->num_cu * 4, s_);
+            (void)launch_zero_counts(d_rcnt_.as<uint32_t>() + base, d_ccnt_.as<uint32_t>() + base, nb,
+                                     reinterpret_cast<uint32_t *>(d_counters_.as<unsigned long long>() + 3), s_);
+            (void)hipStreamSynchronize(s_);
+        }
+        free_buckets(base, nb);
+        throw;
+    }
     inst->stats.seed_pairs = h_new_[slot];
     inst->rounds = 0;
     inst->done = false;
+    insts_.push_back(inst);
+    dirty_ = true;
     // the seeds are not a round's new pairs; the slot's statistics start over
     hip_check(launch_fill_u64(d_inst_new_.as<unsigned long long>() + (uint64_t)slot * kCountShards, kCountShards, 0,
                               s_),
               "fill");
-    hip_check(launch_fill_u32(reinterpret_cast<uint32_t *>(d_slot_stats_.as<SlotStats>() + slot), 
+    hip_check(launch_fill_u32(reinterpret_cast<uint32_t *>(d_slot_stats_.as<SlotStats>() + slot),
                               sizeof(SlotStats) / 4, 0, s_),
               "fill");
 }

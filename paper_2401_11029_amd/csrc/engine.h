@@ -190,11 +190,14 @@ void sparse_copy(Instance &inst, uint32_t nt, uint32_t *src, uint32_t *dst, uint
 class Run {
    public:
     // bucket_capacity: sort buckets for all instances admitted at once
-    // (instance_buckets of each); below 2^32.
-    Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t bucket_capacity, uint32_t max_instances);
+    // (instance_buckets of each); below 2^32.  stream: where the rounds run
+    // (null: the context's stream).
+    Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t bucket_capacity, uint32_t max_instances,
+        hipStream_t stream = nullptr);
     ~Run();
     // Admit an instance: assigns its sort buckets, seeds its pairs (they
-    // become the next round's new pairs).  Between rounds only.
+    // become the next round's new pairs).  Between rounds only.  If it
+    // throws, the run is unchanged (the instance is not admitted).
     void add(const std::shared_ptr<Instance> &inst);
     // Drop an instance (finished); between rounds only.
     void remove(Instance *inst);

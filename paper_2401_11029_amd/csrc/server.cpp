@@ -58,6 +58,9 @@ struct cflr_server {
     uint64_t in_use = 0;
     uint64_t slots_in_use = 0, slot_cap = 0;  // running requests' pair slots, and their bound
     std::unique_ptr<Run> run;
+    hipStream_t stream = nullptr;  // the worker's own stream (default priority): rounds are
+                                   // captured on it, so callers' use of the context's
+                                   // stream (readout, frees) never meets a capture
     std::string fatal;
 
     void loop();
@@ -168,9 +171,16 @@ void cflr_server::loop() {
 
 extern "C" {
 
+static cflr_status server_fail(cflr_status st, const std::string &msg) {
+    set_last_error(msg);
+    return st;
+}
+
 cflr_status cflr_server_create(cflr_ctx *ctx, uint64_t hbm_budget_bytes, uint32_t max_slots,
                                const cflr_opts *opts, cflr_server **out) {
-    if (!ctx || !out || !max_slots) return CFLR_EINVAL;
+    set_last_error("");
+    if (!ctx || !out) return server_fail(CFLR_EINVAL, "null argument");
+    if (!max_slots) return server_fail(CFLR_EINVAL, "max_slots must be at least 1");
     *out = nullptr;
     try {
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
@@ -189,20 +199,29 @@ cflr_status cflr_server_create(cflr_ctx *ctx, uint64_t hbm_budget_bytes, uint32_
         // unless the options say otherwise (it grows on overflow).
         uint64_t buckets = std::min<uint64_t>(1ull << 26, std::max<uint64_t>(1ull << 20, hbm_budget_bytes / 65536));
         if (!s->opts.delta_capacity && !ctx->delta_capacity_hint) s->opts.delta_capacity = 1ull << 26;
-        s->run = std::make_unique<Run>(ctx, s->opts, buckets, max_slots);
+        hip_check(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate");
+        try {
+            s->run = std::make_unique<Run>(ctx, s->opts, buckets, max_slots, s->stream);
+        } catch (...) {
+            (void)hipStreamDestroy(s->stream);
+            throw;
+        }
         s->worker = std::thread([p = s.get()] { p->loop(); });
         *out = s.release();
         return CFLR_OK;
     } catch (const Error &e) {
-        return e.status;
-    } catch (...) {
-        return CFLR_EDEVICE;
+        return server_fail(e.status, e.what());
+    } catch (const std::bad_alloc &) {
+        return server_fail(CFLR_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return server_fail(CFLR_EDEVICE, e.what());
     }
 }
 
 cflr_status cflr_server_submit(cflr_server *s, const cflr_grammar *g, const cflr_graph *graph, uint64_t *ticket) {
-    if (!s || !g || !graph || !ticket) return CFLR_EINVAL;
-    if (graph->ctx != s->ctx) return CFLR_EINVAL;
+    set_last_error("");
+    if (!s || !g || !graph || !ticket) return server_fail(CFLR_EINVAL, "null argument");
+    if (graph->ctx != s->ctx) return server_fail(CFLR_EINVAL, "graph belongs to another context");
     auto r = std::make_unique<Request>();
     r->g = g;
     r->graph = graph;
@@ -210,7 +229,7 @@ cflr_status cflr_server_submit(cflr_server *s, const cflr_grammar *g, const cflr
     r->footprint = instance_footprint(g->low, graph->n);
     r->slots = instance_pair_slots(g->low, graph->n);
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) return CFLR_EDEVICE;
+    if (s->stop) return server_fail(CFLR_EDEVICE, "server stopped: " + s->fatal);
     r->ticket = s->next_ticket++;
     *ticket = r->ticket;
     s->queue.push_back(r.get());
@@ -220,7 +239,7 @@ cflr_status cflr_server_submit(cflr_server *s, const cflr_grammar *g, const cflr
 }
 
 static cflr_status take(cflr_server *s, Request *r, cflr_result **out) {
-    if (r->taken) return CFLR_EINVAL;
+    if (r->taken) return server_fail(CFLR_EINVAL, "result of this ticket already taken");
     r->taken = true;
     if (r->status != CFLR_OK) set_last_error(r->error);
     if (r->status != CFLR_OK && r->status != CFLR_ETIMEOUT) return r->status;
@@ -230,35 +249,38 @@ static cflr_status take(cflr_server *s, Request *r, cflr_result **out) {
 }
 
 cflr_status cflr_server_poll(cflr_server *s, uint64_t ticket, cflr_result **out) {
-    if (!s || !out) return CFLR_EINVAL;
+    set_last_error("");
+    if (!s || !out) return server_fail(CFLR_EINVAL, "null argument");
     *out = nullptr;
     std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return CFLR_EINVAL;
+    if (it == s->reqs.end()) return server_fail(CFLR_EINVAL, "unknown ticket");
     if (!it->second->finished) return CFLR_PENDING;
     return take(s, it->second.get(), out);
 }
 
 cflr_status cflr_server_wait(cflr_server *s, uint64_t ticket, uint64_t timeout_ns, cflr_result **out) {
-    if (!s || !out) return CFLR_EINVAL;
+    set_last_error("");
+    if (!s || !out) return server_fail(CFLR_EINVAL, "null argument");
     *out = nullptr;
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return CFLR_EINVAL;
+    if (it == s->reqs.end()) return server_fail(CFLR_EINVAL, "unknown ticket");
     Request *r = it->second.get();
     bool ok = s->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), [&] { return r->finished; });
-    if (!ok) return CFLR_ETIMEOUT;
+    if (!ok) return server_fail(CFLR_ETIMEOUT, "request not finished within the timeout");
     return take(s, r, out);
 }
 
 cflr_status cflr_server_times(cflr_server *s, uint64_t ticket, double *submitted, double *admitted,
                               double *finished) {
-    if (!s) return CFLR_EINVAL;
+    set_last_error("");
+    if (!s) return server_fail(CFLR_EINVAL, "null argument");
     std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return CFLR_EINVAL;
+    if (it == s->reqs.end()) return server_fail(CFLR_EINVAL, "unknown ticket");
     Request *r = it->second.get();
-    if (!r->finished) return CFLR_PENDING;
+    if (!r->finished) return server_fail(CFLR_PENDING, "request not finished");
     if (submitted) *submitted = r->t_submit;
     if (admitted) *admitted = r->t_admit;
     if (finished) *finished = r->t_finish;
@@ -274,6 +296,11 @@ void cflr_server_free(cflr_server *s) {
     }
     if (s->worker.joinable()) s->worker.join();
     s->run.reset();
+    if (s->stream) {
+        (void)hipSetDevice(s->ctx->device);
+        (void)hipStreamSynchronize(s->stream);
+        (void)hipStreamDestroy(s->stream);
+    }
     delete s;
 }
 

@@ -112,3 +112,30 @@ def test_null_arguments_are_rejected(cflr_lib):
     assert cflr_lib.cflr_grammar_info_get(None, None) == 1
     assert cflr_lib.cflr_result_count(None, 0, None) == 1
     assert cflr_lib.cflr_grammar_nonterminal_name(None, 0) is None
+
+
+def test_failing_server_calls_set_the_error_message(cflr_lib):
+    # every cflr_server_* failure returns a status and leaves a message in
+    # cflr_last_error (argument errors are caught before any device call)
+    L = cflr_lib
+    out = C.c_void_p()
+    t = C.c_uint64()
+    assert L.cflr_server_create(None, 1 << 20, 4, None, C.byref(out)) == 1  # CFLR_EINVAL
+    assert L.cflr_last_error() not in (None, b"")
+    L.cflr_opts_default  # keep the binding loaded
+    assert L.cflr_server_submit(None, None, None, C.byref(t)) == 1
+    assert b"null" in L.cflr_last_error()
+    assert L.cflr_server_poll(None, 1, C.byref(out)) == 1
+    assert L.cflr_last_error() != b""
+    assert L.cflr_server_wait(None, 1, 0, C.byref(out)) == 1
+    assert L.cflr_last_error() != b""
+    assert L.cflr_server_times(None, 1, None, None, None) == 1
+    assert L.cflr_last_error() != b""
+
+
+def test_storage_option_and_stat_fields():
+    import paper_2401_11029_amd as cflr
+    from paper_2401_11029_amd._lib import Opts, Stats
+    # the storage choice is the last field of the options and of the stats
+    assert Opts._fields_[-1][0] == "storage" and Stats._fields_[-1][0] == "storage"
+    assert cflr.opts().storage == 0 and cflr.opts(storage=2).storage == 2

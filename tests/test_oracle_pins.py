@@ -376,3 +376,98 @@ def test_planted_oracle_mistakes_are_caught(mutant, oracle_bin, monkeypatch):
             os.unlink(os.path.join(tmp, fn))
         os.rmdir(tmp)
     assert caught, f"pins did not catch mutant {mutant}"
+
+
+# The certificate checker must reject certificates with a planted defect, and
+# the closure check results with one pair or seed missing; a checker that
+# accepted anything would pass the test above.
+
+def _read_raw_cert(path):
+    import struct
+    with open(path, "rb") as f:
+        data = f.read()
+    off = 0
+    (nsym,) = struct.unpack_from("<I", data, off)
+    off += 4
+    syms = []
+    for _ in range(nsym):
+        (k,) = struct.unpack_from("<I", data, off)
+        name = data[off + 4: off + 4 + k]
+        (nt,) = struct.unpack_from("<I", data, off + 4 + k)
+        syms.append((name, nt))
+        off += 8 + k
+    (nr,) = struct.unpack_from("<I", data, off)
+    off += 4
+    rules = np.frombuffer(data, dtype="<u4", count=4 * nr, offset=off).reshape(nr, 4).copy()
+    off += 16 * nr
+    (nf,) = struct.unpack_from("<Q", data, off)
+    off += 8
+    facts = np.frombuffer(data, dtype="<u4", count=5 * nf, offset=off).reshape(nf, 5).copy()
+    return syms, rules, facts
+
+
+def _write_raw_cert(path, syms, rules, facts):
+    import struct
+    with open(path, "wb") as f:
+        f.write(struct.pack("<I", len(syms)))
+        for name, nt in syms:
+            f.write(struct.pack("<I", len(name)) + name + struct.pack("<I", nt))
+        f.write(struct.pack("<I", rules.shape[0]) + rules.astype("<u4").tobytes())
+        f.write(struct.pack("<Q", facts.shape[0]) + facts.astype("<u4").tobytes())
+
+
+def test_certificate_checker_rejects_planted_defects(oracle_bin):
+    text, g = G.ALIAS_FIG5A_WCNF, graphs.alias_graph(300, seed=11)
+    r = oracle.solve(text, g, cert=True)
+    tmp = os.path.dirname(r.cert_path)
+    try:
+        syms, rules, facts = _read_raw_cert(r.cert_path)
+        good = os.path.join(tmp, "good.bin")
+        _write_raw_cert(good, syms, rules, facts)
+        certified = check_certificate(text, g, good)  # the rewrite itself is faithful
+        check_closed(text, g, certified)
+        NONE = 0xFFFFFFFF
+        binary = [t for t in range(facts.shape[0]) if facts[t, 3] != NONE and rules[facts[t, 3], 0] == 2]
+        assert binary
+        t = binary[len(binary) // 2]
+        s, i, j, rule, mid = facts[t].tolist()
+        left = rules[rule, 2]
+        premise = next(u for u in range(t) if facts[u, 0] == left and facts[u, 1] == i and facts[u, 2] == mid)
+        bad = os.path.join(tmp, "bad.bin")
+        defects = {
+            # a premise of a derived fact dropped from the certificate
+            "dropped premise": np.delete(facts, premise, axis=0),
+            # the derived fact placed before its premise
+            "premise after use": np.concatenate([facts[:premise], facts[t:t + 1], facts[premise:t], facts[t + 1:]]),
+        }
+        wrong_mid = facts.copy()
+        wrong_mid[t, 4] = (mid + 1) % g.n if not any(
+            facts[u, 0] == left and facts[u, 1] == i and facts[u, 2] == (mid + 1) % g.n for u in range(t)) else g.n
+        defects["wrong midpoint"] = wrong_mid
+        wrong_head = facts.copy()
+        other = next(x for x in range(len(syms)) if syms[x][1] == 1 and x != s)
+        wrong_head[t, 0] = other
+        defects["head of another symbol"] = wrong_head
+        fake_edge = facts.copy()
+        first_edge = next(u for u in range(facts.shape[0]) if facts[u, 3] == NONE)
+        fake_edge[first_edge, 2] = (facts[first_edge, 2] + 1) % g.n
+        defects["edge not in the graph"] = fake_edge
+        duplicated = np.concatenate([facts, facts[t:t + 1]])
+        defects["fact listed twice"] = duplicated
+        for name, f in defects.items():
+            _write_raw_cert(bad, syms, rules, f)
+            with pytest.raises(AssertionError):
+                check_certificate(text, g, bad)
+            print("rejected:", name)
+        # closure: one derived pair missing, one eps seed missing
+        x = next(x for x in r.order if len(certified[x]) > 1 and x != "V")
+        short = {k: set(v) for k, v in certified.items()}
+        short[x].discard(next(iter(sorted(certified[x]))))
+        with pytest.raises(AssertionError):
+            check_closed(text, g, short)
+        no_eps = {k: set(v) for k, v in certified.items()}
+        no_eps["V"].discard((0, 0))
+        with pytest.raises(AssertionError):
+            check_closed(text, g, no_eps)
+    finally:
+        shutil.rmtree(tmp)
