@@ -203,6 +203,37 @@ void cflr_graph_free(cflr_graph *g);
 cflr_status cflr_solve(cflr_ctx *ctx, const cflr_grammar *g, const cflr_graph *graph,
                        const cflr_opts *opts, cflr_result **out);
 
+/* ---- solve without allocating ------------------------------------------
+ * For callers that cannot allocate device memory: code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * solve as cflr_solve on sparse storage, but every device structure lives
+ * in one fixed region the library holds per device (a file-scope device
+ * array of CFLR_NOALLOC_SCRATCH_BYTES, kept until the process ends): the
+ * call makes no hipMalloc, hipFree, pinned-host or library allocation.
+ * Inputs: the graph as device arrays src/dst/label (n_edges each, device of
+ * ctx; label[e] < n_labels indexes label_names); the caller keeps them.
+ * Outputs: counts (host array of cflr_grammar_num_nonterminals entries)
+ * receives each user non-terminal's pair count; out_src/out_dst (device
+ * arrays of `capacity` entries) receive the pairs, each non-terminal's
+ * sorted by (i, j), one after another in non-terminal order.  stats
+ * (nullable) as for cflr_result_stats.  opts may be NULL; storage is
+ * ignored.  The region holds the lists of about 2^24 pair entries and a
+ * hash set of 2^24 slots (roughly 10^7 pairs in all, fewer with many
+ * non-terminals on many vertices).
+ * Errors: EINVAL (null arguments, an edge with a vertex >= n_vertices or a
+ * label >= n_labels, capacity below the total: counts are then written but
+ * no pairs), ENOMEM (the solve needs more than the region holds; message
+ * names the structure), ETIMEOUT (max_rounds), EUNSUPPORTED, EDEVICE.
+ * Every call on one device shares that device's region and leaves the last
+ * call's contents in it (each call clears what it needs): calls that
+ * overlap on one device race, so serialise them. */
+#define CFLR_NOALLOC_SCRATCH_BYTES (256ull << 20)
+cflr_status cflr_solve_noalloc(cflr_ctx *ctx, const cflr_grammar *g, uint32_t n_vertices, uint64_t n_edges,
+                               const uint32_t *src, const uint32_t *dst, const uint32_t *label,
+                               uint32_t n_labels, const char *const *label_names, const cflr_opts *opts,
+                               uint32_t *out_src, uint32_t *out_dst, uint64_t capacity, uint64_t *counts,
+                               cflr_stats *stats);
+
 /* Batched form: graphs[k] is solved with grammars[k] (the same grammar may be
  * passed for every k).  Admitted instances advance together: the product of
  * a round is two launches (row parts, then column parts) over every (graph,

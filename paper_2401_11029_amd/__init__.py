@@ -23,7 +23,7 @@ from . import _lib
 from ._lib import Opts, Stats, GrammarInfo, STATUS_NAMES
 
 __all__ = ["CflrError", "Context", "Grammar", "Graph", "Result", "Server",
-           "solve", "solve_batch", "autotune", "opts", "lib"]
+           "solve", "solve_noalloc", "solve_batch", "autotune", "opts", "lib"]
 
 
 class CflrError(RuntimeError):
@@ -236,6 +236,37 @@ def solve(ctx: Context, grammar: Grammar, graph: Graph, options: Opts | None = N
             lib().cflr_result_free(h)
         _check(st)
     return Result(h, grammar)
+
+
+def solve_noalloc(ctx: Context, grammar: Grammar, n: int, src, dst, label, label_names,
+                  capacity: int, options: Opts | None = None, **kw):
+    """The solve of ``solve`` without device allocation (cflr_solve_noalloc):
+    src/dst/label are int32 or uint32 torch tensors on ctx's device, the
+    pairs come back in two int32 tensors of ``capacity`` entries allocated
+    here (by torch, before the call): returns (counts dict, src, dst, stats),
+    each non-terminal's pairs sorted by (i, j), one after another in
+    non-terminal order, in src[:total], dst[:total]."""
+    import torch
+    ctx._no_server()
+    ps, ds, ks = _u32_buffer(src)
+    pd, dd, kd = _u32_buffer(dst)
+    pl, dl, kl = _u32_buffer(label)
+    if not (ds and dd and dl):
+        raise ValueError("src, dst and label must be device tensors")
+    o = options if options is not None else opts(**kw)
+    names = [s.encode("utf-8") for s in label_names]
+    arr = (C.c_char_p * max(1, len(names)))(*names)
+    dev = ks.device
+    out_s = torch.empty(max(1, capacity), dtype=torch.int32, device=dev)
+    out_d = torch.empty(max(1, capacity), dtype=torch.int32, device=dev)
+    nts = grammar.nonterminals
+    counts = (C.c_uint64 * max(1, len(nts)))()
+    st = Stats()
+    torch.cuda.synchronize(dev)
+    _check(lib().cflr_solve_noalloc(ctx._h, grammar._h, int(n), int(len(ks)), C.c_void_p(ps), C.c_void_p(pd),
+                                    C.c_void_p(pl), len(names), arr, C.byref(o), C.c_void_p(out_s.data_ptr()),
+                                    C.c_void_p(out_d.data_ptr()), int(capacity), counts, C.byref(st)))
+    return {x: counts[k] for k, x in enumerate(nts)}, out_s, out_d, st.as_dict()
 
 
 def solve_batch(ctx: Context, grammars, graphs, options: Opts | None = None, **kw):

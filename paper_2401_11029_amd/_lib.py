@@ -77,6 +77,9 @@ SIGNATURES = {
                                     C.POINTER(C.c_char_p), C.c_int, C.POINTER(P)]),
     "cflr_graph_free": (None, [P]),
     "cflr_solve": (C.c_int, [P, P, P, C.POINTER(Opts), C.POINTER(P)]),
+    "cflr_solve_noalloc": (C.c_int, [P, P, C.c_uint32, C.c_uint64, P, P, P, C.c_uint32,
+                                     C.POINTER(C.c_char_p), C.POINTER(Opts), P, P, C.c_uint64,
+                                     C.POINTER(C.c_uint64), C.POINTER(Stats)]),
     "cflr_solve_batch": (C.c_int, [P, C.POINTER(P), C.POINTER(P), C.c_uint32,
                                    C.POINTER(Opts), C.POINTER(P)]),
     "cflr_autotune": (C.c_int, [P, C.POINTER(P), C.POINTER(P), C.c_uint32,

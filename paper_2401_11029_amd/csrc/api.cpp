@@ -340,6 +340,27 @@ cflr_status cflr_solve(cflr_ctx *ctx, const cflr_grammar *g, const cflr_graph *g
     });
 }
 
+cflr_status cflr_solve_noalloc(cflr_ctx *ctx, const cflr_grammar *g, uint32_t n_vertices, uint64_t n_edges,
+                               const uint32_t *src, const uint32_t *dst, const uint32_t *label, uint32_t n_labels,
+                               const char *const *label_names, const cflr_opts *opts, uint32_t *out_src,
+                               uint32_t *out_dst, uint64_t capacity, uint64_t *counts, cflr_stats *stats) {
+    return guard([&]() -> cflr_status {
+        if (!ctx || !g || !counts) return fail(CFLR_EINVAL, "null argument");
+        if (n_edges && (!src || !dst || !label)) return fail(CFLR_EINVAL, "null edge array");
+        if (n_labels && !label_names) return fail(CFLR_EINVAL, "null label names");
+        std::vector<std::string> names;
+        for (uint32_t l = 0; l < n_labels; l++) {
+            if (!label_names[l]) return fail(CFLR_EINVAL, "null label name");
+            names.emplace_back(label_names[l]);
+        }
+        set_device(ctx);
+        cflr_opts o = effective(opts);
+        sparse_solve_noalloc(ctx, g->low, n_vertices, n_edges, src, dst, label, names, o, out_src, out_dst, capacity,
+                             counts, stats);
+        return CFLR_OK;
+    });
+}
+
 cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars, const cflr_graph *const *graphs,
                              uint32_t count, const cflr_opts *opts, cflr_result **outs) {
     return guard([&]() -> cflr_status {

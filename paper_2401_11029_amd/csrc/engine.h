@@ -183,6 +183,12 @@ std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const
 // false; *timed_out when opts.max_rounds stopped it first.
 void sparse_solve(cflr_ctx *ctx, const cflr_opts &opts, Instance &inst, bool *timed_out);
 void sparse_counts(Instance &inst);
+// cflr_solve_noalloc: the sparse engine on the file-scope scratch region (no
+// device allocation); results into the caller's device arrays.
+void sparse_solve_noalloc(cflr_ctx *ctx, const Lowered &low, uint32_t n, uint64_t m, const uint32_t *src,
+                          const uint32_t *dst, const uint32_t *label, const std::vector<std::string> &label_names,
+                          const cflr_opts &o, uint32_t *out_src, uint32_t *out_dst, uint64_t capacity,
+                          uint64_t *counts, cflr_stats *stats);
 void sparse_copy(Instance &inst, uint32_t nt, uint32_t *src, uint32_t *dst, uint64_t count, bool on_device);
 
 // A set of instances advancing round by round together (the product

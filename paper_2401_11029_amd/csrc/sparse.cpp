@@ -14,10 +14,17 @@
 // resumes or re-runs the step.  A re-run is exact: a pair already inserted
 // is found again and not reported twice, and the pairs whose insert was
 // taken back are inserted again.
+//
+// Device memory comes from the context's caching pool, or -- for
+// cflr_solve_noalloc, whose callers cannot allocate -- from the file-scope
+// array `scratch` below, carved once per call; there every structure has a
+// fixed size and an overflow ends the solve with CFLR_ENOMEM.
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "engine.h"
 #include "sparse.h"
@@ -101,15 +108,71 @@ uint64_t pow2_at_least(uint64_t v) {
     return p;
 }
 
+uint64_t pow2_at_most(uint64_t v) {
+    uint64_t p = 1;
+    while (2 * p <= v) p <<= 1;
+    return p;
+}
+
+// Device memory of the engine: a block of the context's caching pool, or a
+// piece of a fixed region (then `buf` is empty and nothing is freed).
+struct Mem {
+    DevBuf buf;
+    void *ptr = nullptr;
+    uint64_t bytes = 0;
+    template <class T>
+    T *as() const {
+        return static_cast<T *>(ptr);
+    }
+};
+
+class Alloc {
+   public:
+    explicit Alloc(DevPool *pool) : pool_(pool) {}
+    Alloc(void *base, uint64_t cap) : base_(static_cast<char *>(base)), cap_(cap) {}
+    bool fixed() const { return pool_ == nullptr; }
+    Mem get(uint64_t bytes, const char *what) {
+        Mem m;
+        bytes = std::max<uint64_t>(1, bytes);
+        if (pool_) {
+            m.buf = DevBuf(pool_, bytes);
+            m.ptr = m.buf.ptr;
+            m.bytes = bytes;
+            return m;
+        }
+        const uint64_t at = (top_ + 255) / 256 * 256;
+        if (at > cap_ || bytes > cap_ - at)
+            throw Error(CFLR_ENOMEM, std::string("input too large for the no-alloc scratch (") + what + " needs " +
+                                         std::to_string(bytes) + " more bytes of " + std::to_string(cap_) + ")");
+        m.ptr = base_ + at;
+        m.bytes = bytes;
+        top_ = at + bytes;
+        return m;
+    }
+    // bytes of the fixed region not handed out yet
+    uint64_t left() const {
+        const uint64_t at = (top_ + 255) / 256 * 256;
+        return at < cap_ ? cap_ - at : 0;
+    }
+    uint64_t mark() const { return top_; }
+    void release_to(uint64_t mark) { top_ = mark; }
+
+   private:
+    DevPool *pool_ = nullptr;
+    char *base_ = nullptr;
+    uint64_t cap_ = 0, top_ = 0;
+};
+
 template <class T>
-void upload(DevBuf &buf, DevPool *pool, const std::vector<T> &v, hipStream_t s) {
-    buf = DevBuf(pool, std::max<size_t>(1, v.size()) * sizeof(T));
-    if (!v.empty()) copy_sync(buf.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+Mem upload(Alloc &A, const std::vector<T> &v, hipStream_t s, const char *what) {
+    Mem m = A.get(std::max<size_t>(1, v.size()) * sizeof(T), what);
+    if (!v.empty()) copy_sync(m.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+    return m;
 }
 
 // A new-pair buffer with its own count word.
 struct Buf {
-    DevBuf key, i, j, count;
+    Mem key, i, j, count;
     uint64_t cap = 0;
     sp::PairBuf dev() const {
         return sp::PairBuf{key.as<uint32_t>(), i.as<uint32_t>(), j.as<uint32_t>(),
@@ -117,19 +180,20 @@ struct Buf {
     }
 };
 
-void alloc_buf(Buf &b, DevPool *pool, uint64_t cap, hipStream_t s) {
-    b.key = DevBuf(pool, cap * 4);
-    b.i = DevBuf(pool, cap * 4);
-    b.j = DevBuf(pool, cap * 4);
-    if (!b.count.ptr) b.count = DevBuf(pool, 8);
+void alloc_buf(Buf &b, Alloc &A, uint64_t cap, hipStream_t s) {
+    b.key = A.get(cap * 4, "a new-pair buffer");
+    b.i = A.get(cap * 4, "a new-pair buffer");
+    b.j = A.get(cap * 4, "a new-pair buffer");
+    if (!b.count.ptr) b.count = A.get(8, "a new-pair buffer");
     b.cap = cap;
     hip_check(sp::launch_fill_u64(b.count.as<unsigned long long>(), 1, 0, s), "fill");
 }
 
 // Grow a buffer to new_cap entries keeping [0, cap); its count becomes the
 // old capacity (the entries there are pairs or holes).
-void grow_buf(Buf &b, DevPool *pool, uint64_t new_cap, hipStream_t s) {
-    DevBuf k(pool, new_cap * 4), i(pool, new_cap * 4), j(pool, new_cap * 4);
+void grow_buf(Buf &b, Alloc &A, uint64_t new_cap, hipStream_t s) {
+    Mem k = A.get(new_cap * 4, "a new-pair buffer"), i = A.get(new_cap * 4, "a new-pair buffer"),
+        j = A.get(new_cap * 4, "a new-pair buffer");
     hip_check(hipMemcpyAsync(k.ptr, b.key.ptr, b.cap * 4, hipMemcpyDeviceToDevice, s), "D2D");
     hip_check(hipMemcpyAsync(i.ptr, b.i.ptr, b.cap * 4, hipMemcpyDeviceToDevice, s), "D2D");
     hip_check(hipMemcpyAsync(j.ptr, b.j.ptr, b.cap * 4, hipMemcpyDeviceToDevice, s), "D2D");
@@ -142,115 +206,159 @@ void grow_buf(Buf &b, DevPool *pool, uint64_t new_cap, hipStream_t s) {
     b.cap = new_cap;
 }
 
-}  // namespace
+// What the seeding kernels read: the edges and the label -> matrix tables.
+struct SeedInput {
+    uint64_t m = 0;
+    const uint32_t *src = nullptr, *dst = nullptr, *lab = nullptr;
+    const uint32_t *lm_ptr = nullptr, *lm_mat = nullptr, *eps_mat = nullptr;
+    uint32_t n_eps = 0;
+    uint64_t max_seeds = 0;
+};
 
-// ------------------------------------------------------------------- solve
+// Slots of the seed buffer beyond the seeds: every wave of the two seeding
+// kernels may leave one partly used chunk.
+uint64_t seed_slack(uint64_t m, uint64_t eps_pairs) {
+    auto waves = [](uint64_t items) {
+        const uint64_t blocks = std::min<uint64_t>(std::max<uint64_t>(1, (items + 255) / 256), sp::kSeedBlocks);
+        return items ? 4 * blocks : 0;
+    };
+    return (waves(m) + waves(eps_pairs)) * sp::kChunk;
+}
 
-void sparse_solve(cflr_ctx *ctx, const cflr_opts &o, Instance &inst, bool *timed_out) {
-    *timed_out = false;
-    hipStream_t s = ctx->stream;
-    DevPool *pool = ctx->pool.get();
-    const Lowered &low = inst.low;
-    const uint32_t n = inst.n;
+struct CoreOut {
+    Mem dir, pool;  // the adjacency lists, kept for readout
+    Plan plan;
+    uint32_t rounds = 0, reruns = 0;
+    uint64_t seed_pairs = 0, new_pairs = 0, max_delta = 0, launches = 0;
+    double product_ms = 0;
+    bool timed_out = false;
+};
+
+// The solve.  A.fixed(): every structure is sized once from what the region
+// leaves, and an overflow is an ENOMEM (nothing can grow); the key-sorted
+// product (bucket arrays over all matrices and vertices) is off there.
+void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered &low, uint32_t n,
+                 const SeedInput &in_seed, Alloc &A, CoreOut &res) {
+    const bool fixed = A.fixed();
     if (n >= sp::kMaxVertices) throw Error(CFLR_EUNSUPPORTED, "sparse storage holds at most 2^24 - 1 vertices");
     if (low.nmat() >= sp::kMaxMatrices) throw Error(CFLR_EUNSUPPORTED, "grammar needs 65535 or more matrices");
     const bool log = std::getenv("CFLR_LOG") != nullptr;
-    Plan P = make_plan(low, n);
+    auto too_small = [&](const char *what) {
+        return Error(CFLR_ENOMEM, std::string("the no-alloc scratch cannot hold ") + what + " of this solve");
+    };
+    res.plan = make_plan(low, n);
+    const Plan &P = res.plan;
 
-    auto store = std::make_shared<SparseStore>();
-    store->hold = CtxRef(ctx);
-    store->ctx = ctx;
-    store->n = n;
-    store->nlayouts = P.nlayouts;
-    store->row_layout.resize(low.nmat());
-    for (uint32_t x = 0; x < low.nmat(); x++) store->row_layout[x] = P.mats[x].row_layout;
-
-    DevBuf d_mats, d_uses, d_obs_ptr, d_obs;
-    upload(d_mats, pool, P.mats, s);
-    upload(d_uses, pool, P.uses, s);
-    upload(d_obs_ptr, pool, P.obs_ptr, s);
-    upload(d_obs, pool, P.obs, s);
+    Mem d_mats = upload(A, P.mats, s, "the matrix table");
+    Mem d_uses = upload(A, P.uses, s, "the use table");
+    Mem d_obs_ptr = upload(A, P.obs_ptr, s, "the observer table");
+    Mem d_obs = upload(A, P.obs, s, "the observer table");
     const uint64_t cells = (uint64_t)P.nlayouts * n;
-    store->dir = DevBuf(pool, std::max<uint64_t>(1, cells) * sizeof(sp::Dir));
-    DevBuf d_cur(pool, std::max<uint64_t>(1, cells) * 4);
-    DevBuf d_mask(pool, std::max<uint64_t>(1, P.mask_words) * 8);
-    DevBuf d_ctl(pool, sp::kCtlWords * 8);
+    res.dir = A.get(cells * sizeof(sp::Dir), "the list directory");
+    Mem d_cur = A.get(cells * 4, "the list cursors");
+    Mem d_mask = A.get(P.mask_words * 8, "the use masks");
+    Mem d_ctl = A.get(sp::kCtlWords * 8, "the control words");
     if (cells) {
-        hip_check(hipMemsetAsync(store->dir.ptr, 0, cells * sizeof(sp::Dir), s), "memset");
-        hip_check(hipMemsetAsync(d_cur.ptr, 0, cells * 4, s), "memset");
+        hip_check(sp::launch_fill_u64(res.dir.as<unsigned long long>(), cells * 2, 0, s), "fill");
+        hip_check(sp::launch_fill_u32(d_cur.as<uint32_t>(), cells, 0, s), "fill");
     }
-    if (P.mask_words) hip_check(hipMemsetAsync(d_mask.ptr, 0, P.mask_words * 8, s), "memset");
-    hip_check(hipMemsetAsync(d_ctl.ptr, 0, sp::kCtlWords * 8, s), "memset");
+    if (P.mask_words) hip_check(sp::launch_fill_u64(d_mask.as<unsigned long long>(), P.mask_words, 0, s), "fill");
+    hip_check(sp::launch_fill_u64(d_ctl.as<unsigned long long>(), sp::kCtlWords, 0, s), "fill");
 
     const uint32_t grid = std::max<uint32_t>(1, ctx->num_cu * 8);
     uint32_t waves = o.grid_waves ? o.grid_waves : ctx->grid_waves_tuned;
     if (!waves) waves = ctx->num_cu * 32;
-    const uint64_t slack = 2ull * waves * 64;  // keys a halted round may insert and take back
+    if (fixed) waves = std::min<uint32_t>(waves, ctx->num_cu * 4);  // less chunk slack in a small region
+    const uint64_t slack = 2ull * waves * 64;                       // keys a halted round may insert and take back
+    const uint64_t out_slack = (uint64_t)waves * sp::kChunk;        // chunk slots a product may leave unused
 
-    // new-pair buffers; the first holds the seeds (their count is bounded).
-    // Capacities start at what earlier solves on this context grew to
-    // (bounded by the size of this input), or at opts.delta_capacity.
-    const uint64_t seeds_max = inst.max_seeds;
+    // capacities: the new-pair buffers (the first holds the seeds), the
+    // list pool, the hash set; from earlier solves on this context (bounded
+    // by the size of this input) or opts.delta_capacity -- or, in a fixed
+    // region, split from what it leaves
+    const uint64_t seeds_max = in_seed.max_seeds;
+    const uint64_t seed_cap = seeds_max + seed_slack(in_seed.m, (uint64_t)in_seed.n_eps * n);
     const uint64_t scale = std::max<uint64_t>(1ull << 16, 4096 * seeds_max);
-    uint64_t cap_out = o.delta_capacity ? std::max<uint64_t>(64, o.delta_capacity)
-                                        : std::max<uint64_t>(1ull << 16, std::min(ctx->sparse_delta_hint, scale));
-    const uint64_t seed_slack = 2ull * 4 * sp::kSeedBlocks * sp::kChunk;
-    Buf A, B;
-    alloc_buf(A, pool, std::max(cap_out, seeds_max + seed_slack), s);
-    alloc_buf(B, pool, cap_out, s);
+    uint64_t cap_out, pool_cap, slots = 0;
+    uint64_t fixed_mark = 0;
+    if (fixed) {
+        // list pool 40 %, hash set 40 %, the two new-pair buffers with
+        // their touched-list and copy queues the rest (52 bytes a pair)
+        const uint64_t R = A.left() > (1u << 20) ? A.left() - (1u << 20) : 0;
+        slots = pow2_at_most(std::max<uint64_t>(1, R * 2 / 5 / 8));
+        pool_cap = R * 2 / 5 / 4;
+        cap_out = R / 5 / 52;
+        if (cap_out < seed_cap || cap_out <= out_slack) throw too_small("the seeds");
+    } else {
+        cap_out = o.delta_capacity ? std::max<uint64_t>(64, o.delta_capacity)
+                                   : std::max<uint64_t>(1ull << 16, std::min(ctx->sparse_delta_hint, scale));
+        pool_cap = std::max<uint64_t>(1ull << 20, 4 * seeds_max);
+        if (!o.delta_capacity) pool_cap = std::max(pool_cap, std::min(ctx->sparse_pool_hint, 16 * scale));
+    }
+    Mem d_pool = A.get(pool_cap * 4, "the list pool");
+    if (fixed) fixed_mark = A.mark();  // everything after this is free again after the solve
+    Buf BA, BB;
+    alloc_buf(BA, A, fixed ? cap_out : std::max(cap_out, seed_cap), s);
+    alloc_buf(BB, A, cap_out, s);
 
     // hash set: at most 70 % full, counting what the next round may add
     uint64_t hash_keys = 0;       // pairs in the table
     uint64_t tombs_resident = 0;  // tombstones in the table (a rehash drops them)
-    uint64_t slots = 0;
-    DevBuf hash;
+    uint64_t cur_slots = 0;
+    Mem hash;
     auto hash_need = [&](uint64_t extra) {
         return pow2_at_least((hash_keys + tombs_resident + extra + slack) * 10 / 7 + 1);
     };
     sp::State S{};
+    S.ctl = d_ctl.as<unsigned long long>();
     auto rehash_to = [&](uint64_t new_slots) {
         if (new_slots & (new_slots - 1)) throw Error(CFLR_EDEVICE, "internal: hash slots not a power of two");
-        DevBuf nh(pool, new_slots * 8);
+        if (fixed && cur_slots) throw too_small("the pairs");
+        Mem nh = A.get(new_slots * 8, "the hash set");
         hip_check(sp::launch_fill_u64(nh.as<unsigned long long>(), new_slots, sp::kEmpty, s), "fill");
-        if (slots) {
+        if (cur_slots) {
             S.hash = nh.as<unsigned long long>();
             S.hash_mask = new_slots - 1;
-            hip_check(sp::launch_rehash(S, hash.as<unsigned long long>(), slots, s), "rehash");
+            hip_check(sp::launch_rehash(S, hash.as<unsigned long long>(), cur_slots, s), "rehash");
         }
         hash = std::move(nh);
-        slots = new_slots;
+        cur_slots = new_slots;
         S.hash = hash.as<unsigned long long>();
-        S.hash_mask = slots - 1;
+        S.hash_mask = cur_slots - 1;
         tombs_resident = 0;
         hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlTomb, 1, 0, s), "fill");
     };
 
-    // the pool of list entries
-    uint64_t pool_cap = std::max<uint64_t>(1ull << 20, 4 * seeds_max);
-    if (!o.delta_capacity) pool_cap = std::max(pool_cap, std::min(ctx->sparse_pool_hint, 16 * scale));
-    DevBuf d_pool(pool, pool_cap * 4);
-    DevBuf d_touched, d_moves;
+    Mem d_touched, d_moves;
     uint64_t touched_cap = 0;
+    auto size_touched = [&](uint64_t in_cap) {
+        if (touched_cap >= 2 * in_cap) return;
+        touched_cap = 2 * in_cap;
+        d_touched = A.get(touched_cap * 8, "the touched lists");
+        d_moves = A.get(std::max<uint64_t>(1, touched_cap / 4) * 24, "the list copy queue");
+    };
+    if (fixed) size_touched(cap_out);
 
     // the grouped product: new pairs sorted by (matrix, key); buckets whose
     // products reach `threshold` (n / 2 by default: below that the per-item
     // cost of the bit set outweighs the hash probes it saves, measured on
     // the 200,000-vertex points-to graph) are expanded into an LDS bit set.
-    // Off when the bucket space or the bit set is too large.
+    // Off when the bucket space or the bit set is too large, and in a fixed
+    // region.
     sp::KeySort K{};
     K.nb0 = (uint64_t)P.nrank0 * n;
     K.nb = K.nb0 + (uint64_t)P.nrank1 * n;
-    const bool grouped = K.nb > 0 && K.nb < (1ull << 30) && sp::heavy_lds_bytes(n) <= sp::kHeavyMaxLds &&
+    const bool grouped = !fixed && K.nb > 0 && K.nb < (1ull << 30) && sp::heavy_lds_bytes(n) <= sp::kHeavyMaxLds &&
                          std::getenv("CFLR_SPARSE_UNGROUPED") == nullptr;
     K.threshold = std::max<uint64_t>(1, n / 2);
     if (const char *h = std::getenv("CFLR_SPARSE_HEAVY")) K.threshold = std::max<uint64_t>(1, std::strtoull(h, nullptr, 10));
     K.big_entry = 0x7FFFFFFFu;
     if (const char *h = std::getenv("CFLR_SPARSE_BIG")) K.big_entry = (uint32_t)std::strtoul(h, nullptr, 10);
-    DevBuf k_start, k_work, k_bsum, k_entry, k_heavy, k_ework;
+    Mem k_start, k_work, k_bsum, k_entry, k_heavy, k_ework;
     if (grouped) {
-        k_start = DevBuf(pool, (K.nb + 1) * 4);
-        k_work = DevBuf(pool, K.nb * 8);
-        k_bsum = DevBuf(pool, sp::key_sort_scan_blocks(K.nb) * 4);
+        k_start = A.get((K.nb + 1) * 4, "the key sort");
+        k_work = A.get(K.nb * 8, "the key sort");
+        k_bsum = A.get(sp::key_sort_scan_blocks(K.nb) * 4, "the key sort");
         K.start = k_start.as<uint32_t>();
         K.work = k_work.as<unsigned long long>();
         K.bsum = k_bsum.as<uint32_t>();
@@ -262,21 +370,21 @@ void sparse_solve(cflr_ctx *ctx, const cflr_opts &o, Instance &inst, bool *timed
     S.uses = d_uses.as<sp::Use>();
     S.obs_ptr = d_obs_ptr.as<uint32_t>();
     S.obs = d_obs.as<sp::Obs>();
-    S.dir = store->dir.as<sp::Dir>();
+    S.dir = res.dir.as<sp::Dir>();
     S.cur = d_cur.as<uint32_t>();
     S.mask = d_mask.as<uint64_t>();
     S.pool = d_pool.as<uint32_t>();
     S.pool_cap = pool_cap;
-    S.ctl = d_ctl.as<unsigned long long>();
-    rehash_to(pow2_at_least(
-        std::max(hash_need(seeds_max), o.delta_capacity ? 0 : std::min(ctx->sparse_slots_hint, 16 * scale))));
+    if (fixed) {
+        if (hash_need(seeds_max) > slots) throw too_small("the seeds");
+        rehash_to(slots);
+    } else {
+        rehash_to(pow2_at_least(
+            std::max(hash_need(seeds_max), o.delta_capacity ? 0 : std::min(ctx->sparse_slots_hint, 16 * scale))));
+    }
 
-    unsigned long long *h_ctl = nullptr;
-    hip_check(hipHostMalloc((void **)&h_ctl, (sp::kCtlWords + 2) * 8, 0), "hipHostMalloc");
-    struct PinFree {
-        unsigned long long *p;
-        ~PinFree() { (void)hipHostFree(p); }
-    } pin_guard{h_ctl};
+    // control words read back after each step (pageable: no pinned allocation)
+    unsigned long long h_ctl[sp::kCtlWords + 2] = {};
     auto read_ctl = [&](const Buf *out) {
         hip_check(hipMemcpyAsync(h_ctl, d_ctl.ptr, sp::kCtlWords * 8, hipMemcpyDeviceToHost, s), "D2H");
         if (out) hip_check(hipMemcpyAsync(h_ctl + sp::kCtlWords, out->count.ptr, 8, hipMemcpyDeviceToHost, s), "D2H");
@@ -293,53 +401,55 @@ void sparse_solve(cflr_ctx *ctx, const cflr_opts &o, Instance &inst, bool *timed
     // ---- seeds (a re-run after an overflow inserts only what is missing)
     hip_check(sp::launch_round_start(S, s), "round start");
     for (int attempt = 0;; attempt++) {
-        hip_check(sp::launch_seed(S, inst.graph->src.as<uint32_t>(), inst.graph->dst.as<uint32_t>(),
-                                  inst.graph->lab.as<uint32_t>(), inst.graph->m, inst.lm_ptr.as<uint32_t>(),
-                                  inst.lm_mat.as<uint32_t>(), inst.eps_mat.as<uint32_t>(), inst.n_eps, A.dev(), s),
+        hip_check(sp::launch_seed(S, in_seed.src, in_seed.dst, in_seed.lab, in_seed.m, in_seed.lm_ptr, in_seed.lm_mat,
+                                  in_seed.eps_mat, in_seed.n_eps, BA.dev(), s),
                   "seed");
-        read_ctl(&A);
+        read_ctl(&BA);
         if (!h_ctl[sp::kCtlHalt]) break;
+        if (fixed) throw too_small("the seeds");
         if (attempt > 64) throw Error(CFLR_ENOMEM, "seeding keeps overflowing");
         if (h_ctl[sp::kCtlBufOver]) {
             const uint64_t asked = h_ctl[sp::kCtlWords];
-            grow_buf(A, pool, std::max<uint64_t>(2 * A.cap, asked + asked / 2), s);
+            grow_buf(BA, A, std::max<uint64_t>(2 * BA.cap, asked + asked / 2), s);
         }
         const uint64_t resident = h_ctl[sp::kCtlNew] + h_ctl[sp::kCtlTomb];
         uint64_t want = pow2_at_least((resident + seeds_max + slack) * 10 / 7 + 1);
-        if (h_ctl[sp::kCtlHashFull]) want = std::max(want, 2 * slots);
-        if (want > slots) rehash_to(want);
+        if (h_ctl[sp::kCtlHashFull]) want = std::max(want, 2 * cur_slots);
+        if (want > cur_slots) rehash_to(want);
         clear_flags();
     }
     uint64_t pending = h_ctl[sp::kCtlNew];
-    inst.stats.seed_pairs = pending;
+    res.seed_pairs = pending;
     hash_keys += pending;
     tombs_resident += h_ctl[sp::kCtlTomb];
     hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlTomb, 1, 0, s), "fill");
 
-    Buf *in = &A, *out = &B;
-    uint32_t rounds = 0;
-    uint64_t new_total = 0, max_delta = 0;
-    double product_ms = 0;
-    uint64_t launches = 0;
+    Buf *in = &BA, *out = &BB;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (o.kernel_timing) {
+    struct EvFree {
+        hipEvent_t *a, *b;
+        ~EvFree() {
+            if (*a) (void)hipEventDestroy(*a);
+            if (*b) (void)hipEventDestroy(*b);
+        }
+    } ev_guard{&ev0, &ev1};
+    if (o.kernel_timing && !fixed) {
         hip_check(hipEventCreate(&ev0), "event");
         hip_check(hipEventCreate(&ev1), "event");
     }
     while (pending) {
-        if (o.max_rounds && rounds >= o.max_rounds) {
-            *timed_out = true;
+        if (o.max_rounds && res.rounds >= o.max_rounds) {
+            res.timed_out = true;
             break;
         }
-        rounds++;
+        res.rounds++;
         // room for this round: hash load, touched lists, the output buffer
         const uint64_t want_slots = hash_need(out->cap);
-        if (want_slots > slots) rehash_to(want_slots);
-        if (touched_cap < 2 * in->cap) {
-            touched_cap = 2 * in->cap;
-            d_touched = DevBuf(pool, touched_cap * 8);
-            d_moves = DevBuf(pool, std::max<uint64_t>(1, touched_cap / 4) * 24);
+        if (want_slots > cur_slots) {
+            if (fixed) throw too_small("the pairs");
+            rehash_to(want_slots);
         }
+        size_touched(in->cap);
         S.touched = d_touched.as<uint64_t>();
         S.touched_cap = touched_cap;
         S.moves = d_moves.as<uint64_t>();
@@ -353,9 +463,10 @@ void sparse_solve(cflr_ctx *ctx, const cflr_opts &o, Instance &inst, bool *timed
         while (h_ctl[sp::kCtlHalt]) {
             if (h_ctl[sp::kCtlTouchedOver]) throw Error(CFLR_EDEVICE, "internal: touched-list array too small");
             if (!h_ctl[sp::kCtlPoolOver]) throw Error(CFLR_EDEVICE, "internal: integration halted");
+            if (fixed) throw too_small("the adjacency lists");
             const uint64_t top = h_ctl[sp::kCtlPoolTop], need = top + h_ctl[sp::kCtlAlloc];
             const uint64_t ncap = std::max<uint64_t>(2 * pool_cap, need + need / 2);
-            DevBuf np(pool, ncap * 4);
+            Mem np = A.get(ncap * 4, "the list pool");
             hip_check(hipMemcpyAsync(np.ptr, d_pool.ptr, top * 4, hipMemcpyDeviceToDevice, s), "D2D");
             hip_check(hipStreamSynchronize(s), "sync");
             d_pool = std::move(np);
@@ -373,95 +484,144 @@ void sparse_solve(cflr_ctx *ctx, const cflr_opts &o, Instance &inst, bool *timed
             if (K.entry_cap < 2 * in->cap) {
                 if (2 * in->cap >= (1ull << 32)) throw Error(CFLR_ENOMEM, "more than 2^31 new pairs in one round");
                 K.entry_cap = K.heavy_cap = 2 * in->cap;
-                k_entry = DevBuf(pool, K.entry_cap * 8);
-                k_heavy = DevBuf(pool, K.heavy_cap * 4);
-                k_ework = DevBuf(pool, K.entry_cap * 4);
+                k_entry = A.get(K.entry_cap * 8, "the key sort");
+                k_heavy = A.get(K.heavy_cap * 4, "the key sort");
+                k_ework = A.get(K.entry_cap * 4, "the key sort");
                 K.entry = k_entry.as<uint64_t>();
                 K.heavy = k_heavy.as<uint32_t>();
                 K.ework = k_ework.as<uint32_t>();
             }
             hip_check(sp::launch_key_sort(S, in->dev(), K, s), "key sort");
         }
-        auto product = [&]() {
+        auto timed_product = [&]() {
+            if (ev0) hip_check(hipEventRecord(ev0, s), "event");
             if (grouped) hip_check(sp::launch_grouped_product(S, K, out->dev(), waves, s), "product");
             else hip_check(sp::launch_product(S, in->dev(), out->dev(), waves, s), "product");
+            if (ev1) hip_check(hipEventRecord(ev1, s), "event");
+            res.launches++;
+            read_ctl(out);
+            if (ev1) {
+                float ms = 0;
+                hip_check(hipEventElapsedTime(&ms, ev0, ev1), "event");
+                res.product_ms += ms;
+            }
         };
         hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlNew, 1, 0, s), "fill");
         hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlProducts, 1, 0, s), "fill");
         hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlHeavyProducts, 2, 0, s), "fill");
-        if (ev0) hip_check(hipEventRecord(ev0, s), "event");
-        product();
-        if (ev1) hip_check(hipEventRecord(ev1, s), "event");
-        launches++;
-        read_ctl(out);
-        if (ev1) {
-            float ms = 0;
-            hip_check(hipEventElapsedTime(&ms, ev0, ev1), "event");
-            product_ms += ms;
-        }
+        timed_product();
         for (int attempt = 0; h_ctl[sp::kCtlHalt]; attempt++) {
+            if (fixed) throw too_small("the pairs");
             if (attempt > 64) throw Error(CFLR_ENOMEM, "new-pair buffer or hash set keeps overflowing");
-            inst.stats.reruns++;
+            res.reruns++;
             if (h_ctl[sp::kCtlBufOver]) {
                 const uint64_t asked = h_ctl[sp::kCtlWords];
                 const uint64_t ncap = std::max<uint64_t>(2 * out->cap, asked + asked / 2);
                 if (ncap > (1ull << 34)) throw Error(CFLR_ENOMEM, "new-pair buffer beyond 2^34 pairs");
-                grow_buf(*out, pool, ncap, s);
+                grow_buf(*out, A, ncap, s);
             }
             // the table holds the pairs appended so far this round and the
             // tombstones of the halted run: room for what the re-run may add
             const uint64_t resident = hash_keys + h_ctl[sp::kCtlNew] + tombs_resident + h_ctl[sp::kCtlTomb];
             uint64_t want = pow2_at_least((resident + out->cap + slack) * 10 / 7 + 1);
-            if (h_ctl[sp::kCtlHashFull]) want = std::max(want, 2 * slots);
-            if (want > slots) rehash_to(want);  // drops the tombstones
+            if (h_ctl[sp::kCtlHashFull]) want = std::max(want, 2 * cur_slots);
+            if (want > cur_slots) rehash_to(want);  // drops the tombstones
             if (log)
-                std::fprintf(stderr, "[cflr] sparse: round %u re-run (buffer %llu, slots %llu)\n", rounds,
-                             (unsigned long long)out->cap, (unsigned long long)slots);
+                std::fprintf(stderr, "[cflr] sparse: round %u re-run (buffer %llu, slots %llu)\n", res.rounds,
+                             (unsigned long long)out->cap, (unsigned long long)cur_slots);
             clear_flags();
-            if (ev0) hip_check(hipEventRecord(ev0, s), "event");
-            product();
-            if (ev1) hip_check(hipEventRecord(ev1, s), "event");
-            launches++;
-            read_ctl(out);
-            if (ev1) {
-                float ms = 0;
-                hip_check(hipEventElapsedTime(&ms, ev0, ev1), "event");
-                product_ms += ms;
-            }
+            timed_product();
         }
         // kCtlNew counts every pair appended this round, over re-runs too
         const uint64_t fresh = h_ctl[sp::kCtlNew];
-        new_total += fresh;
+        res.new_pairs += fresh;
         hash_keys += fresh;
         tombs_resident += h_ctl[sp::kCtlTomb];
         hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlTomb, 1, 0, s), "fill");
-        max_delta = std::max(max_delta, fresh);
+        res.max_delta = std::max(res.max_delta, fresh);
         if (log)
             std::fprintf(stderr,
                          "[cflr] sparse round %u: in %llu new %llu products %llu heavy items %llu products %llu "
                          "candidates %llu pool %llu/%llu slots %llu\n",
-                         rounds, (unsigned long long)pending, (unsigned long long)fresh,
+                         res.rounds, (unsigned long long)pending, (unsigned long long)fresh,
                          (unsigned long long)h_ctl[sp::kCtlProducts], (unsigned long long)h_ctl[sp::kCtlHeavy],
                          (unsigned long long)h_ctl[sp::kCtlHeavyProducts], (unsigned long long)h_ctl[sp::kCtlHeavyCand],
                          (unsigned long long)h_ctl[sp::kCtlPoolTop], (unsigned long long)pool_cap,
-                         (unsigned long long)slots);
+                         (unsigned long long)cur_slots);
         pending = fresh;
         std::swap(in, out);
     }
-    if (!pending && !*timed_out) rounds++;  // the round that derived nothing (counted as the dense engine does)
-    if (ev0) (void)hipEventDestroy(ev0);
-    if (ev1) (void)hipEventDestroy(ev1);
-    inst.rounds = rounds;
-    inst.done = !*timed_out;
-    inst.stats.rounds = rounds;
-    inst.stats.new_pairs = new_total;
-    inst.stats.max_delta = max_delta;
-    inst.stats.product_ms = product_ms;
-    inst.stats.product_launches = launches;
-    ctx->sparse_delta_hint = std::max({ctx->sparse_delta_hint, A.cap, B.cap});
-    ctx->sparse_pool_hint = std::max(ctx->sparse_pool_hint, pool_cap);
-    ctx->sparse_slots_hint = std::max(ctx->sparse_slots_hint, slots);
-    store->pool = std::move(d_pool);
+    if (!pending && !res.timed_out) res.rounds++;  // the round that derived nothing (counted as the dense engine does)
+    if (!fixed) {
+        ctx->sparse_delta_hint = std::max({ctx->sparse_delta_hint, BA.cap, BB.cap});
+        ctx->sparse_pool_hint = std::max(ctx->sparse_pool_hint, pool_cap);
+        ctx->sparse_slots_hint = std::max(ctx->sparse_slots_hint, cur_slots);
+    }
+    res.pool = std::move(d_pool);
+    if (fixed) {
+        hip_check(hipStreamSynchronize(s), "sync");
+        A.release_to(fixed_mark);  // the hash set, buffers and queues are free again (readout scratch)
+    }
+}
+
+// Graph label -> the matrices x with x -> label (after lowering), as
+// offsets and a flat list; also the most matrices one label seeds.
+void label_tables(const Lowered &low, const std::vector<std::string> &label_names, std::vector<uint32_t> *ptr,
+                  std::vector<uint32_t> *mats, uint32_t *max_per_label) {
+    std::map<std::string, uint32_t> term_id;
+    for (uint32_t t = 0; t < low.terminals.size(); t++) term_id[low.terminals[t]] = t;
+    std::vector<std::vector<uint32_t>> by_term(low.terminals.size());
+    for (auto &tm : low.term) by_term[tm.first].push_back(tm.second);
+    const uint32_t L = (uint32_t)label_names.size();
+    ptr->assign(L + 1, 0);
+    mats->clear();
+    *max_per_label = 0;
+    for (uint32_t l = 0; l < L; l++) {
+        auto it = term_id.find(label_names[l]);
+        if (it != term_id.end())
+            for (uint32_t x : by_term[it->second]) mats->push_back(x);
+        (*ptr)[l + 1] = (uint32_t)mats->size();
+        *max_per_label = std::max(*max_per_label, (*ptr)[l + 1] - (*ptr)[l]);
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- solve
+
+void sparse_solve(cflr_ctx *ctx, const cflr_opts &o, Instance &inst, bool *timed_out) {
+    Alloc A(ctx->pool.get());
+    SeedInput in;
+    in.m = inst.graph->m;
+    in.src = inst.graph->src.as<uint32_t>();
+    in.dst = inst.graph->dst.as<uint32_t>();
+    in.lab = inst.graph->lab.as<uint32_t>();
+    in.lm_ptr = inst.lm_ptr.as<uint32_t>();
+    in.lm_mat = inst.lm_mat.as<uint32_t>();
+    in.eps_mat = inst.eps_mat.as<uint32_t>();
+    in.n_eps = inst.n_eps;
+    in.max_seeds = inst.max_seeds;
+    CoreOut res;
+    sparse_core(ctx, ctx->stream, o, inst.low, inst.n, in, A, res);
+    *timed_out = res.timed_out;
+    auto store = std::make_shared<SparseStore>();
+    store->hold = CtxRef(ctx);
+    store->ctx = ctx;
+    store->n = inst.n;
+    store->nlayouts = res.plan.nlayouts;
+    store->row_layout.resize(inst.low.nmat());
+    for (uint32_t x = 0; x < inst.low.nmat(); x++) store->row_layout[x] = res.plan.mats[x].row_layout;
+    store->dir = std::move(res.dir.buf);
+    store->pool = std::move(res.pool.buf);
+    inst.rounds = res.rounds;
+    inst.done = !res.timed_out;
+    inst.stats.rounds = res.rounds;
+    inst.stats.reruns = res.reruns;
+    inst.stats.seed_pairs = res.seed_pairs;
+    inst.stats.new_pairs = res.new_pairs;
+    inst.stats.max_delta = res.max_delta;
+    inst.stats.product_ms = res.product_ms;
+    inst.stats.product_launches = res.launches;
     inst.stats.device_bytes = store->dir.bytes + store->pool.bytes;
     inst.sp = store;
 }
@@ -515,6 +675,123 @@ void sparse_copy(Instance &inst, uint32_t nt, uint32_t *src, uint32_t *dst, uint
     hip_check(hipMemcpyAsync(src, dsrc.ptr, count * 4, hipMemcpyDeviceToHost, s), "D2H");
     hip_check(hipMemcpyAsync(dst, ddst.ptr, count * 4, hipMemcpyDeviceToHost, s), "D2H");
     hip_check(hipStreamSynchronize(s), "sync");
+}
+
+// ------------------------------------------------------- no-alloc entry point
+
+// The fixed device region of cflr_solve_noalloc.  In host code `scratch` is
+// a stand-in for the symbol, not a device address: every use goes through
+// the address hipGetSymbolAddress gives for the current device.
+constexpr uint64_t kScratchBytes = CFLR_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;  // device -> its copy of `scratch`
+
+// With the device current: the address of its `scratch`, looked up once.
+void *scratch_address(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) return it->second;
+    void *p = nullptr;
+    hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p) throw Error(CFLR_EDEVICE, "hipGetSymbolAddress(scratch) returned null");
+    g_scratch_ptr[device] = p;
+    return p;
+}
+
+}  // namespace
+
+void sparse_solve_noalloc(cflr_ctx *ctx, const Lowered &low, uint32_t n, uint64_t m, const uint32_t *src,
+                          const uint32_t *dst, const uint32_t *label, const std::vector<std::string> &label_names,
+                          const cflr_opts &o, uint32_t *out_src, uint32_t *out_dst, uint64_t capacity,
+                          uint64_t *counts, cflr_stats *stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = ctx->stream;
+    Alloc A(scratch_address(ctx->device), kScratchBytes);
+    // the seeding tables, and a check of the edges on the device
+    std::vector<uint32_t> ptr, mats;
+    uint32_t max_per_label = 0;
+    label_tables(low, label_names, &ptr, &mats, &max_per_label);
+    Mem lm_ptr = upload(A, ptr, s, "the label table");
+    Mem lm_mat = upload(A, mats, s, "the label table");
+    Mem eps_mat = upload(A, low.eps, s, "the eps table");
+    if (m) {
+        Mem bad = A.get(8, "the edge check");
+        hip_check(sp::launch_fill_u64(bad.as<unsigned long long>(), 1, 0, s), "fill");
+        hip_check(sp::launch_check_edges(src, dst, label, m, n, (uint32_t)label_names.size(),
+                                         bad.as<unsigned long long>(), s),
+                  "edge check");
+        unsigned long long h = 0;
+        copy_sync(&h, bad.ptr, 8, hipMemcpyDeviceToHost, s);
+        if (h) throw Error(CFLR_EINVAL, "an edge has a vertex >= n or a label >= n_labels");
+    }
+    SeedInput in;
+    in.m = m;
+    in.src = src;
+    in.dst = dst;
+    in.lab = label;
+    in.lm_ptr = lm_ptr.as<uint32_t>();
+    in.lm_mat = lm_mat.as<uint32_t>();
+    in.eps_mat = eps_mat.as<uint32_t>();
+    in.n_eps = (uint32_t)low.eps.size();
+    in.max_seeds = m * max_per_label + (uint64_t)n * in.n_eps;
+    CoreOut res;
+    sparse_core(ctx, s, o, low, n, in, A, res);
+    // readout into the caller's arrays, each non-terminal's pairs sorted by
+    // (i, j), one after another in first-appearance order; the scratch
+    // after the lists holds the counts, offsets and sort bit sets
+    const uint32_t U = (uint32_t)low.user_names.size();
+    Mem tot = A.get(8ull * std::max<uint32_t>(1, U), "the readout");
+    hip_check(sp::launch_fill_u64(tot.as<unsigned long long>(), std::max<uint32_t>(1, U), 0, s), "fill");
+    const sp::Dir *dir = res.dir.as<sp::Dir>();
+    for (uint32_t x = 0; x < U; x++)
+        hip_check(sp::launch_layout_count(dir + (uint64_t)res.plan.mats[x].row_layout * n, n,
+                                          tot.as<unsigned long long>() + x, s),
+                  "count");
+    std::vector<unsigned long long> h(std::max<uint32_t>(1, U));
+    copy_sync(h.data(), tot.ptr, 8ull * std::max<uint32_t>(1, U), hipMemcpyDeviceToHost, s);
+    uint64_t total = 0;
+    for (uint32_t x = 0; x < U; x++) {
+        counts[x] = h[x];
+        total += h[x];
+    }
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        stats->rounds = res.rounds;
+        stats->seed_pairs = res.seed_pairs;
+        stats->new_pairs = res.new_pairs;
+        stats->total_pairs = total;
+        stats->max_delta = res.max_delta;
+        stats->product_launches = res.launches;
+        stats->device_bytes = kScratchBytes;
+        stats->storage = CFLR_STORAGE_SPARSE;
+    }
+    if (res.timed_out) throw Error(CFLR_ETIMEOUT, "round limit reached before the fixpoint (nothing written)");
+    if (total > capacity)
+        throw Error(CFLR_EINVAL, "capacity " + std::to_string(capacity) + " is smaller than the " +
+                                     std::to_string(total) + " pairs (counts written, pairs not)");
+    if (total && (!out_src || !out_dst)) throw Error(CFLR_EINVAL, "null output array");
+    const uint32_t sort_grid = std::max<uint32_t>(1, std::min<uint32_t>(ctx->num_cu, std::max<uint32_t>(1, n)));
+    const uint64_t nw = ((uint64_t)n + 63) / 64;
+    Mem off = A.get((uint64_t)std::max<uint32_t>(1, n) * 8, "the readout");
+    Mem bm = A.get((uint64_t)sort_grid * std::max<uint64_t>(1, nw) * 8, "the readout");
+    hip_check(sp::launch_fill_u64(bm.as<unsigned long long>(), (uint64_t)sort_grid * std::max<uint64_t>(1, nw), 0, s),
+              "fill");
+    uint64_t at = 0;
+    for (uint32_t x = 0; x < U; x++) {
+        if (h[x])
+            hip_check(sp::launch_layout_write(dir + (uint64_t)res.plan.mats[x].row_layout * n, res.pool.as<uint32_t>(),
+                                              n, off.as<uint64_t>(), bm.as<uint64_t>(), sort_grid, out_src + at,
+                                              out_dst + at, s),
+                      "readout");
+        at += h[x];
+    }
+    hip_check(hipStreamSynchronize(s), "sync");
+    if (stats)
+        stats->fixpoint_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
 }  // namespace cflr

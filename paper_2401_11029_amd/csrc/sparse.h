@@ -192,6 +192,9 @@ constexpr uint64_t kHeavyMaxLds = 64 * 1024;
 // Re-insert every key of `old_tab` (tombstones dropped) into S.hash (empty).
 hipError_t launch_rehash(const State &S, const unsigned long long *old_tab, uint64_t old_slots, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long v, hipStream_t s);
+// *bad |= 1 if some edge has src or dst >= n or label >= n_labels.
+hipError_t launch_check_edges(const uint32_t *src, const uint32_t *dst, const uint32_t *lab, uint64_t m, uint32_t n,
+                              uint32_t n_labels, unsigned long long *bad, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *a, uint64_t n, uint32_t v, hipStream_t s);
 // Readout of one row layout: per-row counts (sum into *total), then the
 // pairs sorted by (i, j) at the exclusive offsets of the counts.

@@ -925,6 +925,12 @@ __global__ __launch_bounds__(256) void rehash_kernel(State S, const unsigned lon
     }
 }
 
+__global__ void check_edges_kernel(const uint32_t *src, const uint32_t *dst, const uint32_t *lab, uint64_t m,
+                                   uint32_t n, uint32_t n_labels, unsigned long long *bad) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
+        if (src[e] >= n || dst[e] >= n || lab[e] >= n_labels) atomicOr(bad, 1ull);
+}
+
 __global__ void fill_u64_kernel(unsigned long long *a, uint64_t n, unsigned long long v) {
     for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n; x += (uint64_t)gridDim.x * blockDim.x)
         a[x] = v;
@@ -1157,6 +1163,14 @@ hipError_t launch_rehash(const State &S, const unsigned long long *old_tab, uint
 hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long v, hipStream_t s) {
     if (!n) return hipSuccess;
     fill_u64_kernel<<<grid_for(n, 256, 65536), 256, 0, s>>>(a, n, v);
+    SP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_check_edges(const uint32_t *src, const uint32_t *dst, const uint32_t *lab, uint64_t m, uint32_t n,
+                              uint32_t n_labels, unsigned long long *bad, hipStream_t s) {
+    if (!m) return hipSuccess;
+    check_edges_kernel<<<grid_for(m, 256, 8192), 256, 0, s>>>(src, dst, lab, m, n, n_labels, bad);
     SP_LAUNCH_CHECK();
     return hipSuccess;
 }
