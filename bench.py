@@ -1,23 +1,34 @@
 """Benchmark: CFL-reachability fixpoint on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode single|batch|serve]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode single|batch|serve|...]
 
-A step is one whole solve of the memory-alias workload: the binarised
-alias grammar (Fig. 5a of the paper, 9 non-terminals, 13 matrices after
-lowering) on a 50,000-vertex power-law graph (alpha 2.1, 50,000 forward a/d
-edges plus their reversed a_bar/d_bar edges, seed 1).  The graph is resident
-in device memory before timing starts; a step runs seeding, every round and
-the convergence test.  value = derived pairs per second over the K timed
-steps (pairs in the result minus pairs set by seeding).
+A step is one whole solve of the largest single-solve workload: the
+field-sensitive points-to grammar (Fig. 4b of the paper at 64 fields, 386
+non-terminals, 644 matrices after lowering) on a 200,000-vertex power-law
+graph (alpha 2.1, 300,000 forward edges alloc/assign/load_f/store_f plus
+their reversed edges, fields Zipf(1.1), seed 2).  Its dense bit matrices
+would need terabytes, so the library solves it on sparse storage.  The
+graph is resident in device memory before timing starts; a step runs
+seeding, every round and the convergence test.  value = derived pairs per
+second over the K timed steps: pairs of the grammar's non-terminals minus
+the pairs seeding puts there.
 
 The JSON line also carries:
-  roofline      the product kernel (the dominant kernel) against HBM: the
-                algorithmic bytes it must move per launch (counted on the
-                device in an untimed accounting solve) over its average
-                launch time (HIP events on the library's stream, timed
-                steps);
-  cpu_baseline  the CPU oracle on a bounded sample of the same workload (the
-                same generator at 6,000 vertices), one host thread.
+  roofline      the dominant kernel of the sparse engine's product (the
+                light-bucket or the heavy-bucket kernel, whichever takes
+                longer) against HBM: its algorithmic bytes per launch
+                (counted on the device in an untimed accounting solve: 8 per
+                sorted new pair, 4 per entry of each distinct partner list
+                and output row read in a round, 16 per pair derived) over
+                its average launch time (HIP events on the library's stream
+                in the timed steps); traffic from the committed rocprofv3
+                FETCH_SIZE / WRITE_SIZE summary of the same kernel;
+  cpu_baseline  the CPU oracle, pinned to one host core, on a bounded sample
+                of the same workload (the same generator at 24,000
+                vertices), with the oracle's full-size time beside it;
+  other_configs the memory-alias configuration (Fig. 5a, 50,000 vertices,
+                dense storage), timed the same way, its pairs counted over
+                Fig. 5a's own non-terminals (M, V, V1, V2, V3).
 
 --mode batch reports the batched form (256 alias graphs in one call vs one
 plain solve after another); --mode serve reports the served form (Poisson
@@ -35,6 +46,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -42,8 +54,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE_PMC = os.path.join(ROOT, "profiles", "product_kernel_alias50k_pmc.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2401_11029_amd", "csrc", "kernels.hip")
+HEADLINE = "pointsto_200k"
+PROFILE_PMC = os.path.join(ROOT, "profiles", "sparse_product_pointsto200k_pmc.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2401_11029_amd", "csrc", "sparse_kernels.hip")
+GOLDEN_FULL = os.path.join(ROOT, "tests", "golden", "pointsto_200k.json")
+CPU_SAMPLE_N = 40000
+# Fig. 5a's own non-terminals in the binarised text (Y1..Y4 are its helpers)
+ALIAS_FIG5A_NTS = ["M", "V", "V1", "V2", "V3"]
 
 
 def log(*a):
@@ -55,8 +72,8 @@ def kernel_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per product launch from the committed rocprofv3 --pmc
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
     summary, or None when the kernel source changed since it was taken."""
     try:
         with open(PROFILE_PMC) as f:
@@ -65,7 +82,7 @@ def measured_traffic():
         return None
     if p.get("kernel_source_sha256_16") != kernel_hash():
         return None
-    return p.get("hbm_bytes_per_launch")
+    return p.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
 
 
 def host_cpu():
@@ -79,80 +96,149 @@ def host_cpu():
     return "unknown CPU"
 
 
-def cpu_baseline():
-    """The oracle, as it is, on the same generator at 6,000 vertices."""
-    import oracle
-    import workloads
-    n = 6000
-    text, g = workloads.config("alias_50k", n=n)
-    r = oracle.solve(text, g, pairs=False, digest=True)
-    derived = sum(r.count.values()) - seeded_user_pairs(text, g)
-    return {"value": derived / r.seconds, "unit": "pairs/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"alias generator at n={n} (seed 1), one full solve: "
-                      f"{derived} derived pairs in {r.seconds:.1f} s on one host thread "
-                      f"({host_cpu()}, {os.cpu_count()} logical CPUs visible)"}
-
-
-def seeded_user_pairs(text, g):
+def seeded_user_pairs(text, g, names=None):
     """Pairs that seeding puts into the grammar's non-terminals directly:
-    (i, i) for x -> eps and the edges of t for x -> t."""
+    (i, i) for x -> eps and the edges of t for x -> t (restricted to
+    `names` when given)."""
     from oracle.textgrammar import TextGrammar
     tg = TextGrammar(text)
-    count = len(set(tg.eps)) * g.n
-    names = g.label_names
+    keep = (lambda x: True) if names is None else (lambda x: x in names)
+    count = len({x for x in tg.eps if keep(x)}) * g.n
     for x, y in tg.unit:
-        if y in tg.terminals:
-            lab = names.index(y) if y in names else -1
+        if y in tg.terminals and keep(x):
+            lab = g.label_names.index(y) if y in g.label_names else -1
             sel = g.label == lab
             count += len(set(zip(g.src[sel].tolist(), g.dst[sel].tolist())))
     return count
+
+
+def cpu_baseline():
+    """The oracle, as it is, pinned to one host core, on the same generator
+    at CPU_SAMPLE_N vertices; the full-size oracle time from the stored
+    golden beside it."""
+    import oracle
+    import workloads
+    text, g = workloads.config(HEADLINE, n=CPU_SAMPLE_N)
+    import shutil
+    cpus = sorted(os.sched_getaffinity(0))
+    cpu = cpus[0] if cpus and shutil.which("taskset") else None
+    r = oracle.solve(text, g, pairs=False, digest=True, cpu=cpu)
+    derived = sum(r.count.values()) - seeded_user_pairs(text, g)
+    out = {"value": derived / r.seconds, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+           "sample": f"points-to generator at n={CPU_SAMPLE_N} (seed 2), one full solve: "
+                     f"{derived} derived pairs in {r.seconds:.1f} s, "
+                     + (f"pinned to host core {cpu} " if cpu is not None else "one thread, not pinned ")
+                     + f"({host_cpu()}, {len(cpus)} cores available)"}
+    try:
+        with open(GOLDEN_FULL) as f:
+            gold = json.load(f)
+        _, gfull = workloads.config(HEADLINE)
+        full_derived = gold["total"] - seeded_user_pairs(text, gfull)
+        out["full_size"] = {"pairs_per_s": full_derived / gold["oracle_seconds"],
+                            "seconds": gold["oracle_seconds"], "derived_pairs": full_derived,
+                            "host": "the build container (one core of an x86_64 host), "
+                                    "from tests/golden/pointsto_200k.json"}
+    except (OSError, ValueError, KeyError):
+        pass
+    return out
+
+
+def time_solves(cflr, ctx, gr, graph, warmup, steps, tag):
+    import torch
+    for w in range(warmup):
+        r = cflr.solve(ctx, gr, graph)
+        log(f"{tag} warmup {w}: {r.stats()['fixpoint_ms']:.1f} ms")
+        r.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(steps):
+        r = cflr.solve(ctx, gr, graph, kernel_timing=1)
+        stats.append(r.stats())
+        counts = r.counts() if k == steps - 1 else None
+        r.close()
+        log(f"{tag} step {k}: {stats[-1]['fixpoint_ms']:.1f} ms, {stats[-1]['rounds']} rounds, "
+            f"{stats[-1]['reruns']} re-runs")
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, stats, counts
+
+
+def fix_summary(stats):
+    fix = sorted(s["fixpoint_ms"] for s in stats)
+    mean = sum(fix) / len(fix)
+    std = (sum((x - mean) ** 2 for x in fix) / max(1, len(fix) - 1)) ** 0.5
+    return {"fixpoint_ms_mean": mean, "fixpoint_ms_median": fix[len(fix) // 2], "fixpoint_ms_std": std}
+
+
+def alias_context(cflr, args):
+    """The memory-alias configuration, timed as the headline (fewer steps)."""
+    import workloads
+    text, g = workloads.config("alias_50k")
+    ctx = cflr.Context(0)
+    gr = cflr.Grammar(text)
+    graph = cflr.Graph.from_workload(ctx, g)
+    steps = max(1, min(3, args.steps))
+    secs, stats, counts = time_solves(cflr, ctx, gr, graph, max(1, args.warmup), steps, "alias_50k")
+    own = sum(counts[x] for x in ALIAS_FIG5A_NTS) - seeded_user_pairs(text, g, ALIAS_FIG5A_NTS)
+    out = {"workload": "alias_50k: memory-alias grammar (Fig. 5a, binarised in the text with helpers "
+                       "Y1..Y4) on a 50,000-vertex power-law graph (alpha 2.1, 100,000 stored edges, seed 1)",
+           "storage": "dense" if stats[-1]["storage"] == 1 else "sparse",
+           "rounds": stats[-1]["rounds"],
+           "derived_pairs_fig5a_nts": own,
+           "derived_pairs_per_s_fig5a_nts": own * steps / secs,
+           "derived_pairs_all_nts_incl_helpers": stats[-1]["new_pairs"],
+           "ms_per_step": secs * 1e3 / steps}
+    out.update(fix_summary(stats))
+    del graph, gr
+    ctx.close()
+    return out
 
 
 def single(args):
     import torch
     import paper_2401_11029_amd as cflr
     import workloads
-    text, g = workloads.config("alias_50k")
-    log(f"workload alias_50k: n={g.n} edges={g.m}")
+    text, g = workloads.config(HEADLINE)
+    log(f"workload {HEADLINE}: n={g.n} edges={g.m}")
     ctx = cflr.Context(0)
     gr = cflr.Grammar(text)
     graph = cflr.Graph.from_workload(ctx, g)
     torch.cuda.synchronize()
     for w in range(args.warmup):
         r = cflr.solve(ctx, gr, graph)
-        log(f"warmup {w}: {r.stats()['fixpoint_ms']:.1f} ms")
+        log(f"warmup {w}: {r.stats()['fixpoint_ms']:.1f} ms, {r.stats()['reruns']} re-runs")
         r.close()
-    # untimed accounting solve: algorithmic bytes of the product kernel
+    # untimed accounting solve: algorithmic bytes of the product's kernels
     r = cflr.solve(ctx, gr, graph, count_traffic=1)
     acct = r.stats()
     r.close()
-    bytes_per_launch = acct["algo_bytes"] / max(1, acct["product_launches"])
-    log(f"accounting: {acct['algo_bytes'] / 1e9:.1f} GB over {acct['product_launches']} launches")
-    # timed steps
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for k in range(args.steps):
-        r = cflr.solve(ctx, gr, graph, kernel_timing=1)
-        stats.append(r.stats())
-        r.close()
-        log(f"step {k}: {stats[-1]['fixpoint_ms']:.1f} ms, {stats[-1]['rounds']} rounds")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    secs = t1 - t0
-    # every pair a round derives lies in a user non-terminal (helper wrappers
-    # only ever hold seeded edges), so new_pairs is the derived-pair count
-    derived = sum(s["new_pairs"] for s in stats)
-    value = derived / secs
-    fix = sorted(s["fixpoint_ms"] for s in stats)
-    fix_mean = sum(fix) / len(fix)
-    fix_std = (sum((x - fix_mean) ** 2 for x in fix) / max(1, len(fix) - 1)) ** 0.5
-    launches = sum(s["product_launches"] for s in stats)
-    prod_ms = sum(s["product_ms"] for s in stats)
-    avg_launch_s = prod_ms / 1e3 / max(1, launches)
-    achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
-    traffic = measured_traffic()
+    nl = max(1, acct["heavy_launches"])
+    log(f"accounting: heavy {acct['heavy_algo_bytes'] / 1e9:.1f} GB, light {acct['light_algo_bytes'] / 1e9:.1f} GB "
+        f"over {nl} launches each")
+    secs, stats, counts = time_solves(cflr, ctx, gr, graph, 0, args.steps, HEADLINE)
+    derived = stats[-1]["total_pairs"] - seeded_user_pairs(text, g)
+    value = derived * args.steps / secs
+    launches = max(1, sum(s["heavy_launches"] for s in stats))
+    kern = {}
+    for name, key in (("heavy_kernel", "heavy"), ("light_kernel", "light")):
+        ms = sum(s[f"{key}_ms"] for s in stats)
+        per_launch_bytes = acct[f"{key}_algo_bytes"] / nl
+        avg_s = ms / 1e3 / launches
+        kern[name] = {"algo_bytes_per_launch": per_launch_bytes, "avg_launch_ms": avg_s * 1e3,
+                      "achieved": per_launch_bytes / avg_s / 1e9 if avg_s > 0 else 0.0,
+                      "share_of_fixpoint": ms / max(1e-9, sum(s["fixpoint_ms"] for s in stats))}
+    dom = max(kern, key=lambda k: kern[k]["avg_launch_ms"])
+    d = kern[dom]
+    traffic = measured_traffic(dom)
+    cfg = {"workload": "pointsto_200k: field-sensitive points-to grammar (Fig. 4b, 64 fields, "
+                       "386 non-terminals) on a 200,000-vertex power-law graph (alpha 2.1, 600,000 "
+                       "stored edges alloc/assign/load_f/store_f and reversed, fields Zipf(1.1), seed 2)",
+           "vertices": g.n, "edges": g.m,
+           "storage": "sparse" if stats[-1]["storage"] == 2 else "dense",
+           "pairs": stats[-1]["total_pairs"], "derived_pairs": derived,
+           "rounds": stats[-1]["rounds"],
+           "product_ms_mean": sum(s["product_ms"] for s in stats) / len(stats)}
+    cfg.update(fix_summary(stats))
     out = {
         "metric": "CFL-r fixpoint derived pairs/s (single solve)",
         "value": value,
@@ -164,25 +250,23 @@ def single(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64",
+        "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "alias_50k: binarised memory-alias grammar (Fig. 5a) "
-                               "on a 50,000-vertex power-law graph (alpha 2.1, "
-                               "100,000 stored edges a/d/a_bar/d_bar, seed 1)",
-                   "vertices": g.n, "edges": g.m,
-                   "pairs": stats[-1]["total_pairs"],
-                   "rounds": stats[-1]["rounds"],
-                   "fixpoint_ms_mean": fix_mean,
-                   "fixpoint_ms_median": fix[len(fix) // 2],
-                   "fixpoint_ms_std": fix_std},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        "config": cfg,
+        "roofline": {"bound": "hbm", "achieved": d["achieved"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": d["achieved"] / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "amplification": (traffic / bytes_per_launch) if traffic and bytes_per_launch else None,
-                     "kernel": "product_kernel",
-                     "algo_bytes_per_launch": bytes_per_launch,
-                     "avg_launch_ms": avg_launch_s * 1e3},
+                     "amplification": (traffic / d["algo_bytes_per_launch"])
+                     if traffic and d["algo_bytes_per_launch"] else None,
+                     "kernel": dom,
+                     "algo_bytes_per_launch": d["algo_bytes_per_launch"],
+                     "avg_launch_ms": d["avg_launch_ms"],
+                     "kernels": kern},
     }
+    if not args.no_other:
+        del graph, gr
+        ctx.close()
+        out["other_configs"] = {"alias_50k": alias_context(cflr, args)}
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline()
@@ -443,6 +527,7 @@ def main():
     ap.add_argument("--serve-per-grammar", type=int, default=30)
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[0.5, 1.0, 2.0, 4.0, 8.0])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-other", action="store_true", help="skip the memory-alias context line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB int32 read+write kernel "
                          "(reference for the HBM byte counters)")

@@ -114,6 +114,17 @@ typedef struct cflr_stats {
     uint64_t device_bytes;     /* device memory held for this solve */
     uint64_t max_delta;        /* largest number of new pairs in one round */
     uint32_t storage;          /* engine that solved: CFLR_STORAGE_DENSE or _SPARSE */
+    /* sparse storage, key-sorted product: its two kernels, for the heavy
+       buckets (one workgroup and an LDS bit set per run of a bucket) and
+       the light ones (a hash probe per product); one launch each a round */
+    double heavy_ms;           /* heavy kernel time (kernel_timing) */
+    uint64_t heavy_launches;   /* launches of each of the two */
+    uint64_t heavy_algo_bytes; /* algorithmic bytes (count_traffic): 8 per
+                                  sorted new pair, 4 per entry of each
+                                  distinct partner list and output row read
+                                  in a round, 16 per pair derived */
+    double light_ms;           /* light kernel time (kernel_timing) */
+    uint64_t light_algo_bytes; /* its algorithmic bytes, as heavy_algo_bytes */
 } cflr_stats;
 
 void cflr_opts_default(cflr_opts *opts);

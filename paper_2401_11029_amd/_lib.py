@@ -37,7 +37,12 @@ class Stats(C.Structure):
                 ("algo_bytes", C.c_uint64),
                 ("device_bytes", C.c_uint64),
                 ("max_delta", C.c_uint64),
-                ("storage", C.c_uint32)]
+                ("storage", C.c_uint32),
+                ("heavy_ms", C.c_double),
+                ("heavy_launches", C.c_uint64),
+                ("heavy_algo_bytes", C.c_uint64),
+                ("light_ms", C.c_double),
+                ("light_algo_bytes", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

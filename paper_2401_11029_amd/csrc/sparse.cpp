@@ -231,6 +231,9 @@ struct CoreOut {
     uint32_t rounds = 0, reruns = 0;
     uint64_t seed_pairs = 0, new_pairs = 0, max_delta = 0, launches = 0;
     double product_ms = 0;
+    // the heavy-bucket kernel of the grouped product (timing and accounting)
+    double heavy_ms = 0, light_ms = 0;
+    uint64_t heavy_launches = 0, heavy_bytes = 0, light_bytes = 0;
     bool timed_out = false;
 };
 
@@ -354,7 +357,7 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
     if (const char *h = std::getenv("CFLR_SPARSE_HEAVY")) K.threshold = std::max<uint64_t>(1, std::strtoull(h, nullptr, 10));
     K.big_entry = 0x7FFFFFFFu;
     if (const char *h = std::getenv("CFLR_SPARSE_BIG")) K.big_entry = (uint32_t)std::strtoul(h, nullptr, 10);
-    Mem k_start, k_work, k_bsum, k_entry, k_heavy, k_ework;
+    Mem k_start, k_work, k_bsum, k_entry, k_heavy, k_ework, k_touch, k_acct;
     if (grouped) {
         k_start = A.get((K.nb + 1) * 4, "the key sort");
         k_work = A.get(K.nb * 8, "the key sort");
@@ -362,6 +365,13 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         K.start = k_start.as<uint32_t>();
         K.work = k_work.as<unsigned long long>();
         K.bsum = k_bsum.as<uint32_t>();
+        if (o.count_traffic) {
+            k_touch = A.get((cells + 31) / 32 * 4, "the traffic accounting");
+            k_acct = A.get(16, "the traffic accounting");
+            K.touch = k_touch.as<uint32_t>();
+            K.acct = k_acct.as<unsigned long long>();
+            K.acct_light = K.acct + 1;
+        }
     }
 
     S.n = n;
@@ -425,16 +435,17 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
     hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlTomb, 1, 0, s), "fill");
 
     Buf *in = &BA, *out = &BB;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, evh = nullptr, ev1 = nullptr;
     struct EvFree {
-        hipEvent_t *a, *b;
+        hipEvent_t *e[3];
         ~EvFree() {
-            if (*a) (void)hipEventDestroy(*a);
-            if (*b) (void)hipEventDestroy(*b);
+            for (auto p : e)
+                if (*p) (void)hipEventDestroy(*p);
         }
-    } ev_guard{&ev0, &ev1};
+    } ev_guard{{&ev0, &evh, &ev1}};
     if (o.kernel_timing && !fixed) {
         hip_check(hipEventCreate(&ev0), "event");
+        hip_check(hipEventCreate(&evh), "event");
         hip_check(hipEventCreate(&ev1), "event");
     }
     while (pending) {
@@ -494,9 +505,19 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
             hip_check(sp::launch_key_sort(S, in->dev(), K, s), "key sort");
         }
         auto timed_product = [&]() {
+            if (K.acct) {
+                hip_check(sp::launch_fill_u32(K.touch, (cells + 31) / 32, 0, s), "fill");
+                hip_check(sp::launch_fill_u64(K.acct, 2, 0, s), "fill");
+            }
             if (ev0) hip_check(hipEventRecord(ev0, s), "event");
-            if (grouped) hip_check(sp::launch_grouped_product(S, K, out->dev(), waves, s), "product");
-            else hip_check(sp::launch_product(S, in->dev(), out->dev(), waves, s), "product");
+            if (grouped) {
+                hip_check(sp::launch_heavy(S, K, out->dev(), waves, s), "product");
+                if (evh) hip_check(hipEventRecord(evh, s), "event");
+                hip_check(sp::launch_light(S, K, out->dev(), waves, s), "product");
+                res.heavy_launches++;
+            } else {
+                hip_check(sp::launch_product(S, in->dev(), out->dev(), waves, s), "product");
+            }
             if (ev1) hip_check(hipEventRecord(ev1, s), "event");
             res.launches++;
             read_ctl(out);
@@ -504,6 +525,18 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
                 float ms = 0;
                 hip_check(hipEventElapsedTime(&ms, ev0, ev1), "event");
                 res.product_ms += ms;
+                if (grouped) {
+                    float hm = 0;
+                    hip_check(hipEventElapsedTime(&hm, ev0, evh), "event");
+                    res.heavy_ms += hm;
+                    res.light_ms += ms - hm;
+                }
+            }
+            if (K.acct) {
+                unsigned long long b[2] = {0, 0};
+                copy_sync(b, K.acct, 16, hipMemcpyDeviceToHost, s);
+                res.heavy_bytes += b[0];
+                res.light_bytes += b[1];
             }
         };
         hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlNew, 1, 0, s), "fill");
@@ -622,6 +655,11 @@ void sparse_solve(cflr_ctx *ctx, const cflr_opts &o, Instance &inst, bool *timed
     inst.stats.max_delta = res.max_delta;
     inst.stats.product_ms = res.product_ms;
     inst.stats.product_launches = res.launches;
+    inst.stats.heavy_ms = res.heavy_ms;
+    inst.stats.heavy_launches = res.heavy_launches;
+    inst.stats.heavy_algo_bytes = res.heavy_bytes;
+    inst.stats.light_ms = res.light_ms;
+    inst.stats.light_algo_bytes = res.light_bytes;
     inst.stats.device_bytes = store->dir.bytes + store->pool.bytes;
     inst.sp = store;
 }

@@ -106,6 +106,15 @@ struct KeySort {
     uint64_t threshold;
     uint32_t big_entry;        // products that make an entry a heavy item of its own
     uint32_t *bsum;            // scan scratch
+    // traffic accounting (null unless counting): a bit per (layout,
+    // vertex) list, set on its first read in a round, and the algorithmic
+    // bytes of the heavy and the light kernel: 8 per sorted entry, 4 per
+    // entry of every distinct partner list and output row (the head's list
+    // at the key, the mask of the candidates) read in the round, 16 per
+    // new pair
+    uint32_t *touch;
+    unsigned long long *acct;        // heavy kernel
+    unsigned long long *acct_light;  // light kernel
 };
 
 // New pairs of a round: (matrix, i, j); kHoleKey marks an unused entry.
@@ -183,7 +192,8 @@ constexpr uint32_t kHeavyThreads = 256;
 constexpr uint32_t kHeavyRun = kHeavyThreads;  // entries of a heavy item at most
 
 hipError_t launch_key_sort(const State &S, PairBuf in, const KeySort &K, hipStream_t s);
-hipError_t launch_grouped_product(const State &S, const KeySort &K, PairBuf out, uint32_t grid_waves, hipStream_t s);
+hipError_t launch_heavy(const State &S, const KeySort &K, PairBuf out, uint32_t grid_waves, hipStream_t s);
+hipError_t launch_light(const State &S, const KeySort &K, PairBuf out, uint32_t grid_waves, hipStream_t s);
 uint64_t key_sort_scan_blocks(uint64_t nb);
 // LDS bytes of a heavy workgroup's accumulator (n bits); the grouped product
 // needs n small enough for it to fit.

@@ -403,6 +403,12 @@ __global__ __launch_bounds__(256) void unmark_kernel(State S) {
 
 // ------------------------------------------------------------------ product
 
+// first read of list `cell` (layout * n + vertex) in this round?
+__device__ __forceinline__ bool first_read(const KeySort &K, uint64_t cell) {
+    const uint32_t m = 1u << (cell & 31);
+    return !(atomicOr(&K.touch[cell >> 5], m) & m);
+}
+
 // One lane's pair (x, pi, pj) against the partner lists of its uses in
 // parts [p_lo, p_hi): the lane walks the set bits of its use masks (part 0
 // at its column pj, part 1 at its row pi), one use per step; per step the
@@ -411,7 +417,7 @@ __global__ __launch_bounds__(256) void unmark_kernel(State S) {
 // false: an overflow (the round is re-run).
 __device__ __forceinline__ bool expand_uses(const State &S, const PairBuf &out, Chunk &ch, uint64_t &appended,
                                             uint64_t &products, bool valid, uint32_t x, uint32_t pi, uint32_t pj,
-                                            uint32_t p_lo, uint32_t p_hi) {
+                                            uint32_t p_lo, uint32_t p_hi, const KeySort *acct, uint64_t &bytes) {
     const uint32_t lane = lane_id();
     bool more = valid;
     MatInfo mi{};
@@ -456,6 +462,12 @@ __device__ __forceinline__ bool expand_uses(const State &S, const PairBuf &out, 
             const Dir d = S.dir[(uint64_t)lay * S.n + k];
             off = d.off;
             len = d.len;
+            if (acct) {
+                if (first_read(*acct, (uint64_t)lay * S.n + k)) bytes += 4ull * d.len;
+                const uint32_t own = col ? S.mats[c].col_layout : S.mats[c].row_layout;
+                if (own != kNone && first_read(*acct, (uint64_t)own * S.n + fixed))
+                    bytes += 4ull * S.dir[(uint64_t)own * S.n + fixed].len;
+            }
         }
         uint32_t total;
         const uint32_t pre = wave_excl_scan(len, &total);
@@ -504,7 +516,8 @@ __global__ __launch_bounds__(256) void product_kernel(State S, PairBuf in, PairB
             pi = in.i[e];
             pj = in.j[e];
         }
-        if (!expand_uses(S, out, ch, appended, products, x != kHoleKey, x, pi, pj, 0, 2)) break;
+        uint64_t unused = 0;
+        if (!expand_uses(S, out, ch, appended, products, x != kHoleKey, x, pi, pj, 0, 2, nullptr, unused)) break;
     }
     chunk_retire(out, ch);
     add_appended(S, appended);
@@ -732,7 +745,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
     uint64_t nheavy = S.ctl[kCtlHeavy];
     if (nheavy > K.heavy_cap) nheavy = K.heavy_cap;
     Chunk ch;
-    uint64_t appended = 0, products = 0, cands = 0;
+    uint64_t appended = 0, products = 0, cands = 0, bytes = 0;
     for (uint32_t w = t; w < nw; w += kHeavyThreads) acc[w] = 0;
     if (t == 0) sh_fail = 0;
     // each wave emits the candidates of words [wave * per, (wave + 1) * per)
@@ -762,6 +775,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
         if (t > 0 && e0 + t < sh_e1 && item_start(K, e0 + t, bstart)) atomicMin(&sh_e1, e0 + t);
         __syncthreads();
         const uint32_t cnt = sh_e1 - e0;
+        if (K.acct && t == 0) bytes += 8ull * cnt;
         const uint32_t W = order ? mi.w1 : mi.w0, first = order ? mi.use1 : mi.use0,
                        nuse = order ? mi.nuse1 : mi.nuse0;
         const uint64_t mbase = order ? mi.mask1 : mi.mask0;
@@ -786,6 +800,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
                     const Dir d = S.dir[(uint64_t)u.layout * S.n + k];
                     off = d.off;
                     len = d.len;
+                    if (K.acct && first_read(K, (uint64_t)u.layout * S.n + k)) bytes += 4ull * d.len;
                 }
                 uint32_t total;
                 const uint32_t pre = block_excl_scan(len, &total, wsum);
@@ -814,6 +829,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
                 const uint32_t own = order ? S.mats[u.c].col_layout : S.mats[u.c].row_layout;
                 if (own != kNone) {
                     const Dir d = S.dir[(uint64_t)own * S.n + key];
+                    if (K.acct && t == 0 && first_read(K, (uint64_t)own * S.n + key)) bytes += 4ull * d.len;
                     __syncthreads();  // every product is in the bit set
                     for (uint32_t p = t; p < d.len; p += kHeavyThreads) {
                         const uint32_t v = S.pool[d.off + p];
@@ -871,6 +887,10 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
         atomicAdd(&S.ctl[kCtlHeavyProducts], (unsigned long long)products);
     }
     if (lane == 0 && cands) atomicAdd(&S.ctl[kCtlHeavyCand], (unsigned long long)cands);
+    if (K.acct) {
+        if (lane == 0) bytes += 16ull * appended;
+        if (bytes) atomicAdd(K.acct, (unsigned long long)bytes);
+    }
 }
 
 // Light buckets: 64 sorted entries per task, a lane per entry, expanded
@@ -882,7 +902,8 @@ __global__ __launch_bounds__(256) void light_kernel(State S, KeySort K, PairBuf 
     const uint64_t total0 = K.start[K.nb0];
     const uint64_t ntask = (total + 63) / 64;
     Chunk ch;
-    uint64_t appended = 0, products = 0;
+    uint64_t appended = 0, products = 0, bytes = 0;
+    const KeySort *acct = K.acct_light ? &K : nullptr;
     while (true) {
         unsigned long long t = 0;
         if (lane == 0) t = atomicAdd(&S.ctl[kCtlTasks], 1ull);
@@ -903,11 +924,16 @@ __global__ __launch_bounds__(256) void light_kernel(State S, KeySort K, PairBuf 
             const uint64_t b = order ? K.nb0 + (uint64_t)mi.rank1 * S.n + key : (uint64_t)mi.rank0 * S.n + key;
             if (K.work[b] >= K.threshold) valid = false;
         }
-        if (!expand_uses(S, out, ch, appended, products, valid, x, pi, pj, order, order + 1)) break;
+        if (acct && valid) bytes += 8;
+        if (!expand_uses(S, out, ch, appended, products, valid, x, pi, pj, order, order + 1, acct, bytes)) break;
     }
     chunk_retire(out, ch);
     add_appended(S, appended);
     if (lane == 0 && products) atomicAdd(&S.ctl[kCtlProducts], (unsigned long long)products);
+    if (acct) {
+        if (lane == 0) bytes += 16ull * appended;
+        if (bytes) atomicAdd(K.acct_light, (unsigned long long)bytes);
+    }
 }
 
 // ------------------------------------------------------------------- rehash
@@ -1145,10 +1171,15 @@ hipError_t launch_key_sort(const State &S, PairBuf in, const KeySort &K, hipStre
     return hipSuccess;
 }
 
-hipError_t launch_grouped_product(const State &S, const KeySort &K, PairBuf out, uint32_t grid_waves, hipStream_t s) {
+hipError_t launch_heavy(const State &S, const KeySort &K, PairBuf out, uint32_t grid_waves, hipStream_t s) {
     const uint32_t blocks = grid_waves / 4 ? grid_waves / 4 : 1;
     heavy_kernel<<<blocks, kHeavyThreads, (uint32_t)heavy_lds_bytes(S.n), s>>>(S, K, out);
     SP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_light(const State &S, const KeySort &K, PairBuf out, uint32_t grid_waves, hipStream_t s) {
+    const uint32_t blocks = grid_waves / 4 ? grid_waves / 4 : 1;
     light_kernel<<<blocks, 256, 0, s>>>(S, K, out);
     SP_LAUNCH_CHECK();
     return hipSuccess;

@@ -137,5 +137,7 @@ def test_storage_option_and_stat_fields():
     import paper_2401_11029_amd as cflr
     from paper_2401_11029_amd._lib import Opts, Stats
     # the storage choice is the last field of the options and of the stats
-    assert Opts._fields_[-1][0] == "storage" and Stats._fields_[-1][0] == "storage"
+    assert Opts._fields_[-1][0] == "storage"
+    assert [f[0] for f in Stats._fields_[-6:]] == ["storage", "heavy_ms", "heavy_launches", "heavy_algo_bytes",
+                                                   "light_ms", "light_algo_bytes"]
     assert cflr.opts().storage == 0 and cflr.opts(storage=2).storage == 2
