@@ -61,8 +61,8 @@ Plan make_plan(const Lowered &low, uint32_t n) {
         if (low.slot_a[x]) P.mats[x].col_layout = P.nlayouts++;
     std::vector<std::vector<sp::Use>> u0(M), u1(M);
     for (const auto &b : low.binary) {
-        u0[b.a].push_back(sp::Use{b.c, P.mats[b.b].row_layout});
-        u1[b.b].push_back(sp::Use{b.c, P.mats[b.a].col_layout});
+        u0[b.a].push_back(sp::Use{b.c, P.mats[b.b].row_layout, P.mats[b.c].row_layout, 0});
+        u1[b.b].push_back(sp::Use{b.c, P.mats[b.a].col_layout, P.mats[b.c].col_layout, 0});
     }
     std::vector<std::vector<sp::Obs>> ob(P.nlayouts);
     uint64_t mw = 0;
@@ -343,20 +343,27 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
     if (fixed) size_touched(cap_out);
 
     // the grouped product: new pairs sorted by (matrix, key); buckets whose
-    // products reach `threshold` (n / 2 by default: below that the per-item
-    // cost of the bit set outweighs the hash probes it saves, measured on
-    // the 200,000-vertex points-to graph) are expanded into an LDS bit set.
-    // Off when the bucket space or the bit set is too large, and in a fixed
-    // region.
+    // products reach `threshold` are expanded into an LDS bit set, where a
+    // use with at most `direct` products skips the bit set and a head's own
+    // pairs are cleared from it when they are at most `row_factor` times
+    // the use's products.  Defaults (512, 256, 4) from sweeps on the
+    // 200,000-vertex points-to graph: the bit set and the own-row clear
+    // replace most hash probes, and below these sizes a probe is cheaper
+    // than the workgroup's fixed cost per use.  Off when the bucket space or
+    // the bit set is too large, and in a fixed region.
     sp::KeySort K{};
     K.nb0 = (uint64_t)P.nrank0 * n;
     K.nb = K.nb0 + (uint64_t)P.nrank1 * n;
     const bool grouped = !fixed && K.nb > 0 && K.nb < (1ull << 30) && sp::heavy_lds_bytes(n) <= sp::kHeavyMaxLds &&
                          std::getenv("CFLR_SPARSE_UNGROUPED") == nullptr;
-    K.threshold = std::max<uint64_t>(1, n / 2);
+    K.threshold = 512;
     if (const char *h = std::getenv("CFLR_SPARSE_HEAVY")) K.threshold = std::max<uint64_t>(1, std::strtoull(h, nullptr, 10));
     K.big_entry = 0x7FFFFFFFu;
     if (const char *h = std::getenv("CFLR_SPARSE_BIG")) K.big_entry = (uint32_t)std::strtoul(h, nullptr, 10);
+    K.direct = 256;
+    if (const char *h = std::getenv("CFLR_SPARSE_DIRECT")) K.direct = (uint32_t)std::strtoul(h, nullptr, 10);
+    K.row_factor = 4;
+    if (const char *h = std::getenv("CFLR_SPARSE_ROWF")) K.row_factor = (uint32_t)std::strtoul(h, nullptr, 10);
     Mem k_start, k_work, k_bsum, k_entry, k_heavy, k_ework, k_touch, k_acct;
     if (grouped) {
         k_start = A.get((K.nb + 1) * 4, "the key sort");
@@ -542,6 +549,7 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlNew, 1, 0, s), "fill");
         hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlProducts, 1, 0, s), "fill");
         hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlHeavyProducts, 2, 0, s), "fill");
+        const double heavy_ms0 = res.heavy_ms, light_ms0 = res.light_ms;
         timed_product();
         for (int attempt = 0; h_ctl[sp::kCtlHalt]; attempt++) {
             if (fixed) throw too_small("the pairs");
@@ -575,12 +583,12 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         if (log)
             std::fprintf(stderr,
                          "[cflr] sparse round %u: in %llu new %llu products %llu heavy items %llu products %llu "
-                         "candidates %llu pool %llu/%llu slots %llu\n",
+                         "candidates %llu pool %llu/%llu slots %llu heavy %.2f ms light %.2f ms\n",
                          res.rounds, (unsigned long long)pending, (unsigned long long)fresh,
                          (unsigned long long)h_ctl[sp::kCtlProducts], (unsigned long long)h_ctl[sp::kCtlHeavy],
                          (unsigned long long)h_ctl[sp::kCtlHeavyProducts], (unsigned long long)h_ctl[sp::kCtlHeavyCand],
                          (unsigned long long)h_ctl[sp::kCtlPoolTop], (unsigned long long)pool_cap,
-                         (unsigned long long)cur_slots);
+                         (unsigned long long)cur_slots, res.heavy_ms - heavy_ms0, res.light_ms - light_ms0);
         pending = fresh;
         std::swap(in, out);
     }

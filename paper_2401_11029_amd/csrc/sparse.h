@@ -60,12 +60,15 @@ struct Dir {
     uint32_t len, cap;
 };
 
-// A production seen from one of its operands: the head c and the partner
+// A production seen from one of its operands: the head c, the partner
 // layout the product reads (part 0: b's row layout; part 1: a's column
-// layout).
+// layout) and c's own layout in the candidates' orientation (part 0: its
+// row layout; part 1: its column layout; kNone when c has none).
 struct Use {
     uint32_t c;
     uint32_t layout;
+    uint32_t own;
+    uint32_t pad;
 };
 
 // A use mask to update when a list of some layout becomes non-empty at
@@ -105,6 +108,12 @@ struct KeySort {
     uint64_t heavy_cap;
     uint64_t threshold;
     uint32_t big_entry;        // products that make an entry a heavy item of its own
+    uint32_t direct;           // a heavy item's use with at most this many products inserts
+                               // them into the hash set directly (no bit set)
+    uint32_t row_factor;       // a heavy item clears the head's pairs at its key from the
+                               // bit set only when that list is at most row_factor times
+                               // the item's products for the head (else the hash set
+                               // alone rejects them)
     uint32_t *bsum;            // scan scratch
     // traffic accounting (null unless counting): a bit per (layout,
     // vertex) list, set on its first read in a round, and the algorithmic
@@ -198,7 +207,7 @@ uint64_t key_sort_scan_blocks(uint64_t nb);
 // LDS bytes of a heavy workgroup's accumulator (n bits); the grouped product
 // needs n small enough for it to fit.
 inline uint64_t heavy_lds_bytes(uint32_t n) { return ((uint64_t)n + 31) / 32 * 4; }
-constexpr uint64_t kHeavyMaxLds = 64 * 1024;
+constexpr uint64_t kHeavyMaxLds = 52 * 1024;  // with the kernel's static LDS (about 12 KiB), within 64 KiB
 // Re-insert every key of `old_tab` (tombstones dropped) into S.hash (empty).
 hipError_t launch_rehash(const State &S, const unsigned long long *old_tab, uint64_t old_slots, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long v, hipStream_t s);

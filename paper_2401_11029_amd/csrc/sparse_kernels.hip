@@ -427,7 +427,7 @@ __device__ __forceinline__ bool expand_uses(const State &S, const PairBuf &out, 
     while (__any(more)) {
         // this lane's next use: head c, partner layout, fixed index of the
         // candidates and the partner vertex k
-        uint32_t c = 0, lay = kNone, fixed = 0, k = 0, col = 0;
+        uint32_t c = 0, lay = kNone, own = kNone, fixed = 0, k = 0, col = 0;
         if (more) {
             while (!bits) {
                 const uint32_t W = part == 0 ? mi.w0 : mi.w1;
@@ -449,6 +449,7 @@ __device__ __forceinline__ bool expand_uses(const State &S, const PairBuf &out, 
                 const Use u = S.uses[(part == 0 ? mi.use0 : mi.use1) + q];
                 c = u.c;
                 lay = u.layout;
+                own = u.own;
                 // part 0: pair (i, k) of a meets row k of b -> (c, i, j')
                 // part 1: pair (k, j) of b meets column k of a -> (c, i', j)
                 fixed = part == 0 ? pi : pj;
@@ -464,7 +465,6 @@ __device__ __forceinline__ bool expand_uses(const State &S, const PairBuf &out, 
             len = d.len;
             if (acct) {
                 if (first_read(*acct, (uint64_t)lay * S.n + k)) bytes += 4ull * d.len;
-                const uint32_t own = col ? S.mats[c].col_layout : S.mats[c].row_layout;
                 if (own != kNone && first_read(*acct, (uint64_t)own * S.n + fixed))
                     bytes += 4ull * S.dir[(uint64_t)own * S.n + fixed].len;
             }
@@ -643,31 +643,45 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t *a, u
 
 // Products of every sorted entry (the lengths of the partner lists its use
 // masks select), summed per bucket.
+// The entries are in bucket order, so a wave's lanes of one bucket are
+// consecutive: their products are summed over the wave first (a scan over
+// runs of equal bucket) and the run's last lane adds the sum.
 __global__ __launch_bounds__(256) void classify_kernel(State S, KeySort K) {
     uint64_t total = K.start[K.nb];
     if (total > K.entry_cap) total = K.entry_cap;
     const uint64_t total0 = K.start[K.nb0];
-    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total;
-         e += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t v = K.entry[e];
-        const uint32_t x = (uint32_t)(v >> 48), key = (uint32_t)(v >> 24) & 0xFFFFFFu, k = (uint32_t)v & 0xFFFFFFu;
-        const uint32_t order = e >= total0 ? 1u : 0u;
-        const MatInfo mi = S.mats[x];
-        const uint32_t W = order ? mi.w1 : mi.w0, first = order ? mi.use1 : mi.use0;
-        const uint64_t mbase = order ? mi.mask1 : mi.mask0;
-        uint64_t work = 0;
-        for (uint32_t w = 0; w < W; w++) {
-            uint64_t bits = S.mask[mbase + (uint64_t)k * W + w];
-            while (bits) {
-                const uint32_t q = w * 64 + (uint32_t)__builtin_ctzll(bits);
-                bits &= bits - 1;
-                work += S.dir[(uint64_t)S.uses[first + q].layout * S.n + k].len;
+    const uint32_t lane = lane_id();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); base < total; base += stride) {
+        const uint64_t e = base + lane;
+        uint64_t b = ~0ull, work = 0;
+        if (e < total) {
+            const uint64_t v = K.entry[e];
+            const uint32_t x = (uint32_t)(v >> 48), key = (uint32_t)(v >> 24) & 0xFFFFFFu, k = (uint32_t)v & 0xFFFFFFu;
+            const uint32_t order = e >= total0 ? 1u : 0u;
+            const MatInfo mi = S.mats[x];
+            const uint32_t W = order ? mi.w1 : mi.w0, first = order ? mi.use1 : mi.use0;
+            const uint64_t mbase = order ? mi.mask1 : mi.mask0;
+            for (uint32_t w = 0; w < W; w++) {
+                uint64_t bits = S.mask[mbase + (uint64_t)k * W + w];
+                while (bits) {
+                    const uint32_t q = w * 64 + (uint32_t)__builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    work += S.dir[(uint64_t)S.uses[first + q].layout * S.n + k].len;
+                }
             }
+            K.ework[e] = work < 0x7FFFFFFFull ? (uint32_t)work : 0x7FFFFFFFu;
+            b = order ? K.nb0 + (uint64_t)mi.rank1 * S.n + key : (uint64_t)mi.rank0 * S.n + key;
         }
-        K.ework[e] = work < 0x7FFFFFFFull ? (uint32_t)work : 0x7FFFFFFFu;
-        if (!work) continue;
-        const uint64_t b = order ? K.nb0 + (uint64_t)mi.rank1 * S.n + key : (uint64_t)mi.rank0 * S.n + key;
-        atomicAdd(&K.work[b], (unsigned long long)work);
+        uint64_t sum = work;
+#pragma unroll
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint64_t ob = shfl64(b, lane >= d ? lane - d : lane);
+            const uint64_t os = shfl64(sum, lane >= d ? lane - d : lane);
+            if (lane >= d && ob == b) sum += os;
+        }
+        const uint64_t nb = shfl64(b, lane < 63 ? lane + 1 : lane);
+        if (b != ~0ull && sum && (lane == 63 || nb != b)) atomicAdd(&K.work[b], (unsigned long long)sum);
     }
 }
 
@@ -712,6 +726,55 @@ __global__ __launch_bounds__(256) void heavy_items_kernel(State S, KeySort K) {
 // The bit set is left zero for the next use.
 constexpr uint32_t kMaxUseWords = 8;  // uses selected through an LDS OR of the masks (512)
 constexpr uint32_t kUnroll = 4;       // passes of products whose loads are issued together
+constexpr uint32_t kTouchCap = 2048;  // words listed as set; past that the whole bit set is scanned
+
+// The first use at or after `from` that some entry of the item selects (its
+// bit in the OR of the entries' masks; every use when the masks were not
+// gathered), else nuse.
+__device__ __forceinline__ uint32_t next_use(const uint64_t *um, bool gathered, uint32_t nuse, uint32_t from) {
+    while (from < nuse) {
+        const uint32_t w = from / 64;
+        const uint64_t bits = (gathered ? um[w] : ~0ull) & (~0ull << (from % 64));
+        if (bits) {
+            const uint32_t q = w * 64 + (uint32_t)__builtin_ctzll(bits);
+            return q < nuse ? q : nuse;
+        }
+        from = (w + 1) * 64;
+    }
+    return nuse;
+}
+
+// A use of a heavy item as one thread sees it: the production, the
+// partner list at its entry's partner vertex (empty when its entry does
+// not select the use) and the head's own list at the item's key.
+struct UseLoad {
+    Use u;
+    uint64_t off;
+    uint32_t len;
+    Dir own;
+};
+
+__device__ __forceinline__ UseLoad load_use(const State &S, const KeySort &K, uint32_t q, uint32_t nuse,
+                                            uint32_t first, bool mine, uint32_t k, uint32_t key, uint64_t m0,
+                                            uint64_t m1, uint64_t mbase, uint32_t W, uint64_t &bytes) {
+    UseLoad L{};
+    L.u.own = kNone;
+    if (q >= nuse) return L;
+    L.u = S.uses[first + q];
+    bool sel = false;
+    if (mine) {
+        const uint64_t m = q < 64 ? m0 : q < 128 ? m1 : S.mask[mbase + (uint64_t)k * W + q / 64];
+        sel = (m >> (q % 64)) & 1;
+    }
+    if (sel) {
+        const Dir d = S.dir[(uint64_t)L.u.layout * S.n + k];
+        L.off = d.off;
+        L.len = d.len;
+        if (K.acct && first_read(K, (uint64_t)L.u.layout * S.n + k)) bytes += 4ull * d.len;
+    }
+    if (L.u.own != kNone) L.own = S.dir[(uint64_t)L.u.own * S.n + key];
+    return L;
+}
 
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total, uint32_t *wsum) {
     constexpr uint32_t kWaves = kHeavyThreads / 64;
@@ -737,8 +800,9 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
     __shared__ uint64_t s_off[kHeavyThreads];
     __shared__ uint32_t s_pre[kHeavyThreads];
     __shared__ uint32_t wsum[kHeavyThreads / 64];
+    __shared__ uint32_t s_touch[kTouchCap];
     __shared__ unsigned long long sh_item;
-    __shared__ uint32_t sh_e1, sh_fail;
+    __shared__ uint32_t sh_e1, sh_fail, sh_ntouch;
     constexpr uint32_t kWaves = kHeavyThreads / 64;
     const uint32_t t = threadIdx.x, lane = lane_id(), wave = t / 64;
     const uint32_t nw = (S.n + 31) / 32;
@@ -747,7 +811,10 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
     Chunk ch;
     uint64_t appended = 0, products = 0, cands = 0, bytes = 0;
     for (uint32_t w = t; w < nw; w += kHeavyThreads) acc[w] = 0;
-    if (t == 0) sh_fail = 0;
+    if (t == 0) {
+        sh_fail = 0;
+        sh_ntouch = 0;
+    }
     // each wave emits the candidates of words [wave * per, (wave + 1) * per)
     const uint32_t per = ((nw + kWaves - 1) / kWaves + 63) / 64 * 64;
     bool stop = false;
@@ -780,104 +847,136 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
                        nuse = order ? mi.nuse1 : mi.nuse0;
         const uint64_t mbase = order ? mi.mask1 : mi.mask0;
         const bool gathered = W <= kMaxUseWords;
-        const uint32_t k = t < cnt ? (uint32_t)K.entry[e0 + t] & 0xFFFFFFu : 0u;
-        if (gathered && t < cnt)
+        const bool mine = t < cnt;
+        const uint32_t k = mine ? (uint32_t)K.entry[e0 + t] & 0xFFFFFFu : 0u;
+        // this entry's first two mask words stay in registers
+        uint64_t m0 = 0, m1 = 0;
+        if (mine)
             for (uint32_t w = 0; w < W; w++) {
                 const uint64_t m = S.mask[mbase + (uint64_t)k * W + w];
-                if (m) atomicOr((unsigned long long *)&um[w], (unsigned long long)m);
+                if (w == 0) m0 = m;
+                if (w == 1) m1 = m;
+                if (gathered && m) atomicOr((unsigned long long *)&um[w], (unsigned long long)m);
             }
         __syncthreads();
-        for (uint32_t w = 0; w < W && !stop; w++) {
-            uint64_t bits = gathered ? um[w] : ~0ull;
-            if (w * 64 + 64 > nuse) bits &= (1ull << (nuse - w * 64)) - 1;  // nuse - 64w < 64 here
-            while (bits && !stop) {
-                const uint32_t q = w * 64 + (uint32_t)__builtin_ctzll(bits);
-                bits &= bits - 1;
-                const Use u = S.uses[first + q];
-                uint64_t off = 0;
-                uint32_t len = 0;
-                if (t < cnt && ((S.mask[mbase + (uint64_t)k * W + q / 64] >> (q % 64)) & 1)) {
-                    const Dir d = S.dir[(uint64_t)u.layout * S.n + k];
-                    off = d.off;
-                    len = d.len;
-                    if (K.acct && first_read(K, (uint64_t)u.layout * S.n + k)) bytes += 4ull * d.len;
-                }
-                uint32_t total;
-                const uint32_t pre = block_excl_scan(len, &total, wsum);
-                s_pre[t] = pre;
-                s_off[t] = off;
-                __syncthreads();
-                products += total;
-                for (uint32_t r = 0; r < total; r += kHeavyThreads * kUnroll) {
-                    uint32_t v[kUnroll];
-#pragma unroll
-                    for (uint32_t uu = 0; uu < kUnroll; uu++) {
-                        const uint32_t tt = r + uu * kHeavyThreads + t;
-                        v[uu] = 0xFFFFFFFFu;
-                        if (tt < total) {
-                            uint32_t src = 0;  // last entry whose first product is <= tt
-#pragma unroll
-                            for (uint32_t step = kHeavyThreads / 2; step; step >>= 1)
-                                if (src + step < cnt && s_pre[src + step] <= tt) src += step;
-                            v[uu] = S.pool[s_off[src] + (tt - s_pre[src])];
-                        }
-                    }
-#pragma unroll
-                    for (uint32_t uu = 0; uu < kUnroll; uu++)
-                        if (v[uu] != 0xFFFFFFFFu) atomicOr(&acc[v[uu] >> 5], 1u << (v[uu] & 31));
-                }
-                const uint32_t own = order ? S.mats[u.c].col_layout : S.mats[u.c].row_layout;
-                if (own != kNone) {
-                    const Dir d = S.dir[(uint64_t)own * S.n + key];
-                    if (K.acct && t == 0 && first_read(K, (uint64_t)own * S.n + key)) bytes += 4ull * d.len;
-                    __syncthreads();  // every product is in the bit set
-                    for (uint32_t p = t; p < d.len; p += kHeavyThreads) {
-                        const uint32_t v = S.pool[d.off + p];
-                        atomicAnd(&acc[v >> 5], ~(1u << (v & 31)));
-                    }
-                }
-                __syncthreads();
-                bool ok = true;
-                const uint32_t w_end = (wave + 1) * per < nw ? (wave + 1) * per : nw;
-                for (uint32_t base = wave * per; base < w_end; base += 64) {
-                    const uint32_t wi = base + lane;
-                    uint32_t word = 0;
-                    if (wi < w_end) {
-                        word = acc[wi];
-                        acc[wi] = 0;
-                    }
-                    if (!ok) continue;
-                    uint32_t ctot;
-                    const uint32_t cpre = wave_excl_scan((uint32_t)__popc(word), &ctot);
-                    cands += ctot;
-                    for (uint32_t r = 0; r < ctot; r += 64) {
-                        const uint32_t tt = r + lane;
+        // the uses some entry selects, in order, each loaded one use ahead
+        uint32_t q = next_use(um, gathered, nuse, 0);
+        UseLoad cur = load_use(S, K, q, nuse, first, mine, k, key, m0, m1, mbase, W, bytes);
+        while (q < nuse && !stop) {
+            const uint32_t qn = next_use(um, gathered, nuse, q + 1);
+            const UseLoad nxt = load_use(S, K, qn, nuse, first, mine, k, key, m0, m1, mbase, W, bytes);
+            const Use u = cur.u;
+            uint32_t total;
+            const uint32_t pre = block_excl_scan(cur.len, &total, wsum);
+            s_pre[t] = pre;
+            s_off[t] = cur.off;
+            __syncthreads();
+            products += total;
+            bool ok = true;
+            if (total <= K.direct) {
+                // few products: each one goes to the hash set as it is
+                cands += total;
+                for (uint32_t r = 0; r < total; r += kHeavyThreads) {
+                    const uint32_t tt = r + t;
+                    uint32_t v = 0;
+                    if (tt < total) {
                         uint32_t src = 0;
 #pragma unroll
-                        for (uint32_t step = 32; step; step >>= 1)
-                            if (shfl32(cpre, src + step) <= tt) src += step;
-                        const uint32_t sword = shfl32(word, src);
-                        uint32_t rank = tt - shfl32(cpre, src), bit = 0;
-#pragma unroll
-                        for (uint32_t width = 16; width; width >>= 1) {
-                            const uint32_t c2 = (uint32_t)__popc((sword >> bit) & ((1u << width) - 1));
-                            if (rank >= c2) {
-                                rank -= c2;
-                                bit += width;
-                            }
-                        }
-                        const bool has = tt < ctot;
-                        const uint32_t v = (base + src) * 32 + bit;
-                        if (!insert_append(S, out, ch, appended, has, u.c, order ? v : key, order ? key : v)) {
-                            ok = false;
-                            break;
-                        }
+                        for (uint32_t step = kHeavyThreads / 2; step; step >>= 1)
+                            if (src + step < cnt && s_pre[src + step] <= tt) src += step;
+                        v = S.pool[s_off[src] + (tt - s_pre[src])];
+                    }
+                    if (!insert_append(S, out, ch, appended, tt < total, u.c, order ? v : key, order ? key : v)) {
+                        ok = false;
+                        break;
                     }
                 }
                 if (!ok && lane == 0) atomicOr(&sh_fail, 1u);
                 __syncthreads();
                 stop = sh_fail != 0;
+                q = qn;
+                cur = nxt;
+                continue;
             }
+            for (uint32_t r = 0; r < total; r += kHeavyThreads * kUnroll) {
+                uint32_t v[kUnroll];
+#pragma unroll
+                for (uint32_t uu = 0; uu < kUnroll; uu++) {
+                    const uint32_t tt = r + uu * kHeavyThreads + t;
+                    v[uu] = 0xFFFFFFFFu;
+                    if (tt < total) {
+                        uint32_t src = 0;  // last entry whose first product is <= tt
+#pragma unroll
+                        for (uint32_t step = kHeavyThreads / 2; step; step >>= 1)
+                            if (src + step < cnt && s_pre[src + step] <= tt) src += step;
+                        v[uu] = S.pool[s_off[src] + (tt - s_pre[src])];
+                    }
+                }
+                // the first product into a word lists it (one thread sees it zero)
+#pragma unroll
+                for (uint32_t uu = 0; uu < kUnroll; uu++)
+                    if (v[uu] != 0xFFFFFFFFu && !atomicOr(&acc[v[uu] >> 5], 1u << (v[uu] & 31))) {
+                        const uint32_t slot = atomicAdd(&sh_ntouch, 1u);
+                        if (slot < kTouchCap) s_touch[slot] = v[uu] >> 5;
+                    }
+            }
+            if (u.own != kNone && (uint64_t)cur.own.len <= (uint64_t)K.row_factor * total) {
+                if (K.acct && t == 0 && first_read(K, (uint64_t)u.own * S.n + key)) bytes += 4ull * cur.own.len;
+                __syncthreads();  // every product is in the bit set
+                for (uint32_t p = t; p < cur.own.len; p += kHeavyThreads) {
+                    const uint32_t v = S.pool[cur.own.off + p];
+                    atomicAnd(&acc[v >> 5], ~(1u << (v & 31)));
+                }
+            }
+            __syncthreads();
+            // the listed words, else every word; each wave a quarter
+            const uint32_t ntouch = sh_ntouch;
+            const bool listed = ntouch <= kTouchCap;
+            const uint32_t span = listed ? ntouch : nw;
+            const uint32_t per_w = listed ? ((ntouch + kWaves - 1) / kWaves + 63) / 64 * 64 : per;
+            const uint32_t w_end = (wave + 1) * per_w < span ? (wave + 1) * per_w : span;
+            for (uint32_t base = wave * per_w; base < w_end; base += 64) {
+                uint32_t wi = base + lane;
+                uint32_t word = 0;
+                if (wi < w_end) {
+                    if (listed) wi = s_touch[wi];
+                    word = acc[wi];
+                    acc[wi] = 0;
+                }
+                if (!ok) continue;
+                uint32_t ctot;
+                const uint32_t cpre = wave_excl_scan((uint32_t)__popc(word), &ctot);
+                cands += ctot;
+                for (uint32_t r = 0; r < ctot; r += 64) {
+                    const uint32_t tt = r + lane;
+                    uint32_t src = 0;
+#pragma unroll
+                    for (uint32_t step = 32; step; step >>= 1)
+                        if (shfl32(cpre, src + step) <= tt) src += step;
+                    const uint32_t sword = shfl32(word, src);
+                    uint32_t rank = tt - shfl32(cpre, src), bit = 0;
+#pragma unroll
+                    for (uint32_t width = 16; width; width >>= 1) {
+                        const uint32_t c2 = (uint32_t)__popc((sword >> bit) & ((1u << width) - 1));
+                        if (rank >= c2) {
+                            rank -= c2;
+                            bit += width;
+                        }
+                    }
+                    const bool has = tt < ctot;
+                    const uint32_t v = shfl32(wi, src) * 32 + bit;
+                    if (!insert_append(S, out, ch, appended, has, u.c, order ? v : key, order ? key : v)) {
+                        ok = false;
+                        break;
+                    }
+                }
+            }
+            if (!ok && lane == 0) atomicOr(&sh_fail, 1u);
+            __syncthreads();
+            if (t == 0) sh_ntouch = 0;  // read again only after the next use's scan
+            stop = sh_fail != 0;
+            q = qn;
+            cur = nxt;
         }
     }
     chunk_retire(out, ch);
@@ -895,6 +994,8 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
 
 // Light buckets: 64 sorted entries per task, a lane per entry, expanded
 // against the uses of its own part; entries of heavy buckets are skipped.
+// A wave claims kLightClaim tasks at a time (one counter serves them all).
+constexpr uint32_t kLightClaim = 16;
 __global__ __launch_bounds__(256) void light_kernel(State S, KeySort K, PairBuf out) {
     const uint32_t lane = lane_id();
     uint64_t total = K.start[K.nb];
@@ -904,11 +1005,15 @@ __global__ __launch_bounds__(256) void light_kernel(State S, KeySort K, PairBuf 
     Chunk ch;
     uint64_t appended = 0, products = 0, bytes = 0;
     const KeySort *acct = K.acct_light ? &K : nullptr;
-    while (true) {
-        unsigned long long t = 0;
-        if (lane == 0) t = atomicAdd(&S.ctl[kCtlTasks], 1ull);
-        t = first_lane64(t);
-        if (t >= ntask) break;
+    uint64_t t = 0, t_end = 0;  // this wave's claimed tasks
+    for (;; t++) {
+        if (t == t_end) {
+            unsigned long long c = 0;
+            if (lane == 0) c = atomicAdd(&S.ctl[kCtlTasks], (unsigned long long)kLightClaim);
+            t = first_lane64(c);
+            if (t >= ntask) break;
+            t_end = t + kLightClaim < ntask ? t + kLightClaim : ntask;
+        }
         if (first_lane64(load_relaxed(&S.ctl[kCtlHalt]))) break;
         const uint64_t e = t * 64 + lane;
         bool valid = e < total;

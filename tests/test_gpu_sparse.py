@@ -20,19 +20,25 @@ pytestmark = pytest.mark.gpu
 SPARSE = 2
 
 # The product's paths: buckets of new pairs sorted by key, heavy ones through
-# an LDS bit set (default threshold n / 64), every bucket heavy, every
-# bucket light, and the unsorted product.
+# an LDS bit set (the default threshold), every bucket heavy, every bucket
+# heavy with small uses sent straight to the hash set, every bucket heavy
+# without clearing the head's own pairs from the bit set, every bucket
+# light, and the unsorted product.
 MODES = {
     "grouped": {},
-    "all_heavy": {"CFLR_SPARSE_HEAVY": "1"},
+    "all_heavy": {"CFLR_SPARSE_HEAVY": "1", "CFLR_SPARSE_DIRECT": "0", "CFLR_SPARSE_ROWF": str(2**32 - 1)},
+    "heavy_direct": {"CFLR_SPARSE_HEAVY": "1", "CFLR_SPARSE_DIRECT": "200"},
+    "heavy_no_row_clear": {"CFLR_SPARSE_HEAVY": "1", "CFLR_SPARSE_DIRECT": "0", "CFLR_SPARSE_ROWF": "0"},
     "all_light": {"CFLR_SPARSE_HEAVY": str(1 << 62)},
     "ungrouped": {"CFLR_SPARSE_UNGROUPED": "1"},
 }
 
+KNOBS = ("CFLR_SPARSE_HEAVY", "CFLR_SPARSE_UNGROUPED", "CFLR_SPARSE_DIRECT", "CFLR_SPARSE_ROWF")
+
 
 @pytest.fixture(params=list(MODES))
 def mode(request, monkeypatch):
-    for k in ("CFLR_SPARSE_HEAVY", "CFLR_SPARSE_UNGROUPED"):
+    for k in KNOBS:
         monkeypatch.delenv(k, raising=False)
     for k, v in MODES[request.param].items():
         monkeypatch.setenv(k, v)
