@@ -1,9 +1,10 @@
-"""Full-size parity: the 50,000-vertex memory-alias configuration and the
+"""Full-size parity: the 50,000-vertex memory-alias configuration, the
 200,000-vertex field-sensitive points-to configuration (Fig. 4b, 64 fields,
-386 non-terminals), each solved with the launch configuration bench.py times
-(default options), against the oracle's stored per-non-terminal counts and
-SHA-256 digests (tests/golden/alias_50k.json, pointsto_200k.json, written by
-tests/golden/make_goldens.py)."""
+386 non-terminals) and the 256-graph memory-alias batch, each solved with
+the launch configuration bench.py times (default options), against the
+oracle's stored per-non-terminal counts and SHA-256 digests
+(tests/golden/alias_50k.json, pointsto_200k.json, alias_batch_le8k.json,
+written by tests/golden/make_goldens.py)."""
 
 import hashlib
 import json
@@ -18,6 +19,7 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "alias_50k.json")
 GOLDEN_PT = os.path.join(os.path.dirname(__file__), "golden", "pointsto_200k.json")
+GOLDEN_BATCH = os.path.join(os.path.dirname(__file__), "golden", "alias_batch_le8k.json")
 
 
 def sha_of_pairs(s, d, chunk=1 << 26):
@@ -67,3 +69,33 @@ def test_pointsto_200k_matches_oracle_digests(ctx):
         s, d = r.pairs(x)
         assert sha_of_pairs(s, d) == gold["sha256"][x], x
         del s, d
+
+
+def test_alias_batch_matches_oracle_digests(ctx):
+    """One batched call over the whole 256-graph memory-alias batch (n
+    log-uniform in [1000, 40000]), as the batched bench mode makes it; each
+    of its 141 graphs of at most 8,000 vertices against the oracle's counts
+    and digests for every non-terminal (the oracle solved each alone)."""
+    import paper_2401_11029_amd as cflr
+    from workloads import grammars, graphs
+    with open(GOLDEN_BATCH) as f:
+        gold = json.load(f)
+    gs = graphs.alias_batch(256)
+    gr = cflr.Grammar(grammars.ALIAS_FIG5A_WCNF)
+    objs = [cflr.Graph.from_workload(ctx, g) for g in gs]
+    print("alias batch: one solve_batch call over 256 graphs", flush=True)
+    res = cflr.solve_batch(ctx, gr, objs)
+    try:
+        assert len(gold["graphs"]) == sum(1 for g in gs if g.n <= 8000)
+        for key, want in gold["graphs"].items():
+            q = int(key)
+            assert (gs[q].n, gs[q].m) == (want["n"], want["m"]), q
+            r = res[q]
+            assert r.grammar.nonterminals == want["order"]
+            assert r.counts() == want["count"], q
+            for x in want["order"]:
+                s, d = r.pairs(x)
+                assert sha_of_pairs(s, d) == want["sha256"][x], (q, x)
+    finally:
+        for r in res:
+            r.close()
