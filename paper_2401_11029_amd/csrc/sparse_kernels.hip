@@ -249,9 +249,34 @@ __global__ void round_start_kernel(State S) {
     S.ctl[kCtlHeavyTasks] = 0;
 }
 
-__device__ __forceinline__ void touch(const State &S, uint32_t layout, uint32_t r) {
-    const uint64_t idx = (uint64_t)layout * S.n + r;
-    const uint32_t p = atomicAdd(&S.cur[idx], 1u);
+// Runs of equal list index among consecutive lanes (the products emit many
+// pairs of one row together): the lane's rank in its run, the run's first
+// lane and, for that lane, the run's length.  kNoList marks no list.
+constexpr uint64_t kNoList = ~0ull;
+
+struct Run {
+    uint32_t rank, head, len;
+};
+
+__device__ __forceinline__ Run lane_run(uint64_t idx) {
+    const uint32_t lane = lane_id();
+    const uint64_t prev = shfl64(idx, lane ? lane - 1 : 0);
+    const uint64_t heads = __ballot(lane == 0 || prev != idx);
+    const uint64_t upto = lane == 63 ? ~0ull : (2ull << lane) - 1;  // lanes <= this one
+    Run r;
+    r.head = 63u - (uint32_t)__builtin_clzll(heads & upto);
+    r.rank = lane - r.head;
+    const uint64_t after = heads & ~upto;
+    r.len = (after ? (uint32_t)__builtin_ctzll(after) : 64u) - lane;
+    return r;
+}
+
+// Adds a run's pairs to its list's pending count (one atomic per run); the
+// list's first pending pair records it as touched.
+__device__ __forceinline__ void touch(const State &S, uint64_t idx) {
+    const Run r = lane_run(idx);
+    if (idx == kNoList || r.rank) return;
+    const uint32_t p = atomicAdd(&S.cur[idx], r.len);
     if (p == 0) {
         const unsigned long long t = atomicAdd(&S.ctl[kCtlTouched], 1ull);
         if (t < S.touched_cap) S.touched[t] = idx;
@@ -262,13 +287,20 @@ __device__ __forceinline__ void touch(const State &S, uint32_t layout, uint32_t 
 __global__ __launch_bounds__(256) void count_kernel(State S, PairBuf in) {
     uint64_t nin = *in.count;
     if (nin > in.cap) nin = in.cap;
-    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < nin;
-         x += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t key = in.key[x];
-        if (key == kHoleKey) continue;
-        const MatInfo mi = S.mats[key];
-        if (mi.row_layout != kNone) touch(S, mi.row_layout, in.i[x]);
-        if (mi.col_layout != kNone) touch(S, mi.col_layout, in.j[x]);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); base < nin; base += stride) {
+        const uint64_t x = base + lane_id();
+        uint64_t row = kNoList, col = kNoList;
+        if (x < nin) {
+            const uint32_t key = in.key[x];
+            if (key != kHoleKey) {
+                const MatInfo mi = S.mats[key];
+                if (mi.row_layout != kNone) row = (uint64_t)mi.row_layout * S.n + in.i[x];
+                if (mi.col_layout != kNone) col = (uint64_t)mi.col_layout * S.n + in.j[x];
+            }
+        }
+        touch(S, row);
+        touch(S, col);
     }
 }
 
@@ -369,28 +401,39 @@ __global__ __launch_bounds__(256) void copy_kernel(State S) {
     }
 }
 
+// Appends value v to list idx: a run of lanes with one list takes its
+// positions with one atomic.
+__device__ __forceinline__ void append(const State &S, uint64_t idx, uint32_t v) {
+    const Run r = lane_run(idx);
+    uint32_t p = 0;
+    if (idx != kNoList && !r.rank) p = atomicAdd(&S.cur[idx], r.len);
+    p = shfl32(p, r.head) + r.rank;
+    if (idx == kNoList) return;
+    const Dir d = S.dir[idx];
+    if (p < d.cap) S.pool[d.off + p] = v;
+}
+
 __global__ __launch_bounds__(256) void scatter_kernel(State S, PairBuf in) {
     if (S.ctl[kCtlHalt]) return;
     uint64_t nin = *in.count;
     if (nin > in.cap) nin = in.cap;
-    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < nin;
-         x += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t key = in.key[x];
-        if (key == kHoleKey) continue;
-        const MatInfo mi = S.mats[key];
-        const uint32_t i = in.i[x], j = in.j[x];
-        if (mi.row_layout != kNone) {
-            const uint64_t idx = (uint64_t)mi.row_layout * S.n + i;
-            const uint32_t p = atomicAdd(&S.cur[idx], 1u);
-            const Dir d = S.dir[idx];
-            if (p < d.cap) S.pool[d.off + p] = j;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); base < nin; base += stride) {
+        const uint64_t x = base + lane_id();
+        uint64_t row = kNoList, col = kNoList;
+        uint32_t i = 0, j = 0;
+        if (x < nin) {
+            const uint32_t key = in.key[x];
+            if (key != kHoleKey) {
+                const MatInfo mi = S.mats[key];
+                i = in.i[x];
+                j = in.j[x];
+                if (mi.row_layout != kNone) row = (uint64_t)mi.row_layout * S.n + i;
+                if (mi.col_layout != kNone) col = (uint64_t)mi.col_layout * S.n + j;
+            }
         }
-        if (mi.col_layout != kNone) {
-            const uint64_t idx = (uint64_t)mi.col_layout * S.n + j;
-            const uint32_t p = atomicAdd(&S.cur[idx], 1u);
-            const Dir d = S.dir[idx];
-            if (p < d.cap) S.pool[d.off + p] = i;
-        }
+        append(S, row, j);
+        append(S, col, i);
     }
 }
 
@@ -725,7 +768,7 @@ __global__ __launch_bounds__(256) void heavy_items_kernel(State S, KeySort K) {
 // are the item's candidates for c, each inserted into the hash set once.
 // The bit set is left zero for the next use.
 constexpr uint32_t kMaxUseWords = 8;  // uses selected through an LDS OR of the masks (512)
-constexpr uint32_t kUnroll = 4;       // passes of products whose loads are issued together
+constexpr uint32_t kUnroll = 8;       // passes of products whose loads are issued together
 constexpr uint32_t kTouchCap = 2048;  // words listed as set; past that the whole bit set is scanned
 
 // The first use at or after `from` that some entry of the item selects (its
@@ -776,33 +819,39 @@ __device__ __forceinline__ UseLoad load_use(const State &S, const KeySort &K, ui
     return L;
 }
 
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total, uint32_t *wsum) {
-    constexpr uint32_t kWaves = kHeavyThreads / 64;
-    const uint32_t wave = threadIdx.x / 64;
-    uint32_t wt;
-    const uint32_t pre = wave_excl_scan(v, &wt);
-    if (lane_id() == 0) wsum[wave] = wt;
-    __syncthreads();
-    uint32_t off = 0, tot = 0;
+// Product tt of a use -> the entry (thread) whose list holds it and the
+// position in that list.  pre: the wave-local exclusive prefix sums of the
+// entries' list lengths; o1..o3: the first product of waves 1..3.  The wave
+// is the number of wave offsets at or below tt (a wave with no products is
+// skipped, as its offset equals the next one's); within it, the last lane
+// whose first product is at or below tt (a lane with an empty list shares
+// its prefix with a later lane, which wins).
+__device__ __forceinline__ uint32_t locate(const uint32_t *pre, uint32_t o1, uint32_t o2, uint32_t o3, uint32_t tt,
+                                           uint32_t *rel) {
+    const uint32_t w = (uint32_t)(tt >= o1) + (uint32_t)(tt >= o2) + (uint32_t)(tt >= o3);
+    const uint32_t lo = w == 0 ? 0u : w == 1 ? o1 : w == 2 ? o2 : o3;
+    const uint32_t x = tt - lo;
+    uint32_t src = w * 64;
 #pragma unroll
-    for (uint32_t w = 0; w < kWaves; w++) {
-        if (w < wave) off += wsum[w];
-        tot += wsum[w];
-    }
-    __syncthreads();
-    *total = tot;
-    return pre + off;
+    for (uint32_t step = 32; step; step >>= 1)
+        if (pre[src + step] <= x) src += step;
+    *rel = x - pre[src];
+    return src;
 }
 
 __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K, PairBuf out) {
     extern __shared__ uint32_t acc[];
     __shared__ uint64_t um[kMaxUseWords];
-    __shared__ uint64_t s_off[kHeavyThreads];
-    __shared__ uint32_t s_pre[kHeavyThreads];
-    __shared__ uint32_t wsum[kHeavyThreads / 64];
+    // per use, alternating between two buffers so that one barrier per use
+    // suffices: a use's buffers are written again two uses later, after
+    // every thread has passed the next use's barrier
+    __shared__ uint64_t s_off[2][kHeavyThreads];
+    __shared__ uint32_t s_pre[2][kHeavyThreads];
+    __shared__ uint32_t wsum[2][kHeavyThreads / 64];
+    __shared__ uint32_t sh_ntouch[2];
     __shared__ uint32_t s_touch[kTouchCap];
     __shared__ unsigned long long sh_item;
-    __shared__ uint32_t sh_e1, sh_fail, sh_ntouch;
+    __shared__ uint32_t sh_e1, sh_fail;
     constexpr uint32_t kWaves = kHeavyThreads / 64;
     const uint32_t t = threadIdx.x, lane = lane_id(), wave = t / 64;
     const uint32_t nw = (S.n + 31) / 32;
@@ -813,21 +862,22 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
     for (uint32_t w = t; w < nw; w += kHeavyThreads) acc[w] = 0;
     if (t == 0) {
         sh_fail = 0;
-        sh_ntouch = 0;
+        sh_ntouch[0] = sh_ntouch[1] = 0;
     }
     // each wave emits the candidates of words [wave * per, (wave + 1) * per)
     const uint32_t per = ((nw + kWaves - 1) / kWaves + 63) / 64 * 64;
-    bool stop = false;
-    while (!stop) {
+    uint32_t par = 0;
+    while (true) {
         __syncthreads();
         if (t == 0) {
+            // an overflow here or elsewhere ends the launch at an item boundary
             unsigned long long it = atomicAdd(&S.ctl[kCtlHeavyTasks], 1ull);
-            if (load_relaxed(&S.ctl[kCtlHalt])) it = nheavy;
+            if (sh_fail || load_relaxed(&S.ctl[kCtlHalt])) it = nheavy;
             sh_item = it;
         }
         __syncthreads();
         const uint64_t h = sh_item;
-        if (h >= nheavy || sh_fail) break;
+        if (h >= nheavy) break;
         // the item: entries [e0, e1) of one bucket
         const uint32_t e0 = K.heavy[h];
         const uint64_t head = K.entry[e0];
@@ -862,17 +912,22 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
         // the uses some entry selects, in order, each loaded one use ahead
         uint32_t q = next_use(um, gathered, nuse, 0);
         UseLoad cur = load_use(S, K, q, nuse, first, mine, k, key, m0, m1, mbase, W, bytes);
-        while (q < nuse && !stop) {
+        while (q < nuse) {
             const uint32_t qn = next_use(um, gathered, nuse, q + 1);
             const UseLoad nxt = load_use(S, K, qn, nuse, first, mine, k, key, m0, m1, mbase, W, bytes);
             const Use u = cur.u;
-            uint32_t total;
-            const uint32_t pre = block_excl_scan(cur.len, &total, wsum);
-            s_pre[t] = pre;
-            s_off[t] = cur.off;
-            __syncthreads();
+            uint32_t wt;
+            const uint32_t wpre = wave_excl_scan(cur.len, &wt);
+            s_pre[par][t] = wpre;
+            s_off[par][t] = cur.off;
+            if (lane == 0) wsum[par][wave] = wt;
+            __syncthreads();  // the use's lists are in LDS; the previous use is done
+            if (t == 0) sh_ntouch[par ^ 1] = 0;  // counted into by the next use
+            const uint32_t *pre = s_pre[par];
+            const uint64_t *offs = s_off[par];
+            const uint32_t o1 = wsum[par][0], o2 = o1 + wsum[par][1], o3 = o2 + wsum[par][2];
+            const uint32_t total = o3 + wsum[par][3];
             products += total;
-            bool ok = true;
             if (total <= K.direct) {
                 // few products: each one goes to the hash set as it is
                 cands += total;
@@ -880,20 +935,16 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
                     const uint32_t tt = r + t;
                     uint32_t v = 0;
                     if (tt < total) {
-                        uint32_t src = 0;
-#pragma unroll
-                        for (uint32_t step = kHeavyThreads / 2; step; step >>= 1)
-                            if (src + step < cnt && s_pre[src + step] <= tt) src += step;
-                        v = S.pool[s_off[src] + (tt - s_pre[src])];
+                        uint32_t rel;
+                        const uint32_t src = locate(pre, o1, o2, o3, tt, &rel);
+                        v = S.pool[offs[src] + rel];
                     }
                     if (!insert_append(S, out, ch, appended, tt < total, u.c, order ? v : key, order ? key : v)) {
-                        ok = false;
+                        if (lane == 0) atomicOr(&sh_fail, 1u);
                         break;
                     }
                 }
-                if (!ok && lane == 0) atomicOr(&sh_fail, 1u);
-                __syncthreads();
-                stop = sh_fail != 0;
+                par ^= 1;
                 q = qn;
                 cur = nxt;
                 continue;
@@ -905,18 +956,16 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
                     const uint32_t tt = r + uu * kHeavyThreads + t;
                     v[uu] = 0xFFFFFFFFu;
                     if (tt < total) {
-                        uint32_t src = 0;  // last entry whose first product is <= tt
-#pragma unroll
-                        for (uint32_t step = kHeavyThreads / 2; step; step >>= 1)
-                            if (src + step < cnt && s_pre[src + step] <= tt) src += step;
-                        v[uu] = S.pool[s_off[src] + (tt - s_pre[src])];
+                        uint32_t rel;
+                        const uint32_t src = locate(pre, o1, o2, o3, tt, &rel);
+                        v[uu] = S.pool[offs[src] + rel];
                     }
                 }
                 // the first product into a word lists it (one thread sees it zero)
 #pragma unroll
                 for (uint32_t uu = 0; uu < kUnroll; uu++)
                     if (v[uu] != 0xFFFFFFFFu && !atomicOr(&acc[v[uu] >> 5], 1u << (v[uu] & 31))) {
-                        const uint32_t slot = atomicAdd(&sh_ntouch, 1u);
+                        const uint32_t slot = atomicAdd(&sh_ntouch[par], 1u);
                         if (slot < kTouchCap) s_touch[slot] = v[uu] >> 5;
                     }
             }
@@ -928,13 +977,16 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
                     atomicAnd(&acc[v >> 5], ~(1u << (v & 31)));
                 }
             }
-            __syncthreads();
-            // the listed words, else every word; each wave a quarter
-            const uint32_t ntouch = sh_ntouch;
+            __syncthreads();  // the bit set holds the use's candidates
+            // the listed words, else every word; each wave a quarter.  The
+            // words are zeroed as they are read; the next use writes the bit
+            // set only after its barrier.
+            const uint32_t ntouch = sh_ntouch[par];
             const bool listed = ntouch <= kTouchCap;
             const uint32_t span = listed ? ntouch : nw;
             const uint32_t per_w = listed ? ((ntouch + kWaves - 1) / kWaves + 63) / 64 * 64 : per;
             const uint32_t w_end = (wave + 1) * per_w < span ? (wave + 1) * per_w : span;
+            bool ok = true;
             for (uint32_t base = wave * per_w; base < w_end; base += 64) {
                 uint32_t wi = base + lane;
                 uint32_t word = 0;
@@ -972,9 +1024,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
                 }
             }
             if (!ok && lane == 0) atomicOr(&sh_fail, 1u);
-            __syncthreads();
-            if (t == 0) sh_ntouch = 0;  // read again only after the next use's scan
-            stop = sh_fail != 0;
+            par ^= 1;
             q = qn;
             cur = nxt;
         }
