@@ -208,10 +208,16 @@ def single(args):
         r = cflr.solve(ctx, gr, graph)
         log(f"warmup {w}: {r.stats()['fixpoint_ms']:.1f} ms, {r.stats()['reruns']} re-runs")
         r.close()
-    # untimed accounting solve: algorithmic bytes of the product's kernels
-    r = cflr.solve(ctx, gr, graph, count_traffic=1)
-    acct = r.stats()
-    r.close()
+    # untimed accounting solve: algorithmic bytes of the product's kernels,
+    # taken from a solve without overflow re-runs (a re-run launch is cut
+    # short and would skew the per-launch figures)
+    while True:
+        r = cflr.solve(ctx, gr, graph, count_traffic=1)
+        acct = r.stats()
+        r.close()
+        if not acct["reruns"]:
+            break
+        log(f"accounting solve had {acct['reruns']} re-runs; again with the grown buffers")
     nl = max(1, acct["heavy_launches"])
     log(f"accounting: heavy {acct['heavy_algo_bytes'] / 1e9:.1f} GB, light {acct['light_algo_bytes'] / 1e9:.1f} GB "
         f"over {nl} launches each")

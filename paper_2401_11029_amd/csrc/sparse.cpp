@@ -550,6 +550,7 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlProducts, 1, 0, s), "fill");
         hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlHeavyProducts, 2, 0, s), "fill");
         const double heavy_ms0 = res.heavy_ms, light_ms0 = res.light_ms;
+        const uint64_t heavy_b0 = res.heavy_bytes, light_b0 = res.light_bytes;
         timed_product();
         for (int attempt = 0; h_ctl[sp::kCtlHalt]; attempt++) {
             if (fixed) throw too_small("the pairs");
@@ -583,12 +584,15 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         if (log)
             std::fprintf(stderr,
                          "[cflr] sparse round %u: in %llu new %llu products %llu heavy items %llu products %llu "
-                         "candidates %llu pool %llu/%llu slots %llu heavy %.2f ms light %.2f ms\n",
+                         "candidates %llu pool %llu/%llu slots %llu heavy %.2f ms light %.2f ms "
+                         "algo bytes heavy %llu light %llu\n",
                          res.rounds, (unsigned long long)pending, (unsigned long long)fresh,
                          (unsigned long long)h_ctl[sp::kCtlProducts], (unsigned long long)h_ctl[sp::kCtlHeavy],
                          (unsigned long long)h_ctl[sp::kCtlHeavyProducts], (unsigned long long)h_ctl[sp::kCtlHeavyCand],
                          (unsigned long long)h_ctl[sp::kCtlPoolTop], (unsigned long long)pool_cap,
-                         (unsigned long long)cur_slots, res.heavy_ms - heavy_ms0, res.light_ms - light_ms0);
+                         (unsigned long long)cur_slots, res.heavy_ms - heavy_ms0, res.light_ms - light_ms0,
+                         (unsigned long long)(res.heavy_bytes - heavy_b0),
+                         (unsigned long long)(res.light_bytes - light_b0));
         pending = fresh;
         std::swap(in, out);
     }

@@ -797,6 +797,7 @@ struct UseLoad {
     Dir own;
 };
 
+template <bool kAcct>
 __device__ __forceinline__ UseLoad load_use(const State &S, const KeySort &K, uint32_t q, uint32_t nuse,
                                             uint32_t first, bool mine, uint32_t k, uint32_t key, uint64_t m0,
                                             uint64_t m1, uint64_t mbase, uint32_t W, uint64_t &bytes) {
@@ -813,7 +814,7 @@ __device__ __forceinline__ UseLoad load_use(const State &S, const KeySort &K, ui
         const Dir d = S.dir[(uint64_t)L.u.layout * S.n + k];
         L.off = d.off;
         L.len = d.len;
-        if (K.acct && first_read(K, (uint64_t)L.u.layout * S.n + k)) bytes += 4ull * d.len;
+        if (kAcct && first_read(K, (uint64_t)L.u.layout * S.n + k)) bytes += 4ull * d.len;
     }
     if (L.u.own != kNone) L.own = S.dir[(uint64_t)L.u.own * S.n + key];
     return L;
@@ -839,6 +840,9 @@ __device__ __forceinline__ uint32_t locate(const uint32_t *pre, uint32_t o1, uin
     return src;
 }
 
+// kAcct: the accounting variant (algorithmic bytes into K.acct), launched
+// only by solves that ask for it.
+template <bool kAcct>
 __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K, PairBuf out) {
     extern __shared__ uint32_t acc[];
     __shared__ uint64_t um[kMaxUseWords];
@@ -892,7 +896,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
         if (t > 0 && e0 + t < sh_e1 && item_start(K, e0 + t, bstart)) atomicMin(&sh_e1, e0 + t);
         __syncthreads();
         const uint32_t cnt = sh_e1 - e0;
-        if (K.acct && t == 0) bytes += 8ull * cnt;
+        if (kAcct && t == 0) bytes += 8ull * cnt;
         const uint32_t W = order ? mi.w1 : mi.w0, first = order ? mi.use1 : mi.use0,
                        nuse = order ? mi.nuse1 : mi.nuse0;
         const uint64_t mbase = order ? mi.mask1 : mi.mask0;
@@ -911,10 +915,10 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
         __syncthreads();
         // the uses some entry selects, in order, each loaded one use ahead
         uint32_t q = next_use(um, gathered, nuse, 0);
-        UseLoad cur = load_use(S, K, q, nuse, first, mine, k, key, m0, m1, mbase, W, bytes);
+        UseLoad cur = load_use<kAcct>(S, K, q, nuse, first, mine, k, key, m0, m1, mbase, W, bytes);
         while (q < nuse) {
             const uint32_t qn = next_use(um, gathered, nuse, q + 1);
-            const UseLoad nxt = load_use(S, K, qn, nuse, first, mine, k, key, m0, m1, mbase, W, bytes);
+            const UseLoad nxt = load_use<kAcct>(S, K, qn, nuse, first, mine, k, key, m0, m1, mbase, W, bytes);
             const Use u = cur.u;
             uint32_t wt;
             const uint32_t wpre = wave_excl_scan(cur.len, &wt);
@@ -969,8 +973,10 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
                         if (slot < kTouchCap) s_touch[slot] = v[uu] >> 5;
                     }
             }
+            // the head's pairs at the key count as read whether or not they are cleared
+            if (kAcct && t == 0 && u.own != kNone && first_read(K, (uint64_t)u.own * S.n + key))
+                bytes += 4ull * cur.own.len;
             if (u.own != kNone && (uint64_t)cur.own.len <= (uint64_t)K.row_factor * total) {
-                if (K.acct && t == 0 && first_read(K, (uint64_t)u.own * S.n + key)) bytes += 4ull * cur.own.len;
                 __syncthreads();  // every product is in the bit set
                 for (uint32_t p = t; p < cur.own.len; p += kHeavyThreads) {
                     const uint32_t v = S.pool[cur.own.off + p];
@@ -1036,7 +1042,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
         atomicAdd(&S.ctl[kCtlHeavyProducts], (unsigned long long)products);
     }
     if (lane == 0 && cands) atomicAdd(&S.ctl[kCtlHeavyCand], (unsigned long long)cands);
-    if (K.acct) {
+    if (kAcct) {
         if (lane == 0) bytes += 16ull * appended;
         if (bytes) atomicAdd(K.acct, (unsigned long long)bytes);
     }
@@ -1046,6 +1052,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
 // against the uses of its own part; entries of heavy buckets are skipped.
 // A wave claims kLightClaim tasks at a time (one counter serves them all).
 constexpr uint32_t kLightClaim = 16;
+template <bool kAcct>
 __global__ __launch_bounds__(256) void light_kernel(State S, KeySort K, PairBuf out) {
     const uint32_t lane = lane_id();
     uint64_t total = K.start[K.nb];
@@ -1054,7 +1061,7 @@ __global__ __launch_bounds__(256) void light_kernel(State S, KeySort K, PairBuf 
     const uint64_t ntask = (total + 63) / 64;
     Chunk ch;
     uint64_t appended = 0, products = 0, bytes = 0;
-    const KeySort *acct = K.acct_light ? &K : nullptr;
+    const KeySort *acct = kAcct ? &K : nullptr;
     uint64_t t = 0, t_end = 0;  // this wave's claimed tasks
     for (;; t++) {
         if (t == t_end) {
@@ -1085,7 +1092,7 @@ __global__ __launch_bounds__(256) void light_kernel(State S, KeySort K, PairBuf 
     chunk_retire(out, ch);
     add_appended(S, appended);
     if (lane == 0 && products) atomicAdd(&S.ctl[kCtlProducts], (unsigned long long)products);
-    if (acct) {
+    if (kAcct) {
         if (lane == 0) bytes += 16ull * appended;
         if (bytes) atomicAdd(K.acct_light, (unsigned long long)bytes);
     }
@@ -1328,14 +1335,20 @@ hipError_t launch_key_sort(const State &S, PairBuf in, const KeySort &K, hipStre
 
 hipError_t launch_heavy(const State &S, const KeySort &K, PairBuf out, uint32_t grid_waves, hipStream_t s) {
     const uint32_t blocks = grid_waves / 4 ? grid_waves / 4 : 1;
-    heavy_kernel<<<blocks, kHeavyThreads, (uint32_t)heavy_lds_bytes(S.n), s>>>(S, K, out);
+    if (K.acct)
+        heavy_kernel<true><<<blocks, kHeavyThreads, (uint32_t)heavy_lds_bytes(S.n), s>>>(S, K, out);
+    else
+        heavy_kernel<false><<<blocks, kHeavyThreads, (uint32_t)heavy_lds_bytes(S.n), s>>>(S, K, out);
     SP_LAUNCH_CHECK();
     return hipSuccess;
 }
 
 hipError_t launch_light(const State &S, const KeySort &K, PairBuf out, uint32_t grid_waves, hipStream_t s) {
     const uint32_t blocks = grid_waves / 4 ? grid_waves / 4 : 1;
-    light_kernel<<<blocks, 256, 0, s>>>(S, K, out);
+    if (K.acct_light)
+        light_kernel<true><<<blocks, 256, 0, s>>>(S, K, out);
+    else
+        light_kernel<false><<<blocks, 256, 0, s>>>(S, K, out);
     SP_LAUNCH_CHECK();
     return hipSuccess;
 }
