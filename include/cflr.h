@@ -87,6 +87,12 @@ typedef struct cflr_opts {
                                   keys again); 0 = 2^20 */
     uint32_t storage;          /* single solves: CFLR_STORAGE_AUTO (default),
                                   _DENSE or _SPARSE (see cflr_solve) */
+    uint32_t witness;          /* 1: record one derivation per pair for
+                                  cflr_result_witness (single-path
+                                  semantics); single solves on the sparse
+                                  engine only (AUTO then picks it), grammars
+                                  without right sides of three or more
+                                  symbols.  0 (default): none */
 } cflr_opts;
 
 /* Storage engines of a single solve (cflr_opts.storage, cflr_stats.storage). */
@@ -166,6 +172,12 @@ uint32_t cflr_grammar_num_nonterminals(const cflr_grammar *g);
 /* Name of user non-terminal nt (0-based, first-appearance order); NULL if
    out of range.  Owned by the grammar. */
 const char *cflr_grammar_nonterminal_name(const cflr_grammar *g, uint32_t nt);
+/* Terminals of the grammar (the labels its rules name), 0-based in order of
+   first appearance; in a witness (cflr_result_witness) terminal t has symbol
+   number cflr_grammar_num_nonterminals(g) + t.  The name is owned by the
+   grammar; NULL if out of range. */
+uint32_t cflr_grammar_num_terminals(const cflr_grammar *g);
+const char *cflr_grammar_terminal_name(const cflr_grammar *g, uint32_t t);
 
 /* Shape of the lowered (strict WCNF) grammar the device works on. */
 typedef struct cflr_grammar_info {
@@ -209,7 +221,8 @@ void cflr_graph_free(cflr_graph *g);
  * holds the device storage until cflr_result_free.
  * Errors: EINVAL, ENOMEM (storage does not fit), EDEVICE, EUNSUPPORTED
  * (sparse storage with semi_naive = 0, more than 2^24 - 1 vertices or 65535
- * matrices), ETIMEOUT (max_rounds reached; *out is still set and holds the
+ * matrices; witnesses with dense storage or with a right side of three or
+ * more symbols), ETIMEOUT (max_rounds reached; *out is still set and holds the
  * partial state, a subset of the fixpoint). */
 cflr_status cflr_solve(cflr_ctx *ctx, const cflr_grammar *g, const cflr_graph *graph,
                        const cflr_opts *opts, cflr_result **out);
@@ -234,7 +247,8 @@ cflr_status cflr_solve(cflr_ctx *ctx, const cflr_grammar *g, const cflr_graph *g
  * Errors: EINVAL (null arguments, an edge with a vertex >= n_vertices or a
  * label >= n_labels, capacity below the total: counts are then written but
  * no pairs), ENOMEM (the solve needs more than the region holds; message
- * names the structure), ETIMEOUT (max_rounds), EUNSUPPORTED, EDEVICE.
+ * names the structure), ETIMEOUT (max_rounds), EUNSUPPORTED (also
+ * opts->witness), EDEVICE.
  * Every call on one device shares that device's region and leaves the last
  * call's contents in it (each call clears what it needs): calls that
  * overlap on one device race, so serialise them. */
@@ -254,7 +268,9 @@ cflr_status cflr_solve_noalloc(cflr_ctx *ctx, const cflr_grammar *g, uint32_t n_
  * vertices x n partners per matrix -- sum to at most the larger of
  * 2^28 and the largest single graph's; the others wait for retirements.
  * outs: caller array of count pointers, each set to a result (or NULL on
- * failure).  Results are identical to cflr_solve of each graph alone. */
+ * failure).  Results are identical to cflr_solve of each graph alone.
+ * Batches run on dense storage without witnesses (opts->witness and
+ * storage = SPARSE give EUNSUPPORTED). */
 cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
                              const cflr_graph *const *graphs, uint32_t count,
                              const cflr_opts *opts, cflr_result **outs);
@@ -286,6 +302,28 @@ cflr_status cflr_result_count(const cflr_result *r, uint32_t nt, uint64_t *n_pai
  * EINVAL if capacity is smaller than the count (nothing is written). */
 cflr_status cflr_result_copy(const cflr_result *r, uint32_t nt, uint32_t *src, uint32_t *dst,
                              uint64_t capacity, int on_device, uint64_t *written);
+/* Single-path semantics (the footnote to Section 5: the same fixpoint over
+ * a semiring that carries, for each pair, one derivation).  For a solve with
+ * cflr_opts.witness = 1, one derivation of every pair of nt, in the order of
+ * cflr_result_copy (arrays of capacity entries each; host or device
+ * pointers as there; owned by the caller):
+ *   x -> eps:      left = right = mid = CFLR_NONE (and i == j);
+ *   x -> t (edge): left = symbol of terminal t, right = mid = CFLR_NONE;
+ *   x -> y z:      left = symbol of y, right = symbol of z, mid = k such
+ *                  that (i, k) is a pair of y and (k, j) one of z (for a
+ *                  terminal, an edge);
+ * where symbols number the non-terminals first, then the terminals
+ * (cflr_grammar_num_terminals).  The rule is the grammar's own or, when x
+ * reaches y' through unit rules, the rule of y' that derived the pair (x's
+ * pair then rests on the same pair of y').  round[p] = the round that
+ * derived the pair (0 for seeds); a derivation's premises come from earlier
+ * rounds, so the rounds order the pairs into a well-founded derivation.
+ * *written = entries written.  Errors: EINVAL (null, nt out of range,
+ * capacity below the count, a solve without witnesses), EDEVICE. */
+#define CFLR_NONE 0xFFFFFFFFu
+cflr_status cflr_result_witness(const cflr_result *r, uint32_t nt, uint32_t *left, uint32_t *right,
+                                uint32_t *mid, uint32_t *round, uint64_t capacity, int on_device,
+                                uint64_t *written);
 /* Statistics of the solve (rounds, pairs seeded and derived, times; see
  * cflr_stats).  Errors: EINVAL. */
 cflr_status cflr_result_stats(const cflr_result *r, cflr_stats *out);
@@ -312,7 +350,8 @@ void cflr_result_free(cflr_result *r);
  * The server runs its rounds on a stream of its own on ctx's device, so the
  * caller's thread may read results and free handles (on ctx's stream) while
  * it runs; do not start other solves on ctx while the server lives.
- * Errors (every server call sets cflr_last_error): EINVAL, ENOMEM, EDEVICE. */
+ * Errors (every server call sets cflr_last_error): EINVAL, ENOMEM, EDEVICE,
+ * EUNSUPPORTED (opts->witness). */
 cflr_status cflr_server_create(cflr_ctx *ctx, uint64_t hbm_budget_bytes, uint32_t max_slots,
                                const cflr_opts *opts, cflr_server **out);
 /* Queue a request; the grammar and graph must stay alive until its result is

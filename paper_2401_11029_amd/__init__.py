@@ -103,6 +103,17 @@ class Grammar:
         return [L.cflr_grammar_nonterminal_name(self._h, i).decode()
                 for i in range(k)]
 
+    @property
+    def terminals(self):
+        L = lib()
+        k = L.cflr_grammar_num_terminals(self._h)
+        return [L.cflr_grammar_terminal_name(self._h, i).decode() for i in range(k)]
+
+    @property
+    def symbols(self):
+        """Symbol numbering of witnesses: non-terminals, then terminals."""
+        return self.nonterminals + self.terminals
+
     def info(self) -> dict:
         i = GrammarInfo()
         _check(lib().cflr_grammar_info_get(self._h, C.byref(i)))
@@ -203,6 +214,26 @@ class Result:
         _check(lib().cflr_result_copy(self._h, k, C.c_void_p(s.ctypes.data),
                                       C.c_void_p(d.ctypes.data), cnt, 0, C.byref(w)))
         return s, d
+
+    def witness(self, nt, device=None):
+        """One derivation per pair of nt, in the order of pairs(nt), for a
+        solve with witness=1: (left, right, mid, round) arrays -- see
+        cflr_result_witness; symbols index Grammar.symbols and NONE
+        (0xFFFFFFFF) marks an absent field.  numpy uint32 arrays, or torch
+        int32 tensors on `device` when given."""
+        k = self._nt(nt)
+        cnt = self.count(k)
+        w = C.c_uint64()
+        if device is not None:
+            import torch
+            out = [torch.empty(cnt, dtype=torch.int32, device=device) for _ in range(4)]
+            ptrs = [C.c_void_p(t.data_ptr()) for t in out]
+            _check(lib().cflr_result_witness(self._h, k, *ptrs, cnt, 1, C.byref(w)))
+            return tuple(out)
+        out = [np.empty(cnt, dtype=np.uint32) for _ in range(4)]
+        ptrs = [C.c_void_p(a.ctypes.data) for a in out]
+        _check(lib().cflr_result_witness(self._h, k, *ptrs, cnt, 0, C.byref(w)))
+        return tuple(out)
 
     def pair_set(self, nt):
         s, d = self.pairs(nt)

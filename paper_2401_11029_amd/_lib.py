@@ -22,7 +22,8 @@ class Opts(C.Structure):
                 ("grid_waves", C.c_uint32),
                 ("rounds_per_sync", C.c_uint32),
                 ("chunk_pairs", C.c_uint32),
-                ("storage", C.c_uint32)]
+                ("storage", C.c_uint32),
+                ("witness", C.c_uint32)]
 
 
 class Stats(C.Structure):
@@ -78,6 +79,8 @@ SIGNATURES = {
     "cflr_grammar_num_nonterminals": (C.c_uint32, [P]),
     "cflr_grammar_nonterminal_name": (C.c_char_p, [P, C.c_uint32]),
     "cflr_grammar_info_get": (C.c_int, [P, C.POINTER(GrammarInfo)]),
+    "cflr_grammar_num_terminals": (C.c_uint32, [P]),
+    "cflr_grammar_terminal_name": (C.c_char_p, [P, C.c_uint32]),
     "cflr_graph_create": (C.c_int, [P, C.c_uint32, C.c_uint64, P, P, P, C.c_uint32,
                                     C.POINTER(C.c_char_p), C.c_int, C.POINTER(P)]),
     "cflr_graph_free": (None, [P]),
@@ -93,6 +96,8 @@ SIGNATURES = {
     "cflr_result_count": (C.c_int, [P, C.c_uint32, C.POINTER(C.c_uint64)]),
     "cflr_result_copy": (C.c_int, [P, C.c_uint32, P, P, C.c_uint64, C.c_int,
                                    C.POINTER(C.c_uint64)]),
+    "cflr_result_witness": (C.c_int, [P, C.c_uint32, P, P, P, P, C.c_uint64, C.c_int,
+                                      C.POINTER(C.c_uint64)]),
     "cflr_result_stats": (C.c_int, [P, C.POINTER(Stats)]),
     "cflr_result_free": (None, [P]),
     "cflr_server_create": (C.c_int, [P, C.c_uint64, C.c_uint32, C.POINTER(Opts),

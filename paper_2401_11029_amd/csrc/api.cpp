@@ -98,6 +98,15 @@ void set_device(cflr_ctx *ctx) { hip_check(hipSetDevice(ctx->device), "hipSetDev
 // Storage of a single solve: dense bit matrices while they take at most a
 // quarter of the device memory, else pair storage (cflr_opts.storage).
 bool use_sparse(cflr_ctx *ctx, const cflr_opts &o, const Lowered &low, uint32_t n) {
+    if (o.witness) {
+        // witnesses live in the sparse engine's pair set, and are named in the
+        // grammar text's symbols (no hidden helpers)
+        if (o.storage == CFLR_STORAGE_DENSE)
+            throw Error(CFLR_EUNSUPPORTED, "witnesses are recorded by the sparse storage only");
+        if (low.helpers) throw Error(CFLR_EUNSUPPORTED, "witnesses need right sides of at most two symbols");
+        if (!o.semi_naive) throw Error(CFLR_EUNSUPPORTED, "sparse storage runs the semi-naive rounds only");
+        return true;
+    }
     if (o.storage == CFLR_STORAGE_SPARSE) {
         if (!o.semi_naive) throw Error(CFLR_EUNSUPPORTED, "sparse storage runs the semi-naive rounds only");
         return true;
@@ -198,6 +207,13 @@ uint32_t cflr_grammar_num_nonterminals(const cflr_grammar *g) {
 const char *cflr_grammar_nonterminal_name(const cflr_grammar *g, uint32_t nt) {
     if (!g || nt >= g->low.user_names.size()) return nullptr;
     return g->low.user_names[nt].c_str();
+}
+
+uint32_t cflr_grammar_num_terminals(const cflr_grammar *g) { return g ? (uint32_t)g->low.terminals.size() : 0; }
+
+const char *cflr_grammar_terminal_name(const cflr_grammar *g, uint32_t t) {
+    if (!g || t >= g->low.terminals.size()) return nullptr;
+    return g->low.terminals[t].c_str();
 }
 
 cflr_status cflr_grammar_info_get(const cflr_grammar *g, cflr_grammar_info *out) {
@@ -355,6 +371,7 @@ cflr_status cflr_solve_noalloc(cflr_ctx *ctx, const cflr_grammar *g, uint32_t n_
         }
         set_device(ctx);
         cflr_opts o = effective(opts);
+        if (o.witness) return fail(CFLR_EUNSUPPORTED, "the no-alloc solve records no witnesses");
         sparse_solve_noalloc(ctx, g->low, n_vertices, n_edges, src, dst, label, names, o, out_src, out_dst, capacity,
                              counts, stats);
         return CFLR_OK;
@@ -375,6 +392,7 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
         cflr_opts o = effective(opts);
         if (o.storage == CFLR_STORAGE_SPARSE)
             return fail(CFLR_EUNSUPPORTED, "batched solves use dense storage only");
+        if (o.witness) return fail(CFLR_EUNSUPPORTED, "batched solves record no witnesses");
         // admission by device memory: instances join as earlier ones finish
         size_t free_b = 0, total_b = 0;
         hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
@@ -555,6 +573,24 @@ cflr_status cflr_result_copy(const cflr_result *r, uint32_t nt, uint32_t *src, u
         instance_counts(in);
         if (in.counts[nt] > 0 && (!src || !dst)) return fail(CFLR_EINVAL, "null output array");
         instance_copy(in, nt, src, dst, capacity, on_device != 0, written);
+        return CFLR_OK;
+    });
+}
+
+cflr_status cflr_result_witness(const cflr_result *r, uint32_t nt, uint32_t *left, uint32_t *right, uint32_t *mid,
+                                uint32_t *round, uint64_t capacity, int on_device, uint64_t *written) {
+    return guard([&]() -> cflr_status {
+        if (!r || !written) return fail(CFLR_EINVAL, "null argument");
+        Instance &in = *r->inst;
+        if (nt >= in.low.user_names.size()) return fail(CFLR_EINVAL, "non-terminal index out of range");
+        if (!in.sp || !in.sp->hash_slots) return fail(CFLR_EINVAL, "no witnesses: solve with cflr_opts.witness = 1");
+        set_device(in.ctx);
+        instance_counts(in);
+        const uint64_t count = (uint64_t)in.counts[nt];
+        if (capacity < count) return fail(CFLR_EINVAL, "capacity smaller than the pair count");
+        if (count && (!left || !right || !mid || !round)) return fail(CFLR_EINVAL, "null output array");
+        sparse_witness(in, nt, left, right, mid, round, count, on_device != 0);
+        *written = count;
         return CFLR_OK;
     });
 }

@@ -134,6 +134,13 @@ struct SparseStore {
     uint32_t n = 0, nlayouts = 0;
     DevBuf dir, pool;
     std::vector<uint32_t> row_layout;  // per matrix; every user non-terminal has one
+    // witnesses (single-path semantics), when the solve recorded them: the
+    // pair set, a witness per slot, and the tables that name a witness in
+    // the grammar text's symbols (per binary production its two operands;
+    // per graph label its terminal)
+    DevBuf hash, wit;
+    uint64_t hash_slots = 0;
+    std::vector<uint32_t> prod_sym, label_sym;
 };
 
 // One graph being solved (or solved): its matrices live in `arena` (dense
@@ -190,6 +197,9 @@ void sparse_solve_noalloc(cflr_ctx *ctx, const Lowered &low, uint32_t n, uint64_
                           const cflr_opts &o, uint32_t *out_src, uint32_t *out_dst, uint64_t capacity,
                           uint64_t *counts, cflr_stats *stats);
 void sparse_copy(Instance &inst, uint32_t nt, uint32_t *src, uint32_t *dst, uint64_t count, bool on_device);
+// The witnesses of nt's pairs, in the order of sparse_copy (count of them).
+void sparse_witness(Instance &inst, uint32_t nt, uint32_t *left, uint32_t *right, uint32_t *mid, uint32_t *round,
+                    uint64_t count, bool on_device);
 
 // A set of instances advancing round by round together (the product
 // launches of a round cover all of them).

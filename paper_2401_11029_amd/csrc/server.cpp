@@ -181,6 +181,7 @@ cflr_status cflr_server_create(cflr_ctx *ctx, uint64_t hbm_budget_bytes, uint32_
     set_last_error("");
     if (!ctx || !out) return server_fail(CFLR_EINVAL, "null argument");
     if (!max_slots) return server_fail(CFLR_EINVAL, "max_slots must be at least 1");
+    if (opts && opts->witness) return server_fail(CFLR_EUNSUPPORTED, "served requests record no witnesses");
     *out = nullptr;
     try {
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");

@@ -60,9 +60,10 @@ Plan make_plan(const Lowered &low, uint32_t n) {
     for (uint32_t x = 0; x < M; x++)
         if (low.slot_a[x]) P.mats[x].col_layout = P.nlayouts++;
     std::vector<std::vector<sp::Use>> u0(M), u1(M);
-    for (const auto &b : low.binary) {
-        u0[b.a].push_back(sp::Use{b.c, P.mats[b.b].row_layout, P.mats[b.c].row_layout, 0});
-        u1[b.b].push_back(sp::Use{b.c, P.mats[b.a].col_layout, P.mats[b.c].col_layout, 0});
+    for (uint32_t q = 0; q < (uint32_t)low.binary.size(); q++) {
+        const auto &b = low.binary[q];
+        u0[b.a].push_back(sp::Use{b.c, P.mats[b.b].row_layout, P.mats[b.c].row_layout, q});
+        u1[b.b].push_back(sp::Use{b.c, P.mats[b.a].col_layout, P.mats[b.c].col_layout, q});
     }
     std::vector<std::vector<sp::Obs>> ob(P.nlayouts);
     uint64_t mw = 0;
@@ -227,6 +228,8 @@ uint64_t seed_slack(uint64_t m, uint64_t eps_pairs) {
 
 struct CoreOut {
     Mem dir, pool;  // the adjacency lists, kept for readout
+    Mem hash, wit;  // the pair set and its witnesses, kept when witnesses are recorded
+    uint64_t hash_slots = 0;
     Plan plan;
     uint32_t rounds = 0, reruns = 0;
     uint64_t seed_pairs = 0, new_pairs = 0, max_delta = 0, launches = 0;
@@ -243,6 +246,10 @@ struct CoreOut {
 void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered &low, uint32_t n,
                  const SeedInput &in_seed, Alloc &A, CoreOut &res) {
     const bool fixed = A.fixed();
+    const bool witness = o.witness != 0;
+    if (witness && fixed) throw Error(CFLR_EUNSUPPORTED, "witnesses are not recorded by the no-alloc solve");
+    if (witness && low.binary.size() >= sp::kWitEps)
+        throw Error(CFLR_EUNSUPPORTED, "too many binary productions for witnesses");
     if (n >= sp::kMaxVertices) throw Error(CFLR_EUNSUPPORTED, "sparse storage holds at most 2^24 - 1 vertices");
     if (low.nmat() >= sp::kMaxMatrices) throw Error(CFLR_EUNSUPPORTED, "grammar needs 65535 or more matrices");
     const bool log = std::getenv("CFLR_LOG") != nullptr;
@@ -308,7 +315,7 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
     uint64_t hash_keys = 0;       // pairs in the table
     uint64_t tombs_resident = 0;  // tombstones in the table (a rehash drops them)
     uint64_t cur_slots = 0;
-    Mem hash;
+    Mem hash, wit;
     auto hash_need = [&](uint64_t extra) {
         return pow2_at_least((hash_keys + tombs_resident + extra + slack) * 10 / 7 + 1);
     };
@@ -319,15 +326,22 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         if (fixed && cur_slots) throw too_small("the pairs");
         Mem nh = A.get(new_slots * 8, "the hash set");
         hip_check(sp::launch_fill_u64(nh.as<unsigned long long>(), new_slots, sp::kEmpty, s), "fill");
+        Mem nw;
+        if (witness) nw = A.get(new_slots * 8, "the witnesses");
         if (cur_slots) {
             S.hash = nh.as<unsigned long long>();
             S.hash_mask = new_slots - 1;
-            hip_check(sp::launch_rehash(S, hash.as<unsigned long long>(), cur_slots, s), "rehash");
+            S.wit = witness ? nw.as<unsigned long long>() : nullptr;
+            hip_check(sp::launch_rehash(S, hash.as<unsigned long long>(), witness ? wit.as<unsigned long long>() : nullptr,
+                                        cur_slots, s),
+                      "rehash");
         }
         hash = std::move(nh);
+        if (witness) wit = std::move(nw);
         cur_slots = new_slots;
         S.hash = hash.as<unsigned long long>();
         S.hash_mask = cur_slots - 1;
+        S.wit = witness ? wit.as<unsigned long long>() : nullptr;
         tombs_resident = 0;
         hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlTomb, 1, 0, s), "fill");
     };
@@ -358,6 +372,7 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
                          std::getenv("CFLR_SPARSE_UNGROUPED") == nullptr;
     K.threshold = 512;
     if (const char *h = std::getenv("CFLR_SPARSE_HEAVY")) K.threshold = std::max<uint64_t>(1, std::strtoull(h, nullptr, 10));
+    if (witness) K.threshold = ~0ull;  // every product keeps its midpoint: no bucket goes to the bit set
     K.big_entry = 0x7FFFFFFFu;
     if (const char *h = std::getenv("CFLR_SPARSE_BIG")) K.big_entry = (uint32_t)std::strtoul(h, nullptr, 10);
     K.direct = 256;
@@ -461,6 +476,7 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
             break;
         }
         res.rounds++;
+        S.round = res.rounds;
         // room for this round: hash load, touched lists, the output buffer
         const uint64_t want_slots = hash_need(out->cap);
         if (want_slots > cur_slots) {
@@ -603,6 +619,11 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         ctx->sparse_slots_hint = std::max(ctx->sparse_slots_hint, cur_slots);
     }
     res.pool = std::move(d_pool);
+    if (witness) {
+        res.hash = std::move(hash);
+        res.wit = std::move(wit);
+        res.hash_slots = cur_slots;
+    }
     if (fixed) {
         hip_check(hipStreamSynchronize(s), "sync");
         A.release_to(fixed_mark);  // the hash set, buffers and queues are free again (readout scratch)
@@ -658,6 +679,28 @@ void sparse_solve(cflr_ctx *ctx, const cflr_opts &o, Instance &inst, bool *timed
     for (uint32_t x = 0; x < inst.low.nmat(); x++) store->row_layout[x] = res.plan.mats[x].row_layout;
     store->dir = std::move(res.dir.buf);
     store->pool = std::move(res.pool.buf);
+    if (o.witness) {
+        store->hash = std::move(res.hash.buf);
+        store->wit = std::move(res.wit.buf);
+        store->hash_slots = res.hash_slots;
+        // symbols: user non-terminals, then U + terminal index
+        const Lowered &low = inst.low;
+        const uint32_t U = (uint32_t)low.user_names.size();
+        std::vector<uint32_t> sym(low.nmat(), CFLR_NONE);
+        for (uint32_t x = 0; x < U; x++) sym[x] = x;
+        for (auto &tm : low.term)
+            if (tm.second >= U) sym[tm.second] = U + tm.first;  // a wrapper T_t -> t stands for t
+        for (auto &b : low.binary) {
+            store->prod_sym.push_back(sym[b.a]);
+            store->prod_sym.push_back(sym[b.b]);
+        }
+        std::map<std::string, uint32_t> term_id;
+        for (uint32_t t = 0; t < low.terminals.size(); t++) term_id[low.terminals[t]] = t;
+        for (auto &name : inst.graph->label_names) {
+            auto it = term_id.find(name);
+            store->label_sym.push_back(it == term_id.end() ? CFLR_NONE : U + it->second);
+        }
+    }
     inst.rounds = res.rounds;
     inst.done = !res.timed_out;
     inst.stats.rounds = res.rounds;
@@ -724,6 +767,53 @@ void sparse_copy(Instance &inst, uint32_t nt, uint32_t *src, uint32_t *dst, uint
               "readout");
     hip_check(hipMemcpyAsync(src, dsrc.ptr, count * 4, hipMemcpyDeviceToHost, s), "D2H");
     hip_check(hipMemcpyAsync(dst, ddst.ptr, count * 4, hipMemcpyDeviceToHost, s), "D2H");
+    hip_check(hipStreamSynchronize(s), "sync");
+}
+
+void sparse_witness(Instance &inst, uint32_t nt, uint32_t *left, uint32_t *right, uint32_t *mid, uint32_t *round,
+                    uint64_t count, bool on_device) {
+    SparseStore &st = *inst.sp;
+    if (!st.hash_slots) throw Error(CFLR_EINVAL, "no witnesses: solve with cflr_opts.witness = 1");
+    if (!count) return;
+    cflr_ctx *ctx = inst.ctx;
+    hipStream_t s = ctx->stream;
+    DevPool *pool = ctx->pool.get();
+    DevBuf dsrc(pool, count * 4), ddst(pool, count * 4);
+    sparse_copy(inst, nt, dsrc.as<uint32_t>(), ddst.as<uint32_t>(), count, true);
+    const uint64_t np = std::max<size_t>(1, st.prod_sym.size()), nl = std::max<size_t>(1, st.label_sym.size());
+    DevBuf psym(pool, np * 4), lsym(pool, nl * 4), miss(pool, 8);
+    if (!st.prod_sym.empty())
+        copy_sync(psym.ptr, st.prod_sym.data(), st.prod_sym.size() * 4, hipMemcpyHostToDevice, s);
+    if (!st.label_sym.empty())
+        copy_sync(lsym.ptr, st.label_sym.data(), st.label_sym.size() * 4, hipMemcpyHostToDevice, s);
+    hip_check(sp::launch_fill_u64(miss.as<unsigned long long>(), 1, 0, s), "fill");
+    DevBuf tl, tr, tm, td;
+    uint32_t *L = left, *R = right, *Md = mid, *Rd = round;
+    if (!on_device) {
+        tl = DevBuf(pool, count * 4);
+        tr = DevBuf(pool, count * 4);
+        tm = DevBuf(pool, count * 4);
+        td = DevBuf(pool, count * 4);
+        L = tl.as<uint32_t>();
+        R = tr.as<uint32_t>();
+        Md = tm.as<uint32_t>();
+        Rd = td.as<uint32_t>();
+    }
+    const uint32_t x = nt;  // user non-terminals are the first matrices
+    hip_check(sp::launch_witness(st.hash.as<unsigned long long>(), st.hash_slots - 1, st.wit.as<unsigned long long>(),
+                                 x, dsrc.as<uint32_t>(), ddst.as<uint32_t>(), count, psym.as<uint32_t>(),
+                                 (uint32_t)(st.prod_sym.size() / 2), lsym.as<uint32_t>(),
+                                 (uint32_t)st.label_sym.size(), L, R, Md, Rd, miss.as<unsigned long long>(), s),
+              "witness");
+    unsigned long long missing = 0;
+    copy_sync(&missing, miss.ptr, 8, hipMemcpyDeviceToHost, s);
+    if (missing) throw Error(CFLR_EDEVICE, "internal: a result pair has no witness in the pair set");
+    if (!on_device) {
+        hip_check(hipMemcpyAsync(left, L, count * 4, hipMemcpyDeviceToHost, s), "D2H");
+        hip_check(hipMemcpyAsync(right, R, count * 4, hipMemcpyDeviceToHost, s), "D2H");
+        hip_check(hipMemcpyAsync(mid, Md, count * 4, hipMemcpyDeviceToHost, s), "D2H");
+        hip_check(hipMemcpyAsync(round, Rd, count * 4, hipMemcpyDeviceToHost, s), "D2H");
+    }
     hip_check(hipStreamSynchronize(s), "sync");
 }
 

@@ -54,6 +54,17 @@ __host__ __device__ inline uint64_t pair_key(uint32_t m, uint32_t i, uint32_t j)
     return ((uint64_t)m << 48) | ((uint64_t)i << 24) | (uint64_t)j;
 }
 
+// Witness of a pair (single-path semantics; kept per hash slot when a solve
+// asks for it): the round that derived it (bits 48..63; seeds 0), what
+// derived it (bits 24..47: the index of a binary production, kWitEdge or
+// kWitEps) and its midpoint (bits 0..23; for an edge, the edge's graph
+// label).
+constexpr uint32_t kWitEdge = 0xFFFFFF, kWitEps = 0xFFFFFE, kWitMaxRound = 0xFFFF;
+__host__ __device__ inline uint64_t make_witness(uint32_t round, uint32_t code, uint32_t mid) {
+    const uint64_t r = round < kWitMaxRound ? round : kWitMaxRound;
+    return (r << 48) | ((uint64_t)(code & 0xFFFFFF) << 24) | (uint64_t)(mid & 0xFFFFFF);
+}
+
 // One adjacency list: entries pool[off, off + len), room for cap.
 struct Dir {
     uint64_t off;
@@ -62,13 +73,14 @@ struct Dir {
 
 // A production seen from one of its operands: the head c, the partner
 // layout the product reads (part 0: b's row layout; part 1: a's column
-// layout) and c's own layout in the candidates' orientation (part 0: its
-// row layout; part 1: its column layout; kNone when c has none).
+// layout), c's own layout in the candidates' orientation (part 0: its row
+// layout; part 1: its column layout; kNone when c has none) and the
+// production's index among the binary productions (for witnesses).
 struct Use {
     uint32_t c;
     uint32_t layout;
     uint32_t own;
-    uint32_t pad;
+    uint32_t rule;
 };
 
 // A use mask to update when a list of some layout becomes non-empty at
@@ -148,6 +160,8 @@ struct State {
     uint64_t pool_cap;
     unsigned long long *hash;  // hash slots
     uint64_t hash_mask;        // slots - 1 (a power of two minus one)
+    unsigned long long *wit;   // per hash slot, the witness of its pair (null: not kept)
+    uint32_t round;            // the round being run (0 while seeding), for witnesses
     // bookkeeping words (kCtl* below)
     unsigned long long *ctl;
     uint64_t *touched;  // lists with pending entries: layout * n + row
@@ -209,7 +223,18 @@ uint64_t key_sort_scan_blocks(uint64_t nb);
 inline uint64_t heavy_lds_bytes(uint32_t n) { return ((uint64_t)n + 31) / 32 * 4; }
 constexpr uint64_t kHeavyMaxLds = 48 * 1024;  // with the kernel's static LDS (about 15 KiB), within 64 KiB
 // Re-insert every key of `old_tab` (tombstones dropped) into S.hash (empty).
-hipError_t launch_rehash(const State &S, const unsigned long long *old_tab, uint64_t old_slots, hipStream_t s);
+hipError_t launch_rehash(const State &S, const unsigned long long *old_tab, const unsigned long long *old_wit,
+                         uint64_t old_slots, hipStream_t s);
+// Witnesses of `count` pairs (x, src[p], dst[p]) read from the hash set, in
+// symbols of the grammar text: prod_sym[2q], [2q + 1] = the operands of
+// binary production q < nprod, label_sym[l] = the terminal of graph label
+// l < nlabels.  Pairs not found, or with a witness outside these tables,
+// are counted in *missing.
+hipError_t launch_witness(const unsigned long long *tab, uint64_t hmask, const unsigned long long *wit, uint32_t x,
+                          const uint32_t *src, const uint32_t *dst, uint64_t count, const uint32_t *prod_sym,
+                          uint32_t nprod, const uint32_t *label_sym, uint32_t nlabels, uint32_t *left,
+                          uint32_t *right, uint32_t *mid, uint32_t *round, unsigned long long *missing,
+                          hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long v, hipStream_t s);
 // *bad |= 1 if some edge has src or dst >= n or label >= n_labels.
 hipError_t launch_check_edges(const uint32_t *src, const uint32_t *dst, const uint32_t *lab, uint64_t m, uint32_t n,

@@ -143,11 +143,12 @@ __device__ __forceinline__ bool chunk_reserve(const PairBuf &B, Chunk &ch, uint3
     return true;
 }
 
-// Insert (m, i, j) for the lanes with `has`; append the new ones.  Every
-// lane calls this together.  false: an overflow (this wave's new keys of
-// the call were taken back; the round is re-run).
+// Insert (m, i, j) for the lanes with `has`; append the new ones and, when
+// the solve keeps witnesses, record w for them.  Every lane calls this
+// together.  false: an overflow (this wave's new keys of the call were
+// taken back; the round is re-run).
 __device__ __forceinline__ bool insert_append(const State &S, const PairBuf &out, Chunk &ch, uint64_t &appended,
-                                              bool has, uint32_t m, uint32_t i, uint32_t j) {
+                                              bool has, uint32_t m, uint32_t i, uint32_t j, uint64_t w) {
     int ins = kPresent;
     uint64_t where = 0;
     if (has) ins = hash_insert(S.hash, S.hash_mask, pair_key(m, i, j), &where);
@@ -170,6 +171,7 @@ __device__ __forceinline__ bool insert_append(const State &S, const PairBuf &out
         out.key[pos] = m;
         out.i[pos] = i;
         out.j[pos] = j;
+        if (S.wit) S.wit[where] = w;
     }
     appended += (uint64_t)__popcll(__ballot(ins == kInserted));
     return true;
@@ -207,7 +209,8 @@ __global__ __launch_bounds__(256) void seed_edges_kernel(State S, const uint32_t
         for (uint32_t q = q0;; q++) {
             const bool has = q < q1;
             if (!__any(has)) break;
-            if (!insert_append(S, out, ch, appended, has, has ? lm_mat[q] : 0u, u, v)) {
+            if (!insert_append(S, out, ch, appended, has, has ? lm_mat[q] : 0u, u, v,
+                               make_witness(0, kWitEdge, e < m ? lab[e] : 0u))) {
                 add_appended(S, appended);
                 return;
             }
@@ -226,7 +229,7 @@ __global__ __launch_bounds__(256) void seed_eps_kernel(State S, const uint32_t *
         const uint64_t x = base + lane_id();
         const bool has = x < total;
         const uint32_t e = has ? (uint32_t)(x / S.n) : 0u, i = has ? (uint32_t)(x % S.n) : 0u;
-        if (!insert_append(S, out, ch, appended, has, has ? eps_mat[e] : 0u, i, i)) {
+        if (!insert_append(S, out, ch, appended, has, has ? eps_mat[e] : 0u, i, i, make_witness(0, kWitEps, 0))) {
             add_appended(S, appended);
             return;
         }
@@ -470,7 +473,7 @@ __device__ __forceinline__ bool expand_uses(const State &S, const PairBuf &out, 
     while (__any(more)) {
         // this lane's next use: head c, partner layout, fixed index of the
         // candidates and the partner vertex k
-        uint32_t c = 0, lay = kNone, own = kNone, fixed = 0, k = 0, col = 0;
+        uint32_t c = 0, lay = kNone, own = kNone, fixed = 0, k = 0, col = 0, rule = 0;
         if (more) {
             while (!bits) {
                 const uint32_t W = part == 0 ? mi.w0 : mi.w1;
@@ -493,6 +496,7 @@ __device__ __forceinline__ bool expand_uses(const State &S, const PairBuf &out, 
                 c = u.c;
                 lay = u.layout;
                 own = u.own;
+                rule = u.rule;
                 // part 0: pair (i, k) of a meets row k of b -> (c, i, j')
                 // part 1: pair (k, j) of b meets column k of a -> (c, i', j)
                 fixed = part == 0 ? pi : pj;
@@ -531,7 +535,10 @@ __device__ __forceinline__ bool expand_uses(const State &S, const PairBuf &out, 
                 ci = scol ? v : sfix;
                 cj = scol ? sfix : v;
             }
-            if (!insert_append(S, out, ch, appended, has, sc, ci, cj)) return false;
+            // the witness: this production, midpoint k (the source lane's partner vertex)
+            uint64_t w = 0;
+            if (S.wit) w = make_witness(S.round, shfl32(rule, src), shfl32(k, src));
+            if (!insert_append(S, out, ch, appended, has, sc, ci, cj, w)) return false;
         }
     }
     return true;
@@ -758,7 +765,8 @@ __global__ __launch_bounds__(256) void heavy_items_kernel(State S, KeySort K) {
 
 // ---------------------------------------------------------- grouped product
 
-// Heavy items, one workgroup each (taken from a counter): a run of at most
+// Heavy items (never launched with items when witnesses are kept: a
+// candidate of the bit set has lost its midpoint), one workgroup each (taken from a counter): a run of at most
 // kHeavyRun entries of one bucket, thread t holding entry t.  For every use
 // q selected by some entry of the item, the partner lists of the entries
 // selecting it are ORed into an LDS bit set over the n columns (the lists'
@@ -943,7 +951,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
                         const uint32_t src = locate(pre, o1, o2, o3, tt, &rel);
                         v = S.pool[offs[src] + rel];
                     }
-                    if (!insert_append(S, out, ch, appended, tt < total, u.c, order ? v : key, order ? key : v)) {
+                    if (!insert_append(S, out, ch, appended, tt < total, u.c, order ? v : key, order ? key : v, 0)) {
                         if (lane == 0) atomicOr(&sh_fail, 1u);
                         break;
                     }
@@ -1023,7 +1031,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
                     }
                     const bool has = tt < ctot;
                     const uint32_t v = shfl32(wi, src) * 32 + bit;
-                    if (!insert_append(S, out, ch, appended, has, u.c, order ? v : key, order ? key : v)) {
+                    if (!insert_append(S, out, ch, appended, has, u.c, order ? v : key, order ? key : v, 0)) {
                         ok = false;
                         break;
                     }
@@ -1100,16 +1108,76 @@ __global__ __launch_bounds__(256) void light_kernel(State S, KeySort K, PairBuf 
 
 // ------------------------------------------------------------------- rehash
 
-__global__ __launch_bounds__(256) void rehash_kernel(State S, const unsigned long long *old_tab, uint64_t old_slots) {
+__global__ __launch_bounds__(256) void rehash_kernel(State S, const unsigned long long *old_tab,
+                                                     const unsigned long long *old_wit, uint64_t old_slots) {
     for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < old_slots;
          x += (uint64_t)gridDim.x * blockDim.x) {
         const unsigned long long v = old_tab[x];
         if (v == kEmpty || v == kTomb) continue;
-        uint64_t where;
-        if (hash_insert(S.hash, S.hash_mask, v, &where) == kFull) {
+        uint64_t where = 0;
+        const int r = hash_insert(S.hash, S.hash_mask, v, &where);
+        if (r == kFull) {
             atomicOr(&S.ctl[kCtlHashFull], 1ull);
             atomicOr(&S.ctl[kCtlHalt], 1ull);
+        } else if (r == kInserted && S.wit) {
+            S.wit[where] = old_wit[x];
         }
+    }
+}
+
+// ---------------------------------------------------------------- witnesses
+
+// Per pair: its slot in the hash set (linear probing as inserted; every
+// pair read out is in the set), its witness decoded into the grammar
+// text's symbols.  A pair not found (none should be) is counted in
+// *missing and gets round = CFLR_NONE.
+__global__ __launch_bounds__(256) void witness_kernel(const unsigned long long *tab, uint64_t hmask,
+                                                      const unsigned long long *wit, uint32_t x, const uint32_t *src,
+                                                      const uint32_t *dst, uint64_t count, const uint32_t *prod_sym,
+                                                      uint32_t nprod, const uint32_t *label_sym, uint32_t nlabels,
+                                                      uint32_t *left, uint32_t *right, uint32_t *mid, uint32_t *round,
+                                                      unsigned long long *missing) {
+    constexpr uint32_t kNoSym = 0xFFFFFFFFu;
+    for (uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; p < count;
+         p += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = pair_key(x, src[p], dst[p]);
+        uint64_t h = mix64(key) & hmask;
+        bool found = false;
+        for (uint64_t probes = 0; probes <= hmask; probes++) {
+            const unsigned long long v = tab[h];
+            if (v == key) {
+                found = true;
+                break;
+            }
+            if (v == kEmpty) break;
+            h = (h + 1) & hmask;
+        }
+        uint32_t l = kNoSym, r = kNoSym, md = kNoSym, rd = kNoSym;
+        bool ok = found;
+        if (found) {
+            const uint64_t w = wit[h];
+            const uint32_t code = (uint32_t)(w >> 24) & 0xFFFFFFu, low = (uint32_t)w & 0xFFFFFFu;
+            rd = (uint32_t)(w >> 48);
+            if (code == kWitEdge) {
+                ok = low < nlabels;
+                if (ok) l = label_sym[low];
+            } else if (code != kWitEps) {
+                ok = code < nprod;
+                if (ok) {
+                    l = prod_sym[2 * (uint64_t)code];
+                    r = prod_sym[2 * (uint64_t)code + 1];
+                    md = low;
+                }
+            }
+        }
+        if (!ok) {
+            rd = kNoSym;
+            atomicAdd(missing, 1ull);
+        }
+        left[p] = l;
+        right[p] = r;
+        mid[p] = md;
+        round[p] = rd;
     }
 }
 
@@ -1353,8 +1421,21 @@ hipError_t launch_light(const State &S, const KeySort &K, PairBuf out, uint32_t 
     return hipSuccess;
 }
 
-hipError_t launch_rehash(const State &S, const unsigned long long *old_tab, uint64_t old_slots, hipStream_t s) {
-    rehash_kernel<<<grid_for(old_slots, 256, 65536), 256, 0, s>>>(S, old_tab, old_slots);
+hipError_t launch_rehash(const State &S, const unsigned long long *old_tab, const unsigned long long *old_wit,
+                         uint64_t old_slots, hipStream_t s) {
+    rehash_kernel<<<grid_for(old_slots, 256, 65536), 256, 0, s>>>(S, old_tab, old_wit, old_slots);
+    SP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_witness(const unsigned long long *tab, uint64_t hmask, const unsigned long long *wit, uint32_t x,
+                          const uint32_t *src, const uint32_t *dst, uint64_t count, const uint32_t *prod_sym,
+                          uint32_t nprod, const uint32_t *label_sym, uint32_t nlabels, uint32_t *left,
+                          uint32_t *right, uint32_t *mid, uint32_t *round, unsigned long long *missing,
+                          hipStream_t s) {
+    if (!count) return hipSuccess;
+    witness_kernel<<<grid_for(count, 256, 65536), 256, 0, s>>>(tab, hmask, wit, x, src, dst, count, prod_sym, nprod,
+                                                               label_sym, nlabels, left, right, mid, round, missing);
     SP_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -133,11 +133,33 @@ def test_failing_server_calls_set_the_error_message(cflr_lib):
     assert L.cflr_last_error() != b""
 
 
-def test_storage_option_and_stat_fields():
+def _struct_fields(name):
+    """Field names of `typedef struct name { ... } name;` in include/cflr.h."""
+    import re
+    with open(os.path.join(ROOT, "include", "cflr.h")) as f:
+        text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), text, re.S).group(1)
+    return re.findall(r"\b(?:uint32_t|uint64_t|double|int)\s+(\w+);", body)
+
+
+def test_binding_structs_mirror_the_header():
     import paper_2401_11029_amd as cflr
     from paper_2401_11029_amd._lib import Opts, Stats
-    # the storage choice is the last field of the options and of the stats
-    assert Opts._fields_[-1][0] == "storage"
-    assert [f[0] for f in Stats._fields_[-6:]] == ["storage", "heavy_ms", "heavy_launches", "heavy_algo_bytes",
-                                                   "light_ms", "light_algo_bytes"]
+    assert [f[0] for f in Opts._fields_] == _struct_fields("cflr_opts")
+    assert [f[0] for f in Stats._fields_] == _struct_fields("cflr_stats")
     assert cflr.opts().storage == 0 and cflr.opts(storage=2).storage == 2
+    assert cflr.opts().witness == 0 and cflr.opts(witness=1).witness == 1
+
+
+def test_grammar_symbols_for_witnesses():
+    import ctypes as C
+    import paper_2401_11029_amd as cflr
+    g = cflr.Grammar("S -> eps | a S b | S S\nT -> c\n")
+    assert g.nonterminals == ["S", "T"]
+    assert sorted(g.terminals) == ["a", "b", "c"]
+    assert g.symbols == g.nonterminals + g.terminals
+    L = cflr.lib()
+    assert L.cflr_grammar_terminal_name(g._h, 3) is None
+    w = C.c_uint64()
+    assert L.cflr_result_witness(None, 0, None, None, None, None, 0, 0, C.byref(w)) == 1
+    assert L.cflr_last_error() != b""

@@ -99,3 +99,64 @@ def test_alias_batch_matches_oracle_digests(ctx):
     finally:
         for r in res:
             r.close()
+
+
+def test_pointsto_200k_witnesses_on_a_sample(ctx):
+    """Witnesses at full size: the solve with witnesses gives the oracle's
+    counts; for 2,000 sampled pairs of each of eight non-terminals (both
+    sides of field 0 and PT, FT), the witness's premises are pairs of the
+    result (or edges of the graph) derived in earlier rounds -- the
+    soundness condition of a derivation, checked one pair at a time."""
+    import paper_2401_11029_amd as cflr
+    with open(GOLDEN_PT) as f:
+        gold = json.load(f)
+    text, g = workloads.config("pointsto_200k")
+    gr = cflr.Grammar(text)
+    r = cflr.solve(ctx, gr, cflr.Graph.from_workload(ctx, g), witness=1)
+    st = r.stats()
+    print(f"pointsto_200k with witnesses: {st['rounds']} rounds, {st['fixpoint_ms']:.0f} ms", flush=True)
+    assert st["total_pairs"] == gold["total"]
+    syms = gr.symbols
+    U = len(gr.nonterminals)
+    n = g.n
+    edges = {}
+    for name in set(g.label_names):
+        k = g.label_names.index(name)
+        sel = g.label == k
+        edges[name] = np.unique(g.src[sel].astype(np.uint64) * n + g.dst[sel].astype(np.uint64))
+    cache = {}
+
+    def keys_and_rounds(x):
+        # sorted pair keys of non-terminal x and the round of each
+        if x not in cache:
+            s, d = r.pairs(x)
+            _, _, _, rd = r.witness(x)
+            cache[x] = (s.astype(np.uint64) * n + d.astype(np.uint64), rd)
+        return cache[x]
+
+    def premise_round(sym, i, j):
+        key = np.uint64(i) * np.uint64(n) + np.uint64(j)
+        if sym >= U:                                   # a terminal: an edge, present before round 1
+            e = edges.get(syms[sym])
+            ok = e is not None and np.searchsorted(e, key) < e.size and e[np.searchsorted(e, key)] == key
+            return 0 if ok else None
+        keys, rd = keys_and_rounds(syms[sym])
+        p = np.searchsorted(keys, key)
+        return int(rd[p]) if p < keys.size and keys[p] == key else None
+
+    rng = np.random.Generator(np.random.PCG64(7))
+    for x in ("PT", "FT", "LP_0", "FS_0", "LPFS_0", "SP_0", "FL_0", "SPFL_0"):
+        keys, rd = keys_and_rounds(x)
+        left, right, mid, _ = r.witness(x)
+        assert keys.size == gold["count"][x], x
+        for p in rng.choice(keys.size, size=min(2000, keys.size), replace=False).tolist():
+            i, j = int(keys[p] // n), int(keys[p] % n)
+            if right[p] == 0xFFFFFFFF:                 # an edge x -> t
+                assert left[p] != 0xFFFFFFFF and premise_round(int(left[p]), i, j) == 0, (x, i, j)
+                continue
+            k = int(mid[p])
+            ra = premise_round(int(left[p]), i, k)
+            rb = premise_round(int(right[p]), k, j)
+            assert ra is not None and rb is not None, (x, i, j, k)
+            assert ra < rd[p] and rb < rd[p], (x, i, j, k, ra, rb, int(rd[p]))
+    r.close()
