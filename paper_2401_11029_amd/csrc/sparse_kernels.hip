@@ -862,6 +862,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
     __shared__ uint32_t wsum[2][kHeavyThreads / 64];
     __shared__ uint32_t sh_ntouch[2];
     __shared__ uint32_t s_touch[kTouchCap];
+    __shared__ uint64_t ubig[kMaxUseWords];  // uses whose products go through the bit set
     __shared__ unsigned long long sh_item;
     __shared__ uint32_t sh_e1, sh_fail;
     constexpr uint32_t kWaves = kHeavyThreads / 64;
@@ -871,6 +872,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
     if (nheavy > K.heavy_cap) nheavy = K.heavy_cap;
     Chunk ch;
     uint64_t appended = 0, products = 0, cands = 0, bytes = 0;
+    uint64_t wprod = 0;  // this wave's products of small uses
     for (uint32_t w = t; w < nw; w += kHeavyThreads) acc[w] = 0;
     if (t == 0) {
         sh_fail = 0;
@@ -921,11 +923,80 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
                 if (gathered && m) atomicOr((unsigned long long *)&um[w], (unsigned long long)m);
             }
         __syncthreads();
-        // the uses some entry selects, in order, each loaded one use ahead
-        uint32_t q = next_use(um, gathered, nuse, 0);
+        // Each selected use's products over the item (its entries' list
+        // lengths summed in LDS, in the word list's space, free between
+        // items).  A use with at most K.direct of them skips the bit set:
+        // each wave inserts its own entries' products into the hash set, with
+        // no barrier; the others go through the bit set below.
+        if (gathered) {
+            uint32_t *tot = s_touch;
+            for (uint32_t q2 = t; q2 < nuse; q2 += kHeavyThreads) tot[q2] = 0;
+            if (t < kMaxUseWords) ubig[t] = 0;
+            __syncthreads();
+            if (mine)
+                for (uint32_t w = 0; w < W; w++) {
+                    uint64_t bits = w == 0 ? m0 : w == 1 ? m1 : S.mask[mbase + (uint64_t)k * W + w];
+                    while (bits) {
+                        const uint32_t q2 = w * 64 + (uint32_t)__builtin_ctzll(bits);
+                        bits &= bits - 1;
+                        const uint32_t len = S.dir[(uint64_t)S.uses[first + q2].layout * S.n + k].len;
+                        if (len) atomicAdd(&tot[q2], len);
+                    }
+                }
+            __syncthreads();
+            for (uint32_t q2 = t; q2 < nuse; q2 += kHeavyThreads)
+                if (tot[q2] > K.direct) atomicOr((unsigned long long *)&ubig[q2 / 64], 1ull << (q2 % 64));
+            __syncthreads();
+            bool wok = true;
+            for (uint32_t w = 0; w < W && wok; w++) {
+                uint64_t bits = um[w] & ~ubig[w];
+                while (bits && wok) {
+                    const uint32_t q2 = w * 64 + (uint32_t)__builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    const Use u = S.uses[first + q2];
+                    bool sel = false;
+                    if (mine) {
+                        const uint64_t m = q2 < 64 ? m0 : q2 < 128 ? m1 : S.mask[mbase + (uint64_t)k * W + q2 / 64];
+                        sel = (m >> (q2 % 64)) & 1;
+                    }
+                    uint64_t off = 0;
+                    uint32_t len = 0;
+                    if (sel) {
+                        const Dir d = S.dir[(uint64_t)u.layout * S.n + k];
+                        off = d.off;
+                        len = d.len;
+                        if (kAcct && first_read(K, (uint64_t)u.layout * S.n + k)) bytes += 4ull * d.len;
+                    }
+                    if (kAcct && t == 0 && u.own != kNone && first_read(K, (uint64_t)u.own * S.n + key))
+                        bytes += 4ull * S.dir[(uint64_t)u.own * S.n + key].len;
+                    uint32_t wtot;
+                    const uint32_t pre = wave_excl_scan(len, &wtot);
+                    wprod += wtot;
+                    for (uint32_t r = 0; r < wtot; r += 64) {
+                        const uint32_t tt = r + lane;
+                        uint32_t src = 0;  // last lane whose first product is <= tt
+#pragma unroll
+                        for (uint32_t step = 32; step; step >>= 1)
+                            if (shfl32(pre, src + step) <= tt) src += step;
+                        const uint64_t soff = shfl64(off, src);
+                        const uint32_t spre = shfl32(pre, src);
+                        const bool has = tt < wtot;
+                        const uint32_t v = has ? S.pool[soff + (tt - spre)] : 0u;
+                        if (!insert_append(S, out, ch, appended, has, u.c, order ? v : key, order ? key : v, 0)) {
+                            wok = false;
+                            break;
+                        }
+                    }
+                }
+            }
+            if (!wok && lane == 0) atomicOr(&sh_fail, 1u);
+        }
+        // the other uses, in order, each loaded one use ahead
+        const uint64_t *sel_uses = gathered ? ubig : um;
+        uint32_t q = next_use(sel_uses, gathered, nuse, 0);
         UseLoad cur = load_use<kAcct>(S, K, q, nuse, first, mine, k, key, m0, m1, mbase, W, bytes);
         while (q < nuse) {
-            const uint32_t qn = next_use(um, gathered, nuse, q + 1);
+            const uint32_t qn = next_use(sel_uses, gathered, nuse, q + 1);
             const UseLoad nxt = load_use<kAcct>(S, K, qn, nuse, first, mine, k, key, m0, m1, mbase, W, bytes);
             const Use u = cur.u;
             uint32_t wt;
@@ -1049,6 +1120,11 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
         atomicAdd(&S.ctl[kCtlProducts], (unsigned long long)products);
         atomicAdd(&S.ctl[kCtlHeavyProducts], (unsigned long long)products);
     }
+    if (lane == 0 && wprod) {
+        atomicAdd(&S.ctl[kCtlProducts], (unsigned long long)wprod);
+        atomicAdd(&S.ctl[kCtlHeavyProducts], (unsigned long long)wprod);
+    }
+    cands += wprod;
     if (lane == 0 && cands) atomicAdd(&S.ctl[kCtlHeavyCand], (unsigned long long)cands);
     if (kAcct) {
         if (lane == 0) bytes += 16ull * appended;
