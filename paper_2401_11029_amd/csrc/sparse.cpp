@@ -373,8 +373,6 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
     K.threshold = 512;
     if (const char *h = std::getenv("CFLR_SPARSE_HEAVY")) K.threshold = std::max<uint64_t>(1, std::strtoull(h, nullptr, 10));
     if (witness) K.threshold = ~0ull;  // every product keeps its midpoint: no bucket goes to the bit set
-    K.big_entry = 0x7FFFFFFFu;
-    if (const char *h = std::getenv("CFLR_SPARSE_BIG")) K.big_entry = (uint32_t)std::strtoul(h, nullptr, 10);
     K.direct = 256;
     if (const char *h = std::getenv("CFLR_SPARSE_DIRECT")) K.direct = (uint32_t)std::strtoul(h, nullptr, 10);
     K.row_factor = 4;

@@ -119,7 +119,6 @@ struct KeySort {
                                // first entry of a run of at most kHeavyRun entries
     uint64_t heavy_cap;
     uint64_t threshold;
-    uint32_t big_entry;        // products that make an entry a heavy item of its own
     uint32_t direct;           // a heavy item's use with at most this many products inserts
                                // them into the hash set directly (no bit set)
     uint32_t row_factor;       // a heavy item clears the head's pairs at its key from the

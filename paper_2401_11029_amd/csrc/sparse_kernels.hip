@@ -580,38 +580,58 @@ __device__ __forceinline__ uint64_t pack_entry(uint32_t x, uint32_t key, uint32_
     return ((uint64_t)x << 48) | ((uint64_t)key << 24) | (uint64_t)partner;
 }
 
+// Runs of lanes with one bucket (pairs the product emitted for one key
+// together) take one atomic per run, as the list appends do.
 __global__ __launch_bounds__(256) void key_count_kernel(State S, PairBuf in, KeySort K) {
     uint64_t nin = *in.count;
     if (nin > in.cap) nin = in.cap;
-    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < nin;
-         x += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t key = in.key[x];
-        if (key == kHoleKey) continue;
-        const MatInfo mi = S.mats[key];
-        if (mi.rank0 != kNone) atomicAdd(&K.start[(uint64_t)mi.rank0 * S.n + in.i[x]], 1u);
-        if (mi.rank1 != kNone) atomicAdd(&K.start[K.nb0 + (uint64_t)mi.rank1 * S.n + in.j[x]], 1u);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); base < nin; base += stride) {
+        const uint64_t x = base + lane_id();
+        uint64_t b0 = kNoList, b1 = kNoList;
+        if (x < nin) {
+            const uint32_t key = in.key[x];
+            if (key != kHoleKey) {
+                const MatInfo mi = S.mats[key];
+                if (mi.rank0 != kNone) b0 = (uint64_t)mi.rank0 * S.n + in.i[x];
+                if (mi.rank1 != kNone) b1 = K.nb0 + (uint64_t)mi.rank1 * S.n + in.j[x];
+            }
+        }
+        const Run r0 = lane_run(b0), r1 = lane_run(b1);
+        if (b0 != kNoList && !r0.rank) atomicAdd(&K.start[b0], r0.len);
+        if (b1 != kNoList && !r1.rank) atomicAdd(&K.start[b1], r1.len);
     }
 }
 
-// The counts hold inclusive ends: taking one off the end places an entry
-// and leaves the bucket's first position behind.
+// The counts hold inclusive ends: taking a run's length off the end places
+// its entries and, once every entry is placed, leaves the bucket's first
+// position behind.
 __global__ __launch_bounds__(256) void key_scatter_kernel(State S, PairBuf in, KeySort K) {
     uint64_t nin = *in.count;
     if (nin > in.cap) nin = in.cap;
-    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < nin;
-         x += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t key = in.key[x];
-        if (key == kHoleKey) continue;
-        const MatInfo mi = S.mats[key];
-        const uint32_t i = in.i[x], j = in.j[x];
-        if (mi.rank0 != kNone) {
-            const uint32_t p = atomicSub(&K.start[(uint64_t)mi.rank0 * S.n + i], 1u) - 1;
-            if (p < K.entry_cap) K.entry[p] = pack_entry(key, i, j);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); base < nin; base += stride) {
+        const uint64_t x = base + lane_id();
+        uint64_t b0 = kNoList, b1 = kNoList;
+        uint32_t key = 0, i = 0, j = 0;
+        if (x < nin) {
+            key = in.key[x];
+            if (key != kHoleKey) {
+                const MatInfo mi = S.mats[key];
+                i = in.i[x];
+                j = in.j[x];
+                if (mi.rank0 != kNone) b0 = (uint64_t)mi.rank0 * S.n + i;
+                if (mi.rank1 != kNone) b1 = K.nb0 + (uint64_t)mi.rank1 * S.n + j;
+            }
         }
-        if (mi.rank1 != kNone) {
-            const uint32_t p = atomicSub(&K.start[K.nb0 + (uint64_t)mi.rank1 * S.n + j], 1u) - 1;
-            if (p < K.entry_cap) K.entry[p] = pack_entry(key, j, i);
-        }
+        const Run r0 = lane_run(b0), r1 = lane_run(b1);
+        uint32_t p0 = 0, p1 = 0;
+        if (b0 != kNoList && !r0.rank) p0 = atomicSub(&K.start[b0], r0.len);
+        if (b1 != kNoList && !r1.rank) p1 = atomicSub(&K.start[b1], r1.len);
+        p0 = shfl32(p0, r0.head) - 1 - r0.rank;  // the run's slots end at the old end
+        p1 = shfl32(p1, r1.head) - 1 - r1.rank;
+        if (b0 != kNoList && p0 < K.entry_cap) K.entry[p0] = pack_entry(key, i, j);
+        if (b1 != kNoList && p1 < K.entry_cap) K.entry[p1] = pack_entry(key, j, i);
     }
 }
 
@@ -735,17 +755,12 @@ __global__ __launch_bounds__(256) void classify_kernel(State S, KeySort K) {
     }
 }
 
-// Is entry e of a heavy bucket starting at bstart the first of an item?  Items
-// are runs of at most kHeavyRun entries (restarting every kHeavyRun entries of
-// the bucket), and an entry with kBigEntry products or more is an item of
-// its own (K.big_entry), so that no item holds a workgroup much longer than
-// the others.
-__device__ __forceinline__ bool item_start(const KeySort &K, uint64_t e, uint64_t bstart) {
-    if (e == bstart || (e - bstart) % kHeavyRun == 0) return true;
-    return K.ework[e] >= K.big_entry || K.ework[e - 1] >= K.big_entry;
-}
-
-// The items of the heavy buckets, listed by their first entry.
+// Items: the runs of a heavy bucket's entries that do not cross a multiple
+// of kHeavyRun in the sorted order (at most kHeavyRun entries each).  Entry
+// e starts one when it starts its bucket -- its (matrix, key) differs from
+// entry e - 1's, or it is the first of a part -- or when e is a multiple of
+// kHeavyRun; the neighbour comparison replaces a lookup of the bucket's
+// start.  The items of the heavy buckets are listed by their first entry.
 __global__ __launch_bounds__(256) void heavy_items_kernel(State S, KeySort K) {
     uint64_t total = K.start[K.nb];
     if (total > K.entry_cap) total = K.entry_cap;
@@ -753,11 +768,13 @@ __global__ __launch_bounds__(256) void heavy_items_kernel(State S, KeySort K) {
     for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total;
          e += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t v = K.entry[e];
+        const bool starts = e == 0 || e == total0 || e % kHeavyRun == 0 || (K.entry[e - 1] >> 24) != (v >> 24);
+        if (!starts) continue;
         const uint32_t x = (uint32_t)(v >> 48), key = (uint32_t)(v >> 24) & 0xFFFFFFu;
         const uint32_t order = e >= total0 ? 1u : 0u;
         const MatInfo mi = S.mats[x];
         const uint64_t b = order ? K.nb0 + (uint64_t)mi.rank1 * S.n + key : (uint64_t)mi.rank0 * S.n + key;
-        if (K.work[b] < K.threshold || !item_start(K, e, K.start[b])) continue;
+        if (K.work[b] < K.threshold) continue;
         const unsigned long long h = atomicAdd(&S.ctl[kCtlHeavy], 1ull);
         if (h < K.heavy_cap) K.heavy[h] = (uint32_t)e;
     }
@@ -864,7 +881,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
     __shared__ uint32_t s_touch[kTouchCap];
     __shared__ uint64_t ubig[kMaxUseWords];  // uses whose products go through the bit set
     __shared__ unsigned long long sh_item;
-    __shared__ uint32_t sh_e1, sh_fail;
+    __shared__ uint32_t sh_fail;
     constexpr uint32_t kWaves = kHeavyThreads / 64;
     const uint32_t t = threadIdx.x, lane = lane_id(), wave = t / 64;
     const uint32_t nw = (S.n + 31) / 32;
@@ -899,13 +916,11 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
         const uint32_t order = e0 >= K.start[K.nb0] ? 1u : 0u;
         const MatInfo mi = S.mats[x];
         const uint64_t b = order ? K.nb0 + (uint64_t)mi.rank1 * S.n + key : (uint64_t)mi.rank0 * S.n + key;
-        const uint32_t bstart = K.start[b], bend = K.start[b + 1];
-        if (t == 0) sh_e1 = bend - e0 > kHeavyRun ? e0 + kHeavyRun : bend;
+        // the item ends with its bucket or at the next multiple of kHeavyRun
+        const uint32_t bend = K.start[b + 1], run_end = (e0 / kHeavyRun + 1) * kHeavyRun;
+        const uint32_t cnt = (bend < run_end ? bend : run_end) - e0;
         if (t < kMaxUseWords) um[t] = 0;
         __syncthreads();
-        if (t > 0 && e0 + t < sh_e1 && item_start(K, e0 + t, bstart)) atomicMin(&sh_e1, e0 + t);
-        __syncthreads();
-        const uint32_t cnt = sh_e1 - e0;
         if (kAcct && t == 0) bytes += 8ull * cnt;
         const uint32_t W = order ? mi.w1 : mi.w0, first = order ? mi.use1 : mi.use0,
                        nuse = order ? mi.nuse1 : mi.nuse0;
