@@ -182,6 +182,18 @@ __device__ __forceinline__ void add_appended(const State &S, uint64_t appended) 
     if (lane_id() == 0 && appended) atomicAdd(&S.ctl[kCtlNew], (unsigned long long)appended);
 }
 
+// Lanes with `want` take consecutive slots of a device counter: one atomic
+// per wave; every lane calls this together.  Returns the lane's slot (valid
+// where want).
+__device__ __forceinline__ uint64_t wave_reserve(unsigned long long *ctr, bool want) {
+    const uint64_t mask = __ballot(want);
+    if (!mask) return 0;
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(ctr, (unsigned long long)__popcll(mask));
+    base = first_lane64(base);
+    return base + (uint64_t)__popcll(mask & ((1ull << lane_id()) - 1));
+}
+
 __device__ __forceinline__ uint64_t wave_global_id() {
     return ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
 }
@@ -278,13 +290,13 @@ __device__ __forceinline__ Run lane_run(uint64_t idx) {
 // list's first pending pair records it as touched.
 __device__ __forceinline__ void touch(const State &S, uint64_t idx) {
     const Run r = lane_run(idx);
-    if (idx == kNoList || r.rank) return;
-    const uint32_t p = atomicAdd(&S.cur[idx], r.len);
-    if (p == 0) {
-        const unsigned long long t = atomicAdd(&S.ctl[kCtlTouched], 1ull);
-        if (t < S.touched_cap) S.touched[t] = idx;
-        else atomicOr(&S.ctl[kCtlTouchedOver], 1ull);
-    }
+    uint32_t p = 1;
+    if (idx != kNoList && !r.rank) p = atomicAdd(&S.cur[idx], r.len);
+    const bool first = p == 0;
+    const uint64_t t = wave_reserve(&S.ctl[kCtlTouched], first);
+    if (!first) return;
+    if (t < S.touched_cap) S.touched[t] = idx;
+    else atomicOr(&S.ctl[kCtlTouchedOver], 1ull);
 }
 
 __global__ __launch_bounds__(256) void count_kernel(State S, PairBuf in) {
@@ -357,25 +369,41 @@ constexpr uint32_t kInlineCopy = 16;
 __global__ __launch_bounds__(256) void move_kernel(State S) {
     if (S.ctl[kCtlHalt]) return;
     const uint64_t nt = touched_count(S);
-    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < nt; t += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t idx = S.touched[t];
-        const Dir d = S.dir[idx];
-        const uint32_t pend = S.cur[idx];
-        const uint32_t need = d.len + pend;
-        Dir nd = d;
-        nd.len = need;
-        if (need > d.cap) {
-            nd.cap = grown_cap(need);
-            nd.off = atomicAdd(&S.ctl[kCtlPoolTop], (unsigned long long)nd.cap);
+    const uint32_t lane = lane_id();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); base < nt; base += stride) {
+        const uint64_t t = base + lane;
+        uint64_t idx = 0;
+        Dir d{}, nd{};
+        uint32_t pend = 0, grow = 0;
+        if (t < nt) {
+            idx = S.touched[t];
+            d = S.dir[idx];
+            pend = S.cur[idx];
+            nd = d;
+            nd.len = d.len + pend;
+            if (nd.len > d.cap) {
+                nd.cap = grown_cap(nd.len);
+                grow = nd.cap;
+            }
+        }
+        // the wave's new blocks: one reservation of the pool for all of them
+        uint32_t tot;
+        const uint32_t pre = wave_excl_scan(grow, &tot);
+        unsigned long long top = 0;
+        if (lane == 0 && tot) top = atomicAdd(&S.ctl[kCtlPoolTop], (unsigned long long)tot);
+        top = first_lane64(top);
+        const bool queue = grow && d.len > kInlineCopy;
+        const uint64_t mv = wave_reserve(&S.ctl[kCtlMoves], queue);
+        if (t >= nt) continue;
+        if (grow) {
+            nd.off = top + pre;
             bool queued = false;
-            if (d.len > kInlineCopy) {
-                const unsigned long long mv = atomicAdd(&S.ctl[kCtlMoves], 1ull);
-                if (mv < S.moves_cap) {
-                    S.moves[3 * mv] = d.off;
-                    S.moves[3 * mv + 1] = nd.off;
-                    S.moves[3 * mv + 2] = d.len;
-                    queued = true;
-                }
+            if (queue && mv < S.moves_cap) {
+                S.moves[3 * mv] = d.off;
+                S.moves[3 * mv + 1] = nd.off;
+                S.moves[3 * mv + 2] = d.len;
+                queued = true;
             }
             if (!queued)
                 for (uint32_t q = 0; q < d.len; q++) S.pool[nd.off + q] = S.pool[d.off + q];
@@ -765,18 +793,22 @@ __global__ __launch_bounds__(256) void heavy_items_kernel(State S, KeySort K) {
     uint64_t total = K.start[K.nb];
     if (total > K.entry_cap) total = K.entry_cap;
     const uint64_t total0 = K.start[K.nb0];
-    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total;
-         e += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t v = K.entry[e];
-        const bool starts = e == 0 || e == total0 || e % kHeavyRun == 0 || (K.entry[e - 1] >> 24) != (v >> 24);
-        if (!starts) continue;
-        const uint32_t x = (uint32_t)(v >> 48), key = (uint32_t)(v >> 24) & 0xFFFFFFu;
-        const uint32_t order = e >= total0 ? 1u : 0u;
-        const MatInfo mi = S.mats[x];
-        const uint64_t b = order ? K.nb0 + (uint64_t)mi.rank1 * S.n + key : (uint64_t)mi.rank0 * S.n + key;
-        if (K.work[b] < K.threshold) continue;
-        const unsigned long long h = atomicAdd(&S.ctl[kCtlHeavy], 1ull);
-        if (h < K.heavy_cap) K.heavy[h] = (uint32_t)e;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); base < total; base += stride) {
+        const uint64_t e = base + lane_id();
+        bool item = false;
+        if (e < total) {
+            const uint64_t v = K.entry[e];
+            if (e == 0 || e == total0 || e % kHeavyRun == 0 || (K.entry[e - 1] >> 24) != (v >> 24)) {
+                const uint32_t x = (uint32_t)(v >> 48), key = (uint32_t)(v >> 24) & 0xFFFFFFu;
+                const uint32_t order = e >= total0 ? 1u : 0u;
+                const MatInfo mi = S.mats[x];
+                const uint64_t b = order ? K.nb0 + (uint64_t)mi.rank1 * S.n + key : (uint64_t)mi.rank0 * S.n + key;
+                item = K.work[b] >= K.threshold;
+            }
+        }
+        const uint64_t h = wave_reserve(&S.ctl[kCtlHeavy], item);
+        if (item && h < K.heavy_cap) K.heavy[h] = (uint32_t)e;
     }
 }
 
