@@ -485,13 +485,17 @@ __device__ __forceinline__ bool first_read(const KeySort &K, uint64_t cell) {
 
 // One lane's pair (x, pi, pj) against the partner lists of its uses in
 // parts [p_lo, p_hi): the lane walks the set bits of its use masks (part 0
-// at its column pj, part 1 at its row pi), one use per step; per step the
+// at its column pj, part 1 at its row pi), one use per step, skipping the
+// uses set in `skip` (when given; up to kSkipWords words); per step the
 // wave expands the 64 lanes' partner lists together, each product a
 // candidate inserted into the hash set.  Every lane calls this together.
 // false: an overflow (the round is re-run).
+constexpr uint32_t kSkipWords = 8;
+
 __device__ __forceinline__ bool expand_uses(const State &S, const PairBuf &out, Chunk &ch, uint64_t &appended,
                                             uint64_t &products, bool valid, uint32_t x, uint32_t pi, uint32_t pj,
-                                            uint32_t p_lo, uint32_t p_hi, const KeySort *acct, uint64_t &bytes) {
+                                            uint32_t p_lo, uint32_t p_hi, const KeySort *acct, uint64_t &bytes,
+                                            const uint64_t *skip = nullptr) {
     const uint32_t lane = lane_id();
     bool more = valid;
     MatInfo mi{};
@@ -508,6 +512,7 @@ __device__ __forceinline__ bool expand_uses(const State &S, const PairBuf &out, 
                 if (part < p_hi && w < W) {
                     bits = part == 0 ? S.mask[mi.mask0 + (uint64_t)pj * mi.w0 + w]
                                      : S.mask[mi.mask1 + (uint64_t)pi * mi.w1 + w];
+                    if (skip && w < kSkipWords) bits &= ~skip[w];
                     w++;
                 } else if (part + 1 < p_hi) {
                     part++;
@@ -994,48 +999,10 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
             for (uint32_t q2 = t; q2 < nuse; q2 += kHeavyThreads)
                 if (tot[q2] > K.direct) atomicOr((unsigned long long *)&ubig[q2 / 64], 1ull << (q2 % 64));
             __syncthreads();
-            bool wok = true;
-            for (uint32_t w = 0; w < W && wok; w++) {
-                uint64_t bits = um[w] & ~ubig[w];
-                while (bits && wok) {
-                    const uint32_t q2 = w * 64 + (uint32_t)__builtin_ctzll(bits);
-                    bits &= bits - 1;
-                    const Use u = S.uses[first + q2];
-                    bool sel = false;
-                    if (mine) {
-                        const uint64_t m = q2 < 64 ? m0 : q2 < 128 ? m1 : S.mask[mbase + (uint64_t)k * W + q2 / 64];
-                        sel = (m >> (q2 % 64)) & 1;
-                    }
-                    uint64_t off = 0;
-                    uint32_t len = 0;
-                    if (sel) {
-                        const Dir d = S.dir[(uint64_t)u.layout * S.n + k];
-                        off = d.off;
-                        len = d.len;
-                        if (kAcct && first_read(K, (uint64_t)u.layout * S.n + k)) bytes += 4ull * d.len;
-                    }
-                    if (kAcct && t == 0 && u.own != kNone && first_read(K, (uint64_t)u.own * S.n + key))
-                        bytes += 4ull * S.dir[(uint64_t)u.own * S.n + key].len;
-                    uint32_t wtot;
-                    const uint32_t pre = wave_excl_scan(len, &wtot);
-                    wprod += wtot;
-                    for (uint32_t r = 0; r < wtot; r += 64) {
-                        const uint32_t tt = r + lane;
-                        uint32_t src = 0;  // last lane whose first product is <= tt
-#pragma unroll
-                        for (uint32_t step = 32; step; step >>= 1)
-                            if (shfl32(pre, src + step) <= tt) src += step;
-                        const uint64_t soff = shfl64(off, src);
-                        const uint32_t spre = shfl32(pre, src);
-                        const bool has = tt < wtot;
-                        const uint32_t v = has ? S.pool[soff + (tt - spre)] : 0u;
-                        if (!insert_append(S, out, ch, appended, has, u.c, order ? v : key, order ? key : v, 0)) {
-                            wok = false;
-                            break;
-                        }
-                    }
-                }
-            }
+            // each lane walks its own entry's small uses, the wave expanding
+            // the 64 lanes' lists together (lanes at different uses at once)
+            const bool wok = expand_uses(S, out, ch, appended, wprod, mine, x, order ? k : key, order ? key : k,
+                                         order, order + 1, kAcct ? &K : nullptr, bytes, ubig);
             if (!wok && lane == 0) atomicOr(&sh_fail, 1u);
         }
         // the other uses, in order, each loaded one use ahead
