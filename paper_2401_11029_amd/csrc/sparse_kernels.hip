@@ -789,31 +789,30 @@ __global__ __launch_bounds__(256) void classify_kernel(State S, KeySort K) {
 }
 
 // Items: the runs of a heavy bucket's entries that do not cross a multiple
-// of kHeavyRun in the sorted order (at most kHeavyRun entries each).  Entry
-// e starts one when it starts its bucket -- its (matrix, key) differs from
-// entry e - 1's, or it is the first of a part -- or when e is a multiple of
-// kHeavyRun; the neighbour comparison replaces a lookup of the bucket's
-// start.  The items of the heavy buckets are listed by their first entry.
+// of kHeavyRun in the sorted order (at most kHeavyRun entries each): the
+// bucket's first entry and every multiple of kHeavyRun inside it.  One
+// lane per bucket; a wave reserves the slots of all its items at once.
 __global__ __launch_bounds__(256) void heavy_items_kernel(State S, KeySort K) {
-    uint64_t total = K.start[K.nb];
-    if (total > K.entry_cap) total = K.entry_cap;
-    const uint64_t total0 = K.start[K.nb0];
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); base < total; base += stride) {
-        const uint64_t e = base + lane_id();
-        bool item = false;
-        if (e < total) {
-            const uint64_t v = K.entry[e];
-            if (e == 0 || e == total0 || e % kHeavyRun == 0 || (K.entry[e - 1] >> 24) != (v >> 24)) {
-                const uint32_t x = (uint32_t)(v >> 48), key = (uint32_t)(v >> 24) & 0xFFFFFFu;
-                const uint32_t order = e >= total0 ? 1u : 0u;
-                const MatInfo mi = S.mats[x];
-                const uint64_t b = order ? K.nb0 + (uint64_t)mi.rank1 * S.n + key : (uint64_t)mi.rank0 * S.n + key;
-                item = K.work[b] >= K.threshold;
-            }
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); base < K.nb; base += stride) {
+        const uint64_t b = base + lane_id();
+        uint32_t s0 = 0, s1 = 0, items = 0;
+        if (b < K.nb && K.work[b] >= K.threshold) {
+            s0 = K.start[b];
+            s1 = K.start[b + 1];
+            if (s1 > K.entry_cap) s1 = (uint32_t)K.entry_cap;
+            if (s1 > s0) items = (s1 - 1) / kHeavyRun - s0 / kHeavyRun + 1;
         }
-        const uint64_t h = wave_reserve(&S.ctl[kCtlHeavy], item);
-        if (item && h < K.heavy_cap) K.heavy[h] = (uint32_t)e;
+        uint32_t tot;
+        const uint32_t pre = wave_excl_scan(items, &tot);
+        unsigned long long h0 = 0;
+        if (lane_id() == 0 && tot) h0 = atomicAdd(&S.ctl[kCtlHeavy], (unsigned long long)tot);
+        h0 = first_lane64(h0);
+        for (uint32_t q = 0; q < items; q++) {
+            const uint64_t h = h0 + pre + q;
+            const uint32_t e = q == 0 ? s0 : (s0 / kHeavyRun + q) * kHeavyRun;
+            if (h < K.heavy_cap) K.heavy[h] = e;
+        }
     }
 }
 
@@ -1486,7 +1485,7 @@ hipError_t launch_key_sort(const State &S, PairBuf in, const KeySort &K, hipStre
     SP_LAUNCH_CHECK();
     classify_kernel<<<grid_for(2 * in.cap, 256, 8192), 256, 0, s>>>(S, K);
     SP_LAUNCH_CHECK();
-    heavy_items_kernel<<<grid_for(2 * in.cap, 256, 8192), 256, 0, s>>>(S, K);
+    heavy_items_kernel<<<grid_for(K.nb, 256, 8192), 256, 0, s>>>(S, K);
     SP_LAUNCH_CHECK();
     return hipSuccess;
 }
