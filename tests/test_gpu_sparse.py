@@ -168,3 +168,21 @@ def test_sparse_rejects_the_naive_variant(ctx):
     with pytest.raises(m.CflrError) as e:
         sparse_solve(ctx, G.DYCK1, graphs.erdos_renyi(30, 60, seed=1), semi_naive=0)
     assert e.value.status == 7
+
+
+def test_sparse_largest_vertex_ids(ctx):
+    # the most vertices sparse storage takes (2^24 - 1): pairs whose vertex
+    # ids fill the 24-bit fields of the keys and sorted entries
+    n = (1 << 24) - 1
+    rng = np.random.Generator(np.random.PCG64(31))
+    ids = np.concatenate([[0, 1], np.arange(n - 400, n)]).astype(np.int64)
+    triples = [(int(rng.choice(ids)), "a" if rng.random() < 0.5 else "b", int(rng.choice(ids)))
+               for _ in range(1200)]
+    g = graphs.make_graph(n, triples, label_names=["a", "b"])
+    text = "S -> A B | A X | S S\nX -> S B\nA -> a\nB -> b\n"
+    print(f"sparse largest ids n={n}", flush=True)
+    assert_matches_oracle(sparse_solve(ctx, text, g), text, g, "n = 2^24 - 1")
+    m = cflr()
+    with pytest.raises(m.CflrError) as e:
+        sparse_solve(ctx, text, graphs.make_graph(1 << 24, triples, label_names=["a", "b"]))
+    assert e.value.status == 7
