@@ -411,7 +411,7 @@ def serve(args):
     for mult in args.serve_rates:
         lam = mult * plain_rate
         arrivals = graphs.poisson_trace(len(objs), lam, seed=4 + int(mult * 100))
-        srv = cflr.Server(ctx, hbm_budget_bytes=int(free * 0.5), max_slots=64)
+        srv = cflr.Server(ctx, hbm_budget_bytes=int(free * 0.5), max_slots=args.serve_slots)
         t0 = time.perf_counter()
         tickets = []
         for (gr, o), a in zip(objs, arrivals):
@@ -439,7 +439,7 @@ def serve(args):
     print(json.dumps({"metric": "served solves/s (continuous batching)", "value": best,
                       "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
                       "data": "synthetic", "plain_solves_per_s": plain_rate,
-                      "sweep": rows,
+                      "sweep": rows, "max_slots_per_class": args.serve_slots,
                       "config": {"workload": f"serve_mix: {len(objs)} queries, Dyck-1 "
                                              f"(n<=20000), alias (n<=30000), points-to 64 fields "
                                              f"(n<=4096), n log-uniform from 1000, Poisson arrivals"}}),
@@ -532,6 +532,7 @@ def main():
                     choices=["single", "batch", "serve", "grammars", "analyses"])
     ap.add_argument("--serve-per-grammar", type=int, default=30)
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[0.5, 1.0, 2.0, 4.0, 8.0])
+    ap.add_argument("--serve-slots", type=int, default=8, help="requests running at once per size class")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="skip the memory-alias context line")
     ap.add_argument("--copy-calibration", action="store_true",

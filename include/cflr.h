@@ -331,17 +331,22 @@ void cflr_result_free(cflr_result *r);
 
 /* ---- server (continuous batching) --------------------------------------
  * A worker thread keeps the device busy with every admitted request: between
- * rounds it admits queued requests while the estimated device footprint of
- * the running ones plus the new one stays within hbm_budget_bytes, their
+ * rounds it admits queued requests (in arrival order; one that does not fit
+ * yet lets later ones pass) while the estimated device footprint of the
+ * running ones plus the new one stays within hbm_budget_bytes, their
  * (key tile, partner) slots (key tiles of 256 vertices x n partners per
  * matrix) stay within hbm_budget_bytes / 16 (between 2^20 and 2^29), and
- * fewer than max_slots run, and retires requests that converged.  Each round's
- * product is two launches (row parts, then column parts) over all running
- * requests.  Requests may use different grammars.  Results are identical to
+ * fewer than max_slots run in the request's class, and retires requests that
+ * converged.  Requests whose footprint is at most hbm_budget_bytes / 64 form
+ * the small class, the others the large one; each class runs its own rounds,
+ * and the small class runs two round batches per batch of the large one, so
+ * a small request does not wait for a large request's round for each of its
+ * own.  Each round's product is two launches (row parts, then column parts)
+ * over the class's running requests.  Requests may use different grammars.  Results are identical to
  * cflr_solve of the same input.  A request whose footprint alone exceeds the
- * budget fails with ENOMEM.  Besides the budget the server holds the sort's
- * bucket counters (8 bytes per bucket, budget / 65536 buckets, at least 2^20
- * and at most 2^26) and a new-pair buffer of 44 bytes per pair, starting at
+ * budget fails with ENOMEM.  Besides the budget the server holds, per class,
+ * the sort's bucket counters (8 bytes per bucket, budget / 65536 buckets, at
+ * least 2^20 and at most 2^26) and a new-pair buffer of 44 bytes per pair, starting at
  * the size earlier solves on ctx grew it to (else 2^26 pairs) unless
  * opts->delta_capacity says otherwise (it grows when a round overflows it).
  * It also admits a request only while the running requests' (key tile,

@@ -1,14 +1,19 @@
 // server.cpp -- continuous batching of CFL-reachability requests.
 //
-// A worker thread owns one Run.  Between rounds it retires the instances that
-// converged (their matrices are compacted to the user non-terminals and
-// handed to the waiting caller) and admits queued requests, first come first
-// served, while the estimated device footprint of the running instances plus
-// the next one fits the budget and a slot is free.  Every round is one fused
-// product launch over all running instances, so a request that arrives while
-// others are on the device starts at the next round boundary and shares the
-// device with them.  Each instance's arithmetic is independent of the others
-// (its own matrices, rows and new pairs), so its result equals a solo solve.
+// A worker thread owns two Runs: one for small requests (device footprint at
+// most 1/64 of the budget) and one for the rest.  Between rounds it retires
+// the instances that converged (their matrices are compacted to the user
+// non-terminals and handed to the waiting caller) and admits queued
+// requests in arrival order, each into its class's run, while the estimated
+// footprint of the running instances plus the next one fits the budget and
+// a slot is free (a request that does not fit yet lets later ones of the
+// other class pass).  Every round is one fused product launch over all
+// instances of a run, so a request that arrives while others are on the
+// device starts at the next round boundary of its run.  The small run takes
+// kSmallPace round batches per batch of the large run: its rounds are short,
+// so a small request does not wait a large request's round for each of its
+// own.  Each instance's arithmetic is independent of the others (its own
+// matrices, rows and new pairs), so its result equals a solo solve.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -37,7 +42,11 @@ struct Request {
     std::shared_ptr<Instance> inst;
     uint64_t footprint = 0;
     uint64_t slots = 0;  // (key tile, partner) slots of its matrices (instance_pair_slots)
+    int cls = 1;         // 0: small, 1: large
 };
+
+constexpr uint64_t kSmallShare = 64;  // small: footprint at most budget / kSmallShare
+constexpr uint32_t kSmallPace = 2;    // small-run round batches per large-run batch
 
 }  // namespace
 
@@ -56,30 +65,85 @@ struct cflr_server {
     bool stop = false;
     uint64_t next_ticket = 1;
     uint64_t in_use = 0;
-    uint64_t slots_in_use = 0, slot_cap = 0;  // running requests' pair slots, and their bound
-    std::unique_ptr<Run> run;
+    uint64_t slots_in_use[2] = {0, 0}, slot_cap = 0;  // running requests' pair slots per run, and their bound
+    uint32_t count[2] = {0, 0};                         // running requests per run
+    std::unique_ptr<Run> run[2];                        // small, large
     hipStream_t stream = nullptr;  // the worker's own stream (default priority): rounds are
                                    // captured on it, so callers' use of the context's
                                    // stream (readout, frees) never meets a capture
     std::string fatal;
 
     void loop();
+    bool step(Run &r);
 };
+
+// Rounds of one run, then its converged (or round-limited) instances handed
+// back.  false: a device failure ended every request.
+bool cflr_server::step(Run &rn) {
+    try {
+        rn.rounds(opts.rounds_per_sync ? opts.rounds_per_sync : 2);
+        std::vector<std::shared_ptr<Instance>> done;
+        for (auto &ip : rn.instances())
+            if (ip->done || (opts.max_rounds && ip->rounds >= opts.max_rounds)) done.push_back(ip);
+        for (auto &ip : done) {
+            rn.remove(ip.get());
+            ip->stats.rounds = ip->rounds;
+            ip->stats.reruns = rn.reruns();
+            cflr_status st = ip->done ? CFLR_OK : CFLR_ETIMEOUT;
+            compact_instance(*ip);
+            instance_counts(*ip);
+            std::lock_guard<std::mutex> lk(mu);
+            Request *r = running[ip.get()];
+            running.erase(ip.get());
+            in_use -= r->footprint;
+            slots_in_use[r->cls] -= r->slots;
+            count[r->cls]--;
+            r->status = st;
+            if (st != CFLR_OK) r->error = "round limit reached before the fixpoint";
+            r->t_finish = now_s();
+            r->inst->stats.fixpoint_ms = (r->t_finish - r->t_admit) * 1e3;
+            r->finished = true;
+        }
+        if (!done.empty()) cv_done.notify_all();
+        return true;
+    } catch (const std::exception &e) {
+        // a device failure ends every running request
+        std::lock_guard<std::mutex> lk(mu);
+        fatal = e.what();
+        for (auto &kv : running) {
+            kv.second->status = CFLR_EDEVICE;
+            kv.second->error = fatal;
+            kv.second->finished = true;
+            kv.second->t_finish = now_s();
+        }
+        running.clear();
+        for (Request *r : queue) {
+            r->status = CFLR_EDEVICE;
+            r->error = fatal;
+            r->finished = true;
+        }
+        queue.clear();
+        stop = true;
+        cv_done.notify_all();
+        return false;
+    }
+}
 
 void cflr_server::loop() {
     (void)hipSetDevice(ctx->device);
+    uint64_t batch = 0;
     while (true) {
         std::vector<Request *> admit;
         {
             std::unique_lock<std::mutex> lk(mu);
             cv_work.wait(lk, [&] { return stop || !queue.empty() || !running.empty(); });
             if (stop && queue.empty() && running.empty()) break;
-            uint64_t planned = in_use, planned_slots = slots_in_use;
-            size_t slots = running.size();
-            while (!queue.empty() && slots < max_slots) {
-                Request *r = queue.front();
+            uint64_t planned = in_use, planned_slots[2] = {slots_in_use[0], slots_in_use[1]};
+            uint32_t planned_count[2] = {count[0], count[1]};
+            for (auto it = queue.begin(); it != queue.end();) {
+                Request *r = *it;
                 if (r->footprint > budget) {
-                    queue.pop_front();
+                    it = queue.erase(it);
                     r->status = CFLR_ENOMEM;
                     r->error = "request footprint exceeds the server budget";
                     r->finished = true;
@@ -87,26 +151,35 @@ void cflr_server::loop() {
                     cv_done.notify_all();
                     continue;
                 }
+                const int c = r->cls;
                 // the pair-slot bound keeps one round's new pairs inside the
                 // 2^32-entry buffer and a round short enough for latency
-                if (slots && (planned + r->footprint > budget || planned_slots + r->slots > slot_cap)) break;
-                queue.pop_front();
+                const bool idle = planned_count[0] + planned_count[1] == 0;
+                const bool fits = planned_count[c] < max_slots &&
+                                  (idle || (planned + r->footprint <= budget &&
+                                            (planned_count[c] == 0 || planned_slots[c] + r->slots <= slot_cap)));
+                if (!fits) {
+                    ++it;
+                    continue;
+                }
+                it = queue.erase(it);
                 admit.push_back(r);
                 planned += r->footprint;
-                planned_slots += r->slots;
-                slots++;
+                planned_slots[c] += r->slots;
+                planned_count[c]++;
             }
         }
         for (Request *r : admit) {
             try {
                 auto inst = make_instance(ctx, r->g->low, r->graph);
-                run->add(inst);
+                run[r->cls]->add(inst);
                 std::lock_guard<std::mutex> lk(mu);
                 r->inst = inst;
                 r->t_admit = now_s();
                 running[inst.get()] = r;
                 in_use += r->footprint;
-                slots_in_use += r->slots;
+                slots_in_use[r->cls] += r->slots;
+                count[r->cls]++;
             } catch (const Error &e) {
                 std::lock_guard<std::mutex> lk(mu);
                 if (e.status == CFLR_ENOMEM && !running.empty()) {
@@ -120,52 +193,11 @@ void cflr_server::loop() {
                 }
             }
         }
-        if (run->size() == 0) continue;
-        try {
-            run->rounds(opts.rounds_per_sync ? opts.rounds_per_sync : 2);
-            std::vector<std::shared_ptr<Instance>> done;
-            for (auto &ip : run->instances())
-                if (ip->done || (opts.max_rounds && ip->rounds >= opts.max_rounds)) done.push_back(ip);
-            for (auto &ip : done) {
-                run->remove(ip.get());
-                ip->stats.rounds = ip->rounds;
-                ip->stats.reruns = run->reruns();
-                cflr_status st = ip->done ? CFLR_OK : CFLR_ETIMEOUT;
-                compact_instance(*ip);
-                instance_counts(*ip);
-                std::lock_guard<std::mutex> lk(mu);
-                Request *r = running[ip.get()];
-                running.erase(ip.get());
-                in_use -= r->footprint;
-                slots_in_use -= r->slots;
-                r->status = st;
-                if (st != CFLR_OK) r->error = "round limit reached before the fixpoint";
-                r->t_finish = now_s();
-                r->inst->stats.fixpoint_ms = (r->t_finish - r->t_admit) * 1e3;
-                r->finished = true;
-            }
-            if (!done.empty()) cv_done.notify_all();
-        } catch (const std::exception &e) {
-            // a device failure ends every running request
-            std::lock_guard<std::mutex> lk(mu);
-            fatal = e.what();
-            for (auto &kv : running) {
-                kv.second->status = CFLR_EDEVICE;
-                kv.second->error = fatal;
-                kv.second->finished = true;
-                kv.second->t_finish = now_s();
-            }
-            running.clear();
-            for (Request *r : queue) {
-                r->status = CFLR_EDEVICE;
-                r->error = fatal;
-                r->finished = true;
-            }
-            queue.clear();
-            stop = true;
-            cv_done.notify_all();
-            break;
-        }
+        const bool small = run[0]->size() > 0, large = run[1]->size() > 0;
+        if (!small && !large) continue;
+        if (small && !step(*run[0])) break;
+        if (large && (!small || batch % kSmallPace == 0) && !step(*run[1])) break;
+        batch++;
     }
 }
 
@@ -202,8 +234,9 @@ cflr_status cflr_server_create(cflr_ctx *ctx, uint64_t hbm_budget_bytes, uint32_
         if (!s->opts.delta_capacity && !ctx->delta_capacity_hint) s->opts.delta_capacity = 1ull << 26;
         hip_check(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate");
         try {
-            s->run = std::make_unique<Run>(ctx, s->opts, buckets, max_slots, s->stream);
+            for (auto &rn : s->run) rn = std::make_unique<Run>(ctx, s->opts, buckets, max_slots, s->stream);
         } catch (...) {
+            for (auto &rn : s->run) rn.reset();
             (void)hipStreamDestroy(s->stream);
             throw;
         }
@@ -229,6 +262,7 @@ cflr_status cflr_server_submit(cflr_server *s, const cflr_grammar *g, const cflr
     r->t_submit = now_s();
     r->footprint = instance_footprint(g->low, graph->n);
     r->slots = instance_pair_slots(g->low, graph->n);
+    r->cls = r->footprint <= s->budget / kSmallShare ? 0 : 1;
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return server_fail(CFLR_EDEVICE, "server stopped: " + s->fatal);
     r->ticket = s->next_ticket++;
@@ -296,7 +330,7 @@ void cflr_server_free(cflr_server *s) {
         s->cv_work.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
-    s->run.reset();
+    for (auto &rn : s->run) rn.reset();
     if (s->stream) {
         (void)hipSetDevice(s->ctx->device);
         (void)hipStreamSynchronize(s->stream);

@@ -330,7 +330,9 @@ def test_server_results_equal_alone_and_in_the_mix(ctx):
              (G.ALIAS_FIG5B, graphs.alias_graph(1000, seed=24))] * 2
     grams = {t: m.Grammar(t) for t, _ in cases}
     objs = [m.Graph.from_workload(ctx, g) for _, g in cases]
-    srv = m.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=5)
+    # a 512 MiB budget: requests of at most 8 MiB (Dyck-1, alias 5b) run in
+    # the small-request run, the others in the large one
+    srv = m.Server(ctx, hbm_budget_bytes=512 << 20, max_slots=5)
     tickets = [srv.submit(grams[t], o) for (t, _), o in zip(cases, objs)]
     mixed = [srv.wait(t, timeout_s=300) for t in tickets]
     times = [srv.times(t) for t in tickets]
