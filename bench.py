@@ -475,6 +475,7 @@ def compare_forms(cases, steps, metric):
             log(f"{name} {label}: median {med:.1f} ms, {st['rounds']} rounds, "
                 f"{info['matrices']} matrices, {counts[label]} {shared} pairs")
             rows.append({"graph": name, "vertices": g.n, "edges": g.m, "grammar": label,
+                         "storage": "sparse" if st["storage"] == 2 else "dense",
                          "matrices": info["matrices"], "binary": info["binary"],
                          "fixpoint_ms_median": med, "rounds": st["rounds"],
                          "pairs": st["total_pairs"],
@@ -489,15 +490,21 @@ def compare_forms(cases, steps, metric):
 
 def analyses_mode(args):
     """The two further analyses of the paper on graphs of their Table 3
-    shapes, scaled to 40,000 vertices: field-sensitive C/C++ alias (Fig. 6b
-    by hand, Fig. 6a as given; 64 fields, 2.7 stored edges per vertex) and
-    context-sensitive value flow (Fig. 7b by hand, Fig. 7a as given; 64 call
-    sites, 1.7 edges per vertex)."""
+    shapes: field-sensitive C/C++ alias (Fig. 6b by hand, Fig. 6a as given;
+    64 fields, 2.7 stored edges per vertex) at 40,000 vertices, the size of
+    its Table 3 graphs; context-sensitive value flow (Fig. 7b by hand, Fig.
+    7a as given; 64 call sites, 1.7 edges per vertex) at 40,000 vertices and
+    at the vertex and edge counts of Table 3's povray graph (346,034 and
+    581,210; sparse storage, chosen by the default)."""
+    import workloads
     from workloads import grammars as G, graphs
     cases = [("fsca", graphs.fsca_graph(40000, fields=64), "M",
               [("Fig. 6b (WCNF by hand)", G.fsca_fig6b(64)),
                ("Fig. 6a as given, normalised by the library", G.fsca_fig6a_cfg(64))]),
              ("cscvf", graphs.valueflow_graph(40000, m_fwd=68000, calls=64), "A",
+              [("Fig. 7b (WCNF by hand)", G.cscvf_fig7b(64)),
+               ("Fig. 7a as given, normalised by the library", G.cscvf_fig7a_cfg(64))]),
+             ("cscvf_346k", workloads.config("valueflow_346k")[1], "A",
               [("Fig. 7b (WCNF by hand)", G.cscvf_fig7b(64)),
                ("Fig. 7a as given, normalised by the library", G.cscvf_fig7a_cfg(64))])]
     compare_forms(cases, args.steps, "fixpoint ms, field-sensitive alias and value-flow analyses")

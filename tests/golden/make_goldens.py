@@ -40,6 +40,9 @@ GOLDENS = {
                            graphs.alias_graph(8000, seed=1)),
     # the points-to configuration at its full size (200,000 vertices)
     "pointsto_200k": lambda: workloads.config("pointsto_200k"),
+    # value flow (Fig. 7b, 64 call sites) at the vertex and edge counts of
+    # Table 3's povray graph
+    "valueflow_346k": lambda: workloads.config("valueflow_346k"),
 }
 
 # The 256-graph alias batch (the batched configuration): every graph with at

@@ -27,6 +27,11 @@ CONFIGS = {
     "pointsto_200k": dict(grammar=grammars.pointsto_fig4b(64),
                           make=lambda: graphs.pointsto_graph(200_000,
                                                              seed=2)),
+    # context-sensitive value flow (Fig. 7b) on a graph with the vertex and
+    # edge counts of Table 3's povray value-flow graph (346,034 vertices,
+    # 581,210 edges), with 64 call sites (the table's graph has thousands)
+    "valueflow_346k": dict(grammar=grammars.cscvf_fig7b(64),
+                           make=lambda: graphs.valueflow_graph(346_034, m_fwd=581_210, calls=64)),
 }
 
 
@@ -43,6 +48,8 @@ def config(name, n=None):
         return c["grammar"], graphs.alias_graph(n, seed=1)
     if name == "pointsto_200k":
         return c["grammar"], graphs.pointsto_graph(n, seed=2)
+    if name == "valueflow_346k":
+        return c["grammar"], graphs.valueflow_graph(n, m_fwd=n * 581_210 // 346_034, calls=64)
     raise KeyError(name)
 
 
