@@ -360,7 +360,7 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
     // products reach `threshold` are expanded into an LDS bit set, where a
     // use with at most `direct` products skips the bit set and a head's own
     // pairs are cleared from it when they are at most `row_factor` times
-    // the use's products.  Defaults (512, 256, 4) from sweeps on the
+    // the use's products.  Defaults (256, 256, 4) from sweeps on the
     // 200,000-vertex points-to graph: the bit set and the own-row clear
     // replace most hash probes, and below these sizes a probe is cheaper
     // than the workgroup's fixed cost per use.  Off when the bucket space or
@@ -370,14 +370,14 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
     K.nb = K.nb0 + (uint64_t)P.nrank1 * n;
     const bool grouped = !fixed && K.nb > 0 && K.nb < (1ull << 30) && sp::heavy_lds_bytes(n) <= sp::kHeavyMaxLds &&
                          std::getenv("CFLR_SPARSE_UNGROUPED") == nullptr;
-    K.threshold = 512;
+    K.threshold = 256;
     if (const char *h = std::getenv("CFLR_SPARSE_HEAVY")) K.threshold = std::max<uint64_t>(1, std::strtoull(h, nullptr, 10));
     if (witness) K.threshold = ~0ull;  // every product keeps its midpoint: no bucket goes to the bit set
     K.direct = 256;
     if (const char *h = std::getenv("CFLR_SPARSE_DIRECT")) K.direct = (uint32_t)std::strtoul(h, nullptr, 10);
     K.row_factor = 4;
     if (const char *h = std::getenv("CFLR_SPARSE_ROWF")) K.row_factor = (uint32_t)std::strtoul(h, nullptr, 10);
-    Mem k_start, k_work, k_bsum, k_entry, k_heavy, k_ework, k_touch, k_acct;
+    Mem k_start, k_work, k_bsum, k_entry, k_heavy, k_light, k_ework, k_touch, k_acct;
     if (grouped) {
         k_start = A.get((K.nb + 1) * 4, "the key sort");
         k_work = A.get(K.nb * 8, "the key sort");
@@ -515,12 +515,14 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         if (grouped) {
             if (K.entry_cap < 2 * in->cap) {
                 if (2 * in->cap >= (1ull << 32)) throw Error(CFLR_ENOMEM, "more than 2^31 new pairs in one round");
-                K.entry_cap = K.heavy_cap = 2 * in->cap;
+                K.entry_cap = K.heavy_cap = K.light_cap = 2 * in->cap;
                 k_entry = A.get(K.entry_cap * 8, "the key sort");
                 k_heavy = A.get(K.heavy_cap * 4, "the key sort");
+                k_light = A.get(K.light_cap * 4, "the key sort");
                 k_ework = A.get(K.entry_cap * 4, "the key sort");
                 K.entry = k_entry.as<uint64_t>();
                 K.heavy = k_heavy.as<uint32_t>();
+                K.light = k_light.as<uint32_t>();
                 K.ework = k_ework.as<uint32_t>();
             }
             hip_check(sp::launch_key_sort(S, in->dev(), K, s), "key sort");

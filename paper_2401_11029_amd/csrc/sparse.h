@@ -118,6 +118,8 @@ struct KeySort {
     uint32_t *heavy;           // items of the buckets whose products reach `threshold`: the
                                // first entry of a run of at most kHeavyRun entries
     uint64_t heavy_cap;
+    uint32_t *light;           // the entries of the other buckets, listed bucket by bucket
+    uint64_t light_cap;
     uint64_t threshold;
     uint32_t direct;           // a heavy item's use with at most this many products inserts
                                // them into the hash set directly (no bit set)
@@ -186,7 +188,8 @@ constexpr int kCtlPoolTop = 0,   // pool entries handed out
     kCtlHeavyTasks = 14,         // heavy buckets taken
     kCtlHeavyProducts = 15,      // products of the heavy items
     kCtlHeavyCand = 16,          // candidates the heavy items sent to the hash set
-    kCtlWords = 17;
+    kCtlLight = 17,              // entries of the light buckets listed
+    kCtlWords = 18;
 
 // ------------------------------------------------------------------ launchers
 

@@ -261,6 +261,7 @@ __global__ void round_start_kernel(State S) {
     S.ctl[kCtlMoves] = 0;
     S.ctl[kCtlNew] = 0;
     S.ctl[kCtlHeavy] = 0;
+    S.ctl[kCtlLight] = 0;
     S.ctl[kCtlHeavyTasks] = 0;
 }
 
@@ -790,18 +791,22 @@ __global__ __launch_bounds__(256) void classify_kernel(State S, KeySort K) {
 
 // Items: the runs of a heavy bucket's entries that do not cross a multiple
 // of kHeavyRun in the sorted order (at most kHeavyRun entries each): the
-// bucket's first entry and every multiple of kHeavyRun inside it.  One
-// lane per bucket; a wave reserves the slots of all its items at once.
+// bucket's first entry and every multiple of kHeavyRun inside it.  The
+// entries of the other buckets are listed for the light kernel.  One lane
+// per bucket; a wave reserves the slots of all its items (entries) at once.
 __global__ __launch_bounds__(256) void heavy_items_kernel(State S, KeySort K) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); base < K.nb; base += stride) {
         const uint64_t b = base + lane_id();
-        uint32_t s0 = 0, s1 = 0, items = 0;
-        if (b < K.nb && K.work[b] >= K.threshold) {
+        uint32_t s0 = 0, s1 = 0, items = 0, light = 0;
+        if (b < K.nb) {
             s0 = K.start[b];
             s1 = K.start[b + 1];
             if (s1 > K.entry_cap) s1 = (uint32_t)K.entry_cap;
-            if (s1 > s0) items = (s1 - 1) / kHeavyRun - s0 / kHeavyRun + 1;
+            if (s1 > s0) {
+                if (K.work[b] >= K.threshold) items = (s1 - 1) / kHeavyRun - s0 / kHeavyRun + 1;
+                else light = s1 - s0;
+            }
         }
         uint32_t tot;
         const uint32_t pre = wave_excl_scan(items, &tot);
@@ -813,6 +818,13 @@ __global__ __launch_bounds__(256) void heavy_items_kernel(State S, KeySort K) {
             const uint32_t e = q == 0 ? s0 : (s0 / kHeavyRun + q) * kHeavyRun;
             if (h < K.heavy_cap) K.heavy[h] = e;
         }
+        uint32_t ltot;
+        const uint32_t lpre = wave_excl_scan(light, &ltot);
+        unsigned long long l0 = 0;
+        if (lane_id() == 0 && ltot) l0 = atomicAdd(&S.ctl[kCtlLight], (unsigned long long)ltot);
+        l0 = first_lane64(l0);
+        for (uint32_t q = 0; q < light; q++)
+            if (l0 + lpre + q < K.light_cap) K.light[l0 + lpre + q] = s0 + q;
     }
 }
 
@@ -1145,15 +1157,15 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
     }
 }
 
-// Light buckets: 64 sorted entries per task, a lane per entry, expanded
-// against the uses of its own part; entries of heavy buckets are skipped.
+// Light buckets: 64 listed entries per task, a lane per entry, expanded
+// against the uses of its own part.
 // A wave claims kLightClaim tasks at a time (one counter serves them all).
 constexpr uint32_t kLightClaim = 16;
 template <bool kAcct>
 __global__ __launch_bounds__(256) void light_kernel(State S, KeySort K, PairBuf out) {
     const uint32_t lane = lane_id();
-    uint64_t total = K.start[K.nb];
-    if (total > K.entry_cap) total = K.entry_cap;
+    uint64_t total = S.ctl[kCtlLight];
+    if (total > K.light_cap) total = K.light_cap;
     const uint64_t total0 = K.start[K.nb0];
     const uint64_t ntask = (total + 63) / 64;
     Chunk ch;
@@ -1169,19 +1181,17 @@ __global__ __launch_bounds__(256) void light_kernel(State S, KeySort K, PairBuf 
             t_end = t + kLightClaim < ntask ? t + kLightClaim : ntask;
         }
         if (first_lane64(load_relaxed(&S.ctl[kCtlHalt]))) break;
-        const uint64_t e = t * 64 + lane;
-        bool valid = e < total;
+        const uint64_t q = t * 64 + lane;
+        const bool valid = q < total;
         uint32_t x = 0, pi = 0, pj = 0, order = 0;
         if (valid) {
+            const uint32_t e = K.light[q];
             const uint64_t v = K.entry[e];
             x = (uint32_t)(v >> 48);
             const uint32_t key = (uint32_t)(v >> 24) & 0xFFFFFFu, k = (uint32_t)v & 0xFFFFFFu;
             order = e >= total0 ? 1u : 0u;
             pi = order ? k : key;
             pj = order ? key : k;
-            const MatInfo mi = S.mats[x];
-            const uint64_t b = order ? K.nb0 + (uint64_t)mi.rank1 * S.n + key : (uint64_t)mi.rank0 * S.n + key;
-            if (K.work[b] >= K.threshold) valid = false;
         }
         if (acct && valid) bytes += 8;
         if (!expand_uses(S, out, ch, appended, products, valid, x, pi, pj, order, order + 1, acct, bytes)) break;
