@@ -360,7 +360,7 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
     // products reach `threshold` are expanded into an LDS bit set, where a
     // use with at most `direct` products skips the bit set and a head's own
     // pairs are cleared from it when they are at most `row_factor` times
-    // the use's products.  Defaults (256, 256, 4) from sweeps on the
+    // the use's products.  Defaults (128, 256, 4) from sweeps on the
     // 200,000-vertex points-to graph: the bit set and the own-row clear
     // replace most hash probes, and below these sizes a probe is cheaper
     // than the workgroup's fixed cost per use.  Off when the bucket space or
@@ -370,7 +370,7 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
     K.nb = K.nb0 + (uint64_t)P.nrank1 * n;
     const bool grouped = !fixed && K.nb > 0 && K.nb < (1ull << 30) && sp::heavy_lds_bytes(n) <= sp::kHeavyMaxLds &&
                          std::getenv("CFLR_SPARSE_UNGROUPED") == nullptr;
-    K.threshold = 256;
+    K.threshold = 128;
     if (const char *h = std::getenv("CFLR_SPARSE_HEAVY")) K.threshold = std::max<uint64_t>(1, std::strtoull(h, nullptr, 10));
     if (witness) K.threshold = ~0ull;  // every product keeps its midpoint: no bucket goes to the bit set
     K.direct = 256;
@@ -489,8 +489,24 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         hip_check(sp::launch_fill_u64(out->count.as<unsigned long long>(), 1, 0, s), "fill");
         hip_check(sp::launch_round_start(S, s), "round start");
 
+        // the key sort's arrays for this round's pairs (its bucket counts are
+        // taken in the integration's pass)
+        if (grouped && K.entry_cap < 2 * in->cap) {
+            if (2 * in->cap >= (1ull << 32)) throw Error(CFLR_ENOMEM, "more than 2^31 new pairs in one round");
+            K.entry_cap = K.heavy_cap = K.light_cap = 2 * in->cap;
+            k_entry = A.get(K.entry_cap * 8, "the key sort");
+            k_heavy = A.get(K.heavy_cap * 4, "the key sort");
+            k_light = A.get(K.light_cap * 4, "the key sort");
+            k_ework = A.get(K.entry_cap * 4, "the key sort");
+            K.entry = k_entry.as<uint64_t>();
+            K.heavy = k_heavy.as<uint32_t>();
+            K.light = k_light.as<uint32_t>();
+            K.ework = k_ework.as<uint32_t>();
+        }
+        const sp::KeySort *Kp = grouped ? &K : nullptr;
+
         // integrate the pending pairs into the lists
-        hip_check(sp::launch_integrate(S, in->dev(), false, grid, s), "integrate");
+        hip_check(sp::launch_integrate(S, in->dev(), Kp, false, grid, s), "integrate");
         read_ctl(nullptr);
         while (h_ctl[sp::kCtlHalt]) {
             if (h_ctl[sp::kCtlTouchedOver]) throw Error(CFLR_EDEVICE, "internal: touched-list array too small");
@@ -507,26 +523,13 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
             S.pool_cap = pool_cap;
             if (log) std::fprintf(stderr, "[cflr] sparse: pool grown to %llu entries\n", (unsigned long long)ncap);
             clear_flags();
-            hip_check(sp::launch_integrate(S, in->dev(), true, grid, s), "integrate");
+            hip_check(sp::launch_integrate(S, in->dev(), Kp, true, grid, s), "integrate");
             read_ctl(nullptr);
         }
+        hip_check(sp::launch_integrate_finish(S, in->dev(), Kp, grid, s), "integrate");
 
         // the product
-        if (grouped) {
-            if (K.entry_cap < 2 * in->cap) {
-                if (2 * in->cap >= (1ull << 32)) throw Error(CFLR_ENOMEM, "more than 2^31 new pairs in one round");
-                K.entry_cap = K.heavy_cap = K.light_cap = 2 * in->cap;
-                k_entry = A.get(K.entry_cap * 8, "the key sort");
-                k_heavy = A.get(K.heavy_cap * 4, "the key sort");
-                k_light = A.get(K.light_cap * 4, "the key sort");
-                k_ework = A.get(K.entry_cap * 4, "the key sort");
-                K.entry = k_entry.as<uint64_t>();
-                K.heavy = k_heavy.as<uint32_t>();
-                K.light = k_light.as<uint32_t>();
-                K.ework = k_ework.as<uint32_t>();
-            }
-            hip_check(sp::launch_key_sort(S, in->dev(), K, s), "key sort");
-        }
+        if (grouped) hip_check(sp::launch_key_sort(S, in->dev(), K, s), "key sort");
         auto timed_product = [&]() {
             if (K.acct) {
                 hip_check(sp::launch_fill_u32(K.touch, (cells + 31) / 32, 0, s), "fill");

@@ -198,10 +198,15 @@ constexpr int kCtlPoolTop = 0,   // pool entries handed out
 hipError_t launch_seed(const State &S, const uint32_t *src, const uint32_t *dst, const uint32_t *lab, uint64_t m,
                        const uint32_t *lm_ptr, const uint32_t *lm_mat, const uint32_t *eps_mat, uint32_t n_eps,
                        PairBuf out, hipStream_t s);
-// Add the new pairs `in` to the adjacency lists (count, plan, check, move, scatter, reset).
-// With resume = true only the steps after the capacity check run (after the
-// host grew an overflowing pool).
-hipError_t launch_integrate(const State &S, PairBuf in, bool resume, uint32_t grid, hipStream_t s);
+// Add the new pairs `in` to the adjacency lists, in two launches: count
+// (and, with K, the key sort's bucket counts in the same pass), plan, check,
+// move; then, once the pool held (launch_integrate_finish), the buckets'
+// scan, the appends (and the sorted entries), reset.  With resume = true
+// only the steps from the capacity check on run (after the host grew an
+// overflowing pool).
+hipError_t launch_integrate(const State &S, PairBuf in, const KeySort *K, bool resume, uint32_t grid,
+                            hipStream_t s);
+hipError_t launch_integrate_finish(const State &S, PairBuf in, const KeySort *K, uint32_t grid, hipStream_t s);
 // Zero the counters a round starts from (touched lists, planned
 // allocation, tasks, queued copies).
 hipError_t launch_round_start(const State &S, hipStream_t s);
@@ -216,6 +221,8 @@ hipError_t launch_product(const State &S, PairBuf in, PairBuf out, uint32_t grid
 constexpr uint32_t kHeavyThreads = 256;
 constexpr uint32_t kHeavyRun = kHeavyThreads;  // entries of a heavy item at most
 
+// The key sort's last steps (after launch_integrate_finish placed the
+// entries): per entry its products, the heavy items and the light list.
 hipError_t launch_key_sort(const State &S, PairBuf in, const KeySort &K, hipStream_t s);
 hipError_t launch_heavy(const State &S, const KeySort &K, PairBuf out, uint32_t grid_waves, hipStream_t s);
 hipError_t launch_light(const State &S, const KeySort &K, PairBuf out, uint32_t grid_waves, hipStream_t s);

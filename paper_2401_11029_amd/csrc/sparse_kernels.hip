@@ -250,6 +250,11 @@ __global__ __launch_bounds__(256) void seed_eps_kernel(State S, const uint32_t *
     add_appended(S, appended);
 }
 
+// A sorted entry of the key sort: matrix, key vertex, partner vertex.
+__device__ __forceinline__ uint64_t pack_entry(uint32_t x, uint32_t key, uint32_t partner) {
+    return ((uint64_t)x << 48) | ((uint64_t)key << 24) | (uint64_t)partner;
+}
+
 // --------------------------------------------------------------- integrate
 
 // Reset the round's counters (touched rows, planned allocation, tasks,
@@ -300,23 +305,35 @@ __device__ __forceinline__ void touch(const State &S, uint64_t idx) {
     else atomicOr(&S.ctl[kCtlTouchedOver], 1ull);
 }
 
-__global__ __launch_bounds__(256) void count_kernel(State S, PairBuf in) {
+// Per pending pair: its lists' pending counts and, when the product is
+// grouped (K.start set), its key-sort buckets' counts (runs of lanes with
+// one bucket take one atomic), in one pass over the pairs.
+__global__ __launch_bounds__(256) void count_kernel(State S, PairBuf in, KeySort K) {
     uint64_t nin = *in.count;
     if (nin > in.cap) nin = in.cap;
+    const bool keys = K.start != nullptr;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); base < nin; base += stride) {
         const uint64_t x = base + lane_id();
-        uint64_t row = kNoList, col = kNoList;
+        uint64_t row = kNoList, col = kNoList, b0 = kNoList, b1 = kNoList;
         if (x < nin) {
             const uint32_t key = in.key[x];
             if (key != kHoleKey) {
                 const MatInfo mi = S.mats[key];
-                if (mi.row_layout != kNone) row = (uint64_t)mi.row_layout * S.n + in.i[x];
-                if (mi.col_layout != kNone) col = (uint64_t)mi.col_layout * S.n + in.j[x];
+                const uint32_t i = in.i[x], j = in.j[x];
+                if (mi.row_layout != kNone) row = (uint64_t)mi.row_layout * S.n + i;
+                if (mi.col_layout != kNone) col = (uint64_t)mi.col_layout * S.n + j;
+                if (keys && mi.rank0 != kNone) b0 = (uint64_t)mi.rank0 * S.n + i;
+                if (keys && mi.rank1 != kNone) b1 = K.nb0 + (uint64_t)mi.rank1 * S.n + j;
             }
         }
         touch(S, row);
         touch(S, col);
+        if (keys) {
+            const Run r0 = lane_run(b0), r1 = lane_run(b1);
+            if (b0 != kNoList && !r0.rank) atomicAdd(&K.start[b0], r0.len);
+            if (b1 != kNoList && !r1.rank) atomicAdd(&K.start[b1], r1.len);
+        }
     }
 }
 
@@ -445,27 +462,44 @@ __device__ __forceinline__ void append(const State &S, uint64_t idx, uint32_t v)
     if (p < d.cap) S.pool[d.off + p] = v;
 }
 
-__global__ __launch_bounds__(256) void scatter_kernel(State S, PairBuf in) {
+// Per pending pair: its entries in its lists and, when the product is
+// grouped, its sorted entries (the bucket counts hold inclusive ends:
+// taking a run's length off the end places its entries and, once every
+// entry is placed, leaves the bucket's first position behind).
+__global__ __launch_bounds__(256) void scatter_kernel(State S, PairBuf in, KeySort K) {
     if (S.ctl[kCtlHalt]) return;
     uint64_t nin = *in.count;
     if (nin > in.cap) nin = in.cap;
+    const bool keys = K.start != nullptr;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); base < nin; base += stride) {
         const uint64_t x = base + lane_id();
-        uint64_t row = kNoList, col = kNoList;
-        uint32_t i = 0, j = 0;
+        uint64_t row = kNoList, col = kNoList, b0 = kNoList, b1 = kNoList;
+        uint32_t key = 0, i = 0, j = 0;
         if (x < nin) {
-            const uint32_t key = in.key[x];
+            key = in.key[x];
             if (key != kHoleKey) {
                 const MatInfo mi = S.mats[key];
                 i = in.i[x];
                 j = in.j[x];
                 if (mi.row_layout != kNone) row = (uint64_t)mi.row_layout * S.n + i;
                 if (mi.col_layout != kNone) col = (uint64_t)mi.col_layout * S.n + j;
+                if (keys && mi.rank0 != kNone) b0 = (uint64_t)mi.rank0 * S.n + i;
+                if (keys && mi.rank1 != kNone) b1 = K.nb0 + (uint64_t)mi.rank1 * S.n + j;
             }
         }
         append(S, row, j);
         append(S, col, i);
+        if (keys) {
+            const Run r0 = lane_run(b0), r1 = lane_run(b1);
+            uint32_t p0 = 0, p1 = 0;
+            if (b0 != kNoList && !r0.rank) p0 = atomicSub(&K.start[b0], r0.len);
+            if (b1 != kNoList && !r1.rank) p1 = atomicSub(&K.start[b1], r1.len);
+            p0 = shfl32(p0, r0.head) - 1 - r0.rank;  // the run's slots end at the old end
+            p1 = shfl32(p1, r1.head) - 1 - r1.rank;
+            if (b0 != kNoList && p0 < K.entry_cap) K.entry[p0] = pack_entry(key, i, j);
+            if (b1 != kNoList && p1 < K.entry_cap) K.entry[p1] = pack_entry(key, j, i);
+        }
     }
 }
 
@@ -610,64 +644,6 @@ __global__ __launch_bounds__(256) void product_kernel(State S, PairBuf in, PairB
 
 // ----------------------------------------------------------- key-order sort
 
-__device__ __forceinline__ uint64_t pack_entry(uint32_t x, uint32_t key, uint32_t partner) {
-    return ((uint64_t)x << 48) | ((uint64_t)key << 24) | (uint64_t)partner;
-}
-
-// Runs of lanes with one bucket (pairs the product emitted for one key
-// together) take one atomic per run, as the list appends do.
-__global__ __launch_bounds__(256) void key_count_kernel(State S, PairBuf in, KeySort K) {
-    uint64_t nin = *in.count;
-    if (nin > in.cap) nin = in.cap;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); base < nin; base += stride) {
-        const uint64_t x = base + lane_id();
-        uint64_t b0 = kNoList, b1 = kNoList;
-        if (x < nin) {
-            const uint32_t key = in.key[x];
-            if (key != kHoleKey) {
-                const MatInfo mi = S.mats[key];
-                if (mi.rank0 != kNone) b0 = (uint64_t)mi.rank0 * S.n + in.i[x];
-                if (mi.rank1 != kNone) b1 = K.nb0 + (uint64_t)mi.rank1 * S.n + in.j[x];
-            }
-        }
-        const Run r0 = lane_run(b0), r1 = lane_run(b1);
-        if (b0 != kNoList && !r0.rank) atomicAdd(&K.start[b0], r0.len);
-        if (b1 != kNoList && !r1.rank) atomicAdd(&K.start[b1], r1.len);
-    }
-}
-
-// The counts hold inclusive ends: taking a run's length off the end places
-// its entries and, once every entry is placed, leaves the bucket's first
-// position behind.
-__global__ __launch_bounds__(256) void key_scatter_kernel(State S, PairBuf in, KeySort K) {
-    uint64_t nin = *in.count;
-    if (nin > in.cap) nin = in.cap;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); base < nin; base += stride) {
-        const uint64_t x = base + lane_id();
-        uint64_t b0 = kNoList, b1 = kNoList;
-        uint32_t key = 0, i = 0, j = 0;
-        if (x < nin) {
-            key = in.key[x];
-            if (key != kHoleKey) {
-                const MatInfo mi = S.mats[key];
-                i = in.i[x];
-                j = in.j[x];
-                if (mi.rank0 != kNone) b0 = (uint64_t)mi.rank0 * S.n + i;
-                if (mi.rank1 != kNone) b1 = K.nb0 + (uint64_t)mi.rank1 * S.n + j;
-            }
-        }
-        const Run r0 = lane_run(b0), r1 = lane_run(b1);
-        uint32_t p0 = 0, p1 = 0;
-        if (b0 != kNoList && !r0.rank) p0 = atomicSub(&K.start[b0], r0.len);
-        if (b1 != kNoList && !r1.rank) p1 = atomicSub(&K.start[b1], r1.len);
-        p0 = shfl32(p0, r0.head) - 1 - r0.rank;  // the run's slots end at the old end
-        p1 = shfl32(p1, r1.head) - 1 - r1.rank;
-        if (b0 != kNoList && p0 < K.entry_cap) K.entry[p0] = pack_entry(key, i, j);
-        if (b1 != kNoList && p1 < K.entry_cap) K.entry[p1] = pack_entry(key, j, i);
-    }
-}
 
 // Inclusive scan of one u32 array, three phases (block sums, their scan,
 // apply).
@@ -1446,9 +1422,19 @@ hipError_t launch_round_start(const State &S, hipStream_t s) {
     return hipSuccess;
 }
 
-hipError_t launch_integrate(const State &S, PairBuf in, bool resume, uint32_t grid, hipStream_t s) {
+hipError_t launch_integrate(const State &S, PairBuf in, const KeySort *K, bool resume, uint32_t grid,
+                            hipStream_t s) {
+    KeySort none{};
+    const KeySort &Kk = K ? *K : none;
     if (!resume) {
-        count_kernel<<<grid, 256, 0, s>>>(S, in);
+        if (K) {
+            const uint64_t len = K->nb + 1;
+            fill_u32_kernel<<<grid_for(len, 256, 65536), 256, 0, s>>>(K->start, len, 0);
+            SP_LAUNCH_CHECK();
+            fill_u64_kernel<<<grid_for(K->nb, 256, 65536), 256, 0, s>>>(K->work, K->nb, 0);
+            SP_LAUNCH_CHECK();
+        }
+        count_kernel<<<grid, 256, 0, s>>>(S, in, Kk);
         SP_LAUNCH_CHECK();
         plan_kernel<<<grid, 256, 0, s>>>(S);
         SP_LAUNCH_CHECK();
@@ -1459,7 +1445,21 @@ hipError_t launch_integrate(const State &S, PairBuf in, bool resume, uint32_t gr
     SP_LAUNCH_CHECK();
     copy_kernel<<<grid, 256, 0, s>>>(S);
     SP_LAUNCH_CHECK();
-    scatter_kernel<<<grid, 256, 0, s>>>(S, in);
+    return hipSuccess;
+}
+
+hipError_t launch_integrate_finish(const State &S, PairBuf in, const KeySort *K, uint32_t grid, hipStream_t s) {
+    KeySort none{};
+    if (K) {
+        const uint64_t len = K->nb + 1, nblk = key_sort_scan_blocks(K->nb);
+        scan_reduce_kernel<<<(uint32_t)nblk, kScanThreads, 0, s>>>(K->start, len, K->bsum);
+        SP_LAUNCH_CHECK();
+        scan_blocks_kernel<<<1, 1024, 0, s>>>(K->bsum, nblk);
+        SP_LAUNCH_CHECK();
+        scan_apply_kernel<<<(uint32_t)nblk, kScanThreads, 0, s>>>(K->start, len, K->bsum);
+        SP_LAUNCH_CHECK();
+    }
+    scatter_kernel<<<grid, 256, 0, s>>>(S, in, K ? *K : none);
     SP_LAUNCH_CHECK();
     unmark_kernel<<<grid, 256, 0, s>>>(S);
     SP_LAUNCH_CHECK();
@@ -1476,23 +1476,6 @@ hipError_t launch_product(const State &S, PairBuf in, PairBuf out, uint32_t grid
 uint64_t key_sort_scan_blocks(uint64_t nb) { return (nb + 1 + kScanTile - 1) / kScanTile; }
 
 hipError_t launch_key_sort(const State &S, PairBuf in, const KeySort &K, hipStream_t s) {
-    const uint64_t len = K.nb + 1;
-    fill_u32_kernel<<<grid_for(len, 256, 65536), 256, 0, s>>>(K.start, len, 0);
-    SP_LAUNCH_CHECK();
-    fill_u64_kernel<<<grid_for(K.nb, 256, 65536), 256, 0, s>>>(K.work, K.nb, 0);
-    SP_LAUNCH_CHECK();
-    const uint32_t grid = grid_for(in.cap, 256, 8192);
-    key_count_kernel<<<grid, 256, 0, s>>>(S, in, K);
-    SP_LAUNCH_CHECK();
-    const uint64_t nblk = key_sort_scan_blocks(K.nb);
-    scan_reduce_kernel<<<(uint32_t)nblk, kScanThreads, 0, s>>>(K.start, len, K.bsum);
-    SP_LAUNCH_CHECK();
-    scan_blocks_kernel<<<1, 1024, 0, s>>>(K.bsum, nblk);
-    SP_LAUNCH_CHECK();
-    scan_apply_kernel<<<(uint32_t)nblk, kScanThreads, 0, s>>>(K.start, len, K.bsum);
-    SP_LAUNCH_CHECK();
-    key_scatter_kernel<<<grid, 256, 0, s>>>(S, in, K);
-    SP_LAUNCH_CHECK();
     classify_kernel<<<grid_for(2 * in.cap, 256, 8192), 256, 0, s>>>(S, K);
     SP_LAUNCH_CHECK();
     heavy_items_kernel<<<grid_for(K.nb, 256, 8192), 256, 0, s>>>(S, K);
