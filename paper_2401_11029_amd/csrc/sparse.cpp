@@ -370,9 +370,10 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
     K.nb = K.nb0 + (uint64_t)P.nrank1 * n;
     const bool grouped = !fixed && K.nb > 0 && K.nb < (1ull << 30) && sp::heavy_lds_bytes(n) <= sp::kHeavyMaxLds &&
                          std::getenv("CFLR_SPARSE_UNGROUPED") == nullptr;
-    K.threshold = 128;
-    if (const char *h = std::getenv("CFLR_SPARSE_HEAVY")) K.threshold = std::max<uint64_t>(1, std::strtoull(h, nullptr, 10));
-    if (witness) K.threshold = ~0ull;  // every product keeps its midpoint: no bucket goes to the bit set
+    uint64_t threshold = 128;
+    if (const char *h = std::getenv("CFLR_SPARSE_HEAVY")) threshold = std::max<uint64_t>(1, std::strtoull(h, nullptr, 10));
+    if (witness) threshold = ~0ull;  // every product keeps its midpoint: no bucket goes to the bit set
+    K.threshold = threshold;
     K.direct = 256;
     if (const char *h = std::getenv("CFLR_SPARSE_DIRECT")) K.direct = (uint32_t)std::strtoul(h, nullptr, 10);
     K.row_factor = 4;
@@ -528,8 +529,12 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         }
         hip_check(sp::launch_integrate_finish(S, in->dev(), Kp, grid, s), "integrate");
 
-        // the product
-        if (grouped) hip_check(sp::launch_key_sort(S, in->dev(), K, s), "key sort");
+        // the product (a pool past kHeavyMaxPool entries sends every bucket to
+        // the light kernel)
+        if (grouped) {
+            K.threshold = pool_cap <= sp::kHeavyMaxPool ? threshold : ~0ull;
+            hip_check(sp::launch_key_sort(S, in->dev(), K, s), "key sort");
+        }
         auto timed_product = [&]() {
             if (K.acct) {
                 hip_check(sp::launch_fill_u32(K.touch, (cells + 31) / 32, 0, s), "fill");

@@ -230,7 +230,8 @@ uint64_t key_sort_scan_blocks(uint64_t nb);
 // LDS bytes of a heavy workgroup's accumulator (n bits); the grouped product
 // needs n small enough for it to fit.
 inline uint64_t heavy_lds_bytes(uint32_t n) { return ((uint64_t)n + 31) / 32 * 4; }
-constexpr uint64_t kHeavyMaxLds = 48 * 1024;  // with the kernel's static LDS (about 15 KiB), within 64 KiB
+constexpr uint64_t kHeavyMaxLds = 56 * 1024;  // with the kernel's static LDS (about 6 KiB), within 64 KiB
+constexpr uint64_t kHeavyMaxPool = 1ull << 33;  // pool entries whose (even) offsets the heavy items hold halved in 32 bits
 // Re-insert every key of `old_tab` (tombstones dropped) into S.hash (empty).
 hipError_t launch_rehash(const State &S, const unsigned long long *old_tab, const unsigned long long *old_wit,
                          uint64_t old_slots, hipStream_t s);

@@ -818,7 +818,7 @@ __global__ __launch_bounds__(256) void heavy_items_kernel(State S, KeySort K) {
 // The bit set is left zero for the next use.
 constexpr uint32_t kMaxUseWords = 8;  // uses selected through an LDS OR of the masks (512)
 constexpr uint32_t kUnroll = 8;       // passes of products whose loads are issued together
-constexpr uint32_t kTouchCap = 2048;  // words listed as set; past that the whole bit set is scanned
+constexpr uint32_t kTouchCap = 512;   // words listed as set; past that the whole bit set is scanned
 
 // The first use at or after `from` that some entry of the item selects (its
 // bit in the OR of the entries' masks; every use when the masks were not
@@ -897,8 +897,12 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
     __shared__ uint64_t um[kMaxUseWords];
     // per use, alternating between two buffers so that one barrier per use
     // suffices: a use's buffers are written again two uses later, after
-    // every thread has passed the next use's barrier
-    __shared__ uint64_t s_off[2][kHeavyThreads];
+    // every thread has passed the next use's barrier.  List offsets are
+    // even (blocks of at least two entries from an even pool top) and held
+    // halved in 32 bits (the host keeps the pool below 2^33 entries for the
+    // heavy items); with the 512-word list this keeps the static LDS near
+    // 6 KiB, so five workgroups fit a CU at 200,000 vertices.
+    __shared__ uint32_t s_off[2][kHeavyThreads];
     __shared__ uint32_t s_pre[2][kHeavyThreads];
     __shared__ uint32_t wsum[2][kHeavyThreads / 64];
     __shared__ uint32_t sh_ntouch[2];
@@ -1003,12 +1007,12 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
             uint32_t wt;
             const uint32_t wpre = wave_excl_scan(cur.len, &wt);
             s_pre[par][t] = wpre;
-            s_off[par][t] = cur.off;
+            s_off[par][t] = (uint32_t)(cur.off >> 1);
             if (lane == 0) wsum[par][wave] = wt;
             __syncthreads();  // the use's lists are in LDS; the previous use is done
             if (t == 0) sh_ntouch[par ^ 1] = 0;  // counted into by the next use
             const uint32_t *pre = s_pre[par];
-            const uint64_t *offs = s_off[par];
+            const uint32_t *offs = s_off[par];
             const uint32_t o1 = wsum[par][0], o2 = o1 + wsum[par][1], o3 = o2 + wsum[par][2];
             const uint32_t total = o3 + wsum[par][3];
             products += total;
@@ -1021,7 +1025,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
                     if (tt < total) {
                         uint32_t rel;
                         const uint32_t src = locate(pre, o1, o2, o3, tt, &rel);
-                        v = S.pool[offs[src] + rel];
+                        v = S.pool[2 * (uint64_t)offs[src] + rel];
                     }
                     if (!insert_append(S, out, ch, appended, tt < total, u.c, order ? v : key, order ? key : v, 0)) {
                         if (lane == 0) atomicOr(&sh_fail, 1u);
@@ -1042,7 +1046,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(State S, KeySort K
                     if (tt < total) {
                         uint32_t rel;
                         const uint32_t src = locate(pre, o1, o2, o3, tt, &rel);
-                        v[uu] = S.pool[offs[src] + rel];
+                        v[uu] = S.pool[2 * (uint64_t)offs[src] + rel];
                     }
                 }
                 // the first product into a word lists it (one thread sees it zero)
