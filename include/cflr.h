@@ -346,9 +346,11 @@ void cflr_result_free(cflr_result *r);
  * cflr_solve of the same input.  A request whose footprint alone exceeds the
  * budget fails with ENOMEM.  Besides the budget the server holds, per class,
  * the sort's bucket counters (8 bytes per bucket, budget / 65536 buckets, at
- * least 2^20 and at most 2^26) and a new-pair buffer of 44 bytes per pair, starting at
- * the size earlier solves on ctx grew it to (else 2^26 pairs) unless
- * opts->delta_capacity says otherwise (it grows when a round overflows it).
+ * least 2^20 and at most 2^26) and a new-pair buffer of 44 bytes per pair:
+ * the large class's starts at the size earlier solves on ctx grew it to
+ * (else 2^26 pairs), at most budget / 44 pairs (at least 2^20), the small
+ * class's at 2^22 pairs at most, unless opts->delta_capacity says
+ * otherwise (each grows when a round overflows it).
  * It also admits a request only while the running requests' (key tile,
  * partner) slots -- key tiles of 256 vertices x n partners per matrix --
  * stay within hbm_budget_bytes / 16 (between 2^20 and 2^29).

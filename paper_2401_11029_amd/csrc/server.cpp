@@ -227,14 +227,22 @@ cflr_status cflr_server_create(cflr_ctx *ctx, uint64_t hbm_budget_bytes, uint32_
         s->max_slots = max_slots;
         // sort buckets: an instance needs far less than 1/65536 of its
         // footprint in buckets (one per key tile and 4096-partner segment of
-        // a sorted matrix); capped at 2^26.  The new-pair buffer starts at
-        // the size earlier solves on ctx grew it to, else at 2^26 pairs,
-        // unless the options say otherwise (it grows on overflow).
+        // a sorted matrix); capped at 2^26.  The large run's new-pair buffer
+        // starts at the size earlier solves on ctx grew it to (else 2^26
+        // pairs), at most a budget's worth (44 bytes a pair), the small
+        // run's at 2^22 pairs at most, unless the options say otherwise
+        // (both grow on overflow).
         uint64_t buckets = std::min<uint64_t>(1ull << 26, std::max<uint64_t>(1ull << 20, hbm_budget_bytes / 65536));
-        if (!s->opts.delta_capacity && !ctx->delta_capacity_hint) s->opts.delta_capacity = 1ull << 26;
+        cflr_opts o_run[2] = {s->opts, s->opts};
+        if (!s->opts.delta_capacity) {
+            const uint64_t want = ctx->delta_capacity_hint ? ctx->delta_capacity_hint : 1ull << 26;
+            o_run[1].delta_capacity = std::max<uint64_t>(1ull << 20, std::min(want, hbm_budget_bytes / 44));
+            o_run[0].delta_capacity = std::min<uint64_t>(o_run[1].delta_capacity, 1ull << 22);
+        }
         hip_check(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate");
         try {
-            for (auto &rn : s->run) rn = std::make_unique<Run>(ctx, s->opts, buckets, max_slots, s->stream);
+            for (int c = 0; c < 2; c++)
+                s->run[c] = std::make_unique<Run>(ctx, o_run[c], buckets, max_slots, s->stream);
         } catch (...) {
             for (auto &rn : s->run) rn.reset();
             (void)hipStreamDestroy(s->stream);
