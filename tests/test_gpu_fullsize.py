@@ -1,10 +1,11 @@
 """Full-size parity: the 50,000-vertex memory-alias configuration, the
 200,000-vertex field-sensitive points-to configuration (Fig. 4b, 64 fields,
-386 non-terminals) and the 256-graph memory-alias batch, each solved with
-the launch configuration bench.py times (default options), against the
-oracle's stored per-non-terminal counts and SHA-256 digests
-(tests/golden/alias_50k.json, pointsto_200k.json, alias_batch_le8k.json,
-written by tests/golden/make_goldens.py)."""
+386 non-terminals), value flow at the size of Table 3's povray graph and
+the 256-graph memory-alias batch, each solved with the launch configuration
+bench.py times (default options), against the oracle's stored
+per-non-terminal counts and SHA-256 digests (tests/golden/alias_50k.json,
+pointsto_200k.json, valueflow_346k.json, alias_batch_le8k.json, written by
+tests/golden/make_goldens.py)."""
 
 import hashlib
 import json
@@ -20,6 +21,7 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "alias_50k.json")
 GOLDEN_PT = os.path.join(os.path.dirname(__file__), "golden", "pointsto_200k.json")
 GOLDEN_BATCH = os.path.join(os.path.dirname(__file__), "golden", "alias_batch_le8k.json")
+GOLDEN_VF = os.path.join(os.path.dirname(__file__), "golden", "valueflow_346k.json")
 
 
 def sha_of_pairs(s, d, chunk=1 << 26):
@@ -69,6 +71,29 @@ def test_pointsto_200k_matches_oracle_digests(ctx):
         s, d = r.pairs(x)
         assert sha_of_pairs(s, d) == gold["sha256"][x], x
         del s, d
+
+
+def test_valueflow_346k_matches_oracle_digests(ctx):
+    """Value flow (Fig. 7b, 64 call sites) at the vertex and edge counts of
+    Table 3's povray graph: 1.54e9 pairs on sparse storage (chosen by the
+    default), every non-terminal's count and digest against the oracle's."""
+    import paper_2401_11029_amd as cflr
+    with open(GOLDEN_VF) as f:
+        gold = json.load(f)
+    text, g = workloads.config("valueflow_346k")
+    r = cflr.solve(ctx, cflr.Grammar(text), cflr.Graph.from_workload(ctx, g))
+    st = r.stats()
+    print(f"valueflow_346k: {st['total_pairs']} pairs, {st['rounds']} rounds, "
+          f"{st['fixpoint_ms']:.0f} ms, storage {st['storage']}", flush=True)
+    assert st["storage"] == 2
+    assert r.grammar.nonterminals == gold["order"]
+    assert st["total_pairs"] == gold["total"]
+    for x in gold["order"]:
+        assert r.count(x) == gold["count"][x], x
+        s, d = r.pairs(x)
+        assert sha_of_pairs(s, d) == gold["sha256"][x], x
+        del s, d
+    r.close()
 
 
 def test_alias_batch_matches_oracle_digests(ctx):
