@@ -93,7 +93,27 @@ typedef struct cflr_opts {
                                   engine only (AUTO then picks it), grammars
                                   without right sides of three or more
                                   symbols.  0 (default): none */
+    uint32_t mirror;           /* sparse engine: CFLR_MIRROR_AUTO (default)
+                                  or CFLR_MIRROR_OFF (see below) */
 } cflr_opts;
+
+/* Mirror plans (cflr_opts.mirror; the sparse engine).  The analyses of the
+   paper's appendix hold every edge with its reverse, (u, t, v) and
+   (v, t_bar, u), and their grammars are closed under reversal: Fig. 4b's
+   PT -> LPFS_i PT is the mirror of FT -> FT SPFL_i, and FT holds the
+   transposes of PT's pairs.  Then every semi-naive round (Section 3,
+   opt. 1) derives a set closed under mirroring, and the product of one
+   production of each mirror pair gives the other's new pairs as
+   transposes.  AUTO finds the mirror of the grammar (labels pair by name,
+   t with t_bar; a label without a partner is its own reverse), checks it
+   on the grammar exactly and on the seeds of the graph (every seeded pair's
+   mirror must be seeded), and uses it when both hold; otherwise, and with
+   OFF, every production has its own product.  The result is the same
+   either way (cflr_stats.mirror says which plan ran). */
+enum {
+    CFLR_MIRROR_AUTO = 0,
+    CFLR_MIRROR_OFF = 1
+};
 
 /* Storage engines of a single solve (cflr_opts.storage, cflr_stats.storage). */
 enum {
@@ -131,6 +151,8 @@ typedef struct cflr_stats {
                                   in a round, 16 per pair derived */
     double light_ms;           /* light kernel time (kernel_timing) */
     uint64_t light_algo_bytes; /* its algorithmic bytes, as heavy_algo_bytes */
+    uint32_t mirror;           /* 1: the solve ran a mirror plan (see
+                                  CFLR_MIRROR_AUTO) */
 } cflr_stats;
 
 void cflr_opts_default(cflr_opts *opts);
@@ -189,6 +211,9 @@ typedef struct cflr_grammar_info {
     uint32_t eps_rules;          /* x -> eps after lowering */
     uint32_t terminals;          /* distinct terminal names */
     uint32_t helpers;            /* matrices for suffixes of right sides longer than two */
+    uint32_t mirror_skipped;     /* binary productions whose product a mirror
+                                    plan leaves out (CFLR_MIRROR_AUTO); 0: the
+                                    grammar has no mirror */
 } cflr_grammar_info;
 cflr_status cflr_grammar_info_get(const cflr_grammar *g, cflr_grammar_info *out);
 

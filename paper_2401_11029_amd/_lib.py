@@ -23,7 +23,8 @@ class Opts(C.Structure):
                 ("rounds_per_sync", C.c_uint32),
                 ("chunk_pairs", C.c_uint32),
                 ("storage", C.c_uint32),
-                ("witness", C.c_uint32)]
+                ("witness", C.c_uint32),
+                ("mirror", C.c_uint32)]
 
 
 class Stats(C.Structure):
@@ -43,7 +44,8 @@ class Stats(C.Structure):
                 ("heavy_launches", C.c_uint64),
                 ("heavy_algo_bytes", C.c_uint64),
                 ("light_ms", C.c_double),
-                ("light_algo_bytes", C.c_uint64)]
+                ("light_algo_bytes", C.c_uint64),
+                ("mirror", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -57,7 +59,8 @@ class GrammarInfo(C.Structure):
                 ("terminal_rules", C.c_uint32),
                 ("eps_rules", C.c_uint32),
                 ("terminals", C.c_uint32),
-                ("helpers", C.c_uint32)]
+                ("helpers", C.c_uint32),
+                ("mirror_skipped", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

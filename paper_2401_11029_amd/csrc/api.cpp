@@ -227,6 +227,7 @@ cflr_status cflr_grammar_info_get(const cflr_grammar *g, cflr_grammar_info *out)
         out->eps_rules = (uint32_t)g->low.eps.size();
         out->terminals = (uint32_t)g->low.terminals.size();
         out->helpers = g->low.helpers;
+        out->mirror_skipped = mirror_skipped(g->low);
         return CFLR_OK;
     });
 }

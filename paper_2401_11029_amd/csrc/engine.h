@@ -189,6 +189,10 @@ std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const
 // The sparse engine (sparse.cpp): solves one instance made with dense =
 // false; *timed_out when opts.max_rounds stopped it first.
 void sparse_solve(cflr_ctx *ctx, const cflr_opts &opts, Instance &inst, bool *timed_out);
+// Binary productions a mirror plan of the sparse engine leaves without a
+// product of their own (one of each mirror pair); 0 when the grammar has no
+// mirror (cflr_opts.mirror).
+uint32_t mirror_skipped(const Lowered &low);
 void sparse_counts(Instance &inst);
 // cflr_solve_noalloc: the sparse engine on the file-scope scratch region (no
 // device allocation); results into the caller's device arrays.

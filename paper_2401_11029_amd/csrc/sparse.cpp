@@ -24,7 +24,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 
 #include "engine.h"
 #include "sparse.h"
@@ -45,22 +47,150 @@ struct Plan {
     uint32_t nrank0 = 0, nrank1 = 0;  // matrices with part 0 (part 1) uses
 };
 
+// The mirror of a grammar, when it has one.  Graphs of the paper's
+// analyses hold every edge twice: (u, t, v) and its reverse (v, t_bar, u).
+// If an involution s of the matrices maps every production c -> a b to a
+// production s(c) -> s(b) s(a), every x -> t to s(x) -> t' (t' the reverse
+// label of t) and keeps eps rules, and the seeds are their own mirror image
+// ((x, i, j) seeded iff (s(x), j, i) is), then every round of the
+// semi-naive fixpoint (Section 3, opt. 1) derives a mirror-closed set: by
+// induction, s(c)'s candidates from s(b) s(a) are the transposes of c's
+// from a b, with the same midpoints.  Only one production of each mirror
+// pair then needs its product; the other's new pairs are the transposes.
+// Labels pair by name: t and t_bar; a terminal without a partner is its
+// own reverse.  s is found by refining candidate sets (a greatest fixpoint
+// over the production structure), then checked exactly; mat[x] = s(x),
+// rule[q] = the index of q's mirror production.
+bool find_mirror(const Lowered &low, std::vector<uint32_t> *mat, std::vector<uint32_t> *rule) {
+    const uint32_t M = low.nmat(), T = (uint32_t)low.terminals.size();
+    if (!M || M > 8192 || low.binary.empty()) return false;
+    std::map<std::string, uint32_t> tid;
+    for (uint32_t t = 0; t < T; t++) tid[low.terminals[t]] = t;
+    std::vector<uint32_t> tau(T);
+    for (uint32_t t = 0; t < T; t++) tau[t] = t;
+    // t_bar pairs with t, and an indexed t_bar_k with t_k
+    const std::string bar = "_bar";
+    for (uint32_t t = 0; t < T; t++) {
+        const std::string &nm = low.terminals[t];
+        for (size_t at = nm.find(bar); at != std::string::npos && at > 0; at = nm.find(bar, at + 1)) {
+            const size_t end = at + bar.size();
+            if (end != nm.size() && nm[end] != '_') continue;
+            auto it = tid.find(nm.substr(0, at) + nm.substr(end));
+            if (it != tid.end() && it->second != t) {
+                tau[t] = it->second;
+                tau[it->second] = t;
+                break;
+            }
+        }
+    }
+    std::vector<uint8_t> eps(M, 0);
+    for (uint32_t x : low.eps) eps[x] = 1;
+    std::vector<std::vector<uint32_t>> terms(M), rterms(M);
+    for (auto &tm : low.term) {
+        terms[tm.second].push_back(tm.first);
+        rterms[tm.second].push_back(tau[tm.first]);
+    }
+    for (uint32_t x = 0; x < M; x++) {
+        std::sort(terms[x].begin(), terms[x].end());
+        std::sort(rterms[x].begin(), rterms[x].end());
+    }
+    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> bins(M);
+    for (auto &b : low.binary) bins[b.c].push_back({b.a, b.b});
+    // cand[x * M + y]: y may be s(x)
+    std::vector<uint8_t> cand((size_t)M * M, 0);
+    for (uint32_t x = 0; x < M; x++)
+        for (uint32_t y = 0; y < M; y++)
+            cand[(size_t)x * M + y] = eps[x] == eps[y] && rterms[x] == terms[y] && bins[x].size() == bins[y].size();
+    for (bool changed = true; changed;) {
+        changed = false;
+        for (uint32_t x = 0; x < M; x++)
+            for (uint32_t y = 0; y < M; y++) {
+                if (!cand[(size_t)x * M + y]) continue;
+                bool ok = cand[(size_t)y * M + x];
+                for (size_t p = 0; ok && p < bins[x].size(); p++) {
+                    const uint32_t a = bins[x][p].first, b = bins[x][p].second;
+                    bool found = false;
+                    for (auto &q : bins[y])
+                        if (cand[(size_t)b * M + q.first] && cand[(size_t)a * M + q.second]) {
+                            found = true;
+                            break;
+                        }
+                    ok = found;
+                }
+                if (!ok) {
+                    cand[(size_t)x * M + y] = 0;
+                    changed = true;
+                }
+            }
+    }
+    // pick s from the candidates (first preferring another matrix, then x
+    // itself) and check it exactly against the productions
+    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, uint32_t> prod;
+    for (uint32_t q = 0; q < (uint32_t)low.binary.size(); q++) {
+        const auto &b = low.binary[q];
+        prod[std::make_tuple(b.c, b.a, b.b)] = q;
+    }
+    std::vector<uint32_t> s;
+    auto attempt = [&](bool prefer_self) {
+        s.assign(M, kNone);
+        for (uint32_t x = 0; x < M; x++) {
+            if (s[x] != kNone) continue;
+            uint32_t pick = prefer_self && cand[(size_t)x * M + x] ? x : kNone;
+            for (uint32_t y = 0; pick == kNone && y < M; y++)
+                if (y != x && cand[(size_t)x * M + y] && s[y] == kNone) pick = y;
+            if (pick == kNone && cand[(size_t)x * M + x]) pick = x;
+            if (pick == kNone) return false;
+            s[x] = pick;
+            s[pick] = x;
+        }
+        rule->assign(low.binary.size(), kNone);
+        for (uint32_t q = 0; q < (uint32_t)low.binary.size(); q++) {
+            const auto &b = low.binary[q];
+            auto it = prod.find(std::make_tuple(s[b.c], s[b.b], s[b.a]));
+            if (it == prod.end()) return false;
+            (*rule)[q] = it->second;
+        }
+        for (uint32_t x = 0; x < M; x++)
+            if (s[s[x]] != x || eps[x] != eps[s[x]] || rterms[x] != terms[s[x]]) return false;
+        return true;
+    };
+    if (!attempt(false) && !attempt(true)) return false;
+    bool any = false;
+    for (uint32_t q = 0; q < (uint32_t)rule->size(); q++) any = any || (*rule)[q] != q;
+    if (!any) return false;  // nothing to save
+    *mat = std::move(s);
+    return true;
+}
+
 // Layouts, use tables and observers of a lowered grammar on n vertices.
 // Row layouts: matrices in a b slot and the text's non-terminals (results
-// are read out by rows); column layouts: matrices in an a slot.
-Plan make_plan(const Lowered &low, uint32_t n) {
+// are read out by rows); column layouts: matrices in an a slot.  Under a
+// mirror plan (rule_mirror non-empty) only one production of each mirror
+// pair -- the one with the lower index -- gets uses, and only its operands'
+// layouts are kept.
+Plan make_plan(const Lowered &low, uint32_t n, const std::vector<uint32_t> &rule_mirror) {
     Plan P;
     const uint32_t M = low.nmat(), U = (uint32_t)low.user_names.size();
+    const uint32_t B = (uint32_t)low.binary.size();
+    std::vector<uint8_t> keep(B, 1), slot_a(M, 0), slot_b(M, 0);
+    for (uint32_t q = 0; q < B; q++) {
+        if (!rule_mirror.empty() && rule_mirror[q] < q) keep[q] = 0;
+        if (keep[q]) {
+            slot_a[low.binary[q].a] = 1;
+            slot_b[low.binary[q].b] = 1;
+        }
+    }
     sp::MatInfo none{};
     none.row_layout = none.col_layout = kNone;
     none.rank0 = none.rank1 = kNone;
     P.mats.assign(M, none);
     for (uint32_t x = 0; x < M; x++)
-        if (low.slot_b[x] || x < U) P.mats[x].row_layout = P.nlayouts++;
+        if (slot_b[x] || x < U) P.mats[x].row_layout = P.nlayouts++;
     for (uint32_t x = 0; x < M; x++)
-        if (low.slot_a[x]) P.mats[x].col_layout = P.nlayouts++;
+        if (slot_a[x]) P.mats[x].col_layout = P.nlayouts++;
     std::vector<std::vector<sp::Use>> u0(M), u1(M);
-    for (uint32_t q = 0; q < (uint32_t)low.binary.size(); q++) {
+    for (uint32_t q = 0; q < B; q++) {
+        if (!keep[q]) continue;
         const auto &b = low.binary[q];
         u0[b.a].push_back(sp::Use{b.c, P.mats[b.b].row_layout, P.mats[b.c].row_layout, q});
         u1[b.b].push_back(sp::Use{b.c, P.mats[b.a].col_layout, P.mats[b.c].col_layout, q});
@@ -226,7 +356,12 @@ uint64_t seed_slack(uint64_t m, uint64_t eps_pairs) {
     return (waves(m) + waves(eps_pairs)) * sp::kChunk;
 }
 
+// Thrown by sparse_core when the seeds of a mirror plan are not their own
+// mirror image; solve_core then solves without the plan.
+struct MirrorRejected {};
+
 struct CoreOut {
+    bool mirror = false;  // a mirror plan ran
     Mem dir, pool;  // the adjacency lists, kept for readout
     Mem hash, wit;  // the pair set and its witnesses, kept when witnesses are recorded
     uint64_t hash_slots = 0;
@@ -235,7 +370,7 @@ struct CoreOut {
     uint64_t seed_pairs = 0, new_pairs = 0, max_delta = 0, launches = 0;
     double product_ms = 0;
     // the heavy-bucket kernel of the grouped product (timing and accounting)
-    double heavy_ms = 0, light_ms = 0;
+    double heavy_ms = 0, light_ms = 0, mirror_ms = 0;
     uint64_t heavy_launches = 0, heavy_bytes = 0, light_bytes = 0;
     bool timed_out = false;
 };
@@ -256,8 +391,18 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
     auto too_small = [&](const char *what) {
         return Error(CFLR_ENOMEM, std::string("the no-alloc scratch cannot hold ") + what + " of this solve");
     };
-    res.plan = make_plan(low, n);
+    // a mirror plan when the grammar has a mirror (checked on the seeds below)
+    std::vector<uint32_t> mirror_mat, mirror_rule;
+    const bool mirrored = o.mirror != CFLR_MIRROR_OFF && find_mirror(low, &mirror_mat, &mirror_rule);
+    if (!mirrored) mirror_rule.clear();
+    res.plan = make_plan(low, n, mirror_rule);
+    res.mirror = mirrored;
     const Plan &P = res.plan;
+    Mem d_mirror, d_mirror_rule;
+    if (mirrored) {
+        d_mirror = upload(A, mirror_mat, s, "the mirror tables");
+        d_mirror_rule = upload(A, mirror_rule, s, "the mirror tables");
+    }
 
     Mem d_mats = upload(A, P.mats, s, "the matrix table");
     Mem d_uses = upload(A, P.uses, s, "the use table");
@@ -421,12 +566,17 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         if (out) hip_check(hipMemcpyAsync(h_ctl + sp::kCtlWords, out->count.ptr, 8, hipMemcpyDeviceToHost, s), "D2H");
         hip_check(hipStreamSynchronize(s), "sync");
     };
-    auto clear_flags = [&]() {
-        // halt, overflow flags; keep the pool top and the tombstone count
+    auto clear_flags = [&](bool counters = true) {
+        // halt, overflow flags and (counters) the product's counts; keep the
+        // pool top and the tombstone count
         const int words[] = {sp::kCtlHalt,     sp::kCtlPoolOver,   sp::kCtlBufOver,         sp::kCtlHashFull,
                              sp::kCtlTasks,    sp::kCtlProducts,   sp::kCtlHeavyTasks,      sp::kCtlHeavyProducts,
                              sp::kCtlHeavyCand};
-        for (int w : words) hip_check(sp::launch_fill_u64(S.ctl + w, 1, 0, s), "fill");
+        for (int w : words) {
+            if (!counters && w != sp::kCtlHalt && w != sp::kCtlPoolOver && w != sp::kCtlBufOver && w != sp::kCtlHashFull)
+                continue;
+            hip_check(sp::launch_fill_u64(S.ctl + w, 1, 0, s), "fill");
+        }
     };
 
     // ---- seeds (a re-run after an overflow inserts only what is missing)
@@ -448,6 +598,21 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         if (h_ctl[sp::kCtlHashFull]) want = std::max(want, 2 * cur_slots);
         if (want > cur_slots) rehash_to(want);
         clear_flags();
+    }
+    if (mirrored) {
+        // the seeds must be their own mirror image (the graph holds every
+        // edge with its reverse); else the caller solves without the plan
+        S.mirror = d_mirror.as<uint32_t>();
+        S.mirror_rule = d_mirror_rule.as<uint32_t>();
+        hip_check(sp::launch_mirror_check(S, BA.dev(), std::min<uint64_t>(h_ctl[sp::kCtlWords], BA.cap), s),
+                  "mirror check");
+        read_ctl(nullptr);
+        if (h_ctl[sp::kCtlMirrorMiss]) {
+            if (log)
+                std::fprintf(stderr, "[cflr] sparse: %llu seeds without their mirror; no mirror plan\n",
+                             (unsigned long long)h_ctl[sp::kCtlMirrorMiss]);
+            throw MirrorRejected{};
+        }
     }
     uint64_t pending = h_ctl[sp::kCtlNew];
     res.seed_pairs = pending;
@@ -573,10 +738,10 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlNew, 1, 0, s), "fill");
         hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlProducts, 1, 0, s), "fill");
         hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlHeavyProducts, 2, 0, s), "fill");
-        const double heavy_ms0 = res.heavy_ms, light_ms0 = res.light_ms;
+        const double heavy_ms0 = res.heavy_ms, light_ms0 = res.light_ms, mirror_ms0 = res.mirror_ms;
         const uint64_t heavy_b0 = res.heavy_bytes, light_b0 = res.light_bytes;
-        timed_product();
-        for (int attempt = 0; h_ctl[sp::kCtlHalt]; attempt++) {
+        // an overflow halted the step: grow what overflowed before re-running it
+        auto grow_for_rerun = [&](int attempt, const char *step, bool counters) {
             if (fixed) throw too_small("the pairs");
             if (attempt > 64) throw Error(CFLR_ENOMEM, "new-pair buffer or hash set keeps overflowing");
             res.reruns++;
@@ -593,10 +758,34 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
             if (h_ctl[sp::kCtlHashFull]) want = std::max(want, 2 * cur_slots);
             if (want > cur_slots) rehash_to(want);  // drops the tombstones
             if (log)
-                std::fprintf(stderr, "[cflr] sparse: round %u re-run (buffer %llu, slots %llu)\n", res.rounds,
+                std::fprintf(stderr, "[cflr] sparse: round %u %s re-run (buffer %llu, slots %llu)\n", res.rounds, step,
                              (unsigned long long)out->cap, (unsigned long long)cur_slots);
-            clear_flags();
+            clear_flags(counters);
+        };
+        timed_product();
+        for (int attempt = 0; h_ctl[sp::kCtlHalt]; attempt++) {
+            grow_for_rerun(attempt, "product", true);
             timed_product();
+        }
+        if (mirrored) {
+            // the mirrors of the product's pairs, appended behind them
+            const uint64_t nprod = std::min<uint64_t>(h_ctl[sp::kCtlWords], out->cap);
+            if (ev0) hip_check(hipEventRecord(ev0, s), "event");
+            hip_check(sp::launch_mirror(S, out->dev(), nprod, waves, s), "mirror");
+            read_ctl(out);
+            for (int attempt = 0; h_ctl[sp::kCtlHalt]; attempt++) {
+                grow_for_rerun(attempt, "mirror pass", false);
+                hip_check(sp::launch_mirror(S, out->dev(), nprod, waves, s), "mirror");
+                read_ctl(out);
+            }
+            if (ev0) {
+                hip_check(hipEventRecord(ev1, s), "event");
+                hip_check(hipEventSynchronize(ev1), "event");
+                float ms = 0;
+                hip_check(hipEventElapsedTime(&ms, ev0, ev1), "event");
+                res.mirror_ms += ms;
+                res.product_ms += ms;
+            }
         }
         // kCtlNew counts every pair appended this round, over re-runs too
         const uint64_t fresh = h_ctl[sp::kCtlNew];
@@ -608,13 +797,14 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         if (log)
             std::fprintf(stderr,
                          "[cflr] sparse round %u: in %llu new %llu products %llu heavy items %llu products %llu "
-                         "candidates %llu pool %llu/%llu slots %llu heavy %.2f ms light %.2f ms "
+                         "candidates %llu pool %llu/%llu slots %llu heavy %.2f ms light %.2f ms mirror %.2f ms "
                          "algo bytes heavy %llu light %llu\n",
                          res.rounds, (unsigned long long)pending, (unsigned long long)fresh,
                          (unsigned long long)h_ctl[sp::kCtlProducts], (unsigned long long)h_ctl[sp::kCtlHeavy],
                          (unsigned long long)h_ctl[sp::kCtlHeavyProducts], (unsigned long long)h_ctl[sp::kCtlHeavyCand],
                          (unsigned long long)h_ctl[sp::kCtlPoolTop], (unsigned long long)pool_cap,
                          (unsigned long long)cur_slots, res.heavy_ms - heavy_ms0, res.light_ms - light_ms0,
+                         res.mirror_ms - mirror_ms0,
                          (unsigned long long)(res.heavy_bytes - heavy_b0),
                          (unsigned long long)(res.light_bytes - light_b0));
         pending = fresh;
@@ -636,6 +826,25 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         hip_check(hipStreamSynchronize(s), "sync");
         A.release_to(fixed_mark);  // the hash set, buffers and queues are free again (readout scratch)
     }
+}
+
+// sparse_core with a mirror plan when one applies; when the seeds reject
+// it, again without (from the same point of the region, in a fixed one).
+void solve_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered &low, uint32_t n,
+                const SeedInput &in_seed, Alloc &A, CoreOut &res) {
+    if (o.mirror != CFLR_MIRROR_OFF) {
+        const uint64_t mark = A.fixed() ? A.mark() : 0;
+        try {
+            sparse_core(ctx, s, o, low, n, in_seed, A, res);
+            return;
+        } catch (const MirrorRejected &) {
+            res = CoreOut{};
+            if (A.fixed()) A.release_to(mark);
+        }
+    }
+    cflr_opts off = o;
+    off.mirror = CFLR_MIRROR_OFF;
+    sparse_core(ctx, s, off, low, n, in_seed, A, res);
 }
 
 // Graph label -> the matrices x with x -> label (after lowering), as
@@ -663,6 +872,15 @@ void label_tables(const Lowered &low, const std::vector<std::string> &label_name
 
 // ------------------------------------------------------------------- solve
 
+uint32_t mirror_skipped(const Lowered &low) {
+    std::vector<uint32_t> mat, rule;
+    if (!find_mirror(low, &mat, &rule)) return 0;
+    uint32_t k = 0;
+    for (uint32_t q = 0; q < (uint32_t)rule.size(); q++) k += rule[q] < q;
+    return k;
+}
+
+
 void sparse_solve(cflr_ctx *ctx, const cflr_opts &o, Instance &inst, bool *timed_out) {
     Alloc A(ctx->pool.get());
     SeedInput in;
@@ -676,7 +894,7 @@ void sparse_solve(cflr_ctx *ctx, const cflr_opts &o, Instance &inst, bool *timed
     in.n_eps = inst.n_eps;
     in.max_seeds = inst.max_seeds;
     CoreOut res;
-    sparse_core(ctx, ctx->stream, o, inst.low, inst.n, in, A, res);
+    solve_core(ctx, ctx->stream, o, inst.low, inst.n, in, A, res);
     *timed_out = res.timed_out;
     auto store = std::make_shared<SparseStore>();
     store->hold = CtxRef(ctx);
@@ -723,6 +941,7 @@ void sparse_solve(cflr_ctx *ctx, const cflr_opts &o, Instance &inst, bool *timed
     inst.stats.heavy_algo_bytes = res.heavy_bytes;
     inst.stats.light_ms = res.light_ms;
     inst.stats.light_algo_bytes = res.light_bytes;
+    inst.stats.mirror = res.mirror ? 1 : 0;
     inst.stats.device_bytes = store->dir.bytes + store->pool.bytes;
     inst.sp = store;
 }
@@ -887,7 +1106,7 @@ void sparse_solve_noalloc(cflr_ctx *ctx, const Lowered &low, uint32_t n, uint64_
     in.n_eps = (uint32_t)low.eps.size();
     in.max_seeds = m * max_per_label + (uint64_t)n * in.n_eps;
     CoreOut res;
-    sparse_core(ctx, s, o, low, n, in, A, res);
+    solve_core(ctx, s, o, low, n, in, A, res);
     // readout into the caller's arrays, each non-terminal's pairs sorted by
     // (i, j), one after another in first-appearance order; the scratch
     // after the lists holds the counts, offsets and sort bit sets

@@ -162,6 +162,11 @@ struct State {
     unsigned long long *hash;  // hash slots
     uint64_t hash_mask;        // slots - 1 (a power of two minus one)
     unsigned long long *wit;   // per hash slot, the witness of its pair (null: not kept)
+    // mirror plan (null: none): per matrix its mirror, per binary production
+    // its mirror production; after a round's product, the mirror pass
+    // inserts (mirror[x], j, i) for each new pair (x, i, j)
+    const uint32_t *mirror;
+    const uint32_t *mirror_rule;
     uint32_t round;            // the round being run (0 while seeding), for witnesses
     // bookkeeping words (kCtl* below)
     unsigned long long *ctl;
@@ -189,7 +194,8 @@ constexpr int kCtlPoolTop = 0,   // pool entries handed out
     kCtlHeavyProducts = 15,      // products of the heavy items
     kCtlHeavyCand = 16,          // candidates the heavy items sent to the hash set
     kCtlLight = 17,              // entries of the light buckets listed
-    kCtlWords = 18;
+    kCtlMirrorMiss = 18,         // seeds whose mirror pair is missing (mirror plans)
+    kCtlWords = 19;
 
 // ------------------------------------------------------------------ launchers
 
@@ -198,6 +204,15 @@ constexpr int kCtlPoolTop = 0,   // pool entries handed out
 hipError_t launch_seed(const State &S, const uint32_t *src, const uint32_t *dst, const uint32_t *lab, uint64_t m,
                        const uint32_t *lm_ptr, const uint32_t *lm_mat, const uint32_t *eps_mat, uint32_t n_eps,
                        PairBuf out, hipStream_t s);
+// Mirror plans: count into ctl[kCtlMirrorMiss] the first `count` entries
+// (m, i, j) of the seed buffer whose mirror (S.mirror[m], j, i) is not in
+// the hash set (holes skipped).
+hipError_t launch_mirror_check(const State &S, PairBuf seeds, uint64_t count, hipStream_t s);
+// Mirror plans, after a round's product: insert the mirror of each of the
+// first `count` pairs of `out` and append the new ones behind them (an
+// overflow halts the pass; the host grows and re-runs it over the same
+// `count` pairs).
+hipError_t launch_mirror(const State &S, PairBuf out, uint64_t count, uint32_t grid_waves, hipStream_t s);
 // Add the new pairs `in` to the adjacency lists, in two launches: count
 // (and, with K, the key sort's bucket counts in the same pass), plan, check,
 // move; then, once the pool held (launch_integrate_finish), the buckets'

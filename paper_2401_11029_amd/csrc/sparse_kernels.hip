@@ -250,6 +250,81 @@ __global__ __launch_bounds__(256) void seed_eps_kernel(State S, const uint32_t *
     add_appended(S, appended);
 }
 
+// Is `key` in the table?  Linear probing as hash_insert (tombstones are
+// passed over).
+__device__ __forceinline__ bool hash_contains(const unsigned long long *tab, uint64_t hmask, uint64_t key) {
+    uint64_t h = mix64(key) & hmask;
+    for (uint32_t p = 0; p < kMaxProbes; p++) {
+        const unsigned long long v = tab[h];
+        if (v == key) return true;
+        if (v == kEmpty) return false;
+        h = (h + 1) & hmask;
+    }
+    return false;
+}
+
+// A mirror plan is exact only when the seeds are their own mirror image:
+// count (into ctl[kCtlMirrorMiss]) the seeds (m, i, j) whose mirror
+// (mirror[m], j, i) is not in the hash set.
+__global__ __launch_bounds__(256) void mirror_check_kernel(State S, PairBuf seeds, uint64_t count) {
+    unsigned long long miss = 0;
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < count;
+         p += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t m = seeds.key[p];
+        if (m == kHoleKey) continue;
+        if (!hash_contains(S.hash, S.hash_mask, pair_key(S.mirror[m], seeds.j[p], seeds.i[p]))) miss++;
+    }
+    miss = wave_sum64(miss);
+    if (lane_id() == 0 && miss) atomicAdd(&S.ctl[kCtlMirrorMiss], miss);
+}
+
+// The hash slot holding `key`, or ~0 when it is not in the table.
+__device__ __forceinline__ uint64_t hash_slot(const unsigned long long *tab, uint64_t hmask, uint64_t key) {
+    uint64_t h = mix64(key) & hmask;
+    for (uint32_t p = 0; p < kMaxProbes; p++) {
+        const unsigned long long v = tab[h];
+        if (v == key) return h;
+        if (v == kEmpty) return ~0ull;
+        h = (h + 1) & hmask;
+    }
+    return ~0ull;
+}
+
+// Mirror plans: after a round's product, insert the mirror (mirror[m], j, i)
+// of each of the round's first `count` new pairs (m, i, j) and append the
+// ones that are new behind them, with the mirror production in the witness.
+// A re-run after an overflow covers the same `count` pairs: mirrors already
+// appended are found present.
+__global__ __launch_bounds__(256) void mirror_kernel(State S, PairBuf out, uint64_t count) {
+    Chunk ch;
+    uint64_t appended = 0;
+    for (uint64_t base = wave_global_id() * 64; base < count; base += waves_in_grid() * 64) {
+        const uint64_t p = base + lane_id();
+        uint32_t m = kHoleKey, i = 0, j = 0;
+        if (p < count) {
+            m = out.key[p];
+            i = out.i[p];
+            j = out.j[p];
+        }
+        const bool has = m != kHoleKey;
+        uint64_t w = 0;
+        if (S.wit && has) {
+            const uint64_t at = hash_slot(S.hash, S.hash_mask, pair_key(m, i, j));
+            if (at != ~0ull) {
+                w = S.wit[at];
+                const uint32_t rule = (uint32_t)(w >> 24) & 0xFFFFFFu;
+                if (rule < kWitEps) w = (w & ~(0xFFFFFFull << 24)) | ((uint64_t)(S.mirror_rule[rule] & 0xFFFFFFu) << 24);
+            }
+        }
+        if (!insert_append(S, out, ch, appended, has, has ? S.mirror[m] : 0u, j, i, w)) {
+            add_appended(S, appended);
+            return;
+        }
+    }
+    chunk_retire(out, ch);
+    add_appended(S, appended);
+}
+
 // A sorted entry of the key sort: matrix, key vertex, partner vertex.
 __device__ __forceinline__ uint64_t pack_entry(uint32_t x, uint32_t key, uint32_t partner) {
     return ((uint64_t)x << 48) | ((uint64_t)key << 24) | (uint64_t)partner;
@@ -1418,6 +1493,20 @@ hipError_t launch_seed(const State &S, const uint32_t *src, const uint32_t *dst,
         SP_LAUNCH_CHECK();
     }
     return hipSuccess;
+}
+
+hipError_t launch_mirror_check(const State &S, PairBuf seeds, uint64_t count, hipStream_t s) {
+    if (!count) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((count + 255) / 256, 4096);
+    mirror_check_kernel<<<(uint32_t)blocks, 256, 0, s>>>(S, seeds, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_mirror(const State &S, PairBuf out, uint64_t count, uint32_t grid_waves, hipStream_t s) {
+    if (!count) return hipSuccess;
+    const uint64_t waves = std::min<uint64_t>(grid_waves, (count + 63) / 64);
+    mirror_kernel<<<(uint32_t)((waves + 3) / 4), 256, 0, s>>>(S, out, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_round_start(const State &S, hipStream_t s) {

@@ -51,7 +51,31 @@ def test_lowering_dyck1(cflr_lib):
     nts, i = info(G.DYCK1)
     assert nts == ["S", "X", "A", "B"]
     assert i == dict(user_nonterminals=4, wrappers=0, matrices=4, binary=4,
-                     terminal_rules=2, eps_rules=1, terminals=2, helpers=0)
+                     terminal_rules=2, eps_rules=1, terminals=2, helpers=0, mirror_skipped=0)
+
+
+def test_mirror_of_grammars(cflr_lib):
+    # Fig. 4b is closed under reversal (PT <-> FT, LP_i <-> FL_i, FS_i <->
+    # SP_i, LPFS_i <-> SPFL_i; t <-> t_bar): one production of each of the
+    # 257 mirror pairs keeps its product.  Fig. 4a, the alias grammars and
+    # Dyck-1 have no syntactic mirror.
+    assert info(G.pointsto_fig4b(64))[1]["mirror_skipped"] == 257
+    assert info(G.pointsto_fig4b(8))[1]["mirror_skipped"] == 33
+    for text in (G.pointsto_fig4a(8), G.ALIAS_FIG5A, G.ALIAS_FIG5B, G.DYCK1, G.fsca_fig6b(4), G.cscvf_fig7b(4)):
+        assert info(text)[1]["mirror_skipped"] == 0
+    # a mirror pair found through the structure: FT's production mirrors PT's
+    base = "PT -> alloc | assign PT\nFT -> alloc_bar | FT assign_bar\n"
+    assert info(base)[1]["mirror_skipped"] == 1
+    # a rule whose mirror is missing breaks it
+    assert info(base + "PT -> PT load\n")[1]["mirror_skipped"] == 0
+    assert info("PT -> alloc | assign PT\nFT -> alloc_bar | assign_bar FT\n")[1]["mirror_skipped"] == 0
+    # a self-mirrored non-terminal: S -> A T | T2 B with T -> S B, T2 -> A S
+    # (S and the eps rule are their own mirror; T <-> T2, A <-> B)
+    assert info("S -> eps | A T | T2 B\nT -> S B\nT2 -> A S\nA -> a\nB -> a_bar\n")[1]["mirror_skipped"] == 2
+    # a label without a partner is its own reverse: X <-> Y through c
+    assert info("R -> c | X R | R Y\nX -> c\nY -> c\n")[1]["mirror_skipped"] == 1
+    # the same language without the mirrored productions has no mirror
+    assert info("S -> eps | A S2\nS2 -> S B\nA -> a\nB -> a_bar\n")[1]["mirror_skipped"] == 0
 
 
 def test_lowering_long_right_sides(cflr_lib):
@@ -61,7 +85,7 @@ def test_lowering_long_right_sides(cflr_lib):
     nts, i = info(G.ALIAS_FIG5A)
     assert nts == ["M", "V", "V1", "V2", "V3"]
     assert i == dict(user_nonterminals=5, wrappers=4, matrices=12, binary=8,
-                     terminal_rules=4, eps_rules=4, terminals=4, helpers=3)
+                     terminal_rules=4, eps_rules=4, terminals=4, helpers=3, mirror_skipped=0)
     # a right side of four symbols: two helpers per distinct suffix chain
     nts, i = info("S -> a S b S | eps")
     assert nts == ["S"] and i["helpers"] == 2 and i["binary"] == 3 and i["wrappers"] == 2

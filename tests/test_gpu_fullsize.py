@@ -64,6 +64,7 @@ def test_pointsto_200k_matches_oracle_digests(ctx):
     print(f"pointsto_200k: {st['total_pairs']} pairs, {st['rounds']} rounds, "
           f"{st['fixpoint_ms']:.0f} ms, storage {st['storage']}", flush=True)
     assert st["storage"] == 2  # the dense matrices would not fit: sparse storage
+    assert st["mirror"] == 1   # Fig. 4b on a graph with every reverse edge: the mirror plan
     assert r.grammar.nonterminals == gold["order"]
     assert st["total_pairs"] == gold["total"]
     for x in gold["order"]:
@@ -71,6 +72,14 @@ def test_pointsto_200k_matches_oracle_digests(ctx):
         s, d = r.pairs(x)
         assert sha_of_pairs(s, d) == gold["sha256"][x], x
         del s, d
+    r.close()
+    # every production with its own product: the same counts
+    r = cflr.solve(ctx, cflr.Grammar(text), cflr.Graph.from_workload(ctx, g), mirror=1)
+    st = r.stats()
+    print(f"pointsto_200k without the mirror plan: {st['fixpoint_ms']:.0f} ms", flush=True)
+    assert st["mirror"] == 0 and st["total_pairs"] == gold["total"]
+    assert r.counts() == gold["count"]
+    r.close()
 
 
 def test_valueflow_346k_matches_oracle_digests(ctx):
@@ -141,6 +150,7 @@ def test_pointsto_200k_witnesses_on_a_sample(ctx):
     st = r.stats()
     print(f"pointsto_200k with witnesses: {st['rounds']} rounds, {st['fixpoint_ms']:.0f} ms", flush=True)
     assert st["total_pairs"] == gold["total"]
+    assert st["mirror"] == 1  # the mirrored pairs carry the mirror production
     syms = gr.symbols
     U = len(gr.nonterminals)
     n = g.n

@@ -59,6 +59,8 @@ def test_witnesses_certify_the_fixpoint(ctx, tmp_path, case):
         text, g = g
     print(f"witness {name} n={g.n} m={g.m}", flush=True)
     gr, r, res = solve_with_witnesses(ctx, text, g)
+    if name == "pointsto":  # Fig. 4b: half of the pairs come from the mirror plan's transposes
+        assert r.stats()["mirror"] == 1
     orc = oracle.solve(text, g)
     for x in gr.nonterminals:
         s, d = res[x][:2]
