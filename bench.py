@@ -11,7 +11,11 @@ would need terabytes, so the library solves it on sparse storage.  The
 graph is resident in device memory before timing starts; a step runs
 seeding, every round and the convergence test.  value = derived pairs per
 second over the K timed steps: pairs of the grammar's non-terminals minus
-the pairs seeding puts there.
+the pairs seeding puts there.  The grammar is closed under reversal and the
+graph holds every edge with its reverse, so the library solves it with a
+mirror plan (one production of each mirror pair keeps its product; the
+transposes of its new pairs are the other's); other_configs gives the same
+solve with every production's product (cflr_opts.mirror = OFF).
 
 The JSON line also carries:
   roofline      the dominant kernel of the sparse engine's product (the
@@ -22,7 +26,10 @@ The JSON line also carries:
                 and output row read in a round, 16 per pair derived) over
                 its average launch time (HIP events on the library's stream
                 in the timed steps); traffic from the committed rocprofv3
-                FETCH_SIZE / WRITE_SIZE summary of the same kernel;
+                FETCH_SIZE / WRITE_SIZE summary of the same kernel; beside
+                the 8 TB/s peak, the bandwidth of a plain device copy
+                measured on the same GPU (stream_copy_gbs) as a second
+                denominator;
   cpu_baseline  the CPU oracle, pinned to one host core, on a bounded sample
                 of the same workload (the same generator at 24,000
                 vertices), with the oracle's full-size time beside it;
@@ -194,10 +201,57 @@ def alias_context(cflr, args):
     return out
 
 
+def stream_copy_gbs(reps=5, words=1 << 29):
+    """Bandwidth of a plain device copy (2 GiB read, 2 GiB written by one
+    kernel), best of `reps`, timed with HIP events."""
+    import torch
+    a = torch.ones(words, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * 4 * words / (best / 1e3) / 1e9
+
+
+def plain_plan(cflr, args, text, g):
+    """The headline solve with every production's own product (no mirror
+    plan), timed as the headline (fewer steps)."""
+    ctx = cflr.Context(0)
+    gr = cflr.Grammar(text)
+    graph = cflr.Graph.from_workload(ctx, g)
+    for w in range(max(1, args.warmup)):
+        cflr.solve(ctx, gr, graph, mirror=1).close()
+    stats = []
+    for k in range(max(1, min(2, args.steps))):
+        r = cflr.solve(ctx, gr, graph, mirror=1, kernel_timing=1)
+        stats.append(r.stats())
+        r.close()
+        log(f"plain plan step {k}: {stats[-1]['fixpoint_ms']:.1f} ms")
+    del graph, gr
+    ctx.close()
+    out = {"workload": "pointsto_200k without the mirror plan (cflr_opts.mirror = OFF): every one of "
+                       "the 514 binary productions has its own product",
+           "mirror_plan": bool(stats[-1]["mirror"]), "total_pairs": stats[-1]["total_pairs"],
+           "heavy_ms_mean": sum(s["heavy_ms"] for s in stats) / len(stats)}
+    out.update(fix_summary(stats))
+    return out
+
+
 def single(args):
     import torch
     import paper_2401_11029_amd as cflr
     import workloads
+    copy_gbs = stream_copy_gbs()
+    log(f"stream copy: {copy_gbs:.0f} GB/s")
     text, g = workloads.config(HEADLINE)
     log(f"workload {HEADLINE}: n={g.n} edges={g.m}")
     ctx = cflr.Context(0)
@@ -243,6 +297,7 @@ def single(args):
            "storage": "sparse" if stats[-1]["storage"] == 2 else "dense",
            "pairs": stats[-1]["total_pairs"], "derived_pairs": derived,
            "rounds": stats[-1]["rounds"],
+           "mirror_plan": bool(stats[-1]["mirror"]),
            "product_ms_mean": sum(s["product_ms"] for s in stats) / len(stats)}
     cfg.update(fix_summary(stats))
     out = {
@@ -264,6 +319,8 @@ def single(args):
                      "traffic": traffic,
                      "amplification": (traffic / d["algo_bytes_per_launch"])
                      if traffic and d["algo_bytes_per_launch"] else None,
+                     "stream_copy_gbs": copy_gbs,
+                     "frac_of_stream_copy": d["achieved"] / copy_gbs,
                      "kernel": dom,
                      "algo_bytes_per_launch": d["algo_bytes_per_launch"],
                      "avg_launch_ms": d["avg_launch_ms"],
@@ -272,7 +329,8 @@ def single(args):
     if not args.no_other:
         del graph, gr
         ctx.close()
-        out["other_configs"] = {"alias_50k": alias_context(cflr, args)}
+        out["other_configs"] = {"pointsto_200k_plain_plan": plain_plan(cflr, args, text, g),
+                                "alias_50k": alias_context(cflr, args)}
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline()
