@@ -38,7 +38,9 @@ The JSON line also carries:
                 Fig. 5a's own non-terminals (M, V, V1, V2, V3).
 
 --mode batch reports the batched form (256 alias graphs in one call vs one
-plain solve after another); --mode serve reports the served form (Poisson
+plain solve after another; --batch-grammar dyck: Dyck-1 on G(n, m) graphs of
+the same sizes; beside it the oracle over the small graphs on every host
+core); --mode serve reports the served form (Poisson
 arrivals of mixed queries, solves/s and p50/p99 latency against a
 one-at-a-time plain path); --mode grammars times the paper's hand-normalised
 grammars against the automatically normalised ones on the same graphs
@@ -337,18 +339,42 @@ def single(args):
     print(json.dumps(out), flush=True)
 
 
+def oracle_pool(text, gs, threads):
+    """The oracle, as it is, over independent graphs on `threads` host cores
+    at once (one oracle process per graph): wall seconds."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda g: oracle.solve(text, g, pairs=False, digest=False), gs))
+    return time.perf_counter() - t0
+
+
 def batch(args):
-    """256 alias graphs (n log-uniform in [1k, 40k], stored degree U[2, 3])
-    solved by one batched call vs one plain solve after another."""
+    """256 graphs (n log-uniform in [1k, 40k], stored degree U[2, 3]) of the
+    alias grammar (Fig. 5a; the default) or of Dyck-1 on G(n, m) graphs
+    (--batch-grammar dyck) solved by one batched call vs one plain solve
+    after another; beside it the oracle over the graphs of at most
+    --batch-oracle-max-n vertices on every host core (one oracle process
+    per graph) against the batched call on the same graphs."""
     import torch
     import paper_2401_11029_amd as cflr
     from workloads import graphs, grammars
     os.environ["CFLR_PROGRESS"] = "1"
-    gs = graphs.alias_batch(args.batch_count, n_hi=args.batch_max_n)
+    if args.batch_grammar == "dyck":
+        gs = graphs.dyck_batch(args.batch_count, n_hi=args.batch_max_n)
+        text = grammars.DYCK1
+        wl = (f"dyck_batch: {len(gs)} Dyck-1 graphs (directed G(n, m), labels a/b), n log-uniform "
+              f"[1000, {args.batch_max_n}], stored degree U[2,3], seeds 3000+g")
+    else:
+        gs = graphs.alias_batch(args.batch_count, n_hi=args.batch_max_n)
+        text = grammars.ALIAS_FIG5A_WCNF
+        wl = (f"alias_batch: {len(gs)} alias graphs, n log-uniform [1000, {args.batch_max_n}], "
+              f"stored degree U[2,3], seeds 3000+g")
     log(f"batch: {len(gs)} graphs, n {min(g.n for g in gs)}..{max(g.n for g in gs)}, "
         f"{sum(g.m for g in gs)} edges")
     ctx = cflr.Context(0)
-    gr = cflr.Grammar(grammars.ALIAS_FIG5A_WCNF)
+    gr = cflr.Grammar(text)
     objs = [cflr.Graph.from_workload(ctx, g) for g in gs]
     # warm-up: one full untimed batch, so that the timed one starts with the
     # new-pair buffer already grown to what the batch needs
@@ -368,6 +394,16 @@ def batch(args):
     for r in res:
         r.close()
     log(f"batched: {tb:.2f} s")
+    # the same call on the small graphs alone (the oracle's share below)
+    small = [k for k, g in enumerate(gs) if g.n <= args.batch_oracle_max_n]
+    tb_small = None
+    if small:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in cflr.solve_batch(ctx, gr, [objs[k] for k in small]):
+            r.close()
+        torch.cuda.synchronize()
+        tb_small = time.perf_counter() - t0
     # the plain solves get a context of their own: a context starts its
     # new-pair buffer at the largest size an earlier run on it needed, and
     # the batch's would oversize every single solve.  The batch's context
@@ -390,6 +426,16 @@ def batch(args):
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
     log(f"sequential: {ts:.2f} s")
+    cpu = None
+    if small and not args.no_cpu:
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        log(f"oracle on {len(small)} graphs with n <= {args.batch_oracle_max_n}, {threads} at once ...")
+        to = oracle_pool(text, [gs[k] for k in small], threads)
+        cpu = {"value": len(small) / to, "unit": "solves/s", "cores": threads, "kind": "oracle",
+               "sample": f"the {len(small)} graphs of the batch with n <= {args.batch_oracle_max_n}, one "
+                         f"oracle process per graph, {threads} at once on the host cores "
+                         f"({host_cpu()}): {to:.1f} s",
+               "gpu_batched_same_graphs_solves_per_s": len(small) / tb_small}
     print(json.dumps({
         "metric": "batched solves/s", "value": len(gs) / tb, "unit": "solves/s",
         "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
@@ -397,8 +443,8 @@ def batch(args):
         "pairs": int(sum(batch_pairs)), "derived_pairs_per_s": sum(batch_pairs) / tb,
         "same_pair_counts_as_sequential": batch_pairs == seq_pairs,
         "autotuned": tuned,
-        "config": {"workload": f"alias_batch: {len(gs)} alias graphs, n log-uniform "
-                               f"[1000, {args.batch_max_n}], stored degree U[2,3], seeds 3000+g"}}),
+        "cpu_baseline": cpu,
+        "config": {"workload": wl}}),
         flush=True)
 
 
@@ -605,6 +651,9 @@ def main():
                          "(reference for the HBM byte counters)")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-max-n", type=int, default=40000)
+    ap.add_argument("--batch-grammar", default="alias", choices=["alias", "dyck"])
+    ap.add_argument("--batch-oracle-max-n", type=int, default=8000,
+                    help="graphs the oracle solves beside the batch (all host cores)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "

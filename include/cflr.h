@@ -292,6 +292,10 @@ cflr_status cflr_solve_noalloc(cflr_ctx *ctx, const cflr_grammar *g, uint32_t n_
  * device memory and their (key tile, partner) slots -- key tiles of 256
  * vertices x n partners per matrix -- sum to at most the larger of
  * 2^28 and the largest single graph's; the others wait for retirements.
+ * If the running graphs derive more new pairs in one round than the
+ * new-pair buffer may hold (2^32; the dense engine's sort positions are 32
+ * bits), they start again from scratch with at most half as many running
+ * at once, and the context keeps that bound for its later batches.
  * outs: caller array of count pointers, each set to a result (or NULL on
  * failure).  Results are identical to cflr_solve of each graph alone.
  * Batches run on dense storage without witnesses (opts->witness and

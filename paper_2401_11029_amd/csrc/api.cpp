@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -410,17 +411,16 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
         hip_check(hipEventCreate(&e0), "event");
         hip_check(hipEventCreate(&e1), "event");
         hip_check(hipEventRecord(e0, ctx->stream), "event");
-        Run run(ctx, o, buckets, count);
+        auto run = std::make_unique<Run>(ctx, o, buckets, count);
         // device memory for matrices: 70 % of what is free, minus the
         // new-pair buffer (44 bytes a pair: the append, two sort stages and
         // two sorted orders; grown on overflow) and headroom for it to
         // double once
         const uint64_t avail = (uint64_t)((double)(free_b + ctx->pool->held()) * 0.7);
-        const uint64_t delta_bytes = 3 * 44ull * run.delta_capacity();
+        const uint64_t delta_bytes = 3 * 44ull * run->delta_capacity();
         const uint64_t budget = avail > delta_bytes ? avail - delta_bytes : avail / 4;
         std::vector<std::shared_ptr<Instance>> all(count);
         uint64_t in_use = 0;
-        uint32_t next = 0;
         cflr_status status = CFLR_OK;
         std::vector<uint64_t> fp(count), wt(count);
         uint64_t max_wt = 0;
@@ -434,46 +434,95 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
         uint64_t wt_in = 0;
         const bool progress = std::getenv("CFLR_PROGRESS") != nullptr;
         uint32_t finished = 0;
+        // graphs waiting for admission, in order; a round whose new pairs
+        // pass the buffer's 2^32 limit with several graphs running sends the
+        // running ones back here (from scratch) and halves how many may run
+        std::deque<uint32_t> waiting;
+        for (uint32_t k = 0; k < count; k++) waiting.push_back(k);
+        std::vector<uint8_t> retired(count, 0);
+        // a context that had to restart a batch's graphs starts later batches
+        // at the concurrency that fitted
+        uint32_t max_running = ctx->batch_running_cap ? std::min(count, ctx->batch_running_cap) : count;
+        const auto t_batch = std::chrono::steady_clock::now();
+        double product_ms = 0;
+        uint64_t launches = 0, algo = 0, reruns = 0;
+        auto fold_run_stats = [&]() {
+            product_ms += run->product_ms();
+            launches += run->product_launches();
+            algo += run->algo_bytes();
+            reruns += run->reruns();
+        };
         while (true) {
             // admit
-            while (next < count) {
-                uint64_t need = fp[next];
-                if (run.size() && (in_use + need > budget || wt_in + wt[next] > wt_cap)) break;
-                auto inst = make_instance(ctx, grammars[next]->low, graphs[next]);
+            while (!waiting.empty() && run->size() < max_running) {
+                const uint32_t k = waiting.front();
+                const uint64_t need = fp[k];
+                if (run->size() && (in_use + need > budget || wt_in + wt[k] > wt_cap)) break;
+                auto inst = make_instance(ctx, grammars[k]->low, graphs[k]);
                 try {
-                    run.add(inst);
+                    run->add(inst);
                 } catch (const Error &e) {
-                    if (!run.size()) throw;
+                    if (!run->size()) throw;
                     break;  // bucket space full: wait for a retirement
                 }
-                all[next] = inst;
+                all[k] = inst;
                 in_use += need;
-                wt_in += wt[next];
-                next++;
+                wt_in += wt[k];
+                waiting.pop_front();
             }
-            if (!run.size()) break;
-            run.rounds(o.rounds_per_sync ? o.rounds_per_sync
-                                         : (ctx->rounds_per_sync_tuned ? ctx->rounds_per_sync_tuned : 4));
+            if (!run->size()) break;
+            try {
+                run->rounds(o.rounds_per_sync ? o.rounds_per_sync
+                                              : (ctx->rounds_per_sync_tuned ? ctx->rounds_per_sync_tuned : 4));
+            } catch (const Error &e) {
+                if (e.status != CFLR_ENOMEM || run->size() < 2) throw;
+                // restart the running graphs in a new run with at most half as many at once
+                std::vector<uint32_t> back;
+                for (uint32_t k = 0; k < count; k++)
+                    if (all[k] && !retired[k]) back.push_back(k);
+                if (progress)
+                    std::fprintf(stderr,
+                                 "[cflr] batch: %s with %zu graphs running after %.2f s; they start again, %zu at most\n",
+                                 e.what(), back.size(),
+                                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t_batch).count(),
+                                 std::max<size_t>(1, back.size() / 2));
+                max_running = std::max<uint32_t>(1, (uint32_t)back.size() / 2);
+                ctx->batch_running_cap = max_running;
+                fold_run_stats();
+                run.reset();
+                for (auto it = back.rbegin(); it != back.rend(); ++it) {
+                    all[*it].reset();
+                    waiting.push_front(*it);
+                }
+                in_use = wt_in = 0;
+                cflr_opts ro = o;
+                if (!ro.delta_capacity) ro.delta_capacity = 1ull << 28;  // not the limit the last run reached
+                run = std::make_unique<Run>(ctx, ro, buckets, count);
+                continue;
+            }
             // retire finished instances
             std::vector<std::shared_ptr<Instance>> done;
-            for (auto &ip : run.instances())
+            for (auto &ip : run->instances())
                 if (ip->done || (o.max_rounds && ip->rounds >= o.max_rounds)) done.push_back(ip);
             for (auto &ip : done) {
                 if (!ip->done) {
                     ip->status = CFLR_ETIMEOUT;
                     status = CFLR_ETIMEOUT;
                 }
-                run.remove(ip.get());
+                run->remove(ip.get());
                 in_use -= ip->footprint;
                 wt_in -= instance_pair_slots(ip->low, ip->n);
                 ip->stats.rounds = ip->rounds;
                 compact_instance(*ip);
+                for (uint32_t k = 0; k < count; k++)
+                    if (all[k].get() == ip.get()) retired[k] = 1;
             }
             finished += (uint32_t)done.size();
             if (progress && !done.empty())
                 std::fprintf(stderr, "[cflr] batch: %u of %u graphs done, %zu running\n", finished, count,
-                             run.size());
+                             run->size());
         }
+        fold_run_stats();
         hip_check(hipEventRecord(e1, ctx->stream), "event");
         hip_check(hipEventSynchronize(e1), "event");
         float ms = 0;
@@ -483,10 +532,10 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
         for (uint32_t k = 0; k < count; k++) {
             Instance &in = *all[k];
             in.stats.fixpoint_ms = ms;  // the whole batch shares one clock
-            in.stats.product_ms = run.product_ms();
-            in.stats.product_launches = run.product_launches();
-            in.stats.algo_bytes = run.algo_bytes();
-            in.stats.reruns = run.reruns();
+            in.stats.product_ms = product_ms;
+            in.stats.product_launches = launches;
+            in.stats.algo_bytes = algo;
+            in.stats.reruns = reruns;
             instance_counts(in);
             outs[k] = new cflr_result{all[k]};
         }

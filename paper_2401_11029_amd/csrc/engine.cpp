@@ -259,6 +259,8 @@ Run::Run(cflr_ctx *ctx, const cflr_opts &opts, uint64_t bucket_capacity, uint32_
     hip_check(hipHostMalloc((void **)&h_stats_, (uint64_t)max_inst_ * sizeof(SlotStats), 0), "hipHostMalloc");
     hip_check(hipEventCreate(&ev0_), "event");
     hip_check(hipEventCreate(&ev1_), "event");
+    if (const char *l = std::getenv("CFLR_DENSE_PAIR_LIMIT"))
+        ap_limit_ = std::max<uint64_t>(1024, std::min<uint64_t>(ap_limit_, std::strtoull(l, nullptr, 10)));
     uint64_t cap = opts_.delta_capacity ? opts_.delta_capacity : ctx->delta_capacity_hint;
     // first guess: an eighth of a pair per (key tile, partner) of the run
     if (!cap) cap = std::max<uint64_t>(1ull << 22, std::min<uint64_t>(bucket_cap_ * (kSegCols / 8), 1ull << 28));
@@ -281,7 +283,7 @@ Run::~Run() {
 
 void Run::ensure_capacity(uint64_t pairs, bool keep) {
     if (pairs <= ap_cap_) return;
-    const uint64_t limit = 0xFFFFFFF0ull;
+    const uint64_t limit = ap_limit_;
     if (ap_cap_ >= limit) throw Error(CFLR_ENOMEM, "new-pair buffer at its 2^32 limit");
     pairs = std::min(pairs, limit);
     DevPool *pool = ctx_->pool.get();

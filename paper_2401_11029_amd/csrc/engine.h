@@ -80,6 +80,8 @@ struct cflr_ctx {
     uint64_t delta_capacity_hint = 0;  // grown new-pair capacity, reused by later solves
     uint32_t grid_waves_tuned = 0;     // autotuned product grid (0 = not yet)
     uint32_t rounds_per_sync_tuned = 0;  // autotuned rounds per graph replay (batches)
+    uint32_t batch_running_cap = 0;      // graphs a batch ran at most when its new pairs last fit the
+                                         // buffer's limit after a restart (0: no restart yet)
     // sizes the sparse engine grew to (new-pair buffer, list pool, hash
     // slots), the starting point of later sparse solves on this context
     uint64_t sparse_delta_hint = 0, sparse_pool_hint = 0, sparse_slots_hint = 0;
@@ -268,6 +270,10 @@ class Run {
     DevBuf d_rcnt_, d_ccnt_, d_bsum_;
     DevBuf d_ap_key_, d_ap_i_, d_ap_j_, d_rs_, d_cs_, d_rs_stage_, d_cs_stage_;
     uint64_t ap_cap_ = 0;
+    // most pairs the new-pair buffer may hold: 32-bit sort positions; the
+    // environment variable CFLR_DENSE_PAIR_LIMIT lowers it (tests of what
+    // callers do at the limit)
+    uint64_t ap_limit_ = 0xFFFFFFF0ull;
     DevBuf d_counters_;  // [0] ap_count, [1] items taken (row parts), [2] algo_bytes, [3] halt (u32),
                          // [4] items taken (column parts)
     DevBuf d_inst_new_, d_inst_over_, d_active_, d_slot_stats_;

@@ -271,6 +271,13 @@ def alias_batch(count=256, n_lo=1000, n_hi=40000, seed=3):
     return out
 
 
+def dyck_batch(count=256, n_lo=1000, n_hi=40000, seed=3):
+    """The Dyck-1 reading of the batch: the same sizes as alias_batch, each
+    graph a directed G(n, m) with labels a / b (p = 1/2) and m = n * degree
+    stored edges (no reversed edges: Dyck-1 has no bar labels)."""
+    return [erdos_renyi(n, int(round(n * deg)), seed=s) for n, deg, s in batch_specs(count, n_lo, n_hi, seed=seed)]
+
+
 def poisson_trace(count, rate, seed=4):
     """Arrival times (seconds) of a Poisson process with the given rate."""
     rng = np.random.Generator(np.random.PCG64(seed))
