@@ -372,18 +372,28 @@ void cflr_result_free(cflr_result *r);
  * a small request does not wait for a large request's round for each of its
  * own.  Each round's product is two launches (row parts, then column parts)
  * over the class's running requests.  Requests may use different grammars.  Results are identical to
- * cflr_solve of the same input.  A request whose footprint alone exceeds the
- * budget fails with ENOMEM.  Besides the budget the server holds, per class,
+ * cflr_solve of the same input.  A request whose dense footprint exceeds
+ * the budget goes to the sparse lane instead: a second thread
+ * solves such requests one at a time on the sparse engine (cflr_stats.storage
+ * = CFLR_STORAGE_SPARSE; mirror plans apply), on a stream of its own, beside
+ * the two classes; its memory grows with its pairs and is not counted in
+ * the budget.  When a class's running requests derive more new pairs in one
+ * round than the dense engine's buffer may hold (2^32), or the buffer's
+ * growth finds no memory, they start again from scratch at the front of
+ * the queue and the class admits at most half as many from then on; a
+ * request whose dense memory cannot be had while nothing else holds any
+ * goes to the sparse lane.  Besides the budget the server holds, per class,
  * the sort's bucket counters (8 bytes per bucket, budget / 65536 buckets, at
  * least 2^20 and at most 2^26) and a new-pair buffer of 44 bytes per pair:
  * the large class's starts at the size earlier solves on ctx grew it to
- * (else 2^26 pairs), at most budget / 44 pairs (at least 2^20), the small
+ * (else 2^26 pairs), at most a quarter of the budget (44 bytes a pair; at
+ * least 2^20 pairs), the small
  * class's at 2^22 pairs at most, unless opts->delta_capacity says
  * otherwise (each grows when a round overflows it).
  * It also admits a request only while the running requests' (key tile,
  * partner) slots -- key tiles of 256 vertices x n partners per matrix --
  * stay within hbm_budget_bytes / 16 (between 2^20 and 2^29).
- * The server runs its rounds on a stream of its own on ctx's device, so the
+ * The server runs its rounds on streams of its own on ctx's device, so the
  * caller's thread may read results and free handles (on ctx's stream) while
  * it runs; do not start other solves on ctx while the server lives.
  * Errors (every server call sets cflr_last_error): EINVAL, ENOMEM, EDEVICE,

@@ -536,6 +536,7 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
             in.stats.product_launches = launches;
             in.stats.algo_bytes = algo;
             in.stats.reruns = reruns;
+            in.stats.storage = CFLR_STORAGE_DENSE;
             instance_counts(in);
             outs[k] = new cflr_result{all[k]};
         }

@@ -189,8 +189,10 @@ uint64_t instance_pair_slots(const Lowered &low, uint32_t n);
 std::shared_ptr<Instance> make_instance(cflr_ctx *ctx, const Lowered &low, const cflr_graph *g, bool dense = true);
 
 // The sparse engine (sparse.cpp): solves one instance made with dense =
-// false; *timed_out when opts.max_rounds stopped it first.
-void sparse_solve(cflr_ctx *ctx, const cflr_opts &opts, Instance &inst, bool *timed_out);
+// false on `stream` (null: the context's); *timed_out when opts.max_rounds
+// stopped it first.
+void sparse_solve(cflr_ctx *ctx, const cflr_opts &opts, Instance &inst, bool *timed_out,
+                  hipStream_t stream = nullptr);
 // Binary productions a mirror plan of the sparse engine leaves without a
 // product of their own (one of each mirror pair); 0 when the grammar has no
 // mirror (cflr_opts.mirror).

@@ -881,7 +881,7 @@ uint32_t mirror_skipped(const Lowered &low) {
 }
 
 
-void sparse_solve(cflr_ctx *ctx, const cflr_opts &o, Instance &inst, bool *timed_out) {
+void sparse_solve(cflr_ctx *ctx, const cflr_opts &o, Instance &inst, bool *timed_out, hipStream_t stream) {
     Alloc A(ctx->pool.get());
     SeedInput in;
     in.m = inst.graph->m;
@@ -894,7 +894,7 @@ void sparse_solve(cflr_ctx *ctx, const cflr_opts &o, Instance &inst, bool *timed
     in.n_eps = inst.n_eps;
     in.max_seeds = inst.max_seeds;
     CoreOut res;
-    solve_core(ctx, ctx->stream, o, inst.low, inst.n, in, A, res);
+    solve_core(ctx, stream ? stream : ctx->stream, o, inst.low, inst.n, in, A, res);
     *timed_out = res.timed_out;
     auto store = std::make_shared<SparseStore>();
     store->hold = CtxRef(ctx);

@@ -286,6 +286,7 @@ def test_batch_matches_single_solves(ctx):
     graph_objs = [m.Graph.from_workload(ctx, g) for _, g in cases]
     res = m.solve_batch(ctx, [grams[t] for t, _ in cases], graph_objs)
     for (text, g), r in zip(cases, res):
+        assert r.stats()["storage"] == 1
         assert_matches_oracle(r, text, g, "batch")
 
 
@@ -350,15 +351,52 @@ def test_server_results_equal_alone_and_in_the_mix(ctx):
     assert admits[1] < finishes[0]
 
 
-def test_server_rejects_oversized_request(ctx):
+def test_server_sends_large_requests_to_the_sparse_lane(ctx):
+    # a 16 MiB budget: requests whose dense matrices would not fit it are
+    # solved on the sparse engine by the server's second lane, beside the
+    # dense runs
     m = cflr()
-    srv = m.Server(ctx, hbm_budget_bytes=1 << 20, max_slots=2)
-    g = m.Graph.from_workload(ctx, graphs.alias_graph(4000, seed=3))
-    t = srv.submit(m.Grammar(G.ALIAS_FIG5A_WCNF), g)
-    with pytest.raises(m.CflrError) as e:
-        srv.wait(t, timeout_s=60)
-    assert e.value.status == 3
+    cases = [(G.ALIAS_FIG5A_WCNF, graphs.alias_graph(4000, seed=3)),
+             (G.pointsto_fig4b(64), graphs.pointsto_graph(3000, seed=4)),
+             (G.DYCK1, graphs.erdos_renyi(300, 900, seed=5)),
+             (G.pointsto_fig4b(8), graphs.pointsto_graph(1500, fields=8, seed=6))]
+    grams = {t: m.Grammar(t) for t, _ in cases}
+    objs = [m.Graph.from_workload(ctx, g) for _, g in cases]
+    srv = m.Server(ctx, hbm_budget_bytes=16 << 20, max_slots=2)
+    tickets = [srv.submit(grams[t], o) for (t, _), o in zip(cases, objs)]
+    res = [srv.wait(t, timeout_s=300) for t in tickets]
     srv.close()
+    assert [r.stats()["storage"] for r in res] == [2, 2, 1, 2]
+    assert res[1].stats()["mirror"] == 1  # Fig. 4b on its graph: the mirror plan
+    for (text, g), r in zip(cases, res):
+        assert_matches_oracle(r, text, g, "sparse lane")
+        r.close()
+
+
+def test_server_restarts_requests_at_the_pair_limit(ctx, monkeypatch, capfd):
+    # more new pairs in one round than the dense buffer may hold (the limit
+    # lowered through CFLR_DENSE_PAIR_LIMIT): the running requests start
+    # again with half as many at once, and every result is the oracle's
+    m = cflr()
+    cases = [graphs.erdos_renyi(600, 1500, seed=80 + k) for k in range(8)]
+    gr = m.Grammar(G.DYCK1)
+    objs = [m.Graph.from_workload(ctx, g) for g in cases]
+    need = 0
+    for o in objs:
+        r = m.solve(ctx, gr, o, storage=1)
+        need = max(need, r.stats()["max_delta"] + 2 * 600 * 3)
+        r.close()
+    monkeypatch.setenv("CFLR_DENSE_PAIR_LIMIT", str(4 * need))
+    monkeypatch.setenv("CFLR_PROGRESS", "1")
+    srv = m.Server(ctx, hbm_budget_bytes=1 << 30, max_slots=8, rounds_per_sync=1)
+    tickets = [srv.submit(gr, o) for o in objs]
+    res = [srv.wait(t, timeout_s=300) for t in tickets]
+    srv.close()
+    err = capfd.readouterr().err
+    assert "start again" in err, err[-2000:]
+    for g, r in zip(cases, res):
+        assert_matches_oracle(r, G.DYCK1, g, "served at the limit")
+        r.close()
 
 
 def test_library_loaded_before_torch_still_leaves_torch_a_device():
