@@ -165,10 +165,13 @@ bool find_mirror(const Lowered &low, std::vector<uint32_t> *mat, std::vector<uin
 // Layouts, use tables and observers of a lowered grammar on n vertices.
 // Row layouts: matrices in a b slot and the text's non-terminals (results
 // are read out by rows); column layouts: matrices in an a slot.  Under a
-// mirror plan (rule_mirror non-empty) only one production of each mirror
-// pair -- the one with the lower index -- gets uses, and only its operands'
-// layouts are kept.
-Plan make_plan(const Lowered &low, uint32_t n, const std::vector<uint32_t> &rule_mirror) {
+// mirror plan (rule_mirror and mat_mirror non-empty) only one production of
+// each mirror pair -- the one with the lower index -- gets uses, and only
+// its operands' layouts are kept; x's column layout is then the row layout
+// of its mirror s(x) (column j of x lists the i with x(i, j), which row j of
+// s(x) lists), filled by s(x)'s pairs only.
+Plan make_plan(const Lowered &low, uint32_t n, const std::vector<uint32_t> &rule_mirror,
+               const std::vector<uint32_t> &mat_mirror) {
     Plan P;
     const uint32_t M = low.nmat(), U = (uint32_t)low.user_names.size();
     const uint32_t B = (uint32_t)low.binary.size();
@@ -181,13 +184,25 @@ Plan make_plan(const Lowered &low, uint32_t n, const std::vector<uint32_t> &rule
         }
     }
     sp::MatInfo none{};
-    none.row_layout = none.col_layout = kNone;
+    none.row_layout = none.col_layout = none.app_row = none.app_col = kNone;
     none.rank0 = none.rank1 = kNone;
     P.mats.assign(M, none);
+    const bool alias = !mat_mirror.empty();
+    std::vector<uint8_t> need_row(M, 0);
+    for (uint32_t x = 0; x < M; x++) {
+        if (slot_b[x] || x < U) need_row[x] = 1;
+        if (alias && slot_a[x] && mat_mirror[x] != x) need_row[mat_mirror[x]] = 1;
+    }
     for (uint32_t x = 0; x < M; x++)
-        if (slot_b[x] || x < U) P.mats[x].row_layout = P.nlayouts++;
-    for (uint32_t x = 0; x < M; x++)
-        if (slot_a[x]) P.mats[x].col_layout = P.nlayouts++;
+        if (need_row[x]) P.mats[x].row_layout = P.mats[x].app_row = P.nlayouts++;
+    for (uint32_t x = 0; x < M; x++) {
+        if (!slot_a[x]) continue;
+        if (alias && mat_mirror[x] != x) {
+            P.mats[x].col_layout = P.mats[mat_mirror[x]].row_layout;  // a view: x appends nothing to it
+        } else {
+            P.mats[x].col_layout = P.mats[x].app_col = P.nlayouts++;
+        }
+    }
     std::vector<std::vector<sp::Use>> u0(M), u1(M);
     for (uint32_t q = 0; q < B; q++) {
         if (!keep[q]) continue;
@@ -395,7 +410,8 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
     std::vector<uint32_t> mirror_mat, mirror_rule;
     const bool mirrored = o.mirror != CFLR_MIRROR_OFF && find_mirror(low, &mirror_mat, &mirror_rule);
     if (!mirrored) mirror_rule.clear();
-    res.plan = make_plan(low, n, mirror_rule);
+    if (!mirrored) mirror_mat.clear();
+    res.plan = make_plan(low, n, mirror_rule, mirror_mat);
     res.mirror = mirrored;
     const Plan &P = res.plan;
     Mem d_mirror, d_mirror_rule;

@@ -93,6 +93,10 @@ struct Obs {
 
 struct MatInfo {
     uint32_t row_layout, col_layout;  // kNone when absent
+    // the layouts the matrix's own pairs are appended to (kNone: none; a
+    // mirror plan's column layout is the mirror's row layout, which only
+    // the mirror's pairs fill)
+    uint32_t app_row, app_col;
     uint32_t use0, nuse0;             // part 0 uses (x in an a slot) in the use table
     uint32_t use1, nuse1;             // part 1 uses (x in a b slot)
     uint32_t w0, w1;                  // mask words per vertex for each part

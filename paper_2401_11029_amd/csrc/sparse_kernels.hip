@@ -396,8 +396,8 @@ __global__ __launch_bounds__(256) void count_kernel(State S, PairBuf in, KeySort
             if (key != kHoleKey) {
                 const MatInfo mi = S.mats[key];
                 const uint32_t i = in.i[x], j = in.j[x];
-                if (mi.row_layout != kNone) row = (uint64_t)mi.row_layout * S.n + i;
-                if (mi.col_layout != kNone) col = (uint64_t)mi.col_layout * S.n + j;
+                if (mi.app_row != kNone) row = (uint64_t)mi.app_row * S.n + i;
+                if (mi.app_col != kNone) col = (uint64_t)mi.app_col * S.n + j;
                 if (keys && mi.rank0 != kNone) b0 = (uint64_t)mi.rank0 * S.n + i;
                 if (keys && mi.rank1 != kNone) b1 = K.nb0 + (uint64_t)mi.rank1 * S.n + j;
             }
@@ -557,8 +557,8 @@ __global__ __launch_bounds__(256) void scatter_kernel(State S, PairBuf in, KeySo
                 const MatInfo mi = S.mats[key];
                 i = in.i[x];
                 j = in.j[x];
-                if (mi.row_layout != kNone) row = (uint64_t)mi.row_layout * S.n + i;
-                if (mi.col_layout != kNone) col = (uint64_t)mi.col_layout * S.n + j;
+                if (mi.app_row != kNone) row = (uint64_t)mi.app_row * S.n + i;
+                if (mi.app_col != kNone) col = (uint64_t)mi.app_col * S.n + j;
                 if (keys && mi.rank0 != kNone) b0 = (uint64_t)mi.rank0 * S.n + i;
                 if (keys && mi.rank1 != kNone) b1 = K.nb0 + (uint64_t)mi.rank1 * S.n + j;
             }
