@@ -135,7 +135,10 @@ struct SparseStore {
     cflr_ctx *ctx = nullptr;
     uint32_t n = 0, nlayouts = 0;
     DevBuf dir, pool;
-    std::vector<uint32_t> row_layout;  // per matrix; every user non-terminal has one
+    std::vector<uint32_t> row_layout;  // per matrix (kNone: none)
+    // per matrix: ~0u, or the mirror whose rows hold its pairs transposed
+    // (a user non-terminal without rows of its own is read out from them)
+    std::vector<uint32_t> readout_mirror;
     // witnesses (single-path semantics), when the solve recorded them: the
     // pair set, a witness per slot, and the tables that name a witness in
     // the grammar text's symbols (per binary production its two operands;

@@ -45,6 +45,10 @@ struct Plan {
     uint32_t nlayouts = 0;
     uint64_t mask_words = 0;
     uint32_t nrank0 = 0, nrank1 = 0;  // matrices with part 0 (part 1) uses
+    // per matrix: kNone, or the mirror whose row layout holds its pairs
+    // transposed (a text's non-terminal that no kept production reads by
+    // rows; its readout transposes the mirror's rows)
+    std::vector<uint32_t> readout_mirror;
 };
 
 // The mirror of a grammar, when it has one.  Graphs of the paper's
@@ -169,9 +173,11 @@ bool find_mirror(const Lowered &low, std::vector<uint32_t> *mat, std::vector<uin
 // each mirror pair -- the one with the lower index -- gets uses, and only
 // its operands' layouts are kept; x's column layout is then the row layout
 // of its mirror s(x) (column j of x lists the i with x(i, j), which row j of
-// s(x) lists), filled by s(x)'s pairs only.
+// s(x) lists), filled by s(x)'s pairs only.  With drop_readout, a text's
+// non-terminal whose rows only the readout needs keeps none when its mirror
+// has row lists: its pairs are read out as the mirror's, transposed.
 Plan make_plan(const Lowered &low, uint32_t n, const std::vector<uint32_t> &rule_mirror,
-               const std::vector<uint32_t> &mat_mirror) {
+               const std::vector<uint32_t> &mat_mirror, bool drop_readout) {
     Plan P;
     const uint32_t M = low.nmat(), U = (uint32_t)low.user_names.size();
     const uint32_t B = (uint32_t)low.binary.size();
@@ -188,10 +194,23 @@ Plan make_plan(const Lowered &low, uint32_t n, const std::vector<uint32_t> &rule
     none.rank0 = none.rank1 = kNone;
     P.mats.assign(M, none);
     const bool alias = !mat_mirror.empty();
-    std::vector<uint8_t> need_row(M, 0);
+    P.readout_mirror.assign(M, kNone);
+    std::vector<uint8_t> need_row(M, 0), head(M, 0);
+    for (uint32_t q = 0; q < B; q++)
+        if (keep[q]) head[low.binary[q].c] = 1;
     for (uint32_t x = 0; x < M; x++) {
-        if (slot_b[x] || x < U) need_row[x] = 1;
+        if (slot_b[x] || (x < U && head[x])) need_row[x] = 1;  // read as a partner, or the head's own rows
         if (alias && slot_a[x] && mat_mirror[x] != x) need_row[mat_mirror[x]] = 1;
+    }
+    for (uint32_t x = 0; x < U; x++) {
+        if (need_row[x]) continue;
+        // rows only for the readout
+        const uint32_t y = alias ? mat_mirror[x] : kNone;
+        if (drop_readout && y != kNone && y != x && need_row[y]) {  // the mirror keeps rows: read x from them
+            P.readout_mirror[x] = y;
+            continue;
+        }
+        need_row[x] = 1;
     }
     for (uint32_t x = 0; x < M; x++)
         if (need_row[x]) P.mats[x].row_layout = P.mats[x].app_row = P.nlayouts++;
@@ -411,7 +430,7 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
     const bool mirrored = o.mirror != CFLR_MIRROR_OFF && find_mirror(low, &mirror_mat, &mirror_rule);
     if (!mirrored) mirror_rule.clear();
     if (!mirrored) mirror_mat.clear();
-    res.plan = make_plan(low, n, mirror_rule, mirror_mat);
+    res.plan = make_plan(low, n, mirror_rule, mirror_mat, !fixed);
     res.mirror = mirrored;
     const Plan &P = res.plan;
     Mem d_mirror, d_mirror_rule;
@@ -919,6 +938,7 @@ void sparse_solve(cflr_ctx *ctx, const cflr_opts &o, Instance &inst, bool *timed
     store->nlayouts = res.plan.nlayouts;
     store->row_layout.resize(inst.low.nmat());
     for (uint32_t x = 0; x < inst.low.nmat(); x++) store->row_layout[x] = res.plan.mats[x].row_layout;
+    store->readout_mirror = res.plan.readout_mirror;
     store->dir = std::move(res.dir.buf);
     store->pool = std::move(res.pool.buf);
     if (o.witness) {
@@ -971,10 +991,12 @@ void sparse_counts(Instance &inst) {
     const uint32_t U = (uint32_t)inst.low.user_names.size();
     DevBuf tot(ctx->pool.get(), 8ull * std::max<uint32_t>(1, U));
     hip_check(hipMemsetAsync(tot.ptr, 0, 8ull * std::max<uint32_t>(1, U), s), "memset");
-    for (uint32_t x = 0; x < U; x++)
-        hip_check(sp::launch_layout_count(st.dir.as<sp::Dir>() + (uint64_t)st.row_layout[x] * st.n, st.n,
+    for (uint32_t x = 0; x < U; x++) {
+        const uint32_t from = st.readout_mirror[x] == kNone ? x : st.readout_mirror[x];  // equal counts
+        hip_check(sp::launch_layout_count(st.dir.as<sp::Dir>() + (uint64_t)st.row_layout[from] * st.n, st.n,
                                           tot.as<unsigned long long>() + x, s),
                   "count");
+    }
     std::vector<unsigned long long> h(std::max<uint32_t>(1, U));
     hip_check(hipMemcpyAsync(h.data(), tot.ptr, 8ull * std::max<uint32_t>(1, U), hipMemcpyDeviceToHost, s), "D2H");
     hip_check(hipStreamSynchronize(s), "sync");
@@ -996,16 +1018,46 @@ void sparse_copy(Instance &inst, uint32_t nt, uint32_t *src, uint32_t *dst, uint
     const uint64_t nw = ((uint64_t)n + 63) / 64;
     DevBuf off(pool, (uint64_t)n * 8), bm(pool, std::max<uint64_t>(1, (uint64_t)sort_grid * nw) * 8);
     hip_check(hipMemsetAsync(bm.ptr, 0, (uint64_t)sort_grid * nw * 8, s), "memset");
-    const sp::Dir *dir = st.dir.as<sp::Dir>() + (uint64_t)st.row_layout[nt] * n;
+    const sp::Dir *dir = nullptr;
+    const uint32_t *lists = st.pool.as<uint32_t>();
+    DevBuf tdir, tpool;
+    if (st.readout_mirror[nt] == kNone) {
+        dir = st.dir.as<sp::Dir>() + (uint64_t)st.row_layout[nt] * n;
+    } else {
+        // nt's pairs are its mirror's rows transposed: count the entries per
+        // column, lay the columns out as lists, fill them, then read those
+        // lists as rows
+        const sp::Dir *mdir = st.dir.as<sp::Dir>() + (uint64_t)st.row_layout[st.readout_mirror[nt]] * n;
+        DevBuf cnt(pool, (uint64_t)n * 4), cur(pool, (uint64_t)n * 4);
+        hip_check(hipMemsetAsync(cnt.ptr, 0, (uint64_t)n * 4, s), "memset");
+        hip_check(hipMemsetAsync(cur.ptr, 0, (uint64_t)n * 4, s), "memset");
+        hip_check(sp::launch_transpose_count(mdir, st.pool.as<uint32_t>(), n, cnt.as<uint32_t>(), s), "readout");
+        std::vector<uint32_t> hc(n);
+        copy_sync(hc.data(), cnt.ptr, (uint64_t)n * 4, hipMemcpyDeviceToHost, s);
+        std::vector<sp::Dir> td(n);
+        uint64_t at = 0;
+        for (uint32_t j = 0; j < n; j++) {
+            td[j] = sp::Dir{at, hc[j], hc[j]};
+            at += hc[j];
+        }
+        if (at != count) throw Error(CFLR_EDEVICE, "internal: transposed readout count differs");
+        tdir = DevBuf(pool, (uint64_t)n * sizeof(sp::Dir));
+        tpool = DevBuf(pool, std::max<uint64_t>(1, at) * 4);
+        copy_sync(tdir.ptr, td.data(), (uint64_t)n * sizeof(sp::Dir), hipMemcpyHostToDevice, s);
+        hip_check(sp::launch_transpose_scatter(mdir, st.pool.as<uint32_t>(), n, tdir.as<sp::Dir>(),
+                                               cur.as<uint32_t>(), tpool.as<uint32_t>(), s),
+                  "readout");
+        dir = tdir.as<sp::Dir>();
+        lists = tpool.as<uint32_t>();
+    }
     if (on_device) {
-        hip_check(sp::launch_layout_write(dir, st.pool.as<uint32_t>(), n, off.as<uint64_t>(), bm.as<uint64_t>(),
-                                          sort_grid, src, dst, s),
+        hip_check(sp::launch_layout_write(dir, lists, n, off.as<uint64_t>(), bm.as<uint64_t>(), sort_grid, src, dst, s),
                   "readout");
         hip_check(hipStreamSynchronize(s), "sync");
         return;
     }
     DevBuf dsrc(pool, count * 4), ddst(pool, count * 4);
-    hip_check(sp::launch_layout_write(dir, st.pool.as<uint32_t>(), n, off.as<uint64_t>(), bm.as<uint64_t>(), sort_grid,
+    hip_check(sp::launch_layout_write(dir, lists, n, off.as<uint64_t>(), bm.as<uint64_t>(), sort_grid,
                                       dsrc.as<uint32_t>(), ddst.as<uint32_t>(), s),
               "readout");
     hip_check(hipMemcpyAsync(src, dsrc.ptr, count * 4, hipMemcpyDeviceToHost, s), "D2H");

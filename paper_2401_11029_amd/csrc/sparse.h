@@ -269,6 +269,14 @@ hipError_t launch_fill_u64(unsigned long long *a, uint64_t n, unsigned long long
 hipError_t launch_check_edges(const uint32_t *src, const uint32_t *dst, const uint32_t *lab, uint64_t m, uint32_t n,
                               uint32_t n_labels, unsigned long long *bad, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *a, uint64_t n, uint32_t v, hipStream_t s);
+// Transposed readout of a row layout (the pairs of a matrix kept only as
+// its mirror's rows): cnt[j] (zeroed by the caller) counts the entries j
+// over all n lists; then every entry j of list i is written as i into
+// tpool at tdir[j].off + (a cursor[j] slot; cursor zeroed by the caller).
+// tdir (built by the host from cnt) is then a row layout of the transpose.
+hipError_t launch_transpose_count(const Dir *dir, const uint32_t *pool, uint32_t n, uint32_t *cnt, hipStream_t s);
+hipError_t launch_transpose_scatter(const Dir *dir, const uint32_t *pool, uint32_t n, const Dir *tdir,
+                                    uint32_t *cursor, uint32_t *tpool, hipStream_t s);
 // Readout of one row layout: per-row counts (sum into *total), then the
 // pairs sorted by (i, j) at the exclusive offsets of the counts.
 hipError_t launch_layout_count(const Dir *dir, uint32_t n, unsigned long long *total, hipStream_t s);

@@ -1353,6 +1353,30 @@ __global__ void fill_u32_kernel(uint32_t *a, uint64_t n, uint32_t v) {
 
 // ------------------------------------------------------------------ readout
 
+// Transposed readout (a matrix whose pairs are read from its mirror's row
+// layout): cnt[j] += 1 for every entry j of every list, a wave per list.
+__global__ __launch_bounds__(256) void transpose_count_kernel(const Dir *dir, const uint32_t *pool, uint32_t n,
+                                                             uint32_t *cnt) {
+    for (uint64_t i = wave_global_id(); i < n; i += waves_in_grid()) {
+        const Dir d = dir[i];
+        for (uint32_t e = lane_id(); e < d.len; e += 64) atomicAdd(&cnt[pool[d.off + e]], 1u);
+    }
+}
+
+// Every entry j of list i goes to tdir[j]'s block as i (unsorted within the
+// block; the row readout sorts it).
+__global__ __launch_bounds__(256) void transpose_scatter_kernel(const Dir *dir, const uint32_t *pool, uint32_t n,
+                                                               const Dir *tdir, uint32_t *cursor, uint32_t *tpool) {
+    for (uint64_t i = wave_global_id(); i < n; i += waves_in_grid()) {
+        const Dir d = dir[i];
+        for (uint32_t e = lane_id(); e < d.len; e += 64) {
+            const uint32_t j = pool[d.off + e];
+            const uint32_t at = atomicAdd(&cursor[j], 1u);
+            tpool[tdir[j].off + at] = (uint32_t)i;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void layout_count_kernel(const Dir *dir, uint32_t n, unsigned long long *total) {
     uint64_t s = 0;
     for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x)
@@ -1640,6 +1664,21 @@ hipError_t launch_fill_u32(uint32_t *a, uint64_t n, uint32_t v, hipStream_t s) {
 hipError_t launch_layout_count(const Dir *dir, uint32_t n, unsigned long long *total, hipStream_t s) {
     if (!n) return hipSuccess;
     layout_count_kernel<<<grid_for(n, 256, 4096), 256, 0, s>>>(dir, n, total);
+    SP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_transpose_count(const Dir *dir, const uint32_t *pool, uint32_t n, uint32_t *cnt, hipStream_t s) {
+    if (!n) return hipSuccess;
+    transpose_count_kernel<<<grid_for(n, 4, 8192), 256, 0, s>>>(dir, pool, n, cnt);
+    SP_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_transpose_scatter(const Dir *dir, const uint32_t *pool, uint32_t n, const Dir *tdir,
+                                    uint32_t *cursor, uint32_t *tpool, hipStream_t s) {
+    if (!n) return hipSuccess;
+    transpose_scatter_kernel<<<grid_for(n, 4, 8192), 256, 0, s>>>(dir, pool, n, tdir, cursor, tpool);
     SP_LAUNCH_CHECK();
     return hipSuccess;
 }
