@@ -49,6 +49,7 @@ struct Plan {
     // transposed (a text's non-terminal that no kept production reads by
     // rows; its readout transposes the mirror's rows)
     std::vector<uint32_t> readout_mirror;
+    std::vector<uint8_t> kept_head;  // per matrix: head of a production with uses
 };
 
 // The mirror of a grammar, when it has one.  Graphs of the paper's
@@ -198,6 +199,7 @@ Plan make_plan(const Lowered &low, uint32_t n, const std::vector<uint32_t> &rule
     std::vector<uint8_t> need_row(M, 0), head(M, 0);
     for (uint32_t q = 0; q < B; q++)
         if (keep[q]) head[low.binary[q].c] = 1;
+    P.kept_head = head;
     for (uint32_t x = 0; x < M; x++) {
         if (slot_b[x] || (x < U && head[x])) need_row[x] = 1;  // read as a partner, or the head's own rows
         if (alias && slot_a[x] && mat_mirror[x] != x) need_row[mat_mirror[x]] = 1;
@@ -396,6 +398,7 @@ struct MirrorRejected {};
 
 struct CoreOut {
     bool mirror = false;  // a mirror plan ran
+    uint64_t mirror_skipped = 0;  // new pairs whose mirror the pass left out (counted in new_pairs)
     Mem dir, pool;  // the adjacency lists, kept for readout
     Mem hash, wit;  // the pair set and its witnesses, kept when witnesses are recorded
     uint64_t hash_slots = 0;
@@ -433,10 +436,23 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
     res.plan = make_plan(low, n, mirror_rule, mirror_mat, !fixed);
     res.mirror = mirrored;
     const Plan &P = res.plan;
-    Mem d_mirror, d_mirror_rule;
+    Mem d_mirror, d_mirror_rule, d_mirror_ins;
     if (mirrored) {
         d_mirror = upload(A, mirror_mat, s, "the mirror tables");
         d_mirror_rule = upload(A, mirror_rule, s, "the mirror tables");
+        // the pass leaves out mirrors that take no part in the rounds: no
+        // uses, no lists of their own, head of no kept production (their
+        // pairs are read out through their mirror's rows); with witnesses
+        // every mirror is inserted (the readout looks each pair up)
+        std::vector<uint32_t> ins(mirror_mat.size());
+        for (uint32_t x = 0; x < (uint32_t)ins.size(); x++) {
+            const uint32_t y = mirror_mat[x];
+            const sp::MatInfo &my = P.mats[y];
+            const bool inert = !witness && !my.nuse0 && !my.nuse1 && my.app_row == kNone && my.app_col == kNone &&
+                               !P.kept_head[y];
+            ins[x] = inert ? kNone : y;
+        }
+        d_mirror_ins = upload(A, ins, s, "the mirror tables");
     }
 
     Mem d_mats = upload(A, P.mats, s, "the matrix table");
@@ -639,6 +655,7 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         // edge with its reverse); else the caller solves without the plan
         S.mirror = d_mirror.as<uint32_t>();
         S.mirror_rule = d_mirror_rule.as<uint32_t>();
+        S.mirror_ins = d_mirror_ins.as<uint32_t>();
         hip_check(sp::launch_mirror_check(S, BA.dev(), std::min<uint64_t>(h_ctl[sp::kCtlWords], BA.cap), s),
                   "mirror check");
         read_ctl(nullptr);
@@ -806,13 +823,16 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
             // the mirrors of the product's pairs, appended behind them
             const uint64_t nprod = std::min<uint64_t>(h_ctl[sp::kCtlWords], out->cap);
             if (ev0) hip_check(hipEventRecord(ev0, s), "event");
+            hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlMirrorSkip, 1, 0, s), "fill");
             hip_check(sp::launch_mirror(S, out->dev(), nprod, waves, s), "mirror");
             read_ctl(out);
             for (int attempt = 0; h_ctl[sp::kCtlHalt]; attempt++) {
                 grow_for_rerun(attempt, "mirror pass", false);
+                hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlMirrorSkip, 1, 0, s), "fill");
                 hip_check(sp::launch_mirror(S, out->dev(), nprod, waves, s), "mirror");
                 read_ctl(out);
             }
+            res.mirror_skipped += h_ctl[sp::kCtlMirrorSkip];
             if (ev0) {
                 hip_check(hipEventRecord(ev1, s), "event");
                 hip_check(hipEventSynchronize(ev1), "event");
@@ -824,7 +844,7 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
         }
         // kCtlNew counts every pair appended this round, over re-runs too
         const uint64_t fresh = h_ctl[sp::kCtlNew];
-        res.new_pairs += fresh;
+        res.new_pairs += fresh + (mirrored ? h_ctl[sp::kCtlMirrorSkip] : 0);
         hash_keys += fresh;
         tombs_resident += h_ctl[sp::kCtlTomb];
         hip_check(sp::launch_fill_u64(S.ctl + sp::kCtlTomb, 1, 0, s), "fill");

@@ -171,6 +171,10 @@ struct State {
     // inserts (mirror[x], j, i) for each new pair (x, i, j)
     const uint32_t *mirror;
     const uint32_t *mirror_rule;
+    // per matrix x: the mirror the pass inserts for x's new pairs, or kNone
+    // when that mirror takes no part in the rounds (no uses, no lists of its
+    // own, head of no kept production) and no witnesses are kept
+    const uint32_t *mirror_ins;
     uint32_t round;            // the round being run (0 while seeding), for witnesses
     // bookkeeping words (kCtl* below)
     unsigned long long *ctl;
@@ -199,7 +203,8 @@ constexpr int kCtlPoolTop = 0,   // pool entries handed out
     kCtlHeavyCand = 16,          // candidates the heavy items sent to the hash set
     kCtlLight = 17,              // entries of the light buckets listed
     kCtlMirrorMiss = 18,         // seeds whose mirror pair is missing (mirror plans)
-    kCtlWords = 19;
+    kCtlMirrorSkip = 19,         // new pairs whose mirror the pass left out (mirror_ins)
+    kCtlWords = 20;
 
 // ------------------------------------------------------------------ launchers
 

@@ -292,12 +292,13 @@ __device__ __forceinline__ uint64_t hash_slot(const unsigned long long *tab, uin
 
 // Mirror plans: after a round's product, insert the mirror (mirror[m], j, i)
 // of each of the round's first `count` new pairs (m, i, j) and append the
-// ones that are new behind them, with the mirror production in the witness.
-// A re-run after an overflow covers the same `count` pairs: mirrors already
-// appended are found present.
+// ones that are new behind them, with the mirror production in the witness;
+// a pair whose mirror takes no part in the rounds (mirror_ins[m] = kNone) is
+// only counted (ctl[kCtlMirrorSkip]).  A re-run after an overflow covers the
+// same `count` pairs: mirrors already appended are found present.
 __global__ __launch_bounds__(256) void mirror_kernel(State S, PairBuf out, uint64_t count) {
     Chunk ch;
-    uint64_t appended = 0;
+    uint64_t appended = 0, skipped = 0;
     for (uint64_t base = wave_global_id() * 64; base < count; base += waves_in_grid() * 64) {
         const uint64_t p = base + lane_id();
         uint32_t m = kHoleKey, i = 0, j = 0;
@@ -306,7 +307,9 @@ __global__ __launch_bounds__(256) void mirror_kernel(State S, PairBuf out, uint6
             i = out.i[p];
             j = out.j[p];
         }
-        const bool has = m != kHoleKey;
+        const uint32_t target = m != kHoleKey ? S.mirror_ins[m] : kNone;
+        if (m != kHoleKey && target == kNone) skipped++;
+        const bool has = target != kNone;
         uint64_t w = 0;
         if (S.wit && has) {
             const uint64_t at = hash_slot(S.hash, S.hash_mask, pair_key(m, i, j));
@@ -316,13 +319,15 @@ __global__ __launch_bounds__(256) void mirror_kernel(State S, PairBuf out, uint6
                 if (rule < kWitEps) w = (w & ~(0xFFFFFFull << 24)) | ((uint64_t)(S.mirror_rule[rule] & 0xFFFFFFu) << 24);
             }
         }
-        if (!insert_append(S, out, ch, appended, has, has ? S.mirror[m] : 0u, j, i, w)) {
+        if (!insert_append(S, out, ch, appended, has, has ? target : 0u, j, i, w)) {
             add_appended(S, appended);
             return;
         }
     }
     chunk_retire(out, ch);
     add_appended(S, appended);
+    skipped = wave_sum64(skipped);
+    if (lane_id() == 0 && skipped) atomicAdd(&S.ctl[kCtlMirrorSkip], (unsigned long long)skipped);
 }
 
 // A sorted entry of the key sort: matrix, key vertex, partner vertex.
