@@ -559,10 +559,25 @@ def serve(args):
         log(json.dumps(row))
         rows.append(row)
     best = max(r["solves_per_s"] for r in rows)
+    cpu = None
+    if not args.no_cpu:
+        small = [k for k, (_, g) in enumerate(pool) if g.n <= args.batch_oracle_max_n]
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        log(f"oracle on the {len(small)} queries with n <= {args.batch_oracle_max_n}, {threads} at once ...")
+        t0 = time.perf_counter()
+        from concurrent.futures import ThreadPoolExecutor
+        import oracle
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(lambda k: oracle.solve(pool[k][0], pool[k][1], pairs=False, digest=False), small))
+        to = time.perf_counter() - t0
+        cpu = {"value": len(small) / to, "unit": "solves/s", "cores": threads, "kind": "oracle",
+               "sample": f"the {len(small)} queries of the pool with n <= {args.batch_oracle_max_n}, one oracle "
+                         f"process per query, {threads} at once on the host cores ({host_cpu()}): {to:.1f} s",
+               "gpu_plain_same_queries_solves_per_s": len(small) / sum(service[k] for k in small)}
     print(json.dumps({"metric": "served solves/s (continuous batching)", "value": best,
                       "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
                       "data": "synthetic", "plain_solves_per_s": plain_rate,
-                      "sweep": rows, "max_slots_per_class": args.serve_slots,
+                      "sweep": rows, "max_slots_per_class": args.serve_slots, "cpu_baseline": cpu,
                       "config": {"workload": f"serve_mix ({args.serve_mix}): {len(objs)} queries, "
                                              + ", ".join(f"{nm} n in [{lo}, {hi}]" for nm, lo, hi in
                                                          SERVE_MIX[args.serve_mix])

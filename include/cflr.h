@@ -95,6 +95,11 @@ typedef struct cflr_opts {
                                   symbols.  0 (default): none */
     uint32_t mirror;           /* sparse engine: CFLR_MIRROR_AUTO (default)
                                   or CFLR_MIRROR_OFF (see below) */
+    uint32_t sparse_heavy;     /* sparse engine: a bucket of new pairs (one
+                                  matrix, one key vertex) whose products
+                                  reach this many goes to the LDS bit-set
+                                  kernel; 0 = automatic (autotuned, else
+                                  128) */
 } cflr_opts;
 
 /* Mirror plans (cflr_opts.mirror; the sparse engine).  The analyses of the
@@ -304,18 +309,29 @@ cflr_status cflr_solve_batch(cflr_ctx *ctx, const cflr_grammar *const *grammars,
                              const cflr_graph *const *graphs, uint32_t count,
                              const cflr_opts *opts, cflr_result **outs);
 
-/* Autotuner: solves graphs[0..count) (as cflr_solve_batch would) once per
- * candidate launch shape -- product grid of {16, 32, 48} waves per
- * compute unit, and for batches of more than one graph {2, 4, 8} rounds
- * per hipGraph replay -- and keeps the fastest in ctx for every later solve
- * on it that leaves those options at 0.  Results are identical for every
- * shape (only the interleaving of the atomics changes); they are discarded.
- * out_grid_waves / out_rounds_per_sync (nullable) receive the choice;
- * out_best_ms (nullable) its time.  Errors: as cflr_solve_batch. */
+/* Autotuner: solves graphs[0..count) (as cflr_solve_batch would, or as
+ * cflr_solve for one graph) once per candidate and keeps the fastest in ctx
+ * for every later solve on it that leaves those options at 0.  Candidates,
+ * one option at a time with the others at the best so far: the product
+ * grid ({16, 32, 48} waves per compute unit); for batches of more than one
+ * graph the rounds per hipGraph replay ({2, 4, 8}); on dense storage the
+ * pairs one work item takes at most (chunk_pairs: 2^18, 2^20, 2^22); on
+ * sparse storage the products that make a bucket heavy (sparse_heavy: 64,
+ * 128, 256).  Results are identical for every candidate (only the
+ * interleaving of the atomics changes); they are discarded.
+ * out_grid_waves / out_rounds_per_sync (nullable) receive those two
+ * choices, out_best_ms (nullable) the best time; cflr_ctx_tuned gives them
+ * all.  Errors: as cflr_solve_batch. */
 cflr_status cflr_autotune(cflr_ctx *ctx, const cflr_grammar *const *grammars,
                           const cflr_graph *const *graphs, uint32_t count,
                           uint32_t *out_grid_waves, uint32_t *out_rounds_per_sync,
                           double *out_best_ms);
+
+/* The options a context fills in for those a solve leaves at 0 (after
+ * cflr_autotune; 0 where nothing was tuned): grid_waves, rounds_per_sync,
+ * chunk_pairs, sparse_heavy; the other fields as cflr_opts_default.
+ * Errors: EINVAL. */
+cflr_status cflr_ctx_tuned(const cflr_ctx *ctx, cflr_opts *out);
 
 /* ---- results --------------------------------------------------------------
  * Algorithm 1's Result, read per non-terminal: the set of pairs (i, j)

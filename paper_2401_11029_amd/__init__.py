@@ -321,7 +321,9 @@ def solve_batch(ctx: Context, grammars, graphs, options: Opts | None = None, **k
 
 def autotune(ctx: Context, grammars, graphs):
     """Pick the product grid (and, for several graphs, rounds per graph
-    replay) by timing each candidate; later solves on ctx use the choice."""
+    replay; on dense storage the work-item size, on sparse storage the
+    heavy-bucket threshold) by timing each candidate; later solves on ctx
+    use the choice."""
     ctx._no_server()
     graphs = list(graphs)
     if isinstance(grammars, Grammar):
@@ -331,7 +333,10 @@ def autotune(ctx: Context, grammars, graphs):
     gr = (C.c_void_p * n)(*[g._h.value for g in graphs])
     w, r, ms = C.c_uint32(), C.c_uint32(), C.c_double()
     _check(lib().cflr_autotune(ctx._h, ga, gr, n, C.byref(w), C.byref(r), C.byref(ms)))
-    return {"grid_waves": w.value, "rounds_per_sync": r.value, "best_ms": ms.value}
+    t = Opts()
+    _check(lib().cflr_ctx_tuned(ctx._h, C.byref(t)))
+    return {"grid_waves": w.value, "rounds_per_sync": r.value, "chunk_pairs": t.chunk_pairs,
+            "sparse_heavy": t.sparse_heavy, "best_ms": ms.value}
 
 
 class Server:

@@ -24,7 +24,8 @@ class Opts(C.Structure):
                 ("chunk_pairs", C.c_uint32),
                 ("storage", C.c_uint32),
                 ("witness", C.c_uint32),
-                ("mirror", C.c_uint32)]
+                ("mirror", C.c_uint32),
+                ("sparse_heavy", C.c_uint32)]
 
 
 class Stats(C.Structure):
@@ -77,6 +78,7 @@ SIGNATURES = {
     "cflr_ctx_create": (C.c_int, [C.c_int, P, C.POINTER(P)]),
     "cflr_ctx_destroy": (None, [P]),
     "cflr_ctx_mem_info": (C.c_int, [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "cflr_ctx_tuned": (C.c_int, [P, C.POINTER(Opts)]),
     "cflr_grammar_parse": (C.c_int, [C.c_char_p, C.c_size_t, C.POINTER(P)]),
     "cflr_grammar_free": (None, [P]),
     "cflr_grammar_num_nonterminals": (C.c_uint32, [P]),

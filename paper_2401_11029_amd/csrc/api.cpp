@@ -551,51 +551,81 @@ cflr_status cflr_autotune(cflr_ctx *ctx, const cflr_grammar *const *grammars, co
     return guard([&]() -> cflr_status {
         if (!ctx || !count || !grammars || !graphs) return fail(CFLR_EINVAL, "null argument");
         set_device(ctx);
-        const uint32_t waves[3] = {16, 32, 48};
-        const uint32_t rps_batch[3] = {2, 4, 8};
-        const uint32_t n_rps = count > 1 ? 3 : 1;
         const bool verbose = std::getenv("CFLR_TUNE_LOG") != nullptr;
-        double best = 1e300;
-        uint32_t best_w = 0, best_r = 0;
         std::vector<cflr_result *> outs(count, nullptr);
-        for (uint32_t wi = 0; wi < 3; wi++) {
-            for (uint32_t ri = 0; ri < n_rps; ri++) {
-                cflr_opts o;
-                cflr_opts_default(&o);
-                o.grid_waves = waves[wi] * ctx->num_cu;
-                o.rounds_per_sync = count > 1 ? rps_batch[ri] : 1;
-                hipEvent_t e0, e1;
-                hip_check(hipEventCreate(&e0), "event");
-                hip_check(hipEventCreate(&e1), "event");
-                hip_check(hipEventRecord(e0, ctx->stream), "event");
-                cflr_status st = count > 1 ? cflr_solve_batch(ctx, grammars, graphs, count, &o, outs.data())
-                                           : cflr_solve(ctx, grammars[0], graphs[0], &o, outs.data());
-                hip_check(hipEventRecord(e1, ctx->stream), "event");
-                hip_check(hipEventSynchronize(e1), "event");
-                float ms = 0;
-                hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                for (auto &r : outs) {
-                    cflr_result_free(r);
-                    r = nullptr;
-                }
+        uint32_t storage = 0;  // the engine the first trial ran on
+        // one timed solve (or batch) with these options
+        auto trial = [&](const cflr_opts &o, double *ms_out) -> cflr_status {
+            hipEvent_t e0, e1;
+            hip_check(hipEventCreate(&e0), "event");
+            hip_check(hipEventCreate(&e1), "event");
+            hip_check(hipEventRecord(e0, ctx->stream), "event");
+            cflr_status st = count > 1 ? cflr_solve_batch(ctx, grammars, graphs, count, &o, outs.data())
+                                       : cflr_solve(ctx, grammars[0], graphs[0], &o, outs.data());
+            hip_check(hipEventRecord(e1, ctx->stream), "event");
+            hip_check(hipEventSynchronize(e1), "event");
+            float ms = 0;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            if (st == CFLR_OK && outs[0] && !storage) storage = outs[0]->inst->stats.storage;
+            for (auto &r : outs) {
+                cflr_result_free(r);
+                r = nullptr;
+            }
+            if (verbose && st == CFLR_OK)
+                std::fprintf(stderr,
+                             "[cflr] autotune grid_waves=%u rounds_per_sync=%u chunk_pairs=%u sparse_heavy=%u: %.1f ms\n",
+                             o.grid_waves, o.rounds_per_sync, o.chunk_pairs, o.sparse_heavy, ms);
+            *ms_out = ms;
+            return st;
+        };
+        cflr_opts best;
+        cflr_opts_default(&best);
+        best.grid_waves = 32 * ctx->num_cu;
+        best.rounds_per_sync = count > 1 ? 4 : 1;
+        double best_ms = 1e300;
+        // sweep one field over its candidates, the others at the best so far
+        auto sweep = [&](uint32_t cflr_opts::*field, const std::vector<uint32_t> &cands) -> cflr_status {
+            for (uint32_t v : cands) {
+                cflr_opts o = best;
+                o.*field = v;
+                double ms = 0;
+                cflr_status st = trial(o, &ms);
                 if (st != CFLR_OK) return st;
-                if (verbose)
-                    std::fprintf(stderr, "[cflr] autotune grid_waves=%u rounds_per_sync=%u: %.1f ms\n", o.grid_waves,
-                                 o.rounds_per_sync, ms);
-                if (ms < best) {
-                    best = ms;
-                    best_w = o.grid_waves;
-                    best_r = o.rounds_per_sync;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = o;
                 }
             }
-        }
-        ctx->grid_waves_tuned = best_w;
-        ctx->rounds_per_sync_tuned = best_r;
-        if (out_grid_waves) *out_grid_waves = best_w;
-        if (out_rounds_per_sync) *out_rounds_per_sync = best_r;
-        if (out_best_ms) *out_best_ms = best;
+            return CFLR_OK;
+        };
+        cflr_status st = sweep(&cflr_opts::grid_waves, {16 * ctx->num_cu, 32 * ctx->num_cu, 48 * ctx->num_cu});
+        if (st == CFLR_OK && count > 1) st = sweep(&cflr_opts::rounds_per_sync, {2, 4, 8});
+        if (st == CFLR_OK && storage == CFLR_STORAGE_DENSE)
+            st = sweep(&cflr_opts::chunk_pairs, {1u << 18, 1u << 20, 1u << 22});
+        if (st == CFLR_OK && storage == CFLR_STORAGE_SPARSE) st = sweep(&cflr_opts::sparse_heavy, {64, 128, 256});
+        if (st != CFLR_OK) return st;
+        ctx->grid_waves_tuned = best.grid_waves;
+        ctx->rounds_per_sync_tuned = best.rounds_per_sync;
+        // the defaults a trial left at 0 are kept as what they stand for
+        if (storage == CFLR_STORAGE_DENSE) ctx->chunk_pairs_tuned = best.chunk_pairs ? best.chunk_pairs : kChunkPairs;
+        if (storage == CFLR_STORAGE_SPARSE) ctx->sparse_heavy_tuned = best.sparse_heavy ? best.sparse_heavy : 128;
+        if (out_grid_waves) *out_grid_waves = best.grid_waves;
+        if (out_rounds_per_sync) *out_rounds_per_sync = best.rounds_per_sync;
+        if (out_best_ms) *out_best_ms = best_ms;
+        return CFLR_OK;
+    });
+}
+
+cflr_status cflr_ctx_tuned(const cflr_ctx *ctx, cflr_opts *out) {
+    return guard([&]() -> cflr_status {
+        if (!ctx || !out) return fail(CFLR_EINVAL, "null argument");
+        cflr_opts_default(out);
+        out->grid_waves = ctx->grid_waves_tuned;
+        out->rounds_per_sync = ctx->rounds_per_sync_tuned;
+        out->chunk_pairs = ctx->chunk_pairs_tuned;
+        out->sparse_heavy = ctx->sparse_heavy_tuned;
         return CFLR_OK;
     });
 }

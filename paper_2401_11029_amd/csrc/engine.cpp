@@ -582,7 +582,7 @@ void Run::enqueue_product(bool timed, bool rerun) {
     P.work_counter0 = counters + 1;
     P.work_counter1 = counters + 4;
     P.halt = halt;
-    P.chunk = opts_.chunk_pairs ? opts_.chunk_pairs : kChunkPairs;
+    P.chunk = opts_.chunk_pairs ? opts_.chunk_pairs : (ctx_->chunk_pairs_tuned ? ctx_->chunk_pairs_tuned : kChunkPairs);
     P.ap_cap = ap_cap_;
     if (!rerun) {
         // the prep reads the bucket starts of this round's new pairs; then

@@ -80,6 +80,8 @@ struct cflr_ctx {
     uint64_t delta_capacity_hint = 0;  // grown new-pair capacity, reused by later solves
     uint32_t grid_waves_tuned = 0;     // autotuned product grid (0 = not yet)
     uint32_t rounds_per_sync_tuned = 0;  // autotuned rounds per graph replay (batches)
+    uint32_t chunk_pairs_tuned = 0;      // autotuned work-item size (dense engine)
+    uint32_t sparse_heavy_tuned = 0;     // autotuned heavy-bucket threshold (sparse engine)
     uint32_t batch_running_cap = 0;      // graphs a batch ran at most when its new pairs last fit the
                                          // buffer's limit after a restart (0: no restart yet)
     // sizes the sparse engine grew to (new-pair buffer, list pool, hash

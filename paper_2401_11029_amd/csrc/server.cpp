@@ -99,16 +99,16 @@ struct cflr_server {
     void sparse_loop();
     bool step(int c);
     void fail_all(const std::string &what);
-    void renew_run(int c);
+    void renew_run(int c, bool small);
 };
 
-// Replace run c by a new one whose new-pair buffer starts small (it grows
-// on overflow); when the device has no memory for it now, run c stays empty
-// and the worker loop tries again later.
-void cflr_server::renew_run(int c) {
+// Replace run c by a new one (small: its new-pair buffer starts at 2^22
+// pairs at most; it grows on overflow); when the device has no memory for it
+// now, run c stays empty and the worker loop tries again later.
+void cflr_server::renew_run(int c, bool small) {
     run[c].reset();
     cflr_opts o = run_opts[c];
-    o.delta_capacity = std::min<uint64_t>(o.delta_capacity, 1ull << 22);
+    if (small) o.delta_capacity = std::min<uint64_t>(o.delta_capacity, 1ull << 22);
     try {
         run[c] = std::make_unique<Run>(ctx, o, buckets, max_slots, stream);
     } catch (const Error &e) {
@@ -179,7 +179,7 @@ bool cflr_server::step(int c) {
                 run_cap[c] = std::max<uint32_t>(1, (uint32_t)back.size() / 2);
             }
             count[c] = 0;
-            renew_run(c);
+            renew_run(c, true);
             return true;
         }
         std::vector<std::shared_ptr<Instance>> done;
@@ -213,11 +213,13 @@ bool cflr_server::step(int c) {
             r->finished = true;
         }
         if (!done.empty()) {
-            // an idle run whose new-pair buffer grew gives the memory back
-            // (a later large request or the sparse lane may need it)
-            if (rn.size() == 0 && rn.delta_capacity() > std::max<uint64_t>(run_opts[c].delta_capacity, 1ull << 22)) {
+            // an idle run whose new-pair buffer grew past a quarter of the
+            // budget (44 bytes a pair) gives the memory back: a later large
+            // request or the sparse lane may need it
+            if (rn.size() == 0 && rn.delta_capacity() > run_opts[c].delta_capacity &&
+                rn.delta_capacity() * 44 > budget / 4) {
                 std::lock_guard<std::mutex> lk(mu);
-                renew_run(c);
+                renew_run(c, false);
             }
             cv_done.notify_all();
         }
@@ -299,7 +301,7 @@ void cflr_server::loop() {
         try {
             std::lock_guard<std::mutex> lk(mu);
             for (int c = 0; c < 2; c++) {
-                if (!run[c]) renew_run(c);
+                if (!run[c]) renew_run(c, true);
                 have[c] = run[c] != nullptr;
             }
         } catch (const std::exception &e) {

@@ -566,7 +566,7 @@ void sparse_core(cflr_ctx *ctx, hipStream_t s, const cflr_opts &o, const Lowered
     K.nb = K.nb0 + (uint64_t)P.nrank1 * n;
     const bool grouped = !fixed && K.nb > 0 && K.nb < (1ull << 30) && sp::heavy_lds_bytes(n) <= sp::kHeavyMaxLds &&
                          std::getenv("CFLR_SPARSE_UNGROUPED") == nullptr;
-    uint64_t threshold = 128;
+    uint64_t threshold = o.sparse_heavy ? o.sparse_heavy : (ctx->sparse_heavy_tuned ? ctx->sparse_heavy_tuned : 128);
     if (const char *h = std::getenv("CFLR_SPARSE_HEAVY")) threshold = std::max<uint64_t>(1, std::strtoull(h, nullptr, 10));
     if (witness) threshold = ~0ull;  // every product keeps its midpoint: no bucket goes to the bit set
     K.threshold = threshold;

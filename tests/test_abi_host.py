@@ -38,6 +38,7 @@ def test_version_and_defaults(cflr_lib):
     assert o.semi_naive == 1 and o.max_rounds == 0
     # automatic sizes unless set: new-pair buffer, grid, replay depth, item size
     assert o.delta_capacity == 0 and o.grid_waves == 0 and o.rounds_per_sync == 0 and o.chunk_pairs == 0
+    assert o.mirror == 0 and o.sparse_heavy == 0 and o.witness == 0
     assert cflr.opts(chunk_pairs=1000).chunk_pairs == 1000
 
 

@@ -227,9 +227,30 @@ def test_autotune_then_batch_matches_oracle():
     gg = [m.Graph.from_workload(own, g) for g in gs]
     t = m.autotune(own, gr, gg)
     assert t["grid_waves"] > 0 and t["rounds_per_sync"] in (2, 4, 8) and t["best_ms"] > 0
+    assert t["chunk_pairs"] in (1 << 18, 1 << 20, 1 << 22) and t["sparse_heavy"] == 0  # dense storage
     res = m.solve_batch(own, gr, gg)
     for r, g in zip(res, gs):
         assert_matches_oracle(r, G.ALIAS_FIG5A_WCNF, g, "tuned batch")
+
+
+def test_autotune_sparse_then_solve_matches_oracle():
+    # the points-to generator at 24,000 vertices: its 644 dense matrices
+    # would take more than a quarter of the device, so the solves are
+    # sparse; the tuner picks the grid, then the heavy-bucket threshold,
+    # and a later solve on the context uses them
+    m = cflr()
+    own = m.Context(0)
+    text, g = workloads.config("pointsto_200k", n=24000)
+    gr = m.Grammar(text)
+    go = m.Graph.from_workload(own, g)
+    t = m.autotune(own, gr, [go])
+    assert t["sparse_heavy"] in (64, 128, 256) and t["chunk_pairs"] == 0 and t["rounds_per_sync"] == 1
+    r = m.solve(own, gr, go)
+    assert r.stats()["storage"] == 2
+    o = oracle.solve(text, g, pairs=False, digest=True)
+    for x in o.order:
+        s_, d_ = r.pairs(x)
+        assert s_.shape[0] == o.count[x] and digest(s_, d_) == o.digest[x], x
 
 
 def test_naive_variant_matches(ctx):
