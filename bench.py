@@ -518,7 +518,9 @@ def serve(args):
         r.close()
     plain_rate = len(objs) / sum(service)
     log(f"plain: {plain_rate:.1f} solves/s")
+    ctx.trim()  # the plain solves' cached blocks: the budget is half of what is really free
     free, _ = ctx.mem_info()
+    log(f"free device memory: {free / 2**30:.1f} GiB")
     rows = []
     for mult in args.serve_rates:
         lam = mult * plain_rate
@@ -541,6 +543,8 @@ def serve(args):
                 results.append(None)
                 failed.append(f"query {q} (n={pool[q][1].n}): {e}")
                 log(f"served query {q} failed: {e}")
+            if q % 10 == 9:
+                log(f"rate {mult}x: {q + 1} of {len(tickets)} served, {time.perf_counter() - t0:.1f} s")
         times = [srv.times(t) for t in tickets]
         srv.close()
         same = [r.stats()["total_pairs"] if r else None for r in results] == plain_pairs

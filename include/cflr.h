@@ -176,8 +176,13 @@ const char *cflr_version(void);
  * Errors: EINVAL (bad device), EDEVICE. */
 cflr_status cflr_ctx_create(int hip_device, void *hip_stream, cflr_ctx **out);
 void cflr_ctx_destroy(cflr_ctx *ctx);
-/* Free and total device memory seen by the context, in bytes. */
+/* Free and total device memory seen by the context, in bytes (blocks the
+ * context's pool keeps for reuse count as used; cflr_ctx_trim frees them). */
 cflr_status cflr_ctx_mem_info(cflr_ctx *ctx, uint64_t *free_bytes, uint64_t *total_bytes);
+/* Hand the device blocks the context's pool keeps for reuse back to the HIP
+ * runtime (results and graphs keep theirs).  Not while a server of the
+ * context runs.  Errors: EINVAL. */
+cflr_status cflr_ctx_trim(cflr_ctx *ctx);
 
 /* ---- grammar (host only; needs no device) -----------------------------
  * Text format: one production per line, "LHS -> ALT | ALT ...", where ALT is

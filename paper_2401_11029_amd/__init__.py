@@ -75,6 +75,11 @@ class Context:
         _check(lib().cflr_ctx_mem_info(self._h, C.byref(f), C.byref(t)))
         return f.value, t.value
 
+    def trim(self):
+        """Free the device blocks the context's pool keeps for reuse."""
+        self._no_server()
+        _check(lib().cflr_ctx_trim(self._h))
+
     def close(self):
         if getattr(self, "_h", None):
             lib().cflr_ctx_destroy(self._h)

@@ -79,6 +79,7 @@ SIGNATURES = {
     "cflr_ctx_destroy": (None, [P]),
     "cflr_ctx_mem_info": (C.c_int, [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "cflr_ctx_tuned": (C.c_int, [P, C.POINTER(Opts)]),
+    "cflr_ctx_trim": (C.c_int, [P]),
     "cflr_grammar_parse": (C.c_int, [C.c_char_p, C.c_size_t, C.POINTER(P)]),
     "cflr_grammar_free": (None, [P]),
     "cflr_grammar_num_nonterminals": (C.c_uint32, [P]),

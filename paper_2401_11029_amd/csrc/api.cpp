@@ -185,6 +185,16 @@ cflr_status cflr_ctx_mem_info(cflr_ctx *ctx, uint64_t *free_bytes, uint64_t *tot
     });
 }
 
+cflr_status cflr_ctx_trim(cflr_ctx *ctx) {
+    return guard([&]() -> cflr_status {
+        if (!ctx) return fail(CFLR_EINVAL, "null argument");
+        set_device(ctx);
+        hip_check(hipStreamSynchronize(ctx->stream), "sync");
+        ctx->pool->trim();
+        return CFLR_OK;
+    });
+}
+
 // ------------------------------------------------------------------ grammar
 
 cflr_status cflr_grammar_parse(const char *text, size_t len, cflr_grammar **out) {

@@ -93,6 +93,9 @@ struct cflr_server {
     std::deque<Request *> sparse_queue;
     Request *sparse_current = nullptr;
     hipStream_t sparse_stream = nullptr;
+    // a request that found no memory beside a busy sparse lane waits for the
+    // lane's request to end before the dense runs admit again
+    bool wait_for_lane = false;
     std::string fatal;
 
     void loop();
@@ -177,6 +180,7 @@ bool cflr_server::step(int c) {
             } else {
                 for (auto it = back.rbegin(); it != back.rend(); ++it) queue.push_front(*it);
                 run_cap[c] = std::max<uint32_t>(1, (uint32_t)back.size() / 2);
+                if (sparse_current && running.empty()) wait_for_lane = true;
             }
             count[c] = 0;
             renew_run(c, true);
@@ -318,6 +322,10 @@ void cflr_server::loop() {
         std::vector<Request *> admit;
         {
             std::unique_lock<std::mutex> lk(mu);
+            if (wait_for_lane) {
+                cv_done.wait(lk, [&] { return stop || !sparse_current; });
+                wait_for_lane = false;
+            }
             cv_work.wait(lk, [&] { return stop || !queue.empty() || !running.empty(); });
             if (stop && queue.empty() && running.empty()) break;
             uint64_t planned = in_use, planned_slots[2] = {slots_in_use[0], slots_in_use[1]};
