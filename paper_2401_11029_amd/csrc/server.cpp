@@ -550,6 +550,7 @@ void cflr_server_free(cflr_server *s) {
         s->stop = true;
         s->cv_work.notify_all();
         s->cv_sparse.notify_all();
+        s->cv_done.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
     if (s->sparse_worker.joinable()) s->sparse_worker.join();
