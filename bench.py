@@ -525,9 +525,12 @@ def serve(args):
     for mult in args.serve_rates:
         lam = mult * plain_rate
         arrivals = graphs.poisson_trace(len(objs), lam, seed=4 + int(mult * 100))
-        # the budget covers the dense runs; the sparse lane's solves take
-        # what they need beside it
-        srv = cflr.Server(ctx, hbm_budget_bytes=int(free * 0.5), max_slots=args.serve_slots)
+        # the budget covers the dense runs' matrices; their new-pair buffers
+        # (up to a quarter of the budget each) and the sparse lane's solves
+        # take memory beside it, so the configured mix, whose lane requests
+        # hold tens of GB, gets a quarter of the free memory
+        frac = 0.25 if args.serve_mix == "configured" else 0.5
+        srv = cflr.Server(ctx, hbm_budget_bytes=int(free * frac), max_slots=args.serve_slots)
         t0 = time.perf_counter()
         tickets = []
         for (gr, o), a in zip(objs, arrivals):
