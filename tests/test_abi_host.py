@@ -188,3 +188,40 @@ def test_grammar_symbols_for_witnesses():
     w = C.c_uint64()
     assert L.cflr_result_witness(None, 0, None, None, None, None, 0, 0, C.byref(w)) == 1
     assert L.cflr_last_error() != b""
+
+
+def test_mirror_of_random_closed_grammars(cflr_lib):
+    # grammars closed under reversal by construction (every production
+    # added with its mirror: X_k <-> Y_k, t <-> t_bar) have a mirror, and
+    # the plan keeps one production of each mirror pair; dropping one
+    # production of a pair breaks the mirror
+    import random
+    for seed in range(20):
+        rnd = random.Random(seed)
+        k = rnd.randint(2, 6)
+        nts = [(f"X{i}", f"Y{i}") for i in range(k)]
+        mir = {}
+        for x, y in nts:
+            mir[x], mir[y] = y, x
+        terms = [(f"t{i}", f"t{i}_bar") for i in range(rnd.randint(1, 3))]
+        lines, prods = [], set()
+        for x, y in nts:  # every non-terminal derives a terminal
+            t, tb = rnd.choice(terms)
+            lines += [f"{x} -> {t}", f"{y} -> {tb}"]
+        for _ in range(rnd.randint(2, 8)):
+            c, a, b = (rnd.choice(nts)[rnd.randint(0, 1)] for _ in range(3))
+            p, q = (c, a, b), (mir[c], mir[b], mir[a])
+            if p in prods or q in prods:
+                continue
+            prods |= {p, q}
+            lines += [f"{c} -> {a} {b}", f"{mir[c]} -> {mir[b]} {mir[a]}"]
+        text = "\n".join(lines) + "\n"
+        pairs = len({frozenset([p, (mir[p[0]], mir[p[2]], mir[p[1]])]) for p in prods})
+        self_mirrored = sum(1 for p in prods if p == (mir[p[0]], mir[p[2]], mir[p[1]]))
+        assert info(text)[1]["mirror_skipped"] == pairs - self_mirrored, (seed, text)
+        # remove the second production of one non-self pair
+        non_self = [p for p in prods if p != (mir[p[0]], mir[p[2]], mir[p[1]])]
+        if non_self:
+            c, a, b = non_self[0]
+            broken = text.replace(f"{c} -> {a} {b}\n", "", 1)
+            assert info(broken)[1]["mirror_skipped"] < pairs - self_mirrored or pairs == 0, (seed, broken)
