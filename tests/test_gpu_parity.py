@@ -443,3 +443,24 @@ def test_library_loaded_before_torch_still_leaves_torch_a_device():
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0 and out.stdout.strip().endswith("ok"), out.stderr[-2000:]
+
+
+def test_trim_and_tuned_options_of_a_fresh_context():
+    # a fresh context has nothing tuned; trimming its pool frees the cached
+    # blocks and later solves allocate again
+    m = cflr()
+    own = m.Context(0)
+    import ctypes as C
+    t = m.Opts()
+    assert m.lib().cflr_ctx_tuned(own._h, C.byref(t)) == 0
+    assert t.grid_waves == 0 and t.rounds_per_sync == 0 and t.chunk_pairs == 0 and t.sparse_heavy == 0
+    assert t.semi_naive == 1
+    text, g = G.ALIAS_FIG5A_WCNF, graphs.alias_graph(3000, seed=91)
+    gr = m.Grammar(text)
+    go = m.Graph.from_workload(own, g)
+    m.solve(own, gr, go).close()          # its buffers go back to the pool's cache
+    free_before, _ = own.mem_info()
+    own.trim()
+    free_after, _ = own.mem_info()
+    assert free_after >= free_before
+    assert_matches_oracle(m.solve(own, gr, go), text, g, "after trim")
