@@ -15,7 +15,11 @@ the pairs seeding puts there.  The grammar is closed under reversal and the
 graph holds every edge with its reverse, so the library solves it with a
 mirror plan (one production of each mirror pair keeps its product; the
 transposes of its new pairs are the other's); other_configs gives the same
-solve with every production's product (cflr_opts.mirror = OFF).
+solve with every production's product (cflr_opts.mirror = OFF).  Under the
+plan the pairs of FT and SP_i are held as the transposes of PT's and FS_i's
+row lists (the readout writes them out transposed, outside the timed
+region, as it writes every pair out); every pair is derived in the timed
+steps and the counts include them all.
 
 The JSON line also carries:
   roofline      the dominant kernel of the sparse engine's product (the
