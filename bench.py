@@ -228,6 +228,26 @@ def stream_copy_gbs(reps=5, words=1 << 29):
     return 2 * 4 * words / (best / 1e3) / 1e9
 
 
+def readout_all_ms(cflr, ctx, gr, graph, **kw):
+    """One more solve, then every non-terminal's pairs written out sorted
+    into device memory (cflr_result_copy to torch tensors): wall ms of the
+    readout alone (under a mirror plan it includes writing out the
+    non-terminals held as their mirror's transposed rows)."""
+    import torch
+    r = cflr.solve(ctx, gr, graph, **kw)
+    dev = torch.device("cuda", 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for x in gr.nonterminals:
+        s, d = r.pairs(x, device=dev)
+        del s, d
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    r.close()
+    torch.cuda.empty_cache()
+    return ms
+
+
 def plain_plan(cflr, args, text, g):
     """The headline solve with every production's own product (no mirror
     plan), timed as the headline (fewer steps)."""
@@ -242,12 +262,14 @@ def plain_plan(cflr, args, text, g):
         stats.append(r.stats())
         r.close()
         log(f"plain plan step {k}: {stats[-1]['fixpoint_ms']:.1f} ms")
+    readout_ms = readout_all_ms(cflr, ctx, gr, graph, mirror=1)
     del graph, gr
     ctx.close()
     out = {"workload": "pointsto_200k without the mirror plan (cflr_opts.mirror = OFF): every one of "
                        "the 514 binary productions has its own product",
            "mirror_plan": bool(stats[-1]["mirror"]), "total_pairs": stats[-1]["total_pairs"],
-           "heavy_ms_mean": sum(s["heavy_ms"] for s in stats) / len(stats)}
+           "heavy_ms_mean": sum(s["heavy_ms"] for s in stats) / len(stats),
+           "readout_all_ms": readout_ms}
     out.update(fix_summary(stats))
     return out
 
@@ -282,6 +304,8 @@ def single(args):
     log(f"accounting: heavy {acct['heavy_algo_bytes'] / 1e9:.1f} GB, light {acct['light_algo_bytes'] / 1e9:.1f} GB "
         f"over {nl} launches each")
     secs, stats, counts = time_solves(cflr, ctx, gr, graph, 0, args.steps, HEADLINE)
+    readout_ms = readout_all_ms(cflr, ctx, gr, graph)
+    log(f"readout of every non-terminal's pairs into device memory: {readout_ms:.0f} ms")
     derived = stats[-1]["total_pairs"] - seeded_user_pairs(text, g)
     value = derived * args.steps / secs
     launches = max(1, sum(s["heavy_launches"] for s in stats))
@@ -304,6 +328,7 @@ def single(args):
            "pairs": stats[-1]["total_pairs"], "derived_pairs": derived,
            "rounds": stats[-1]["rounds"],
            "mirror_plan": bool(stats[-1]["mirror"]),
+           "readout_all_ms": readout_ms,
            "product_ms_mean": sum(s["product_ms"] for s in stats) / len(stats)}
     cfg.update(fix_summary(stats))
     out = {
